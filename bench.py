@@ -1,0 +1,255 @@
+"""Benchmark: fused state-vector evolution of the 30-qubit grid random circuit.
+
+Workload: 5x6 grid random circuit, depth 20, 845 gates (600 single-qubit
+sqrt(X)/sqrt(Y)/sqrt(W), 245 fSim(pi/2, pi/6)), complex64 state of 2^30
+amplitudes (8 GiB), seed 1.  One step = reset to |0..0>, fuse the gates
+(greedy fusion, blocks of at most max_k qubits) and apply every block, then
+the FP64 norm: the whole path from gate list to reduced result.  Inputs are
+resident on the device before the timed region.
+
+Reported next to the fused throughput: the plain per-gate complex64 run, the
+fidelity error and amplitude max-abs error of both against a complex128 GPU
+run of the same circuit (first 2^20 amplitudes for the max-abs), the roofline
+of the dominant kernel (HIP-event timed inside the timed region), and the CPU
+oracle timed on a bounded sample.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--max-k K]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+MFMA_FP32_PEAK_TFLOPS = 157.3
+FAMILY_NAMES = {1: "reg", 2: "generic", 3: "mfma_f32", 4: "split_bf16", 5: "split_fp16"}
+KERNEL_SOURCES = {1: "apply.hip", 2: "apply.hip", 3: "mfma.hip", 4: "mfma.hip", 5: "mfma.hip"}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def source_hash(fam: int) -> str:
+    p = os.path.join(ROOT, "paper_2111_06868_amd", "csrc", KERNEL_SOURCES[fam])
+    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+
+
+def read_traffic(fam: int, k: int, n: int):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or
+    None when there is none or the kernel source changed since."""
+    name = os.path.join(ROOT, "profiles", "traffic_%s_k%d_%dq.md" % (FAMILY_NAMES[fam], k, n))
+    if not os.path.exists(name):
+        return None
+    kv = {}
+    for ln in open(name):
+        if ":" in ln and ln.startswith("- "):
+            key, _, val = ln[2:].partition(":")
+            kv[key.strip()] = val.strip().strip("`")
+    if kv.get("kernel_source_sha256_16") != source_hash(fam):
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(n, gates, budget_s=20.0):
+    """The oracle (complex128, gate at a time, OpenMP over amplitude groups)
+    on the full-size state for the circuit's first gates."""
+    import numpy as np
+    from oracle import ref
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    psi = np.zeros(1 << n, dtype=np.complex128)
+    psi[0] = 1.0
+    ops = [(ref.matrix_of(g), g.qubits) for g in gates]
+    done = 0
+    t0 = time.perf_counter()
+    while done < len(ops):
+        ref.run_matrices(psi, ops[done:done + 1])
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = time.perf_counter() - t0
+    del psi
+    return {"value": done / dt, "unit": "gates/s", "cores": threads, "kind": "oracle",
+            "sample": "first %d of %d gates on the full %d-qubit complex128 state" % (done, len(ops), n)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--max-k", type=int, default=5)
+    ap.add_argument("--rule", default="enhanced", choices=["paper", "enhanced"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--config", type=int, default=1, choices=[1, 2])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-reference", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the state-vector path here is built and measured "
+              "on a single MI355X (--gpus %d is not supported)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2111_06868_amd as sv
+    from workloads import circuits as wc
+
+    torch.cuda.set_device(0)
+    n, gates = wc.config_circuit(args.config)
+    bound = [(g.name, g.qubits, g.params) for g in gates]
+    ga = sv.GateArray(bound)
+    rule = sv.RULE_ENHANCED if args.rule == "enhanced" else sv.RULE_PAPER
+    prec = {"fp32": sv.PREC_FP32, "bf16": sv.PREC_SPLIT_BF16, "fp16": sv.PREC_SPLIT_FP16}[args.precision]
+    G = len(gates)
+    pass_bytes = 16.0 * (1 << n)
+
+    plan = sv.fuse(ga, n, args.max_k, rule)
+    blocks = plan.blocks(False)
+    n_passes = len(blocks)
+    kh = {}
+    for b in blocks:
+        kh[len(b.qubits)] = kh.get(len(b.qubits), 0) + 1
+    log("n=%d gates=%d fused blocks=%d k-histogram=%s" % (n, G, n_passes, kh))
+
+    st = sv.State(n, "c64")
+    stream = st.stream
+
+    def step():
+        st.set_basis(0)
+        st.run(ga, max_k=args.max_k, rule=rule, precision=prec)
+        return st.norm2()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    sv.stats_reset()
+    sv.stats_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        nrm = step()
+        log("step %d done, norm-1 = %.2e" % (i, nrm - 1))
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    sv.stats_enable(False)
+    ms_step = 1e3 * t_total / args.steps
+
+    # dominant kernel class in the timed region
+    per_class = {}
+    for fam in FAMILY_NAMES:
+        for k in range(1, 7):
+            cnt, ms = sv.stats_query(FAMILY_NAMES[fam], k)
+            if cnt:
+                per_class[(fam, k)] = (cnt, ms)
+    (dfam, dk), (dcnt, dms) = max(per_class.items(), key=lambda kv: kv[1][1])
+    avg_ms = dms / dcnt
+    achieved = pass_bytes / (avg_ms * 1e-3) / 1e9
+    kernel_ms_total = sum(ms for _, ms in per_class.values()) / args.steps
+    traffic = read_traffic(dfam, dk, n)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+                "kernel": "%s k=%d" % (FAMILY_NAMES[dfam], dk), "avg_launch_ms": round(avg_ms, 4),
+                "launches_per_step": dcnt // args.steps,
+                "algorithmic_bytes_per_launch": pass_bytes}
+    if dfam in (3, 4, 5):
+        flops = 8.0 * (1 << dk) * (1 << n) * (3 if dfam in (4, 5) else 1)
+        roofline["mfma_tflops"] = round(flops / (avg_ms * 1e-3) / 1e12, 2)
+        if dfam == 3:
+            roofline["mfma_frac"] = round(roofline["mfma_tflops"] / MFMA_FP32_PEAK_TFLOPS, 4)
+    log("timed %.1f ms/step; dominant %s avg %.3f ms -> %.0f GB/s" % (ms_step, roofline["kernel"], avg_ms, achieved))
+    fused_state = st
+
+    extra = {}
+    # plain per-gate complex64 run (same circuit), one timed run
+    pg = sv.State(n, "c64")
+    pg.run(ga, rule=sv.RULE_NONE)  # warm
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    pg.set_basis(0)
+    pg.run(ga, rule=sv.RULE_NONE)
+    pg.norm2()
+    torch.cuda.synchronize()
+    t_pg = time.perf_counter() - t1
+    extra["per_gate_gates_per_s"] = round(G / t_pg, 2)
+    extra["per_gate_ms"] = round(1e3 * t_pg, 2)
+    extra["fused_speedup_vs_per_gate"] = round(t_pg * 1e3 / ms_step, 3)
+    log("per-gate: %.1f ms" % (1e3 * t_pg))
+
+    if not args.no_reference:
+        refst = sv.State(n, "c128")
+        refst.run(ga, rule=sv.RULE_NONE)
+        nr = refst.norm2()
+        fe_fused = sv.fidelity_error(refst, fused_state)
+        fe_pg = sv.fidelity_error(refst, pg)
+        first = 1 << 20
+        a = refst.read(0, first)
+        extra["fidelity_err_fused"] = fe_fused
+        extra["fidelity_err_per_gate"] = fe_pg
+        extra["max_abs_first_2^20_fused"] = float(np.max(np.abs(fused_state.read(0, first) - a)))
+        extra["max_abs_first_2^20_per_gate"] = float(np.max(np.abs(pg.read(0, first) - a)))
+        extra["norm_minus_1_fused"] = fused_state.norm2() - 1.0
+        extra["norm_minus_1_c128"] = nr - 1.0
+        log("fidelity err fused %.2e per-gate %.2e" % (fe_fused, fe_pg))
+        del refst
+    del pg
+
+    # plain device copy for the achievable-bandwidth context
+    x = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        y.copy_(x)
+    ev1.record()
+    torch.cuda.synchronize()
+    extra["copy_kernel_GBps"] = round(10 * 2 * x.numel() * 4 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9, 1)
+    del x, y
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(n, gates, args.cpu_budget)
+
+    out = {
+        "metric": "gates/s + effective HBM GB/s at 30q; fused vs per-gate at <=1e-5 fidelity err",
+        "value": round(G / (ms_step * 1e-3), 2),
+        "unit": "gates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "grid random circuit %s, %d qubits, %d gates, complex64, fused k<=%d (%s rule, %s)"
+                   % ({1: "5x6 depth 20 seed 1", 2: "4x8 depth 14 seed 2"}[args.config], n, G, args.max_k,
+                      args.rule, args.precision),
+                   "qubits": n, "gates": G, "max_k": args.max_k, "blocks": n_passes,
+                   "block_sizes": {str(k): v for k, v in sorted(kh.items())}},
+        "effective_GBps": round(n_passes * pass_bytes / (ms_step * 1e-3) / 1e9, 1),
+        "kernel_ms_per_step": round(kernel_ms_total, 3),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,306 @@
+/*
+ * sv.h -- C ABI of the MI355X (gfx950) state-vector library.
+ *
+ * The library evolves a 2^n-amplitude complex state by an ordered list of
+ * gates, each applied to the amplitude groups it touches, or by gates greedily
+ * fused into dense k-qubit blocks.  This is the "evolution" method of the
+ * HybridQ paper (Simulations section, State Vector subsection: the state vector
+ * is updated by one matrix-vector product per gate; Circuit utilities: compress()
+ * fuses gates into blocks of at most max_n_qubits qubits).
+ *
+ * General conventions
+ *   - Every entry point returns SV_OK (0) or a negative SV_ERR_* code; the
+ *     thread-local message of the last failure is sv_last_error().  No C++
+ *     exception crosses this boundary.
+ *   - Arguments are validated on the host before any device work is enqueued:
+ *     a call that fails validation has no effect.
+ *   - Device work is asynchronous on the state's HIP stream unless an entry
+ *     point says it synchronises.  An asynchronous device fault is reported as
+ *     SV_ERR_HIP by the next synchronising call.
+ *   - Qubits are POSITIONS: position p is bit p of an amplitude index (position
+ *     0 = least significant bit).  The paper's (2,)*n arrays with axis j
+ *     following order[j] in C order put order[0] at position n-1 (its Grover
+ *     example fixes this).
+ *   - A k-qubit matrix is 2^k x 2^k complex128, row-major, each entry stored as
+ *     (re, im) doubles; the most significant bit of its local index belongs to
+ *     q[0].
+ *   - States are interleaved complex arrays (re, im), complex64 (SV_C64) or
+ *     complex128 (SV_C128), in caller-owned device memory (for example a torch
+ *     tensor) or in memory the library allocates.
+ *   - A state handle, plan or batch is used from one host thread at a time.
+ */
+#ifndef SV_H
+#define SV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SV_MAX_K 6            /* largest gate / fused block, in qubits        */
+#define SV_MAX_QUBITS_C64 35  /* 256 GiB of complex64 amplitudes              */
+#define SV_MAX_QUBITS_C128 34 /* 256 GiB of complex128 amplitudes             */
+#define SV_MAX_PAULI_TERMS 4096
+
+/* status codes */
+#define SV_OK 0
+#define SV_ERR_ARG (-1)         /* bad argument (NULL, out of range, bad enum) */
+#define SV_ERR_QUBIT (-2)       /* qubit position out of range or repeated     */
+#define SV_ERR_SIZE (-3)        /* buffer too small for the requested state    */
+#define SV_ERR_HIP (-4)         /* HIP runtime error (message has details)     */
+#define SV_ERR_UNSUPPORTED (-5) /* valid request this build cannot serve       */
+
+/* amplitude types */
+#define SV_C64 0
+#define SV_C128 1
+
+/* arithmetic used to apply fused blocks (sv_run_opts.precision) */
+#define SV_PREC_FP32 0       /* complex64 state; FP32 matvec / FP32 MFMA           */
+#define SV_PREC_SPLIT_BF16 1 /* complex64 state; k>=4 blocks as hi+lo BF16 MFMA    */
+#define SV_PREC_SPLIT_FP16 2 /* complex64 state; k>=4 blocks as hi+lo FP16 MFMA    */
+#define SV_PREC_FP64 3       /* complex128 state; FP64 arithmetic throughout       */
+
+/* fusion rules (sv_fuse) */
+#define SV_RULE_PAPER 0    /* the paper's compress() rule, reproduced exactly    */
+#define SV_RULE_ENHANCED 1 /* paper rule, then cost-aware merging of blocks      */
+#define SV_RULE_NONE 2     /* one block per gate (plain per-gate application)    */
+
+/* gate kinds.  Matrices (paper, Gates and Properties section, names only; the
+ * matrices are the textbook ones):
+ *   SQRT_P = ((1+i) I + (1-i) P) / 2 for P in {X, Y, W}, W = (X + Y)/sqrt 2
+ *   R_P(t) = cos(t/2) I - i sin(t/2) P                      (params[0] = t)
+ *   CZ = diag(1,1,1,-1); CPHASE(a) = diag(1,1,1,e^{ia})     (params[0] = a)
+ *   CX: control q[0], target q[1];  SWAP
+ *   FSIM(t, f) = [[1,0,0,0],[0,cos t,-i sin t,0],[0,-i sin t,cos t,0],
+ *                 [0,0,0,e^{-if}]]                           (params = t, f)
+ *   MATRIX: the caller's dense matrix in sv_gate.m (k = 1..SV_MAX_K). */
+enum sv_gate_kind {
+    SV_G_MATRIX = 0,
+    SV_G_I = 1,
+    SV_G_X = 2,
+    SV_G_Y = 3,
+    SV_G_Z = 4,
+    SV_G_H = 5,
+    SV_G_SQRT_X = 6,
+    SV_G_SQRT_Y = 7,
+    SV_G_SQRT_W = 8,
+    SV_G_RX = 9,
+    SV_G_RY = 10,
+    SV_G_RZ = 11,
+    SV_G_CZ = 12,
+    SV_G_CX = 13,
+    SV_G_CPHASE = 14,
+    SV_G_SWAP = 15,
+    SV_G_FSIM = 16,
+    SV_G_COUNT = 17
+};
+
+/* One gate of a circuit (paper, Circuits section: a circuit is an ordered list
+ * of gates acting on qubits).  k must equal the kind's arity (1 or 2) except for
+ * SV_G_MATRIX.  `param` is the index of params[0] in the parameter vector that
+ * sv_backward differentiates (rotations only), or -1.  The matrix behind `m`
+ * is read during the call and not retained. */
+typedef struct sv_gate {
+    int32_t kind;
+    int32_t k;
+    int32_t q[SV_MAX_K];
+    double params[2];
+    int32_t param;
+    int32_t reserved; /* must be 0 */
+    const double *m;
+} sv_gate;
+
+/* Real linear combination of Pauli strings H = sum_t coef[t] P_t.  Bit p of
+ * xmask[t] is set when P_t has X or Y at position p, bit p of zmask[t] when it
+ * has Z or Y there (Y = i X Z).  Host arrays of n_terms entries. */
+typedef struct sv_pauli_sum {
+    int32_t n_terms;
+    int32_t reserved; /* must be 0 */
+    const double *coef;
+    const uint64_t *xmask;
+    const uint64_t *zmask;
+} sv_pauli_sum;
+
+/* Options of sv_run_circuit. */
+typedef struct sv_run_opts {
+    int32_t max_k;     /* largest fused block, 1..SV_MAX_K; -1 = choose the
+                          value with the lowest cost in the autotuned table   */
+    int32_t precision; /* SV_PREC_*; must match the state's amplitude type    */
+    int32_t rule;      /* SV_RULE_*                                           */
+    int32_t use_graph; /* 1: capture the launches in a hipGraph, replay it    */
+} sv_run_opts;
+
+typedef struct sv_state sv_state;
+typedef struct sv_plan sv_plan;
+typedef struct sv_batch sv_batch;
+
+/* ---------------------------------------------------------------- misc */
+/* Message of the last failing call on this thread ("" if none). */
+const char *sv_last_error(void);
+/* ABI version (monotone integer). */
+int sv_version(void);
+
+/* ---------------------------------------------------------------- states */
+/* Bind a handle to an n-qubit state of amplitude type `dtype` (SV_C64 or
+ * SV_C128) held in `dev_buf` (device memory of at least 2^n amplitudes,
+ * 256-byte aligned; the caller keeps it alive until sv_free and keeps
+ * ownership).  dev_buf == NULL makes the library allocate (and later free) the
+ * buffer.  `hip_stream` (a hipStream_t, may be NULL = default stream) is the
+ * stream every call on this state enqueues on.  The state starts as |0...0>
+ * (paper, Initial and Final State Specification section).
+ * Errors: SV_ERR_ARG (n < 1, n above SV_MAX_QUBITS_*, bad dtype, out NULL,
+ * misaligned buffer), SV_ERR_SIZE (bytes < 2^n amplitudes), SV_ERR_HIP. */
+int sv_alloc(int n, int dtype, void *dev_buf, size_t bytes, void *hip_stream, sv_state **out);
+/* Release the handle (and the buffer if the library allocated it). Synchronises. */
+int sv_free(sv_state *s);
+/* Query the handle: qubit count, amplitude type, device pointer. */
+int sv_info(const sv_state *s, int *n, int *dtype, void **dev_ptr);
+/* Product state from tokens '0' '1' '+' '-' (paper, Initial and Final State
+ * Specification section): either n characters, token j describing position
+ * n-1-j, or one character broadcast to every qubit.  SV_ERR_ARG otherwise. */
+int sv_set_product(sv_state *s, const char *tokens);
+/* Computational basis state |index>.  SV_ERR_ARG if index >= 2^n. */
+int sv_set_basis(sv_state *s, uint64_t index);
+/* Copy amplitudes [first, first+count) to host memory (in the state's own
+ * amplitude type).  Synchronises.  SV_ERR_ARG if the range exceeds 2^n. */
+int sv_read(sv_state *s, uint64_t first, uint64_t count, void *host);
+/* Copy amplitudes from host memory into [first, first+count).  Synchronises.
+ * Together with sv_read this checkpoints and resumes a long circuit. */
+int sv_write(sv_state *s, uint64_t first, uint64_t count, const void *host);
+/* dst <- src amplitude by amplitude (types may differ: complex64 <-> complex128).
+ * Both states must have the same n.  Enqueued on dst's stream after src's work. */
+int sv_copy(sv_state *dst, sv_state *src);
+/* Wait for all work enqueued on the state's stream. */
+int sv_synchronize(sv_state *s);
+
+/* ---------------------------------------------------------------- gates */
+/* Host only: write the 2^k x 2^k complex128 matrix of gate g into `out`
+ * (row-major, (re, im) pairs).  Validates kind, k and parameters but not qubit
+ * positions. */
+int sv_gate_matrix(const sv_gate *g, double *out);
+/* Apply one gate to the state (the paper's per-gate matrix-vector product,
+ * State Vector section).  k <= 3 runs the register kernel, k >= 4 the dense
+ * block kernels.  complex64 states use FP32 arithmetic, complex128 FP64.
+ * Errors: SV_ERR_QUBIT (position >= n or repeated), SV_ERR_ARG. */
+int sv_apply_gate(sv_state *s, const sv_gate *g);
+
+/* ---------------------------------------------------------------- fusion */
+/* Host only.  Partition the G gates into blocks of at most max_k qubits
+ * (paper, Circuit utilities section, compress()).  SV_RULE_PAPER: each gate
+ * joins the last block that shares a qubit with it if the union stays within
+ * max_k qubits, otherwise it opens a new block.  SV_RULE_ENHANCED: the paper
+ * rule, then a gate that meets no block joins the last block when that fits,
+ * and adjacent-by-commutation blocks are merged whenever the autotuned cost
+ * table (or, without one, the pass count) says the merged block is cheaper.
+ * SV_RULE_NONE: one block per gate.  Each block's qubits are sorted
+ * ascending (q[0] = most significant local bit) and its matrix is the ordered
+ * product of its members (FP64).  n bounds the positions.  max_k = -1 uses the
+ * autotuned cost table for n (SV_ERR_ARG if there is none).
+ * The plan is owned by the caller and released with sv_plan_free. */
+int sv_fuse(const sv_gate *g, int G, int n, int max_k, int rule, sv_plan **out);
+int sv_plan_free(sv_plan *p);
+/* Number of blocks; for block b: its size k, its positions q[0..k-1] (array of
+ * SV_MAX_K) and its member count. */
+int sv_plan_num_blocks(const sv_plan *p, int *out);
+int sv_plan_block(const sv_plan *p, int b, int32_t *k, int32_t *q, int32_t *n_members);
+/* Indices (into the fused gate list) of block b's members, in order. */
+int sv_plan_block_members(const sv_plan *p, int b, int32_t *members);
+/* Block b's 2^k x 2^k complex128 matrix. */
+int sv_plan_block_matrix(const sv_plan *p, int b, double *m);
+/* The max_k the plan was built with (the chosen one when -1 was asked). */
+int sv_plan_max_k(const sv_plan *p, int *out);
+/* Apply a plan's blocks in order with the given SV_PREC_* arithmetic; with
+ * use_graph = 1 the launches are captured into a hipGraph that is replayed
+ * once (and the call synchronises).  SV_ERR_QUBIT if the plan's positions do
+ * not fit the state. */
+int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int use_graph);
+
+/* ---------------------------------------------------------------- circuits */
+/* Validate the G gates, fuse them (sv_fuse with o->max_k, o->rule) and apply
+ * the blocks in order (paper, Simulations section: simulate(..., optimize=
+ * 'evolution')).  Nothing is applied if any gate is invalid.  Asynchronous
+ * (synchronises when o->use_graph = 1).  o == NULL means plain per-gate
+ * application: {SV_MAX_K, FP32 or FP64 by amplitude type, SV_RULE_NONE, 0}. */
+int sv_run_circuit(sv_state *s, const sv_gate *g, int G, const sv_run_opts *o);
+
+/* ---------------------------------------------------------------- reductions */
+/* ||psi||^2 in FP64 (fixed-order two-stage reduction).  Synchronises. */
+int sv_norm(sv_state *s, double *out);
+/* <a|b> = sum_i conj(a_i) b_i in FP64; a and b have the same n, any types.
+ * Synchronises (enqueued on b's stream after a's work). */
+int sv_inner(sv_state *a, sv_state *b, double *re, double *im);
+/* <psi|H|psi> for a Pauli sum H, FP64 accumulation.  Synchronises.
+ * SV_ERR_ARG if a mask has bits at or above n or too many terms. */
+int sv_expectation(sv_state *s, const sv_pauli_sum *H, double *out);
+/* psi <- H psi for a Pauli sum H (into `out`, a second state of the same n
+ * and type; psi is unchanged).  Asynchronous. */
+int sv_apply_pauli_sum(sv_state *psi, const sv_pauli_sum *H, sv_state *out);
+
+/* ---------------------------------------------------------------- gradients */
+/* Adjoint differentiation of E(theta) = <psi|H|psi>, psi = U_G..U_1 psi_0
+ * (the paper is silent on gradients; method: adjoint differentiation, Jones &
+ * Gacon 2020).  `psi` must hold the forward output of exactly these gates and
+ * is consumed (it ends as U_1^+ .. U_G^+ psi, i.e. psi_0 up to rounding);
+ * `scratch` is a second state of the same n and type.  For every gate with
+ * param >= 0 (which must be SV_G_RX, SV_G_RY or SV_G_RZ),
+ * grad[param] += dE/dtheta, accumulated in FP64; other entries are untouched,
+ * so the caller zeroes grad first.  Synchronises.
+ * Errors: SV_ERR_ARG (param >= n_params, a param on a non-rotation). */
+int sv_backward(sv_state *psi, sv_state *scratch, const sv_gate *g, int G, const sv_pauli_sum *H,
+                double *grad, int n_params);
+
+/* ---------------------------------------------------------------- batches */
+/* Many independent circuits of different qubit counts (noisy trajectories:
+ * the paper's Simulations with noise section samples noise channels on pure
+ * states instead of evolving density matrices).  Trajectory t has n_qubits[t]
+ * qubits (1..SV_MAX_QUBITS_C64) and gates [gate_offsets[t], gate_offsets[t+1])
+ * of `gates`; every state starts at |0...0>.  Noise draws are already
+ * materialised as gates by the caller. */
+typedef struct sv_batch_desc {
+    int32_t n_traj;
+    int32_t max_k;          /* fusion limit per trajectory (1..SV_MAX_K) or -1 */
+    const int32_t *n_qubits;
+    const int64_t *gate_offsets; /* n_traj + 1 entries */
+    const sv_gate *gates;
+} sv_batch_desc;
+/* Device bytes sv_batch_create needs in dev_buf for this batch. */
+int sv_batch_required_bytes(const sv_batch_desc *d, size_t *out);
+/* Fuse every trajectory, upload the work tables and build the launch
+ * schedule on `hip_stream`.  dev_buf (caller-owned, >= required bytes) holds
+ * every trajectory's complex64 state back to back. */
+int sv_batch_create(const sv_batch_desc *d, void *dev_buf, size_t bytes, void *hip_stream,
+                    sv_batch **out);
+/* Run every trajectory from |0...0> and write <Z_0> (FP64) of each into
+ * z0_out[n_traj].  use_graph = 1 replays one captured hipGraph.  Synchronises. */
+int sv_batch_run(sv_batch *b, int use_graph, double *z0_out);
+/* Read amplitudes of trajectory t (after sv_batch_run).  Synchronises. */
+int sv_batch_read(sv_batch *b, int t, uint64_t first, uint64_t count, void *host);
+int sv_batch_free(sv_batch *b);
+
+/* ---------------------------------------------------------------- tuning */
+/* Time the block kernels for k = 1..SV_MAX_K (and their launch shapes) on
+ * the given scratch state (its contents are destroyed) with SV_PREC_*
+ * arithmetic, keep the fastest launch shape per k, and store the cost table
+ * (milliseconds per block application, cost_ms[k], cost_ms[0] unused) for
+ * this (n, precision).  Synchronises. */
+int sv_autotune(sv_state *scratch, int precision, double *cost_ms);
+/* Install a cost table for (n, precision) without timing (e.g. from a cache). */
+int sv_set_cost_table(int n, int precision, const double *cost_ms);
+
+/* ---------------------------------------------------------------- stats */
+/* Per-kernel device timing.  While enabled every kernel launch is bracketed
+ * by HIP events on its stream; sv_stats_query synchronises the recorded
+ * launches and returns, for a kernel class, the launch count and the summed
+ * device milliseconds.  Classes: 10*family + k, families 1 = register apply,
+ * 2 = generic apply, 3 = MFMA FP32, 4 = MFMA split BF16, 5 = MFMA split FP16,
+ * 6 = reductions, 7 = adjoint, 8 = batch. */
+int sv_stats_enable(int on);
+int sv_stats_reset(void);
+int sv_stats_query(int cls, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SV_H */

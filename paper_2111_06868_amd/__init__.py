@@ -1,0 +1,479 @@
+"""MI355X (gfx950) state-vector simulation: Python binding of libsv.so.
+
+This module only marshals arguments: every step of the path (gate matrices,
+fusion, application, reductions, gradients, batches) runs inside the C ABI
+library (include/sv.h).  PyTorch provides device memory (a tensor holds each
+state) and the HIP stream.  There is no CPU fallback: without the built
+library every call raises.
+
+Circuits follow the paper's statement (Circuits section): an ordered list of
+gates acting on qubits.  Gates are given on qubit POSITIONS (bit p of the
+amplitude index); ``positions(order, qubits)`` maps the paper's named qubits
+with an ``order`` list (order[0] = most significant) onto positions.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Sequence
+
+import numpy as np
+
+from . import _native as N
+from ._native import (C64, C128, PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16, PREC_FP64,  # noqa: F401
+                      RULE_PAPER, RULE_ENHANCED, RULE_NONE, SV_MAX_K, GATE_KINDS, SvError,
+                      SvValueError)
+
+__all__ = ["State", "Plan", "fuse", "gate_matrix", "backward", "Energy", "Batch", "positions",
+           "pauli_sum", "autotune", "set_cost_table", "stats_enable", "stats_reset", "stats_query",
+           "C64", "C128", "PREC_FP32", "PREC_SPLIT_BF16", "PREC_SPLIT_FP16", "PREC_FP64",
+           "RULE_PAPER", "RULE_ENHANCED", "RULE_NONE", "SvError", "SvValueError"]
+
+
+def positions(order: Sequence, qubits: Sequence) -> tuple:
+    """Named qubits -> positions: axis j of the paper's (2,)*n array follows
+    order[j] (C order), so order[0] is position n-1."""
+    n = len(order)
+    idx = {q: j for j, q in enumerate(order)}
+    return tuple(n - 1 - idx[q] for q in qubits)
+
+
+# ------------------------------------------------------------------ gates
+class GateArray:
+    """A ctypes sv_gate[] plus the matrices it points to."""
+
+    def __init__(self, gates):
+        gates = list(gates)
+        self.n = len(gates)
+        self.arr = (N.sv_gate * max(self.n, 1))()
+        self._keep = []
+        for i, g in enumerate(gates):
+            name, qubits, params, param_index, matrix = _gate_fields(g)
+            s = self.arr[i]
+            if name not in GATE_KINDS:
+                raise ValueError("unknown gate %r" % name)
+            s.kind = GATE_KINDS[name]
+            s.k = len(qubits)
+            if s.k > SV_MAX_K:
+                raise ValueError("gate on %d qubits (max %d)" % (s.k, SV_MAX_K))
+            for j, q in enumerate(qubits):
+                s.q[j] = int(q)
+            for j, p in enumerate(params[:2]):
+                s.params[j] = float(p)
+            s.param = int(param_index)
+            s.reserved = 0
+            if name == "MATRIX":
+                m = np.ascontiguousarray(matrix, dtype=np.complex128)
+                if m.shape != (1 << s.k, 1 << s.k):
+                    raise ValueError("matrix gate needs a %dx%d matrix" % (1 << s.k, 1 << s.k))
+                buf = m.view(np.float64)
+                self._keep.append(buf)
+                s.m = buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            else:
+                s.m = None
+
+    @property
+    def ptr(self):
+        return ctypes.cast(self.arr, ctypes.POINTER(N.sv_gate))
+
+
+def _gate_fields(g):
+    """Accept objects with name/qubits/params/param_index (and .matrix for
+    MATRIX gates) or tuples (name, qubits[, params[, param_index]])."""
+    if isinstance(g, tuple):
+        name = g[0]
+        qubits = tuple(g[1])
+        params = tuple(g[2]) if len(g) > 2 else ()
+        pidx = g[3] if len(g) > 3 else -1
+        matrix = g[4] if len(g) > 4 else None
+    else:
+        name, qubits = g.name, tuple(g.qubits)
+        params = tuple(getattr(g, "params", ()))
+        pidx = getattr(g, "param_index", -1)
+        matrix = getattr(g, "matrix", None)
+    name = name.upper()
+    if name == "MATRIX" and matrix is None:
+        raise ValueError("MATRIX gate without .matrix")
+    return name, qubits, params, pidx, matrix
+
+
+def gate_matrix(g) -> np.ndarray:
+    """Matrix of one gate as computed by the library (host side)."""
+    ga = GateArray([g])
+    k = ga.arr[0].k
+    out = np.zeros((1 << k) * (1 << k) * 2, dtype=np.float64)
+    N.check(N.lib().sv_gate_matrix(ga.ptr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out.view(np.complex128).reshape(1 << k, 1 << k)
+
+
+# ------------------------------------------------------------------ Pauli sums
+_PAULI_BITS = {"X": (1, 0), "Y": (1, 1), "Z": (0, 1), "I": (0, 0)}
+
+
+class PauliSum:
+    """sv_pauli_sum from [(coef, ((position, 'X'|'Y'|'Z'), ...)), ...]."""
+
+    def __init__(self, terms):
+        terms = list(terms)
+        self.coef = np.array([float(c) for c, _ in terms] or [0.0], dtype=np.float64)
+        xs, zs = [], []
+        for _, factors in terms:
+            x = z = 0
+            for q, p in factors:
+                bx, bz = _PAULI_BITS[p.upper()]
+                x |= bx << int(q)
+                z |= bz << int(q)
+            xs.append(x)
+            zs.append(z)
+        self.x = np.array(xs or [0], dtype=np.uint64)
+        self.z = np.array(zs or [0], dtype=np.uint64)
+        self.s = N.sv_pauli_sum()
+        self.s.n_terms = len(terms)
+        self.s.reserved = 0
+        self.s.coef = self.coef.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self.s.xmask = self.x.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+        self.s.zmask = self.z.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+    @property
+    def ptr(self):
+        return ctypes.byref(self.s)
+
+
+def pauli_sum(terms) -> PauliSum:
+    return PauliSum(terms)
+
+
+# ------------------------------------------------------------------ states
+def _torch():
+    import torch
+    return torch
+
+
+class State:
+    """An n-qubit state in a torch tensor on the current HIP device.
+
+    ``dtype`` is "c64" or "c128".  Work is enqueued on ``stream`` (default:
+    torch's current stream)."""
+
+    def __init__(self, n: int, dtype: str = "c64", stream=None, device=None):
+        torch = _torch()
+        self.n = int(n)
+        self.dtype = C64 if dtype in ("c64", C64) else C128
+        real = torch.float32 if self.dtype == C64 else torch.float64
+        dev = device if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.tensor = torch.empty(2 << self.n, dtype=real, device=dev)
+        st = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.stream = st
+        h = ctypes.c_void_p()
+        N.check(N.lib().sv_alloc(self.n, self.dtype, ctypes.c_void_p(self.tensor.data_ptr()),
+                                 self.tensor.numel() * self.tensor.element_size(),
+                                 ctypes.c_void_p(st.cuda_stream), ctypes.byref(h)))
+        self.h = h
+
+    # -- lifetime
+    def free(self):
+        if getattr(self, "h", None) and self.h.value:
+            N.lib().sv_free(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    # -- contents
+    def set_product(self, tokens: str):
+        N.check(N.lib().sv_set_product(self.h, tokens.encode()))
+        return self
+
+    def set_basis(self, index: int):
+        N.check(N.lib().sv_set_basis(self.h, int(index)))
+        return self
+
+    def read(self, first: int = 0, count: int = None) -> np.ndarray:
+        count = (1 << self.n) - first if count is None else count
+        out = np.empty(count, dtype=np.complex64 if self.dtype == C64 else np.complex128)
+        N.check(N.lib().sv_read(self.h, int(first), int(count), out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def write(self, values, first: int = 0):
+        v = np.ascontiguousarray(values, dtype=np.complex64 if self.dtype == C64 else np.complex128)
+        N.check(N.lib().sv_write(self.h, int(first), int(v.size), v.ctypes.data_as(ctypes.c_void_p)))
+        return self
+
+    def copy_from(self, other: "State"):
+        N.check(N.lib().sv_copy(self.h, other.h))
+        return self
+
+    def synchronize(self):
+        N.check(N.lib().sv_synchronize(self.h))
+
+    # -- evolution
+    def apply_gate(self, gate):
+        ga = GateArray([gate])
+        N.check(N.lib().sv_apply_gate(self.h, ga.ptr))
+        return self
+
+    def run(self, gates, max_k: int = SV_MAX_K, precision: int = None, rule: int = RULE_NONE,
+            use_graph: bool = False):
+        """Fuse (rule, max_k) and apply the gates (sv_run_circuit)."""
+        ga = gates if isinstance(gates, GateArray) else GateArray(gates)
+        o = N.sv_run_opts()
+        o.max_k = int(max_k)
+        o.precision = (PREC_FP32 if self.dtype == C64 else PREC_FP64) if precision is None else int(precision)
+        o.rule = int(rule)
+        o.use_graph = int(bool(use_graph))
+        N.check(N.lib().sv_run_circuit(self.h, ga.ptr, ga.n, ctypes.byref(o)))
+        return self
+
+    def apply_plan(self, plan: "Plan", precision: int = None, use_graph: bool = False):
+        prec = (PREC_FP32 if self.dtype == C64 else PREC_FP64) if precision is None else int(precision)
+        N.check(N.lib().sv_apply_plan(self.h, plan.h, prec, int(bool(use_graph))))
+        return self
+
+    # -- reductions (FP64)
+    def norm2(self) -> float:
+        out = ctypes.c_double()
+        N.check(N.lib().sv_norm(self.h, ctypes.byref(out)))
+        return out.value
+
+    def inner(self, other: "State") -> complex:
+        """<self|other>."""
+        re, im = ctypes.c_double(), ctypes.c_double()
+        N.check(N.lib().sv_inner(self.h, other.h, ctypes.byref(re), ctypes.byref(im)))
+        return complex(re.value, im.value)
+
+    def expectation(self, terms) -> float:
+        H = terms if isinstance(terms, PauliSum) else PauliSum(terms)
+        out = ctypes.c_double()
+        N.check(N.lib().sv_expectation(self.h, H.ptr, ctypes.byref(out)))
+        return out.value
+
+    def apply_pauli_sum(self, terms, out: "State"):
+        H = terms if isinstance(terms, PauliSum) else PauliSum(terms)
+        N.check(N.lib().sv_apply_pauli_sum(self.h, H.ptr, out.h))
+        return out
+
+
+def fidelity_error(ref: State, psi: State) -> float:
+    """1 - |<ref|psi>|^2 / (||ref||^2 ||psi||^2), all in FP64 on the device."""
+    ov = ref.inner(psi)
+    return 1.0 - abs(ov) ** 2 / (ref.norm2() * psi.norm2())
+
+
+# ------------------------------------------------------------------ fusion
+@dataclass
+class Block:
+    qubits: tuple
+    members: list
+    matrix: np.ndarray
+
+
+class Plan:
+    """A fused plan (sv_fuse); blocks are read back on demand."""
+
+    def __init__(self, gates, n: int, max_k: int, rule: int = RULE_PAPER):
+        ga = gates if isinstance(gates, GateArray) else GateArray(gates)
+        h = ctypes.c_void_p()
+        N.check(N.lib().sv_fuse(ga.ptr, ga.n, int(n), int(max_k), int(rule), ctypes.byref(h)))
+        self.h = h
+        self.n = n
+
+    def __del__(self):
+        try:
+            if self.h and self.h.value:
+                N.lib().sv_plan_free(self.h)
+                self.h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+    @property
+    def max_k(self) -> int:
+        out = ctypes.c_int()
+        N.check(N.lib().sv_plan_max_k(self.h, ctypes.byref(out)))
+        return out.value
+
+    def __len__(self) -> int:
+        out = ctypes.c_int()
+        N.check(N.lib().sv_plan_num_blocks(self.h, ctypes.byref(out)))
+        return out.value
+
+    def block(self, b: int, with_matrix: bool = True) -> Block:
+        k = ctypes.c_int32()
+        q = (ctypes.c_int32 * SV_MAX_K)()
+        nm = ctypes.c_int32()
+        N.check(N.lib().sv_plan_block(self.h, b, ctypes.byref(k), q, ctypes.byref(nm)))
+        members = (ctypes.c_int32 * max(nm.value, 1))()
+        N.check(N.lib().sv_plan_block_members(self.h, b, members))
+        mat = None
+        if with_matrix:
+            D = 1 << k.value
+            buf = np.zeros(2 * D * D, dtype=np.float64)
+            N.check(N.lib().sv_plan_block_matrix(self.h, b, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+            mat = buf.view(np.complex128).reshape(D, D)
+        return Block(tuple(q[:k.value]), list(members[:nm.value]), mat)
+
+    def blocks(self, with_matrix: bool = True) -> List[Block]:
+        return [self.block(b, with_matrix) for b in range(len(self))]
+
+
+def fuse(gates, n: int, max_k: int, rule: int = RULE_PAPER) -> Plan:
+    return Plan(gates, n, max_k, rule)
+
+
+# ------------------------------------------------------------------ gradients
+def backward(psi: State, scratch: State, gates, terms, n_params: int) -> np.ndarray:
+    """Adjoint dE/dtheta (sv_backward); psi holds the forward output and is
+    consumed."""
+    ga = gates if isinstance(gates, GateArray) else GateArray(gates)
+    H = terms if isinstance(terms, PauliSum) else PauliSum(terms)
+    grad = np.zeros(max(int(n_params), 1), dtype=np.float64)
+    N.check(N.lib().sv_backward(psi.h, scratch.h, ga.ptr, ga.n, H.ptr,
+                                grad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(n_params)))
+    return grad[:n_params]
+
+
+def _bind_thetas(gates, thetas):
+    out = []
+    for g in gates:
+        name, qubits, params, pidx, matrix = _gate_fields(g)
+        if pidx >= 0:
+            params = (float(thetas[pidx]),) + tuple(params[1:])
+        out.append((name, qubits, params, pidx, matrix))
+    return out
+
+
+def _energy_function():
+    torch = _torch()
+
+    class Energy(torch.autograd.Function):
+        """E(theta) = <psi(theta)|H|psi(theta)> with the adjoint backward.
+
+        forward(thetas, n, gates, terms, max_k, precision): gates carry
+        param_index >= 0 on differentiable rotations; thetas is a CPU or CUDA
+        float64 tensor.  The forward state is kept for the backward pass,
+        which consumes it (two state buffers, no stored trajectory)."""
+
+        @staticmethod
+        def forward(ctx, thetas, n, gates, terms, max_k=SV_MAX_K, rule=RULE_PAPER):
+            th = thetas.detach().double().cpu().numpy()
+            bound = _bind_thetas(gates, th)
+            psi = State(n, "c64")
+            psi.run(bound, max_k=max_k, rule=rule)
+            H = PauliSum(terms)
+            e = psi.expectation(H)
+            ctx.save = (psi, bound, H, n, th.size)
+            return thetas.new_tensor(e)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            psi, bound, H, n, npar = ctx.save
+            scratch = State(n, "c64")
+            g = backward(psi, scratch, bound, H, npar)
+            ctx.save = None
+            gt = torch.as_tensor(g, dtype=torch.float64, device=grad_out.device) * grad_out
+            return gt, None, None, None, None, None
+
+    return Energy
+
+
+class _EnergyProxy:
+    _fn = None
+
+    def apply(self, *args):
+        if _EnergyProxy._fn is None:
+            _EnergyProxy._fn = _energy_function()
+        return _EnergyProxy._fn.apply(*args)
+
+
+Energy = _EnergyProxy()
+
+
+# ------------------------------------------------------------------ batches
+class Batch:
+    """Many trajectories of different qubit counts run together
+    (sv_batch_create / sv_batch_run)."""
+
+    def __init__(self, circuits, max_k: int = -1, stream=None):
+        torch = _torch()
+        circuits = list(circuits)
+        self.n_qubits = np.array([int(n) for n, _ in circuits], dtype=np.int32)
+        offs = [0]
+        flat = []
+        for _, gates in circuits:
+            flat.extend(gates)
+            offs.append(len(flat))
+        self.offsets = np.array(offs, dtype=np.int64)
+        self.gates = GateArray(flat)
+        d = N.sv_batch_desc()
+        d.n_traj = len(circuits)
+        d.max_k = int(max_k)
+        d.n_qubits = self.n_qubits.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.gate_offsets = self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        d.gates = self.gates.ptr
+        self.desc = d
+        need = ctypes.c_size_t()
+        N.check(N.lib().sv_batch_required_bytes(ctypes.byref(d), ctypes.byref(need)))
+        self.tensor = torch.empty(max(need.value // 4, 1), dtype=torch.float32, device="cuda")
+        st = stream if stream is not None else torch.cuda.current_stream()
+        self.stream = st
+        h = ctypes.c_void_p()
+        N.check(N.lib().sv_batch_create(ctypes.byref(d), ctypes.c_void_p(self.tensor.data_ptr()),
+                                        self.tensor.numel() * 4, ctypes.c_void_p(st.cuda_stream),
+                                        ctypes.byref(h)))
+        self.h = h
+
+    def run(self, use_graph: bool = True) -> np.ndarray:
+        z = np.zeros(len(self.n_qubits), dtype=np.float64)
+        N.check(N.lib().sv_batch_run(self.h, int(bool(use_graph)), z.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return z
+
+    def read(self, t: int, first: int = 0, count: int = None) -> np.ndarray:
+        n = int(self.n_qubits[t])
+        count = (1 << n) - first if count is None else count
+        out = np.empty(count, dtype=np.complex64)
+        N.check(N.lib().sv_batch_read(self.h, int(t), int(first), int(count), out.ctypes.data_as(ctypes.c_void_p)))
+        return out
+
+    def __del__(self):
+        try:
+            if self.h and self.h.value:
+                N.lib().sv_batch_free(self.h)
+                self.h = ctypes.c_void_p()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ tuning / stats
+def autotune(scratch: State, precision: int = PREC_FP32) -> np.ndarray:
+    cost = np.zeros(SV_MAX_K + 1, dtype=np.float64)
+    N.check(N.lib().sv_autotune(scratch.h, int(precision), cost.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return cost
+
+
+def set_cost_table(n: int, precision: int, cost) -> None:
+    c = np.ascontiguousarray(cost, dtype=np.float64)
+    assert c.size == SV_MAX_K + 1
+    N.check(N.lib().sv_set_cost_table(int(n), int(precision), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+
+def stats_enable(on: bool = True) -> None:
+    N.check(N.lib().sv_stats_enable(int(bool(on))))
+
+
+def stats_reset() -> None:
+    N.check(N.lib().sv_stats_reset())
+
+
+FAMILIES = {"reg": 1, "generic": 2, "mfma_f32": 3, "split_bf16": 4, "split_fp16": 5,
+            "reduce": 6, "adjoint": 7, "batch": 8}
+
+
+def stats_query(family: str, k: int):
+    """(launch count, summed device milliseconds) of a kernel class."""
+    cls = 10 * FAMILIES[family] + int(k)
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    N.check(N.lib().sv_stats_query(cls, ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value

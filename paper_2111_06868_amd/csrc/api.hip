@@ -1,0 +1,692 @@
+// extern "C" entry points declared in include/sv.h: states, gates, fusion,
+// circuits, reductions, adjoint gradients and timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "runtime.h"
+
+namespace sv {
+const char *last_error_cstr();
+int stats_enable(int on);
+int stats_reset();
+int stats_query(int cls, int64_t *launches, double *total_ms);
+}  // namespace sv
+
+using namespace sv;
+
+namespace {
+
+constexpr int kVersion = 1;
+
+size_t amp_bytes(int dtype) { return dtype == SV_C64 ? 8 : 16; }
+
+int check_state(const sv_state *s)
+{
+    if (!s) return fail(SV_ERR_ARG, "NULL state handle");
+    return SV_OK;
+}
+
+int select_device(const sv_state *s)
+{
+    SV_HIP(hipSetDevice(s->device));
+    return SV_OK;
+}
+
+// Make `to` wait for the work already enqueued on `from`.
+int stream_after(hipStream_t to, hipStream_t from)
+{
+    if (to == from) return SV_OK;
+    hipEvent_t e;
+    SV_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    SV_HIP(hipEventRecord(e, from));
+    SV_HIP(hipStreamWaitEvent(to, e, 0));
+    SV_HIP(hipEventDestroy(e));
+    return SV_OK;
+}
+
+int check_precision(const sv_state *s, int precision)
+{
+    if (precision < SV_PREC_FP32 || precision > SV_PREC_FP64) return fail(SV_ERR_ARG, "unknown precision %d", precision);
+    if ((s->dtype == SV_C128) != (precision == SV_PREC_FP64))
+        return fail(SV_ERR_ARG, "precision %d does not match the state's amplitude type", precision);
+    return SV_OK;
+}
+
+int validate_gates(const sv_gate *g, int G, int n)
+{
+    if (G < 0) return fail(SV_ERR_ARG, "negative gate count");
+    if (G > 0 && !g) return fail(SV_ERR_ARG, "NULL gate array");
+    for (int i = 0; i < G; ++i) {
+        int rc = check_gate_shape(g[i]);
+        if (!rc) rc = check_gate_qubits(g[i], n);
+        if (rc) {
+            std::string msg = std::string("gate ") + std::to_string(i) + ": " + last_error_cstr();
+            return fail(rc, "%s", msg.c_str());
+        }
+    }
+    return SV_OK;
+}
+
+// Upload `bytes` staged bytes and enqueue `launches`; the arena and staging
+// buffers are reused only after the previous user of the arena finished.
+int run_launches(sv_state *s, std::vector<Launch> &launches, bool use_graph)
+{
+    SV_HIP(hipEventSynchronize(s->arena_free));
+    const size_t bytes = pack_operands(launches, s->dtype, s->stage);
+    if (bytes == size_t(-1)) return fail(SV_ERR_HIP, "pinned staging allocation failed");
+    if (bytes) {
+        SV_HIP(s->arena.ensure(bytes));
+        SV_HIP(hipMemcpyAsync(s->arena.p, s->stage.p, bytes, hipMemcpyHostToDevice, s->stream));
+    }
+    if (!use_graph) {
+        int rc = enqueue(launches, s->dtype, s->buf, s->n, s->arena.p, s->stream);
+        SV_HIP(hipEventRecord(s->arena_free, s->stream));
+        return rc;
+    }
+    if (!s->capture_stream) SV_HIP(hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    SV_HIP(hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal));
+    timing_suspend(true);
+    int rc = enqueue(launches, s->dtype, s->buf, s->n, s->arena.p, s->capture_stream);
+    timing_suspend(false);
+    hipError_t e = hipStreamEndCapture(s->capture_stream, &graph);
+    if (rc) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(SV_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(exec, s->stream);
+    if (e == hipSuccess) e = hipEventRecord(s->arena_free, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(SV_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
+    return SV_OK;
+}
+
+void blocks_to_launches(const std::vector<Block> &blocks, const sv_state *s, int precision, std::vector<Launch> &out)
+{
+    out.clear();
+    out.reserve(blocks.size());
+    for (const auto &b : blocks) {
+        Launch L;
+        L.k = b.k;
+        std::copy(b.q, b.q + SV_MAX_K, L.q);
+        L.path = choose_path(s->dtype, precision, b.k, b.q, s->n);
+        L.m = b.m;
+        out.push_back(std::move(L));
+    }
+}
+
+int choose_max_k(const sv_gate *g, int G, int n, int rule, int precision, int *out_k)
+{
+    bool found = false;
+    CostTable cost = lookup_costs(n, precision, &found);
+    int best_k = 1;
+    double best = 1e300;
+    int kmin = 1;
+    for (int i = 0; i < G; ++i) kmin = std::max(kmin, g[i].k);
+    for (int k = kmin; k <= SV_MAX_K; ++k) {
+        if (!found && k == SV_MAX_K) break;  // untuned: stay below the MFMA-bound size
+        std::vector<Block> blocks;
+        int rc = fuse_gates(g, G, n, k, rule == SV_RULE_NONE ? SV_RULE_PAPER : rule, cost, blocks);
+        if (rc) return rc;
+        const double c = plan_cost(blocks, cost);
+        if (c < best - 1e-12) {
+            best = c;
+            best_k = k;
+        }
+    }
+    *out_k = best_k;
+    return SV_OK;
+}
+
+int pauli_tables(sv_state *s, const sv_pauli_sum *H, dev::PauliDev &P);
+
+}  // namespace
+
+// ============================================================== misc
+extern "C" const char *sv_last_error(void) { return last_error_cstr(); }
+extern "C" int sv_version(void) { return kVersion; }
+
+// ============================================================== states
+extern "C" int sv_alloc(int n, int dtype, void *dev_buf, size_t bytes, void *hip_stream, sv_state **out)
+{
+    clear_error();
+    if (!out) return fail(SV_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (dtype != SV_C64 && dtype != SV_C128) return fail(SV_ERR_ARG, "unknown amplitude type %d", dtype);
+    const int nmax = dtype == SV_C64 ? SV_MAX_QUBITS_C64 : SV_MAX_QUBITS_C128;
+    if (n < 1 || n > nmax) return fail(SV_ERR_ARG, "n = %d outside 1..%d", n, nmax);
+    const size_t need = (size_t(1) << n) * amp_bytes(dtype);
+    if (dev_buf) {
+        if (bytes < need) return fail(SV_ERR_SIZE, "buffer of %zu bytes < %zu needed for %d qubits", bytes, need, n);
+        if (reinterpret_cast<uintptr_t>(dev_buf) % 256) return fail(SV_ERR_ARG, "device buffer not 256-byte aligned");
+    }
+    sv_state *s = new sv_state;
+    s->n = n;
+    s->dtype = dtype;
+    s->stream = static_cast<hipStream_t>(hip_stream);
+    hipError_t e = hipGetDevice(&s->device);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->arena_free, hipEventDisableTiming);
+    if (e == hipSuccess && !dev_buf) {
+        e = hipMalloc(&s->buf, need);
+        s->owns = e == hipSuccess;
+        s->bytes = need;
+    } else {
+        s->buf = dev_buf;
+        s->bytes = bytes;
+    }
+    if (e == hipSuccess) e = s->red.ensure(sizeof(double) * (2 * dev::kRedBlocks + 64));
+    if (e == hipSuccess) e = s->red_host.ensure(sizeof(double) * 64);
+    if (e == hipSuccess) e = dev::launch_fill_basis(dtype, s->buf, n, 0, s->stream);
+    if (e != hipSuccess) {
+        int rc = fail(SV_ERR_HIP, "sv_alloc: %s", hipGetErrorString(e));
+        sv_free(s);
+        return rc;
+    }
+    *out = s;
+    return SV_OK;
+}
+
+extern "C" int sv_free(sv_state *s)
+{
+    if (!s) return SV_OK;
+    (void)hipSetDevice(s->device);
+    (void)hipStreamSynchronize(s->stream);
+    if (s->owns && s->buf) (void)hipFree(s->buf);
+    if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
+    if (s->arena_free) (void)hipEventDestroy(s->arena_free);
+    delete s;
+    return SV_OK;
+}
+
+extern "C" int sv_info(const sv_state *s, int *n, int *dtype, void **dev_ptr)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    if (n) *n = s->n;
+    if (dtype) *dtype = s->dtype;
+    if (dev_ptr) *dev_ptr = s->buf;
+    return SV_OK;
+}
+
+extern "C" int sv_set_product(sv_state *s, const char *tokens)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    if (!tokens) return fail(SV_ERR_ARG, "NULL tokens");
+    const size_t len = std::strlen(tokens);
+    if (len != 1 && len != size_t(s->n))
+        return fail(SV_ERR_ARG, "initial state needs 1 or %d tokens, got %zu", s->n, len);
+    double amps[4 * SV_MAX_QUBITS_C64];
+    const double r = 0.70710678118654752440;
+    for (int j = 0; j < s->n; ++j) {
+        const char c = len == 1 ? tokens[0] : tokens[j];
+        const int p = s->n - 1 - j;  // token j describes position n-1-j
+        double *a = amps + 4 * p;
+        switch (c) {
+        case '0': a[0] = 1; a[1] = 0; a[2] = 0; a[3] = 0; break;
+        case '1': a[0] = 0; a[1] = 0; a[2] = 1; a[3] = 0; break;
+        case '+': a[0] = r; a[1] = 0; a[2] = r; a[3] = 0; break;
+        case '-': a[0] = r; a[1] = 0; a[2] = -r; a[3] = 0; break;
+        default: return fail(SV_ERR_ARG, "initial-state token '%c' is not one of 0 1 + -", c);
+        }
+    }
+    if (int rc = select_device(s)) return rc;
+    SV_HIP(dev::launch_product(s->dtype, s->buf, s->n, amps, s->stream));
+    return SV_OK;
+}
+
+extern "C" int sv_set_basis(sv_state *s, uint64_t index)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    if (index >> s->n) return fail(SV_ERR_ARG, "basis index %llu >= 2^%d", (unsigned long long)index, s->n);
+    if (int rc = select_device(s)) return rc;
+    SV_HIP(dev::launch_fill_basis(s->dtype, s->buf, s->n, index, s->stream));
+    return SV_OK;
+}
+
+extern "C" int sv_read(sv_state *s, uint64_t first, uint64_t count, void *host)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    const uint64_t N = uint64_t(1) << s->n;
+    if (first > N || count > N - first) return fail(SV_ERR_ARG, "range [%llu, +%llu) outside the state", (unsigned long long)first, (unsigned long long)count);
+    if (count && !host) return fail(SV_ERR_ARG, "NULL host buffer");
+    if (int rc = select_device(s)) return rc;
+    const size_t ab = amp_bytes(s->dtype);
+    if (count) SV_HIP(hipMemcpyAsync(host, static_cast<char *>(s->buf) + first * ab, count * ab, hipMemcpyDeviceToHost, s->stream));
+    SV_HIP(hipStreamSynchronize(s->stream));
+    return SV_OK;
+}
+
+extern "C" int sv_write(sv_state *s, uint64_t first, uint64_t count, const void *host)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    const uint64_t N = uint64_t(1) << s->n;
+    if (first > N || count > N - first) return fail(SV_ERR_ARG, "range outside the state");
+    if (count && !host) return fail(SV_ERR_ARG, "NULL host buffer");
+    if (int rc = select_device(s)) return rc;
+    const size_t ab = amp_bytes(s->dtype);
+    if (count) SV_HIP(hipMemcpyAsync(static_cast<char *>(s->buf) + first * ab, host, count * ab, hipMemcpyHostToDevice, s->stream));
+    SV_HIP(hipStreamSynchronize(s->stream));
+    return SV_OK;
+}
+
+extern "C" int sv_copy(sv_state *dst, sv_state *src)
+{
+    clear_error();
+    if (!dst || !src) return fail(SV_ERR_ARG, "NULL state handle");
+    if (dst->n != src->n) return fail(SV_ERR_ARG, "qubit counts differ (%d vs %d)", dst->n, src->n);
+    if (int rc = select_device(dst)) return rc;
+    if (int rc = stream_after(dst->stream, src->stream)) return rc;
+    SV_HIP(dev::launch_convert(src->dtype, src->buf, dst->dtype, dst->buf, uint64_t(1) << dst->n, dst->stream));
+    return SV_OK;
+}
+
+extern "C" int sv_synchronize(sv_state *s)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    if (int rc = select_device(s)) return rc;
+    SV_HIP(hipStreamSynchronize(s->stream));
+    return SV_OK;
+}
+
+// ============================================================== gates
+extern "C" int sv_gate_matrix(const sv_gate *g, double *out)
+{
+    clear_error();
+    if (!g || !out) return fail(SV_ERR_ARG, "NULL argument");
+    std::vector<cd> m;
+    if (int rc = gate_matrix_abi(*g, m)) return rc;
+    for (size_t i = 0; i < m.size(); ++i) {
+        out[2 * i] = m[i].real();
+        out[2 * i + 1] = m[i].imag();
+    }
+    return SV_OK;
+}
+
+extern "C" int sv_apply_gate(sv_state *s, const sv_gate *g)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    if (int rc = validate_gates(g, 1, s->n)) return rc;
+    Launch L;
+    L.k = g->k;
+    int sq[SV_MAX_K];
+    if (int rc = gate_matrix_canonical(*g, L.m, sq)) return rc;
+    std::fill(L.q, L.q + SV_MAX_K, 0);
+    std::copy(sq, sq + g->k, L.q);
+    const int prec = s->dtype == SV_C64 ? SV_PREC_FP32 : SV_PREC_FP64;
+    L.path = choose_path(s->dtype, prec, L.k, L.q, s->n);
+    std::vector<Launch> v;
+    v.push_back(std::move(L));
+    if (int rc = select_device(s)) return rc;
+    return run_launches(s, v, false);
+}
+
+// ============================================================== fusion
+extern "C" int sv_fuse(const sv_gate *g, int G, int n, int max_k, int rule, sv_plan **out)
+{
+    clear_error();
+    if (!out) return fail(SV_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > SV_MAX_QUBITS_C64) return fail(SV_ERR_ARG, "n = %d outside 1..%d", n, SV_MAX_QUBITS_C64);
+    if (int rc = validate_gates(g, G, n)) return rc;
+    if (max_k == -1) {
+        if (int rc = choose_max_k(g, G, n, rule, SV_PREC_FP32, &max_k)) return rc;
+    }
+    auto *p = new sv_plan;
+    p->n = n;
+    p->max_k = max_k;
+    p->rule = rule;
+    int rc = fuse_gates(g, G, n, max_k, rule, lookup_costs(n, SV_PREC_FP32, nullptr), p->blocks);
+    if (rc) {
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return SV_OK;
+}
+
+extern "C" int sv_plan_free(sv_plan *p)
+{
+    delete p;
+    return SV_OK;
+}
+
+extern "C" int sv_plan_num_blocks(const sv_plan *p, int *out)
+{
+    clear_error();
+    if (!p || !out) return fail(SV_ERR_ARG, "NULL argument");
+    *out = int(p->blocks.size());
+    return SV_OK;
+}
+
+extern "C" int sv_plan_max_k(const sv_plan *p, int *out)
+{
+    clear_error();
+    if (!p || !out) return fail(SV_ERR_ARG, "NULL argument");
+    *out = p->max_k;
+    return SV_OK;
+}
+
+extern "C" int sv_plan_block(const sv_plan *p, int b, int32_t *k, int32_t *q, int32_t *n_members)
+{
+    clear_error();
+    if (!p) return fail(SV_ERR_ARG, "NULL plan");
+    if (b < 0 || b >= int(p->blocks.size())) return fail(SV_ERR_ARG, "block %d out of range", b);
+    const Block &B = p->blocks[b];
+    if (k) *k = B.k;
+    if (q)
+        for (int j = 0; j < SV_MAX_K; ++j) q[j] = j < B.k ? B.q[j] : -1;
+    if (n_members) *n_members = int(B.members.size());
+    return SV_OK;
+}
+
+extern "C" int sv_plan_block_members(const sv_plan *p, int b, int32_t *members)
+{
+    clear_error();
+    if (!p || !members) return fail(SV_ERR_ARG, "NULL argument");
+    if (b < 0 || b >= int(p->blocks.size())) return fail(SV_ERR_ARG, "block %d out of range", b);
+    const Block &B = p->blocks[b];
+    std::copy(B.members.begin(), B.members.end(), members);
+    return SV_OK;
+}
+
+extern "C" int sv_plan_block_matrix(const sv_plan *p, int b, double *m)
+{
+    clear_error();
+    if (!p || !m) return fail(SV_ERR_ARG, "NULL argument");
+    if (b < 0 || b >= int(p->blocks.size())) return fail(SV_ERR_ARG, "block %d out of range", b);
+    const Block &B = p->blocks[b];
+    std::vector<cd> abi;
+    reverse_local_bits(B.m, B.k, abi);
+    for (size_t i = 0; i < abi.size(); ++i) {
+        m[2 * i] = abi[i].real();
+        m[2 * i + 1] = abi[i].imag();
+    }
+    return SV_OK;
+}
+
+extern "C" int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int use_graph)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    if (!p) return fail(SV_ERR_ARG, "NULL plan");
+    if (int rc = check_precision(s, precision)) return rc;
+    for (const auto &b : p->blocks)
+        for (int j = 0; j < b.k; ++j)
+            if (b.q[j] >= s->n) return fail(SV_ERR_QUBIT, "plan position %d outside a %d-qubit state", b.q[j], s->n);
+    std::vector<Launch> L;
+    blocks_to_launches(p->blocks, s, precision, L);
+    if (int rc = select_device(s)) return rc;
+    return run_launches(s, L, use_graph != 0);
+}
+
+// ============================================================== circuits
+extern "C" int sv_run_circuit(sv_state *s, const sv_gate *g, int G, const sv_run_opts *o)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    sv_run_opts d;
+    d.max_k = SV_MAX_K;
+    d.precision = s->dtype == SV_C64 ? SV_PREC_FP32 : SV_PREC_FP64;
+    d.rule = SV_RULE_NONE;
+    d.use_graph = 0;
+    if (!o) o = &d;
+    if (int rc = check_precision(s, o->precision)) return rc;
+    if (int rc = validate_gates(g, G, s->n)) return rc;
+    int max_k = o->max_k;
+    if (max_k == -1) {
+        if (int rc = choose_max_k(g, G, s->n, o->rule, o->precision, &max_k)) return rc;
+    } else if (max_k < 1 || max_k > SV_MAX_K) {
+        return fail(SV_ERR_ARG, "max_k %d outside 1..%d (or -1)", max_k, SV_MAX_K);
+    }
+    std::vector<Block> blocks;
+    if (int rc = fuse_gates(g, G, s->n, max_k, o->rule, lookup_costs(s->n, o->precision, nullptr), blocks)) return rc;
+    std::vector<Launch> L;
+    blocks_to_launches(blocks, s, o->precision, L);
+    if (int rc = select_device(s)) return rc;
+    return run_launches(s, L, o->use_graph != 0);
+}
+
+// ============================================================== reductions
+namespace {
+
+int read_result(sv_state *s, const double *d_src, size_t count, double *out)
+{
+    SV_HIP(s->red_host.ensure(count * sizeof(double)));
+    SV_HIP(hipMemcpyAsync(s->red_host.p, d_src, count * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    SV_HIP(hipStreamSynchronize(s->stream));
+    std::memcpy(out, s->red_host.p, count * sizeof(double));
+    return SV_OK;
+}
+
+int check_pauli(const sv_pauli_sum *H, int n)
+{
+    if (!H) return fail(SV_ERR_ARG, "NULL Pauli sum");
+    if (H->n_terms < 0 || H->n_terms > SV_MAX_PAULI_TERMS)
+        return fail(SV_ERR_ARG, "Pauli sum with %d terms (0..%d)", H->n_terms, SV_MAX_PAULI_TERMS);
+    if (H->reserved != 0) return fail(SV_ERR_ARG, "sv_pauli_sum.reserved must be 0");
+    if (H->n_terms && (!H->coef || !H->xmask || !H->zmask)) return fail(SV_ERR_ARG, "NULL Pauli arrays");
+    const uint64_t bad = n >= 64 ? 0 : ~((uint64_t(1) << n) - 1);
+    for (int t = 0; t < H->n_terms; ++t) {
+        if ((H->xmask[t] | H->zmask[t]) & bad) return fail(SV_ERR_QUBIT, "Pauli term %d acts beyond qubit %d", t, n - 1);
+        if (!std::isfinite(H->coef[t])) return fail(SV_ERR_ARG, "non-finite Pauli coefficient");
+    }
+    return SV_OK;
+}
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Group terms by x mask, stage the tables and upload them into the arena.
+// The caller synchronised arena_free and records it after its launches.
+int pauli_tables(sv_state *s, const sv_pauli_sum *H, dev::PauliDev &P)
+{
+    const int nt = H->n_terms;
+    std::vector<int> order(nt);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return H->xmask[a] < H->xmask[b]; });
+    std::vector<uint64_t> gx;
+    std::vector<int32_t> goff;
+    for (int i = 0; i < nt; ++i) {
+        if (i == 0 || H->xmask[order[i]] != H->xmask[order[i - 1]]) {
+            gx.push_back(H->xmask[order[i]]);
+            goff.push_back(i);
+        }
+    }
+    goff.push_back(nt);
+    const int ng = int(gx.size());
+    const size_t o_gx = 0, o_goff = al256(o_gx + 8 * std::max(ng, 1)), o_tz = al256(o_goff + 4 * (ng + 1)),
+                 o_tc = al256(o_tz + 8 * std::max(nt, 1)), o_tp = al256(o_tc + 8 * std::max(nt, 1)),
+                 total = al256(o_tp + 4 * std::max(nt, 1));
+    SV_HIP(s->stage.ensure(total));
+    SV_HIP(s->arena.ensure(total));
+    char *h = static_cast<char *>(s->stage.p);
+    std::memcpy(h + o_gx, gx.data(), 8 * ng);
+    std::memcpy(h + o_goff, goff.data(), 4 * (ng + 1));
+    for (int i = 0; i < nt; ++i) {
+        const int t = order[i];
+        reinterpret_cast<uint64_t *>(h + o_tz)[i] = H->zmask[t];
+        reinterpret_cast<double *>(h + o_tc)[i] = H->coef[t];
+        reinterpret_cast<int32_t *>(h + o_tp)[i] = __builtin_popcountll(H->xmask[t] & H->zmask[t]) & 3;
+    }
+    SV_HIP(hipMemcpyAsync(s->arena.p, s->stage.p, total, hipMemcpyHostToDevice, s->stream));
+    char *d = static_cast<char *>(s->arena.p);
+    P.n_groups = ng;
+    P.gx = reinterpret_cast<const uint64_t *>(d + o_gx);
+    P.goff = reinterpret_cast<const int32_t *>(d + o_goff);
+    P.tz = reinterpret_cast<const uint64_t *>(d + o_tz);
+    P.tc = reinterpret_cast<const double *>(d + o_tc);
+    P.tpow = reinterpret_cast<const int32_t *>(d + o_tp);
+    return SV_OK;
+}
+
+}  // namespace
+
+extern "C" int sv_norm(sv_state *s, double *out)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    if (!out) return fail(SV_ERR_ARG, "NULL out");
+    if (int rc = select_device(s)) return rc;
+    double *part = static_cast<double *>(s->red.p);
+    double *res = part + 2 * dev::kRedBlocks;
+    {
+        LaunchTimer t(10 * FAM_REDUCE + 1, s->stream);
+        SV_HIP(dev::launch_norm(s->dtype, s->buf, s->n, part, res, s->stream));
+    }
+    return read_result(s, res, 1, out);
+}
+
+extern "C" int sv_inner(sv_state *a, sv_state *b, double *re, double *im)
+{
+    clear_error();
+    if (!a || !b || !re || !im) return fail(SV_ERR_ARG, "NULL argument");
+    if (a->n != b->n) return fail(SV_ERR_ARG, "qubit counts differ (%d vs %d)", a->n, b->n);
+    if (int rc = select_device(b)) return rc;
+    if (int rc = stream_after(b->stream, a->stream)) return rc;
+    double *part = static_cast<double *>(b->red.p);
+    double *res = part + 2 * dev::kRedBlocks;
+    {
+        LaunchTimer t(10 * FAM_REDUCE + 2, b->stream);
+        SV_HIP(dev::launch_inner(a->dtype, a->buf, b->dtype, b->buf, b->n, part, res, b->stream));
+    }
+    double v[2];
+    if (int rc = read_result(b, res, 2, v)) return rc;
+    *re = v[0];
+    *im = v[1];
+    return SV_OK;
+}
+
+extern "C" int sv_expectation(sv_state *s, const sv_pauli_sum *H, double *out)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    if (!out) return fail(SV_ERR_ARG, "NULL out");
+    if (int rc = check_pauli(H, s->n)) return rc;
+    if (H->n_terms == 0) {
+        *out = 0.0;
+        return SV_OK;
+    }
+    if (int rc = select_device(s)) return rc;
+    SV_HIP(hipEventSynchronize(s->arena_free));
+    dev::PauliDev P;
+    if (int rc = pauli_tables(s, H, P)) return rc;
+    double *part = static_cast<double *>(s->red.p);
+    double *res = part + 2 * dev::kRedBlocks;
+    {
+        LaunchTimer t(10 * FAM_REDUCE + 3, s->stream);
+        SV_HIP(dev::launch_pauli_expect(s->dtype, s->buf, s->n, P, part, res, s->stream));
+    }
+    SV_HIP(hipEventRecord(s->arena_free, s->stream));
+    return read_result(s, res, 1, out);
+}
+
+extern "C" int sv_apply_pauli_sum(sv_state *psi, const sv_pauli_sum *H, sv_state *out)
+{
+    clear_error();
+    if (!psi || !out) return fail(SV_ERR_ARG, "NULL state handle");
+    if (psi == out) return fail(SV_ERR_ARG, "output must be a different state");
+    if (psi->n != out->n || psi->dtype != out->dtype) return fail(SV_ERR_ARG, "states differ in n or type");
+    if (int rc = check_pauli(H, psi->n)) return rc;
+    if (int rc = select_device(psi)) return rc;
+    if (int rc = stream_after(psi->stream, out->stream)) return rc;
+    SV_HIP(hipEventSynchronize(psi->arena_free));
+    dev::PauliDev P;
+    if (H->n_terms == 0) {
+        SV_HIP(dev::launch_fill_basis(out->dtype, out->buf, out->n, ~uint64_t(0), psi->stream));
+    } else {
+        if (int rc = pauli_tables(psi, H, P)) return rc;
+        LaunchTimer t(10 * FAM_REDUCE + 4, psi->stream);
+        SV_HIP(dev::launch_pauli_apply(psi->dtype, psi->buf, out->buf, psi->n, P, psi->stream));
+    }
+    SV_HIP(hipEventRecord(psi->arena_free, psi->stream));
+    if (int rc = stream_after(out->stream, psi->stream)) return rc;
+    return SV_OK;
+}
+
+// ============================================================== adjoint
+extern "C" int sv_backward(sv_state *psi, sv_state *scratch, const sv_gate *g, int G, const sv_pauli_sum *H,
+                           double *grad, int n_params)
+{
+    clear_error();
+    if (!psi || !scratch) return fail(SV_ERR_ARG, "NULL state handle");
+    if (psi == scratch) return fail(SV_ERR_ARG, "scratch must be a different state");
+    if (psi->n != scratch->n || psi->dtype != scratch->dtype) return fail(SV_ERR_ARG, "states differ in n or type");
+    if (n_params < 0 || (n_params > 0 && !grad)) return fail(SV_ERR_ARG, "bad gradient buffer");
+    if (int rc = validate_gates(g, G, psi->n)) return rc;
+    if (int rc = check_pauli(H, psi->n)) return rc;
+    int slots = 0;
+    for (int i = 0; i < G; ++i) {
+        if (g[i].k > 2) return fail(SV_ERR_UNSUPPORTED, "gate %d: the adjoint pass handles gates of at most 2 qubits", i);
+        if (g[i].param >= n_params) return fail(SV_ERR_ARG, "gate %d: param %d >= n_params %d", i, g[i].param, n_params);
+        slots += g[i].param >= 0;
+    }
+    if (int rc = select_device(psi)) return rc;
+    // lam <- H psi on psi's stream
+    if (int rc = sv_apply_pauli_sum(psi, H, scratch)) return rc;
+    const size_t part_doubles = size_t(std::max(slots, 1)) * dev::kRedBlocks * 2;
+    SV_HIP(psi->grad.ensure((part_doubles + 2 * size_t(std::max(slots, 1))) * sizeof(double)));
+    double *part = static_cast<double *>(psi->grad.p);
+    double *sums = part + part_doubles;
+    std::vector<int> slot_param;
+    slot_param.reserve(slots);
+    for (int i = G - 1; i >= 0; --i) {
+        std::vector<cd> m, mdag;
+        int sq[SV_MAX_K];
+        if (int rc = gate_matrix_canonical(g[i], m, sq)) return rc;
+        const int D = 1 << g[i].k;
+        mdag.resize(m.size());
+        for (int r = 0; r < D; ++r)
+            for (int c = 0; c < D; ++c) mdag[size_t(r) * D + c] = std::conj(m[size_t(c) * D + r]);
+        int pauli = 0, slot = -1;
+        if (g[i].param >= 0) {
+            pauli = g[i].kind == SV_G_RX ? 1 : g[i].kind == SV_G_RY ? 2 : 3;
+            slot = int(slot_param.size());
+            slot_param.push_back(g[i].param);
+        }
+        LaunchTimer t(10 * FAM_ADJOINT + g[i].k, psi->stream);
+        SV_HIP(dev::launch_backward_step(psi->dtype, g[i].k, sq, mdag.data(), pauli, psi->buf, scratch->buf, psi->n,
+                                         part, slot, psi->stream));
+    }
+    if (slots) {
+        SV_HIP(dev::launch_sum_partials(part, slots, sums, psi->stream));
+        std::vector<double> h(2 * size_t(slots));
+        if (int rc = read_result(psi, sums, h.size(), h.data())) return rc;
+        for (int sl = 0; sl < slots; ++sl) grad[slot_param[sl]] += h[2 * sl + 1];  // Im <lam|P|phi>
+    } else {
+        SV_HIP(hipStreamSynchronize(psi->stream));
+    }
+    if (int rc = stream_after(scratch->stream, psi->stream)) return rc;
+    return SV_OK;
+}
+
+// ============================================================== stats
+extern "C" int sv_stats_enable(int on)
+{
+    clear_error();
+    return stats_enable(on);
+}
+extern "C" int sv_stats_reset(void)
+{
+    clear_error();
+    return stats_reset();
+}
+extern "C" int sv_stats_query(int cls, int64_t *launches, double *total_ms)
+{
+    clear_error();
+    if (!launches || !total_ms) return fail(SV_ERR_ARG, "NULL argument");
+    return stats_query(cls, launches, total_ms);
+}

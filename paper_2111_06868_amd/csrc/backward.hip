@@ -1,0 +1,181 @@
+// Adjoint-method backward step (one gate, two states in one pass).
+//
+// E(theta) = <psi|H|psi>, psi = U_G..U_1 psi_0.  With phi = U_{g+1}^+..U_G^+ psi
+// and lam = U_{g+1}^+..U_G^+ H psi, and a rotation U_g = exp(-i theta P / 2),
+//   dE/dtheta_g = 2 Re <lam| dU_g/dtheta |phi_{g-1}> = 2 Re <lam| (-i/2) P |phi>
+//               = Im <lam|P|phi>,
+// evaluated before both states move one gate back (phi <- U_g^+ phi,
+// lam <- U_g^+ lam).  One kernel per gate reads both states once, adds the
+// group's share of <lam|P|phi> (FP64) to a per-block partial, and writes both
+// updated states: two buffers, no stored trajectory.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace sv {
+namespace dev {
+
+namespace {
+
+template <typename T, int K>
+struct BwdArgs {
+    T mr[(1 << K) * (1 << K)];
+    T mi[(1 << K) * (1 << K)];
+    int pos[K];
+    int pauli;
+    uint64_t n_groups;
+    double pmat[8];  // generator P as a 2x2 complex matrix (re, im), row-major
+};
+
+__device__ __forceinline__ uint64_t insert_zero_b(uint64_t x, int p)
+{
+    return ((x >> p) << (p + 1)) | (x & ((uint64_t(1) << p) - 1));
+}
+
+template <typename T, int K>
+__device__ __forceinline__ void matvec(const BwdArgs<T, K> &a, const T *vr, const T *vi, T *orr, T *oi)
+{
+    constexpr int D = 1 << K;
+#pragma unroll
+    for (int m = 0; m < D; ++m) {
+        T sr = 0, si = 0;
+#pragma unroll
+        for (int mp = 0; mp < D; ++mp) {
+            const T ar = a.mr[m * D + mp], ai = a.mi[m * D + mp];
+            sr = fma(ar, vr[mp], sr);
+            sr = fma(-ai, vi[mp], sr);
+            si = fma(ar, vi[mp], si);
+            si = fma(ai, vr[mp], si);
+        }
+        orr[m] = sr;
+        oi[m] = si;
+    }
+}
+
+template <typename T, int K>
+__global__ void __launch_bounds__(kRedThreads) k_backward(T *__restrict__ phi, T *__restrict__ lam,
+                                                         const BwdArgs<T, K> a, double *__restrict__ partials)
+{
+    constexpr int D = 1 << K;
+    double gr = 0.0, gi = 0.0;
+    for (uint64_t g = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; g < a.n_groups;
+         g += uint64_t(kRedBlocks) * kRedThreads) {
+        uint64_t base = g;
+#pragma unroll
+        for (int j = 0; j < K; ++j) base = insert_zero_b(base, a.pos[j]);
+        uint64_t idx[D];
+        T fr[D], fi[D], lr[D], li[D];
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            uint64_t o = base;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if ((m >> j) & 1) o += uint64_t(1) << a.pos[j];
+            idx[m] = o;
+            fr[m] = phi[2 * o];
+            fi[m] = phi[2 * o + 1];
+            lr[m] = lam[2 * o];
+            li[m] = lam[2 * o + 1];
+        }
+        if (K == 1 && a.pauli) {
+            // s = <lam|P|phi> restricted to this group, P (2x2, on local bit 0)
+            // given as a matrix: (P phi)_r = sum_c P[r][c] phi_c
+            double pr[2], pi[2];
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                pr[r] = 0.0;
+                pi[r] = 0.0;
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const double gr_ = a.pmat[4 * r + 2 * c], gi_ = a.pmat[4 * r + 2 * c + 1];
+                    const double vr = fr[c * (D - 1)], vi = fi[c * (D - 1)];
+                    pr[r] += gr_ * vr - gi_ * vi;
+                    pi[r] += gr_ * vi + gi_ * vr;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 2; ++r) {
+                const double ur = lr[r * (D - 1)], ui = li[r * (D - 1)];
+                // conj(lam_r) * (P phi)_r
+                gr += ur * pr[r] + ui * pi[r];
+                gi += ur * pi[r] - ui * pr[r];
+            }
+        }
+        T or_[D], oi[D];
+        matvec<T, K>(a, fr, fi, or_, oi);
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            phi[2 * idx[m]] = or_[m];
+            phi[2 * idx[m] + 1] = oi[m];
+        }
+        matvec<T, K>(a, lr, li, or_, oi);
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            lam[2 * idx[m]] = or_[m];
+            lam[2 * idx[m] + 1] = oi[m];
+        }
+    }
+    if (a.pauli) {
+        __shared__ double sr[kRedThreads], si[kRedThreads];
+        const int t = threadIdx.x;
+        sr[t] = gr;
+        si[t] = gi;
+        __syncthreads();
+        for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+            if (t < s) {
+                sr[t] += sr[t + s];
+                si[t] += si[t + s];
+            }
+            __syncthreads();
+        }
+        if (t == 0) {
+            partials[2 * blockIdx.x] = sr[0];
+            partials[2 * blockIdx.x + 1] = si[0];
+        }
+    }
+}
+
+template <typename T, int K>
+hipError_t bwd_launch_t(const int *sorted_q, const cd *mdag, int pauli, T *phi, T *lam, int n, double *d_partials,
+                        int slot, hipStream_t st)
+{
+    BwdArgs<T, K> a;
+    constexpr int D = 1 << K;
+    for (int i = 0; i < D * D; ++i) {
+        a.mr[i] = T(mdag[i].real());
+        a.mi[i] = T(mdag[i].imag());
+    }
+    for (int j = 0; j < K; ++j) a.pos[j] = sorted_q[j];
+    a.pauli = pauli;
+    // X, Y, Z as 2x2 complex matrices
+    static const double P[4][8] = {{0, 0, 0, 0, 0, 0, 0, 0},
+                                   {0, 0, 1, 0, 1, 0, 0, 0},
+                                   {0, 0, 0, -1, 0, 1, 0, 0},
+                                   {1, 0, 0, 0, 0, 0, -1, 0}};
+    for (int i = 0; i < 8; ++i) a.pmat[i] = P[pauli & 3][i];
+    a.n_groups = uint64_t(1) << (n - K);
+    double *part = d_partials + size_t(slot < 0 ? 0 : slot) * kRedBlocks * 2;
+    hipLaunchKernelGGL((k_backward<T, K>), dim3(kRedBlocks), dim3(kRedThreads), 0, st, phi, lam, a, part);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_backward_step(int dtype, int k, const int *sorted_q, const cd *mdag, int pauli, void *phi,
+                                void *lam, int n, double *d_partials, int slot, hipStream_t st)
+{
+    if (n < k || (pauli && k != 1)) return hipErrorInvalidValue;
+    if (dtype == SV_C64) {
+        float *f = static_cast<float *>(phi), *l = static_cast<float *>(lam);
+        if (k == 1) return bwd_launch_t<float, 1>(sorted_q, mdag, pauli, f, l, n, d_partials, slot, st);
+        if (k == 2) return bwd_launch_t<float, 2>(sorted_q, mdag, pauli, f, l, n, d_partials, slot, st);
+        return hipErrorInvalidValue;
+    }
+    double *f = static_cast<double *>(phi), *l = static_cast<double *>(lam);
+    if (k == 1) return bwd_launch_t<double, 1>(sorted_q, mdag, pauli, f, l, n, d_partials, slot, st);
+    if (k == 2) return bwd_launch_t<double, 2>(sorted_q, mdag, pauli, f, l, n, d_partials, slot, st);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace dev
+}  // namespace sv

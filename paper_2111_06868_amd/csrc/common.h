@@ -1,0 +1,74 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/sv.h"
+
+namespace sv {
+
+using cd = std::complex<double>;
+
+// ---------------------------------------------------------------- errors
+// Record a message for sv_last_error() and return `code`.
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+// ---------------------------------------------------------------- gates
+// Arity of a named gate kind (0 for SV_G_MATRIX, -1 for an unknown kind).
+int gate_arity(int kind);
+// Validate kind / k / params (not positions).
+int check_gate_shape(const sv_gate &g);
+// Validate positions against n: in range and pairwise distinct.
+int check_gate_qubits(const sv_gate &g, int n);
+// 2^k x 2^k matrix in the ABI order (q[0] = most significant local bit).
+int gate_matrix_abi(const sv_gate &g, std::vector<cd> &out);
+// Gate matrix and positions in CANONICAL order: positions sorted ascending,
+// local bit j <-> j-th lowest position.
+int gate_matrix_canonical(const sv_gate &g, std::vector<cd> &m, int *sorted_q);
+// Convert between the ABI order of a block whose positions q[0..k-1] are
+// already ascending (q[0] most significant) and the canonical order (q[0]
+// least significant): a bit reversal of the local index, an involution.
+void reverse_local_bits(const std::vector<cd> &in, int k, std::vector<cd> &out);
+
+// ---------------------------------------------------------------- fusion
+struct Block {
+    int k = 0;
+    int q[SV_MAX_K] = {0};       // ascending positions
+    std::vector<int> members;    // gate indices, in circuit order
+    std::vector<cd> m;           // canonical 2^k x 2^k matrix (row-major)
+};
+
+struct CostTable {
+    bool valid = false;
+    double ms[SV_MAX_K + 1] = {0};
+};
+
+// Cost table used when no autotuned table exists (relative units).
+CostTable default_costs();
+// Lookup of an autotuned table for (n, precision); falls back to defaults.
+CostTable lookup_costs(int n, int precision, bool *found);
+void store_costs(int n, int precision, const double *ms);
+
+// Greedy fusion.  Gates must be validated first.  `cost` steers the
+// enhanced rule.  Fills blocks (with canonical matrices).
+int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTable &cost,
+               std::vector<Block> &blocks);
+double plan_cost(const std::vector<Block> &blocks, const CostTable &cost);
+
+// Canonical matrix of a block from its member gates.
+void block_matrix(const sv_gate *g, Block &b);
+
+}  // namespace sv
+
+struct sv_plan {
+    int n = 0;
+    int max_k = 0;
+    int rule = 0;
+    std::vector<sv::Block> blocks;
+    // device-side cache (filled by the runtime when the plan is applied)
+    void *cache = nullptr;
+};

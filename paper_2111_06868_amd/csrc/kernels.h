@@ -1,0 +1,85 @@
+// Launchers of the gfx950 kernels (device code lives in the *.hip files).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "common.h"
+
+namespace sv {
+namespace dev {
+
+constexpr int kRedBlocks = 1024;  // fixed first-stage grid of every reduction
+constexpr int kRedThreads = 256;
+
+// ------------------------------------------------------------------ apply
+// Register kernel: k <= 3 (k = 4 for complex64), canonical matrix (local bit
+// j <-> sorted_q[j]).  Needs n >= 2 + (number of positions >= 2).
+bool reg_supported(int dtype, int k, const int *sorted_q, int n);
+hipError_t launch_reg(int dtype, int k, const int *sorted_q, const cd *m, void *psi, int n,
+                      hipStream_t st, int grid_cap);
+// Generic kernel: k = 1..6, canonical matrix already on the device in the
+// state's real type (interleaved re, im).
+hipError_t launch_generic(int dtype, int k, const int *sorted_q, const void *d_m, void *psi, int n,
+                          hipStream_t st);
+// Dense-block MFMA kernels (complex64 state).  k = 4..6, n - k >= 5.
+bool mfma_supported(int k, int n);
+// FP32: d_a = real-form matrix (2^(k+1) x 2^(k+1) floats, see mfma.hip).
+hipError_t launch_mfma_f32(int k, const int *sorted_q, const float *d_a, void *psi, int n,
+                           hipStream_t st, int tc_log, int grid_cap);
+// Split precision: d_ahi / d_alo = hi and lo parts of the real-form matrix as
+// BF16 (fp16 = false) or FP16 (fp16 = true) bit patterns.
+hipError_t launch_mfma_split(int k, bool fp16, const int *sorted_q, const uint16_t *d_ahi,
+                             const uint16_t *d_alo, void *psi, int n, hipStream_t st, int tc_log,
+                             int grid_cap);
+// Host-side packing of the MFMA operands of a canonical k-qubit matrix.
+void pack_real_form_f32(const cd *m, int k, float *out);
+void pack_real_form_split(const cd *m, int k, bool fp16, uint16_t *hi, uint16_t *lo);
+size_t real_form_elems(int k);
+
+// ------------------------------------------------------------------ state init / copy
+hipError_t launch_fill_basis(int dtype, void *psi, int n, uint64_t index, hipStream_t st);
+// amps[4*p .. 4*p+3] = (re0, im0, re1, im1) of the one-qubit factor at position p
+hipError_t launch_product(int dtype, void *psi, int n, const double *amps, hipStream_t st);
+hipError_t launch_convert(int src_dtype, const void *src, int dst_dtype, void *dst, uint64_t count,
+                          hipStream_t st);
+
+// ------------------------------------------------------------------ reductions
+// All write their FP64 result (1 or 2 doubles) to d_out, using d_partials
+// (2 * kRedBlocks doubles) as the first-stage buffer.
+hipError_t launch_norm(int dtype, const void *psi, int n, double *d_partials, double *d_out,
+                       hipStream_t st);
+hipError_t launch_inner(int dtype_a, const void *a, int dtype_b, const void *b, int n,
+                        double *d_partials, double *d_out, hipStream_t st);
+// Pauli terms grouped by x mask: group g covers terms [goff[g], goff[g+1]) all
+// with x mask gx[g]; per term the z mask, the coefficient and the power of i
+// (number of Y factors mod 4).  Device arrays.
+struct PauliDev {
+    int n_groups;
+    const uint64_t *gx;
+    const int32_t *goff;
+    const uint64_t *tz;
+    const double *tc;
+    const int32_t *tpow;
+};
+hipError_t launch_pauli_expect(int dtype, const void *psi, int n, const PauliDev &H, double *d_partials,
+                               double *d_out, hipStream_t st);
+hipError_t launch_pauli_apply(int dtype, const void *psi, void *out, int n, const PauliDev &H,
+                              hipStream_t st);
+
+// ------------------------------------------------------------------ adjoint
+// One backward step for a k <= 2 gate: if pauli >= 1 (1 = X, 2 = Y, 3 = Z on
+// sorted_q[0]), d_partials[slot * kRedBlocks + block] receives the block's
+// partial of <lam|P|phi> (re, im: 2 doubles per block); then phi <- U^+ phi and
+// lam <- U^+ lam, U^+ given canonically in `mdag`.
+hipError_t launch_backward_step(int dtype, int k, const int *sorted_q, const cd *mdag, int pauli,
+                                void *phi, void *lam, int n, double *d_partials, int slot,
+                                hipStream_t st);
+// out[s] = sum over blocks of d_partials[s][*] (fixed order), s < n_slots.
+hipError_t launch_sum_partials(const double *d_partials, int n_slots, double *d_out, hipStream_t st);
+
+// ------------------------------------------------------------------ batches
+struct BatchTables;  // defined in batch.hip
+}  // namespace dev
+}  // namespace sv

@@ -1,0 +1,230 @@
+// FP64 reductions over a state: norm, inner product, Pauli-sum expectation,
+// and the Pauli-sum matvec used by the adjoint method.
+//
+// Every reduction is a fixed-shape two-stage tree (kRedBlocks x kRedThreads
+// first stage with a fixed grid-stride assignment, LDS tree inside a block,
+// then one block summing the partials in a fixed order), so results are
+// bitwise reproducible run to run.  Amplitudes are widened to FP64 before any
+// product.
+//
+// Pauli strings: P = i^{#Y} X^x Z^z (per qubit Y = i X Z), hence
+//   (P psi)[i] = i^{#Y} (-1)^{popcount((i ^ x) & z)} psi[i ^ x].
+// Terms are grouped by their x mask on the host so that each partner
+// amplitude psi[i ^ x] is loaded once per group.
+#include <hip/hip_runtime.h>
+
+#include "kernels.h"
+
+namespace sv {
+namespace dev {
+
+namespace {
+
+template <int C>
+struct Acc {
+    double v[C];
+};
+
+template <int C>
+__device__ __forceinline__ void block_reduce_store(Acc<C> a, double *__restrict__ out)
+{
+    __shared__ double sh[C][kRedThreads];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int c = 0; c < C; ++c) sh[c][t] = a.v[c];
+    __syncthreads();
+    for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+        if (t < s) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) sh[c][t] += sh[c][t + s];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[c] = sh[c][0];
+    }
+}
+
+__device__ __forceinline__ void ld(const float *p, uint64_t i, double &re, double &im)
+{
+    const float2 v = reinterpret_cast<const float2 *>(p)[i];
+    re = v.x;
+    im = v.y;
+}
+__device__ __forceinline__ void ld(const double *p, uint64_t i, double &re, double &im)
+{
+    const double2 v = reinterpret_cast<const double2 *>(p)[i];
+    re = v.x;
+    im = v.y;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) k_norm(const T *__restrict__ psi, uint64_t N, double *partials)
+{
+    Acc<1> a{{0.0}};
+    for (uint64_t i = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; i < N; i += uint64_t(kRedBlocks) * kRedThreads) {
+        double r, m;
+        ld(psi, i, r, m);
+        a.v[0] = fma(r, r, fma(m, m, a.v[0]));
+    }
+    block_reduce_store<1>(a, partials + blockIdx.x);
+}
+
+template <typename A, typename B>
+__global__ void __launch_bounds__(kRedThreads) k_inner(const A *__restrict__ a, const B *__restrict__ b, uint64_t N,
+                                                      double *partials)
+{
+    Acc<2> s{{0.0, 0.0}};
+    for (uint64_t i = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; i < N; i += uint64_t(kRedBlocks) * kRedThreads) {
+        double ar, ai, br, bi;
+        ld(a, i, ar, ai);
+        ld(b, i, br, bi);
+        // conj(a) * b
+        s.v[0] = fma(ar, br, fma(ai, bi, s.v[0]));
+        s.v[1] = fma(ar, bi, fma(-ai, br, s.v[1]));
+    }
+    block_reduce_store<2>(s, partials + 2 * blockIdx.x);
+}
+
+// weight of group g at partner index j: sum_t c_t i^{pow_t} (-1)^{popcount(j & z_t)}
+__device__ __forceinline__ void group_weight(const PauliDev &H, int g, uint64_t j, double &wr, double &wi)
+{
+    wr = 0.0;
+    wi = 0.0;
+    for (int t = H.goff[g]; t < H.goff[g + 1]; ++t) {
+        double c = H.tc[t];
+        if (__popcll(j & H.tz[t]) & 1) c = -c;
+        switch (H.tpow[t] & 3) {
+        case 0: wr += c; break;
+        case 1: wi += c; break;
+        case 2: wr -= c; break;
+        default: wi -= c; break;
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) k_pauli_expect(const T *__restrict__ psi, uint64_t N, const PauliDev H,
+                                                             double *partials)
+{
+    Acc<1> a{{0.0}};
+    for (uint64_t i = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; i < N; i += uint64_t(kRedBlocks) * kRedThreads) {
+        double cr, ci;
+        ld(psi, i, cr, ci);
+        double sr = 0.0, si = 0.0;
+        for (int g = 0; g < H.n_groups; ++g) {
+            const uint64_t j = i ^ H.gx[g];
+            double pr, pi, wr, wi;
+            ld(psi, j, pr, pi);
+            group_weight(H, g, j, wr, wi);
+            sr = fma(wr, pr, fma(-wi, pi, sr));
+            si = fma(wr, pi, fma(wi, pr, si));
+        }
+        // Re(conj(psi_i) * s)
+        a.v[0] = fma(cr, sr, fma(ci, si, a.v[0]));
+    }
+    block_reduce_store<1>(a, partials + blockIdx.x);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_pauli_apply(const T *__restrict__ psi, T *__restrict__ out, uint64_t N,
+                                                    const PauliDev H)
+{
+    const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
+    for (uint64_t i = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+        double sr = 0.0, si = 0.0;
+        for (int g = 0; g < H.n_groups; ++g) {
+            const uint64_t j = i ^ H.gx[g];
+            double pr, pi, wr, wi;
+            ld(psi, j, pr, pi);
+            group_weight(H, g, j, wr, wi);
+            sr = fma(wr, pr, fma(-wi, pi, sr));
+            si = fma(wr, pi, fma(wi, pr, si));
+        }
+        out[2 * i] = T(sr);
+        out[2 * i + 1] = T(si);
+    }
+}
+
+// Second stage: sums C-component partials of `nb` blocks for `slots` slots
+// (one workgroup per slot) in a fixed order.
+template <int C>
+__global__ void __launch_bounds__(kRedThreads) k_final(const double *__restrict__ partials, int nb, double *out)
+{
+    const double *p = partials + size_t(blockIdx.x) * nb * C;
+    Acc<C> a;
+#pragma unroll
+    for (int c = 0; c < C; ++c) a.v[c] = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kRedThreads) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) a.v[c] += p[size_t(i) * C + c];
+    }
+    block_reduce_store<C>(a, out + size_t(blockIdx.x) * C);
+}
+
+}  // namespace
+
+hipError_t launch_norm(int dtype, const void *psi, int n, double *d_partials, double *d_out, hipStream_t st)
+{
+    const uint64_t N = uint64_t(1) << n;
+    if (dtype == SV_C64)
+        hipLaunchKernelGGL(k_norm<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<const float *>(psi), N, d_partials);
+    else
+        hipLaunchKernelGGL(k_norm<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<const double *>(psi), N, d_partials);
+    hipLaunchKernelGGL(k_final<1>, dim3(1), dim3(kRedThreads), 0, st, d_partials, kRedBlocks, d_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_inner(int dtype_a, const void *a, int dtype_b, const void *b, int n, double *d_partials,
+                        double *d_out, hipStream_t st)
+{
+    const uint64_t N = uint64_t(1) << n;
+    const dim3 g(kRedBlocks), t(kRedThreads);
+    if (dtype_a == SV_C64 && dtype_b == SV_C64)
+        hipLaunchKernelGGL((k_inner<float, float>), g, t, 0, st, static_cast<const float *>(a), static_cast<const float *>(b), N, d_partials);
+    else if (dtype_a == SV_C64)
+        hipLaunchKernelGGL((k_inner<float, double>), g, t, 0, st, static_cast<const float *>(a), static_cast<const double *>(b), N, d_partials);
+    else if (dtype_b == SV_C64)
+        hipLaunchKernelGGL((k_inner<double, float>), g, t, 0, st, static_cast<const double *>(a), static_cast<const float *>(b), N, d_partials);
+    else
+        hipLaunchKernelGGL((k_inner<double, double>), g, t, 0, st, static_cast<const double *>(a), static_cast<const double *>(b), N, d_partials);
+    hipLaunchKernelGGL(k_final<2>, dim3(1), dim3(kRedThreads), 0, st, d_partials, kRedBlocks, d_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pauli_expect(int dtype, const void *psi, int n, const PauliDev &H, double *d_partials,
+                               double *d_out, hipStream_t st)
+{
+    const uint64_t N = uint64_t(1) << n;
+    if (dtype == SV_C64)
+        hipLaunchKernelGGL(k_pauli_expect<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<const float *>(psi), N, H, d_partials);
+    else
+        hipLaunchKernelGGL(k_pauli_expect<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<const double *>(psi), N, H, d_partials);
+    hipLaunchKernelGGL(k_final<1>, dim3(1), dim3(kRedThreads), 0, st, d_partials, kRedBlocks, d_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pauli_apply(int dtype, const void *psi, void *out, int n, const PauliDev &H, hipStream_t st)
+{
+    const uint64_t N = uint64_t(1) << n;
+    uint64_t blocks = (N + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (dtype == SV_C64)
+        hipLaunchKernelGGL(k_pauli_apply<float>, dim3(unsigned(blocks)), dim3(256), 0, st, static_cast<const float *>(psi),
+                           static_cast<float *>(out), N, H);
+    else
+        hipLaunchKernelGGL(k_pauli_apply<double>, dim3(unsigned(blocks)), dim3(256), 0, st, static_cast<const double *>(psi),
+                           static_cast<double *>(out), N, H);
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double *d_partials, int n_slots, double *d_out, hipStream_t st)
+{
+    if (n_slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_final<2>, dim3(n_slots), dim3(kRedThreads), 0, st, d_partials, kRedBlocks, d_out);
+    return hipGetLastError();
+}
+
+}  // namespace dev
+}  // namespace sv

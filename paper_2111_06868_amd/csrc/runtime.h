@@ -1,0 +1,115 @@
+// Runtime pieces shared by the API translation units: state handle, device
+// buffers, launch timing, kernel-path selection and tuning knobs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <vector>
+
+#include "kernels.h"
+
+#define SV_HIP(expr)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return sv::fail(SV_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+namespace sv {
+
+// Growable device buffer (hipMalloc; freed on destruction).
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes);
+    void release();
+    ~DevBuf() { release(); }
+};
+
+// Growable pinned host buffer.
+struct PinBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes);
+    void release();
+    ~PinBuf() { release(); }
+};
+
+// Kernel classes for timing (10 * family + k).
+enum Family {
+    FAM_REG = 1,
+    FAM_GENERIC = 2,
+    FAM_MFMA32 = 3,
+    FAM_SPLIT_BF16 = 4,
+    FAM_SPLIT_FP16 = 5,
+    FAM_REDUCE = 6,
+    FAM_ADJOINT = 7,
+    FAM_BATCH = 8,
+};
+
+// RAII: brackets one launch with HIP events on `st` when timing is enabled.
+class LaunchTimer {
+  public:
+    LaunchTimer(int cls, hipStream_t st);
+    ~LaunchTimer();
+    LaunchTimer(const LaunchTimer &) = delete;
+    LaunchTimer &operator=(const LaunchTimer &) = delete;
+
+  private:
+    int cls_;
+    hipStream_t st_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+// Suspend timing (inside graph capture).
+void timing_suspend(bool on);
+
+// Kernel paths for a block.
+enum Path { PATH_REG, PATH_GENERIC, PATH_MFMA32, PATH_SPLIT_BF16, PATH_SPLIT_FP16 };
+
+struct Tuning {
+    int reg_grid_cap[SV_MAX_K + 1];   // 0 = one thread per group
+    int mfma_tc_log[SV_MAX_K + 1];    // log2 columns per tile
+    int mfma_grid_cap[SV_MAX_K + 1];
+    int split_tc_log[SV_MAX_K + 1];
+    bool k4_reg;                      // FP32: k = 4 via the register kernel
+};
+Tuning &tuning();
+Path choose_path(int dtype, int precision, int k, const int *sorted_q, int n);
+int path_family(Path p);
+
+// One block prepared for launch.
+struct Launch {
+    Path path;
+    int k;
+    int q[SV_MAX_K];
+    std::vector<cd> m;     // canonical matrix (register path)
+    size_t arena_off = 0;  // byte offset of device operands (other paths)
+    size_t arena_off2 = 0; // second operand (split lo part)
+};
+
+// Pack the device operands of `launches` into `stage` (host) and return the
+// total byte count; offsets are written into the launches.
+size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage);
+// Enqueue the launches on `st` with device operands at `arena`.
+int enqueue(const std::vector<Launch> &launches, int dtype, void *psi, int n, const void *arena,
+            hipStream_t st);
+
+}  // namespace sv
+
+struct sv_state {
+    int n = 0;
+    int dtype = SV_C64;
+    void *buf = nullptr;
+    size_t bytes = 0;
+    bool owns = false;
+    hipStream_t stream = nullptr;
+    hipStream_t capture_stream = nullptr;
+    int device = 0;
+    sv::DevBuf red;        // reduction partials + result
+    sv::PinBuf red_host;   // pinned result readback
+    sv::DevBuf arena;      // device operands (matrices, Pauli tables)
+    sv::PinBuf stage;      // pinned staging of the operands
+    hipEvent_t arena_free = nullptr;  // recorded after the last launch reading the arena
+    sv::DevBuf grad;       // adjoint partials
+};

@@ -1,0 +1,295 @@
+// Runtime: buffers, launch timing, kernel-path choice, operand packing and
+// launch sequencing for fused plans.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+
+#include "runtime.h"
+
+namespace sv {
+
+// ---------------------------------------------------------------- buffers
+hipError_t DevBuf::ensure(size_t bytes)
+{
+    if (bytes <= cap) return hipSuccess;
+    release();
+    size_t want = std::max(bytes, size_t(4096));
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        p = nullptr;
+        return e;
+    }
+    cap = want;
+    return hipSuccess;
+}
+
+void DevBuf::release()
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+}
+
+hipError_t PinBuf::ensure(size_t bytes)
+{
+    if (bytes <= cap) return hipSuccess;
+    release();
+    size_t want = std::max(bytes, size_t(4096));
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        p = nullptr;
+        return e;
+    }
+    cap = want;
+    return hipSuccess;
+}
+
+void PinBuf::release()
+{
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+}
+
+// ---------------------------------------------------------------- timing
+namespace {
+struct Pending {
+    int cls;
+    hipEvent_t a, b;
+};
+struct StatsState {
+    std::mutex mu;
+    bool on = false;
+    bool suspended = false;
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> free_events;
+    std::map<int, std::pair<int64_t, double>> totals;
+};
+StatsState &stats()
+{
+    static StatsState s;
+    return s;
+}
+hipEvent_t take_event(StatsState &s)
+{
+    if (!s.free_events.empty()) {
+        hipEvent_t e = s.free_events.back();
+        s.free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+// Fold pending launches into the totals (synchronises on their events).
+int drain(StatsState &s)
+{
+    int rc = SV_OK;
+    for (auto &p : s.pending) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(p.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, p.a, p.b);
+        if (e != hipSuccess) {
+            rc = fail(SV_ERR_HIP, "launch timing: %s", hipGetErrorString(e));
+        } else {
+            auto &t = s.totals[p.cls];
+            t.first += 1;
+            t.second += ms;
+        }
+        s.free_events.push_back(p.a);
+        s.free_events.push_back(p.b);
+    }
+    s.pending.clear();
+    return rc;
+}
+}  // namespace
+
+LaunchTimer::LaunchTimer(int cls, hipStream_t st) : cls_(cls), st_(st)
+{
+    auto &s = stats();
+    std::lock_guard<std::mutex> lk(s.mu);
+    if (!s.on || s.suspended) return;
+    a_ = take_event(s);
+    b_ = take_event(s);
+    if (a_ && b_) (void)hipEventRecord(a_, st_);
+}
+
+LaunchTimer::~LaunchTimer()
+{
+    if (!a_ || !b_) return;
+    auto &s = stats();
+    std::lock_guard<std::mutex> lk(s.mu);
+    (void)hipEventRecord(b_, st_);
+    s.pending.push_back({cls_, a_, b_});
+    if (s.pending.size() > 4096) drain(s);
+}
+
+void timing_suspend(bool on)
+{
+    auto &s = stats();
+    std::lock_guard<std::mutex> lk(s.mu);
+    s.suspended = on;
+}
+
+int stats_enable(int on)
+{
+    auto &s = stats();
+    std::lock_guard<std::mutex> lk(s.mu);
+    s.on = on != 0;
+    return SV_OK;
+}
+
+int stats_reset()
+{
+    auto &s = stats();
+    std::lock_guard<std::mutex> lk(s.mu);
+    int rc = drain(s);
+    s.totals.clear();
+    return rc;
+}
+
+int stats_query(int cls, int64_t *launches, double *total_ms)
+{
+    auto &s = stats();
+    std::lock_guard<std::mutex> lk(s.mu);
+    int rc = drain(s);
+    auto it = s.totals.find(cls);
+    *launches = it == s.totals.end() ? 0 : it->second.first;
+    *total_ms = it == s.totals.end() ? 0.0 : it->second.second;
+    return rc;
+}
+
+// ---------------------------------------------------------------- paths
+Tuning &tuning()
+{
+    static Tuning t = [] {
+        Tuning x;
+        for (int k = 0; k <= SV_MAX_K; ++k) {
+            x.reg_grid_cap[k] = 8192;
+            x.mfma_tc_log[k] = 6;
+            x.mfma_grid_cap[k] = 2048;
+            x.split_tc_log[k] = 6;
+        }
+        x.mfma_tc_log[4] = 7;
+        x.split_tc_log[4] = 7;
+        x.mfma_tc_log[6] = 5;
+        x.split_tc_log[6] = 5;
+        x.k4_reg = false;
+        return x;
+    }();
+    return t;
+}
+
+Path choose_path(int dtype, int precision, int k, const int *q, int n)
+{
+    if (dtype == SV_C128) return dev::reg_supported(dtype, k, q, n) ? PATH_REG : PATH_GENERIC;
+    if (k >= 4 && dev::mfma_supported(k, n)) {
+        if (precision == SV_PREC_SPLIT_BF16) return PATH_SPLIT_BF16;
+        if (precision == SV_PREC_SPLIT_FP16) return PATH_SPLIT_FP16;
+        if (!(k == 4 && tuning().k4_reg && dev::reg_supported(dtype, k, q, n))) return PATH_MFMA32;
+    }
+    if (dev::reg_supported(dtype, k, q, n)) return PATH_REG;
+    return PATH_GENERIC;
+}
+
+int path_family(Path p)
+{
+    switch (p) {
+    case PATH_REG: return FAM_REG;
+    case PATH_GENERIC: return FAM_GENERIC;
+    case PATH_MFMA32: return FAM_MFMA32;
+    case PATH_SPLIT_BF16: return FAM_SPLIT_BF16;
+    default: return FAM_SPLIT_FP16;
+    }
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage)
+{
+    // pass 1: sizes
+    size_t total = 0;
+    for (auto &L : launches) {
+        const int D = 1 << L.k;
+        switch (L.path) {
+        case PATH_REG: break;
+        case PATH_GENERIC:
+            L.arena_off = total;
+            total = align256(total + size_t(D) * D * 2 * (dtype == SV_C64 ? 4 : 8));
+            break;
+        case PATH_MFMA32:
+            L.arena_off = total;
+            total = align256(total + dev::real_form_elems(L.k) * 4);
+            break;
+        default:
+            L.arena_off = total;
+            total = align256(total + dev::real_form_elems(L.k) * 2);
+            L.arena_off2 = total;
+            total = align256(total + dev::real_form_elems(L.k) * 2);
+            break;
+        }
+    }
+    if (total == 0) return 0;
+    if (stage.ensure(total) != hipSuccess) return size_t(-1);
+    char *h = static_cast<char *>(stage.p);
+    for (auto &L : launches) {
+        const int D = 1 << L.k;
+        switch (L.path) {
+        case PATH_REG: break;
+        case PATH_GENERIC:
+            if (dtype == SV_C64) {
+                float *f = reinterpret_cast<float *>(h + L.arena_off);
+                for (int i = 0; i < D * D; ++i) {
+                    f[2 * i] = float(L.m[i].real());
+                    f[2 * i + 1] = float(L.m[i].imag());
+                }
+            } else {
+                double *f = reinterpret_cast<double *>(h + L.arena_off);
+                for (int i = 0; i < D * D; ++i) {
+                    f[2 * i] = L.m[i].real();
+                    f[2 * i + 1] = L.m[i].imag();
+                }
+            }
+            break;
+        case PATH_MFMA32:
+            dev::pack_real_form_f32(L.m.data(), L.k, reinterpret_cast<float *>(h + L.arena_off));
+            break;
+        default:
+            dev::pack_real_form_split(L.m.data(), L.k, L.path == PATH_SPLIT_FP16,
+                                      reinterpret_cast<uint16_t *>(h + L.arena_off),
+                                      reinterpret_cast<uint16_t *>(h + L.arena_off2));
+            break;
+        }
+    }
+    return total;
+}
+
+int enqueue(const std::vector<Launch> &launches, int dtype, void *psi, int n, const void *arena, hipStream_t st)
+{
+    const char *A = static_cast<const char *>(arena);
+    const Tuning &T = tuning();
+    for (const auto &L : launches) {
+        LaunchTimer timer(10 * path_family(L.path) + L.k, st);
+        hipError_t e = hipSuccess;
+        switch (L.path) {
+        case PATH_REG: e = dev::launch_reg(dtype, L.k, L.q, L.m.data(), psi, n, st, T.reg_grid_cap[L.k]); break;
+        case PATH_GENERIC: e = dev::launch_generic(dtype, L.k, L.q, A + L.arena_off, psi, n, st); break;
+        case PATH_MFMA32:
+            e = dev::launch_mfma_f32(L.k, L.q, reinterpret_cast<const float *>(A + L.arena_off), psi, n, st,
+                                     T.mfma_tc_log[L.k], T.mfma_grid_cap[L.k]);
+            break;
+        default:
+            e = dev::launch_mfma_split(L.k, L.path == PATH_SPLIT_FP16, L.q,
+                                       reinterpret_cast<const uint16_t *>(A + L.arena_off),
+                                       reinterpret_cast<const uint16_t *>(A + L.arena_off2), psi, n, st,
+                                       T.split_tc_log[L.k], T.mfma_grid_cap[L.k]);
+            break;
+        }
+        if (e != hipSuccess) return fail(SV_ERR_HIP, "kernel launch (path %d, k=%d): %s", int(L.path), L.k, hipGetErrorString(e));
+    }
+    return SV_OK;
+}
+
+}  // namespace sv

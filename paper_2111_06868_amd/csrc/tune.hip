@@ -1,0 +1,200 @@
+// Autotuner: times the block kernels on the caller's scratch state and keeps
+// the fastest launch shape per block size k; the per-k times form the cost
+// table that fusion (max_k = -1, enhanced merging) optimises against.
+//
+// Candidates per k (complex64):
+//   k <= 3 : register kernel, grid caps {2048, 4096, 8192, 16384, unbounded};
+//   k = 4  : register kernel (same caps) and the MFMA kernel;
+//   k >= 4 : MFMA kernel, column tiles 2^5..2^7 (where the tile fits) x grid
+//            caps {1024, 2048, 4096} (split kernels for SPLIT_* precisions).
+// Complex128 (FP64) times the register kernel for k <= 3 and the generic
+// kernel above.  Each candidate is timed on three position sets (lowest k
+// positions, highest k, and a spread set) and the mean is kept.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "runtime.h"
+
+using namespace sv;
+
+namespace {
+
+std::vector<cd> dft_matrix(int k)
+{
+    const int D = 1 << k;
+    std::vector<cd> m(size_t(D) * D);
+    const double s = 1.0 / std::sqrt(double(D));
+    for (int r = 0; r < D; ++r)
+        for (int c = 0; c < D; ++c) m[size_t(r) * D + c] = std::polar(s, 2.0 * M_PI * r * c / D);
+    return m;
+}
+
+std::vector<std::vector<int>> position_sets(int n, int k)
+{
+    std::vector<std::vector<int>> sets;
+    std::vector<int> lo, hi, spread;
+    for (int j = 0; j < k; ++j) {
+        lo.push_back(j);
+        hi.push_back(n - k + j);
+        spread.push_back(int(std::lround(double(j) * (n - 1) / std::max(k - 1, 1))));
+    }
+    std::sort(spread.begin(), spread.end());
+    spread.erase(std::unique(spread.begin(), spread.end()), spread.end());
+    sets.push_back(lo);
+    sets.push_back(hi);
+    if (int(spread.size()) == k) sets.push_back(spread);
+    return sets;
+}
+
+struct Cand {
+    Path path;
+    int grid_cap;
+    int tc_log;
+};
+
+// Mean milliseconds per application over the position sets (reps each).
+int time_candidate(sv_state *s, int k, const Cand &c, int reps, double *ms_out)
+{
+    Tuning saved = tuning();
+    Tuning &T = tuning();
+    T.reg_grid_cap[k] = c.grid_cap;
+    T.mfma_grid_cap[k] = c.grid_cap;
+    if (c.path == PATH_MFMA32) T.mfma_tc_log[k] = c.tc_log;
+    if (c.path == PATH_SPLIT_BF16 || c.path == PATH_SPLIT_FP16) T.split_tc_log[k] = c.tc_log;
+    hipEvent_t a, b;
+    SV_HIP(hipEventCreate(&a));
+    SV_HIP(hipEventCreate(&b));
+    double total = 0;
+    int count = 0;
+    int rc = SV_OK;
+    const std::vector<cd> m = dft_matrix(k);
+    for (const auto &pos : position_sets(s->n, k)) {
+        std::vector<Launch> L(1);
+        L[0].path = c.path;
+        L[0].k = k;
+        std::fill(L[0].q, L[0].q + SV_MAX_K, 0);
+        std::copy(pos.begin(), pos.end(), L[0].q);
+        L[0].m = m;
+        if (c.path == PATH_REG && !dev::reg_supported(s->dtype, k, L[0].q, s->n)) continue;
+        if (c.path != PATH_REG && c.path != PATH_GENERIC && !dev::mfma_supported(k, s->n)) continue;
+        SV_HIP(hipEventSynchronize(s->arena_free));
+        const size_t bytes = pack_operands(L, s->dtype, s->stage);
+        if (bytes) {
+            SV_HIP(s->arena.ensure(bytes));
+            SV_HIP(hipMemcpyAsync(s->arena.p, s->stage.p, bytes, hipMemcpyHostToDevice, s->stream));
+        }
+        rc = enqueue(L, s->dtype, s->buf, s->n, s->arena.p, s->stream);  // warm-up
+        if (rc) break;
+        SV_HIP(hipEventRecord(a, s->stream));
+        for (int r = 0; r < reps && !rc; ++r) rc = enqueue(L, s->dtype, s->buf, s->n, s->arena.p, s->stream);
+        SV_HIP(hipEventRecord(b, s->stream));
+        SV_HIP(hipEventRecord(s->arena_free, s->stream));
+        SV_HIP(hipEventSynchronize(b));
+        float ms = 0;
+        SV_HIP(hipEventElapsedTime(&ms, a, b));
+        total += ms / reps;
+        ++count;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    tuning() = saved;
+    if (rc) return rc;
+    *ms_out = count ? total / count : 1e30;
+    return SV_OK;
+}
+
+}  // namespace
+
+extern "C" int sv_autotune(sv_state *s, int precision, double *cost_ms)
+{
+    clear_error();
+    if (!s || !cost_ms) return fail(SV_ERR_ARG, "NULL argument");
+    if (precision < SV_PREC_FP32 || precision > SV_PREC_FP64) return fail(SV_ERR_ARG, "precision %d", precision);
+    if ((s->dtype == SV_C128) != (precision == SV_PREC_FP64))
+        return fail(SV_ERR_ARG, "precision %d does not match the state's amplitude type", precision);
+    SV_HIP(hipSetDevice(s->device));
+    // timing runs must not be recorded by the launch statistics
+    timing_suspend(true);
+    int rc = SV_OK;
+    {
+        double amps[4 * SV_MAX_QUBITS_C64];
+        for (int p = 0; p < s->n; ++p) {
+            amps[4 * p] = amps[4 * p + 2] = 0.70710678118654752440;
+            amps[4 * p + 1] = amps[4 * p + 3] = 0.0;
+        }
+        hipError_t e = dev::launch_product(s->dtype, s->buf, s->n, amps, s->stream);
+        if (e != hipSuccess) rc = fail(SV_ERR_HIP, "autotune init: %s", hipGetErrorString(e));
+    }
+    const int reps = s->n >= 26 ? 3 : 10;
+    const int caps[] = {2048, 4096, 8192, 16384, 0};
+    const int mcaps[] = {1024, 2048, 4096};
+    cost_ms[0] = 0;
+    Tuning best_tuning = tuning();
+    for (int k = 1; k <= SV_MAX_K && !rc; ++k) {
+        std::vector<Cand> cands;
+        if (s->dtype == SV_C128) {
+            if (k <= 3)
+                for (int c : caps) cands.push_back({PATH_REG, c, 0});
+            else
+                cands.push_back({PATH_GENERIC, 0, 0});
+        } else {
+            if (k <= 4)
+                for (int c : caps) cands.push_back({PATH_REG, c, 0});
+            if (k >= 4 && dev::mfma_supported(k, s->n)) {
+                Path p = precision == SV_PREC_SPLIT_BF16 ? PATH_SPLIT_BF16
+                         : precision == SV_PREC_SPLIT_FP16 ? PATH_SPLIT_FP16 : PATH_MFMA32;
+                const bool split = p != PATH_MFMA32;
+                for (int tcl = 5; tcl <= 7; ++tcl) {
+                    if (k == 6 && tcl > (split ? 5 : 6)) continue;
+                    if (split && k == 5 && tcl > 6) continue;
+                    if (tcl > s->n - k) continue;
+                    for (int c : mcaps) cands.push_back({p, c, tcl});
+                }
+            }
+            if (cands.empty()) cands.push_back({PATH_GENERIC, 0, 0});
+        }
+        double best = 1e30;
+        Cand bc = cands[0];
+        for (const auto &c : cands) {
+            double ms = 0;
+            rc = time_candidate(s, k, c, reps, &ms);
+            if (rc) break;
+            if (ms < best) {
+                best = ms;
+                bc = c;
+            }
+        }
+        if (rc) break;
+        cost_ms[k] = best;
+        if (bc.path == PATH_REG) best_tuning.reg_grid_cap[k] = bc.grid_cap;
+        if (bc.path == PATH_MFMA32) {
+            best_tuning.mfma_tc_log[k] = bc.tc_log;
+            best_tuning.mfma_grid_cap[k] = bc.grid_cap;
+        }
+        if (bc.path == PATH_SPLIT_BF16 || bc.path == PATH_SPLIT_FP16) {
+            best_tuning.split_tc_log[k] = bc.tc_log;
+            best_tuning.mfma_grid_cap[k] = bc.grid_cap;
+        }
+        if (k == 4 && s->dtype == SV_C64 && precision == SV_PREC_FP32) best_tuning.k4_reg = bc.path == PATH_REG;
+    }
+    timing_suspend(false);
+    if (rc) return rc;
+    tuning() = best_tuning;
+    store_costs(s->n, precision, cost_ms);
+    return SV_OK;
+}
+
+extern "C" int sv_set_cost_table(int n, int precision, const double *cost_ms)
+{
+    clear_error();
+    if (n < 1 || n > SV_MAX_QUBITS_C64) return fail(SV_ERR_ARG, "n = %d", n);
+    if (precision < SV_PREC_FP32 || precision > SV_PREC_FP64) return fail(SV_ERR_ARG, "precision %d", precision);
+    if (!cost_ms) return fail(SV_ERR_ARG, "NULL cost table");
+    for (int k = 1; k <= SV_MAX_K; ++k)
+        if (!(cost_ms[k] > 0) || !std::isfinite(cost_ms[k])) return fail(SV_ERR_ARG, "cost_ms[%d] must be positive", k);
+    store_costs(n, precision, cost_ms);
+    return SV_OK;
+}

@@ -1,0 +1,182 @@
+"""The C ABI library on the host (no GPU needed): it loads, exports every
+declared symbol, and its host-only logic (gate table, fusion, argument
+validation) agrees with the oracle.  No call here launches device work."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import paper_2111_06868_amd as sv
+from paper_2111_06868_amd import _native as N
+from oracle import brute, ref
+from workloads import circuits as wc
+from helpers import header_functions, to_binding
+
+
+def test_library_exports_every_declared_symbol():
+    L = N.lib()
+    declared = header_functions()
+    assert len(declared) >= 30
+    for name in declared:
+        assert hasattr(L, name), name
+        assert name in N.SIGNATURES, name
+    assert set(N.SIGNATURES) == set(declared)
+
+
+def test_version():
+    assert N.lib().sv_version() >= 1
+
+
+@pytest.mark.parametrize("name,params", [
+    ("I", ()), ("X", ()), ("Y", ()), ("Z", ()), ("H", ()), ("SQRT_X", ()), ("SQRT_Y", ()),
+    ("SQRT_W", ()), ("RX", (0.37,)), ("RY", (-2.1,)), ("RZ", (5.5,)), ("CZ", ()), ("CX", ()),
+    ("CPHASE", (1.3,)), ("SWAP", ()), ("FSIM", (math.pi / 2, math.pi / 6)), ("FSIM", (0.3, 2.9)),
+])
+def test_gate_table_matches_oracle(name, params):
+    k = 1 if name in ("I", "X", "Y", "Z", "H", "SQRT_X", "SQRT_Y", "SQRT_W", "RX", "RY", "RZ") else 2
+    got = sv.gate_matrix((name, tuple(range(k)), params))
+    assert np.max(np.abs(got - ref.gate_matrix(name, params))) <= 1e-15
+
+
+def test_matrix_gate_roundtrip():
+    M = wc.haar_unitary_from_seed(5, 3)
+    got = sv.gate_matrix(("MATRIX", (0, 1, 2), (), -1, M))
+    assert np.array_equal(got, M)
+
+
+def test_fuse_paper_compress_example():
+    """Circuit utilities section: compress(max_n_qubits=3) prints blocks
+    (0,1,2), (0,3,4), (1,3,4), (2,3,4)."""
+    gates = to_binding(wc.paper_compress_example())
+    plan = sv.fuse(gates, 5, 3, sv.RULE_PAPER)
+    assert [b.qubits for b in plan.blocks(False)] == [(0, 1, 2), (0, 3, 4), (1, 3, 4), (2, 3, 4)]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_fuse_paper_rule_matches_oracle(seed):
+    rng = np.random.default_rng(100 + seed)
+    n = 9
+    gates = wc.random_gate_list(n, 60, rng, max_k=2)
+    for k in range(2, 7):
+        plan = sv.fuse(to_binding(gates), n, k, sv.RULE_PAPER)
+        want = ref.fuse_paper([g.qubits for g in gates], k)
+        got = [(b.qubits, b.members) for b in plan.blocks(False)]
+        assert got == [(q, m) for q, m in want]
+
+
+def test_fused_block_matrices_match_oracle():
+    rng = np.random.default_rng(7)
+    n = 8
+    gates = wc.random_gate_list(n, 40, rng, max_k=3)
+    ops = [(ref.matrix_of(g), g.qubits) for g in gates]
+    for k in (3, 4, 6):
+        plan = sv.fuse(to_binding(gates), n, k, sv.RULE_PAPER)
+        for b in plan.blocks():
+            want = ref.block_matrix([ops[i] for i in b.members], b.qubits)
+            assert np.max(np.abs(b.matrix - want)) <= 1e-13
+
+
+@pytest.mark.parametrize("rule", [sv.RULE_PAPER, sv.RULE_ENHANCED, sv.RULE_NONE])
+def test_plan_product_equals_circuit_unitary(rule):
+    """Several plans are correct; each must reproduce the circuit's unitary."""
+    rng = np.random.default_rng(11)
+    for n in (5, 7):
+        gates = wc.random_gate_list(n, 30, rng, max_k=2)
+        U = brute.circuit_unitary(n, [(ref.matrix_of(g), g.qubits) for g in gates])
+        for k in (2, 3, 5):
+            plan = sv.fuse(to_binding(gates), n, k, rule)
+            blocks = plan.blocks()
+            assert sorted(i for b in blocks for i in b.members) == list(range(len(gates)))
+            for b in blocks:
+                assert rule == sv.RULE_NONE or len(b.qubits) <= k
+                assert all(set(gates[i].qubits) <= set(b.qubits) for i in b.members)
+            V = brute.circuit_unitary(n, [(b.matrix, b.qubits) for b in blocks])
+            assert np.max(np.abs(V - U)) <= 1e-12
+
+
+def test_enhanced_rule_never_needs_more_passes():
+    for cfg in (0, 1, 2):
+        n, gates = wc.config_circuit(cfg)
+        g = to_binding(gates)
+        for k in (2, 3, 4, 5, 6):
+            p = len(sv.fuse(g, n, k, sv.RULE_PAPER))
+            e = len(sv.fuse(g, n, k, sv.RULE_ENHANCED))
+            assert e <= p, (cfg, k, e, p)
+        assert len(sv.fuse(g, n, 2, sv.RULE_NONE)) == len(gates)
+
+
+def test_paper_rule_pass_counts_on_workloads():
+    for cfg in (1, 2):
+        n, gates = wc.config_circuit(cfg)
+        for k in (2, 3, 4, 5, 6):
+            got = len(sv.fuse(to_binding(gates), n, k, sv.RULE_PAPER))
+            assert got == len(ref.fuse_paper([x.qubits for x in gates], k))
+
+
+# ------------------------------------------------------------ argument checks
+def _gate(kind, qubits, params=(0.0, 0.0)):
+    g = N.sv_gate()
+    g.kind = N.GATE_KINDS[kind]
+    g.k = len(qubits)
+    for j, q in enumerate(qubits):
+        g.q[j] = q
+    g.params[0], g.params[1] = params
+    g.param = -1
+    return g
+
+
+def _fuse_rc(gates, n, k=3, rule=N.RULE_PAPER):
+    arr = (N.sv_gate * len(gates))(*gates)
+    h = ctypes.c_void_p()
+    rc = N.lib().sv_fuse(ctypes.cast(arr, ctypes.POINTER(N.sv_gate)), len(gates), n, k, rule, ctypes.byref(h))
+    if rc == 0:
+        N.lib().sv_plan_free(h)
+    return rc
+
+
+def test_validation_error_codes():
+    assert _fuse_rc([_gate("H", (0,))], 4) == N.OK
+    assert _fuse_rc([_gate("H", (4,))], 4) == N.ERR_QUBIT          # out of range
+    assert _fuse_rc([_gate("CZ", (1, 1))], 4) == N.ERR_QUBIT       # repeated
+    g = _gate("CZ", (0, 1)); g.k = 1
+    assert _fuse_rc([g], 4) == N.ERR_ARG                           # arity mismatch
+    g = _gate("H", (0,)); g.kind = 99
+    assert _fuse_rc([g], 4) == N.ERR_ARG                           # unknown kind
+    g = _gate("RX", (0,), (float("nan"), 0.0))
+    assert _fuse_rc([g], 4) == N.ERR_ARG                           # non-finite parameter
+    g = _gate("CZ", (0, 1)); g.param = 0
+    assert _fuse_rc([g], 4) == N.ERR_ARG                           # param on a non-rotation
+    g = _gate("H", (0,)); g.kind = 0; g.k = 1; g.m = None
+    assert _fuse_rc([g], 4) == N.ERR_ARG                           # matrix gate without matrix
+    assert _fuse_rc([_gate("CZ", (0, 1))], 4, k=1) == N.ERR_ARG    # gate larger than max_k
+    assert _fuse_rc([_gate("H", (0,))], 4, k=7) == N.ERR_ARG
+    assert _fuse_rc([_gate("H", (0,))], 4, rule=9) == N.ERR_ARG
+    assert "max_k" in N.lib().sv_last_error().decode() or N.lib().sv_last_error()
+
+
+def test_alloc_rejects_bad_arguments_before_device_work():
+    L = N.lib()
+    h = ctypes.c_void_p()
+    assert L.sv_alloc(0, N.C64, None, 0, None, ctypes.byref(h)) == N.ERR_ARG
+    assert L.sv_alloc(36, N.C64, None, 0, None, ctypes.byref(h)) == N.ERR_ARG
+    assert L.sv_alloc(35, N.C128, None, 0, None, ctypes.byref(h)) == N.ERR_ARG
+    assert L.sv_alloc(4, 7, None, 0, None, ctypes.byref(h)) == N.ERR_ARG
+    # a buffer too small for the state (the pointer is never dereferenced)
+    assert L.sv_alloc(10, N.C64, ctypes.c_void_p(4096), 8 * 1023, None, ctypes.byref(h)) == N.ERR_SIZE
+    assert L.sv_alloc(10, N.C64, ctypes.c_void_p(4096 + 8), 1 << 20, None, ctypes.byref(h)) == N.ERR_ARG
+    assert L.sv_alloc(4, N.C64, None, 0, None, None) == N.ERR_ARG
+    assert h.value is None
+
+
+def test_binding_raises_value_error_for_bad_input():
+    with pytest.raises(ValueError):
+        sv.fuse([("H", (9,))], 4, 2)
+    with pytest.raises(ValueError):
+        sv.gate_matrix(("NOPE", (0,)))
+
+
+def test_positions_follow_paper_order():
+    # Grover example: order [0, 1, 2] puts qubit 0 at the most significant bit
+    assert sv.positions([0, 1, 2], [1, 2]) == (1, 0)
+    assert sv.positions(["a", "b"], ["a"]) == (1,)

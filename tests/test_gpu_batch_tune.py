@@ -1,0 +1,77 @@
+"""GPU: batched noisy trajectories and the autotuner, against the oracle."""
+import numpy as np
+import pytest
+
+import paper_2111_06868_amd as sv
+from oracle import ref
+from workloads import circuits as wc
+from helpers import to_binding
+
+pytestmark = pytest.mark.gpu
+
+
+def _batch_inputs(trajs):
+    return [(t.n, to_binding(t.gates)) for t in trajs]
+
+
+@pytest.mark.parametrize("max_k", [1, 2, 3, 5, -1])
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_small_vs_oracle(max_k, use_graph):
+    trajs = wc.trajectory_batch(count=14, root_seed=77, p=0.2, n_range=(3, 17), depth_range=(2, 7))
+    assert sum(t.n_inserted for t in trajs) > 0
+    b = sv.Batch(_batch_inputs(trajs), max_k=max_k)
+    for rep in range(2):
+        z = b.run(use_graph=use_graph)
+        for i, t in enumerate(trajs):
+            want = ref.simulate(t.n, t.gates, "0")
+            got = b.read(i)
+            fe = ref.fidelity_error(want, got)
+            assert fe <= 1e-5, (i, t.n, fe)
+            assert abs(z[i] - ref.z0(want)) <= 1e-5, (i, z[i], ref.z0(want))
+    print("[parity] batch max_k=%s graph=%s ok" % (max_k, use_graph), flush=True)
+
+
+def test_batch_full_size_sampled():
+    """The 512-trajectory noisy batch (n in 10..22, depth 8..24, p = 1e-3):
+    every trajectory with n <= 15 and six larger ones against the oracle."""
+    trajs = wc.trajectory_batch()
+    b = sv.Batch(_batch_inputs(trajs), max_k=-1)
+    z = b.run(use_graph=True)
+    z2 = b.run(use_graph=True)
+    assert np.array_equal(z, z2)
+    picks = [i for i, t in enumerate(trajs) if t.n <= 15]
+    big = [i for i, t in enumerate(trajs) if t.n > 15]
+    picks += big[:: max(1, len(big) // 6)][:6]
+    worst = 0.0
+    for i in picks:
+        want = ref.z0(ref.simulate(trajs[i].n, trajs[i].gates, "0"))
+        worst = max(worst, abs(z[i] - want))
+    print("[parity] batch 512: %d sampled, max |dZ0| = %.3e, mean Z0 = %.6f" % (len(picks), worst, z.mean()), flush=True)
+    assert worst <= 1e-5
+    assert np.all(np.abs(z) <= 1 + 1e-6)
+
+
+@pytest.mark.parametrize("precision", [sv.PREC_FP32, sv.PREC_SPLIT_BF16, sv.PREC_FP64])
+def test_autotune_then_fuse_auto(precision):
+    n = 16
+    dtype = "c128" if precision == sv.PREC_FP64 else "c64"
+    scratch = sv.State(n, dtype)
+    cost = sv.autotune(scratch, precision)
+    print("[tune] n=%d precision=%d cost_ms=%s" % (n, precision, np.array2string(cost, precision=4)), flush=True)
+    assert np.all(cost[1:] > 0)
+    rng = np.random.default_rng(3)
+    gates = wc.random_gate_list(n, 200, rng, max_k=2)
+    want = ref.simulate(n, gates, "+")
+    st = sv.State(n, dtype).set_product("+").run(to_binding(gates), max_k=-1, rule=sv.RULE_ENHANCED,
+                                                 precision=precision)
+    fe = ref.fidelity_error(want, st.read())
+    assert fe <= (1e-12 if dtype == "c128" else 1e-5)
+
+
+def test_native_library_is_loaded():
+    import os
+    from paper_2111_06868_amd import _native
+    L = _native.lib()
+    maps = open("/proc/self/maps").read()
+    assert os.path.realpath(_native.LIB_PATH) in maps
+    assert L.sv_version() >= 1

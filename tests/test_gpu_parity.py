@@ -1,0 +1,285 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  Complex64 results must reach fidelity error <= 1e-5
+(the stated bar for complex64) and every case prints its amplitude max-abs
+error; complex128 results must match the oracle to 1e-12."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2111_06868_amd as sv
+from oracle import ref
+from workloads import circuits as wc
+from workloads.circuits import Gate
+from helpers import to_binding
+
+pytestmark = pytest.mark.gpu
+
+FID_C64 = 1e-5
+
+
+def _report(tag, want, got):
+    fe = ref.fidelity_error(want, got)
+    ma = ref.max_abs(want, got)
+    print("[parity] %-40s 1-F=%.3e max_abs=%.3e" % (tag, fe, ma), flush=True)
+    sys.stdout.flush()
+    return fe, ma
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    yield
+    torch.cuda.synchronize()
+
+
+def _tokens(n, rng):
+    return "".join("01+-"[int(x)] for x in rng.integers(4, size=n))
+
+
+def run_both(n, gates, tokens="0", dtype="c64", **kw):
+    want = ref.simulate(n, gates, tokens)
+    st = sv.State(n, dtype).set_product(tokens)
+    st.run(to_binding(gates), **kw)
+    return want, st.read(), st
+
+
+# ----------------------------------------------------------------- per gate
+def test_c0_per_gate_all_amplitudes():
+    n, gates = wc.config_circuit(0)
+    want, got, st = run_both(n, gates, "0", "c64")
+    fe, ma = _report("c0 14q per-gate c64", want, got)
+    assert fe <= FID_C64
+    assert ma <= 1e-5
+    assert abs(st.norm2() - 1) <= 1e-5
+
+
+def test_c0_per_gate_c128():
+    n, gates = wc.config_circuit(0)
+    want, got, _ = run_both(n, gates, "0", "c128")
+    _, ma = _report("c0 14q per-gate c128", want, got)
+    assert ma <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_every_position_and_pair(dtype):
+    """Named 1q gates on every position and 2q gates on every ordered pair
+    (covers every low/high target pattern of the register kernel)."""
+    n = 9
+    rng = np.random.default_rng(21)
+    gates = []
+    for q in range(n):
+        for nm in ("H", "SQRT_X", "SQRT_Y", "SQRT_W", "RX", "RY", "RZ"):
+            gates.append(Gate(nm, (q,), (float(rng.uniform(0, 6)),) if nm[0] == "R" else ()))
+    for a in range(n):
+        for b in range(n):
+            if a != b:
+                nm = ("CX", "FSIM", "CPHASE", "SWAP", "CZ")[int(rng.integers(5))]
+                params = {"FSIM": (0.7, 1.9), "CPHASE": (0.4,)}.get(nm, ())
+                gates.append(Gate(nm, (a, b), params))
+    tok = _tokens(n, rng)
+    want, got, _ = run_both(n, gates, tok, dtype)
+    fe, ma = _report("all positions %s" % dtype, want, got)
+    if dtype == "c128":
+        assert ma <= 1e-12
+    else:
+        assert fe <= FID_C64 and ma <= 1e-5
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 8, 13, 17])
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_random_circuits(n, dtype):
+    rng = np.random.default_rng(1000 + n)
+    gates = wc.random_gate_list(n, 120, rng, max_k=min(3, n))
+    tok = _tokens(n, rng)
+    want, got, _ = run_both(n, gates, tok, dtype)
+    fe, ma = _report("random n=%d %s" % (n, dtype), want, got)
+    if dtype == "c128":
+        assert ma <= 1e-12
+    else:
+        assert fe <= FID_C64
+
+
+# ----------------------------------------------------------------- dense blocks
+def _dense_case(n, k, rng, pos=None):
+    qs = tuple(int(x) for x in (pos if pos is not None else rng.choice(n, size=k, replace=False)))
+    return Gate("MATRIX", qs, (float(rng.integers(1 << 30)),))
+
+
+DENSE_POS = [
+    (12, (0, 1, 2, 3)), (12, (7, 8, 10, 11)), (12, (0, 5, 9, 11)), (13, (1, 2, 3, 4, 5)),
+    (13, (0, 1, 2, 3, 4, 5)), (14, (8, 9, 10, 11, 12, 13)), (16, (0, 3, 6, 9, 12, 15)),
+    (11, (1, 4, 6, 10)), (10, (2, 3, 4, 5, 6)), (9, (0, 2, 4, 6)), (20, (19, 0, 7, 13, 2)),
+]
+
+
+@pytest.mark.parametrize("n,pos", DENSE_POS)
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16", "fp64"])
+def test_dense_block_paths(n, pos, precision):
+    """One dense k = 4..6 block per case (MFMA path for complex64, generic
+    FP64 kernel for complex128), positions chosen to span low, high, and
+    mixed layouts, and tiles narrower than the default."""
+    rng = np.random.default_rng(hash((n, pos)) & 0xFFFF)
+    pre = [g for g in wc.random_gate_list(n, 3 * n, rng, max_k=2)]
+    blk = _dense_case(n, len(pos), rng, pos)
+    gates = pre + [blk, _dense_case(n, len(pos), rng)]
+    prec = {"fp32": sv.PREC_FP32, "bf16": sv.PREC_SPLIT_BF16, "fp16": sv.PREC_SPLIT_FP16,
+            "fp64": sv.PREC_FP64}[precision]
+    dtype = "c128" if precision == "fp64" else "c64"
+    want, got, _ = run_both(n, gates, "+", dtype, precision=prec)
+    fe, ma = _report("dense n=%d k=%d %s" % (n, len(pos), precision), want, got)
+    if precision == "fp64":
+        assert ma <= 1e-12
+    elif precision == "fp32":
+        assert fe <= 1e-6
+    else:
+        assert fe <= FID_C64
+
+
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("rule", [sv.RULE_PAPER, sv.RULE_ENHANCED])
+def test_c0_fused(k, rule):
+    n, gates = wc.config_circuit(0)
+    want, got, _ = run_both(n, gates, "0", "c64", max_k=k, rule=rule)
+    fe, ma = _report("c0 fused k<=%d rule=%d" % (k, rule), want, got)
+    assert fe <= FID_C64 and ma <= 1e-5
+
+
+@pytest.mark.parametrize("precision", [sv.PREC_SPLIT_BF16, sv.PREC_SPLIT_FP16])
+def test_c0_fused_split(precision):
+    n, gates = wc.config_circuit(0)
+    want, got, _ = run_both(n, gates, "0", "c64", max_k=6, rule=sv.RULE_ENHANCED, precision=precision)
+    fe, ma = _report("c0 fused k<=6 split %d" % precision, want, got)
+    assert fe <= FID_C64
+
+
+def test_c0_fused_c128():
+    n, gates = wc.config_circuit(0)
+    want, got, _ = run_both(n, gates, "0", "c128", max_k=5, rule=sv.RULE_PAPER)
+    _, ma = _report("c0 fused k<=5 c128", want, got)
+    assert ma <= 1e-12
+
+
+# ----------------------------------------------------------------- states and reductions
+def test_product_states_and_basis():
+    for n in (1, 4, 11):
+        rng = np.random.default_rng(n)
+        tok = _tokens(n, rng)
+        st = sv.State(n, "c128").set_product(tok)
+        assert np.max(np.abs(st.read() - ref.product_state(n, tok))) <= 1e-15
+        st.set_basis((1 << n) - 1)
+        v = st.read()
+        assert v[-1] == 1 and np.count_nonzero(v) == 1
+    st = sv.State(5, "c64").set_product("+")
+    assert np.max(np.abs(st.read() - 2 ** -2.5)) <= 1e-7
+    with pytest.raises(ValueError):
+        st.set_product("0+x")
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_norm_inner_expectation(dtype):
+    n = 12
+    rng = np.random.default_rng(5)
+    gates = wc.random_gate_list(n, 80, rng, max_k=2)
+    psi = ref.simulate(n, gates, "0")
+    a = sv.State(n, dtype).run(to_binding(gates))
+    b = sv.State(n, "c128").set_product("+")
+    tol = 1e-12 if dtype == "c128" else 2e-6
+    assert abs(a.norm2() - ref.norm2(psi)) <= tol
+    ov = b.inner(a)
+    want = ref.inner(ref.product_state(n, "+"), psi)
+    assert abs(ov - want) <= tol
+    terms = []
+    for _ in range(12):
+        f = tuple((q, "XYZ"[int(rng.integers(3))]) for q in range(n) if rng.random() < 0.3)
+        terms.append((float(rng.normal()), f))
+    terms.append((0.5, ()))
+    e = a.expectation(terms)
+    assert abs(e - ref.expectation(psi, terms)) <= (1e-12 if dtype == "c128" else 1e-5)
+    out = sv.State(n, dtype)
+    a.apply_pauli_sum(terms[:5], out)
+    want_h = sum(c * ref.pauli_apply(psi, f) for c, f in terms[:5])
+    assert np.max(np.abs(out.read() - want_h)) <= (1e-12 if dtype == "c128" else 1e-5)
+
+
+def test_reductions_deterministic():
+    n = 18
+    rng = np.random.default_rng(9)
+    gates = to_binding(wc.random_gate_list(n, 40, rng, max_k=2))
+    a = sv.State(n, "c64").run(gates)
+    r1 = (a.norm2(), a.expectation([(1.0, ((0, "Z"),)), (0.3, ((3, "X"), (7, "Y")))]))
+    r2 = (a.norm2(), a.expectation([(1.0, ((0, "Z"),)), (0.3, ((3, "X"), (7, "Y")))]))
+    assert r1 == r2
+    b = sv.State(n, "c64").run(gates)
+    assert np.array_equal(a.read(), b.read())
+
+
+def test_checkpoint_resume():
+    n, gates = wc.config_circuit(0)
+    g = to_binding(gates)
+    full = sv.State(n, "c64").run(g, max_k=4, rule=sv.RULE_PAPER).read()
+    first = sv.State(n, "c64").run(g[:100]).read()
+    resumed = sv.State(n, "c64").write(first).run(g[100:]).read()
+    want = ref.simulate(n, gates, "0")
+    assert ref.fidelity_error(want, resumed) <= FID_C64
+    assert ref.fidelity_error(want, full) <= FID_C64
+
+
+def test_graph_replay_matches_eager():
+    n, gates = wc.config_circuit(0)
+    g = to_binding(gates)
+    eager = sv.State(n, "c64").run(g, max_k=3, rule=sv.RULE_ENHANCED).read()
+    for _ in range(3):
+        st = sv.State(n, "c64").run(g, max_k=3, rule=sv.RULE_ENHANCED, use_graph=True)
+        assert np.array_equal(st.read(), eager)
+        sv.State(n, "c64").run(g[:10])  # eager work between replays
+
+
+def test_stats_count_launches():
+    n, gates = wc.config_circuit(0)
+    sv.stats_reset()
+    sv.stats_enable(True)
+    try:
+        sv.State(n, "c64").run(to_binding(gates)).synchronize()
+        c1, ms1 = sv.stats_query("reg", 1)
+        c2, ms2 = sv.stats_query("reg", 2)
+    finally:
+        sv.stats_enable(False)
+        sv.stats_reset()
+    assert c1 == 168 and c2 == 57
+    assert ms1 > 0 and ms2 > 0
+
+
+# ----------------------------------------------------------------- gradients
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_adjoint_small_ansatz(dtype):
+    n, layers = 6, 3
+    gates, thetas = wc.ansatz_circuit(n, layers, seed=31)
+    H = wc.ansatz_observable(n)
+    psi = sv.State(n, dtype).run(to_binding(gates))
+    scratch = sv.State(n, dtype)
+    e = psi.expectation(H)
+    assert abs(e - ref.energy(n, gates, thetas, H)) <= (1e-12 if dtype == "c128" else 1e-5)
+    g = sv.backward(psi, scratch, to_binding(gates), H, len(thetas))
+    ps = ref.param_shift_grad(n, gates, thetas, H)
+    rel = np.linalg.norm(g - ps) / np.linalg.norm(ps)
+    print("[parity] adjoint n=%d %s rel=%.3e" % (n, dtype, rel), flush=True)
+    assert rel <= (1e-10 if dtype == "c128" else 1e-4)
+    # psi was consumed back to |0..0>
+    back = psi.read()
+    assert abs(abs(back[0]) - 1) <= (1e-12 if dtype == "c128" else 1e-5)
+
+
+def test_energy_autograd():
+    import torch
+    n, layers = 5, 2
+    gates, thetas = wc.ansatz_circuit(n, layers, seed=32)
+    H = wc.ansatz_observable(n)
+    th = torch.tensor(thetas, dtype=torch.float64, requires_grad=True)
+    E = sv.Energy.apply(th, n, to_binding(gates), H, 3, sv.RULE_PAPER)
+    E.backward()
+    ps = ref.param_shift_grad(n, gates, thetas, H)
+    assert abs(E.item() - ref.energy(n, gates, thetas, H)) <= 1e-5
+    assert np.linalg.norm(th.grad.numpy() - ps) / np.linalg.norm(ps) <= 1e-4
