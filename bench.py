@@ -94,6 +94,8 @@ def main():
     ap.add_argument("--config", type=int, default=1, choices=[1, 2])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference", action="store_true")
+    ap.add_argument("--no-per-gate", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="tune launch shapes first, fuse with max_k=-1")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -115,7 +117,17 @@ def main():
     G = len(gates)
     pass_bytes = 16.0 * (1 << n)
 
-    plan = sv.fuse(ga, n, args.max_k, rule)
+    max_k = args.max_k
+    if args.autotune:
+        scratch = sv.State(n, "c64")
+        cost = sv.autotune(scratch, prec)
+        del scratch
+        log("autotuned cost table (ms per block, k=1..6): %s" % ", ".join("%.3f" % c for c in cost[1:]))
+        max_k = -1
+    plan = sv.fuse(ga, n, max_k, rule)
+    if max_k == -1:
+        max_k = plan.max_k
+        args.max_k = max_k
     blocks = plan.blocks(False)
     n_passes = len(blocks)
     kh = {}
@@ -172,36 +184,40 @@ def main():
     fused_state = st
 
     extra = {}
-    # plain per-gate complex64 run (same circuit), one timed run
-    pg = sv.State(n, "c64")
-    pg.run(ga, rule=sv.RULE_NONE)  # warm
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    pg.set_basis(0)
-    pg.run(ga, rule=sv.RULE_NONE)
-    pg.norm2()
-    torch.cuda.synchronize()
-    t_pg = time.perf_counter() - t1
-    extra["per_gate_gates_per_s"] = round(G / t_pg, 2)
-    extra["per_gate_ms"] = round(1e3 * t_pg, 2)
-    extra["fused_speedup_vs_per_gate"] = round(t_pg * 1e3 / ms_step, 3)
-    log("per-gate: %.1f ms" % (1e3 * t_pg))
+    pg = None
+    if not args.no_per_gate:
+        # plain per-gate complex64 run (same circuit), one timed run
+        pg = sv.State(n, "c64")
+        pg.run(ga, rule=sv.RULE_NONE)  # warm
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        pg.set_basis(0)
+        pg.run(ga, rule=sv.RULE_NONE)
+        pg.norm2()
+        torch.cuda.synchronize()
+        t_pg = time.perf_counter() - t1
+        extra["per_gate_gates_per_s"] = round(G / t_pg, 2)
+        extra["per_gate_ms"] = round(1e3 * t_pg, 2)
+        extra["fused_speedup_vs_per_gate"] = round(t_pg * 1e3 / ms_step, 3)
+        log("per-gate: %.1f ms" % (1e3 * t_pg))
 
     if not args.no_reference:
         refst = sv.State(n, "c128")
         refst.run(ga, rule=sv.RULE_NONE)
         nr = refst.norm2()
         fe_fused = sv.fidelity_error(refst, fused_state)
-        fe_pg = sv.fidelity_error(refst, pg)
         first = 1 << 20
         a = refst.read(0, first)
         extra["fidelity_err_fused"] = fe_fused
-        extra["fidelity_err_per_gate"] = fe_pg
         extra["max_abs_first_2^20_fused"] = float(np.max(np.abs(fused_state.read(0, first) - a)))
-        extra["max_abs_first_2^20_per_gate"] = float(np.max(np.abs(pg.read(0, first) - a)))
+        fe_pg = None
+        if pg is not None:
+            fe_pg = sv.fidelity_error(refst, pg)
+            extra["fidelity_err_per_gate"] = fe_pg
+            extra["max_abs_first_2^20_per_gate"] = float(np.max(np.abs(pg.read(0, first) - a)))
         extra["norm_minus_1_fused"] = fused_state.norm2() - 1.0
         extra["norm_minus_1_c128"] = nr - 1.0
-        log("fidelity err fused %.2e per-gate %.2e" % (fe_fused, fe_pg))
+        log("fidelity err fused %.2e per-gate %s" % (fe_fused, fe_pg))
         del refst
     del pg
 
