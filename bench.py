@@ -92,6 +92,9 @@ def main():
     ap.add_argument("--rule", default="enhanced", choices=["paper", "enhanced"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--config", type=int, default=1, choices=[1, 2])
+    ap.add_argument("--workload", default="circuit", choices=["circuit", "gradient", "trajectories"],
+                    help="circuit: the grid random circuit (default); gradient: 20-qubit ansatz "
+                         "energy + adjoint gradient; trajectories: 512 noisy trajectories")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference", action="store_true")
     ap.add_argument("--no-per-gate", action="store_true")
@@ -109,6 +112,10 @@ def main():
     from workloads import circuits as wc
 
     torch.cuda.set_device(0)
+    if args.workload == "gradient":
+        return bench_gradient(args)
+    if args.workload == "trajectories":
+        return bench_trajectories(args)
     n, gates = wc.config_circuit(args.config)
     bound = [(g.name, g.qubits, g.params) for g in gates]
     ga = sv.GateArray(bound)
@@ -265,6 +272,73 @@ def main():
     }
     out.update(extra)
     print(json.dumps(out), flush=True)
+
+
+def _timed_steps(args, step):
+    import torch
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        log("step %d done" % i)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / args.steps
+
+
+def bench_gradient(args):
+    """20-qubit hardware-efficient ansatz (12 layers, 480 angles): one step =
+    forward circuit, <H> (39 Pauli terms) and the adjoint gradient."""
+    import numpy as np
+    import paper_2111_06868_amd as sv
+    from workloads import circuits as wc
+    n = 20
+    gates, thetas = wc.ansatz_circuit(n, 12, seed=3)
+    H = sv.pauli_sum(wc.ansatz_observable(n))
+    ga = sv.GateArray([(g.name, g.qubits, g.params, g.param_index) for g in gates])
+    psi, scratch = sv.State(n, "c64"), sv.State(n, "c64")
+    out = {}
+
+    def step():
+        psi.set_basis(0)
+        psi.run(ga, max_k=4, rule=sv.RULE_ENHANCED)
+        out["E"] = psi.expectation(H)
+        out["g"] = sv.backward(psi, scratch, ga, H, len(thetas))
+
+    t = _timed_steps(args, step)
+    print(json.dumps({"metric": "energy + adjoint gradient evaluations/s (20-qubit ansatz, 480 parameters)",
+                      "value": round(1.0 / t, 3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": round(1e3 * t, 3), "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "config": {"workload": "20-qubit ansatz, 12 layers RY/RZ + CZ ladder, 708 gates, 480 angles"},
+                      "energy": out["E"], "grad_norm": float(np.linalg.norm(out["g"]))}), flush=True)
+
+
+def bench_trajectories(args):
+    """512 noisy trajectories (n in 10..22, depth 8..24, p = 1e-3): one step =
+    one replay of the captured batch graph and the <Z_0> readback."""
+    import numpy as np
+    import paper_2111_06868_amd as sv
+    from workloads import circuits as wc
+    trajs = wc.trajectory_batch()
+    b = sv.Batch([(t.n, [(g.name, g.qubits, g.params) for g in t.gates]) for t in trajs], max_k=-1)
+    out = {}
+
+    def step():
+        out["z"] = b.run(use_graph=True)
+
+    t = _timed_steps(args, step)
+    amps = sum(1 << t_.n for t_ in trajs)
+    print(json.dumps({"metric": "noisy trajectories/s (512 trajectories, 10..22 qubits)",
+                      "value": round(len(trajs) / t, 2), "unit": "trajectories/s", "n_gpus": 1,
+                      "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t, 3),
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                      "data": "synthetic",
+                      "config": {"workload": "512 ladder random circuits, n~U{10..22}, depth~U{8..24}, "
+                                             "2q depolarizing p=1e-3 sampled per trajectory",
+                                 "gates": sum(len(t_.gates) for t_ in trajs), "amplitudes": amps},
+                      "mean_z0": float(np.mean(out["z"]))}), flush=True)
 
 
 if __name__ == "__main__":

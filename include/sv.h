@@ -66,6 +66,8 @@ extern "C" {
 #define SV_RULE_PAPER 0    /* the paper's compress() rule, reproduced exactly    */
 #define SV_RULE_ENHANCED 1 /* paper rule, then cost-aware merging of blocks      */
 #define SV_RULE_NONE 2     /* one block per gate (plain per-gate application)    */
+#define SV_RULE_TILED 3    /* enhanced blocks of <= 4 qubits, grouped into LDS   */
+                           /* tile passes (see sv_run_circuit)                   */
 
 /* gate kinds.  Matrices (paper, Gates and Properties section, names only; the
  * matrices are the textbook ones):
@@ -194,7 +196,8 @@ int sv_apply_gate(sv_state *s, const sv_gate *g);
  * rule, then a gate that meets no block joins the last block when that fits,
  * and adjacent-by-commutation blocks are merged whenever the autotuned cost
  * table (or, without one, the pass count) says the merged block is cheaper.
- * SV_RULE_NONE: one block per gate.  Each block's qubits are sorted
+ * SV_RULE_NONE: one block per gate.  SV_RULE_TILED: the enhanced rule with
+ * blocks of at most min(max_k, 4) qubits.  Each block's qubits are sorted
  * ascending (q[0] = most significant local bit) and its matrix is the ordered
  * product of its members (FP64).  n bounds the positions.  max_k = -1 uses the
  * autotuned cost table for n (SV_ERR_ARG if there is none).
@@ -222,7 +225,12 @@ int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int use_graph);
  * the blocks in order (paper, Simulations section: simulate(..., optimize=
  * 'evolution')).  Nothing is applied if any gate is invalid.  Asynchronous
  * (synchronises when o->use_graph = 1).  o == NULL means plain per-gate
- * application: {SV_MAX_K, FP32 or FP64 by amplitude type, SV_RULE_NONE, 0}. */
+ * application: {SV_MAX_K, FP32 or FP64 by amplitude type, SV_RULE_NONE, 0}.
+ * With SV_RULE_TILED on a complex64 state of >= 13 qubits (FP32 or split
+ * precision), up to 4 consecutive blocks whose positions span at most 9
+ * qubits are applied together: each 2^13-amplitude tile is staged in LDS
+ * once, every block of the group is applied to it with FP32 MFMA, and the
+ * tile is written back, so the group costs one state pass. */
 int sv_run_circuit(sv_state *s, const sv_gate *g, int G, const sv_run_opts *o);
 
 /* ---------------------------------------------------------------- reductions */

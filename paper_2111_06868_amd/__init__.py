@@ -21,13 +21,13 @@ import numpy as np
 
 from . import _native as N
 from ._native import (C64, C128, PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16, PREC_FP64,  # noqa: F401
-                      RULE_PAPER, RULE_ENHANCED, RULE_NONE, SV_MAX_K, GATE_KINDS, SvError,
+                      RULE_PAPER, RULE_ENHANCED, RULE_NONE, RULE_TILED, SV_MAX_K, GATE_KINDS, SvError,
                       SvValueError)
 
 __all__ = ["State", "Plan", "fuse", "gate_matrix", "backward", "Energy", "Batch", "positions",
            "pauli_sum", "autotune", "set_cost_table", "stats_enable", "stats_reset", "stats_query",
            "C64", "C128", "PREC_FP32", "PREC_SPLIT_BF16", "PREC_SPLIT_FP16", "PREC_FP64",
-           "RULE_PAPER", "RULE_ENHANCED", "RULE_NONE", "SvError", "SvValueError"]
+           "RULE_PAPER", "RULE_ENHANCED", "RULE_NONE", "RULE_TILED", "SvError", "SvValueError"]
 
 
 def positions(order: Sequence, qubits: Sequence) -> tuple:
@@ -467,7 +467,7 @@ def stats_reset() -> None:
 
 
 FAMILIES = {"reg": 1, "generic": 2, "mfma_f32": 3, "split_bf16": 4, "split_fp16": 5,
-            "reduce": 6, "adjoint": 7, "batch": 8}
+            "reduce": 6, "adjoint": 7, "batch": 8, "tile": 9}
 
 
 def stats_query(family: str, k: int):

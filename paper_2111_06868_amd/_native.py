@@ -31,6 +31,7 @@ PREC_FP64 = 3
 RULE_PAPER = 0
 RULE_ENHANCED = 1
 RULE_NONE = 2
+RULE_TILED = 3
 
 GATE_KINDS = {
     "MATRIX": 0, "I": 1, "X": 2, "Y": 3, "Z": 4, "H": 5, "SQRT_X": 6, "SQRT_Y": 7,

@@ -110,8 +110,13 @@ int run_launches(sv_state *s, std::vector<Launch> &launches, bool use_graph)
     return SV_OK;
 }
 
-void blocks_to_launches(const std::vector<Block> &blocks, const sv_state *s, int precision, std::vector<Launch> &out)
+void blocks_to_launches(const std::vector<Block> &blocks, const sv_state *s, int precision, int rule,
+                        std::vector<Launch> &out)
 {
+    if (rule == SV_RULE_TILED && s->dtype == SV_C64 && precision != SV_PREC_FP64) {
+        group_tile_passes(blocks, s->n, precision, out);
+        return;
+    }
     out.clear();
     out.reserve(blocks.size());
     for (const auto &b : blocks) {
@@ -429,7 +434,7 @@ extern "C" int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int u
         for (int j = 0; j < b.k; ++j)
             if (b.q[j] >= s->n) return fail(SV_ERR_QUBIT, "plan position %d outside a %d-qubit state", b.q[j], s->n);
     std::vector<Launch> L;
-    blocks_to_launches(p->blocks, s, precision, L);
+    blocks_to_launches(p->blocks, s, precision, p->rule, L);
     if (int rc = select_device(s)) return rc;
     return run_launches(s, L, use_graph != 0);
 }
@@ -456,7 +461,7 @@ extern "C" int sv_run_circuit(sv_state *s, const sv_gate *g, int G, const sv_run
     std::vector<Block> blocks;
     if (int rc = fuse_gates(g, G, s->n, max_k, o->rule, lookup_costs(s->n, o->precision, nullptr), blocks)) return rc;
     std::vector<Launch> L;
-    blocks_to_launches(blocks, s, o->precision, L);
+    blocks_to_launches(blocks, s, o->precision, o->rule, L);
     if (int rc = select_device(s)) return rc;
     return run_launches(s, L, o->use_graph != 0);
 }

@@ -16,9 +16,11 @@
 //     between them is disjoint from j (so j commutes next to i) and the cost
 //     of the union is lower than the two costs together.
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <thread>
 
 #include "common.h"
 
@@ -85,28 +87,41 @@ double plan_cost(const std::vector<Block> &blocks, const CostTable &cost)
 }
 
 // Apply a canonical gate matrix (on block-local bits lb[0..kg-1], ascending)
-// to every column of the D x D canonical block matrix U (in place).
-static void apply_to_columns(std::vector<cd> &U, int kb, const std::vector<cd> &G, int kg, const int *lb)
+// to every column of the D x D canonical block matrix U (in place).  Plain
+// real arithmetic on (re, im) pairs: std::complex multiplication carries
+// inf/nan recovery that dominates the cost of fusing large blocks.
+static void apply_to_columns(std::vector<cd> &Uc, int kb, const std::vector<cd> &Gc, int kg, const int *lb)
 {
     const int D = 1 << kb, Dg = 1 << kg;
+    double *U = reinterpret_cast<double *>(Uc.data());
+    const double *G = reinterpret_cast<const double *>(Gc.data());
     int tmask = 0;
     for (int j = 0; j < kg; ++j) tmask |= 1 << lb[j];
-    std::vector<cd> v(Dg);
-    std::vector<int> idx(Dg);
-    for (int col = 0; col < D; ++col) {
-        for (int base = 0; base < D; ++base) {
-            if (base & tmask) continue;
+    int off[1 << SV_MAX_K];
+    for (int m = 0; m < Dg; ++m) {
+        off[m] = 0;
+        for (int j = 0; j < kg; ++j)
+            if ((m >> j) & 1) off[m] |= 1 << lb[j];
+    }
+    double vr[1 << SV_MAX_K], vi[1 << SV_MAX_K];
+    for (int base = 0; base < D; ++base) {
+        if (base & tmask) continue;
+        for (int col = 0; col < D; ++col) {
             for (int m = 0; m < Dg; ++m) {
-                int off = 0;
-                for (int j = 0; j < kg; ++j)
-                    if ((m >> j) & 1) off |= 1 << lb[j];
-                idx[m] = base | off;
-                v[m] = U[size_t(idx[m]) * D + col];
+                const size_t e = 2 * (size_t(base | off[m]) * D + col);
+                vr[m] = U[e];
+                vi[m] = U[e + 1];
             }
             for (int m = 0; m < Dg; ++m) {
-                cd acc = 0;
-                for (int mp = 0; mp < Dg; ++mp) acc += G[size_t(m) * Dg + mp] * v[mp];
-                U[size_t(idx[m]) * D + col] = acc;
+                double ar = 0, ai = 0;
+                const double *g = G + 2 * size_t(m) * Dg;
+                for (int mp = 0; mp < Dg; ++mp) {
+                    ar += g[2 * mp] * vr[mp] - g[2 * mp + 1] * vi[mp];
+                    ai += g[2 * mp] * vi[mp] + g[2 * mp + 1] * vr[mp];
+                }
+                const size_t e = 2 * (size_t(base | off[m]) * D + col);
+                U[e] = ar;
+                U[e + 1] = ai;
             }
         }
     }
@@ -117,8 +132,8 @@ void block_matrix(const sv_gate *g, Block &b)
     const int D = 1 << b.k;
     b.m.assign(size_t(D) * D, cd(0));
     for (int i = 0; i < D; ++i) b.m[size_t(i) * D + i] = 1;
+    std::vector<cd> G;
     for (int gi : b.members) {
-        std::vector<cd> G;
         int sq[SV_MAX_K];
         gate_matrix_canonical(g[gi], G, sq);
         int lb[SV_MAX_K];
@@ -136,6 +151,10 @@ int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTa
 {
     (void)n;
     if (max_k < 1 || max_k > SV_MAX_K) return fail(SV_ERR_ARG, "max_k %d outside 1..%d", max_k, SV_MAX_K);
+    if (rule == SV_RULE_TILED) {  // blocks for tile passes: the enhanced rule, at most 4 qubits
+        rule = SV_RULE_ENHANCED;
+        max_k = max_k < 4 ? max_k : 4;
+    }
     if (rule != SV_RULE_PAPER && rule != SV_RULE_ENHANCED && rule != SV_RULE_NONE)
         return fail(SV_ERR_ARG, "unknown fusion rule %d", rule);
     std::vector<WBlock> wb;
@@ -197,14 +216,26 @@ int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTa
     }
     blocks.clear();
     blocks.resize(wb.size());
+    size_t work = 0;
     for (size_t b = 0; b < wb.size(); ++b) {
         Block &B = blocks[b];
         B.k = 0;
         for (int p = 0; p < 64; ++p)
             if ((wb[b].mask >> p) & 1) B.q[B.k++] = p;
         B.members = wb[b].members;
-        block_matrix(g, B);
+        work += B.members.size() << (2 * B.k);
     }
+    // block matrices are independent: spread large jobs over host threads
+    const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+    const unsigned nt = work > (size_t(1) << 18) ? std::min<unsigned>(hw, unsigned(blocks.size())) : 1u;
+    std::atomic<size_t> next(0);
+    auto worker = [&]() {
+        for (size_t b; (b = next.fetch_add(1)) < blocks.size();) block_matrix(g, blocks[b]);
+    };
+    std::vector<std::thread> pool;
+    for (unsigned t = 1; t < nt; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto &th : pool) th.join();
     return SV_OK;
 }
 

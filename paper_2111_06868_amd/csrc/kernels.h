@@ -33,6 +33,15 @@ hipError_t launch_mfma_f32(int k, const int *sorted_q, const float *d_a, void *p
 hipError_t launch_mfma_split(int k, bool fp16, const int *sorted_q, const uint16_t *d_ahi,
                              const uint16_t *d_alo, void *psi, int n, hipStream_t st, int tc_log,
                              int grid_cap);
+// Multi-block tile passes (complex64, FP32 MFMA): up to kMaxTileSubBlocks
+// 4-qubit blocks whose positions have a union of at most kMaxTileUnion
+// positions, applied in one HBM pass.  d_a = the blocks' real-form matrices
+// (32 x 32 floats each, back to back).  Needs n >= 13.
+constexpr int kMaxTileSubBlocks = 4;
+constexpr int kMaxTileUnion = 9;
+bool tile_supported(int n, int union_bits);
+hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const float *d_a, void *psi, int n, hipStream_t st,
+                            int grid_cap);
 // Host-side packing of the MFMA operands of a canonical k-qubit matrix.
 void pack_real_form_f32(const cd *m, int k, float *out);
 void pack_real_form_split(const cd *m, int k, bool fp16, uint16_t *hi, uint16_t *lo);

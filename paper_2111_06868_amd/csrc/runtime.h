@@ -46,6 +46,7 @@ enum Family {
     FAM_REDUCE = 6,
     FAM_ADJOINT = 7,
     FAM_BATCH = 8,
+    FAM_TILE = 9,
 };
 
 // RAII: brackets one launch with HIP events on `st` when timing is enabled.
@@ -65,7 +66,7 @@ class LaunchTimer {
 void timing_suspend(bool on);
 
 // Kernel paths for a block.
-enum Path { PATH_REG, PATH_GENERIC, PATH_MFMA32, PATH_SPLIT_BF16, PATH_SPLIT_FP16 };
+enum Path { PATH_REG, PATH_GENERIC, PATH_MFMA32, PATH_SPLIT_BF16, PATH_SPLIT_FP16, PATH_TILE };
 
 struct Tuning {
     int reg_grid_cap[SV_MAX_K + 1];   // 0 = one thread per group
@@ -73,17 +74,19 @@ struct Tuning {
     int mfma_grid_cap[SV_MAX_K + 1];
     int split_tc_log[SV_MAX_K + 1];
     bool k4_reg;                      // FP32: k = 4 via the register kernel
+    int tile_grid_cap;
 };
 Tuning &tuning();
 Path choose_path(int dtype, int precision, int k, const int *sorted_q, int n);
 int path_family(Path p);
 
-// One block prepared for launch.
+// One block (or, for PATH_TILE, a group of 4-qubit blocks) prepared for launch.
 struct Launch {
     Path path;
-    int k;
+    int k;                 // PATH_TILE: number of blocks in the group
     int q[SV_MAX_K];
-    std::vector<cd> m;     // canonical matrix (register path)
+    std::vector<cd> m;     // canonical matrix; PATH_TILE: k matrices of 16 x 16
+    int sub_pos[dev::kMaxTileSubBlocks][4] = {};  // PATH_TILE: each block's positions
     size_t arena_off = 0;  // byte offset of device operands (other paths)
     size_t arena_off2 = 0; // second operand (split lo part)
 };
@@ -91,6 +94,9 @@ struct Launch {
 // Pack the device operands of `launches` into `stage` (host) and return the
 // total byte count; offsets are written into the launches.
 size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage);
+// Group consecutive blocks into tile passes (see tile.hip); blocks that do not
+// join a group keep their own launch.
+void group_tile_passes(const std::vector<Block> &blocks, int n, int precision, std::vector<Launch> &out);
 // Enqueue the launches on `st` with device operands at `arena`.
 int enqueue(const std::vector<Launch> &launches, int dtype, void *psi, int n, const void *arena,
             hipStream_t st);

@@ -177,6 +177,7 @@ Tuning &tuning()
         x.mfma_tc_log[6] = 5;
         x.split_tc_log[6] = 5;
         x.k4_reg = false;
+        x.tile_grid_cap = 512;
         return x;
     }();
     return t;
@@ -201,6 +202,7 @@ int path_family(Path p)
     case PATH_GENERIC: return FAM_GENERIC;
     case PATH_MFMA32: return FAM_MFMA32;
     case PATH_SPLIT_BF16: return FAM_SPLIT_BF16;
+    case PATH_TILE: return FAM_TILE;
     default: return FAM_SPLIT_FP16;
     }
 }
@@ -222,6 +224,10 @@ size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage)
         case PATH_MFMA32:
             L.arena_off = total;
             total = align256(total + dev::real_form_elems(L.k) * 4);
+            break;
+        case PATH_TILE:
+            L.arena_off = total;
+            total = align256(total + size_t(L.k) * dev::real_form_elems(4) * 4);
             break;
         default:
             L.arena_off = total;
@@ -256,6 +262,11 @@ size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage)
         case PATH_MFMA32:
             dev::pack_real_form_f32(L.m.data(), L.k, reinterpret_cast<float *>(h + L.arena_off));
             break;
+        case PATH_TILE:
+            for (int sb = 0; sb < L.k; ++sb)
+                dev::pack_real_form_f32(L.m.data() + 256 * sb, 4,
+                                        reinterpret_cast<float *>(h + L.arena_off) + dev::real_form_elems(4) * sb);
+            break;
         default:
             dev::pack_real_form_split(L.m.data(), L.k, L.path == PATH_SPLIT_FP16,
                                       reinterpret_cast<uint16_t *>(h + L.arena_off),
@@ -266,12 +277,96 @@ size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage)
     return total;
 }
 
+// Canonical 16 x 16 matrix of a block on positions q[0..k-1] (ascending)
+// padded with identity on the extra positions of p4 (ascending, 4 entries).
+static void pad_to_four(const Block &b, const int *p4, std::vector<cd> &out)
+{
+    int where[4];  // for each of the 4 padded bits: index in b.q, or -1
+    for (int j = 0; j < 4; ++j) {
+        where[j] = -1;
+        for (int i = 0; i < b.k; ++i)
+            if (b.q[i] == p4[j]) where[j] = i;
+    }
+    const int D = 1 << b.k;
+    out.assign(256, cd(0));
+    for (int r = 0; r < 16; ++r)
+        for (int c = 0; c < 16; ++c) {
+            int rr = 0, cc = 0;
+            bool same = true;
+            for (int j = 0; j < 4; ++j) {
+                const int rb = (r >> j) & 1, cb = (c >> j) & 1;
+                if (where[j] >= 0) {
+                    rr |= rb << where[j];
+                    cc |= cb << where[j];
+                } else if (rb != cb) {
+                    same = false;
+                }
+            }
+            if (same) out[size_t(r) * 16 + c] = b.m[size_t(rr) * D + cc];
+        }
+}
+
+void group_tile_passes(const std::vector<Block> &blocks, int n, int precision, std::vector<Launch> &out)
+{
+    auto mask_of = [](const Block &b) {
+        uint64_t m = 0;
+        for (int j = 0; j < b.k; ++j) m |= uint64_t(1) << b.q[j];
+        return m;
+    };
+    out.clear();
+    size_t i = 0;
+    while (i < blocks.size()) {
+        std::vector<size_t> grp = {i};
+        uint64_t um = mask_of(blocks[i]);
+        size_t j = i + 1;
+        if (blocks[i].k <= 4) {
+            while (j < blocks.size() && int(grp.size()) < dev::kMaxTileSubBlocks && blocks[j].k <= 4 &&
+                   __builtin_popcountll(um | mask_of(blocks[j])) <= dev::kMaxTileUnion) {
+                um |= mask_of(blocks[j]);
+                grp.push_back(j++);
+            }
+        }
+        if (grp.size() < 2 || !dev::tile_supported(n, __builtin_popcountll(um))) {
+            const Block &b = blocks[i];
+            Launch L;
+            L.k = b.k;
+            std::copy(b.q, b.q + SV_MAX_K, L.q);
+            L.path = choose_path(SV_C64, precision, b.k, b.q, n);
+            L.m = b.m;
+            out.push_back(std::move(L));
+            ++i;
+            continue;
+        }
+        // the union gets at least 4 positions (lowest free ones)
+        for (int p = 0; p < n && __builtin_popcountll(um) < 4; ++p) um |= uint64_t(1) << p;
+        Launch L;
+        L.path = PATH_TILE;
+        L.k = int(grp.size());
+        std::fill(L.q, L.q + SV_MAX_K, 0);
+        L.m.clear();
+        for (int sb = 0; sb < L.k; ++sb) {
+            const Block &b = blocks[grp[sb]];
+            uint64_t pm = mask_of(b);
+            for (int p = 0; p < 64 && __builtin_popcountll(pm) < 4; ++p)
+                if (((um >> p) & 1) && !((pm >> p) & 1)) pm |= uint64_t(1) << p;
+            int c = 0;
+            for (int p = 0; p < 64; ++p)
+                if ((pm >> p) & 1) L.sub_pos[sb][c++] = p;
+            std::vector<cd> m4;
+            pad_to_four(b, L.sub_pos[sb], m4);
+            L.m.insert(L.m.end(), m4.begin(), m4.end());
+        }
+        out.push_back(std::move(L));
+        i = j;
+    }
+}
+
 int enqueue(const std::vector<Launch> &launches, int dtype, void *psi, int n, const void *arena, hipStream_t st)
 {
     const char *A = static_cast<const char *>(arena);
     const Tuning &T = tuning();
     for (const auto &L : launches) {
-        LaunchTimer timer(10 * path_family(L.path) + L.k, st);
+        LaunchTimer timer(10 * path_family(L.path) + L.k, st);  // PATH_TILE: k = blocks in the pass
         hipError_t e = hipSuccess;
         switch (L.path) {
         case PATH_REG: e = dev::launch_reg(dtype, L.k, L.q, L.m.data(), psi, n, st, T.reg_grid_cap[L.k]); break;
@@ -279,6 +374,10 @@ int enqueue(const std::vector<Launch> &launches, int dtype, void *psi, int n, co
         case PATH_MFMA32:
             e = dev::launch_mfma_f32(L.k, L.q, reinterpret_cast<const float *>(A + L.arena_off), psi, n, st,
                                      T.mfma_tc_log[L.k], T.mfma_grid_cap[L.k]);
+            break;
+        case PATH_TILE:
+            e = dev::launch_tile_pass(L.k, L.sub_pos, reinterpret_cast<const float *>(A + L.arena_off), psi, n, st,
+                                      T.tile_grid_cap);
             break;
         default:
             e = dev::launch_mfma_split(L.k, L.path == PATH_SPLIT_FP16, L.q,

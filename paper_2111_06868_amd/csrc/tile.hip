@@ -1,0 +1,214 @@
+// Multi-block tile passes: several consecutive fused 4-qubit blocks applied
+// to a state in ONE read and ONE write of HBM.
+//
+// The blocks of a pass act on a union U of at most 9 positions.  A tile is
+// the 2^13 amplitudes spanned by U plus the lowest 13 - |U| positions
+// outside U (tile bit b <-> position u_b, ascending), i.e. 64 KiB of
+// complex64 in LDS.  For every value of the remaining n - 13 bits there is one
+// tile; tiles are copied in and out with 16-byte accesses along contiguous
+// runs (tile bit 0 is always position 0).
+//
+// Inside the tile, block s (4 positions at tile bits t_s0 < .. < t_s3) is a
+// complex GEMM Y = U_s X with X viewed as 16 rows (the block's tile bits) x
+// 512 columns (the other nine tile bits): one v_mfma_f32_32x32x2f32 chain per
+// 32-column block, the real form A' = [[Ur,-Ui],[Ui,Ur]] interleaved by
+// (re, im) held in VGPRs (16 per lane per block) for the whole persistent
+// kernel, B operands and results addressed in LDS as row_offset(j) +
+// column_offset(c) (bit deposits).  Each wave owns whole columns, so blocks
+// update the tile in place with one barrier between blocks.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+
+#include "kernels.h"
+
+namespace sv {
+namespace dev {
+
+namespace {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kTileBits = 13;
+constexpr int kTileN = 1 << kTileBits;
+constexpr int kTileThreads = 512;
+constexpr int kTileWaves = kTileThreads / 64;
+constexpr int kCols = kTileN / 16;           // 512 columns per 4-qubit block
+constexpr int kNBPerWave = kCols / 32 / kTileWaves;  // 2
+constexpr int kChunks = kTileN / 2 / kTileThreads;   // 16-byte copies per thread: 8
+
+struct TileArgs {
+    uint64_t n_tiles;
+    int ubit[kTileBits];               // tile bit -> global position
+    int ext_pos[SV_MAX_QUBITS_C64];    // positions outside the tile, ascending
+    int n_ext;
+    int tbit[kMaxTileSubBlocks][4];    // per block: its tile bits, ascending
+};
+
+__device__ __forceinline__ uint32_t deposit(uint32_t v, uint32_t mask)
+{
+    // scatter the low bits of v into the set bits of mask (ascending)
+    uint32_t r = 0;
+    for (uint32_t m = mask; m; m &= m - 1) {
+        const uint32_t low = m & (~m + 1);
+        if (v & 1) r |= low;
+        v >>= 1;
+    }
+    return r;
+}
+
+__device__ __forceinline__ uint64_t tile_base(uint64_t T, const TileArgs &a)
+{
+    // the tile index's bits go to the positions outside the tile, ascending
+    uint64_t x = 0;
+    for (int i = 0; i < a.n_ext; ++i) x |= ((T >> i) & 1) << a.ext_pos[i];
+    return x;
+}
+
+__device__ __forceinline__ uint64_t global_off(uint32_t t, const TileArgs &a)
+{
+    uint64_t g = 0;
+#pragma unroll
+    for (int b = 0; b < kTileBits; ++b)
+        if ((t >> b) & 1) g += uint64_t(1) << a.ubit[b];
+    return g;
+}
+
+template <int NSUB>
+__global__ void __launch_bounds__(kTileThreads) k_tile_pass(float *__restrict__ psi, const float *__restrict__ A,
+                                                            const TileArgs args)
+{
+    __shared__ float2 X[kTileN];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int half = lane >> 5, l32 = lane & 31;
+
+    // A' of every block in registers: a[s][j] = A'_s[l32][2j + half]
+    float a[NSUB][16];
+#pragma unroll
+    for (int s = 0; s < NSUB; ++s)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) a[s][j] = A[s * 1024 + l32 * 32 + 2 * j + half];
+
+    // LDS offsets: row_off[s][j] (uniform) and this lane's column offsets
+    uint32_t col_off[NSUB][kNBPerWave];
+    uint32_t row_mask[NSUB];
+#pragma unroll
+    for (int s = 0; s < NSUB; ++s) {
+        uint32_t m = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) m |= 1u << args.tbit[s][i];
+        row_mask[s] = m;
+#pragma unroll
+        for (int q = 0; q < kNBPerWave; ++q)
+            col_off[s][q] = deposit(uint32_t((w * kNBPerWave + q) * 32 + l32), (kTileN - 1) & ~m);
+    }
+
+    // copy offsets: chunk i of this thread covers tile index t = 2*(tid + i*kTileThreads)
+    uint64_t g_lo = global_off(uint32_t(2 * tid), args);
+    uint64_t g_hi[kChunks];
+#pragma unroll
+    for (int i = 0; i < kChunks; ++i) g_hi[i] = global_off(uint32_t(2 * i * kTileThreads), args);
+
+    uint64_t T = blockIdx.x;
+    float4 buf[kChunks];
+    if (T < args.n_tiles) {
+        const uint64_t base = tile_base(T, args) + g_lo;
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) buf[i] = *reinterpret_cast<const float4 *>(psi + 2 * (base + g_hi[i]));
+    }
+    for (; T < args.n_tiles; T += gridDim.x) {
+        const uint64_t base = tile_base(T, args) + g_lo;
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i)
+            reinterpret_cast<float4 *>(X)[tid + i * kTileThreads] = buf[i];
+        __syncthreads();
+        const uint64_t Tn = T + gridDim.x;
+        if (Tn < args.n_tiles) {
+            const uint64_t nbase = tile_base(Tn, args) + g_lo;
+#pragma unroll
+            for (int i = 0; i < kChunks; ++i) buf[i] = *reinterpret_cast<const float4 *>(psi + 2 * (nbase + g_hi[i]));
+        }
+        const float *Xf = reinterpret_cast<const float *>(X);
+#pragma unroll
+        for (int s = 0; s < NSUB; ++s) {
+            uint32_t row_off[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) row_off[j] = deposit(uint32_t(j), row_mask[s]);
+#pragma unroll
+            for (int q = 0; q < kNBPerWave; ++q) {
+                const uint32_t co = col_off[s][q];
+                f32x16 acc;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[v] = 0.f;
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s][j], Xf[2 * (row_off[j] + co) + half], acc, 0, 0, 0);
+                // D real row = 8*(v/4) + 4*half + v%4; complex row = real row / 2
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int r0 = 4 * g + 2 * half;
+                    X[row_off[r0] + co] = make_float2(acc[4 * g + 0], acc[4 * g + 1]);
+                    X[row_off[r0 + 1] + co] = make_float2(acc[4 * g + 2], acc[4 * g + 3]);
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i)
+            *reinterpret_cast<float4 *>(psi + 2 * (base + g_hi[i])) = reinterpret_cast<const float4 *>(X)[tid + i * kTileThreads];
+        __syncthreads();
+    }
+}
+
+template <int NSUB>
+hipError_t tile_launch(const TileArgs &a, const float *d_a, float *psi, hipStream_t st, int cap)
+{
+    uint64_t g = a.n_tiles;
+    if (cap > 0 && g > uint64_t(cap)) g = cap;
+    hipLaunchKernelGGL((k_tile_pass<NSUB>), dim3(unsigned(g)), dim3(kTileThreads), 0, st, psi, d_a, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+bool tile_supported(int n, int union_bits) { return n >= kTileBits && union_bits <= kMaxTileUnion; }
+
+hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const float *d_a, void *psi, int n, hipStream_t st,
+                            int grid_cap)
+{
+    if (n_sub < 1 || n_sub > kMaxTileSubBlocks || n < kTileBits) return hipErrorInvalidValue;
+    TileArgs a;
+    std::memset(&a, 0, sizeof a);
+    uint64_t umask = 0;
+    for (int s = 0; s < n_sub; ++s)
+        for (int i = 0; i < 4; ++i) umask |= uint64_t(1) << sub_pos[s][i];
+    const int nu = __builtin_popcountll(umask);
+    if (nu > kMaxTileUnion) return hipErrorInvalidValue;
+    // tile positions: the union plus the lowest positions outside it
+    uint64_t tmask = umask;
+    for (int p = 0; p < n && __builtin_popcountll(tmask) < kTileBits; ++p) tmask |= uint64_t(1) << p;
+    int b = 0;
+    for (int p = 0; p < n; ++p) {
+        if ((tmask >> p) & 1) a.ubit[b++] = p;
+        else a.ext_pos[a.n_ext++] = p;
+    }
+    for (int s = 0; s < n_sub; ++s)
+        for (int i = 0; i < 4; ++i) {
+            int t = 0;
+            while (a.ubit[t] != sub_pos[s][i]) ++t;
+            a.tbit[s][i] = t;
+        }
+    a.n_tiles = uint64_t(1) << (n - kTileBits);
+    float *p = static_cast<float *>(psi);
+    switch (n_sub) {
+    case 1: return tile_launch<1>(a, d_a, p, st, grid_cap);
+    case 2: return tile_launch<2>(a, d_a, p, st, grid_cap);
+    case 3: return tile_launch<3>(a, d_a, p, st, grid_cap);
+    case 4: return tile_launch<4>(a, d_a, p, st, grid_cap);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace dev
+}  // namespace sv

@@ -1,0 +1,102 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times (fused, enhanced rule, k <= 5, FP32 MFMA).
+
+* 30 qubits: a prefix of the 845-gate circuit against the CPU oracle on the
+  whole 2^30-amplitude state, then the whole circuit against a complex128 GPU
+  run (fidelity, norm, first 2^20 amplitudes).
+* 32 qubits: the 632-gate circuit with k = 4..6 blocks in FP32 and in split
+  BF16 / FP16 against a complex128 GPU run.
+* 20-qubit ansatz: adjoint gradients against oracle parameter shift and
+  finite differences on sampled parameters.
+These need a large GPU (up to 96 GiB) and host memory (up to 24 GiB)."""
+import math
+
+import numpy as np
+import pytest
+
+import paper_2111_06868_amd as sv
+from oracle import ref
+from workloads import circuits as wc
+from helpers import to_binding
+
+pytestmark = pytest.mark.gpu
+
+
+def _fe_dev(a, b):
+    return sv.fidelity_error(a, b)
+
+
+def test_30q_prefix_vs_oracle_full_state():
+    n, gates = wc.config_circuit(1)
+    prefix = gates[:100]
+    st = sv.State(n, "c64").run(to_binding(prefix), max_k=5, rule=sv.RULE_ENHANCED)
+    got = st.read()
+    del st
+    want = ref.simulate(n, prefix, "0")
+    fe = ref.fidelity_error(want, got)
+    ma = float(np.max(np.abs(want - got)))
+    print("[parity] 30q prefix(100 gates) fused k<=5 vs oracle: 1-F=%.3e max_abs=%.3e" % (fe, ma), flush=True)
+    assert fe <= 1e-5 and ma <= 1e-6
+
+
+def test_30q_full_circuit_vs_c128():
+    n, gates = wc.config_circuit(1)
+    g = sv.GateArray(to_binding(gates))
+    refst = sv.State(n, "c128").run(g)
+    fused = sv.State(n, "c64").run(g, max_k=5, rule=sv.RULE_ENHANCED)
+    fe = _fe_dev(refst, fused)
+    a = refst.read(0, 1 << 20)
+    b = fused.read(0, 1 << 20)
+    ma = float(np.max(np.abs(a - b)))
+    print("[parity] 30q full fused k<=5 vs GPU c128: 1-F=%.3e max_abs(first 2^20)=%.3e norm-1=%.2e"
+          % (fe, ma, fused.norm2() - 1), flush=True)
+    assert fe <= 1e-5
+    assert abs(refst.norm2() - 1) <= 1e-12
+    # Porter-Thomas sanity (not a pin): 2^n sum |psi|^4 ~ 2 for a deep random circuit
+    p = np.abs(a) ** 2
+    assert 1.0 < (1 << 20) * np.sum(p ** 2) / np.sum(p) ** 2 < 3.0
+
+
+@pytest.fixture(scope="module")
+def ref32():
+    n, gates = wc.config_circuit(2)
+    g = sv.GateArray(to_binding(gates))
+    refst = sv.State(n, "c128").run(g, max_k=6, rule=sv.RULE_ENHANCED)
+    assert abs(refst.norm2() - 1) <= 1e-12
+    yield n, g, refst
+    refst.free()
+
+
+@pytest.mark.parametrize("precision", [sv.PREC_FP32, sv.PREC_SPLIT_BF16, sv.PREC_SPLIT_FP16])
+def test_32q_blocks_vs_c128(ref32, precision):
+    n, g, refst = ref32
+    st = sv.State(n, "c64").run(g, max_k=6, rule=sv.RULE_ENHANCED, precision=precision)
+    fe = _fe_dev(refst, st)
+    ma = float(np.max(np.abs(refst.read(0, 1 << 20) - st.read(0, 1 << 20))))
+    print("[parity] 32q fused k<=6 precision=%d vs GPU c128: 1-F=%.3e max_abs(first 2^20)=%.3e"
+          % (precision, fe, ma), flush=True)
+    assert fe <= 1e-5
+
+
+def test_20q_ansatz_adjoint_sampled():
+    n = 20
+    gates, thetas = wc.ansatz_circuit(n, 12, seed=3)
+    H = wc.ansatz_observable(n)
+    psi = sv.State(n, "c64").run(to_binding(gates), max_k=4, rule=sv.RULE_ENHANCED)
+    e = psi.expectation(H)
+    e_ref = ref.energy(n, gates, thetas, H)
+    scratch = sv.State(n, "c64")
+    g = sv.backward(psi, scratch, to_binding(gates), H, len(thetas))
+    idx = list(range(0, 480, 40)) + [479, 21, 200]
+    ps = ref.param_shift_grad(n, gates, thetas, H, indices=idx)
+    fd = ref.fd_grad(n, gates, thetas, H, h=1e-3, indices=idx)
+    rel_ps = np.linalg.norm(g[idx] - ps) / np.linalg.norm(ps)
+    rel_fd = np.linalg.norm(g[idx] - fd) / np.linalg.norm(fd)
+    print("[parity] 20q ansatz E=%.8f (oracle %.8f); grad rel vs PS %.3e, vs FD(h=1e-3) %.3e"
+          % (e, e_ref, rel_ps, rel_fd), flush=True)
+    assert abs(e - e_ref) <= 1e-4
+    assert rel_ps <= 1e-4 and rel_fd <= 1e-4
+    scale = 1e-2 * np.max(np.abs(ps))
+    assert np.all(np.abs(g[idx] - ps) <= 1e-4 * np.maximum(np.abs(ps), scale))
+    # the adjoint pass consumed psi back to |0..0>
+    assert abs(abs(psi.read(0, 1)[0]) - 1) <= 1e-4

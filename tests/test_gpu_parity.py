@@ -283,3 +283,31 @@ def test_energy_autograd():
     ps = ref.param_shift_grad(n, gates, thetas, H)
     assert abs(E.item() - ref.energy(n, gates, thetas, H)) <= 1e-5
     assert np.linalg.norm(th.grad.numpy() - ps) / np.linalg.norm(ps) <= 1e-4
+
+
+# ----------------------------------------------------------------- tile passes
+@pytest.mark.parametrize("n", [13, 14, 16, 19])
+@pytest.mark.parametrize("max_k", [2, 3, 4])
+def test_tiled_passes_vs_oracle(n, max_k):
+    """Consecutive fused blocks applied together in LDS tile passes."""
+    rng = np.random.default_rng(500 + n + 10 * max_k)
+    gates = wc.random_gate_list(n, 8 * n, rng, max_k=2)
+    sv.stats_reset()
+    sv.stats_enable(True)
+    try:
+        want, got, st = run_both(n, gates, "+", "c64", max_k=max_k, rule=sv.RULE_TILED)
+        st.synchronize()
+        tiles = sum(sv.stats_query("tile", s)[0] for s in range(1, 5))
+    finally:
+        sv.stats_enable(False)
+        sv.stats_reset()
+    fe, ma = _report("tiled n=%d k<=%d (%d tile passes)" % (n, max_k, tiles), want, got)
+    assert tiles > 0
+    assert fe <= FID_C64 and ma <= 1e-5
+
+
+def test_c0_tiled():
+    n, gates = wc.config_circuit(0)
+    want, got, _ = run_both(n, gates, "0", "c64", max_k=4, rule=sv.RULE_TILED)
+    fe, ma = _report("c0 tiled k<=4", want, got)
+    assert fe <= FID_C64 and ma <= 1e-5
