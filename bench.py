@@ -29,8 +29,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 MFMA_FP32_PEAK_TFLOPS = 157.3
-FAMILY_NAMES = {1: "reg", 2: "generic", 3: "mfma_f32", 4: "split_bf16", 5: "split_fp16"}
-KERNEL_SOURCES = {1: "apply.hip", 2: "apply.hip", 3: "mfma.hip", 4: "mfma.hip", 5: "mfma.hip"}
+FAMILY_NAMES = {1: "reg", 2: "generic", 3: "mfma_f32", 4: "split_bf16", 5: "split_fp16", 9: "tile"}
+KERNEL_SOURCES = {1: "apply.hip", 2: "apply.hip", 3: "mfma.hip", 4: "mfma.hip", 5: "mfma.hip", 9: "tile.hip"}
 
 
 def log(*a):
@@ -89,7 +89,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--max-k", type=int, default=5)
-    ap.add_argument("--rule", default="enhanced", choices=["paper", "enhanced"])
+    ap.add_argument("--rule", default="enhanced", choices=["paper", "enhanced", "tiled"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--config", type=int, default=1, choices=[1, 2])
     ap.add_argument("--workload", default="circuit", choices=["circuit", "gradient", "trajectories"],
@@ -119,7 +119,7 @@ def main():
     n, gates = wc.config_circuit(args.config)
     bound = [(g.name, g.qubits, g.params) for g in gates]
     ga = sv.GateArray(bound)
-    rule = sv.RULE_ENHANCED if args.rule == "enhanced" else sv.RULE_PAPER
+    rule = {"enhanced": sv.RULE_ENHANCED, "paper": sv.RULE_PAPER, "tiled": sv.RULE_TILED}[args.rule]
     prec = {"fp32": sv.PREC_FP32, "bf16": sv.PREC_SPLIT_BF16, "fp16": sv.PREC_SPLIT_FP16}[args.precision]
     G = len(gates)
     pass_bytes = 16.0 * (1 << n)
@@ -136,7 +136,7 @@ def main():
         max_k = plan.max_k
         args.max_k = max_k
     blocks = plan.blocks(False)
-    n_passes = len(blocks)
+    n_passes = len(blocks)  # tiled: several blocks share one pass (counted from the launches below)
     kh = {}
     for b in blocks:
         kh[len(b.qubits)] = kh.get(len(b.qubits), 0) + 1
@@ -176,12 +176,17 @@ def main():
     avg_ms = dms / dcnt
     achieved = pass_bytes / (avg_ms * 1e-3) / 1e9
     kernel_ms_total = sum(ms for _, ms in per_class.values()) / args.steps
+    state_passes = sum(cnt for cnt, _ in per_class.values()) // args.steps
     traffic = read_traffic(dfam, dk, n)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
                 "kernel": "%s k=%d" % (FAMILY_NAMES[dfam], dk), "avg_launch_ms": round(avg_ms, 4),
                 "launches_per_step": dcnt // args.steps,
                 "algorithmic_bytes_per_launch": pass_bytes}
+    if dfam == 9:
+        flops = 8.0 * 16 * (1 << n) * dk  # dk blocks of 4 qubits per tile pass
+        roofline["mfma_tflops"] = round(flops / (avg_ms * 1e-3) / 1e12, 2)
+        roofline["mfma_frac"] = round(roofline["mfma_tflops"] / MFMA_FP32_PEAK_TFLOPS, 4)
     if dfam in (3, 4, 5):
         flops = 8.0 * (1 << dk) * (1 << n) * (3 if dfam in (4, 5) else 1)
         roofline["mfma_tflops"] = round(flops / (avg_ms * 1e-3) / 1e12, 2)
@@ -265,7 +270,8 @@ def main():
                       args.rule, args.precision),
                    "qubits": n, "gates": G, "max_k": args.max_k, "blocks": n_passes,
                    "block_sizes": {str(k): v for k, v in sorted(kh.items())}},
-        "effective_GBps": round(n_passes * pass_bytes / (ms_step * 1e-3) / 1e9, 1),
+        "state_passes": state_passes,
+        "effective_GBps": round(state_passes * pass_bytes / (ms_step * 1e-3) / 1e9, 1),
         "kernel_ms_per_step": round(kernel_ms_total, 3),
         "roofline": roofline,
         "cpu_baseline": cpu,

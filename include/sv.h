@@ -251,11 +251,15 @@ int sv_apply_pauli_sum(sv_state *psi, const sv_pauli_sum *H, sv_state *out);
  * (the paper is silent on gradients; method: adjoint differentiation, Jones &
  * Gacon 2020).  `psi` must hold the forward output of exactly these gates and
  * is consumed (it ends as U_1^+ .. U_G^+ psi, i.e. psi_0 up to rounding);
- * `scratch` is a second state of the same n and type.  For every gate with
+ * `scratch` is a second state of the same n and type (lam = H psi, then swept
+ * back with psi: two buffers, no stored trajectory).  For every gate with
  * param >= 0 (which must be SV_G_RX, SV_G_RY or SV_G_RZ),
- * grad[param] += dE/dtheta, accumulated in FP64; other entries are untouched,
- * so the caller zeroes grad first.  Synchronises.
- * Errors: SV_ERR_ARG (param >= n_params, a param on a non-rotation). */
+ * grad[param] += dE/dtheta = Im <lam|P|phi>, accumulated in FP64; other
+ * entries are untouched, so the caller zeroes grad first.  A run of
+ * consecutive rotations on distinct qubits shares one gradient pass (they
+ * commute); runs of other gates are undone as fused dagger blocks.
+ * Synchronises.  Errors: SV_ERR_ARG (param >= n_params, a param on a
+ * non-rotation). */
 int sv_backward(sv_state *psi, sv_state *scratch, const sv_gate *g, int G, const sv_pauli_sum *H,
                 double *grad, int n_params);
 

@@ -623,6 +623,64 @@ extern "C" int sv_apply_pauli_sum(sv_state *psi, const sv_pauli_sum *H, sv_state
 }
 
 // ============================================================== adjoint
+namespace {
+
+// One step of the backward sweep (gates are visited from last to first).
+struct BwdStep {
+    enum Kind { SINGLE, RUN, UNDO } kind;
+    int gate = -1;        // SINGLE: the gate
+    int slot = -1;        // SINGLE: gradient slot or -1; RUN: first slot
+    int n_terms = 0;      // RUN: rotations in the run
+    uint64_t x[dev::kMaxGradTerms] = {}, z[dev::kMaxGradTerms] = {};
+    int pw[dev::kMaxGradTerms] = {};
+    size_t l0 = 0, l1 = 0;  // RUN / UNDO: launches [l0, l1) that undo the gates
+};
+
+// Fuse the daggers of gates hi, hi-1, .., lo (in that order) into blocks and
+// append their launches.
+int dagger_launches(const sv_gate *g, int hi, int lo, const sv_state *s, std::vector<Launch> &out)
+{
+    const int cnt = hi - lo + 1;
+    std::vector<sv_gate> dg(cnt);
+    std::vector<std::vector<double>> store(cnt);
+    int kmax = 1;
+    for (int t = 0; t < cnt; ++t) {
+        const sv_gate &src = g[hi - t];
+        std::vector<cd> m;
+        if (int rc = gate_matrix_abi(src, m)) return rc;
+        const int D = 1 << src.k;
+        store[t].resize(2 * size_t(D) * D);
+        for (int r = 0; r < D; ++r)
+            for (int c = 0; c < D; ++c) {
+                const cd v = std::conj(m[size_t(c) * D + r]);
+                store[t][2 * (size_t(r) * D + c)] = v.real();
+                store[t][2 * (size_t(r) * D + c) + 1] = v.imag();
+            }
+        sv_gate d = src;
+        d.kind = SV_G_MATRIX;
+        d.param = -1;
+        d.m = store[t].data();
+        dg[t] = d;
+        kmax = std::max(kmax, src.k);
+    }
+    std::vector<Block> blocks;
+    const int prec = s->dtype == SV_C64 ? SV_PREC_FP32 : SV_PREC_FP64;
+    if (int rc = fuse_gates(dg.data(), cnt, s->n, std::max(kmax, 4), SV_RULE_ENHANCED, lookup_costs(s->n, prec, nullptr),
+                            blocks))
+        return rc;
+    for (const auto &b : blocks) {
+        Launch L;
+        L.k = b.k;
+        std::copy(b.q, b.q + SV_MAX_K, L.q);
+        L.path = choose_path(s->dtype, prec, b.k, b.q, s->n);
+        L.m = b.m;
+        out.push_back(std::move(L));
+    }
+    return SV_OK;
+}
+
+}  // namespace
+
 extern "C" int sv_backward(sv_state *psi, sv_state *scratch, const sv_gate *g, int G, const sv_pauli_sum *H,
                            double *grad, int n_params)
 {
@@ -633,39 +691,113 @@ extern "C" int sv_backward(sv_state *psi, sv_state *scratch, const sv_gate *g, i
     if (n_params < 0 || (n_params > 0 && !grad)) return fail(SV_ERR_ARG, "bad gradient buffer");
     if (int rc = validate_gates(g, G, psi->n)) return rc;
     if (int rc = check_pauli(H, psi->n)) return rc;
-    int slots = 0;
-    for (int i = 0; i < G; ++i) {
-        if (g[i].k > 2) return fail(SV_ERR_UNSUPPORTED, "gate %d: the adjoint pass handles gates of at most 2 qubits", i);
+    for (int i = 0; i < G; ++i)
         if (g[i].param >= n_params) return fail(SV_ERR_ARG, "gate %d: param %d >= n_params %d", i, g[i].param, n_params);
-        slots += g[i].param >= 0;
+
+    // plan the sweep: runs of rotations on distinct qubits share one gradient
+    // pass (they commute, so each sees the same phi and lam); runs of
+    // non-parameterised gates are undone as fused dagger blocks
+    std::vector<BwdStep> steps;
+    std::vector<Launch> launches;
+    std::vector<int> slot_param;
+    int i = G - 1;
+    while (i >= 0) {
+        if (g[i].param >= 0) {
+            uint64_t used = 0;
+            int j = i;
+            while (j >= 0 && g[j].param >= 0 && g[j].k == 1 && !((used >> g[j].q[0]) & 1) &&
+                   i - j < dev::kMaxGradTerms) {
+                used |= uint64_t(1) << g[j].q[0];
+                --j;
+            }
+            if (i - j >= 2) {
+                BwdStep st;
+                st.kind = BwdStep::RUN;
+                st.slot = int(slot_param.size());
+                for (int t = i; t > j; --t) {
+                    const uint64_t b = uint64_t(1) << g[t].q[0];
+                    const int e = st.n_terms++;
+                    st.x[e] = g[t].kind == SV_G_RZ ? 0 : b;
+                    st.z[e] = g[t].kind == SV_G_RX ? 0 : b;
+                    st.pw[e] = g[t].kind == SV_G_RY ? 1 : 0;
+                    slot_param.push_back(g[t].param);
+                }
+                st.l0 = launches.size();
+                if (int rc = dagger_launches(g, i, j + 1, psi, launches)) return rc;
+                st.l1 = launches.size();
+                steps.push_back(st);
+                i = j;
+                continue;
+            }
+            BwdStep st;
+            st.kind = BwdStep::SINGLE;
+            st.gate = i;
+            st.slot = int(slot_param.size());
+            slot_param.push_back(g[i].param);
+            steps.push_back(st);
+            --i;
+            continue;
+        }
+        int j = i;
+        while (j >= 0 && g[j].param < 0) --j;
+        if (i - j == 1 && g[i].k <= 2) {
+            BwdStep st;
+            st.kind = BwdStep::SINGLE;
+            st.gate = i;
+            steps.push_back(st);
+            --i;
+            continue;
+        }
+        BwdStep st;
+        st.kind = BwdStep::UNDO;
+        st.l0 = launches.size();
+        if (int rc = dagger_launches(g, i, j + 1, psi, launches)) return rc;
+        st.l1 = launches.size();
+        steps.push_back(st);
+        i = j;
     }
+    const int slots = int(slot_param.size());
+
     if (int rc = select_device(psi)) return rc;
     // lam <- H psi on psi's stream
     if (int rc = sv_apply_pauli_sum(psi, H, scratch)) return rc;
+    SV_HIP(hipEventSynchronize(psi->arena_free));
+    const size_t bytes = pack_operands(launches, psi->dtype, psi->stage);
+    if (bytes == size_t(-1)) return fail(SV_ERR_HIP, "pinned staging allocation failed");
+    if (bytes) {
+        SV_HIP(psi->arena.ensure(bytes));
+        SV_HIP(hipMemcpyAsync(psi->arena.p, psi->stage.p, bytes, hipMemcpyHostToDevice, psi->stream));
+    }
     const size_t part_doubles = size_t(std::max(slots, 1)) * dev::kRedBlocks * 2;
     SV_HIP(psi->grad.ensure((part_doubles + 2 * size_t(std::max(slots, 1))) * sizeof(double)));
     double *part = static_cast<double *>(psi->grad.p);
     double *sums = part + part_doubles;
-    std::vector<int> slot_param;
-    slot_param.reserve(slots);
-    for (int i = G - 1; i >= 0; --i) {
-        std::vector<cd> m, mdag;
-        int sq[SV_MAX_K];
-        if (int rc = gate_matrix_canonical(g[i], m, sq)) return rc;
-        const int D = 1 << g[i].k;
-        mdag.resize(m.size());
-        for (int r = 0; r < D; ++r)
-            for (int c = 0; c < D; ++c) mdag[size_t(r) * D + c] = std::conj(m[size_t(c) * D + r]);
-        int pauli = 0, slot = -1;
-        if (g[i].param >= 0) {
-            pauli = g[i].kind == SV_G_RX ? 1 : g[i].kind == SV_G_RY ? 2 : 3;
-            slot = int(slot_param.size());
-            slot_param.push_back(g[i].param);
+    for (const BwdStep &st : steps) {
+        if (st.kind == BwdStep::SINGLE) {
+            const sv_gate &gg = g[st.gate];
+            std::vector<cd> m, mdag;
+            int sq[SV_MAX_K];
+            if (int rc = gate_matrix_canonical(gg, m, sq)) return rc;
+            const int D = 1 << gg.k;
+            mdag.resize(m.size());
+            for (int r = 0; r < D; ++r)
+                for (int c = 0; c < D; ++c) mdag[size_t(r) * D + c] = std::conj(m[size_t(c) * D + r]);
+            const int pauli = st.slot < 0 ? 0 : gg.kind == SV_G_RX ? 1 : gg.kind == SV_G_RY ? 2 : 3;
+            LaunchTimer t(10 * FAM_ADJOINT + gg.k, psi->stream);
+            SV_HIP(dev::launch_backward_step(psi->dtype, gg.k, sq, mdag.data(), pauli, psi->buf, scratch->buf, psi->n,
+                                             part, st.slot, psi->stream));
+            continue;
         }
-        LaunchTimer t(10 * FAM_ADJOINT + g[i].k, psi->stream);
-        SV_HIP(dev::launch_backward_step(psi->dtype, g[i].k, sq, mdag.data(), pauli, psi->buf, scratch->buf, psi->n,
-                                         part, slot, psi->stream));
+        if (st.kind == BwdStep::RUN) {
+            LaunchTimer t(10 * FAM_ADJOINT + 3, psi->stream);
+            SV_HIP(dev::launch_grad_terms(psi->dtype, st.n_terms, st.x, st.z, st.pw, psi->buf, scratch->buf, psi->n,
+                                          part, st.slot, psi->stream));
+        }
+        const std::vector<Launch> sub(launches.begin() + st.l0, launches.begin() + st.l1);
+        if (int rc = enqueue(sub, psi->dtype, psi->buf, psi->n, psi->arena.p, psi->stream)) return rc;
+        if (int rc = enqueue(sub, psi->dtype, scratch->buf, psi->n, psi->arena.p, psi->stream)) return rc;
     }
+    SV_HIP(hipEventRecord(psi->arena_free, psi->stream));
     if (slots) {
         SV_HIP(dev::launch_sum_partials(part, slots, sums, psi->stream));
         std::vector<double> h(2 * size_t(slots));

@@ -159,7 +159,102 @@ hipError_t bwd_launch_t(const int *sorted_q, const cd *mdag, int pauli, T *phi, 
     return hipGetLastError();
 }
 
+// <lam| P_t |phi> for up to kMaxGradTerms Pauli strings in one pass over the
+// two states (used for a run of commuting rotations: every rotation of the
+// run sees the same phi and lam, see sv_backward).
+struct GradTerms {
+    int n_terms;
+    uint64_t x[kMaxGradTerms];
+    uint64_t z[kMaxGradTerms];
+    int pw[kMaxGradTerms];  // power of i (number of Y factors mod 4)
+    uint64_t N;
+};
+
+__device__ __forceinline__ void ld2(const float *p, uint64_t i, double &re, double &im)
+{
+    const float2 v = reinterpret_cast<const float2 *>(p)[i];
+    re = v.x;
+    im = v.y;
+}
+__device__ __forceinline__ void ld2(const double *p, uint64_t i, double &re, double &im)
+{
+    const double2 v = reinterpret_cast<const double2 *>(p)[i];
+    re = v.x;
+    im = v.y;
+}
+
+template <typename T, int NT>
+__global__ void __launch_bounds__(kRedThreads) k_grad_terms(const T *__restrict__ phi, const T *__restrict__ lam,
+                                                           const GradTerms a, double *__restrict__ partials)
+{
+    double sr[NT], si[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) sr[t] = si[t] = 0.0;
+    for (uint64_t i = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; i < a.N; i += uint64_t(kRedBlocks) * kRedThreads) {
+        double lr, li;
+        ld2(lam, i, lr, li);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            if (t >= a.n_terms) break;
+            const uint64_t j = i ^ a.x[t];
+            double pr, pi;
+            ld2(phi, j, pr, pi);
+            if (__popcll(j & a.z[t]) & 1) {
+                pr = -pr;
+                pi = -pi;
+            }
+            // multiply by i^pw
+            double qr = pr, qi = pi;
+            switch (a.pw[t] & 3) {
+            case 1: qr = -pi; qi = pr; break;
+            case 2: qr = -pr; qi = -pi; break;
+            case 3: qr = pi; qi = -pr; break;
+            default: break;
+            }
+            // conj(lam_i) * (P phi)_i
+            sr[t] += lr * qr + li * qi;
+            si[t] += lr * qi - li * qr;
+        }
+    }
+    __shared__ double sh[kRedThreads];
+    const int tid = threadIdx.x;
+    for (int t = 0; t < NT && t < a.n_terms; ++t) {
+        for (int c = 0; c < 2; ++c) {
+            __syncthreads();
+            sh[tid] = c ? si[t] : sr[t];
+            __syncthreads();
+            for (int s = kRedThreads / 2; s > 0; s >>= 1) {
+                if (tid < s) sh[tid] += sh[tid + s];
+                __syncthreads();
+            }
+            if (tid == 0) partials[(size_t(t) * kRedBlocks + blockIdx.x) * 2 + c] = sh[0];
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_grad_terms(int dtype, int n_terms, const uint64_t *x, const uint64_t *z, const int *pw,
+                             const void *phi, const void *lam, int n, double *d_partials, int slot0, hipStream_t st)
+{
+    if (n_terms < 1 || n_terms > kMaxGradTerms) return hipErrorInvalidValue;
+    GradTerms a;
+    a.n_terms = n_terms;
+    for (int t = 0; t < kMaxGradTerms; ++t) {
+        a.x[t] = t < n_terms ? x[t] : 0;
+        a.z[t] = t < n_terms ? z[t] : 0;
+        a.pw[t] = t < n_terms ? pw[t] : 0;
+    }
+    a.N = uint64_t(1) << n;
+    double *part = d_partials + size_t(slot0) * kRedBlocks * 2;
+    if (dtype == SV_C64)
+        hipLaunchKernelGGL((k_grad_terms<float, kMaxGradTerms>), dim3(kRedBlocks), dim3(kRedThreads), 0, st,
+                           static_cast<const float *>(phi), static_cast<const float *>(lam), a, part);
+    else
+        hipLaunchKernelGGL((k_grad_terms<double, kMaxGradTerms>), dim3(kRedBlocks), dim3(kRedThreads), 0, st,
+                           static_cast<const double *>(phi), static_cast<const double *>(lam), a, part);
+    return hipGetLastError();
+}
 
 hipError_t launch_backward_step(int dtype, int k, const int *sorted_q, const cd *mdag, int pauli, void *phi,
                                 void *lam, int n, double *d_partials, int slot, hipStream_t st)

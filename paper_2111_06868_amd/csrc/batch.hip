@@ -42,7 +42,9 @@ struct BBlock {
     int32_t k;
     int32_t q[SV_MAX_K];  // ascending
     int32_t mat_off;      // float2 index into the matrix pool (canonical order)
-    int32_t pad;
+    int32_t lm;           // which of positions 0, 1 are targets (bit mask)
+    int32_t kh;           // number of targets at positions >= 2
+    int32_t hp[4];        // those positions, ascending
 };
 
 struct BSmall {
@@ -121,6 +123,94 @@ __device__ __forceinline__ void apply_group_k(float2 *st, const BBlock &b, const
     }
 }
 
+// Chunked application for large states (the layout of the register kernel):
+// the thread owns 4 consecutive amplitudes for every combination of the
+// block's high targets (positions >= 2); targets at positions 0 / 1 (LM) are
+// inside the chunk.  Chunk group g has its base at insert_zeros(g << 2, hp).
+template <int K, int LM>
+__device__ __forceinline__ void apply_chunk(float2 *__restrict__ st, const BBlock &b, const float2 *__restrict__ m,
+                                            uint64_t g)
+{
+    constexpr int KL = (LM & 1) + ((LM >> 1) & 1);
+    constexpr int KH = K - KL;
+    constexpr int NH = 1 << KH;
+    constexpr int D = 1 << K;
+    uint64_t base = g << 2;
+#pragma unroll
+    for (int j = 0; j < KH; ++j) base = ins0b(base, b.hp[j]);
+    float re[NH][4], im[NH][4];
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+        uint64_t o = base;
+#pragma unroll
+        for (int j = 0; j < KH; ++j)
+            if ((h >> j) & 1) o += uint64_t(1) << b.hp[j];
+        const float4 *p = reinterpret_cast<const float4 *>(st + o);
+        const float4 u = p[0], v = p[1];
+        re[h][0] = u.x; im[h][0] = u.y; re[h][1] = u.z; im[h][1] = u.w;
+        re[h][2] = v.x; im[h][2] = v.y; re[h][3] = v.z; im[h][3] = v.w;
+    }
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        if (f & LM) continue;
+        float vr[D], vi[D];
+#pragma unroll
+        for (int mm = 0; mm < D; ++mm) {
+            const int l = f | (LM == 0 ? 0 : LM == 1 ? (mm & 1) : LM == 2 ? ((mm & 1) << 1) : (mm & 3));
+            vr[mm] = re[mm >> KL][l];
+            vi[mm] = im[mm >> KL][l];
+        }
+#pragma unroll
+        for (int mm = 0; mm < D; ++mm) {
+            float sr = 0.f, si = 0.f;
+#pragma unroll
+            for (int mp = 0; mp < D; ++mp) {
+                const float2 a = m[mm * D + mp];
+                sr = fmaf(a.x, vr[mp], sr);
+                sr = fmaf(-a.y, vi[mp], sr);
+                si = fmaf(a.x, vi[mp], si);
+                si = fmaf(a.y, vr[mp], si);
+            }
+            const int l = f | (LM == 0 ? 0 : LM == 1 ? (mm & 1) : LM == 2 ? ((mm & 1) << 1) : (mm & 3));
+            re[mm >> KL][l] = sr;
+            im[mm >> KL][l] = si;
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < NH; ++h) {
+        uint64_t o = base;
+#pragma unroll
+        for (int j = 0; j < KH; ++j)
+            if ((h >> j) & 1) o += uint64_t(1) << b.hp[j];
+        float4 *p = reinterpret_cast<float4 *>(st + o);
+        p[0] = make_float4(re[h][0], im[h][0], re[h][1], im[h][1]);
+        p[1] = make_float4(re[h][2], im[h][2], re[h][3], im[h][3]);
+    }
+}
+
+template <int K>
+__device__ __forceinline__ void apply_chunk_lm(float2 *st, const BBlock &b, const float2 *m, uint64_t g)
+{
+    switch (b.lm) {
+    case 0: apply_chunk<K, 0>(st, b, m, g); break;
+    case 1: apply_chunk<K, 1>(st, b, m, g); break;
+    case 2: apply_chunk<K, 2>(st, b, m, g); break;
+    default:
+        if constexpr (K >= 2) apply_chunk<K, 3>(st, b, m, g);
+        break;
+    }
+}
+
+__device__ __forceinline__ void apply_chunk_k(float2 *st, const BBlock &b, const float2 *m, uint64_t g)
+{
+    switch (b.k) {
+    case 1: apply_chunk_lm<1>(st, b, m, g); break;
+    case 2: apply_chunk_lm<2>(st, b, m, g); break;
+    case 3: apply_chunk_lm<3>(st, b, m, g); break;
+    default: apply_chunk_lm<4>(st, b, m, g); break;
+    }
+}
+
 __device__ double block_sum(double v)
 {
     __shared__ double sh[kThreads];
@@ -188,9 +278,17 @@ __global__ void __launch_bounds__(kThreads) k_batch_step(const BItem *__restrict
 {
     const BItem it = items[blockIdx.x];
     const BBlock b = blocks[it.block];
-    const uint64_t groups = uint64_t(1) << (b.n - b.k);
     float2 *st = buf + b.state_off;
     const float2 *m = mats + b.mat_off;
+    if (b.k <= 4) {
+        const uint64_t groups = uint64_t(1) << (b.n - 2 - b.kh);
+        for (int j = 0; j < kGroupsPerThread; ++j) {
+            const uint64_t g = it.group0 + uint64_t(j) * kThreads + threadIdx.x;
+            if (g < groups) apply_chunk_k(st, b, m, g);
+        }
+        return;
+    }
+    const uint64_t groups = uint64_t(1) << (b.n - b.k);
     for (int j = 0; j < kGroupsPerThread; ++j) {
         const uint64_t g = it.group0 + uint64_t(j) * kThreads + threadIdx.x;
         if (g < groups) apply_group_k(st, b, m, g);
@@ -297,6 +395,10 @@ int build_schedule(sv_batch *b, const sv_batch_desc *d, int k)
             x.k = B.k;
             for (int j = 0; j < B.k; ++j) x.q[j] = B.q[j];
             x.mat_off = int(mats.size());
+            for (int j = 0; j < B.k; ++j) {
+                if (B.q[j] < 2) x.lm |= 1 << B.q[j];
+                else if (x.kh < 4) x.hp[x.kh++] = B.q[j];
+            }
             for (const cd &v : B.m) mats.push_back(make_float2(float(v.real()), float(v.imag())));
             mine.push_back(int(blocks.size()));
             blocks.push_back(x);
@@ -318,7 +420,7 @@ int build_schedule(sv_batch *b, const sv_batch_desc *d, int k)
         for (auto &v : large_blocks) {
             if (s >= v.size()) continue;
             const BBlock &B = blocks[v[s]];
-            const uint64_t groups = uint64_t(1) << (B.n - B.k);
+            const uint64_t groups = B.k <= 4 ? uint64_t(1) << (B.n - 2 - B.kh) : uint64_t(1) << (B.n - B.k);
             const uint64_t per_wg = uint64_t(kThreads) * kGroupsPerThread;
             for (uint64_t g0 = 0; g0 < groups; g0 += per_wg) items.push_back({v[s], 0, g0});
         }

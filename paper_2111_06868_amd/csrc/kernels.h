@@ -35,13 +35,15 @@ hipError_t launch_mfma_split(int k, bool fp16, const int *sorted_q, const uint16
                              int grid_cap);
 // Multi-block tile passes (complex64, FP32 MFMA): up to kMaxTileSubBlocks
 // 4-qubit blocks whose positions have a union of at most kMaxTileUnion
-// positions, applied in one HBM pass.  d_a = the blocks' real-form matrices
-// (32 x 32 floats each, back to back).  Needs n >= 13.
+// positions, applied in one HBM pass over tiles of 2^tile_bits amplitudes
+// (13 or 14).  d_a = the blocks' real-form matrices (32 x 32 floats each,
+// back to back).  Needs n >= tile_bits.
 constexpr int kMaxTileSubBlocks = 4;
-constexpr int kMaxTileUnion = 9;
+constexpr int kMaxTileUnion = 8;
+constexpr int kMinTileQubits = 14;
 bool tile_supported(int n, int union_bits);
 hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const float *d_a, void *psi, int n, hipStream_t st,
-                            int grid_cap);
+                            int grid_cap, int tile_bits);
 // Host-side packing of the MFMA operands of a canonical k-qubit matrix.
 void pack_real_form_f32(const cd *m, int k, float *out);
 void pack_real_form_split(const cd *m, int k, bool fp16, uint16_t *hi, uint16_t *lo);
@@ -85,6 +87,11 @@ hipError_t launch_pauli_apply(int dtype, const void *psi, void *out, int n, cons
 hipError_t launch_backward_step(int dtype, int k, const int *sorted_q, const cd *mdag, int pauli,
                                 void *phi, void *lam, int n, double *d_partials, int slot,
                                 hipStream_t st);
+// For Pauli strings t < n_terms (x/z masks, pw = power of i), partials of
+// <lam|P_t|phi> into slots slot0 + t (same layout as above).  One pass.
+constexpr int kMaxGradTerms = 16;
+hipError_t launch_grad_terms(int dtype, int n_terms, const uint64_t *x, const uint64_t *z, const int *pw,
+                             const void *phi, const void *lam, int n, double *d_partials, int slot0, hipStream_t st);
 // out[s] = sum over blocks of d_partials[s][*] (fixed order), s < n_slots.
 hipError_t launch_sum_partials(const double *d_partials, int n_slots, double *d_out, hipStream_t st);
 

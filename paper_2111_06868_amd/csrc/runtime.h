@@ -75,6 +75,7 @@ struct Tuning {
     int split_tc_log[SV_MAX_K + 1];
     bool k4_reg;                      // FP32: k = 4 via the register kernel
     int tile_grid_cap;
+    int tile_bits;                    // 13 (64 KiB LDS tiles) or 14 (128 KiB)
 };
 Tuning &tuning();
 Path choose_path(int dtype, int precision, int k, const int *sorted_q, int n);

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 
@@ -178,6 +179,9 @@ Tuning &tuning()
         x.split_tc_log[6] = 5;
         x.k4_reg = false;
         x.tile_grid_cap = 512;
+        x.tile_bits = 14;
+        if (const char *e = std::getenv("SV_TILE_BITS")) x.tile_bits = std::atoi(e) == 13 ? 13 : 14;
+        if (const char *e = std::getenv("SV_TILE_GRID")) x.tile_grid_cap = std::max(1, std::atoi(e));
         return x;
     }();
     return t;
@@ -377,7 +381,8 @@ int enqueue(const std::vector<Launch> &launches, int dtype, void *psi, int n, co
             break;
         case PATH_TILE:
             e = dev::launch_tile_pass(L.k, L.sub_pos, reinterpret_cast<const float *>(A + L.arena_off), psi, n, st,
-                                      T.tile_grid_cap);
+                                      T.tile_bits == 13 ? T.tile_grid_cap : std::max(1, T.tile_grid_cap / 2),
+                                      T.tile_bits);
             break;
         default:
             e = dev::launch_mfma_split(L.k, L.path == PATH_SPLIT_FP16, L.q,

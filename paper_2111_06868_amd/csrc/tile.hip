@@ -1,16 +1,17 @@
 // Multi-block tile passes: several consecutive fused 4-qubit blocks applied
 // to a state in ONE read and ONE write of HBM.
 //
-// The blocks of a pass act on a union U of at most 9 positions.  A tile is
-// the 2^13 amplitudes spanned by U plus the lowest 13 - |U| positions
-// outside U (tile bit b <-> position u_b, ascending), i.e. 64 KiB of
-// complex64 in LDS.  For every value of the remaining n - 13 bits there is one
-// tile; tiles are copied in and out with 16-byte accesses along contiguous
-// runs (tile bit 0 is always position 0).
+// The blocks of a pass act on a union U of at most 8 positions.  A tile is
+// the 2^TB amplitudes (TB = 13 or 14: 64 or 128 KiB of complex64 in LDS)
+// spanned by U plus the lowest TB - |U| positions outside U (tile bit b <->
+// position u_b, ascending); at least 5 low positions join, so the tile is
+// made of contiguous runs of >= 32 amplitudes (256 B).  For every value of
+// the remaining n - TB bits there is one tile; tiles are copied in and out
+// with 16-byte accesses along those runs (tile bit 0 is always position 0).
 //
 // Inside the tile, block s (4 positions at tile bits t_s0 < .. < t_s3) is a
 // complex GEMM Y = U_s X with X viewed as 16 rows (the block's tile bits) x
-// 512 columns (the other nine tile bits): one v_mfma_f32_32x32x2f32 chain per
+// 2^(TB-4) columns (the other tile bits): one v_mfma_f32_32x32x2f32 chain per
 // 32-column block, the real form A' = [[Ur,-Ui],[Ui,Ur]] interleaved by
 // (re, im) held in VGPRs (16 per lane per block) for the whole persistent
 // kernel, B operands and results addressed in LDS as row_offset(j) +
@@ -29,17 +30,22 @@ namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kTileBits = 13;
-constexpr int kTileN = 1 << kTileBits;
+constexpr int kMaxTileBits = 14;
 constexpr int kTileThreads = 512;
 constexpr int kTileWaves = kTileThreads / 64;
-constexpr int kCols = kTileN / 16;           // 512 columns per 4-qubit block
-constexpr int kNBPerWave = kCols / 32 / kTileWaves;  // 2
-constexpr int kChunks = kTileN / 2 / kTileThreads;   // 16-byte copies per thread: 8
+
+// Tile of 2^TB amplitudes: 2^TB / 16 columns per 4-qubit block, split over 8 waves.
+template <int TB>
+struct TileCfg {
+    static constexpr int N = 1 << TB;
+    static constexpr int COLS = N / 16;
+    static constexpr int NB_PER_WAVE = COLS / 32 / kTileWaves;
+    static constexpr int CHUNKS = N / 2 / kTileThreads;  // 16-byte copies per thread
+};
 
 struct TileArgs {
     uint64_t n_tiles;
-    int ubit[kTileBits];               // tile bit -> global position
+    int ubit[kMaxTileBits];            // tile bit -> global position
     int ext_pos[SV_MAX_QUBITS_C64];    // positions outside the tile, ascending
     int n_ext;
     int tbit[kMaxTileSubBlocks][4];    // per block: its tile bits, ascending
@@ -65,19 +71,24 @@ __device__ __forceinline__ uint64_t tile_base(uint64_t T, const TileArgs &a)
     return x;
 }
 
+template <int TB>
 __device__ __forceinline__ uint64_t global_off(uint32_t t, const TileArgs &a)
 {
     uint64_t g = 0;
 #pragma unroll
-    for (int b = 0; b < kTileBits; ++b)
+    for (int b = 0; b < TB; ++b)
         if ((t >> b) & 1) g += uint64_t(1) << a.ubit[b];
     return g;
 }
 
-template <int NSUB>
+template <int TB, int NSUB>
 __global__ void __launch_bounds__(kTileThreads) k_tile_pass(float *__restrict__ psi, const float *__restrict__ A,
                                                             const TileArgs args)
 {
+    using C = TileCfg<TB>;
+    constexpr int kTileN = C::N;
+    constexpr int kNBPerWave = C::NB_PER_WAVE;
+    constexpr int kChunks = C::CHUNKS;
     __shared__ float2 X[kTileN];
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
@@ -105,10 +116,10 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_pass(float *__restrict__ 
     }
 
     // copy offsets: chunk i of this thread covers tile index t = 2*(tid + i*kTileThreads)
-    uint64_t g_lo = global_off(uint32_t(2 * tid), args);
+    uint64_t g_lo = global_off<TB>(uint32_t(2 * tid), args);
     uint64_t g_hi[kChunks];
 #pragma unroll
-    for (int i = 0; i < kChunks; ++i) g_hi[i] = global_off(uint32_t(2 * i * kTileThreads), args);
+    for (int i = 0; i < kChunks; ++i) g_hi[i] = global_off<TB>(uint32_t(2 * i * kTileThreads), args);
 
     uint64_t T = blockIdx.x;
     float4 buf[kChunks];
@@ -135,21 +146,27 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_pass(float *__restrict__ 
             uint32_t row_off[16];
 #pragma unroll
             for (int j = 0; j < 16; ++j) row_off[j] = deposit(uint32_t(j), row_mask[s]);
+            // the wave's column blocks run as independent MFMA chains (ILP)
+            f32x16 acc[kNBPerWave];
+#pragma unroll
+            for (int q = 0; q < kNBPerWave; ++q)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[q][v] = 0.f;
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+#pragma unroll
+                for (int q = 0; q < kNBPerWave; ++q)
+                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s][j], Xf[2 * (row_off[j] + col_off[s][q]) + half],
+                                                                  acc[q], 0, 0, 0);
+            // D real row = 8*(v/4) + 4*half + v%4; complex row = real row / 2
 #pragma unroll
             for (int q = 0; q < kNBPerWave; ++q) {
                 const uint32_t co = col_off[s][q];
-                f32x16 acc;
-#pragma unroll
-                for (int v = 0; v < 16; ++v) acc[v] = 0.f;
-#pragma unroll
-                for (int j = 0; j < 16; ++j)
-                    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s][j], Xf[2 * (row_off[j] + co) + half], acc, 0, 0, 0);
-                // D real row = 8*(v/4) + 4*half + v%4; complex row = real row / 2
 #pragma unroll
                 for (int g = 0; g < 4; ++g) {
                     const int r0 = 4 * g + 2 * half;
-                    X[row_off[r0] + co] = make_float2(acc[4 * g + 0], acc[4 * g + 1]);
-                    X[row_off[r0 + 1] + co] = make_float2(acc[4 * g + 2], acc[4 * g + 3]);
+                    X[row_off[r0] + co] = make_float2(acc[q][4 * g + 0], acc[q][4 * g + 1]);
+                    X[row_off[r0 + 1] + co] = make_float2(acc[q][4 * g + 2], acc[q][4 * g + 3]);
                 }
             }
             __syncthreads();
@@ -161,22 +178,36 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_pass(float *__restrict__ 
     }
 }
 
-template <int NSUB>
+template <int TB, int NSUB>
 hipError_t tile_launch(const TileArgs &a, const float *d_a, float *psi, hipStream_t st, int cap)
 {
     uint64_t g = a.n_tiles;
     if (cap > 0 && g > uint64_t(cap)) g = cap;
-    hipLaunchKernelGGL((k_tile_pass<NSUB>), dim3(unsigned(g)), dim3(kTileThreads), 0, st, psi, d_a, a);
+    hipLaunchKernelGGL((k_tile_pass<TB, NSUB>), dim3(unsigned(g)), dim3(kTileThreads), 0, st, psi, d_a, a);
     return hipGetLastError();
+}
+
+template <int TB>
+hipError_t tile_dispatch(int n_sub, const TileArgs &a, const float *d_a, float *psi, hipStream_t st, int cap)
+{
+    switch (n_sub) {
+    case 1: return tile_launch<TB, 1>(a, d_a, psi, st, cap);
+    case 2: return tile_launch<TB, 2>(a, d_a, psi, st, cap);
+    case 3: return tile_launch<TB, 3>(a, d_a, psi, st, cap);
+    case 4: return tile_launch<TB, 4>(a, d_a, psi, st, cap);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace
 
-bool tile_supported(int n, int union_bits) { return n >= kTileBits && union_bits <= kMaxTileUnion; }
+bool tile_supported(int n, int union_bits) { return n >= kMinTileQubits && union_bits <= kMaxTileUnion; }
 
 hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const float *d_a, void *psi, int n, hipStream_t st,
-                            int grid_cap)
+                            int grid_cap, int tile_bits)
 {
+    const int kTileBits = tile_bits;
+    if (tile_bits != 13 && tile_bits != 14) return hipErrorInvalidValue;
     if (n_sub < 1 || n_sub > kMaxTileSubBlocks || n < kTileBits) return hipErrorInvalidValue;
     TileArgs a;
     std::memset(&a, 0, sizeof a);
@@ -201,13 +232,8 @@ hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const float *d_a
         }
     a.n_tiles = uint64_t(1) << (n - kTileBits);
     float *p = static_cast<float *>(psi);
-    switch (n_sub) {
-    case 1: return tile_launch<1>(a, d_a, p, st, grid_cap);
-    case 2: return tile_launch<2>(a, d_a, p, st, grid_cap);
-    case 3: return tile_launch<3>(a, d_a, p, st, grid_cap);
-    case 4: return tile_launch<4>(a, d_a, p, st, grid_cap);
-    default: return hipErrorInvalidValue;
-    }
+    return tile_bits == 13 ? tile_dispatch<13>(n_sub, a, d_a, p, st, grid_cap)
+                           : tile_dispatch<14>(n_sub, a, d_a, p, st, grid_cap);
 }
 
 }  // namespace dev

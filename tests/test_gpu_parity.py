@@ -286,7 +286,7 @@ def test_energy_autograd():
 
 
 # ----------------------------------------------------------------- tile passes
-@pytest.mark.parametrize("n", [13, 14, 16, 19])
+@pytest.mark.parametrize("n", [14, 15, 16, 19])
 @pytest.mark.parametrize("max_k", [2, 3, 4])
 def test_tiled_passes_vs_oracle(n, max_k):
     """Consecutive fused blocks applied together in LDS tile passes."""
@@ -311,3 +311,43 @@ def test_c0_tiled():
     want, got, _ = run_both(n, gates, "0", "c64", max_k=4, rule=sv.RULE_TILED)
     fe, ma = _report("c0 tiled k<=4", want, got)
     assert fe <= FID_C64 and ma <= 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_adjoint_mixed_circuit(dtype):
+    """Rotations in runs (distinct qubits), isolated, repeated on one qubit,
+    mixed with 2- and 3-qubit gates; one parameter shared by two gates."""
+    n = 7
+    rng = np.random.default_rng(44)
+    gates, p = [], 0
+    for layer in range(4):
+        for q in rng.permutation(n)[:5]:
+            gates.append(Gate(("RX", "RY", "RZ")[int(rng.integers(3))], (int(q),), (0.0,), p))
+            p += 1
+        gates.append(Gate("RY", (0,), (0.0,), p)); p += 1
+        gates.append(Gate("RZ", (0,), (0.0,), p)); p += 1
+        gates += wc.random_gate_list(n, 6, rng, max_k=3, names=("CZ", "FSIM", "MATRIX", "SQRT_X"))
+    gates.append(Gate("RX", (3,), (0.0,), 0))  # shares parameter 0
+    thetas = rng.uniform(0, 2 * math.pi, size=p)
+    from workloads.circuits import with_thetas
+    bound = with_thetas(gates, thetas)
+    H = [(0.7, ((0, "Z"), (1, "Z"))), (0.3, ((2, "X"),)), (-0.5, ((4, "Y"), (5, "X")))]
+    psi = sv.State(n, dtype).run(to_binding(bound))
+    scratch = sv.State(n, dtype)
+    g = sv.backward(psi, scratch, to_binding(bound), H, p)
+    # oracle: parameter shift on every gate, then summed per parameter
+    ps = np.zeros(p)
+    for gi, gate in enumerate(gates):
+        if gate.param_index < 0:
+            continue
+        e = []
+        for sgn in (+1, -1):
+            shifted = [(Gate(x.name, x.qubits, (x.params[0] + sgn * math.pi / 2,), x.param_index) if k == gi else x)
+                       for k, x in enumerate(bound)]
+            e.append(ref.expectation(ref.simulate(n, shifted, "0"), H))
+        ps[gate.param_index] += 0.5 * (e[0] - e[1])
+    rel = np.linalg.norm(g - ps) / np.linalg.norm(ps)
+    print("[parity] adjoint mixed n=%d %s rel=%.3e" % (n, dtype, rel), flush=True)
+    assert rel <= (1e-10 if dtype == "c128" else 1e-4)
+    back = psi.read()
+    assert abs(abs(back[0]) - 1) <= (1e-12 if dtype == "c128" else 1e-5)
