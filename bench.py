@@ -29,8 +29,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 MFMA_FP32_PEAK_TFLOPS = 157.3
-FAMILY_NAMES = {1: "reg", 2: "generic", 3: "mfma_f32", 4: "split_bf16", 5: "split_fp16", 9: "tile"}
-KERNEL_SOURCES = {1: "apply.hip", 2: "apply.hip", 3: "mfma.hip", 4: "mfma.hip", 5: "mfma.hip", 9: "tile.hip"}
+FAMILY_NAMES = {1: "reg", 2: "generic", 3: "mfma_f32", 4: "split_bf16", 5: "split_fp16", 9: "tile",
+                10: "tile_bf16"}
+KERNEL_SOURCES = {1: "apply.hip", 2: "apply.hip", 3: "mfma.hip", 4: "mfma.hip", 5: "mfma.hip", 9: "tile.hip",
+                  10: "tile.hip"}
 
 
 def log(*a):
@@ -183,6 +185,9 @@ def main():
                 "kernel": "%s k=%d" % (FAMILY_NAMES[dfam], dk), "avg_launch_ms": round(avg_ms, 4),
                 "launches_per_step": dcnt // args.steps,
                 "algorithmic_bytes_per_launch": pass_bytes}
+    if dfam == 10:
+        flops = 3 * 8.0 * 16 * (1 << n) * dk  # three BF16 products per 4-qubit block
+        roofline["mfma_tflops"] = round(flops / (avg_ms * 1e-3) / 1e12, 2)
     if dfam == 9:
         flops = 8.0 * 16 * (1 << n) * dk  # dk blocks of 4 qubits per tile pass
         roofline["mfma_tflops"] = round(flops / (avg_ms * 1e-3) / 1e12, 2)

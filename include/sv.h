@@ -226,9 +226,10 @@ int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int use_graph);
  * 'evolution')).  Nothing is applied if any gate is invalid.  Asynchronous
  * (synchronises when o->use_graph = 1).  o == NULL means plain per-gate
  * application: {SV_MAX_K, FP32 or FP64 by amplitude type, SV_RULE_NONE, 0}.
- * With SV_RULE_TILED on a complex64 state of >= 13 qubits (FP32 or split
- * precision), up to 4 consecutive blocks whose positions span at most 9
- * qubits are applied together: each 2^13-amplitude tile is staged in LDS
+ * With SV_RULE_TILED on a complex64 state of >= 14 qubits (FP32 or split
+ * precision), up to 4 blocks whose positions span at most 8 qubits are
+ * applied together (a later block joins a group only if it commutes past
+ * every block it jumps over): each tile of 2^14 amplitudes is staged in LDS
  * once, every block of the group is applied to it with FP32 MFMA, and the
  * tile is written back, so the group costs one state pass. */
 int sv_run_circuit(sv_state *s, const sv_gate *g, int G, const sv_run_opts *o);

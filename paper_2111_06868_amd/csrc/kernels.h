@@ -36,14 +36,15 @@ hipError_t launch_mfma_split(int k, bool fp16, const int *sorted_q, const uint16
 // Multi-block tile passes (complex64, FP32 MFMA): up to kMaxTileSubBlocks
 // 4-qubit blocks whose positions have a union of at most kMaxTileUnion
 // positions, applied in one HBM pass over tiles of 2^tile_bits amplitudes
-// (13 or 14).  d_a = the blocks' real-form matrices (32 x 32 floats each,
-// back to back).  Needs n >= tile_bits.
+// (13 or 14).  d_a = the blocks' real-form matrices, back to back: 32 x 32
+// floats each (FP32), or for split_bf16 the hi then the lo part, 32 x 32
+// bf16 each.  Needs n >= tile_bits.
 constexpr int kMaxTileSubBlocks = 4;
 constexpr int kMaxTileUnion = 8;
 constexpr int kMinTileQubits = 14;
 bool tile_supported(int n, int union_bits);
-hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const float *d_a, void *psi, int n, hipStream_t st,
-                            int grid_cap, int tile_bits);
+hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a, bool split_bf16, void *psi, int n,
+                            hipStream_t st, int grid_cap, int tile_bits);
 // Host-side packing of the MFMA operands of a canonical k-qubit matrix.
 void pack_real_form_f32(const cd *m, int k, float *out);
 void pack_real_form_split(const cd *m, int k, bool fp16, uint16_t *hi, uint16_t *lo);

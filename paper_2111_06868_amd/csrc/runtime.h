@@ -47,6 +47,7 @@ enum Family {
     FAM_ADJOINT = 7,
     FAM_BATCH = 8,
     FAM_TILE = 9,
+    FAM_TILE_BF16 = 10,
 };
 
 // RAII: brackets one launch with HIP events on `st` when timing is enabled.
@@ -66,7 +67,7 @@ class LaunchTimer {
 void timing_suspend(bool on);
 
 // Kernel paths for a block.
-enum Path { PATH_REG, PATH_GENERIC, PATH_MFMA32, PATH_SPLIT_BF16, PATH_SPLIT_FP16, PATH_TILE };
+enum Path { PATH_REG, PATH_GENERIC, PATH_MFMA32, PATH_SPLIT_BF16, PATH_SPLIT_FP16, PATH_TILE, PATH_TILE_BF16 };
 
 struct Tuning {
     int reg_grid_cap[SV_MAX_K + 1];   // 0 = one thread per group

@@ -207,6 +207,7 @@ int path_family(Path p)
     case PATH_MFMA32: return FAM_MFMA32;
     case PATH_SPLIT_BF16: return FAM_SPLIT_BF16;
     case PATH_TILE: return FAM_TILE;
+    case PATH_TILE_BF16: return FAM_TILE_BF16;
     default: return FAM_SPLIT_FP16;
     }
 }
@@ -232,6 +233,10 @@ size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage)
         case PATH_TILE:
             L.arena_off = total;
             total = align256(total + size_t(L.k) * dev::real_form_elems(4) * 4);
+            break;
+        case PATH_TILE_BF16:
+            L.arena_off = total;
+            total = align256(total + size_t(L.k) * dev::real_form_elems(4) * 2 * 2);
             break;
         default:
             L.arena_off = total;
@@ -270,6 +275,12 @@ size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage)
             for (int sb = 0; sb < L.k; ++sb)
                 dev::pack_real_form_f32(L.m.data() + 256 * sb, 4,
                                         reinterpret_cast<float *>(h + L.arena_off) + dev::real_form_elems(4) * sb);
+            break;
+        case PATH_TILE_BF16:
+            for (int sb = 0; sb < L.k; ++sb) {
+                uint16_t *hi = reinterpret_cast<uint16_t *>(h + L.arena_off) + 2 * dev::real_form_elems(4) * sb;
+                dev::pack_real_form_split(L.m.data() + 256 * sb, 4, false, hi, hi + dev::real_form_elems(4));
+            }
             break;
         default:
             dev::pack_real_form_split(L.m.data(), L.k, L.path == PATH_SPLIT_FP16,
@@ -312,22 +323,32 @@ static void pad_to_four(const Block &b, const int *p4, std::vector<cd> &out)
 
 void group_tile_passes(const std::vector<Block> &blocks, int n, int precision, std::vector<Launch> &out)
 {
+    // Greedy, commutation-aware: a pass starts at the first block not yet
+    // applied and takes later blocks of <= 4 qubits while the union stays
+    // within kMaxTileUnion positions; a later block may join only if it is
+    // disjoint from every block it jumps over (so it commutes past them).
     auto mask_of = [](const Block &b) {
         uint64_t m = 0;
         for (int j = 0; j < b.k; ++j) m |= uint64_t(1) << b.q[j];
         return m;
     };
     out.clear();
-    size_t i = 0;
-    while (i < blocks.size()) {
+    std::vector<char> done(blocks.size(), 0);
+    for (size_t i = 0; i < blocks.size(); ++i) {
+        if (done[i]) continue;
         std::vector<size_t> grp = {i};
         uint64_t um = mask_of(blocks[i]);
-        size_t j = i + 1;
         if (blocks[i].k <= 4) {
-            while (j < blocks.size() && int(grp.size()) < dev::kMaxTileSubBlocks && blocks[j].k <= 4 &&
-                   __builtin_popcountll(um | mask_of(blocks[j])) <= dev::kMaxTileUnion) {
-                um |= mask_of(blocks[j]);
-                grp.push_back(j++);
+            uint64_t skipped = 0;
+            for (size_t j = i + 1; j < blocks.size() && int(grp.size()) < dev::kMaxTileSubBlocks; ++j) {
+                if (done[j]) continue;
+                const uint64_t m = mask_of(blocks[j]);
+                if (!(m & skipped) && blocks[j].k <= 4 && __builtin_popcountll(um | m) <= dev::kMaxTileUnion) {
+                    um |= m;
+                    grp.push_back(j);
+                } else {
+                    skipped |= m;
+                }
             }
         }
         if (grp.size() < 2 || !dev::tile_supported(n, __builtin_popcountll(um))) {
@@ -338,18 +359,19 @@ void group_tile_passes(const std::vector<Block> &blocks, int n, int precision, s
             L.path = choose_path(SV_C64, precision, b.k, b.q, n);
             L.m = b.m;
             out.push_back(std::move(L));
-            ++i;
+            done[i] = 1;
             continue;
         }
         // the union gets at least 4 positions (lowest free ones)
         for (int p = 0; p < n && __builtin_popcountll(um) < 4; ++p) um |= uint64_t(1) << p;
         Launch L;
-        L.path = PATH_TILE;
+        L.path = precision == SV_PREC_SPLIT_BF16 || precision == SV_PREC_SPLIT_FP16 ? PATH_TILE_BF16 : PATH_TILE;
         L.k = int(grp.size());
         std::fill(L.q, L.q + SV_MAX_K, 0);
         L.m.clear();
         for (int sb = 0; sb < L.k; ++sb) {
             const Block &b = blocks[grp[sb]];
+            done[grp[sb]] = 1;
             uint64_t pm = mask_of(b);
             for (int p = 0; p < 64 && __builtin_popcountll(pm) < 4; ++p)
                 if (((um >> p) & 1) && !((pm >> p) & 1)) pm |= uint64_t(1) << p;
@@ -361,7 +383,6 @@ void group_tile_passes(const std::vector<Block> &blocks, int n, int precision, s
             L.m.insert(L.m.end(), m4.begin(), m4.end());
         }
         out.push_back(std::move(L));
-        i = j;
     }
 }
 
@@ -380,7 +401,8 @@ int enqueue(const std::vector<Launch> &launches, int dtype, void *psi, int n, co
                                      T.mfma_tc_log[L.k], T.mfma_grid_cap[L.k]);
             break;
         case PATH_TILE:
-            e = dev::launch_tile_pass(L.k, L.sub_pos, reinterpret_cast<const float *>(A + L.arena_off), psi, n, st,
+        case PATH_TILE_BF16:
+            e = dev::launch_tile_pass(L.k, L.sub_pos, A + L.arena_off, L.path == PATH_TILE_BF16, psi, n, st,
                                       T.tile_bits == 13 ? T.tile_grid_cap : std::max(1, T.tile_grid_cap / 2),
                                       T.tile_bits);
             break;

@@ -29,6 +29,7 @@ namespace dev {
 namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kMaxTileBits = 14;
 constexpr int kTileThreads = 512;
@@ -178,23 +179,149 @@ __global__ void __launch_bounds__(kTileThreads) k_tile_pass(float *__restrict__ 
     }
 }
 
+
+// Split-BF16 variant: A' = Ah + Al (bf16, from the host), each B operand
+// (8 consecutive K values = 4 complex rows of one column) is split while it
+// is read from LDS (v_cvt_pk_bf16_f32), and Ah Xh + Ah Xl + Al Xh run on
+// v_mfma_f32_32x32x16_bf16 with FP32 accumulation (the Al Xl term, ~2^-16
+// relative, is dropped).  Everything else is as in k_tile_pass.
 template <int TB, int NSUB>
-hipError_t tile_launch(const TileArgs &a, const float *d_a, float *psi, hipStream_t st, int cap)
+__global__ void __launch_bounds__(kTileThreads) k_tile_pass_bf16(float *__restrict__ psi,
+                                                                 const uint16_t *__restrict__ A,
+                                                                 const TileArgs args)
+{
+    using C = TileCfg<TB>;
+    constexpr int kTileN = C::N;
+    constexpr int kNBPerWave = C::NB_PER_WAVE;
+    constexpr int kChunks = C::CHUNKS;
+    __shared__ float2 X[kTileN];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    const int half = lane >> 5, l32 = lane & 31;
+
+    // A' hi / lo: step i (K = 16 i .. 16 i + 15), lane holds A'[l32][16 i + 8 half + e]
+    uint4 ah[NSUB][2], al[NSUB][2];
+#pragma unroll
+    for (int s = 0; s < NSUB; ++s)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int off = s * 2048 + l32 * 32 + 16 * i + 8 * half;
+            ah[s][i] = *reinterpret_cast<const uint4 *>(A + off);
+            al[s][i] = *reinterpret_cast<const uint4 *>(A + off + 1024);
+        }
+
+    uint32_t col_off[NSUB][kNBPerWave];
+    uint32_t row_mask[NSUB];
+#pragma unroll
+    for (int s = 0; s < NSUB; ++s) {
+        uint32_t m = 0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) m |= 1u << args.tbit[s][i];
+        row_mask[s] = m;
+#pragma unroll
+        for (int q = 0; q < kNBPerWave; ++q)
+            col_off[s][q] = deposit(uint32_t((w * kNBPerWave + q) * 32 + l32), (kTileN - 1) & ~m);
+    }
+    uint64_t g_lo = global_off<TB>(uint32_t(2 * tid), args);
+    uint64_t g_hi[kChunks];
+#pragma unroll
+    for (int i = 0; i < kChunks; ++i) g_hi[i] = global_off<TB>(uint32_t(2 * i * kTileThreads), args);
+
+    uint64_t T = blockIdx.x;
+    float4 buf[kChunks];
+    if (T < args.n_tiles) {
+        const uint64_t base = tile_base(T, args) + g_lo;
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) buf[i] = *reinterpret_cast<const float4 *>(psi + 2 * (base + g_hi[i]));
+    }
+    for (; T < args.n_tiles; T += gridDim.x) {
+        const uint64_t base = tile_base(T, args) + g_lo;
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i)
+            reinterpret_cast<float4 *>(X)[tid + i * kTileThreads] = buf[i];
+        __syncthreads();
+        const uint64_t Tn = T + gridDim.x;
+        if (Tn < args.n_tiles) {
+            const uint64_t nbase = tile_base(Tn, args) + g_lo;
+#pragma unroll
+            for (int i = 0; i < kChunks; ++i) buf[i] = *reinterpret_cast<const float4 *>(psi + 2 * (nbase + g_hi[i]));
+        }
+#pragma unroll
+        for (int s = 0; s < NSUB; ++s) {
+            uint32_t row_off[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) row_off[j] = deposit(uint32_t(j), row_mask[s]);
+            f32x16 acc[kNBPerWave];
+#pragma unroll
+            for (int q = 0; q < kNBPerWave; ++q)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[q][v] = 0.f;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                bf16x8 xah, xal;
+                __builtin_memcpy(&xah, &ah[s][i], 16);
+                __builtin_memcpy(&xal, &al[s][i], 16);
+#pragma unroll
+                for (int q = 0; q < kNBPerWave; ++q) {
+                    bf16x8 bh, bl;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        // complex row 8 i + 4 half + t of this lane's column
+                        const uint32_t r = half ? row_off[8 * i + 4 + t] : row_off[8 * i + t];
+                        const float2 v = X[r + col_off[s][q]];
+                        const __bf16 hr = (__bf16)v.x, hi = (__bf16)v.y;
+                        bh[2 * t] = hr;
+                        bh[2 * t + 1] = hi;
+                        bl[2 * t] = (__bf16)(v.x - (float)hr);
+                        bl[2 * t + 1] = (__bf16)(v.y - (float)hi);
+                    }
+                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah, bh, acc[q], 0, 0, 0);
+                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah, bl, acc[q], 0, 0, 0);
+                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xal, bh, acc[q], 0, 0, 0);
+                }
+            }
+            // each wave owns its columns: its reads precede its writes
+#pragma unroll
+            for (int q = 0; q < kNBPerWave; ++q) {
+                const uint32_t co = col_off[s][q];
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    const int r0 = 4 * g + 2 * half;
+                    X[row_off[r0] + co] = make_float2(acc[q][4 * g + 0], acc[q][4 * g + 1]);
+                    X[row_off[r0 + 1] + co] = make_float2(acc[q][4 * g + 2], acc[q][4 * g + 3]);
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i)
+            *reinterpret_cast<float4 *>(psi + 2 * (base + g_hi[i])) = reinterpret_cast<const float4 *>(X)[tid + i * kTileThreads];
+        __syncthreads();
+    }
+}
+
+template <int TB, int NSUB>
+hipError_t tile_launch(const TileArgs &a, const void *d_a, bool split, float *psi, hipStream_t st, int cap)
 {
     uint64_t g = a.n_tiles;
     if (cap > 0 && g > uint64_t(cap)) g = cap;
-    hipLaunchKernelGGL((k_tile_pass<TB, NSUB>), dim3(unsigned(g)), dim3(kTileThreads), 0, st, psi, d_a, a);
+    if (split)
+        hipLaunchKernelGGL((k_tile_pass_bf16<TB, NSUB>), dim3(unsigned(g)), dim3(kTileThreads), 0, st, psi,
+                           static_cast<const uint16_t *>(d_a), a);
+    else
+        hipLaunchKernelGGL((k_tile_pass<TB, NSUB>), dim3(unsigned(g)), dim3(kTileThreads), 0, st, psi,
+                           static_cast<const float *>(d_a), a);
     return hipGetLastError();
 }
 
 template <int TB>
-hipError_t tile_dispatch(int n_sub, const TileArgs &a, const float *d_a, float *psi, hipStream_t st, int cap)
+hipError_t tile_dispatch(int n_sub, const TileArgs &a, const void *d_a, bool split, float *psi, hipStream_t st, int cap)
 {
     switch (n_sub) {
-    case 1: return tile_launch<TB, 1>(a, d_a, psi, st, cap);
-    case 2: return tile_launch<TB, 2>(a, d_a, psi, st, cap);
-    case 3: return tile_launch<TB, 3>(a, d_a, psi, st, cap);
-    case 4: return tile_launch<TB, 4>(a, d_a, psi, st, cap);
+    case 1: return tile_launch<TB, 1>(a, d_a, split, psi, st, cap);
+    case 2: return tile_launch<TB, 2>(a, d_a, split, psi, st, cap);
+    case 3: return tile_launch<TB, 3>(a, d_a, split, psi, st, cap);
+    case 4: return tile_launch<TB, 4>(a, d_a, split, psi, st, cap);
     default: return hipErrorInvalidValue;
     }
 }
@@ -203,8 +330,8 @@ hipError_t tile_dispatch(int n_sub, const TileArgs &a, const float *d_a, float *
 
 bool tile_supported(int n, int union_bits) { return n >= kMinTileQubits && union_bits <= kMaxTileUnion; }
 
-hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const float *d_a, void *psi, int n, hipStream_t st,
-                            int grid_cap, int tile_bits)
+hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a, bool split_bf16, void *psi, int n,
+                            hipStream_t st, int grid_cap, int tile_bits)
 {
     const int kTileBits = tile_bits;
     if (tile_bits != 13 && tile_bits != 14) return hipErrorInvalidValue;
@@ -232,8 +359,8 @@ hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const float *d_a
         }
     a.n_tiles = uint64_t(1) << (n - kTileBits);
     float *p = static_cast<float *>(psi);
-    return tile_bits == 13 ? tile_dispatch<13>(n_sub, a, d_a, p, st, grid_cap)
-                           : tile_dispatch<14>(n_sub, a, d_a, p, st, grid_cap);
+    return tile_bits == 13 ? tile_dispatch<13>(n_sub, a, d_a, split_bf16, p, st, grid_cap)
+                           : tile_dispatch<14>(n_sub, a, d_a, split_bf16, p, st, grid_cap);
 }
 
 }  // namespace dev

@@ -1,0 +1,32 @@
+"""bench.py host-side behaviour (no GPU): the one-GPU guard and the counter
+summary reader."""
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "4"],
+                       stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+
+
+def test_traffic_summary_is_tied_to_the_kernel_source(tmp_path, monkeypatch):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    src = tmp_path / "paper_2111_06868_amd" / "csrc"
+    src.mkdir(parents=True)
+    (src / "mfma.hip").write_text("// kernel v1\n")
+    sha = bench.source_hash(3)
+    (prof / "traffic_mfma_f32_k5_30q.md").write_text(
+        "- kernel_source_sha256_16: `%s`\n- hbm_bytes_per_launch: 17180946890\n" % sha)
+    assert bench.read_traffic(3, 5, 30) == 17180946890.0
+    (src / "mfma.hip").write_text("// kernel v2\n")
+    assert bench.read_traffic(3, 5, 30) is None
+    assert bench.read_traffic(3, 4, 30) is None

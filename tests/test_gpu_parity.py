@@ -306,6 +306,24 @@ def test_tiled_passes_vs_oracle(n, max_k):
     assert fe <= FID_C64 and ma <= 1e-5
 
 
+@pytest.mark.parametrize("n", [14, 17])
+def test_tiled_passes_split_bf16(n):
+    rng = np.random.default_rng(700 + n)
+    gates = wc.random_gate_list(n, 8 * n, rng, max_k=2)
+    sv.stats_reset()
+    sv.stats_enable(True)
+    try:
+        want, got, st = run_both(n, gates, "+", "c64", max_k=4, rule=sv.RULE_TILED, precision=sv.PREC_SPLIT_BF16)
+        st.synchronize()
+        tiles = sum(sv.stats_query("tile_bf16", s)[0] for s in range(1, 5))
+    finally:
+        sv.stats_enable(False)
+        sv.stats_reset()
+    fe, ma = _report("tiled split-bf16 n=%d (%d tile passes)" % (n, tiles), want, got)
+    assert tiles > 0
+    assert fe <= FID_C64
+
+
 def test_c0_tiled():
     n, gates = wc.config_circuit(0)
     want, got, _ = run_both(n, gates, "0", "c64", max_k=4, rule=sv.RULE_TILED)
