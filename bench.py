@@ -91,7 +91,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--max-k", type=int, default=5)
-    ap.add_argument("--rule", default="enhanced", choices=["paper", "enhanced", "tiled"])
+    ap.add_argument("--rule", default="enhanced", choices=["paper", "enhanced", "tiled", "auto"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--config", type=int, default=1, choices=[1, 2])
     ap.add_argument("--workload", default="circuit", choices=["circuit", "gradient", "trajectories"],
@@ -121,7 +121,8 @@ def main():
     n, gates = wc.config_circuit(args.config)
     bound = [(g.name, g.qubits, g.params) for g in gates]
     ga = sv.GateArray(bound)
-    rule = {"enhanced": sv.RULE_ENHANCED, "paper": sv.RULE_PAPER, "tiled": sv.RULE_TILED}[args.rule]
+    rule = {"enhanced": sv.RULE_ENHANCED, "paper": sv.RULE_PAPER, "tiled": sv.RULE_TILED,
+            "auto": sv.RULE_AUTO}[args.rule]
     prec = {"fp32": sv.PREC_FP32, "bf16": sv.PREC_SPLIT_BF16, "fp16": sv.PREC_SPLIT_FP16}[args.precision]
     G = len(gates)
     pass_bytes = 16.0 * (1 << n)
@@ -134,9 +135,12 @@ def main():
         log("autotuned cost table (ms per block, k=1..6): %s" % ", ".join("%.3f" % c for c in cost[1:]))
         max_k = -1
     plan = sv.fuse(ga, n, max_k, rule)
-    if max_k == -1:
+    if max_k == -1 or rule == sv.RULE_AUTO:
+        # the plan records what was chosen; the timed steps fuse with that choice
         max_k = plan.max_k
         args.max_k = max_k
+        rule = plan.rule
+        args.rule = {sv.RULE_ENHANCED: "enhanced", sv.RULE_PAPER: "paper", sv.RULE_TILED: "tiled"}[rule]
     blocks = plan.blocks(False)
     n_passes = len(blocks)  # tiled: several blocks share one pass (counted from the launches below)
     kh = {}

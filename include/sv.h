@@ -68,6 +68,8 @@ extern "C" {
 #define SV_RULE_NONE 2     /* one block per gate (plain per-gate application)    */
 #define SV_RULE_TILED 3    /* enhanced blocks of <= 4 qubits, grouped into LDS   */
                            /* tile passes (see sv_run_circuit)                   */
+#define SV_RULE_AUTO 4     /* the cheaper of ENHANCED and TILED plans, and its k, */
+                           /* by the autotuned cost table (see sv_run_circuit)    */
 
 /* gate kinds.  Matrices (paper, Gates and Properties section, names only; the
  * matrices are the textbook ones):
@@ -197,7 +199,8 @@ int sv_apply_gate(sv_state *s, const sv_gate *g);
  * and adjacent-by-commutation blocks are merged whenever the autotuned cost
  * table (or, without one, the pass count) says the merged block is cheaper.
  * SV_RULE_NONE: one block per gate.  SV_RULE_TILED: the enhanced rule with
- * blocks of at most min(max_k, 4) qubits.  Each block's qubits are sorted
+ * blocks of at most min(max_k, 4) qubits.  SV_RULE_AUTO: see sv_run_circuit
+ * (the plan records the rule and k it chose).  Each block's qubits are sorted
  * ascending (q[0] = most significant local bit) and its matrix is the ordered
  * product of its members (FP64).  n bounds the positions.  max_k = -1 uses the
  * autotuned cost table for n (SV_ERR_ARG if there is none).
@@ -214,6 +217,8 @@ int sv_plan_block_members(const sv_plan *p, int b, int32_t *members);
 int sv_plan_block_matrix(const sv_plan *p, int b, double *m);
 /* The max_k the plan was built with (the chosen one when -1 was asked). */
 int sv_plan_max_k(const sv_plan *p, int *out);
+/* The rule the plan was built with (the chosen one for SV_RULE_AUTO). */
+int sv_plan_rule(const sv_plan *p, int *out);
 /* Apply a plan's blocks in order with the given SV_PREC_* arithmetic; with
  * use_graph = 1 the launches are captured into a hipGraph that is replayed
  * once (and the call synchronises).  SV_ERR_QUBIT if the plan's positions do
@@ -231,7 +236,11 @@ int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int use_graph);
  * applied together (a later block joins a group only if it commutes past
  * every block it jumps over): each tile of 2^14 amplitudes is staged in LDS
  * once, every block of the group is applied to it with FP32 MFMA, and the
- * tile is written back, so the group costs one state pass. */
+ * tile is written back, so the group costs one state pass.
+ * SV_RULE_AUTO (with max_k = -1, or max_k as an upper bound) evaluates the
+ * enhanced plans for every k and the tiled plans for k <= 4 on block
+ * positions only, prices each with the cost table of (n, precision) (from
+ * sv_autotune, or relative defaults), and fuses the cheapest. */
 int sv_run_circuit(sv_state *s, const sv_gate *g, int G, const sv_run_opts *o);
 
 /* ---------------------------------------------------------------- reductions */

@@ -21,13 +21,13 @@ import numpy as np
 
 from . import _native as N
 from ._native import (C64, C128, PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16, PREC_FP64,  # noqa: F401
-                      RULE_PAPER, RULE_ENHANCED, RULE_NONE, RULE_TILED, SV_MAX_K, GATE_KINDS, SvError,
+                      RULE_PAPER, RULE_ENHANCED, RULE_NONE, RULE_TILED, RULE_AUTO, SV_MAX_K, GATE_KINDS, SvError,
                       SvValueError)
 
 __all__ = ["State", "Plan", "fuse", "gate_matrix", "backward", "Energy", "Batch", "positions",
            "pauli_sum", "autotune", "set_cost_table", "stats_enable", "stats_reset", "stats_query",
            "C64", "C128", "PREC_FP32", "PREC_SPLIT_BF16", "PREC_SPLIT_FP16", "PREC_FP64",
-           "RULE_PAPER", "RULE_ENHANCED", "RULE_NONE", "RULE_TILED", "SvError", "SvValueError"]
+           "RULE_PAPER", "RULE_ENHANCED", "RULE_NONE", "RULE_TILED", "RULE_AUTO", "SvError", "SvValueError"]
 
 
 def positions(order: Sequence, qubits: Sequence) -> tuple:
@@ -287,6 +287,12 @@ class Plan:
                 self.h = ctypes.c_void_p()
         except Exception:
             pass
+
+    @property
+    def rule(self) -> int:
+        out = ctypes.c_int()
+        N.check(N.lib().sv_plan_rule(self.h, ctypes.byref(out)))
+        return out.value
 
     @property
     def max_k(self) -> int:

@@ -32,6 +32,7 @@ RULE_PAPER = 0
 RULE_ENHANCED = 1
 RULE_NONE = 2
 RULE_TILED = 3
+RULE_AUTO = 4
 
 GATE_KINDS = {
     "MATRIX": 0, "I": 1, "X": 2, "Y": 3, "Z": 4, "H": 5, "SQRT_X": 6, "SQRT_Y": 7,
@@ -98,6 +99,7 @@ SIGNATURES = {
     "sv_plan_block_members": (_I, [_P, _I, _I32P]),
     "sv_plan_block_matrix": (_I, [_P, _I, _D]),
     "sv_plan_max_k": (_I, [_P, ctypes.POINTER(_I)]),
+    "sv_plan_rule": (_I, [_P, ctypes.POINTER(_I)]),
     "sv_apply_plan": (_I, [_P, _P, _I, _I]),
     "sv_run_circuit": (_I, [_P, _GP, _I, ctypes.POINTER(sv_run_opts)]),
     "sv_norm": (_I, [_P, _D]),

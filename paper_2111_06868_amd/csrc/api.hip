@@ -129,25 +129,46 @@ void blocks_to_launches(const std::vector<Block> &blocks, const sv_state *s, int
     }
 }
 
-int choose_max_k(const sv_gate *g, int G, int n, int rule, int precision, int *out_k)
+// Resolve (rule, max_k) requests: max_k = -1 picks k by the cost table;
+// SV_RULE_AUTO also picks between the enhanced and the tiled plan.  Candidate
+// plans are priced on block positions only (no matrices are formed).
+int choose_plan(const sv_gate *g, int G, int n, int dtype, int precision, int rule, int max_k, int *out_rule,
+                int *out_k)
 {
     bool found = false;
-    CostTable cost = lookup_costs(n, precision, &found);
-    int best_k = 1;
-    double best = 1e300;
+    const CostTable cost = lookup_costs(n, precision, &found);
     int kmin = 1;
     for (int i = 0; i < G; ++i) kmin = std::max(kmin, g[i].k);
-    for (int k = kmin; k <= SV_MAX_K; ++k) {
-        if (!found && k == SV_MAX_K) break;  // untuned: stay below the MFMA-bound size
-        std::vector<Block> blocks;
-        int rc = fuse_gates(g, G, n, k, rule == SV_RULE_NONE ? SV_RULE_PAPER : rule, cost, blocks);
-        if (rc) return rc;
-        const double c = plan_cost(blocks, cost);
-        if (c < best - 1e-12) {
-            best = c;
-            best_k = k;
+    const int kcap = max_k > 0 ? max_k : SV_MAX_K;
+    if (max_k > 0 && rule != SV_RULE_AUTO) {
+        *out_rule = rule;
+        *out_k = max_k;
+        return SV_OK;
+    }
+    std::vector<int> rules;
+    if (rule == SV_RULE_AUTO) {
+        rules.push_back(SV_RULE_ENHANCED);
+        if (dtype == SV_C64 && precision != SV_PREC_FP64 && n >= dev::kMinTileQubits) rules.push_back(SV_RULE_TILED);
+    } else {
+        rules.push_back(rule == SV_RULE_NONE ? SV_RULE_PAPER : rule);
+    }
+    double best = 1e300;
+    int best_rule = rules[0], best_k = std::min(kmin, kcap);
+    for (int r : rules) {
+        const int khi = std::min(kcap, r == SV_RULE_TILED ? 4 : SV_MAX_K);
+        for (int k = kmin; k <= khi; ++k) {
+            if (!found && k == SV_MAX_K) break;  // untuned: stay below the MFMA-bound size
+            std::vector<Block> blocks;
+            if (int rc = fuse_gates(g, G, n, k, r, cost, blocks, false)) return rc;
+            const double c = r == SV_RULE_TILED ? tiled_plan_cost(blocks, n, cost) : plan_cost(blocks, cost);
+            if (c < best - 1e-12) {
+                best = c;
+                best_rule = r;
+                best_k = k;
+            }
         }
     }
+    *out_rule = rule == SV_RULE_NONE ? SV_RULE_NONE : best_rule;
     *out_k = best_k;
     return SV_OK;
 }
@@ -348,8 +369,10 @@ extern "C" int sv_fuse(const sv_gate *g, int G, int n, int max_k, int rule, sv_p
     *out = nullptr;
     if (n < 1 || n > SV_MAX_QUBITS_C64) return fail(SV_ERR_ARG, "n = %d outside 1..%d", n, SV_MAX_QUBITS_C64);
     if (int rc = validate_gates(g, G, n)) return rc;
-    if (max_k == -1) {
-        if (int rc = choose_max_k(g, G, n, rule, SV_PREC_FP32, &max_k)) return rc;
+    if (rule < SV_RULE_PAPER || rule > SV_RULE_AUTO) return fail(SV_ERR_ARG, "unknown fusion rule %d", rule);
+    if (max_k == -1 || rule == SV_RULE_AUTO) {
+        if (max_k != -1 && (max_k < 1 || max_k > SV_MAX_K)) return fail(SV_ERR_ARG, "max_k %d", max_k);
+        if (int rc = choose_plan(g, G, n, SV_C64, SV_PREC_FP32, rule, max_k, &rule, &max_k)) return rc;
     }
     auto *p = new sv_plan;
     p->n = n;
@@ -383,6 +406,14 @@ extern "C" int sv_plan_max_k(const sv_plan *p, int *out)
     clear_error();
     if (!p || !out) return fail(SV_ERR_ARG, "NULL argument");
     *out = p->max_k;
+    return SV_OK;
+}
+
+extern "C" int sv_plan_rule(const sv_plan *p, int *out)
+{
+    clear_error();
+    if (!p || !out) return fail(SV_ERR_ARG, "NULL argument");
+    *out = p->rule;
     return SV_OK;
 }
 
@@ -452,16 +483,17 @@ extern "C" int sv_run_circuit(sv_state *s, const sv_gate *g, int G, const sv_run
     if (!o) o = &d;
     if (int rc = check_precision(s, o->precision)) return rc;
     if (int rc = validate_gates(g, G, s->n)) return rc;
-    int max_k = o->max_k;
-    if (max_k == -1) {
-        if (int rc = choose_max_k(g, G, s->n, o->rule, o->precision, &max_k)) return rc;
-    } else if (max_k < 1 || max_k > SV_MAX_K) {
+    int max_k = o->max_k, rule = o->rule;
+    if (rule < SV_RULE_PAPER || rule > SV_RULE_AUTO) return fail(SV_ERR_ARG, "unknown fusion rule %d", rule);
+    if (max_k != -1 && (max_k < 1 || max_k > SV_MAX_K))
         return fail(SV_ERR_ARG, "max_k %d outside 1..%d (or -1)", max_k, SV_MAX_K);
+    if (max_k == -1 || rule == SV_RULE_AUTO) {
+        if (int rc = choose_plan(g, G, s->n, s->dtype, o->precision, rule, max_k, &rule, &max_k)) return rc;
     }
     std::vector<Block> blocks;
-    if (int rc = fuse_gates(g, G, s->n, max_k, o->rule, lookup_costs(s->n, o->precision, nullptr), blocks)) return rc;
+    if (int rc = fuse_gates(g, G, s->n, max_k, rule, lookup_costs(s->n, o->precision, nullptr), blocks)) return rc;
     std::vector<Launch> L;
-    blocks_to_launches(blocks, s, o->precision, o->rule, L);
+    blocks_to_launches(blocks, s, o->precision, rule, L);
     if (int rc = select_device(s)) return rc;
     return run_launches(s, L, o->use_graph != 0);
 }

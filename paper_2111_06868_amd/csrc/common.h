@@ -44,20 +44,26 @@ struct Block {
 
 struct CostTable {
     bool valid = false;
-    double ms[SV_MAX_K + 1] = {0};
+    double ms[SV_MAX_K + 1] = {0};  // one application of a k-qubit block
+    double tile[5] = {0};           // one tile pass holding s = 1..4 blocks of 4 qubits
 };
 
 // Cost table used when no autotuned table exists (relative units).
 CostTable default_costs();
 // Lookup of an autotuned table for (n, precision); falls back to defaults.
 CostTable lookup_costs(int n, int precision, bool *found);
-void store_costs(int n, int precision, const double *ms);
+void store_costs(int n, int precision, const double *ms, const double *tile = nullptr);
 
 // Greedy fusion.  Gates must be validated first.  `cost` steers the
 // enhanced rule.  Fills blocks (with canonical matrices).
 int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTable &cost,
-               std::vector<Block> &blocks);
+               std::vector<Block> &blocks, bool with_matrices = true);
 double plan_cost(const std::vector<Block> &blocks, const CostTable &cost);
+// Tile grouping (see group_tile_passes): groups of block indices, in
+// application order; a group of one is applied on its own.
+std::vector<std::vector<size_t>> tile_groups(const std::vector<Block> &blocks, int n);
+// Cost of the tiled plan of `blocks` with the table's tile and block costs.
+double tiled_plan_cost(const std::vector<Block> &blocks, int n, const CostTable &cost);
 
 // Canonical matrix of a block from its member gates.
 void block_matrix(const sv_gate *g, Block &b);

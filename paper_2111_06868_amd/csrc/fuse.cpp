@@ -34,6 +34,9 @@ CostTable default_costs()
     t.valid = true;
     const double c[SV_MAX_K + 1] = {0.0, 1.0, 1.0, 1.0, 1.02, 1.1, 1.6};
     std::memcpy(t.ms, c, sizeof c);
+    // a tile pass is one state pass plus in-LDS work per 4-qubit block
+    const double tl[5] = {0.0, 1.1, 1.15, 1.3, 1.5};
+    std::memcpy(t.tile, tl, sizeof tl);
     return t;
 }
 
@@ -52,11 +55,17 @@ CostTable lookup_costs(int n, int precision, bool *found)
     return default_costs();
 }
 
-void store_costs(int n, int precision, const double *ms)
+void store_costs(int n, int precision, const double *ms, const double *tile)
 {
-    CostTable t;
+    CostTable t = default_costs();
     t.valid = true;
     for (int k = 0; k <= SV_MAX_K; ++k) t.ms[k] = ms[k];
+    if (tile) {
+        for (int s = 0; s <= 4; ++s) t.tile[s] = tile[s];
+    } else {
+        // untimed tile passes: scale the defaults by the measured 4-qubit block cost
+        for (int s = 1; s <= 4; ++s) t.tile[s] *= ms[4] / default_costs().ms[4];
+    }
     std::lock_guard<std::mutex> lk(g_cost_mu);
     g_costs[{n, precision}] = t;
 }
@@ -147,7 +156,7 @@ void block_matrix(const sv_gate *g, Block &b)
 }
 
 int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTable &cost,
-               std::vector<Block> &blocks)
+               std::vector<Block> &blocks, bool with_matrices)
 {
     (void)n;
     if (max_k < 1 || max_k > SV_MAX_K) return fail(SV_ERR_ARG, "max_k %d outside 1..%d", max_k, SV_MAX_K);
@@ -225,6 +234,7 @@ int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTa
         B.members = wb[b].members;
         work += B.members.size() << (2 * B.k);
     }
+    if (!with_matrices) return SV_OK;
     // block matrices are independent: spread large jobs over host threads
     const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
     const unsigned nt = work > (size_t(1) << 18) ? std::min<unsigned>(hw, unsigned(blocks.size())) : 1u;
@@ -237,6 +247,52 @@ int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTa
     worker();
     for (auto &th : pool) th.join();
     return SV_OK;
+}
+
+std::vector<std::vector<size_t>> tile_groups(const std::vector<Block> &blocks, int n)
+{
+    // Greedy, commutation-aware: a group starts at the first block not yet
+    // applied and takes later blocks of <= 4 qubits while the union stays
+    // within 8 positions; a later block may join only if it is disjoint from
+    // every block it jumps over (so it commutes past them).
+    constexpr int kMaxUnion = 8, kMaxBlocks = 4, kMinQubits = 14;
+    auto mask_of = [](const Block &b) {
+        uint64_t m = 0;
+        for (int j = 0; j < b.k; ++j) m |= uint64_t(1) << b.q[j];
+        return m;
+    };
+    std::vector<std::vector<size_t>> out;
+    std::vector<char> done(blocks.size(), 0);
+    for (size_t i = 0; i < blocks.size(); ++i) {
+        if (done[i]) continue;
+        std::vector<size_t> grp = {i};
+        uint64_t um = mask_of(blocks[i]);
+        if (blocks[i].k <= 4 && n >= kMinQubits) {
+            uint64_t skipped = 0;
+            for (size_t j = i + 1; j < blocks.size() && int(grp.size()) < kMaxBlocks; ++j) {
+                if (done[j]) continue;
+                const uint64_t m = mask_of(blocks[j]);
+                if (!(m & skipped) && blocks[j].k <= 4 && popc(um | m) <= kMaxUnion) {
+                    um |= m;
+                    grp.push_back(j);
+                } else {
+                    skipped |= m;
+                }
+            }
+        }
+        if (grp.size() < 2) grp.resize(1);
+        for (size_t b : grp) done[b] = 1;
+        out.push_back(std::move(grp));
+    }
+    return out;
+}
+
+double tiled_plan_cost(const std::vector<Block> &blocks, int n, const CostTable &cost)
+{
+    double c = 0;
+    for (const auto &grp : tile_groups(blocks, n))
+        c += grp.size() == 1 ? cost.ms[blocks[grp[0]].k] : cost.tile[grp.size()];
+    return c;
 }
 
 }  // namespace sv

@@ -323,45 +323,25 @@ static void pad_to_four(const Block &b, const int *p4, std::vector<cd> &out)
 
 void group_tile_passes(const std::vector<Block> &blocks, int n, int precision, std::vector<Launch> &out)
 {
-    // Greedy, commutation-aware: a pass starts at the first block not yet
-    // applied and takes later blocks of <= 4 qubits while the union stays
-    // within kMaxTileUnion positions; a later block may join only if it is
-    // disjoint from every block it jumps over (so it commutes past them).
     auto mask_of = [](const Block &b) {
         uint64_t m = 0;
         for (int j = 0; j < b.k; ++j) m |= uint64_t(1) << b.q[j];
         return m;
     };
     out.clear();
-    std::vector<char> done(blocks.size(), 0);
-    for (size_t i = 0; i < blocks.size(); ++i) {
-        if (done[i]) continue;
-        std::vector<size_t> grp = {i};
-        uint64_t um = mask_of(blocks[i]);
-        if (blocks[i].k <= 4) {
-            uint64_t skipped = 0;
-            for (size_t j = i + 1; j < blocks.size() && int(grp.size()) < dev::kMaxTileSubBlocks; ++j) {
-                if (done[j]) continue;
-                const uint64_t m = mask_of(blocks[j]);
-                if (!(m & skipped) && blocks[j].k <= 4 && __builtin_popcountll(um | m) <= dev::kMaxTileUnion) {
-                    um |= m;
-                    grp.push_back(j);
-                } else {
-                    skipped |= m;
-                }
-            }
-        }
-        if (grp.size() < 2 || !dev::tile_supported(n, __builtin_popcountll(um))) {
-            const Block &b = blocks[i];
+    for (const auto &grp : tile_groups(blocks, n)) {
+        if (grp.size() == 1) {
+            const Block &b = blocks[grp[0]];
             Launch L;
             L.k = b.k;
             std::copy(b.q, b.q + SV_MAX_K, L.q);
             L.path = choose_path(SV_C64, precision, b.k, b.q, n);
             L.m = b.m;
             out.push_back(std::move(L));
-            done[i] = 1;
             continue;
         }
+        uint64_t um = 0;
+        for (size_t b : grp) um |= mask_of(blocks[b]);
         // the union gets at least 4 positions (lowest free ones)
         for (int p = 0; p < n && __builtin_popcountll(um) < 4; ++p) um |= uint64_t(1) << p;
         Launch L;
@@ -371,7 +351,6 @@ void group_tile_passes(const std::vector<Block> &blocks, int n, int precision, s
         L.m.clear();
         for (int sb = 0; sb < L.k; ++sb) {
             const Block &b = blocks[grp[sb]];
-            done[grp[sb]] = 1;
             uint64_t pm = mask_of(b);
             for (int p = 0; p < 64 && __builtin_popcountll(pm) < 4; ++p)
                 if (((um >> p) & 1) && !((pm >> p) & 1)) pm |= uint64_t(1) << p;

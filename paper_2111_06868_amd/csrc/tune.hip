@@ -9,7 +9,10 @@
 //            caps {1024, 2048, 4096} (split kernels for SPLIT_* precisions).
 // Complex128 (FP64) times the register kernel for k <= 3 and the generic
 // kernel above.  Each candidate is timed on three position sets (lowest k
-// positions, highest k, and a spread set) and the mean is kept.
+// positions, highest k, and a spread set) and the mean is kept.  For
+// complex64 states of >= 14 qubits the tile passes holding 1..4 blocks are
+// timed too (FP32, or split BF16 for the split precisions), so SV_RULE_AUTO
+// can price tiled plans against plain fused ones.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -106,6 +109,55 @@ int time_candidate(sv_state *s, int k, const Cand &c, int reps, double *ms_out)
     return SV_OK;
 }
 
+// Mean milliseconds of one tile pass holding nsub 4-qubit blocks, over two
+// union layouts (8 positions spread over the state, and the lowest 8).
+int time_tile(sv_state *s, Path path, int nsub, int reps, double *ms_out)
+{
+    hipEvent_t a, b;
+    SV_HIP(hipEventCreate(&a));
+    SV_HIP(hipEventCreate(&b));
+    const std::vector<cd> m4 = dft_matrix(4);
+    double total = 0;
+    int count = 0, rc = SV_OK;
+    for (int layout = 0; layout < 2 && !rc; ++layout) {
+        int u[8];
+        for (int i = 0; i < 8; ++i) u[i] = layout ? i : int(std::lround(double(i) * (s->n - 1) / 7));
+        std::vector<Launch> L(1);
+        L[0].path = path;
+        L[0].k = nsub;
+        std::fill(L[0].q, L[0].q + SV_MAX_K, 0);
+        for (int sb = 0; sb < nsub; ++sb) {
+            int pos[4];
+            for (int t = 0; t < 4; ++t) pos[t] = u[(2 * sb + t) % 8];
+            std::sort(pos, pos + 4);
+            std::copy(pos, pos + 4, L[0].sub_pos[sb]);
+            L[0].m.insert(L[0].m.end(), m4.begin(), m4.end());
+        }
+        SV_HIP(hipEventSynchronize(s->arena_free));
+        const size_t bytes = pack_operands(L, s->dtype, s->stage);
+        if (bytes) {
+            SV_HIP(s->arena.ensure(bytes));
+            SV_HIP(hipMemcpyAsync(s->arena.p, s->stage.p, bytes, hipMemcpyHostToDevice, s->stream));
+        }
+        rc = enqueue(L, s->dtype, s->buf, s->n, s->arena.p, s->stream);  // warm-up
+        if (rc) break;
+        SV_HIP(hipEventRecord(a, s->stream));
+        for (int r = 0; r < reps && !rc; ++r) rc = enqueue(L, s->dtype, s->buf, s->n, s->arena.p, s->stream);
+        SV_HIP(hipEventRecord(b, s->stream));
+        SV_HIP(hipEventRecord(s->arena_free, s->stream));
+        SV_HIP(hipEventSynchronize(b));
+        float ms = 0;
+        SV_HIP(hipEventElapsedTime(&ms, a, b));
+        total += ms / reps;
+        ++count;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (rc) return rc;
+    *ms_out = count ? total / count : 1e30;
+    return SV_OK;
+}
+
 }  // namespace
 
 extern "C" int sv_autotune(sv_state *s, int precision, double *cost_ms)
@@ -180,10 +232,17 @@ extern "C" int sv_autotune(sv_state *s, int precision, double *cost_ms)
         }
         if (k == 4 && s->dtype == SV_C64 && precision == SV_PREC_FP32) best_tuning.k4_reg = bc.path == PATH_REG;
     }
+    double tile_ms[5] = {0, 0, 0, 0, 0};
+    const bool tiles = !rc && s->dtype == SV_C64 && dev::tile_supported(s->n, 8);
+    if (tiles) {
+        tuning() = best_tuning;
+        const Path tp = precision == SV_PREC_FP32 ? PATH_TILE : PATH_TILE_BF16;
+        for (int nsub = 1; nsub <= dev::kMaxTileSubBlocks && !rc; ++nsub) rc = time_tile(s, tp, nsub, reps, &tile_ms[nsub]);
+    }
     timing_suspend(false);
     if (rc) return rc;
     tuning() = best_tuning;
-    store_costs(s->n, precision, cost_ms);
+    store_costs(s->n, precision, cost_ms, tiles ? tile_ms : nullptr);
     return SV_OK;
 }
 

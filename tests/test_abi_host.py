@@ -180,3 +180,21 @@ def test_positions_follow_paper_order():
     # Grover example: order [0, 1, 2] puts qubit 0 at the most significant bit
     assert sv.positions([0, 1, 2], [1, 2]) == (1, 0)
     assert sv.positions(["a", "b"], ["a"]) == (1,)
+
+
+def test_auto_rule_picks_a_valid_plan():
+    """SV_RULE_AUTO with max_k = -1 chooses a rule and k from the (default)
+    cost table; the plan it returns must still equal the circuit."""
+    rng = np.random.default_rng(21)
+    n = 6
+    gates = wc.random_gate_list(n, 40, rng, max_k=2)
+    plan = sv.fuse(to_binding(gates), n, -1, sv.RULE_AUTO)
+    assert plan.rule in (sv.RULE_ENHANCED, sv.RULE_TILED)
+    assert 2 <= plan.max_k <= 6
+    U = brute.circuit_unitary(n, [(ref.matrix_of(g), g.qubits) for g in gates])
+    V = brute.circuit_unitary(n, [(b.matrix, b.qubits) for b in plan.blocks()])
+    assert np.max(np.abs(V - U)) <= 1e-12
+    # on the 30-qubit workload the tiled plan is priced cheaper by default
+    n30, g30 = wc.config_circuit(1)
+    p30 = sv.fuse(to_binding(g30), n30, -1, sv.RULE_AUTO)
+    assert p30.rule == sv.RULE_TILED and p30.max_k <= 4

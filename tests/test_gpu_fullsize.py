@@ -57,6 +57,30 @@ def test_30q_full_circuit_vs_c128():
     assert 1.0 < (1 << 20) * np.sum(p ** 2) / np.sum(p) ** 2 < 3.0
 
 
+def test_34q_high_positions_64bit_indexing():
+    """A 34-qubit complex64 state (128 GiB): gates on the top positions,
+    checked on the amplitudes they must produce (64-bit index arithmetic)."""
+    import torch
+    torch.cuda.empty_cache()
+    n = 34
+    st = sv.State(n, "c64")
+    st.run([("H", (33,)), ("CX", (33, 0)), ("CX", (0, 32)), ("RZ", (32,), (0.8,))])
+    hi = (1 << 33) | (1 << 32) | 1
+    a0 = st.read(0, 1)[0]
+    a1 = st.read(hi, 1)[0]
+    r = 1 / math.sqrt(2)
+    assert abs(a0 - r * np.exp(-0.4j)) <= 1e-6
+    assert abs(a1 - r * np.exp(0.4j)) <= 1e-6
+    assert abs(st.norm2() - 1) <= 1e-6
+    # a dense block across the top of the state through the MFMA path
+    M = wc.haar_unitary_from_seed(9, 5)
+    st.run([("MATRIX", (33, 31, 29, 2, 0), (), -1, M)], max_k=5, rule=sv.RULE_ENHANCED)
+    assert abs(st.norm2() - 1) <= 1e-5
+    st.free()
+    del st
+    torch.cuda.empty_cache()
+
+
 @pytest.fixture(scope="module")
 def ref32():
     n, gates = wc.config_circuit(2)

@@ -369,3 +369,44 @@ def test_adjoint_mixed_circuit(dtype):
     assert rel <= (1e-10 if dtype == "c128" else 1e-4)
     back = psi.read()
     assert abs(abs(back[0]) - 1) <= (1e-12 if dtype == "c128" else 1e-5)
+
+
+# ----------------------------------------------------------------- edge cases
+def test_empty_circuit_and_identity_gates():
+    n = 10
+    st = sv.State(n, "c64").set_product("+")
+    before = st.read()
+    st.run([], max_k=4, rule=sv.RULE_ENHANCED)
+    st.run([("I", (3,)), ("I", (9,))])
+    assert np.array_equal(st.read(), before)
+
+
+def test_degenerate_sizes():
+    # one qubit; a block as wide as the state; a block that leaves no column bits
+    for dtype in ("c64", "c128"):
+        st = sv.State(1, dtype).run([("H", (0,)), ("SQRT_Y", (0,))])
+        assert abs(st.norm2() - 1) <= 1e-6
+    rng = np.random.default_rng(77)
+    for n, k in ((4, 4), (6, 6), (7, 5)):
+        M = wc.haar_unitary_from_seed(int(rng.integers(1 << 30)), k)
+        qs = tuple(int(x) for x in rng.permutation(n)[:k])
+        psi0 = ref.product_state(n, "+-01+-0"[:n])
+        want = ref.apply(psi0.copy(), M, qs)
+        for dtype, tol in (("c64", 1e-6), ("c128", 1e-13)):
+            st = sv.State(n, dtype).set_product("+-01+-0"[:n]).run([("MATRIX", qs, (), -1, M)])
+            assert np.max(np.abs(st.read() - want)) <= tol, (n, k, dtype)
+
+
+def test_invalid_calls_leave_the_state_untouched():
+    n = 6
+    st = sv.State(n, "c64").set_product("+")
+    before = st.read()
+    with pytest.raises(ValueError):
+        st.run([("H", (0,)), ("CZ", (1, 6))])   # second gate out of range: nothing applied
+    with pytest.raises(ValueError):
+        st.run([("H", (0,)), ("CZ", (2, 2))])
+    with pytest.raises(ValueError):
+        st.run([("H", (0,))], max_k=9)
+    with pytest.raises(ValueError):
+        st.expectation([(1.0, ((7, "Z"),))])
+    assert np.array_equal(st.read(), before)
