@@ -235,8 +235,9 @@ int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int use_graph);
  * precision), up to 4 blocks whose positions span at most 8 qubits are
  * applied together (a later block joins a group only if it commutes past
  * every block it jumps over): each tile of 2^14 amplitudes is staged in LDS
- * once, every block of the group is applied to it with FP32 MFMA, and the
- * tile is written back, so the group costs one state pass.
+ * once, every block of the group is applied to it with FP32 MFMA (split
+ * precisions: hi+lo BF16 MFMA), and the tile is written back, so the group
+ * costs one state pass.
  * SV_RULE_AUTO (with max_k = -1, or max_k as an upper bound) evaluates the
  * enhanced plans for every k and the tiled plans for k <= 4 on block
  * positions only, prices each with the cost table of (n, precision) (from
