@@ -33,6 +33,7 @@ FAMILY_NAMES = {1: "reg", 2: "generic", 3: "mfma_f32", 4: "split_bf16", 5: "spli
                 10: "tile_bf16"}
 KERNEL_SOURCES = {1: "apply.hip", 2: "apply.hip", 3: "mfma.hip", 4: "mfma.hip", 5: "mfma.hip", 9: "tile.hip",
                   10: "tile.hip"}
+TILE_FAMILIES = (9, 10)
 
 
 def log(*a):
@@ -47,7 +48,8 @@ def source_hash(fam: int) -> str:
 def read_traffic(fam: int, k: int, n: int):
     """HBM bytes per launch from a committed rocprofv3 counter summary, or
     None when there is none or the kernel source changed since."""
-    name = os.path.join(ROOT, "profiles", "traffic_%s_k%d_%dq.md" % (FAMILY_NAMES[fam], k, n))
+    tag = FAMILY_NAMES[fam] if k == 0 else "%s_k%d" % (FAMILY_NAMES[fam], k)
+    name = os.path.join(ROOT, "profiles", "traffic_%s_%dq.md" % (tag, n))
     if not os.path.exists(name):
         return None
     kv = {}
@@ -171,13 +173,20 @@ def main():
     sv.stats_enable(False)
     ms_step = 1e3 * t_total / args.steps
 
-    # dominant kernel class in the timed region
-    per_class = {}
+    # dominant kernel in the timed region.  Block kernels are instantiated
+    # per block size k; a tile-pass kernel takes its block count at run time,
+    # so its launches are one kernel whatever the count (k = 0 below).
+    per_class, tile_blocks = {}, {}
     for fam in FAMILY_NAMES:
-        for k in range(1, 7):
+        for k in range(1, 17 if fam in TILE_FAMILIES else 7):
             cnt, ms = sv.stats_query(FAMILY_NAMES[fam], k)
-            if cnt:
-                per_class[(fam, k)] = (cnt, ms)
+            if not cnt:
+                continue
+            key = (fam, 0) if fam in TILE_FAMILIES else (fam, k)
+            c0, m0 = per_class.get(key, (0, 0.0))
+            per_class[key] = (c0 + cnt, m0 + ms)
+            if fam in TILE_FAMILIES:
+                tile_blocks[fam] = tile_blocks.get(fam, 0) + cnt * k
     (dfam, dk), (dcnt, dms) = max(per_class.items(), key=lambda kv: kv[1][1])
     avg_ms = dms / dcnt
     achieved = pass_bytes / (avg_ms * 1e-3) / 1e9
@@ -186,16 +195,18 @@ def main():
     traffic = read_traffic(dfam, dk, n)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
-                "kernel": "%s k=%d" % (FAMILY_NAMES[dfam], dk), "avg_launch_ms": round(avg_ms, 4),
+                "kernel": FAMILY_NAMES[dfam] if dk == 0 else "%s k=%d" % (FAMILY_NAMES[dfam], dk),
+                "avg_launch_ms": round(avg_ms, 4),
                 "launches_per_step": dcnt // args.steps,
                 "algorithmic_bytes_per_launch": pass_bytes}
-    if dfam == 10:
-        flops = 3 * 8.0 * 16 * (1 << n) * dk  # three BF16 products per 4-qubit block
+    if dfam in TILE_FAMILIES:
+        blocks_per_launch = tile_blocks[dfam] / dcnt
+        roofline["blocks_per_launch"] = round(blocks_per_launch, 3)
+        # 8 * 16 flop per amplitude per 4-qubit block; split BF16 runs three products
+        flops = (3 if dfam == 10 else 1) * 8.0 * 16 * (1 << n) * blocks_per_launch
         roofline["mfma_tflops"] = round(flops / (avg_ms * 1e-3) / 1e12, 2)
-    if dfam == 9:
-        flops = 8.0 * 16 * (1 << n) * dk  # dk blocks of 4 qubits per tile pass
-        roofline["mfma_tflops"] = round(flops / (avg_ms * 1e-3) / 1e12, 2)
-        roofline["mfma_frac"] = round(roofline["mfma_tflops"] / MFMA_FP32_PEAK_TFLOPS, 4)
+        if dfam == 9:
+            roofline["mfma_frac"] = round(roofline["mfma_tflops"] / MFMA_FP32_PEAK_TFLOPS, 4)
     if dfam in (3, 4, 5):
         flops = 8.0 * (1 << dk) * (1 << n) * (3 if dfam in (4, 5) else 1)
         roofline["mfma_tflops"] = round(flops / (avg_ms * 1e-3) / 1e12, 2)

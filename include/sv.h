@@ -219,6 +219,10 @@ int sv_plan_block_matrix(const sv_plan *p, int b, double *m);
 int sv_plan_max_k(const sv_plan *p, int *out);
 /* The rule the plan was built with (the chosen one for SV_RULE_AUTO). */
 int sv_plan_rule(const sv_plan *p, int *out);
+/* Tile pass of block b (SV_RULE_TILED plans): consecutive blocks with the same
+ * pass number >= 0 are applied together in one read and one write of the
+ * state; -1 means the block is applied on its own. */
+int sv_plan_block_pass(const sv_plan *p, int b, int32_t *pass);
 /* Apply a plan's blocks in order with the given SV_PREC_* arithmetic; with
  * use_graph = 1 the launches are captured into a hipGraph that is replayed
  * once (and the call synchronises).  SV_ERR_QUBIT if the plan's positions do
@@ -311,14 +315,25 @@ int sv_batch_free(sv_batch *b);
 int sv_autotune(sv_state *scratch, int precision, double *cost_ms);
 /* Install a cost table for (n, precision) without timing (e.g. from a cache). */
 int sv_set_cost_table(int n, int precision, const double *cost_ms);
+/* Select the launch shape of the multi-block tile passes (SV_RULE_TILED):
+ * tiles of 2^tile_bits amplitudes held in LDS by workgroups of `waves`
+ * 64-lane waves.  Supported: (14, 8) and (14, 16), one 128 KiB tile per
+ * compute unit; (13, 4), two 64 KiB workgroups per compute unit; (13, 8).
+ * A launch holds at most 7 blocks ((14, *)), 3 ((13, 4)) or 16 ((13, 8));
+ * longer passes are split into several launches.  sv_autotune
+ * picks one itself; this call overrides it for the whole process (later
+ * launches on every state).  SV_ERR_ARG for other pairs. */
+int sv_set_tile_shape(int tile_bits, int waves);
 
 /* ---------------------------------------------------------------- stats */
 /* Per-kernel device timing.  While enabled every kernel launch is bracketed
  * by HIP events on its stream; sv_stats_query synchronises the recorded
  * launches and returns, for a kernel class, the launch count and the summed
- * device milliseconds.  Classes: 10*family + k, families 1 = register apply,
- * 2 = generic apply, 3 = MFMA FP32, 4 = MFMA split BF16, 5 = MFMA split FP16,
- * 6 = reductions, 7 = adjoint, 8 = batch. */
+ * device milliseconds.  Classes: 100*family + k, families 1 = register
+ * apply, 2 = generic apply, 3 = MFMA FP32, 4 = MFMA split BF16, 5 = MFMA split
+ * FP16, 6 = reductions, 7 = adjoint, 8 = batch, 9 = FP32 tile passes, 10 =
+ * split-BF16 tile passes; k is the block size, or for tile passes the number
+ * of blocks in the launch. */
 int sv_stats_enable(int on);
 int sv_stats_reset(void);
 int sv_stats_query(int cls, int64_t *launches, double *total_ms);

@@ -25,7 +25,8 @@ from ._native import (C64, C128, PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16, PR
                       SvValueError)
 
 __all__ = ["State", "Plan", "fuse", "gate_matrix", "backward", "Energy", "Batch", "positions",
-           "pauli_sum", "autotune", "set_cost_table", "stats_enable", "stats_reset", "stats_query",
+           "pauli_sum", "autotune", "set_cost_table", "set_tile_shape", "TILE_SHAPES",
+           "stats_enable", "stats_reset", "stats_query",
            "C64", "C128", "PREC_FP32", "PREC_SPLIT_BF16", "PREC_SPLIT_FP16", "PREC_FP64",
            "RULE_PAPER", "RULE_ENHANCED", "RULE_NONE", "RULE_TILED", "RULE_AUTO", "SvError", "SvValueError"]
 
@@ -268,6 +269,7 @@ class Block:
     qubits: tuple
     members: list
     matrix: np.ndarray
+    tile_pass: int = -1
 
 
 class Plan:
@@ -318,7 +320,9 @@ class Plan:
             buf = np.zeros(2 * D * D, dtype=np.float64)
             N.check(N.lib().sv_plan_block_matrix(self.h, b, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
             mat = buf.view(np.complex128).reshape(D, D)
-        return Block(tuple(q[:k.value]), list(members[:nm.value]), mat)
+        tp = ctypes.c_int32()
+        N.check(N.lib().sv_plan_block_pass(self.h, b, ctypes.byref(tp)))
+        return Block(tuple(q[:k.value]), list(members[:nm.value]), mat, tp.value)
 
     def blocks(self, with_matrix: bool = True) -> List[Block]:
         return [self.block(b, with_matrix) for b in range(len(self))]
@@ -464,6 +468,15 @@ def set_cost_table(n: int, precision: int, cost) -> None:
     N.check(N.lib().sv_set_cost_table(int(n), int(precision), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
 
+TILE_SHAPES = ((14, 8), (14, 16), (13, 4), (13, 8))
+
+
+def set_tile_shape(tile_bits: int, waves: int) -> None:
+    """Launch shape of the tile passes: 2^tile_bits amplitudes per LDS tile,
+    `waves` waves per workgroup (one of TILE_SHAPES), for the whole process."""
+    N.check(N.lib().sv_set_tile_shape(int(tile_bits), int(waves)))
+
+
 def stats_enable(on: bool = True) -> None:
     N.check(N.lib().sv_stats_enable(int(bool(on))))
 
@@ -478,7 +491,7 @@ FAMILIES = {"reg": 1, "generic": 2, "mfma_f32": 3, "split_bf16": 4, "split_fp16"
 
 def stats_query(family: str, k: int):
     """(launch count, summed device milliseconds) of a kernel class."""
-    cls = 10 * FAMILIES[family] + int(k)
+    cls = 100 * FAMILIES[family] + int(k)
     n = ctypes.c_int64()
     ms = ctypes.c_double()
     N.check(N.lib().sv_stats_query(cls, ctypes.byref(n), ctypes.byref(ms)))

@@ -97,6 +97,7 @@ SIGNATURES = {
     "sv_plan_num_blocks": (_I, [_P, ctypes.POINTER(_I)]),
     "sv_plan_block": (_I, [_P, _I, _I32P, _I32P, _I32P]),
     "sv_plan_block_members": (_I, [_P, _I, _I32P]),
+    "sv_plan_block_pass": (_I, [_P, _I, _I32P]),
     "sv_plan_block_matrix": (_I, [_P, _I, _D]),
     "sv_plan_max_k": (_I, [_P, ctypes.POINTER(_I)]),
     "sv_plan_rule": (_I, [_P, ctypes.POINTER(_I)]),
@@ -114,6 +115,7 @@ SIGNATURES = {
     "sv_batch_free": (_I, [_P]),
     "sv_autotune": (_I, [_P, _I, _D]),
     "sv_set_cost_table": (_I, [_I, _I, _D]),
+    "sv_set_tile_shape": (_I, [_I, _I]),
     "sv_stats_enable": (_I, [_I]),
     "sv_stats_reset": (_I, []),
     "sv_stats_query": (_I, [_I, _I64P, _D]),

@@ -430,6 +430,15 @@ extern "C" int sv_plan_block(const sv_plan *p, int b, int32_t *k, int32_t *q, in
     return SV_OK;
 }
 
+extern "C" int sv_plan_block_pass(const sv_plan *p, int b, int32_t *pass)
+{
+    clear_error();
+    if (!p || !pass) return fail(SV_ERR_ARG, "NULL argument");
+    if (b < 0 || b >= int(p->blocks.size())) return fail(SV_ERR_ARG, "block %d out of range", b);
+    *pass = p->blocks[b].pass;
+    return SV_OK;
+}
+
 extern "C" int sv_plan_block_members(const sv_plan *p, int b, int32_t *members)
 {
     clear_error();
@@ -581,7 +590,7 @@ extern "C" int sv_norm(sv_state *s, double *out)
     double *part = static_cast<double *>(s->red.p);
     double *res = part + 2 * dev::kRedBlocks;
     {
-        LaunchTimer t(10 * FAM_REDUCE + 1, s->stream);
+        LaunchTimer t(stat_class(FAM_REDUCE, 1), s->stream);
         SV_HIP(dev::launch_norm(s->dtype, s->buf, s->n, part, res, s->stream));
     }
     return read_result(s, res, 1, out);
@@ -597,7 +606,7 @@ extern "C" int sv_inner(sv_state *a, sv_state *b, double *re, double *im)
     double *part = static_cast<double *>(b->red.p);
     double *res = part + 2 * dev::kRedBlocks;
     {
-        LaunchTimer t(10 * FAM_REDUCE + 2, b->stream);
+        LaunchTimer t(stat_class(FAM_REDUCE, 2), b->stream);
         SV_HIP(dev::launch_inner(a->dtype, a->buf, b->dtype, b->buf, b->n, part, res, b->stream));
     }
     double v[2];
@@ -624,7 +633,7 @@ extern "C" int sv_expectation(sv_state *s, const sv_pauli_sum *H, double *out)
     double *part = static_cast<double *>(s->red.p);
     double *res = part + 2 * dev::kRedBlocks;
     {
-        LaunchTimer t(10 * FAM_REDUCE + 3, s->stream);
+        LaunchTimer t(stat_class(FAM_REDUCE, 3), s->stream);
         SV_HIP(dev::launch_pauli_expect(s->dtype, s->buf, s->n, P, part, res, s->stream));
     }
     SV_HIP(hipEventRecord(s->arena_free, s->stream));
@@ -646,7 +655,7 @@ extern "C" int sv_apply_pauli_sum(sv_state *psi, const sv_pauli_sum *H, sv_state
         SV_HIP(dev::launch_fill_basis(out->dtype, out->buf, out->n, ~uint64_t(0), psi->stream));
     } else {
         if (int rc = pauli_tables(psi, H, P)) return rc;
-        LaunchTimer t(10 * FAM_REDUCE + 4, psi->stream);
+        LaunchTimer t(stat_class(FAM_REDUCE, 4), psi->stream);
         SV_HIP(dev::launch_pauli_apply(psi->dtype, psi->buf, out->buf, psi->n, P, psi->stream));
     }
     SV_HIP(hipEventRecord(psi->arena_free, psi->stream));
@@ -815,13 +824,13 @@ extern "C" int sv_backward(sv_state *psi, sv_state *scratch, const sv_gate *g, i
             for (int r = 0; r < D; ++r)
                 for (int c = 0; c < D; ++c) mdag[size_t(r) * D + c] = std::conj(m[size_t(c) * D + r]);
             const int pauli = st.slot < 0 ? 0 : gg.kind == SV_G_RX ? 1 : gg.kind == SV_G_RY ? 2 : 3;
-            LaunchTimer t(10 * FAM_ADJOINT + gg.k, psi->stream);
+            LaunchTimer t(stat_class(FAM_ADJOINT, gg.k), psi->stream);
             SV_HIP(dev::launch_backward_step(psi->dtype, gg.k, sq, mdag.data(), pauli, psi->buf, scratch->buf, psi->n,
                                              part, st.slot, psi->stream));
             continue;
         }
         if (st.kind == BwdStep::RUN) {
-            LaunchTimer t(10 * FAM_ADJOINT + 3, psi->stream);
+            LaunchTimer t(stat_class(FAM_ADJOINT, 3), psi->stream);
             SV_HIP(dev::launch_grad_terms(psi->dtype, st.n_terms, st.x, st.z, st.pw, psi->buf, scratch->buf, psi->n,
                                           part, st.slot, psi->stream));
         }

@@ -470,7 +470,7 @@ int enqueue_run(sv_batch *b, hipStream_t main, hipStream_t side)
     SV_HIP(hipEventRecord(b->fork, main));
     SV_HIP(hipStreamWaitEvent(side, b->fork, 0));
     if (b->n_small) {
-        LaunchTimer t(10 * FAM_BATCH + 1, side);
+        LaunchTimer t(stat_class(FAM_BATCH, 1), side);
         const unsigned grid = unsigned(std::min(b->n_small, 2048));
         const size_t lds = size_t(sizeof(float2)) << b->small_max_n;
         hipLaunchKernelGGL(k_batch_small, dim3(grid), dim3(kThreads), lds, side,
@@ -479,7 +479,7 @@ int enqueue_run(sv_batch *b, hipStream_t main, hipStream_t side)
     }
     if (b->n_large) {
         {
-            LaunchTimer t(10 * FAM_BATCH + 2, main);
+            LaunchTimer t(stat_class(FAM_BATCH, 2), main);
             const uint64_t cnt = b->large_end - b->large_begin;
             const unsigned grid = unsigned(std::min<uint64_t>((cnt + 255) / 256, 16384));
             hipLaunchKernelGGL(k_batch_zero, dim3(grid), dim3(256), 0, main, b->buf, b->large_begin, b->large_end);
@@ -489,12 +489,12 @@ int enqueue_run(sv_batch *b, hipStream_t main, hipStream_t side)
         }
         const auto *items = static_cast<const BItem *>(b->d_items.p);
         for (const auto &st : b->steps) {
-            LaunchTimer t(10 * FAM_BATCH + 3, main);
+            LaunchTimer t(stat_class(FAM_BATCH, 3), main);
             hipLaunchKernelGGL(k_batch_step, dim3(st.second), dim3(kThreads), 0, main, items + st.first, blocks, mats,
                                b->buf);
             SV_HIP(hipGetLastError());
         }
-        LaunchTimer t(10 * FAM_BATCH + 4, main);
+        LaunchTimer t(stat_class(FAM_BATCH, 4), main);
         hipLaunchKernelGGL(k_batch_z0, dim3(b->n_large), dim3(kThreads), 0, main,
                            static_cast<const BLarge *>(b->d_large.p), b->buf, z0);
         SV_HIP(hipGetLastError());

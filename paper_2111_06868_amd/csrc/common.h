@@ -35,18 +35,29 @@ int gate_matrix_canonical(const sv_gate &g, std::vector<cd> &m, int *sorted_q);
 void reverse_local_bits(const std::vector<cd> &in, int k, std::vector<cd> &out);
 
 // ---------------------------------------------------------------- fusion
+// Tile passes (SV_RULE_TILED): at most kTilePassMaxBlocks blocks of <= 4
+// qubits whose positions span at most kTilePassMaxUnion positions.
+constexpr int kTilePassMaxBlocks = 16;
+constexpr int kTilePassMaxUnion = 10;
+
 struct Block {
     int k = 0;
     int q[SV_MAX_K] = {0};       // ascending positions
-    std::vector<int> members;    // gate indices, in circuit order
+    std::vector<int> members;    // gate indices, in an order that keeps the circuit's product
     std::vector<cd> m;           // canonical 2^k x 2^k matrix (row-major)
+    int pass = -1;               // tile pass of the block (SV_RULE_TILED), -1 = own launch
 };
 
 struct CostTable {
     bool valid = false;
-    double ms[SV_MAX_K + 1] = {0};  // one application of a k-qubit block
-    double tile[5] = {0};           // one tile pass holding s = 1..4 blocks of 4 qubits
+    double ms[SV_MAX_K + 1] = {0};          // one application of a k-qubit block
+    double tile[kTilePassMaxBlocks + 1] = {0};  // one tile pass holding s blocks of 4 qubits
 };
+
+// Union limit of the tile passes that SV_RULE_TILED plans (8 ..
+// kTilePassMaxUnion; default 8, or the SV_TILE_UNION environment variable).
+int tile_union_limit();
+void set_tile_union_limit(int u);
 
 // Cost table used when no autotuned table exists (relative units).
 CostTable default_costs();
@@ -60,7 +71,8 @@ int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTa
                std::vector<Block> &blocks, bool with_matrices = true);
 double plan_cost(const std::vector<Block> &blocks, const CostTable &cost);
 // Tile grouping (see group_tile_passes): groups of block indices, in
-// application order; a group of one is applied on its own.
+// application order (consecutive blocks of one tile pass); a group of one is
+// applied on its own.
 std::vector<std::vector<size_t>> tile_groups(const std::vector<Block> &blocks, int n);
 // Cost of the tiled plan of `blocks` with the table's tile and block costs.
 double tiled_plan_cost(const std::vector<Block> &blocks, int n, const CostTable &cost);

@@ -8,15 +8,24 @@
 // that shares a qubit with it when the union fits, else it opens a new block.
 // That placement is legal because every later block is disjoint from the gate.
 //
-// The enhanced rule keeps that first pass and adds two cost-aware steps:
-//   - a gate that cannot join the last intersecting block may join any later
-//     block (all of them are disjoint from it) when the cost table says the
-//     grown block is cheaper than a block of its own;
-//   - afterwards, block j is merged into an earlier block i when every block
-//     between them is disjoint from j (so j commutes next to i) and the cost
-//     of the union is lower than the two costs together.
+// The enhanced rule builds two candidate plans and keeps the cheaper one
+// under the cost table:
+//   - the paper's pass plus two cost-aware steps: a gate that cannot join
+//     the last intersecting block may join any later block (all of them are
+//     disjoint from it) when the grown block is cheaper than a block of its
+//     own, and block j is merged into an earlier block i when every block
+//     between them is disjoint from j (so j commutes next to i) and the union
+//     costs less than the two blocks;
+//   - frontier grouping (frontier_groups): gates leave in any order that
+//     keeps each qubit's gate sequence, and a block grows by the ready gate
+//     that adds the fewest new positions.
+// The tiled rule applies frontier grouping twice: passes whose positions
+// span at most tile_union_limit() positions, then blocks of at most 4 qubits
+// inside each pass, which a tile kernel applies in one read and one write of
+// the state.
 #include <algorithm>
 #include <atomic>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -35,10 +44,19 @@ CostTable default_costs()
     const double c[SV_MAX_K + 1] = {0.0, 1.0, 1.0, 1.0, 1.02, 1.1, 1.6};
     std::memcpy(t.ms, c, sizeof c);
     // a tile pass is one state pass plus in-LDS work per 4-qubit block
-    const double tl[5] = {0.0, 1.1, 1.15, 1.3, 1.5};
-    std::memcpy(t.tile, tl, sizeof tl);
+    t.tile[0] = 0;
+    for (int s = 1; s <= kTilePassMaxBlocks; ++s) t.tile[s] = 1.05 + 0.1 * s;
     return t;
 }
+
+static int g_tile_union = [] {
+    int u = 8;
+    if (const char *e = std::getenv("SV_TILE_UNION")) u = std::atoi(e);
+    return std::min(std::max(u, 8), kTilePassMaxUnion);
+}();
+
+int tile_union_limit() { return g_tile_union; }
+void set_tile_union_limit(int u) { g_tile_union = std::min(std::max(u, 8), kTilePassMaxUnion); }
 
 static std::mutex g_cost_mu;
 static std::map<std::pair<int, int>, CostTable> g_costs;
@@ -61,10 +79,10 @@ void store_costs(int n, int precision, const double *ms, const double *tile)
     t.valid = true;
     for (int k = 0; k <= SV_MAX_K; ++k) t.ms[k] = ms[k];
     if (tile) {
-        for (int s = 0; s <= 4; ++s) t.tile[s] = tile[s];
+        for (int s = 0; s <= kTilePassMaxBlocks; ++s) t.tile[s] = tile[s];
     } else {
         // untimed tile passes: scale the defaults by the measured 4-qubit block cost
-        for (int s = 1; s <= 4; ++s) t.tile[s] *= ms[4] / default_costs().ms[4];
+        for (int s = 1; s <= kTilePassMaxBlocks; ++s) t.tile[s] *= ms[4] / default_costs().ms[4];
     }
     std::lock_guard<std::mutex> lk(g_cost_mu);
     g_costs[{n, precision}] = t;
@@ -84,6 +102,82 @@ uint64_t gate_mask(const sv_gate &g)
     uint64_t m = 0;
     for (int j = 0; j < g.k; ++j) m |= uint64_t(1) << g.q[j];
     return m;
+}
+
+// Frontier grouping of the gates idx[0..] (a sequence in which every
+// qubit's gates already appear in circuit order).  Gates leave in an order
+// that keeps each qubit's sequence, so the product of the groups, in order,
+// equals the product of the gates.  A group starts with no positions; it takes
+// every ready gate (first unapplied gate on each of its qubits) whose
+// positions it already covers, and otherwise widens by the ready gate that
+// adds the fewest positions (the earliest on ties) while it stays within
+// max_union positions.  Members are listed in the order they are applied.
+// Every gate must act on at most max_union qubits.
+std::vector<std::vector<int>> frontier_groups(const sv_gate *g, const std::vector<int> &idx, int max_union)
+{
+    const int G = int(idx.size());
+    std::vector<uint64_t> mask(G);
+    std::vector<std::vector<int>> queue(64);
+    for (int t = 0; t < G; ++t) {
+        mask[t] = gate_mask(g[idx[t]]);
+        for (uint64_t m = mask[t]; m; m &= m - 1) queue[__builtin_ctzll(m)].push_back(t);
+    }
+    std::vector<size_t> head(64, 0);
+    auto at_head = [&](int p) { return head[p] < queue[p].size() ? queue[p][head[p]] : -1; };
+    auto ready = [&](int t) {
+        for (uint64_t m = mask[t]; m; m &= m - 1)
+            if (at_head(__builtin_ctzll(m)) != t) return false;
+        return true;
+    };
+    std::vector<std::vector<int>> out;
+    int left = G;
+    while (left > 0) {
+        uint64_t U = 0;
+        std::vector<int> grp;
+        for (;;) {
+            for (bool again = true; again;) {
+                again = false;
+                for (uint64_t m = U; m; m &= m - 1) {
+                    const int p = __builtin_ctzll(m);
+                    for (int t; (t = at_head(p)) >= 0 && !(mask[t] & ~U) && ready(t);) {
+                        grp.push_back(idx[t]);
+                        --left;
+                        for (uint64_t mm = mask[t]; mm; mm &= mm - 1) ++head[__builtin_ctzll(mm)];
+                        again = true;
+                    }
+                }
+            }
+            int best = -1, best_add = 65;
+            for (int p = 0; p < 64; ++p) {
+                const int t = at_head(p);
+                if (t < 0 || !ready(t) || popc(U | mask[t]) > max_union) continue;
+                const int add = popc(mask[t] & ~U);
+                if (add < best_add || (add == best_add && t < best)) {
+                    best_add = add;
+                    best = t;
+                }
+            }
+            if (best < 0) break;
+            U |= mask[best];
+        }
+        if (grp.empty()) break;  // only reachable with a gate wider than max_union
+        out.push_back(std::move(grp));
+    }
+    return out;
+}
+
+// Blocks (positions and members, no matrices) of a list of member groups.
+void blocks_of_groups(const sv_gate *g, const std::vector<std::vector<int>> &groups, std::vector<Block> &blocks)
+{
+    for (const auto &grp : groups) {
+        Block B;
+        uint64_t m = 0;
+        for (int gi : grp) m |= gate_mask(g[gi]);
+        for (int p = 0; p < 64; ++p)
+            if ((m >> p) & 1) B.q[B.k++] = p;
+        B.members = grp;
+        blocks.push_back(std::move(B));
+    }
 }
 
 }  // namespace
@@ -155,17 +249,55 @@ void block_matrix(const sv_gate *g, Block &b)
     }
 }
 
+// Matrices of all blocks; they are independent, so large jobs are spread
+// over host threads.
+static int block_matrices(const sv_gate *g, std::vector<Block> &blocks)
+{
+    size_t work = 0;
+    for (const auto &B : blocks) work += B.members.size() << (2 * B.k);
+    const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+    const unsigned nt = work > (size_t(1) << 18) ? std::min<unsigned>(hw, unsigned(blocks.size())) : 1u;
+    std::atomic<size_t> next(0);
+    auto worker = [&]() {
+        for (size_t b; (b = next.fetch_add(1)) < blocks.size();) block_matrix(g, blocks[b]);
+    };
+    std::vector<std::thread> pool;
+    for (unsigned t = 1; t < nt; ++t) pool.emplace_back(worker);
+    worker();
+    for (auto &th : pool) th.join();
+    return SV_OK;
+}
+
 int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTable &cost,
                std::vector<Block> &blocks, bool with_matrices)
 {
     (void)n;
     if (max_k < 1 || max_k > SV_MAX_K) return fail(SV_ERR_ARG, "max_k %d outside 1..%d", max_k, SV_MAX_K);
-    if (rule == SV_RULE_TILED) {  // blocks for tile passes: the enhanced rule, at most 4 qubits
-        rule = SV_RULE_ENHANCED;
-        max_k = max_k < 4 ? max_k : 4;
-    }
-    if (rule != SV_RULE_PAPER && rule != SV_RULE_ENHANCED && rule != SV_RULE_NONE)
+    if (rule != SV_RULE_PAPER && rule != SV_RULE_ENHANCED && rule != SV_RULE_NONE && rule != SV_RULE_TILED)
         return fail(SV_ERR_ARG, "unknown fusion rule %d", rule);
+    if (rule == SV_RULE_TILED) max_k = max_k < 4 ? max_k : 4;  // tile kernels take blocks of <= 4 qubits
+    blocks.clear();
+    if (rule == SV_RULE_TILED) {
+        for (int gi = 0; gi < G; ++gi)
+            if (g[gi].k > max_k)
+                return fail(SV_ERR_ARG, "gate %d acts on %d qubits, more than max_k=%d", gi, g[gi].k, max_k);
+        std::vector<int> all(G);
+        for (int i = 0; i < G; ++i) all[i] = i;
+        int pass = 0;
+        for (const auto &pg : frontier_groups(g, all, tile_union_limit())) {
+            const auto sub = frontier_groups(g, pg, max_k);
+            for (size_t c = 0; c < sub.size(); c += kTilePassMaxBlocks) {
+                const size_t e = std::min(sub.size(), c + kTilePassMaxBlocks);
+                const size_t first = blocks.size();
+                blocks_of_groups(g, std::vector<std::vector<int>>(sub.begin() + c, sub.begin() + e), blocks);
+                if (e - c >= 2) {
+                    for (size_t b = first; b < blocks.size(); ++b) blocks[b].pass = pass;
+                    ++pass;
+                }
+            }
+        }
+        return with_matrices ? block_matrices(g, blocks) : SV_OK;
+    }
     std::vector<WBlock> wb;
     wb.reserve(G);
     for (int gi = 0; gi < G; ++gi) {
@@ -223,66 +355,38 @@ int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTa
             }
         }
     }
-    blocks.clear();
     blocks.resize(wb.size());
-    size_t work = 0;
     for (size_t b = 0; b < wb.size(); ++b) {
         Block &B = blocks[b];
         B.k = 0;
         for (int p = 0; p < 64; ++p)
             if ((wb[b].mask >> p) & 1) B.q[B.k++] = p;
         B.members = wb[b].members;
-        work += B.members.size() << (2 * B.k);
     }
-    if (!with_matrices) return SV_OK;
-    // block matrices are independent: spread large jobs over host threads
-    const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
-    const unsigned nt = work > (size_t(1) << 18) ? std::min<unsigned>(hw, unsigned(blocks.size())) : 1u;
-    std::atomic<size_t> next(0);
-    auto worker = [&]() {
-        for (size_t b; (b = next.fetch_add(1)) < blocks.size();) block_matrix(g, blocks[b]);
-    };
-    std::vector<std::thread> pool;
-    for (unsigned t = 1; t < nt; ++t) pool.emplace_back(worker);
-    worker();
-    for (auto &th : pool) th.join();
-    return SV_OK;
+    if (rule == SV_RULE_ENHANCED) {
+        // the frontier plan replaces it when the cost table prices it lower
+        std::vector<int> all(G);
+        for (int i = 0; i < G; ++i) all[i] = i;
+        std::vector<Block> alt;
+        blocks_of_groups(g, frontier_groups(g, all, max_k), alt);
+        const double ca = plan_cost(alt, cost), cb = plan_cost(blocks, cost);
+        if (ca < cb - 1e-12 || (ca <= cb + 1e-12 && alt.size() < blocks.size())) blocks.swap(alt);
+    }
+    return with_matrices ? block_matrices(g, blocks) : SV_OK;
 }
+
 
 std::vector<std::vector<size_t>> tile_groups(const std::vector<Block> &blocks, int n)
 {
-    // Greedy, commutation-aware: a group starts at the first block not yet
-    // applied and takes later blocks of <= 4 qubits while the union stays
-    // within 8 positions; a later block may join only if it is disjoint from
-    // every block it jumps over (so it commutes past them).
-    constexpr int kMaxUnion = 8, kMaxBlocks = 4, kMinQubits = 14;
-    auto mask_of = [](const Block &b) {
-        uint64_t m = 0;
-        for (int j = 0; j < b.k; ++j) m |= uint64_t(1) << b.q[j];
-        return m;
-    };
+    // consecutive blocks of one tile pass; states below 14 qubits (one tile
+    // would hold the whole state several times over) apply every block alone
+    constexpr int kMinQubits = 14;
     std::vector<std::vector<size_t>> out;
-    std::vector<char> done(blocks.size(), 0);
     for (size_t i = 0; i < blocks.size(); ++i) {
-        if (done[i]) continue;
-        std::vector<size_t> grp = {i};
-        uint64_t um = mask_of(blocks[i]);
-        if (blocks[i].k <= 4 && n >= kMinQubits) {
-            uint64_t skipped = 0;
-            for (size_t j = i + 1; j < blocks.size() && int(grp.size()) < kMaxBlocks; ++j) {
-                if (done[j]) continue;
-                const uint64_t m = mask_of(blocks[j]);
-                if (!(m & skipped) && blocks[j].k <= 4 && popc(um | m) <= kMaxUnion) {
-                    um |= m;
-                    grp.push_back(j);
-                } else {
-                    skipped |= m;
-                }
-            }
-        }
-        if (grp.size() < 2) grp.resize(1);
-        for (size_t b : grp) done[b] = 1;
-        out.push_back(std::move(grp));
+        if (n >= kMinQubits && blocks[i].pass >= 0 && !out.empty() && blocks[out.back().back()].pass == blocks[i].pass)
+            out.back().push_back(i);
+        else
+            out.push_back({i});
     }
     return out;
 }

@@ -36,15 +36,21 @@ hipError_t launch_mfma_split(int k, bool fp16, const int *sorted_q, const uint16
 // Multi-block tile passes (complex64, FP32 MFMA): up to kMaxTileSubBlocks
 // 4-qubit blocks whose positions have a union of at most kMaxTileUnion
 // positions, applied in one HBM pass over tiles of 2^tile_bits amplitudes
-// (13 or 14).  d_a = the blocks' real-form matrices, back to back: 32 x 32
-// floats each (FP32), or for split_bf16 the hi then the lo part, 32 x 32
-// bf16 each.  Needs n >= tile_bits.
-constexpr int kMaxTileSubBlocks = 4;
-constexpr int kMaxTileUnion = 8;
+// held by workgroups of `waves` waves; shapes (14, 8), (14, 16), (13, 4),
+// (13, 8).
+// sub_pos rows ascending.  d_a = the blocks' real-form matrices, back to
+// back: 32 x 32 floats each (FP32), or for split_bf16 the hi then the lo
+// part, 32 x 32 bf16 each.  Needs n >= tile_bits.
+constexpr int kMaxTileSubBlocks = kTilePassMaxBlocks;
+constexpr int kMaxTileUnion = kTilePassMaxUnion;
 constexpr int kMinTileQubits = 14;
 bool tile_supported(int n, int union_bits);
+bool tile_shape_supported(int tile_bits, int waves);
+int tile_wgs_per_cu(int tile_bits, int waves);
+// Blocks one launch of the shape can hold (their operands sit in LDS).
+int tile_max_blocks(int tile_bits, int waves);
 hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a, bool split_bf16, void *psi, int n,
-                            hipStream_t st, int grid_cap, int tile_bits);
+                            hipStream_t st, int grid_cap, int tile_bits, int waves);
 // Host-side packing of the MFMA operands of a canonical k-qubit matrix.
 void pack_real_form_f32(const cd *m, int k, float *out);
 void pack_real_form_split(const cd *m, int k, bool fp16, uint16_t *hi, uint16_t *lo);

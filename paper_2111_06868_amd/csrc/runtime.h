@@ -50,6 +50,10 @@ enum Family {
     FAM_TILE_BF16 = 10,
 };
 
+// Statistics class of a launch: 100 * family + k (k = block size, or the
+// number of blocks of a tile pass).
+inline int stat_class(int family, int k) { return 100 * family + k; }
+
 // RAII: brackets one launch with HIP events on `st` when timing is enabled.
 class LaunchTimer {
   public:
@@ -75,8 +79,9 @@ struct Tuning {
     int mfma_grid_cap[SV_MAX_K + 1];
     int split_tc_log[SV_MAX_K + 1];
     bool k4_reg;                      // FP32: k = 4 via the register kernel
-    int tile_grid_cap;
+    int tile_grid_cap;                // workgroups per resident slot set (one per CU)
     int tile_bits;                    // 13 (64 KiB LDS tiles) or 14 (128 KiB)
+    int tile_waves;                   // waves per tile workgroup (4 or 8)
 };
 Tuning &tuning();
 Path choose_path(int dtype, int precision, int k, const int *sorted_q, int n);

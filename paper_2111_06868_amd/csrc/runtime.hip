@@ -178,9 +178,12 @@ Tuning &tuning()
         x.mfma_tc_log[6] = 5;
         x.split_tc_log[6] = 5;
         x.k4_reg = false;
-        x.tile_grid_cap = 512;
+        x.tile_grid_cap = 256;
         x.tile_bits = 14;
+        x.tile_waves = 8;
         if (const char *e = std::getenv("SV_TILE_BITS")) x.tile_bits = std::atoi(e) == 13 ? 13 : 14;
+        if (const char *e = std::getenv("SV_TILE_WAVES")) x.tile_waves = std::atoi(e);
+        if (!dev::tile_shape_supported(x.tile_bits, x.tile_waves)) x.tile_waves = 8;
         if (const char *e = std::getenv("SV_TILE_GRID")) x.tile_grid_cap = std::max(1, std::atoi(e));
         return x;
     }();
@@ -370,7 +373,23 @@ int enqueue(const std::vector<Launch> &launches, int dtype, void *psi, int n, co
     const char *A = static_cast<const char *>(arena);
     const Tuning &T = tuning();
     for (const auto &L : launches) {
-        LaunchTimer timer(10 * path_family(L.path) + L.k, st);  // PATH_TILE: k = blocks in the pass
+        if (L.path == PATH_TILE || L.path == PATH_TILE_BF16) {
+            // one launch per chunk of blocks whose operands fit the shape's LDS
+            const int cap = dev::tile_max_blocks(T.tile_bits, T.tile_waves);
+            const size_t op_bytes = 4 * dev::real_form_elems(4);  // FP32, or hi + lo bf16
+            for (int c = 0; c < L.k; c += cap) {
+                const int m = std::min(cap, L.k - c);
+                LaunchTimer timer(stat_class(path_family(L.path), m), st);
+                hipError_t e = dev::launch_tile_pass(m, L.sub_pos + c, A + L.arena_off + c * op_bytes,
+                                                     L.path == PATH_TILE_BF16, psi, n, st,
+                                                     T.tile_grid_cap * dev::tile_wgs_per_cu(T.tile_bits, T.tile_waves),
+                                                     T.tile_bits, T.tile_waves);
+                if (e != hipSuccess)
+                    return fail(SV_ERR_HIP, "tile pass launch (%d blocks): %s", m, hipGetErrorString(e));
+            }
+            continue;
+        }
+        LaunchTimer timer(stat_class(path_family(L.path), L.k), st);
         hipError_t e = hipSuccess;
         switch (L.path) {
         case PATH_REG: e = dev::launch_reg(dtype, L.k, L.q, L.m.data(), psi, n, st, T.reg_grid_cap[L.k]); break;
@@ -378,12 +397,6 @@ int enqueue(const std::vector<Launch> &launches, int dtype, void *psi, int n, co
         case PATH_MFMA32:
             e = dev::launch_mfma_f32(L.k, L.q, reinterpret_cast<const float *>(A + L.arena_off), psi, n, st,
                                      T.mfma_tc_log[L.k], T.mfma_grid_cap[L.k]);
-            break;
-        case PATH_TILE:
-        case PATH_TILE_BF16:
-            e = dev::launch_tile_pass(L.k, L.sub_pos, A + L.arena_off, L.path == PATH_TILE_BF16, psi, n, st,
-                                      T.tile_bits == 13 ? T.tile_grid_cap : std::max(1, T.tile_grid_cap / 2),
-                                      T.tile_bits);
             break;
         default:
             e = dev::launch_mfma_split(L.k, L.path == PATH_SPLIT_FP16, L.q,

@@ -1,22 +1,24 @@
-// Multi-block tile passes: several consecutive fused 4-qubit blocks applied
+// Multi-block tile passes: a sequence of fused blocks of <= 4 qubits applied
 // to a state in ONE read and ONE write of HBM.
 //
-// The blocks of a pass act on a union U of at most 8 positions.  A tile is
-// the 2^TB amplitudes (TB = 13 or 14: 64 or 128 KiB of complex64 in LDS)
-// spanned by U plus the lowest TB - |U| positions outside U (tile bit b <->
-// position u_b, ascending); at least 5 low positions join, so the tile is
-// made of contiguous runs of >= 32 amplitudes (256 B).  For every value of
-// the remaining n - TB bits there is one tile; tiles are copied in and out
-// with 16-byte accesses along those runs (tile bit 0 is always position 0).
+// The blocks of a pass act on a union U of at most kMaxTileUnion positions.
+// A tile is the 2^TB amplitudes (TB = 13 or 14: 64 or 128 KiB of complex64 in
+// LDS) spanned by U plus the lowest TB - |U| positions outside U (tile bit b
+// <-> position u_b, ascending), so it is made of contiguous runs of at least
+// 2^(TB - |U|) amplitudes.  For every value of the remaining n - TB bits there
+// is one tile; tiles are copied in and out with 16-byte accesses along those
+// runs (tile bit 0 is always position 0).
 //
 // Inside the tile, block s (4 positions at tile bits t_s0 < .. < t_s3) is a
 // complex GEMM Y = U_s X with X viewed as 16 rows (the block's tile bits) x
-// 2^(TB-4) columns (the other tile bits): one v_mfma_f32_32x32x2f32 chain per
-// 32-column block, the real form A' = [[Ur,-Ui],[Ui,Ur]] interleaved by
-// (re, im) held in VGPRs (16 per lane per block) for the whole persistent
-// kernel, B operands and results addressed in LDS as row_offset(j) +
-// column_offset(c) (bit deposits).  Each wave owns whole columns, so blocks
-// update the tile in place with one barrier between blocks.
+// 2^(TB-4) columns (the other tile bits): one MFMA chain per 32-column block,
+// the real form A' = [[Ur,-Ui],[Ui,Ur]] interleaved by (re, im) as the A
+// operand.  The A operands of all blocks of the pass, and their column
+// address tables, are staged into LDS once per workgroup next to the tile.
+// B operands and results are addressed in LDS as row(j) XOR column(c) (bit
+// deposits, then an XOR swizzle against bank conflicts).  Each wave owns
+// whole columns, so blocks update the tile in place with one barrier between
+// blocks.
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -29,19 +31,29 @@ namespace dev {
 namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float vf4 __attribute__((ext_vector_type(4)));
+typedef float vf2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kMaxTileBits = 14;
-constexpr int kTileThreads = 512;
-constexpr int kTileWaves = kTileThreads / 64;
+constexpr int kOperandWords = 1024;  // one block's A operand: 32 x 32 FP32, or 2 x 32 x 32 bf16
 
-// Tile of 2^TB amplitudes: 2^TB / 16 columns per 4-qubit block, split over 8 waves.
-template <int TB>
+// Tile of 2^TB amplitudes held by a workgroup of WAVES waves: 2^TB / 16
+// columns per 4-qubit block, in blocks of 32 split evenly over the waves.
+// Shapes: (14, 8) and (14, 16) one 128 KiB tile per CU, with 2 or 4 waves
+// per SIMD; (13, 4) two 64 KiB workgroups per CU, so one can copy while the
+// other computes; (13, 8).  MAX_SUB blocks' operands fit in the LDS left
+// beside the tile.
+template <int TB, int WAVES>
 struct TileCfg {
     static constexpr int N = 1 << TB;
+    static constexpr int THREADS = 64 * WAVES;
     static constexpr int COLS = N / 16;
-    static constexpr int NB_PER_WAVE = COLS / 32 / kTileWaves;
-    static constexpr int CHUNKS = N / 2 / kTileThreads;  // 16-byte copies per thread
+    static constexpr int CBLOCKS = COLS / 32;  // 32-column blocks
+    static constexpr int NB_PER_WAVE = CBLOCKS / WAVES;
+    static constexpr int CHUNKS = N / 2 / THREADS;  // 16-byte copies per thread
+    static constexpr int MAX_SUB = TB == 14 ? 7 : (WAVES == 4 ? 3 : kMaxTileSubBlocks);
+    static_assert(THREADS % 256 == 0 && THREADS <= 1024 && NB_PER_WAVE >= 1, "tile shape");
 };
 
 struct TileArgs {
@@ -49,6 +61,7 @@ struct TileArgs {
     int ubit[kMaxTileBits];            // tile bit -> global position
     int ext_pos[SV_MAX_QUBITS_C64];    // positions outside the tile, ascending
     int n_ext;
+    int n_sub;                         // blocks in this launch
     int tbit[kMaxTileSubBlocks][4];    // per block: its tile bits, ascending
 };
 
@@ -63,6 +76,13 @@ __device__ __forceinline__ uint32_t deposit(uint32_t v, uint32_t mask)
     }
     return r;
 }
+
+// LDS placement of tile index i: tile bits 5..8 are XORed into bits 1..4.
+// Bit 0 is kept, so the pair (2t, 2t + 1) stays one aligned 16-byte slot for
+// the HBM copies, and the map is linear over XOR: swz(a ^ b) = swz(a) ^
+// swz(b).  A block whose rows sit on the lowest tile bits would otherwise
+// read its 32 columns at a 128-byte stride, all in the same few banks.
+__device__ __forceinline__ uint32_t swz(uint32_t i) { return i ^ ((i >> 4) & 0x1Eu); }
 
 __device__ __forceinline__ uint64_t tile_base(uint64_t T, const TileArgs &a)
 {
@@ -82,275 +102,288 @@ __device__ __forceinline__ uint64_t global_off(uint32_t t, const TileArgs &a)
     return g;
 }
 
-template <int TB, int NSUB>
-__global__ void __launch_bounds__(kTileThreads) k_tile_pass(float *__restrict__ psi, const float *__restrict__ A,
-                                                            const TileArgs args)
+// Swizzled LDS index of complex row j (compile-time after unrolling) of a
+// block: the XOR of the per-row-bit values rb[0..3].
+__device__ __forceinline__ uint32_t row_of(const uint32_t *rb, int j)
 {
-    using C = TileCfg<TB>;
-    constexpr int kTileN = C::N;
-    constexpr int kNBPerWave = C::NB_PER_WAVE;
-    constexpr int kChunks = C::CHUNKS;
-    __shared__ float2 X[kTileN];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, w = tid >> 6;
-    const int half = lane >> 5, l32 = lane & 31;
+    uint32_t r = 0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+        if ((j >> b) & 1) r ^= rb[b];
+    return r;
+}
 
-    // A' of every block in registers: a[s][j] = A'_s[l32][2j + half]
-    float a[NSUB][16];
-#pragma unroll
-    for (int s = 0; s < NSUB; ++s)
-#pragma unroll
-        for (int j = 0; j < 16; ++j) a[s][j] = A[s * 1024 + l32 * 32 + 2 * j + half];
+// HBM <-> LDS copies of one tile: thread tid moves float4 slots
+// tid + i * THREADS, i.e. tile indices 2 * slot and 2 * slot + 1.
+template <int TB, int WAVES>
+struct TileCopy {
+    static constexpr int kChunks = TileCfg<TB, WAVES>::CHUNKS;
+    static constexpr int kThreads = TileCfg<TB, WAVES>::THREADS;
+    uint64_t g_lo;               // global offset of tile index 2 * tid
+    uint64_t g_hi[kChunks];      // uniform: offset of tile index 2 * i * THREADS
+    uint32_t lds_slot;           // swizzled float4 slot of tile index 2 * tid
 
-    // LDS offsets: row_off[s][j] (uniform) and this lane's column offsets
-    uint32_t col_off[NSUB][kNBPerWave];
-    uint32_t row_mask[NSUB];
+    __device__ __forceinline__ void init(const TileArgs &args, int tid)
+    {
+        g_lo = global_off<TB>(uint32_t(2 * tid), args);
 #pragma unroll
-    for (int s = 0; s < NSUB; ++s) {
+        for (int i = 0; i < kChunks; ++i) g_hi[i] = global_off<TB>(uint32_t(2 * i * kThreads), args);
+        // swz(2 f) / 2 = f ^ ((f >> 4) & 15); the chunk term only touches bits >= 8
+        lds_slot = uint32_t(tid) ^ ((uint32_t(tid) >> 4) & 15u);
+    }
+    __device__ __forceinline__ void load(vf4 *buf, const float *psi, uint64_t base) const
+    {
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) buf[i] = *reinterpret_cast<const vf4 *>(psi + 2 * (base + g_lo + g_hi[i]));
+    }
+    __device__ __forceinline__ void to_lds(vf4 *X4, const vf4 *buf) const
+    {
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) X4[lds_slot + i * kThreads] = buf[i];
+    }
+    __device__ __forceinline__ void store(float *psi, uint64_t base, const vf4 *X4) const
+    {
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i)
+            *reinterpret_cast<vf4 *>(psi + 2 * (base + g_lo + g_hi[i])) = X4[lds_slot + i * kThreads];
+    }
+};
+
+// Per-block data staged in LDS: the A operand and the swizzled column terms
+// (column c = 32 cb + l: cq[cb] ^ cl[l], with cq[cb] = swz(deposit(32 cb))
+// and cl[l] = swz(deposit(l)) over the block's column bits).
+template <int TB, int WAVES>
+struct TileShared {
+    using C = TileCfg<TB, WAVES>;
+    vf4 X4[C::N / 2];
+    uint32_t op[C::MAX_SUB][kOperandWords];
+    uint32_t cq[C::MAX_SUB][C::CBLOCKS];
+    uint32_t cl[C::MAX_SUB][32];
+};
+
+// Stage the operands and column tables of the launch's blocks.  FP32
+// operands are reordered so that lane (half, l32) finds A'[l32][2 j + half],
+// j = 0..15, as 16 consecutive words; split operands are copied as they are
+// (hi then lo, 32 x 32 bf16 each).
+template <int TB, int WAVES, bool SPLIT>
+__device__ __forceinline__ void stage_blocks(TileShared<TB, WAVES> &sh, const uint32_t *A, const TileArgs &args,
+                                             int tid)
+{
+    using C = TileCfg<TB, WAVES>;
+    const int nsub = args.n_sub;
+    for (int e = tid; e < nsub * kOperandWords; e += C::THREADS) {
+        const int s = e / kOperandWords, r = e % kOperandWords;
+        if (SPLIT) {
+            sh.op[s][r] = A[e];
+        } else {
+            const int lane = r / 16, j = r % 16;
+            sh.op[s][r] = A[s * kOperandWords + (lane & 31) * 32 + 2 * j + (lane >> 5)];
+        }
+    }
+    for (int e = tid; e < nsub * (C::CBLOCKS + 32); e += C::THREADS) {
+        const int s = e / (C::CBLOCKS + 32), r = e % (C::CBLOCKS + 32);
         uint32_t m = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) m |= 1u << args.tbit[s][i];
-        row_mask[s] = m;
-#pragma unroll
-        for (int q = 0; q < kNBPerWave; ++q)
-            col_off[s][q] = deposit(uint32_t((w * kNBPerWave + q) * 32 + l32), (kTileN - 1) & ~m);
-    }
-
-    // copy offsets: chunk i of this thread covers tile index t = 2*(tid + i*kTileThreads)
-    uint64_t g_lo = global_off<TB>(uint32_t(2 * tid), args);
-    uint64_t g_hi[kChunks];
-#pragma unroll
-    for (int i = 0; i < kChunks; ++i) g_hi[i] = global_off<TB>(uint32_t(2 * i * kTileThreads), args);
-
-    uint64_t T = blockIdx.x;
-    float4 buf[kChunks];
-    if (T < args.n_tiles) {
-        const uint64_t base = tile_base(T, args) + g_lo;
-#pragma unroll
-        for (int i = 0; i < kChunks; ++i) buf[i] = *reinterpret_cast<const float4 *>(psi + 2 * (base + g_hi[i]));
-    }
-    for (; T < args.n_tiles; T += gridDim.x) {
-        const uint64_t base = tile_base(T, args) + g_lo;
-#pragma unroll
-        for (int i = 0; i < kChunks; ++i)
-            reinterpret_cast<float4 *>(X)[tid + i * kTileThreads] = buf[i];
-        __syncthreads();
-        const uint64_t Tn = T + gridDim.x;
-        if (Tn < args.n_tiles) {
-            const uint64_t nbase = tile_base(Tn, args) + g_lo;
-#pragma unroll
-            for (int i = 0; i < kChunks; ++i) buf[i] = *reinterpret_cast<const float4 *>(psi + 2 * (nbase + g_hi[i]));
-        }
-        const float *Xf = reinterpret_cast<const float *>(X);
-#pragma unroll
-        for (int s = 0; s < NSUB; ++s) {
-            uint32_t row_off[16];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) row_off[j] = deposit(uint32_t(j), row_mask[s]);
-            // the wave's column blocks run as independent MFMA chains (ILP)
-            f32x16 acc[kNBPerWave];
-#pragma unroll
-            for (int q = 0; q < kNBPerWave; ++q)
-#pragma unroll
-                for (int v = 0; v < 16; ++v) acc[q][v] = 0.f;
-#pragma unroll
-            for (int j = 0; j < 16; ++j)
-#pragma unroll
-                for (int q = 0; q < kNBPerWave; ++q)
-                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s][j], Xf[2 * (row_off[j] + col_off[s][q]) + half],
-                                                                  acc[q], 0, 0, 0);
-            // D real row = 8*(v/4) + 4*half + v%4; complex row = real row / 2
-#pragma unroll
-            for (int q = 0; q < kNBPerWave; ++q) {
-                const uint32_t co = col_off[s][q];
-#pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const int r0 = 4 * g + 2 * half;
-                    X[row_off[r0] + co] = make_float2(acc[q][4 * g + 0], acc[q][4 * g + 1]);
-                    X[row_off[r0 + 1] + co] = make_float2(acc[q][4 * g + 2], acc[q][4 * g + 3]);
-                }
-            }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int i = 0; i < kChunks; ++i)
-            *reinterpret_cast<float4 *>(psi + 2 * (base + g_hi[i])) = reinterpret_cast<const float4 *>(X)[tid + i * kTileThreads];
-        __syncthreads();
+        for (int b = 0; b < 4; ++b) m |= 1u << args.tbit[s][b];
+        const uint32_t cmask = ((1u << TB) - 1) & ~m;
+        if (r < C::CBLOCKS)
+            sh.cq[s][r] = swz(deposit(uint32_t(r * 32), cmask));
+        else
+            sh.cl[s][r - C::CBLOCKS] = swz(deposit(uint32_t(r - C::CBLOCKS), cmask));
     }
 }
 
-
-// Split-BF16 variant: A' = Ah + Al (bf16, from the host), each B operand
-// (8 consecutive K values = 4 complex rows of one column) is split while it
-// is read from LDS (v_cvt_pk_bf16_f32), and Ah Xh + Ah Xl + Al Xh run on
-// v_mfma_f32_32x32x16_bf16 with FP32 accumulation (the Al Xl term, ~2^-16
-// relative, is dropped).  Everything else is as in k_tile_pass.
-template <int TB, int NSUB>
-__global__ void __launch_bounds__(kTileThreads) k_tile_pass_bf16(float *__restrict__ psi,
-                                                                 const uint16_t *__restrict__ A,
-                                                                 const TileArgs args)
+__device__ __forceinline__ void lds_st(char *Xb, uint32_t byte_off, float re, float im)
 {
-    using C = TileCfg<TB>;
-    constexpr int kTileN = C::N;
-    constexpr int kNBPerWave = C::NB_PER_WAVE;
-    constexpr int kChunks = C::CHUNKS;
-    __shared__ float2 X[kTileN];
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, w = tid >> 6;
-    const int half = lane >> 5, l32 = lane & 31;
+    vf2 v;
+    v.x = re;
+    v.y = im;
+    *reinterpret_cast<vf2 *>(Xb + byte_off) = v;
+}
 
-    // A' hi / lo: step i (K = 16 i .. 16 i + 15), lane holds A'[l32][16 i + 8 half + e]
-    uint4 ah[NSUB][2], al[NSUB][2];
+// One block of the pass on the tile in LDS.  D real row = 8 (v / 4) + 4 half
+// + v % 4: acc[4 g + 2 e] and acc[4 g + 2 e + 1] are (re, im) of complex row
+// 4 g + 2 half + e.  Each wave owns its columns, so its reads of the block
+// precede its writes; the caller places the barrier.
+template <int TB, int WAVES, bool SPLIT>
+__device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const TileArgs &args, int s, int w, int half,
+                                            int l32)
+{
+    using C = TileCfg<TB, WAVES>;
+    constexpr int NBW = C::NB_PER_WAVE;
+    char *Xb = reinterpret_cast<char *>(sh.X4);
+    uint32_t rb[4];
 #pragma unroll
-    for (int s = 0; s < NSUB; ++s)
+    for (int b = 0; b < 4; ++b) rb[b] = swz(1u << args.tbit[s][b]);
+    const uint32_t cl = sh.cl[s][l32];
+    uint32_t lq[NBW], wq[NBW];  // lane byte terms of this lane's column in block q
+#pragma unroll
+    for (int q = 0; q < NBW; ++q) {
+        const uint32_t col = cl ^ sh.cq[s][w * NBW + q];
+        // B rows: FP32 2j + half (re | im of complex row j); split 8i + 4 half + t
+        lq[q] = SPLIT ? (col ^ (half ? rb[2] : 0u)) << 3 : (col << 3) | uint32_t(half << 2);
+        wq[q] = (col ^ (half ? rb[1] : 0u)) << 3;  // complex row bit 1 = half
+    }
+    f32x16 acc[NBW];
+#pragma unroll
+    for (int q = 0; q < NBW; ++q)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[q][v] = 0.f;
+    if (!SPLIT) {
+        const vf4 *ap = reinterpret_cast<const vf4 *>(&sh.op[s][(half * 32 + l32) * 16]);
+        float a[16];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const vf4 v = ap[i];
+            a[4 * i] = v.x;
+            a[4 * i + 1] = v.y;
+            a[4 * i + 2] = v.z;
+            a[4 * i + 3] = v.w;
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+#pragma unroll
+            for (int q = 0; q < NBW; ++q) {
+                const float b = *reinterpret_cast<const float *>(Xb + ((row_of(rb, j) << 3) ^ lq[q]));
+                acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j], b, acc[q], 0, 0, 0);
+            }
+    } else {
+        // A' hi / lo: step i (K = 16 i .. 16 i + 15), lane holds A'[l32][16 i + 8 half + e]
+        const uint16_t *op = reinterpret_cast<const uint16_t *>(sh.op[s]);
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-            const int off = s * 2048 + l32 * 32 + 16 * i + 8 * half;
-            ah[s][i] = *reinterpret_cast<const uint4 *>(A + off);
-            al[s][i] = *reinterpret_cast<const uint4 *>(A + off + 1024);
+            bf16x8 xah, xal;
+            __builtin_memcpy(&xah, op + l32 * 32 + 16 * i + 8 * half, 16);
+            __builtin_memcpy(&xal, op + 1024 + l32 * 32 + 16 * i + 8 * half, 16);
+#pragma unroll
+            for (int q = 0; q < NBW; ++q) {
+                bf16x8 bh, bl;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const vf2 v = *reinterpret_cast<const vf2 *>(Xb + ((row_of(rb, 8 * i + t) << 3) ^ lq[q]));
+                    const __bf16 hr = (__bf16)v.x, hi = (__bf16)v.y;
+                    bh[2 * t] = hr;
+                    bh[2 * t + 1] = hi;
+                    bl[2 * t] = (__bf16)(v.x - (float)hr);
+                    bl[2 * t + 1] = (__bf16)(v.y - (float)hi);
+                }
+                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah, bh, acc[q], 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah, bl, acc[q], 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xal, bh, acc[q], 0, 0, 0);
+            }
         }
-
-    uint32_t col_off[NSUB][kNBPerWave];
-    uint32_t row_mask[NSUB];
-#pragma unroll
-    for (int s = 0; s < NSUB; ++s) {
-        uint32_t m = 0;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) m |= 1u << args.tbit[s][i];
-        row_mask[s] = m;
-#pragma unroll
-        for (int q = 0; q < kNBPerWave; ++q)
-            col_off[s][q] = deposit(uint32_t((w * kNBPerWave + q) * 32 + l32), (kTileN - 1) & ~m);
     }
-    uint64_t g_lo = global_off<TB>(uint32_t(2 * tid), args);
-    uint64_t g_hi[kChunks];
 #pragma unroll
-    for (int i = 0; i < kChunks; ++i) g_hi[i] = global_off<TB>(uint32_t(2 * i * kTileThreads), args);
+    for (int q = 0; q < NBW; ++q)
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int e = 0; e < 2; ++e)
+                lds_st(Xb, (row_of(rb, 4 * g + e) << 3) ^ wq[q], acc[q][4 * g + 2 * e], acc[q][4 * g + 2 * e + 1]);
+}
+
+// FP32 (SPLIT = false): A = 32 x 32 FP32 real-form operands, back to back.
+// Split BF16 (SPLIT = true): A' = Ah + Al (bf16 from the host, hi then lo);
+// each B operand (8 consecutive K values = 4 complex rows of one column) is
+// split while it is read from LDS (v_cvt_pk_bf16_f32), and Ah Xh + Ah Xl +
+// Al Xh run on v_mfma_f32_32x32x16_bf16 with FP32 accumulation (the Al Xl
+// term, ~2^-16 relative, is dropped).
+template <int TB, int WAVES, bool SPLIT>
+__global__ void __launch_bounds__(64 * WAVES) k_tile_pass(float *__restrict__ psi, const uint32_t *__restrict__ A,
+                                                          const TileArgs args)
+{
+    using C = TileCfg<TB, WAVES>;
+    __shared__ TileShared<TB, WAVES> sh;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int half = lane >> 5, l32 = lane & 31;
+
+    stage_blocks<TB, WAVES, SPLIT>(sh, A, args, tid);
+    TileCopy<TB, WAVES> cp;
+    cp.init(args, tid);
 
     uint64_t T = blockIdx.x;
-    float4 buf[kChunks];
-    if (T < args.n_tiles) {
-        const uint64_t base = tile_base(T, args) + g_lo;
-#pragma unroll
-        for (int i = 0; i < kChunks; ++i) buf[i] = *reinterpret_cast<const float4 *>(psi + 2 * (base + g_hi[i]));
-    }
+    vf4 buf[C::CHUNKS];
+    if (T < args.n_tiles) cp.load(buf, psi, tile_base(T, args));
     for (; T < args.n_tiles; T += gridDim.x) {
-        const uint64_t base = tile_base(T, args) + g_lo;
-#pragma unroll
-        for (int i = 0; i < kChunks; ++i)
-            reinterpret_cast<float4 *>(X)[tid + i * kTileThreads] = buf[i];
-        __syncthreads();
+        const uint64_t base = tile_base(T, args);
+        cp.to_lds(sh.X4, buf);
+        __syncthreads();  // the first one also publishes the staged blocks
         const uint64_t Tn = T + gridDim.x;
-        if (Tn < args.n_tiles) {
-            const uint64_t nbase = tile_base(Tn, args) + g_lo;
-#pragma unroll
-            for (int i = 0; i < kChunks; ++i) buf[i] = *reinterpret_cast<const float4 *>(psi + 2 * (nbase + g_hi[i]));
-        }
-#pragma unroll
-        for (int s = 0; s < NSUB; ++s) {
-            uint32_t row_off[16];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) row_off[j] = deposit(uint32_t(j), row_mask[s]);
-            f32x16 acc[kNBPerWave];
-#pragma unroll
-            for (int q = 0; q < kNBPerWave; ++q)
-#pragma unroll
-                for (int v = 0; v < 16; ++v) acc[q][v] = 0.f;
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                bf16x8 xah, xal;
-                __builtin_memcpy(&xah, &ah[s][i], 16);
-                __builtin_memcpy(&xal, &al[s][i], 16);
-#pragma unroll
-                for (int q = 0; q < kNBPerWave; ++q) {
-                    bf16x8 bh, bl;
-#pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        // complex row 8 i + 4 half + t of this lane's column
-                        const uint32_t r = half ? row_off[8 * i + 4 + t] : row_off[8 * i + t];
-                        const float2 v = X[r + col_off[s][q]];
-                        const __bf16 hr = (__bf16)v.x, hi = (__bf16)v.y;
-                        bh[2 * t] = hr;
-                        bh[2 * t + 1] = hi;
-                        bl[2 * t] = (__bf16)(v.x - (float)hr);
-                        bl[2 * t + 1] = (__bf16)(v.y - (float)hi);
-                    }
-                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah, bh, acc[q], 0, 0, 0);
-                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah, bl, acc[q], 0, 0, 0);
-                    acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xal, bh, acc[q], 0, 0, 0);
-                }
-            }
-            // each wave owns its columns: its reads precede its writes
-#pragma unroll
-            for (int q = 0; q < kNBPerWave; ++q) {
-                const uint32_t co = col_off[s][q];
-#pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    const int r0 = 4 * g + 2 * half;
-                    X[row_off[r0] + co] = make_float2(acc[q][4 * g + 0], acc[q][4 * g + 1]);
-                    X[row_off[r0 + 1] + co] = make_float2(acc[q][4 * g + 2], acc[q][4 * g + 3]);
-                }
-            }
+        if (Tn < args.n_tiles) cp.load(buf, psi, tile_base(Tn, args));
+        for (int s = 0; s < args.n_sub; ++s) {
+            apply_block<TB, WAVES, SPLIT>(sh, args, s, w, half, l32);
             __syncthreads();
         }
-#pragma unroll
-        for (int i = 0; i < kChunks; ++i)
-            *reinterpret_cast<float4 *>(psi + 2 * (base + g_hi[i])) = reinterpret_cast<const float4 *>(X)[tid + i * kTileThreads];
+        cp.store(psi, base, sh.X4);
         __syncthreads();
     }
 }
 
-template <int TB, int NSUB>
+template <int TB, int WAVES>
 hipError_t tile_launch(const TileArgs &a, const void *d_a, bool split, float *psi, hipStream_t st, int cap)
 {
     uint64_t g = a.n_tiles;
     if (cap > 0 && g > uint64_t(cap)) g = cap;
+    const uint32_t *A = static_cast<const uint32_t *>(d_a);
     if (split)
-        hipLaunchKernelGGL((k_tile_pass_bf16<TB, NSUB>), dim3(unsigned(g)), dim3(kTileThreads), 0, st, psi,
-                           static_cast<const uint16_t *>(d_a), a);
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, true>), dim3(unsigned(g)), dim3(64 * WAVES), 0, st, psi, A, a);
     else
-        hipLaunchKernelGGL((k_tile_pass<TB, NSUB>), dim3(unsigned(g)), dim3(kTileThreads), 0, st, psi,
-                           static_cast<const float *>(d_a), a);
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, false>), dim3(unsigned(g)), dim3(64 * WAVES), 0, st, psi, A, a);
     return hipGetLastError();
-}
-
-template <int TB>
-hipError_t tile_dispatch(int n_sub, const TileArgs &a, const void *d_a, bool split, float *psi, hipStream_t st, int cap)
-{
-    switch (n_sub) {
-    case 1: return tile_launch<TB, 1>(a, d_a, split, psi, st, cap);
-    case 2: return tile_launch<TB, 2>(a, d_a, split, psi, st, cap);
-    case 3: return tile_launch<TB, 3>(a, d_a, split, psi, st, cap);
-    case 4: return tile_launch<TB, 4>(a, d_a, split, psi, st, cap);
-    default: return hipErrorInvalidValue;
-    }
 }
 
 }  // namespace
 
 bool tile_supported(int n, int union_bits) { return n >= kMinTileQubits && union_bits <= kMaxTileUnion; }
 
+bool tile_shape_supported(int tile_bits, int waves)
+{
+    return (tile_bits == 14 && (waves == 8 || waves == 16)) || (tile_bits == 13 && (waves == 4 || waves == 8));
+}
+
+int tile_wgs_per_cu(int tile_bits, int waves)
+{
+    // LDS: a 64 KiB tile leaves room for a second workgroup; registers: two
+    // 8-wave workgroups would need <= 128 VGPRs per lane
+    return tile_bits == 13 && waves == 4 ? 2 : 1;
+}
+
+int tile_max_blocks(int tile_bits, int waves)
+{
+    if (!tile_shape_supported(tile_bits, waves)) return 0;
+    if (tile_bits == 14) return waves == 16 ? TileCfg<14, 16>::MAX_SUB : TileCfg<14, 8>::MAX_SUB;
+    return waves == 4 ? TileCfg<13, 4>::MAX_SUB : TileCfg<13, 8>::MAX_SUB;
+}
+
 hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a, bool split_bf16, void *psi, int n,
-                            hipStream_t st, int grid_cap, int tile_bits)
+                            hipStream_t st, int grid_cap, int tile_bits, int waves)
 {
     const int kTileBits = tile_bits;
-    if (tile_bits != 13 && tile_bits != 14) return hipErrorInvalidValue;
-    if (n_sub < 1 || n_sub > kMaxTileSubBlocks || n < kTileBits) return hipErrorInvalidValue;
+    if (!tile_shape_supported(tile_bits, waves)) return hipErrorInvalidValue;
+    if (n_sub < 1 || n_sub > tile_max_blocks(tile_bits, waves) || n < kTileBits) return hipErrorInvalidValue;
     TileArgs a;
     std::memset(&a, 0, sizeof a);
     uint64_t umask = 0;
     for (int s = 0; s < n_sub; ++s)
-        for (int i = 0; i < 4; ++i) umask |= uint64_t(1) << sub_pos[s][i];
+        for (int i = 0; i < 4; ++i) {
+            // row bit i of block s is its i-th lowest position
+            if (sub_pos[s][i] < 0 || sub_pos[s][i] >= n || (i && sub_pos[s][i] <= sub_pos[s][i - 1]))
+                return hipErrorInvalidValue;
+            umask |= uint64_t(1) << sub_pos[s][i];
+        }
     const int nu = __builtin_popcountll(umask);
     if (nu > kMaxTileUnion) return hipErrorInvalidValue;
     // tile positions: the union plus the lowest positions outside it
     uint64_t tmask = umask;
     for (int p = 0; p < n && __builtin_popcountll(tmask) < kTileBits; ++p) tmask |= uint64_t(1) << p;
+    if (!(tmask & 1)) return hipErrorInvalidValue;  // unreachable: position 0 always joins
     int b = 0;
     for (int p = 0; p < n; ++p) {
         if ((tmask >> p) & 1) a.ubit[b++] = p;
         else a.ext_pos[a.n_ext++] = p;
     }
+    a.n_sub = n_sub;
     for (int s = 0; s < n_sub; ++s)
         for (int i = 0; i < 4; ++i) {
             int t = 0;
@@ -359,8 +392,11 @@ hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a,
         }
     a.n_tiles = uint64_t(1) << (n - kTileBits);
     float *p = static_cast<float *>(psi);
-    return tile_bits == 13 ? tile_dispatch<13>(n_sub, a, d_a, split_bf16, p, st, grid_cap)
-                           : tile_dispatch<14>(n_sub, a, d_a, split_bf16, p, st, grid_cap);
+    if (tile_bits == 14)
+        return waves == 16 ? tile_launch<14, 16>(a, d_a, split_bf16, p, st, grid_cap)
+                           : tile_launch<14, 8>(a, d_a, split_bf16, p, st, grid_cap);
+    return waves == 4 ? tile_launch<13, 4>(a, d_a, split_bf16, p, st, grid_cap)
+                      : tile_launch<13, 8>(a, d_a, split_bf16, p, st, grid_cap);
 }
 
 }  // namespace dev

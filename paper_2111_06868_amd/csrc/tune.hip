@@ -232,11 +232,27 @@ extern "C" int sv_autotune(sv_state *s, int precision, double *cost_ms)
         }
         if (k == 4 && s->dtype == SV_C64 && precision == SV_PREC_FP32) best_tuning.k4_reg = bc.path == PATH_REG;
     }
-    double tile_ms[5] = {0, 0, 0, 0, 0};
+    double tile_ms[kTilePassMaxBlocks + 1] = {0};
     const bool tiles = !rc && s->dtype == SV_C64 && dev::tile_supported(s->n, 8);
     if (tiles) {
         tuning() = best_tuning;
         const Path tp = precision == SV_PREC_FP32 ? PATH_TILE : PATH_TILE_BF16;
+        // tile shape: the fastest pass of 4 blocks
+        const int shapes[][2] = {{14, 8}, {14, 16}, {13, 4}, {13, 8}};
+        double best_shape = 1e30;
+        for (const auto &sh : shapes) {
+            if (rc || !dev::tile_shape_supported(sh[0], sh[1]) || s->n < sh[0]) continue;
+            tuning().tile_bits = sh[0];
+            tuning().tile_waves = sh[1];
+            double ms = 0;
+            rc = time_tile(s, tp, 4, reps, &ms);
+            if (!rc && ms < best_shape) {
+                best_shape = ms;
+                best_tuning.tile_bits = sh[0];
+                best_tuning.tile_waves = sh[1];
+            }
+        }
+        tuning() = best_tuning;
         for (int nsub = 1; nsub <= dev::kMaxTileSubBlocks && !rc; ++nsub) rc = time_tile(s, tp, nsub, reps, &tile_ms[nsub]);
     }
     timing_suspend(false);
@@ -255,5 +271,16 @@ extern "C" int sv_set_cost_table(int n, int precision, const double *cost_ms)
     for (int k = 1; k <= SV_MAX_K; ++k)
         if (!(cost_ms[k] > 0) || !std::isfinite(cost_ms[k])) return fail(SV_ERR_ARG, "cost_ms[%d] must be positive", k);
     store_costs(n, precision, cost_ms);
+    return SV_OK;
+}
+
+extern "C" int sv_set_tile_shape(int tile_bits, int waves)
+{
+    clear_error();
+    if (!dev::tile_shape_supported(tile_bits, waves))
+        return fail(SV_ERR_ARG, "tile shape (%d bits, %d waves) is not one of (14, 8), (14, 16), (13, 4), (13, 8)",
+                    tile_bits, waves);
+    tuning().tile_bits = tile_bits;
+    tuning().tile_waves = waves;
     return SV_OK;
 }

@@ -198,3 +198,70 @@ def test_auto_rule_picks_a_valid_plan():
     n30, g30 = wc.config_circuit(1)
     p30 = sv.fuse(to_binding(g30), n30, -1, sv.RULE_AUTO)
     assert p30.rule == sv.RULE_TILED and p30.max_k <= 4
+
+
+def test_tile_shape_validation():
+    """Only the compiled tile shapes are accepted; the call launches nothing."""
+    for shape in sv.TILE_SHAPES:
+        sv.set_tile_shape(*shape)
+    sv.set_tile_shape(14, 8)
+    for bad in ((14, 4), (12, 8), (13, 2), (15, 8), (13, 16), (14, 32)):
+        with pytest.raises(ValueError):
+            sv.set_tile_shape(*bad)
+
+
+def _valid_order(gates, order):
+    """Every qubit's gates appear in circuit order (so the product is kept)."""
+    last = {}
+    for gi in order:
+        for q in gates[gi].qubits:
+            if last.get(q, -1) > gi:
+                return False
+            last[q] = gi
+    return True
+
+
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_tiled_plan_structure(cfg):
+    """SV_RULE_TILED: passes of <= 8 positions made of blocks of <= 4 qubits,
+    consecutive, with every gate once and each qubit's gates in order."""
+    n, gates = wc.config_circuit(cfg)
+    plan = sv.fuse(to_binding(gates), n, 4, sv.RULE_TILED)
+    blocks = plan.blocks(False)
+    order = [i for b in blocks for i in b.members]
+    assert sorted(order) == list(range(len(gates)))
+    assert _valid_order(gates, order)
+    passes = {}
+    prev = None
+    for b in blocks:
+        assert len(b.qubits) <= 4
+        if b.tile_pass >= 0:
+            assert b.tile_pass not in passes or prev == b.tile_pass  # consecutive
+            passes.setdefault(b.tile_pass, set()).update(b.qubits)
+        prev = b.tile_pass
+    assert passes and all(len(u) <= 8 for u in passes.values())
+    n_launch = len(passes) + sum(1 for b in blocks if b.tile_pass < 0)
+    # far fewer state passes than blocks (30 q: 35 passes for 845 gates)
+    assert n_launch <= len(blocks) // 2
+
+
+@pytest.mark.parametrize("rule", [sv.RULE_TILED, sv.RULE_ENHANCED])
+def test_frontier_plans_equal_circuit_unitary(rule):
+    rng = np.random.default_rng(31)
+    for n in (6, 8):
+        gates = wc.random_gate_list(n, 50, rng, max_k=2)
+        U = brute.circuit_unitary(n, [(ref.matrix_of(g), g.qubits) for g in gates])
+        for k in (2, 3, 4):
+            blocks = sv.fuse(to_binding(gates), n, k, rule).blocks()
+            assert _valid_order(gates, [i for b in blocks for i in b.members])
+            V = brute.circuit_unitary(n, [(b.matrix, b.qubits) for b in blocks])
+            assert np.max(np.abs(V - U)) <= 1e-12
+
+
+def test_enhanced_rule_frontier_counts():
+    """The enhanced rule keeps the cheaper of its two candidate plans; on the
+    30-qubit workload the frontier plan wins for k >= 4."""
+    n, gates = wc.config_circuit(1)
+    got = [len(sv.fuse(to_binding(gates), n, k, sv.RULE_ENHANCED)) for k in (4, 5, 6)]
+    paper = [len(sv.fuse(to_binding(gates), n, k, sv.RULE_PAPER)) for k in (4, 5, 6)]
+    assert all(g < p for g, p in zip(got, paper)), (got, paper)

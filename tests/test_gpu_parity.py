@@ -324,6 +324,33 @@ def test_tiled_passes_split_bf16(n):
     assert fe <= FID_C64
 
 
+@pytest.mark.parametrize("shape", [(14, 8), (14, 16), (13, 4), (13, 8)])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("n", [14, 16])
+def test_tiled_passes_every_shape(shape, precision, n):
+    """Each tile launch shape (tile bits, waves per workgroup) against the oracle."""
+    rng = np.random.default_rng(900 + n + shape[0] + shape[1])
+    gates = wc.random_gate_list(n, 10 * n, rng, max_k=2)
+    prec = sv.PREC_FP32 if precision == "fp32" else sv.PREC_SPLIT_BF16
+    fam = "tile" if precision == "fp32" else "tile_bf16"
+    sv.set_tile_shape(*shape)
+    sv.stats_reset()
+    sv.stats_enable(True)
+    try:
+        want, got, st = run_both(n, gates, "+", "c64", max_k=4, rule=sv.RULE_TILED, precision=prec)
+        st.synchronize()
+        tiles = sum(sv.stats_query(fam, s)[0] for s in range(1, 5))
+    finally:
+        sv.stats_enable(False)
+        sv.stats_reset()
+        sv.set_tile_shape(14, 8)
+    fe, ma = _report("tiled %s shape=%s n=%d (%d tile passes)" % (precision, shape, n, tiles), want, got)
+    assert tiles > 0
+    assert fe <= FID_C64
+    if precision == "fp32":
+        assert ma <= 1e-5
+
+
 def test_c0_tiled():
     n, gates = wc.config_circuit(0)
     want, got, _ = run_both(n, gates, "0", "c64", max_k=4, rule=sv.RULE_TILED)
