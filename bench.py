@@ -92,9 +92,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--max-k", type=int, default=5)
-    ap.add_argument("--rule", default="enhanced", choices=["paper", "enhanced", "tiled", "auto"])
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--max-k", type=int, default=4)
+    ap.add_argument("--rule", default="tiled", choices=["paper", "enhanced", "tiled", "auto"])
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--config", type=int, default=1, choices=[1, 2])
     ap.add_argument("--workload", default="circuit", choices=["circuit", "gradient", "trajectories"],
                     help="circuit: the grid random circuit (default); gradient: 20-qubit ansatz "
@@ -283,7 +283,8 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32", "bf16": "bf16 hi+lo split, f32 accumulate",
+                  "fp16": "f16 hi+lo split, f32 accumulate"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "grid random circuit %s, %d qubits, %d gates, complex64, fused k<=%d (%s rule, %s)"
                    % ({1: "5x6 depth 20 seed 1", 2: "4x8 depth 14 seed 2"}[args.config], n, G, args.max_k,

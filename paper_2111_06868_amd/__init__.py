@@ -469,6 +469,7 @@ def set_cost_table(n: int, precision: int, cost) -> None:
 
 
 TILE_SHAPES = ((14, 8), (14, 16), (13, 4), (13, 8))
+MAX_TILE_LAUNCH_BLOCKS = 16  # blocks one tile-pass launch can hold (stats classes k = 1..16)
 
 
 def set_tile_shape(tile_bits: int, waves: int) -> None:

@@ -11,11 +11,13 @@
 //     persistent workgroup takes trajectories in turn, applies every fused
 //     block of it in LDS, reduces <Z_0> in FP64 and writes the final state
 //     out once.  No HBM traffic per gate.
-//   * LARGE trajectories (n >= 14) advance in lock step: launch s applies
-//     block s of every large trajectory that has one; the launch's
-//     workgroups are laid out from a precomputed (block, first group) table,
-//     so trajectories of different sizes share one grid.  A final launch
-//     reduces <Z_0> (one workgroup per trajectory, fixed order, FP64).
+//   * LARGE trajectories (n >= 14) are planned with the tiled rule (passes of
+//     several <= 4-qubit blocks, one read and one write of the state each)
+//     and advance in lock step: launch s runs pass s of every large
+//     trajectory that has one, as tile ranges of a shared grid (one tile
+//     kernel, per-pass layouts and operands read from device tables).  <Z_0>
+//     is then reduced in fixed-size chunks and summed per trajectory in a
+//     fixed order (FP64).
 //   * the small-trajectory kernel and the large-trajectory chain are
 //     independent and are captured on two forked streams, so they overlap.
 // The fusion limit is chosen per batch: with max_k = -1 the batch is timed
@@ -34,7 +36,7 @@ namespace {
 
 constexpr int kSmallMaxN = 13;
 constexpr int kThreads = 256;
-constexpr int kGroupsPerThread = 4;
+constexpr int kZ0ChunkBits = 16;  // amplitudes per <Z_0> partial sum (2^16)
 
 struct BBlock {
     uint64_t state_off;  // complex elements from the start of the batch buffer
@@ -55,16 +57,18 @@ struct BSmall {
     int32_t out;
 };
 
-struct BItem {
-    int32_t block;
-    int32_t pad;
-    uint64_t group0;
-};
-
 struct BLarge {
     uint64_t state_off;
     int32_t n;
     int32_t out;
+    int32_t zfirst;  // first <Z_0> chunk of the trajectory
+    int32_t zcount;  // its number of chunks
+};
+
+struct BZUnit {
+    uint64_t off;    // complex elements from the start of the batch buffer (even)
+    uint32_t count;
+    uint32_t pad;
 };
 
 __device__ __forceinline__ uint64_t ins0b(uint64_t x, int p)
@@ -120,94 +124,6 @@ __device__ __forceinline__ void apply_group_k(float2 *st, const BBlock &b, const
     case 4: apply_group<4>(st, b, m, g); break;
     case 5: apply_group<5>(st, b, m, g); break;
     default: apply_group<6>(st, b, m, g); break;
-    }
-}
-
-// Chunked application for large states (the layout of the register kernel):
-// the thread owns 4 consecutive amplitudes for every combination of the
-// block's high targets (positions >= 2); targets at positions 0 / 1 (LM) are
-// inside the chunk.  Chunk group g has its base at insert_zeros(g << 2, hp).
-template <int K, int LM>
-__device__ __forceinline__ void apply_chunk(float2 *__restrict__ st, const BBlock &b, const float2 *__restrict__ m,
-                                            uint64_t g)
-{
-    constexpr int KL = (LM & 1) + ((LM >> 1) & 1);
-    constexpr int KH = K - KL;
-    constexpr int NH = 1 << KH;
-    constexpr int D = 1 << K;
-    uint64_t base = g << 2;
-#pragma unroll
-    for (int j = 0; j < KH; ++j) base = ins0b(base, b.hp[j]);
-    float re[NH][4], im[NH][4];
-#pragma unroll
-    for (int h = 0; h < NH; ++h) {
-        uint64_t o = base;
-#pragma unroll
-        for (int j = 0; j < KH; ++j)
-            if ((h >> j) & 1) o += uint64_t(1) << b.hp[j];
-        const float4 *p = reinterpret_cast<const float4 *>(st + o);
-        const float4 u = p[0], v = p[1];
-        re[h][0] = u.x; im[h][0] = u.y; re[h][1] = u.z; im[h][1] = u.w;
-        re[h][2] = v.x; im[h][2] = v.y; re[h][3] = v.z; im[h][3] = v.w;
-    }
-#pragma unroll
-    for (int f = 0; f < 4; ++f) {
-        if (f & LM) continue;
-        float vr[D], vi[D];
-#pragma unroll
-        for (int mm = 0; mm < D; ++mm) {
-            const int l = f | (LM == 0 ? 0 : LM == 1 ? (mm & 1) : LM == 2 ? ((mm & 1) << 1) : (mm & 3));
-            vr[mm] = re[mm >> KL][l];
-            vi[mm] = im[mm >> KL][l];
-        }
-#pragma unroll
-        for (int mm = 0; mm < D; ++mm) {
-            float sr = 0.f, si = 0.f;
-#pragma unroll
-            for (int mp = 0; mp < D; ++mp) {
-                const float2 a = m[mm * D + mp];
-                sr = fmaf(a.x, vr[mp], sr);
-                sr = fmaf(-a.y, vi[mp], sr);
-                si = fmaf(a.x, vi[mp], si);
-                si = fmaf(a.y, vr[mp], si);
-            }
-            const int l = f | (LM == 0 ? 0 : LM == 1 ? (mm & 1) : LM == 2 ? ((mm & 1) << 1) : (mm & 3));
-            re[mm >> KL][l] = sr;
-            im[mm >> KL][l] = si;
-        }
-    }
-#pragma unroll
-    for (int h = 0; h < NH; ++h) {
-        uint64_t o = base;
-#pragma unroll
-        for (int j = 0; j < KH; ++j)
-            if ((h >> j) & 1) o += uint64_t(1) << b.hp[j];
-        float4 *p = reinterpret_cast<float4 *>(st + o);
-        p[0] = make_float4(re[h][0], im[h][0], re[h][1], im[h][1]);
-        p[1] = make_float4(re[h][2], im[h][2], re[h][3], im[h][3]);
-    }
-}
-
-template <int K>
-__device__ __forceinline__ void apply_chunk_lm(float2 *st, const BBlock &b, const float2 *m, uint64_t g)
-{
-    switch (b.lm) {
-    case 0: apply_chunk<K, 0>(st, b, m, g); break;
-    case 1: apply_chunk<K, 1>(st, b, m, g); break;
-    case 2: apply_chunk<K, 2>(st, b, m, g); break;
-    default:
-        if constexpr (K >= 2) apply_chunk<K, 3>(st, b, m, g);
-        break;
-    }
-}
-
-__device__ __forceinline__ void apply_chunk_k(float2 *st, const BBlock &b, const float2 *m, uint64_t g)
-{
-    switch (b.k) {
-    case 1: apply_chunk_lm<1>(st, b, m, g); break;
-    case 2: apply_chunk_lm<2>(st, b, m, g); break;
-    case 3: apply_chunk_lm<3>(st, b, m, g); break;
-    default: apply_chunk_lm<4>(st, b, m, g); break;
     }
 }
 
@@ -272,43 +188,34 @@ __global__ void k_batch_one(const BLarge *__restrict__ large, int n_large, float
     if (t < n_large) buf[large[t].state_off] = make_float2(1.f, 0.f);
 }
 
-__global__ void __launch_bounds__(kThreads) k_batch_step(const BItem *__restrict__ items,
-                                                         const BBlock *__restrict__ blocks,
-                                                         const float2 *__restrict__ mats, float2 *__restrict__ buf)
+// <Z_0> partial sums: one workgroup per chunk of one state (chunks start at
+// even indices, so the parity of the local index is that of the state index).
+__global__ void __launch_bounds__(kThreads) k_batch_z0_part(const BZUnit *__restrict__ units,
+                                                            const float2 *__restrict__ buf,
+                                                            double *__restrict__ partial)
 {
-    const BItem it = items[blockIdx.x];
-    const BBlock b = blocks[it.block];
-    float2 *st = buf + b.state_off;
-    const float2 *m = mats + b.mat_off;
-    if (b.k <= 4) {
-        const uint64_t groups = uint64_t(1) << (b.n - 2 - b.kh);
-        for (int j = 0; j < kGroupsPerThread; ++j) {
-            const uint64_t g = it.group0 + uint64_t(j) * kThreads + threadIdx.x;
-            if (g < groups) apply_chunk_k(st, b, m, g);
-        }
-        return;
-    }
-    const uint64_t groups = uint64_t(1) << (b.n - b.k);
-    for (int j = 0; j < kGroupsPerThread; ++j) {
-        const uint64_t g = it.group0 + uint64_t(j) * kThreads + threadIdx.x;
-        if (g < groups) apply_group_k(st, b, m, g);
-    }
-}
-
-__global__ void __launch_bounds__(kThreads) k_batch_z0(const BLarge *__restrict__ large, const float2 *__restrict__ buf,
-                                                       double *__restrict__ z0)
-{
-    const BLarge tr = large[blockIdx.x];
-    const uint64_t N = uint64_t(1) << tr.n;
-    const float2 *st = buf + tr.state_off;
+    const BZUnit u = units[blockIdx.x];
+    const float2 *st = buf + u.off;
     double acc = 0.0;
-    for (uint64_t i = threadIdx.x; i < N; i += kThreads) {
+    for (uint32_t i = threadIdx.x; i < u.count; i += kThreads) {
         const float2 v = st[i];
         const double p = double(v.x) * v.x + double(v.y) * v.y;
         acc += (i & 1) ? -p : p;
     }
     const double z = block_sum(acc);
-    if (threadIdx.x == 0) z0[tr.out] = z;
+    if (threadIdx.x == 0) partial[blockIdx.x] = z;
+}
+
+// Per trajectory: its partial sums in chunk order.
+__global__ void k_batch_z0_final(const BLarge *__restrict__ large, int n_large, const double *__restrict__ partial,
+                                 double *__restrict__ z0)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_large) return;
+    const BLarge tr = large[t];
+    double z = 0.0;
+    for (int c = 0; c < tr.zcount; ++c) z += partial[tr.zfirst + c];
+    z0[tr.out] = z;
 }
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -325,10 +232,11 @@ struct sv_batch {
     std::vector<int32_t> n_qubits;
     std::vector<uint64_t> state_off;  // complex elements
     // device tables
-    DevBuf d_blocks, d_mats, d_small, d_large, d_items, d_z0;
-    int n_small = 0, n_large = 0, small_max_n = 0;
+    DevBuf d_blocks, d_mats, d_small, d_large, d_z0;
+    DevBuf d_passes, d_units, d_pool, d_zunits, d_partial;
+    int n_small = 0, n_large = 0, small_max_n = 0, n_zunits = 0;
     uint64_t large_begin = 0, large_end = 0;
-    std::vector<std::pair<size_t, int>> steps;  // (offset into items, count)
+    std::vector<std::pair<size_t, int>> steps;  // per layer: (offset into units, count)
     PinBuf h_z0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -374,8 +282,12 @@ int build_schedule(sv_batch *b, const sv_batch_desc *d, int k)
     std::vector<float2> mats;
     std::vector<BSmall> small;
     std::vector<BLarge> large;
-    std::vector<std::vector<int>> large_blocks;  // per large trajectory: its block indices
+    std::vector<dev::TilePass> passes;
+    std::vector<float> pool;                     // FP32 real-form operands, 32 x 32 per block
+    std::vector<std::vector<int>> large_passes;  // per large trajectory: its pass indices
+    std::vector<BZUnit> zunits;
     const CostTable cost = default_costs();
+    const int max_sub = dev::tile_max_blocks(dev::kBatchTileBits, dev::kBatchTileWaves);
     for (int t = 0; t < d->n_traj; ++t) {
         const int n = d->n_qubits[t];
         const sv_gate *g = d->gates + d->gate_offsets[t];
@@ -383,51 +295,80 @@ int build_schedule(sv_batch *b, const sv_batch_desc *d, int k)
         int kk = k;
         for (int i = 0; i < G; ++i) kk = std::max(kk, g[i].k);
         kk = std::min(kk, n);
-        std::vector<Block> fb;
-        if (int rc = fuse_gates(g, G, n, kk, SV_RULE_ENHANCED, cost, fb)) return rc;
-        const int first = int(blocks.size());
-        std::vector<int> mine;
-        for (const Block &B : fb) {
-            BBlock x;
-            std::memset(&x, 0, sizeof x);
-            x.state_off = b->state_off[t];
-            x.n = n;
-            x.k = B.k;
-            for (int j = 0; j < B.k; ++j) x.q[j] = B.q[j];
-            x.mat_off = int(mats.size());
-            for (int j = 0; j < B.k; ++j) {
-                if (B.q[j] < 2) x.lm |= 1 << B.q[j];
-                else if (x.kh < 4) x.hp[x.kh++] = B.q[j];
-            }
-            for (const cd &v : B.m) mats.push_back(make_float2(float(v.real()), float(v.imag())));
-            mine.push_back(int(blocks.size()));
-            blocks.push_back(x);
-        }
         if (n <= kSmallMaxN) {
+            std::vector<Block> fb;
+            if (int rc = fuse_gates(g, G, n, kk, SV_RULE_ENHANCED, cost, fb)) return rc;
+            const int first = int(blocks.size());
+            for (const Block &B : fb) {
+                BBlock x;
+                std::memset(&x, 0, sizeof x);
+                x.state_off = b->state_off[t];
+                x.n = n;
+                x.k = B.k;
+                for (int j = 0; j < B.k; ++j) x.q[j] = B.q[j];
+                x.mat_off = int(mats.size());
+                for (const cd &v : B.m) mats.push_back(make_float2(float(v.real()), float(v.imag())));
+                blocks.push_back(x);
+            }
             small.push_back({b->state_off[t], n, first, int(fb.size()), t});
-        } else {
-            large.push_back({b->state_off[t], n, t});
-            large_blocks.push_back(mine);
+            continue;
         }
+        // tiled plan: groups of consecutive blocks of one pass, at most max_sub per launch
+        std::vector<Block> fb;
+        if (int rc = fuse_gates(g, G, n, std::min(kk, 4), SV_RULE_TILED, cost, fb)) return rc;
+        std::vector<int> mine;
+        for (const auto &grp : tile_groups(fb, n)) {
+            for (size_t c = 0; c < grp.size(); c += size_t(max_sub)) {
+                const int cnt = int(std::min(grp.size() - c, size_t(max_sub)));
+                std::vector<const Block *> bp;
+                for (int i = 0; i < cnt; ++i) bp.push_back(&fb[grp[c + i]]);
+                int sub_pos[dev::kMaxTileSubBlocks][4];
+                std::vector<cd> m4;
+                tile_pass_blocks(bp.data(), cnt, n, sub_pos, m4);
+                dev::TilePass tp;
+                std::memset(&tp, 0, sizeof tp);
+                tp.state_off = b->state_off[t];
+                tp.op_off = pool.size();
+                if (dev::make_tile_args(cnt, sub_pos, n, dev::kBatchTileBits, &tp.args) != hipSuccess)
+                    return fail(SV_ERR_ARG, "trajectory %d: tile pass layout", t);
+                pool.resize(pool.size() + size_t(cnt) * dev::real_form_elems(4));
+                for (int i = 0; i < cnt; ++i)
+                    dev::pack_real_form_f32(m4.data() + 256 * i, 4, pool.data() + tp.op_off + dev::real_form_elems(4) * i);
+                mine.push_back(int(passes.size()));
+                passes.push_back(tp);
+            }
+        }
+        BLarge L;
+        L.state_off = b->state_off[t];
+        L.n = n;
+        L.out = t;
+        L.zfirst = int(zunits.size());
+        const uint64_t N = uint64_t(1) << n, chunk = uint64_t(1) << kZ0ChunkBits;
+        for (uint64_t o = 0; o < N; o += chunk) zunits.push_back({b->state_off[t] + o, uint32_t(std::min(chunk, N - o)), 0});
+        L.zcount = int(zunits.size()) - L.zfirst;
+        large.push_back(L);
+        large_passes.push_back(mine);
     }
-    // layered steps for the large trajectories
-    std::vector<BItem> items;
+    // layered launches: layer s holds pass s of every large trajectory, as
+    // tile ranges (a quarter of the tiles of the largest states per unit)
+    std::vector<dev::TileUnit> units;
     b->steps.clear();
-    size_t max_steps = 0;
-    for (auto &v : large_blocks) max_steps = std::max(max_steps, v.size());
-    for (size_t s = 0; s < max_steps; ++s) {
-        const size_t off = items.size();
-        for (auto &v : large_blocks) {
+    size_t layers = 0;
+    for (auto &v : large_passes) layers = std::max(layers, v.size());
+    for (size_t s = 0; s < layers; ++s) {
+        const size_t off = units.size();
+        for (auto &v : large_passes) {
             if (s >= v.size()) continue;
-            const BBlock &B = blocks[v[s]];
-            const uint64_t groups = B.k <= 4 ? uint64_t(1) << (B.n - 2 - B.kh) : uint64_t(1) << (B.n - B.k);
-            const uint64_t per_wg = uint64_t(kThreads) * kGroupsPerThread;
-            for (uint64_t g0 = 0; g0 < groups; g0 += per_wg) items.push_back({v[s], 0, g0});
+            const dev::TilePass &tp = passes[v[s]];
+            const uint64_t nt = tp.args.n_tiles;
+            const uint64_t per = std::max<uint64_t>(1, nt / 64);
+            for (uint64_t t0 = 0; t0 < nt; t0 += per) units.push_back({v[s], 0, t0, std::min(nt, t0 + per)});
         }
-        b->steps.push_back({off, int(items.size() - off)});
+        b->steps.push_back({off, int(units.size() - off)});
     }
     b->n_small = int(small.size());
     b->n_large = int(large.size());
+    b->n_zunits = int(zunits.size());
     b->small_max_n = 0;
     for (auto &s : small) b->small_max_n = std::max(b->small_max_n, s.n);
     // large states are laid out after the small ones, contiguously
@@ -448,7 +389,11 @@ int build_schedule(sv_batch *b, const sv_batch_desc *d, int k)
     SV_HIP(upload(b->d_mats, mats.data(), mats.size() * sizeof(float2)));
     SV_HIP(upload(b->d_small, small.data(), small.size() * sizeof(BSmall)));
     SV_HIP(upload(b->d_large, large.data(), large.size() * sizeof(BLarge)));
-    SV_HIP(upload(b->d_items, items.data(), items.size() * sizeof(BItem)));
+    SV_HIP(upload(b->d_passes, passes.data(), passes.size() * sizeof(dev::TilePass)));
+    SV_HIP(upload(b->d_units, units.data(), units.size() * sizeof(dev::TileUnit)));
+    SV_HIP(upload(b->d_pool, pool.data(), pool.size() * sizeof(float)));
+    SV_HIP(upload(b->d_zunits, zunits.data(), zunits.size() * sizeof(BZUnit)));
+    SV_HIP(b->d_partial.ensure(std::max<size_t>(zunits.size(), 1) * sizeof(double)));
     b->max_k = k;
     if (b->exec) {
         (void)hipGraphExecDestroy(b->exec);
@@ -487,16 +432,19 @@ int enqueue_run(sv_batch *b, hipStream_t main, hipStream_t side)
                                static_cast<const BLarge *>(b->d_large.p), b->n_large, b->buf);
             SV_HIP(hipGetLastError());
         }
-        const auto *items = static_cast<const BItem *>(b->d_items.p);
+        const auto *units = static_cast<const dev::TileUnit *>(b->d_units.p);
+        const auto *passes = static_cast<const dev::TilePass *>(b->d_passes.p);
+        const auto *pool = static_cast<const uint32_t *>(b->d_pool.p);
         for (const auto &st : b->steps) {
             LaunchTimer t(stat_class(FAM_BATCH, 3), main);
-            hipLaunchKernelGGL(k_batch_step, dim3(st.second), dim3(kThreads), 0, main, items + st.first, blocks, mats,
-                               b->buf);
-            SV_HIP(hipGetLastError());
+            SV_HIP(dev::launch_tile_batch(units + st.first, st.second, passes, pool, b->buf, main));
         }
         LaunchTimer t(stat_class(FAM_BATCH, 4), main);
-        hipLaunchKernelGGL(k_batch_z0, dim3(b->n_large), dim3(kThreads), 0, main,
-                           static_cast<const BLarge *>(b->d_large.p), b->buf, z0);
+        double *partial = static_cast<double *>(b->d_partial.p);
+        hipLaunchKernelGGL(k_batch_z0_part, dim3(b->n_zunits), dim3(kThreads), 0, main,
+                           static_cast<const BZUnit *>(b->d_zunits.p), b->buf, partial);
+        hipLaunchKernelGGL(k_batch_z0_final, dim3((b->n_large + 255) / 256), dim3(256), 0, main,
+                           static_cast<const BLarge *>(b->d_large.p), b->n_large, partial, z0);
         SV_HIP(hipGetLastError());
     }
     SV_HIP(hipEventRecord(b->join, side));

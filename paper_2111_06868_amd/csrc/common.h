@@ -55,7 +55,7 @@ struct CostTable {
 };
 
 // Union limit of the tile passes that SV_RULE_TILED plans (8 ..
-// kTilePassMaxUnion; default 8, or the SV_TILE_UNION environment variable).
+// kTilePassMaxUnion; default 10, or the SV_TILE_UNION environment variable).
 int tile_union_limit();
 void set_tile_union_limit(int u);
 

@@ -50,7 +50,7 @@ CostTable default_costs()
 }
 
 static int g_tile_union = [] {
-    int u = 8;
+    int u = 10;
     if (const char *e = std::getenv("SV_TILE_UNION")) u = std::atoi(e);
     return std::min(std::max(u, 8), kTilePassMaxUnion);
 }();

@@ -44,6 +44,37 @@ hipError_t launch_mfma_split(int k, bool fp16, const int *sorted_q, const uint16
 constexpr int kMaxTileSubBlocks = kTilePassMaxBlocks;
 constexpr int kMaxTileUnion = kTilePassMaxUnion;
 constexpr int kMinTileQubits = 14;
+constexpr int kMaxTileBits = 14;
+// Layout and blocks of one tile pass over one state.
+struct TileArgs {
+    uint64_t n_tiles;
+    int ubit[kMaxTileBits];            // tile bit -> global position
+    int ext_pos[SV_MAX_QUBITS_C64];    // positions outside the tile, ascending
+    int n_ext;
+    int n_sub;                         // blocks in this launch
+    int tbit[kMaxTileSubBlocks][4];    // per block: its tile bits, ascending
+};
+// Tile arguments of n_sub blocks (positions ascending per block) on an
+// n-qubit state with 2^tile_bits-amplitude tiles.
+hipError_t make_tile_args(int n_sub, const int (*sub_pos)[4], int n, int tile_bits, TileArgs *out);
+// Batched passes (FP32 operands, shape (kBatchTileBits, kBatchTileWaves),
+// at most tile_max_blocks() blocks per pass): pass p of state at complex
+// offset state_off with its operands at pool + op_off (32 x 32 FP32 each);
+// each unit is one workgroup's tile range of one pass.
+constexpr int kBatchTileBits = 14;
+constexpr int kBatchTileWaves = 16;
+struct TilePass {
+    uint64_t state_off;  // complex elements from the start of the batch buffer
+    uint64_t op_off;     // 32-bit words into the operand pool
+    TileArgs args;
+};
+struct TileUnit {
+    int32_t pass;
+    int32_t pad;
+    uint64_t t0, t1;     // tiles [t0, t1)
+};
+hipError_t launch_tile_batch(const TileUnit *units, int n_units, const TilePass *passes, const uint32_t *pool,
+                             void *buf, hipStream_t st);
 bool tile_supported(int n, int union_bits);
 bool tile_shape_supported(int tile_bits, int waves);
 int tile_wgs_per_cu(int tile_bits, int waves);

@@ -101,6 +101,11 @@ struct Launch {
 // Pack the device operands of `launches` into `stage` (host) and return the
 // total byte count; offsets are written into the launches.
 size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage);
+// Positions (4 per block, ascending) and padded 16 x 16 canonical matrices of
+// a tile pass made of `count` blocks of <= 4 qubits: a smaller block is
+// padded with the lowest positions of the pass's union (itself completed to
+// at least 4 positions with the lowest free ones).
+void tile_pass_blocks(const Block *const *blocks, int count, int n, int (*sub_pos)[4], std::vector<cd> &mats);
 // Group consecutive blocks into tile passes (see tile.hip); blocks that do not
 // join a group keep their own launch.
 void group_tile_passes(const std::vector<Block> &blocks, int n, int precision, std::vector<Launch> &out);

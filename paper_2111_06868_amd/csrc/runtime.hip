@@ -180,10 +180,10 @@ Tuning &tuning()
         x.k4_reg = false;
         x.tile_grid_cap = 256;
         x.tile_bits = 14;
-        x.tile_waves = 8;
+        x.tile_waves = 16;
         if (const char *e = std::getenv("SV_TILE_BITS")) x.tile_bits = std::atoi(e) == 13 ? 13 : 14;
         if (const char *e = std::getenv("SV_TILE_WAVES")) x.tile_waves = std::atoi(e);
-        if (!dev::tile_shape_supported(x.tile_bits, x.tile_waves)) x.tile_waves = 8;
+        if (!dev::tile_shape_supported(x.tile_bits, x.tile_waves)) x.tile_waves = x.tile_bits == 14 ? 16 : 4;
         if (const char *e = std::getenv("SV_TILE_GRID")) x.tile_grid_cap = std::max(1, std::atoi(e));
         return x;
     }();
@@ -324,13 +324,36 @@ static void pad_to_four(const Block &b, const int *p4, std::vector<cd> &out)
         }
 }
 
+static uint64_t mask_of(const Block &b)
+{
+    uint64_t m = 0;
+    for (int j = 0; j < b.k; ++j) m |= uint64_t(1) << b.q[j];
+    return m;
+}
+
+void tile_pass_blocks(const Block *const *blocks, int count, int n, int (*sub_pos)[4], std::vector<cd> &mats)
+{
+    uint64_t um = 0;
+    for (int i = 0; i < count; ++i) um |= mask_of(*blocks[i]);
+    // the union gets at least 4 positions (lowest free ones)
+    for (int p = 0; p < n && __builtin_popcountll(um) < 4; ++p) um |= uint64_t(1) << p;
+    mats.clear();
+    for (int sb = 0; sb < count; ++sb) {
+        const Block &b = *blocks[sb];
+        uint64_t pm = mask_of(b);
+        for (int p = 0; p < 64 && __builtin_popcountll(pm) < 4; ++p)
+            if (((um >> p) & 1) && !((pm >> p) & 1)) pm |= uint64_t(1) << p;
+        int c = 0;
+        for (int p = 0; p < 64; ++p)
+            if ((pm >> p) & 1) sub_pos[sb][c++] = p;
+        std::vector<cd> m4;
+        pad_to_four(b, sub_pos[sb], m4);
+        mats.insert(mats.end(), m4.begin(), m4.end());
+    }
+}
+
 void group_tile_passes(const std::vector<Block> &blocks, int n, int precision, std::vector<Launch> &out)
 {
-    auto mask_of = [](const Block &b) {
-        uint64_t m = 0;
-        for (int j = 0; j < b.k; ++j) m |= uint64_t(1) << b.q[j];
-        return m;
-    };
     out.clear();
     for (const auto &grp : tile_groups(blocks, n)) {
         if (grp.size() == 1) {
@@ -343,27 +366,13 @@ void group_tile_passes(const std::vector<Block> &blocks, int n, int precision, s
             out.push_back(std::move(L));
             continue;
         }
-        uint64_t um = 0;
-        for (size_t b : grp) um |= mask_of(blocks[b]);
-        // the union gets at least 4 positions (lowest free ones)
-        for (int p = 0; p < n && __builtin_popcountll(um) < 4; ++p) um |= uint64_t(1) << p;
         Launch L;
         L.path = precision == SV_PREC_SPLIT_BF16 || precision == SV_PREC_SPLIT_FP16 ? PATH_TILE_BF16 : PATH_TILE;
         L.k = int(grp.size());
         std::fill(L.q, L.q + SV_MAX_K, 0);
-        L.m.clear();
-        for (int sb = 0; sb < L.k; ++sb) {
-            const Block &b = blocks[grp[sb]];
-            uint64_t pm = mask_of(b);
-            for (int p = 0; p < 64 && __builtin_popcountll(pm) < 4; ++p)
-                if (((um >> p) & 1) && !((pm >> p) & 1)) pm |= uint64_t(1) << p;
-            int c = 0;
-            for (int p = 0; p < 64; ++p)
-                if ((pm >> p) & 1) L.sub_pos[sb][c++] = p;
-            std::vector<cd> m4;
-            pad_to_four(b, L.sub_pos[sb], m4);
-            L.m.insert(L.m.end(), m4.begin(), m4.end());
-        }
+        std::vector<const Block *> bp;
+        for (size_t b : grp) bp.push_back(&blocks[b]);
+        tile_pass_blocks(bp.data(), L.k, n, L.sub_pos, L.m);
         out.push_back(std::move(L));
     }
 }

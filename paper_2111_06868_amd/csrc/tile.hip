@@ -34,8 +34,8 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef float vf2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kMaxTileBits = 14;
 constexpr int kOperandWords = 1024;  // one block's A operand: 32 x 32 FP32, or 2 x 32 x 32 bf16
 
 // Tile of 2^TB amplitudes held by a workgroup of WAVES waves: 2^TB / 16
@@ -54,15 +54,6 @@ struct TileCfg {
     static constexpr int CHUNKS = N / 2 / THREADS;  // 16-byte copies per thread
     static constexpr int MAX_SUB = TB == 14 ? 7 : (WAVES == 4 ? 3 : kMaxTileSubBlocks);
     static_assert(THREADS % 256 == 0 && THREADS <= 1024 && NB_PER_WAVE >= 1, "tile shape");
-};
-
-struct TileArgs {
-    uint64_t n_tiles;
-    int ubit[kMaxTileBits];            // tile bit -> global position
-    int ext_pos[SV_MAX_QUBITS_C64];    // positions outside the tile, ascending
-    int n_ext;
-    int n_sub;                         // blocks in this launch
-    int tbit[kMaxTileSubBlocks][4];    // per block: its tile bits, ascending
 };
 
 __device__ __forceinline__ uint32_t deposit(uint32_t v, uint32_t mask)
@@ -256,16 +247,17 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
             __builtin_memcpy(&xal, op + 1024 + l32 * 32 + 16 * i + 8 * half, 16);
 #pragma unroll
             for (int q = 0; q < NBW; ++q) {
-                bf16x8 bh, bl;
+                // (re, im) pairs split as packed pairs: hi = RNE(v), lo = RNE(v - hi)
+                bf16x2 ph[4], pl[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const vf2 v = *reinterpret_cast<const vf2 *>(Xb + ((row_of(rb, 8 * i + t) << 3) ^ lq[q]));
-                    const __bf16 hr = (__bf16)v.x, hi = (__bf16)v.y;
-                    bh[2 * t] = hr;
-                    bh[2 * t + 1] = hi;
-                    bl[2 * t] = (__bf16)(v.x - (float)hr);
-                    bl[2 * t + 1] = (__bf16)(v.y - (float)hi);
+                    ph[t] = __builtin_convertvector(v, bf16x2);
+                    pl[t] = __builtin_convertvector(v - __builtin_convertvector(ph[t], vf2), bf16x2);
                 }
+                bf16x8 bh, bl;
+                __builtin_memcpy(&bh, ph, 16);
+                __builtin_memcpy(&bl, pl, 16);
                 acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah, bh, acc[q], 0, 0, 0);
                 acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah, bl, acc[q], 0, 0, 0);
                 acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xal, bh, acc[q], 0, 0, 0);
@@ -281,18 +273,19 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
                 lds_st(Xb, (row_of(rb, 4 * g + e) << 3) ^ wq[q], acc[q][4 * g + 2 * e], acc[q][4 * g + 2 * e + 1]);
 }
 
-// FP32 (SPLIT = false): A = 32 x 32 FP32 real-form operands, back to back.
-// Split BF16 (SPLIT = true): A' = Ah + Al (bf16 from the host, hi then lo);
-// each B operand (8 consecutive K values = 4 complex rows of one column) is
-// split while it is read from LDS (v_cvt_pk_bf16_f32), and Ah Xh + Ah Xl +
-// Al Xh run on v_mfma_f32_32x32x16_bf16 with FP32 accumulation (the Al Xl
-// term, ~2^-16 relative, is dropped).
+// The tile loop of one workgroup: tiles T, T + step, .. below T_end of the
+// state at psi.  FP32 (SPLIT = false): A = 32 x 32 FP32 real-form operands,
+// back to back.  Split BF16 (SPLIT = true): A' = Ah + Al (bf16 from the host,
+// hi then lo); each B operand (8 consecutive K values = 4 complex rows of one
+// column) is split while it is read from LDS (v_cvt_pk_bf16_f32), and Ah Xh +
+// Ah Xl + Al Xh run on v_mfma_f32_32x32x16_bf16 with FP32 accumulation (the
+// Al Xl term, ~2^-16 relative, is dropped).
 template <int TB, int WAVES, bool SPLIT>
-__global__ void __launch_bounds__(64 * WAVES) k_tile_pass(float *__restrict__ psi, const uint32_t *__restrict__ A,
-                                                          const TileArgs args)
+__device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__restrict__ psi,
+                                          const uint32_t *__restrict__ A, const TileArgs &args, uint64_t T,
+                                          uint64_t T_end, uint64_t step)
 {
     using C = TileCfg<TB, WAVES>;
-    __shared__ TileShared<TB, WAVES> sh;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -302,15 +295,14 @@ __global__ void __launch_bounds__(64 * WAVES) k_tile_pass(float *__restrict__ ps
     TileCopy<TB, WAVES> cp;
     cp.init(args, tid);
 
-    uint64_t T = blockIdx.x;
     vf4 buf[C::CHUNKS];
-    if (T < args.n_tiles) cp.load(buf, psi, tile_base(T, args));
-    for (; T < args.n_tiles; T += gridDim.x) {
+    if (T < T_end) cp.load(buf, psi, tile_base(T, args));
+    for (; T < T_end; T += step) {
         const uint64_t base = tile_base(T, args);
         cp.to_lds(sh.X4, buf);
         __syncthreads();  // the first one also publishes the staged blocks
-        const uint64_t Tn = T + gridDim.x;
-        if (Tn < args.n_tiles) cp.load(buf, psi, tile_base(Tn, args));
+        const uint64_t Tn = T + step;
+        if (Tn < T_end) cp.load(buf, psi, tile_base(Tn, args));
         for (int s = 0; s < args.n_sub; ++s) {
             apply_block<TB, WAVES, SPLIT>(sh, args, s, w, half, l32);
             __syncthreads();
@@ -318,6 +310,29 @@ __global__ void __launch_bounds__(64 * WAVES) k_tile_pass(float *__restrict__ ps
         cp.store(psi, base, sh.X4);
         __syncthreads();
     }
+}
+
+// One pass over one state: a persistent grid strides over its tiles.
+template <int TB, int WAVES, bool SPLIT>
+__global__ void __launch_bounds__(64 * WAVES) k_tile_pass(float *__restrict__ psi, const uint32_t *__restrict__ A,
+                                                          const TileArgs args)
+{
+    __shared__ TileShared<TB, WAVES> sh;
+    tile_loop<TB, WAVES, SPLIT>(sh, psi, A, args, blockIdx.x, args.n_tiles, gridDim.x);
+}
+
+// Passes of many states in one grid: workgroup i takes tiles [t0, t1) of
+// the pass units[i] names (states of a batch, each with its own tile layout,
+// blocks and operands).
+template <int TB, int WAVES, bool SPLIT>
+__global__ void __launch_bounds__(64 * WAVES) k_tile_batch(const TileUnit *__restrict__ units,
+                                                           const TilePass *__restrict__ passes,
+                                                           const uint32_t *__restrict__ pool, float *__restrict__ buf)
+{
+    __shared__ TileShared<TB, WAVES> sh;
+    const TileUnit u = units[blockIdx.x];
+    const TilePass &p = passes[u.pass];
+    tile_loop<TB, WAVES, SPLIT>(sh, buf + 2 * p.state_off, pool + p.op_off, p.args, u.t0, u.t1, 1);
 }
 
 template <int TB, int WAVES>
@@ -356,13 +371,12 @@ int tile_max_blocks(int tile_bits, int waves)
     return waves == 4 ? TileCfg<13, 4>::MAX_SUB : TileCfg<13, 8>::MAX_SUB;
 }
 
-hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a, bool split_bf16, void *psi, int n,
-                            hipStream_t st, int grid_cap, int tile_bits, int waves)
+hipError_t make_tile_args(int n_sub, const int (*sub_pos)[4], int n, int tile_bits, TileArgs *out)
 {
     const int kTileBits = tile_bits;
-    if (!tile_shape_supported(tile_bits, waves)) return hipErrorInvalidValue;
-    if (n_sub < 1 || n_sub > tile_max_blocks(tile_bits, waves) || n < kTileBits) return hipErrorInvalidValue;
-    TileArgs a;
+    if ((tile_bits != 13 && tile_bits != 14) || n_sub < 1 || n_sub > kMaxTileSubBlocks || n < kTileBits)
+        return hipErrorInvalidValue;
+    TileArgs &a = *out;
     std::memset(&a, 0, sizeof a);
     uint64_t umask = 0;
     for (int s = 0; s < n_sub; ++s)
@@ -391,12 +405,31 @@ hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a,
             a.tbit[s][i] = t;
         }
     a.n_tiles = uint64_t(1) << (n - kTileBits);
+    return hipSuccess;
+}
+
+hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a, bool split_bf16, void *psi, int n,
+                            hipStream_t st, int grid_cap, int tile_bits, int waves)
+{
+    if (!tile_shape_supported(tile_bits, waves)) return hipErrorInvalidValue;
+    if (n_sub < 1 || n_sub > tile_max_blocks(tile_bits, waves)) return hipErrorInvalidValue;
+    TileArgs a;
+    if (hipError_t e = make_tile_args(n_sub, sub_pos, n, tile_bits, &a)) return e;
     float *p = static_cast<float *>(psi);
     if (tile_bits == 14)
         return waves == 16 ? tile_launch<14, 16>(a, d_a, split_bf16, p, st, grid_cap)
                            : tile_launch<14, 8>(a, d_a, split_bf16, p, st, grid_cap);
     return waves == 4 ? tile_launch<13, 4>(a, d_a, split_bf16, p, st, grid_cap)
                       : tile_launch<13, 8>(a, d_a, split_bf16, p, st, grid_cap);
+}
+
+hipError_t launch_tile_batch(const TileUnit *units, int n_units, const TilePass *passes, const uint32_t *pool,
+                             void *buf, hipStream_t st)
+{
+    if (n_units <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_tile_batch<kBatchTileBits, kBatchTileWaves, false>), dim3(unsigned(n_units)),
+                       dim3(64 * kBatchTileWaves), 0, st, units, passes, pool, static_cast<float *>(buf));
+    return hipGetLastError();
 }
 
 }  // namespace dev

@@ -204,7 +204,7 @@ def test_tile_shape_validation():
     """Only the compiled tile shapes are accepted; the call launches nothing."""
     for shape in sv.TILE_SHAPES:
         sv.set_tile_shape(*shape)
-    sv.set_tile_shape(14, 8)
+    sv.set_tile_shape(14, 16)
     for bad in ((14, 4), (12, 8), (13, 2), (15, 8), (13, 16), (14, 32)):
         with pytest.raises(ValueError):
             sv.set_tile_shape(*bad)
@@ -223,8 +223,9 @@ def _valid_order(gates, order):
 
 @pytest.mark.parametrize("cfg", [1, 2])
 def test_tiled_plan_structure(cfg):
-    """SV_RULE_TILED: passes of <= 8 positions made of blocks of <= 4 qubits,
-    consecutive, with every gate once and each qubit's gates in order."""
+    """SV_RULE_TILED: passes of <= 10 positions (the default union limit)
+    made of blocks of <= 4 qubits, consecutive, with every gate once and each
+    qubit's gates in order."""
     n, gates = wc.config_circuit(cfg)
     plan = sv.fuse(to_binding(gates), n, 4, sv.RULE_TILED)
     blocks = plan.blocks(False)
@@ -239,10 +240,10 @@ def test_tiled_plan_structure(cfg):
             assert b.tile_pass not in passes or prev == b.tile_pass  # consecutive
             passes.setdefault(b.tile_pass, set()).update(b.qubits)
         prev = b.tile_pass
-    assert passes and all(len(u) <= 8 for u in passes.values())
+    assert passes and all(len(u) <= 10 for u in passes.values())
     n_launch = len(passes) + sum(1 for b in blocks if b.tile_pass < 0)
-    # far fewer state passes than blocks (30 q: 35 passes for 845 gates)
-    assert n_launch <= len(blocks) // 2
+    # far fewer state passes than blocks (30 q: 26 passes for 845 gates)
+    assert n_launch <= len(blocks) // 3
 
 
 @pytest.mark.parametrize("rule", [sv.RULE_TILED, sv.RULE_ENHANCED])

@@ -297,7 +297,7 @@ def test_tiled_passes_vs_oracle(n, max_k):
     try:
         want, got, st = run_both(n, gates, "+", "c64", max_k=max_k, rule=sv.RULE_TILED)
         st.synchronize()
-        tiles = sum(sv.stats_query("tile", s)[0] for s in range(1, 5))
+        tiles = sum(sv.stats_query("tile", s)[0] for s in range(1, sv.MAX_TILE_LAUNCH_BLOCKS + 1))
     finally:
         sv.stats_enable(False)
         sv.stats_reset()
@@ -315,7 +315,7 @@ def test_tiled_passes_split_bf16(n):
     try:
         want, got, st = run_both(n, gates, "+", "c64", max_k=4, rule=sv.RULE_TILED, precision=sv.PREC_SPLIT_BF16)
         st.synchronize()
-        tiles = sum(sv.stats_query("tile_bf16", s)[0] for s in range(1, 5))
+        tiles = sum(sv.stats_query("tile_bf16", s)[0] for s in range(1, sv.MAX_TILE_LAUNCH_BLOCKS + 1))
     finally:
         sv.stats_enable(False)
         sv.stats_reset()
@@ -339,11 +339,11 @@ def test_tiled_passes_every_shape(shape, precision, n):
     try:
         want, got, st = run_both(n, gates, "+", "c64", max_k=4, rule=sv.RULE_TILED, precision=prec)
         st.synchronize()
-        tiles = sum(sv.stats_query(fam, s)[0] for s in range(1, 5))
+        tiles = sum(sv.stats_query(fam, s)[0] for s in range(1, sv.MAX_TILE_LAUNCH_BLOCKS + 1))
     finally:
         sv.stats_enable(False)
         sv.stats_reset()
-        sv.set_tile_shape(14, 8)
+        sv.set_tile_shape(14, 16)
     fe, ma = _report("tiled %s shape=%s n=%d (%d tile passes)" % (precision, shape, n, tiles), want, got)
     assert tiles > 0
     assert fe <= FID_C64
