@@ -283,7 +283,7 @@ int build_schedule(sv_batch *b, const sv_batch_desc *d, int k)
     std::vector<BSmall> small;
     std::vector<BLarge> large;
     std::vector<dev::TilePass> passes;
-    std::vector<float> pool;                     // FP32 real-form operands, 32 x 32 per block
+    std::vector<uint32_t> pool;                  // FP32 tile operands (pack_tile_operand), one per block
     std::vector<std::vector<int>> large_passes;  // per large trajectory: its pass indices
     std::vector<BZUnit> zunits;
     const CostTable cost = default_costs();
@@ -331,9 +331,9 @@ int build_schedule(sv_batch *b, const sv_batch_desc *d, int k)
                 tp.op_off = pool.size();
                 if (dev::make_tile_args(cnt, sub_pos, n, dev::kBatchTileBits, &tp.args) != hipSuccess)
                     return fail(SV_ERR_ARG, "trajectory %d: tile pass layout", t);
-                pool.resize(pool.size() + size_t(cnt) * dev::real_form_elems(4));
+                pool.resize(pool.size() + size_t(cnt) * dev::kTileOperandWords);
                 for (int i = 0; i < cnt; ++i)
-                    dev::pack_real_form_f32(m4.data() + 256 * i, 4, pool.data() + tp.op_off + dev::real_form_elems(4) * i);
+                    dev::pack_tile_operand(m4.data() + 256 * i, false, pool.data() + tp.op_off + dev::kTileOperandWords * i);
                 mine.push_back(int(passes.size()));
                 passes.push_back(tp);
             }
@@ -391,7 +391,7 @@ int build_schedule(sv_batch *b, const sv_batch_desc *d, int k)
     SV_HIP(upload(b->d_large, large.data(), large.size() * sizeof(BLarge)));
     SV_HIP(upload(b->d_passes, passes.data(), passes.size() * sizeof(dev::TilePass)));
     SV_HIP(upload(b->d_units, units.data(), units.size() * sizeof(dev::TileUnit)));
-    SV_HIP(upload(b->d_pool, pool.data(), pool.size() * sizeof(float)));
+    SV_HIP(upload(b->d_pool, pool.data(), pool.size() * sizeof(uint32_t)));
     SV_HIP(upload(b->d_zunits, zunits.data(), zunits.size() * sizeof(BZUnit)));
     SV_HIP(b->d_partial.ensure(std::max<size_t>(zunits.size(), 1) * sizeof(double)));
     b->max_k = k;

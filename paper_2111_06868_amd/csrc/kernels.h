@@ -33,14 +33,12 @@ hipError_t launch_mfma_f32(int k, const int *sorted_q, const float *d_a, void *p
 hipError_t launch_mfma_split(int k, bool fp16, const int *sorted_q, const uint16_t *d_ahi,
                              const uint16_t *d_alo, void *psi, int n, hipStream_t st, int tc_log,
                              int grid_cap);
-// Multi-block tile passes (complex64, FP32 MFMA): up to kMaxTileSubBlocks
-// 4-qubit blocks whose positions have a union of at most kMaxTileUnion
-// positions, applied in one HBM pass over tiles of 2^tile_bits amplitudes
-// held by workgroups of `waves` waves; shapes (14, 8), (14, 16), (13, 4),
-// (13, 8).
-// sub_pos rows ascending.  d_a = the blocks' real-form matrices, back to
-// back: 32 x 32 floats each (FP32), or for split_bf16 the hi then the lo
-// part, 32 x 32 bf16 each.  Needs n >= tile_bits.
+// Multi-block tile passes (complex64, FP32 or split-BF16 MFMA): up to
+// tile_max_blocks() 4-qubit blocks whose positions have a union of at most
+// kMaxTileUnion positions, applied in one HBM pass over tiles of
+// 2^tile_bits amplitudes held by workgroups of `waves` waves; shapes
+// (14, 8), (14, 16), (13, 4), (13, 8).  sub_pos rows ascending.  d_a = the
+// blocks' operands (pack_tile_operand), back to back.  Needs n >= tile_bits.
 constexpr int kMaxTileSubBlocks = kTilePassMaxBlocks;
 constexpr int kMaxTileUnion = kTilePassMaxUnion;
 constexpr int kMinTileQubits = 14;
@@ -54,13 +52,20 @@ struct TileArgs {
     int n_sub;                         // blocks in this launch
     int tbit[kMaxTileSubBlocks][4];    // per block: its tile bits, ascending
 };
+// Tile-pass operand of one 4-qubit block (canonical 16 x 16 matrix m), in
+// kTileOperandWords 32-bit words: FP32: Re U then Im U (16 x 16 floats each,
+// row-major); split BF16: the hi then the lo parts of U, one word per entry
+// holding (re, im) as bf16 (re in the low half).
+constexpr int kTileOperandWords = 512;
+void pack_tile_operand(const cd *m, bool split_bf16, uint32_t *out);
 // Tile arguments of n_sub blocks (positions ascending per block) on an
 // n-qubit state with 2^tile_bits-amplitude tiles.
 hipError_t make_tile_args(int n_sub, const int (*sub_pos)[4], int n, int tile_bits, TileArgs *out);
 // Batched passes (FP32 operands, shape (kBatchTileBits, kBatchTileWaves),
 // at most tile_max_blocks() blocks per pass): pass p of state at complex
-// offset state_off with its operands at pool + op_off (32 x 32 FP32 each);
-// each unit is one workgroup's tile range of one pass.
+// offset state_off with its operands at pool + op_off (pack_tile_operand
+// layout, kTileOperandWords each); each unit is one workgroup's tile range of
+// one pass.
 constexpr int kBatchTileBits = 14;
 constexpr int kBatchTileWaves = 16;
 struct TilePass {

@@ -234,12 +234,9 @@ size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage)
             total = align256(total + dev::real_form_elems(L.k) * 4);
             break;
         case PATH_TILE:
-            L.arena_off = total;
-            total = align256(total + size_t(L.k) * dev::real_form_elems(4) * 4);
-            break;
         case PATH_TILE_BF16:
             L.arena_off = total;
-            total = align256(total + size_t(L.k) * dev::real_form_elems(4) * 2 * 2);
+            total = align256(total + size_t(L.k) * dev::kTileOperandWords * 4);
             break;
         default:
             L.arena_off = total;
@@ -275,15 +272,10 @@ size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage)
             dev::pack_real_form_f32(L.m.data(), L.k, reinterpret_cast<float *>(h + L.arena_off));
             break;
         case PATH_TILE:
-            for (int sb = 0; sb < L.k; ++sb)
-                dev::pack_real_form_f32(L.m.data() + 256 * sb, 4,
-                                        reinterpret_cast<float *>(h + L.arena_off) + dev::real_form_elems(4) * sb);
-            break;
         case PATH_TILE_BF16:
-            for (int sb = 0; sb < L.k; ++sb) {
-                uint16_t *hi = reinterpret_cast<uint16_t *>(h + L.arena_off) + 2 * dev::real_form_elems(4) * sb;
-                dev::pack_real_form_split(L.m.data() + 256 * sb, 4, false, hi, hi + dev::real_form_elems(4));
-            }
+            for (int sb = 0; sb < L.k; ++sb)
+                dev::pack_tile_operand(L.m.data() + 256 * sb, L.path == PATH_TILE_BF16,
+                                       reinterpret_cast<uint32_t *>(h + L.arena_off) + dev::kTileOperandWords * sb);
             break;
         default:
             dev::pack_real_form_split(L.m.data(), L.k, L.path == PATH_SPLIT_FP16,
@@ -385,7 +377,7 @@ int enqueue(const std::vector<Launch> &launches, int dtype, void *psi, int n, co
         if (L.path == PATH_TILE || L.path == PATH_TILE_BF16) {
             // one launch per chunk of blocks whose operands fit the shape's LDS
             const int cap = dev::tile_max_blocks(T.tile_bits, T.tile_waves);
-            const size_t op_bytes = 4 * dev::real_form_elems(4);  // FP32, or hi + lo bf16
+            const size_t op_bytes = 4 * dev::kTileOperandWords;
             for (int c = 0; c < L.k; c += cap) {
                 const int m = std::min(cap, L.k - c);
                 LaunchTimer timer(stat_class(path_family(L.path), m), st);

@@ -36,7 +36,7 @@ typedef float vf2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
-constexpr int kOperandWords = 1024;  // one block's A operand: 32 x 32 FP32, or 2 x 32 x 32 bf16
+constexpr int kOperandWords = 1024;  // LDS words of one block's A fragments: 64 lanes x 16
 
 // Tile of 2^TB amplitudes held by a workgroup of WAVES waves: 2^TB / 16
 // columns per 4-qubit block, in blocks of 32 split evenly over the waves.
@@ -52,7 +52,11 @@ struct TileCfg {
     static constexpr int CBLOCKS = COLS / 32;  // 32-column blocks
     static constexpr int NB_PER_WAVE = CBLOCKS / WAVES;
     static constexpr int CHUNKS = N / 2 / THREADS;  // 16-byte copies per thread
-    static constexpr int MAX_SUB = TB == 14 ? 7 : (WAVES == 4 ? 3 : kMaxTileSubBlocks);
+    static constexpr int TABLE_WORDS = CBLOCKS + 32;
+    // two (13, 4) workgroups share a CU; the others hold the CU alone
+    static constexpr int LDS_BUDGET = (TB == 13 && WAVES == 4) ? 160 * 1024 / 2 : 160 * 1024;
+    static constexpr int FIT = (LDS_BUDGET - N * 8) / (4 * (kOperandWords + TABLE_WORDS));
+    static constexpr int MAX_SUB = FIT < kMaxTileSubBlocks ? FIT : kMaxTileSubBlocks;
     static_assert(THREADS % 256 == 0 && THREADS <= 1024 && NB_PER_WAVE >= 1, "tile shape");
 };
 
@@ -152,10 +156,17 @@ struct TileShared {
     uint32_t cl[C::MAX_SUB][32];
 };
 
-// Stage the operands and column tables of the launch's blocks.  FP32
-// operands are reordered so that lane (half, l32) finds A'[l32][2 j + half],
-// j = 0..15, as 16 consecutive words; split operands are copied as they are
-// (hi then lo, 32 x 32 bf16 each).
+// Stage the launch's blocks: the A fragments of every lane, expanded from the
+// compact operands (pack_tile_operand) into 16 consecutive words per lane,
+// and the column tables.  Lane (half, l32) takes row r = l32 of the real
+// form A' = [[Ur,-Ui],[Ui,Ur]] interleaved by (re, im): complex row
+// ci = r / 2, part ri = r % 2.
+//   FP32: word j = A'[r][2 j + half], i.e. Ur[ci][j] (ri == half), -Ui[ci][j]
+//   (ri = 0, half = 1) or Ui[ci][j] (ri = 1, half = 0).
+//   split: words 4 p + e (p = 0, 1 hi steps, 2, 3 lo steps; e = 0..3) hold
+//   the bf16 pair A'[r][16 i + 8 half + 2 e + {0, 1}] of step i = p & 1:
+//   (Ur, -Ui) for ri = 0, (Ui, Ur) for ri = 1, at complex column
+//   j = 8 i + 4 half + e.
 template <int TB, int WAVES, bool SPLIT>
 __device__ __forceinline__ void stage_blocks(TileShared<TB, WAVES> &sh, const uint32_t *A, const TileArgs &args,
                                              int tid)
@@ -164,12 +175,19 @@ __device__ __forceinline__ void stage_blocks(TileShared<TB, WAVES> &sh, const ui
     const int nsub = args.n_sub;
     for (int e = tid; e < nsub * kOperandWords; e += C::THREADS) {
         const int s = e / kOperandWords, r = e % kOperandWords;
-        if (SPLIT) {
-            sh.op[s][r] = A[e];
+        const int lane = r / 16, wd = r % 16;
+        const int half = lane >> 5, l32 = lane & 31, ci = l32 >> 1, ri = l32 & 1;
+        const uint32_t *cop = A + s * kTileOperandWords;
+        uint32_t v;
+        if (!SPLIT) {
+            v = cop[(ri == half ? 0 : 256) + ci * 16 + wd];
+            if (ri == 0 && half == 1) v ^= 0x80000000u;
         } else {
-            const int lane = r / 16, j = r % 16;
-            sh.op[s][r] = A[s * kOperandWords + (lane & 31) * 32 + 2 * j + (lane >> 5)];
+            const int part = wd >> 3, i = (wd >> 2) & 1, e4 = wd & 3;
+            const uint32_t w = cop[part * 256 + ci * 16 + 8 * i + 4 * half + e4];
+            v = ri ? ((w >> 16) | (w << 16)) : (w ^ 0x80000000u);
         }
+        sh.op[s][r] = v;
     }
     for (int e = tid; e < nsub * (C::CBLOCKS + 32); e += C::THREADS) {
         const int s = e / (C::CBLOCKS + 32), r = e % (C::CBLOCKS + 32);
@@ -219,8 +237,8 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
     for (int q = 0; q < NBW; ++q)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[q][v] = 0.f;
+    const vf4 *ap = reinterpret_cast<const vf4 *>(&sh.op[s][(half * 32 + l32) * 16]);  // staged fragments
     if (!SPLIT) {
-        const vf4 *ap = reinterpret_cast<const vf4 *>(&sh.op[s][(half * 32 + l32) * 16]);
         float a[16];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -238,13 +256,13 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
                 acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j], b, acc[q], 0, 0, 0);
             }
     } else {
-        // A' hi / lo: step i (K = 16 i .. 16 i + 15), lane holds A'[l32][16 i + 8 half + e]
-        const uint16_t *op = reinterpret_cast<const uint16_t *>(sh.op[s]);
+        // step i (K = 16 i .. 16 i + 15): hi fragment ap[i], lo fragment ap[2 + i]
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
+            const vf4 fh = ap[i], fl = ap[2 + i];
             bf16x8 xah, xal;
-            __builtin_memcpy(&xah, op + l32 * 32 + 16 * i + 8 * half, 16);
-            __builtin_memcpy(&xal, op + 1024 + l32 * 32 + 16 * i + 8 * half, 16);
+            __builtin_memcpy(&xah, &fh, 16);
+            __builtin_memcpy(&xal, &fl, 16);
 #pragma unroll
             for (int q = 0; q < NBW; ++q) {
                 // (re, im) pairs split as packed pairs: hi = RNE(v), lo = RNE(v - hi)
@@ -369,6 +387,41 @@ int tile_max_blocks(int tile_bits, int waves)
     if (!tile_shape_supported(tile_bits, waves)) return 0;
     if (tile_bits == 14) return waves == 16 ? TileCfg<14, 16>::MAX_SUB : TileCfg<14, 8>::MAX_SUB;
     return waves == 4 ? TileCfg<13, 4>::MAX_SUB : TileCfg<13, 8>::MAX_SUB;
+}
+
+static uint32_t f2bf_rne(float x)
+{
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+static float bf2f(uint32_t h)
+{
+    const uint32_t u = h << 16;
+    float x;
+    std::memcpy(&x, &u, 4);
+    return x;
+}
+
+void pack_tile_operand(const cd *m, bool split_bf16, uint32_t *out)
+{
+    for (int r = 0; r < 16; ++r)
+        for (int c = 0; c < 16; ++c) {
+            const double re = m[r * 16 + c].real(), im = m[r * 16 + c].imag();
+            if (!split_bf16) {
+                const float fr = float(re), fi = float(im);
+                std::memcpy(&out[r * 16 + c], &fr, 4);
+                std::memcpy(&out[256 + r * 16 + c], &fi, 4);
+                continue;
+            }
+            // hi = RNE(x), lo = RNE(x - hi), as (re, im) halves of one word
+            const uint32_t hr = f2bf_rne(float(re)), hi = f2bf_rne(float(im));
+            const uint32_t lr = f2bf_rne(float(re - double(bf2f(hr)))), li = f2bf_rne(float(im - double(bf2f(hi))));
+            out[r * 16 + c] = hr | (hi << 16);
+            out[256 + r * 16 + c] = lr | (li << 16);
+        }
 }
 
 hipError_t make_tile_args(int n_sub, const int (*sub_pos)[4], int n, int tile_bits, TileArgs *out)
