@@ -325,11 +325,14 @@ def bench_gradient(args):
     H = sv.pauli_sum(wc.ansatz_observable(n))
     ga = sv.GateArray([(g.name, g.qubits, g.params, g.param_index) for g in gates])
     psi, scratch = sv.State(n, "c64"), sv.State(n, "c64")
+    # launch shapes and block costs for 20-qubit states (sizes the fusion of
+    # the forward circuit and of the adjoint's dagger blocks)
+    sv.autotune(scratch, sv.PREC_FP32)
     out = {}
 
     def step():
         psi.set_basis(0)
-        psi.run(ga, max_k=4, rule=sv.RULE_ENHANCED)
+        psi.run(ga, max_k=-1, rule=sv.RULE_ENHANCED)
         out["E"] = psi.expectation(H)
         out["g"] = sv.backward(psi, scratch, ga, H, len(thetas))
 

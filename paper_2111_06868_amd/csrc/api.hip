@@ -2,6 +2,9 @@
 // circuits, reductions, adjoint gradients and timing.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <unordered_map>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -129,6 +132,9 @@ void blocks_to_launches(const std::vector<Block> &blocks, const sv_state *s, int
     }
 }
 
+int choose_plan_uncached(const sv_gate *g, int G, int n, int dtype, int precision, int rule, int max_k, bool found,
+                         const CostTable &cost, int kmin, int kcap, int *out_rule, int *out_k);
+
 // Resolve (rule, max_k) requests: max_k = -1 picks k by the cost table;
 // SV_RULE_AUTO also picks between the enhanced and the tiled plan.  Candidate
 // plans are priced on block positions only (no matrices are formed).
@@ -145,6 +151,48 @@ int choose_plan(const sv_gate *g, int G, int n, int dtype, int precision, int ru
         *out_k = max_k;
         return SV_OK;
     }
+    // The choice depends on the gates' positions and the cost table only, so
+    // it is remembered per circuit structure (a circuit re-run with new
+    // angles is not re-priced).  A stale or colliding entry can only name
+    // another valid (rule, k), and one below the widest gate is recomputed.
+    uint64_t key = 1469598103934665603ull;
+    auto mix = [&key](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
+    mix(uint64_t(n));
+    mix(uint64_t(dtype));
+    mix(uint64_t(precision));
+    mix(uint64_t(rule));
+    mix(uint64_t(max_k + 8));
+    mix(cost_version());
+    mix(uint64_t(tile_union_limit()));
+    mix(uint64_t(G));
+    for (int i = 0; i < G; ++i) {
+        mix(uint64_t(g[i].kind) | uint64_t(g[i].k) << 8);
+        for (int j = 0; j < g[i].k; ++j) mix(uint64_t(g[i].q[j]));
+    }
+    static std::mutex memo_mu;
+    static std::unordered_map<uint64_t, std::pair<int, int>> memo;
+    {
+        std::lock_guard<std::mutex> lk(memo_mu);
+        auto it = memo.find(key);
+        if (it != memo.end() && it->second.second >= kmin) {
+            *out_rule = it->second.first;
+            *out_k = it->second.second;
+            return SV_OK;
+        }
+    }
+    const int rc = choose_plan_uncached(g, G, n, dtype, precision, rule, max_k, found, cost, kmin, kcap, out_rule,
+                                        out_k);
+    if (!rc) {
+        std::lock_guard<std::mutex> lk(memo_mu);
+        if (memo.size() > 4096) memo.clear();
+        memo[key] = {*out_rule, *out_k};
+    }
+    return rc;
+}
+
+int choose_plan_uncached(const sv_gate *g, int G, int n, int dtype, int precision, int rule, int max_k, bool found,
+                         const CostTable &cost, int kmin, int kcap, int *out_rule, int *out_k)
+{
     std::vector<int> rules;
     if (rule == SV_RULE_AUTO) {
         rules.push_back(SV_RULE_ENHANCED);
@@ -706,9 +754,22 @@ int dagger_launches(const sv_gate *g, int hi, int lo, const sv_state *s, std::ve
     }
     std::vector<Block> blocks;
     const int prec = s->dtype == SV_C64 ? SV_PREC_FP32 : SV_PREC_FP64;
-    if (int rc = fuse_gates(dg.data(), cnt, s->n, std::max(kmax, 4), SV_RULE_ENHANCED, lookup_costs(s->n, prec, nullptr),
-                            blocks))
-        return rc;
+    const CostTable cost = lookup_costs(s->n, prec, nullptr);
+    // block size: the cheapest plan under the cost table (complex64 blocks of
+    // 4..6 qubits run on MFMA; complex128 stays at 4)
+    int kbest = std::max(kmax, 4);
+    if (s->dtype == SV_C64 && s->n >= 11) {
+        double best = 1e300;
+        for (int k = std::max(kmax, 4); k <= SV_MAX_K; ++k) {
+            if (int rc = fuse_gates(dg.data(), cnt, s->n, k, SV_RULE_ENHANCED, cost, blocks, false)) return rc;
+            const double c = plan_cost(blocks, cost);
+            if (c < best - 1e-12) {
+                best = c;
+                kbest = k;
+            }
+        }
+    }
+    if (int rc = fuse_gates(dg.data(), cnt, s->n, kbest, SV_RULE_ENHANCED, cost, blocks)) return rc;
     for (const auto &b : blocks) {
         Launch L;
         L.k = b.k;
@@ -834,9 +895,9 @@ extern "C" int sv_backward(sv_state *psi, sv_state *scratch, const sv_gate *g, i
             SV_HIP(dev::launch_grad_terms(psi->dtype, st.n_terms, st.x, st.z, st.pw, psi->buf, scratch->buf, psi->n,
                                           part, st.slot, psi->stream));
         }
-        const std::vector<Launch> sub(launches.begin() + st.l0, launches.begin() + st.l1);
-        if (int rc = enqueue(sub, psi->dtype, psi->buf, psi->n, psi->arena.p, psi->stream)) return rc;
-        if (int rc = enqueue(sub, psi->dtype, scratch->buf, psi->n, psi->arena.p, psi->stream)) return rc;
+        const Launch *sub = launches.data() + st.l0;
+        const size_t cnt = st.l1 - st.l0;
+        if (int rc = enqueue(sub, cnt, psi->dtype, psi->buf, psi->n, psi->arena.p, psi->stream, scratch->buf)) return rc;
     }
     SV_HIP(hipEventRecord(psi->arena_free, psi->stream));
     if (slots) {

@@ -73,6 +73,7 @@ struct RegArgs {
     T mr[(1 << K) * (1 << K)];
     T mi[(1 << K) * (1 << K)];
     uint64_t n_groups;
+    T *psi2;                // second state for gridDim.y = 2 (same block on both)
     int hp[K > 0 ? K : 1];  // high positions (>= 2), ascending; first kh used
 };
 
@@ -82,8 +83,9 @@ __device__ __forceinline__ uint64_t insert_zero(uint64_t x, int p)
 }
 
 template <typename T, int K, int LM>
-__global__ void __launch_bounds__(256) k_apply_reg(T *__restrict__ psi, const RegArgs<T, K> a)
+__global__ void __launch_bounds__(256) k_apply_reg(T *__restrict__ psi0, const RegArgs<T, K> a)
 {
+    T *__restrict__ psi = blockIdx.y ? a.psi2 : psi0;
     constexpr int KL = popc2<LM>();
     constexpr int KH = K - KL;
     constexpr int NH = 1 << KH;
@@ -140,9 +142,10 @@ __global__ void __launch_bounds__(256) k_apply_reg(T *__restrict__ psi, const Re
 }
 
 template <typename T, int K, int LM>
-hipError_t reg_launch_t(const int *sorted_q, const cd *m, T *psi, int n, hipStream_t st, int grid_cap)
+hipError_t reg_launch_t(const int *sorted_q, const cd *m, T *psi, T *psi2, int n, hipStream_t st, int grid_cap)
 {
     RegArgs<T, K> a;
+    a.psi2 = psi2;
     constexpr int D = 1 << K;
     for (int i = 0; i < D * D; ++i) {
         a.mr[i] = T(m[i].real());
@@ -155,22 +158,22 @@ hipError_t reg_launch_t(const int *sorted_q, const cd *m, T *psi, int n, hipStre
     a.n_groups = uint64_t(1) << (n - 2 - kh);
     uint64_t blocks = (a.n_groups + 255) / 256;
     if (grid_cap > 0 && blocks > uint64_t(grid_cap)) blocks = grid_cap;
-    hipLaunchKernelGGL((k_apply_reg<T, K, LM>), dim3(unsigned(blocks)), dim3(256), 0, st, psi, a);
+    hipLaunchKernelGGL((k_apply_reg<T, K, LM>), dim3(unsigned(blocks), psi2 ? 2 : 1), dim3(256), 0, st, psi, a);
     return hipGetLastError();
 }
 
 template <typename T, int K>
-hipError_t reg_dispatch_lm(const int *sorted_q, const cd *m, T *psi, int n, hipStream_t st, int grid_cap)
+hipError_t reg_dispatch_lm(const int *sorted_q, const cd *m, T *psi, T *psi2, int n, hipStream_t st, int grid_cap)
 {
     int lm = 0;
     for (int j = 0; j < K; ++j)
         if (sorted_q[j] < 2) lm |= 1 << sorted_q[j];
     switch (lm) {
-    case 0: return reg_launch_t<T, K, 0>(sorted_q, m, psi, n, st, grid_cap);
-    case 1: return reg_launch_t<T, K, 1>(sorted_q, m, psi, n, st, grid_cap);
-    case 2: return reg_launch_t<T, K, 2>(sorted_q, m, psi, n, st, grid_cap);
+    case 0: return reg_launch_t<T, K, 0>(sorted_q, m, psi, psi2, n, st, grid_cap);
+    case 1: return reg_launch_t<T, K, 1>(sorted_q, m, psi, psi2, n, st, grid_cap);
+    case 2: return reg_launch_t<T, K, 2>(sorted_q, m, psi, psi2, n, st, grid_cap);
     default:
-        if constexpr (K >= 2) return reg_launch_t<T, K, 3>(sorted_q, m, psi, n, st, grid_cap);
+        if constexpr (K >= 2) return reg_launch_t<T, K, 3>(sorted_q, m, psi, psi2, n, st, grid_cap);
         return hipErrorInvalidValue;
     }
 }
@@ -180,12 +183,14 @@ template <int K>
 struct GenArgs {
     int pos[K];  // ascending
     uint64_t n_groups;
+    void *psi2;  // second state for gridDim.y = 2 (same block on both)
 };
 
 template <typename T, int K>
-__global__ void __launch_bounds__(256) k_apply_generic(T *__restrict__ psi, const T *__restrict__ m,
+__global__ void __launch_bounds__(256) k_apply_generic(T *__restrict__ psi0, const T *__restrict__ m,
                                                        const GenArgs<K> a)
 {
+    T *__restrict__ psi = blockIdx.y ? static_cast<T *>(a.psi2) : psi0;
     constexpr int D = 1 << K;
     const uint64_t stride = uint64_t(gridDim.x) * blockDim.x;
     for (uint64_t g = uint64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < a.n_groups; g += stride) {
@@ -224,27 +229,28 @@ __global__ void __launch_bounds__(256) k_apply_generic(T *__restrict__ psi, cons
 }
 
 template <typename T, int K>
-hipError_t generic_launch_t(const int *sorted_q, const T *d_m, T *psi, int n, hipStream_t st)
+hipError_t generic_launch_t(const int *sorted_q, const T *d_m, T *psi, T *psi2, int n, hipStream_t st)
 {
     GenArgs<K> a;
+    a.psi2 = psi2;
     for (int j = 0; j < K; ++j) a.pos[j] = sorted_q[j];
     a.n_groups = uint64_t(1) << (n - K);
     uint64_t blocks = (a.n_groups + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL((k_apply_generic<T, K>), dim3(unsigned(blocks)), dim3(256), 0, st, psi, d_m, a);
+    hipLaunchKernelGGL((k_apply_generic<T, K>), dim3(unsigned(blocks), psi2 ? 2 : 1), dim3(256), 0, st, psi, d_m, a);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t generic_dispatch(int k, const int *sorted_q, const T *d_m, T *psi, int n, hipStream_t st)
+hipError_t generic_dispatch(int k, const int *sorted_q, const T *d_m, T *psi, T *psi2, int n, hipStream_t st)
 {
     switch (k) {
-    case 1: return generic_launch_t<T, 1>(sorted_q, d_m, psi, n, st);
-    case 2: return generic_launch_t<T, 2>(sorted_q, d_m, psi, n, st);
-    case 3: return generic_launch_t<T, 3>(sorted_q, d_m, psi, n, st);
-    case 4: return generic_launch_t<T, 4>(sorted_q, d_m, psi, n, st);
-    case 5: return generic_launch_t<T, 5>(sorted_q, d_m, psi, n, st);
-    case 6: return generic_launch_t<T, 6>(sorted_q, d_m, psi, n, st);
+    case 1: return generic_launch_t<T, 1>(sorted_q, d_m, psi, psi2, n, st);
+    case 2: return generic_launch_t<T, 2>(sorted_q, d_m, psi, psi2, n, st);
+    case 3: return generic_launch_t<T, 3>(sorted_q, d_m, psi, psi2, n, st);
+    case 4: return generic_launch_t<T, 4>(sorted_q, d_m, psi, psi2, n, st);
+    case 5: return generic_launch_t<T, 5>(sorted_q, d_m, psi, psi2, n, st);
+    case 6: return generic_launch_t<T, 6>(sorted_q, d_m, psi, psi2, n, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -308,34 +314,36 @@ bool reg_supported(int dtype, int k, const int *sorted_q, int n)
 }
 
 hipError_t launch_reg(int dtype, int k, const int *sorted_q, const cd *m, void *psi, int n,
-                      hipStream_t st, int grid_cap)
+                      hipStream_t st, int grid_cap, void *psi2)
 {
     if (dtype == SV_C64) {
-        float *p = static_cast<float *>(psi);
+        float *p = static_cast<float *>(psi), *p2 = static_cast<float *>(psi2);
         switch (k) {
-        case 1: return reg_dispatch_lm<float, 1>(sorted_q, m, p, n, st, grid_cap);
-        case 2: return reg_dispatch_lm<float, 2>(sorted_q, m, p, n, st, grid_cap);
-        case 3: return reg_dispatch_lm<float, 3>(sorted_q, m, p, n, st, grid_cap);
-        case 4: return reg_dispatch_lm<float, 4>(sorted_q, m, p, n, st, grid_cap);
+        case 1: return reg_dispatch_lm<float, 1>(sorted_q, m, p, p2, n, st, grid_cap);
+        case 2: return reg_dispatch_lm<float, 2>(sorted_q, m, p, p2, n, st, grid_cap);
+        case 3: return reg_dispatch_lm<float, 3>(sorted_q, m, p, p2, n, st, grid_cap);
+        case 4: return reg_dispatch_lm<float, 4>(sorted_q, m, p, p2, n, st, grid_cap);
         default: return hipErrorInvalidValue;
         }
     }
-    double *p = static_cast<double *>(psi);
+    double *p = static_cast<double *>(psi), *p2 = static_cast<double *>(psi2);
     switch (k) {
-    case 1: return reg_dispatch_lm<double, 1>(sorted_q, m, p, n, st, grid_cap);
-    case 2: return reg_dispatch_lm<double, 2>(sorted_q, m, p, n, st, grid_cap);
-    case 3: return reg_dispatch_lm<double, 3>(sorted_q, m, p, n, st, grid_cap);
+    case 1: return reg_dispatch_lm<double, 1>(sorted_q, m, p, p2, n, st, grid_cap);
+    case 2: return reg_dispatch_lm<double, 2>(sorted_q, m, p, p2, n, st, grid_cap);
+    case 3: return reg_dispatch_lm<double, 3>(sorted_q, m, p, p2, n, st, grid_cap);
     default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t launch_generic(int dtype, int k, const int *sorted_q, const void *d_m, void *psi, int n,
-                          hipStream_t st)
+                          hipStream_t st, void *psi2)
 {
     if (n < k) return hipErrorInvalidValue;
     if (dtype == SV_C64)
-        return generic_dispatch<float>(k, sorted_q, static_cast<const float *>(d_m), static_cast<float *>(psi), n, st);
-    return generic_dispatch<double>(k, sorted_q, static_cast<const double *>(d_m), static_cast<double *>(psi), n, st);
+        return generic_dispatch<float>(k, sorted_q, static_cast<const float *>(d_m), static_cast<float *>(psi),
+                                       static_cast<float *>(psi2), n, st);
+    return generic_dispatch<double>(k, sorted_q, static_cast<const double *>(d_m), static_cast<double *>(psi),
+                                    static_cast<double *>(psi2), n, st);
 }
 
 hipError_t launch_fill_basis(int dtype, void *psi, int n, uint64_t index, hipStream_t st)

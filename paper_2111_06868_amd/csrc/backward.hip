@@ -183,6 +183,14 @@ __device__ __forceinline__ void ld2(const double *p, uint64_t i, double &re, dou
     im = v.y;
 }
 
+// Sum over the 64 lanes of a wave in a fixed butterfly order.
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
 template <typename T, int NT>
 __global__ void __launch_bounds__(kRedThreads) k_grad_terms(const T *__restrict__ phi, const T *__restrict__ lam,
                                                            const GradTerms a, double *__restrict__ partials)
@@ -191,14 +199,15 @@ __global__ void __launch_bounds__(kRedThreads) k_grad_terms(const T *__restrict_
 #pragma unroll
     for (int t = 0; t < NT; ++t) sr[t] = si[t] = 0.0;
     for (uint64_t i = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; i < a.N; i += uint64_t(kRedBlocks) * kRedThreads) {
-        double lr, li;
+        double lr, li, fr, fi;
         ld2(lam, i, lr, li);
+        ld2(phi, i, fr, fi);
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             if (t >= a.n_terms) break;
             const uint64_t j = i ^ a.x[t];
-            double pr, pi;
-            ld2(phi, j, pr, pi);
+            double pr = fr, pi = fi;
+            if (a.x[t]) ld2(phi, j, pr, pi);  // Z-type terms (x = 0) reuse phi_i
             if (__popcll(j & a.z[t]) & 1) {
                 pr = -pr;
                 pi = -pi;
@@ -216,19 +225,24 @@ __global__ void __launch_bounds__(kRedThreads) k_grad_terms(const T *__restrict_
             si[t] += lr * qi - li * qr;
         }
     }
-    __shared__ double sh[kRedThreads];
-    const int tid = threadIdx.x;
-    for (int t = 0; t < NT && t < a.n_terms; ++t) {
-        for (int c = 0; c < 2; ++c) {
-            __syncthreads();
-            sh[tid] = c ? si[t] : sr[t];
-            __syncthreads();
-            for (int s = kRedThreads / 2; s > 0; s >>= 1) {
-                if (tid < s) sh[tid] += sh[tid + s];
-                __syncthreads();
-            }
-            if (tid == 0) partials[(size_t(t) * kRedBlocks + blockIdx.x) * 2 + c] = sh[0];
+    // workgroup sums: wave butterflies, then the waves' values in wave order
+    constexpr int kWaves = kRedThreads / 64;
+    __shared__ double sh[kWaves][2 * NT];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        if (t >= a.n_terms) break;
+        const double r = wave_sum(sr[t]), m = wave_sum(si[t]);
+        if (lane == 0) {
+            sh[wv][2 * t] = r;
+            sh[wv][2 * t + 1] = m;
         }
+    }
+    __syncthreads();
+    if (tid < 2 * a.n_terms) {
+        double v = 0.0;
+        for (int w = 0; w < kWaves; ++w) v += sh[w][tid];
+        partials[(size_t(tid >> 1) * kRedBlocks + blockIdx.x) * 2 + (tid & 1)] = v;
     }
 }
 

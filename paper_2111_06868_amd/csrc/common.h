@@ -64,6 +64,8 @@ CostTable default_costs();
 // Lookup of an autotuned table for (n, precision); falls back to defaults.
 CostTable lookup_costs(int n, int precision, bool *found);
 void store_costs(int n, int precision, const double *ms, const double *tile = nullptr);
+// Incremented by every store_costs (invalidates choices priced on older tables).
+uint64_t cost_version();
 
 // Greedy fusion.  Gates must be validated first.  `cost` steers the
 // enhanced rule.  Fills blocks (with canonical matrices).

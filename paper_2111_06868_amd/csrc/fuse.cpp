@@ -60,6 +60,9 @@ void set_tile_union_limit(int u) { g_tile_union = std::min(std::max(u, 8), kTile
 
 static std::mutex g_cost_mu;
 static std::map<std::pair<int, int>, CostTable> g_costs;
+static std::atomic<uint64_t> g_cost_version(1);
+
+uint64_t cost_version() { return g_cost_version.load(); }
 
 CostTable lookup_costs(int n, int precision, bool *found)
 {
@@ -86,6 +89,7 @@ void store_costs(int n, int precision, const double *ms, const double *tile)
     }
     std::lock_guard<std::mutex> lk(g_cost_mu);
     g_costs[{n, precision}] = t;
+    ++g_cost_version;
 }
 
 namespace {
@@ -118,10 +122,14 @@ std::vector<std::vector<int>> frontier_groups(const sv_gate *g, const std::vecto
     const int G = int(idx.size());
     std::vector<uint64_t> mask(G);
     std::vector<std::vector<int>> queue(64);
+    uint64_t used = 0;
     for (int t = 0; t < G; ++t) {
         mask[t] = gate_mask(g[idx[t]]);
-        for (uint64_t m = mask[t]; m; m &= m - 1) queue[__builtin_ctzll(m)].push_back(t);
+        used |= mask[t];
     }
+    for (uint64_t m = used; m; m &= m - 1) queue[__builtin_ctzll(m)].reserve(G);
+    for (int t = 0; t < G; ++t)
+        for (uint64_t m = mask[t]; m; m &= m - 1) queue[__builtin_ctzll(m)].push_back(t);
     std::vector<size_t> head(64, 0);
     auto at_head = [&](int p) { return head[p] < queue[p].size() ? queue[p][head[p]] : -1; };
     auto ready = [&](int t) {
@@ -148,8 +156,8 @@ std::vector<std::vector<int>> frontier_groups(const sv_gate *g, const std::vecto
                 }
             }
             int best = -1, best_add = 65;
-            for (int p = 0; p < 64; ++p) {
-                const int t = at_head(p);
+            for (uint64_t pm = used; pm; pm &= pm - 1) {
+                const int t = at_head(__builtin_ctzll(pm));
                 if (t < 0 || !ready(t) || popc(U | mask[t]) > max_union) continue;
                 const int add = popc(mask[t] & ~U);
                 if (add < best_add || (add == best_add && t < best)) {
@@ -190,9 +198,11 @@ double plan_cost(const std::vector<Block> &blocks, const CostTable &cost)
 }
 
 // Apply a canonical gate matrix (on block-local bits lb[0..kg-1], ascending)
-// to every column of the D x D canonical block matrix U (in place).  Plain
-// real arithmetic on (re, im) pairs: std::complex multiplication carries
-// inf/nan recovery that dominates the cost of fusing large blocks.
+// to every column of the D x D canonical block matrix U (in place).  For each
+// group of the 2^kg rows the gate mixes, the new row m is the sum over m' of
+// G[m][m'] times row m', accumulated as whole rows (contiguous re/im pairs,
+// so the inner loop vectorises) in plain real arithmetic: std::complex
+// multiplication carries inf/nan recovery that dominates the cost.
 static void apply_to_columns(std::vector<cd> &Uc, int kb, const std::vector<cd> &Gc, int kg, const int *lb)
 {
     const int D = 1 << kb, Dg = 1 << kg;
@@ -206,35 +216,53 @@ static void apply_to_columns(std::vector<cd> &Uc, int kb, const std::vector<cd> 
         for (int j = 0; j < kg; ++j)
             if ((m >> j) & 1) off[m] |= 1 << lb[j];
     }
-    double vr[1 << SV_MAX_K], vi[1 << SV_MAX_K];
+    std::vector<double> acc(size_t(2) * Dg * D);
     for (int base = 0; base < D; ++base) {
         if (base & tmask) continue;
-        for (int col = 0; col < D; ++col) {
-            for (int m = 0; m < Dg; ++m) {
-                const size_t e = 2 * (size_t(base | off[m]) * D + col);
-                vr[m] = U[e];
-                vi[m] = U[e + 1];
-            }
-            for (int m = 0; m < Dg; ++m) {
-                double ar = 0, ai = 0;
-                const double *g = G + 2 * size_t(m) * Dg;
-                for (int mp = 0; mp < Dg; ++mp) {
-                    ar += g[2 * mp] * vr[mp] - g[2 * mp + 1] * vi[mp];
-                    ai += g[2 * mp] * vi[mp] + g[2 * mp + 1] * vr[mp];
+        std::fill(acc.begin(), acc.end(), 0.0);
+        for (int m = 0; m < Dg; ++m) {
+            double *__restrict__ out = acc.data() + size_t(2) * m * D;
+            for (int mp = 0; mp < Dg; ++mp) {
+                const double gr = G[2 * (size_t(m) * Dg + mp)], gi = G[2 * (size_t(m) * Dg + mp) + 1];
+                if (gr == 0.0 && gi == 0.0) continue;
+                const double *__restrict__ row = U + size_t(2) * (base | off[mp]) * D;
+                for (int c = 0; c < D; ++c) {
+                    out[2 * c] += gr * row[2 * c] - gi * row[2 * c + 1];
+                    out[2 * c + 1] += gr * row[2 * c + 1] + gi * row[2 * c];
                 }
-                const size_t e = 2 * (size_t(base | off[m]) * D + col);
-                U[e] = ar;
-                U[e + 1] = ai;
             }
         }
+        for (int m = 0; m < Dg; ++m)
+            std::copy(acc.begin() + size_t(2) * m * D, acc.begin() + size_t(2) * (m + 1) * D,
+                      U + size_t(2) * (base | off[m]) * D);
     }
+}
+
+// Embed an m-bit operator V (2^m x 2^m) into m + 1 bits with a new identity
+// bit at local position p (bits >= p shift up by one).
+static void insert_identity_bit(std::vector<cd> &V, int m, int p)
+{
+    const int d = 1 << m, d2 = 2 * d;
+    std::vector<cd> W(size_t(d2) * d2, cd(0));
+    const int lo = (1 << p) - 1;
+    auto spread = [&](int x, int bit) { return ((x & ~lo) << 1) | (bit << p) | (x & lo); };
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+            const cd v = V[size_t(r) * d + c];
+            if (v == cd(0)) continue;
+            W[size_t(spread(r, 0)) * d2 + spread(c, 0)] = v;
+            W[size_t(spread(r, 1)) * d2 + spread(c, 1)] = v;
+        }
+    V.swap(W);
 }
 
 void block_matrix(const sv_gate *g, Block &b)
 {
-    const int D = 1 << b.k;
-    b.m.assign(size_t(D) * D, cd(0));
-    for (int i = 0; i < D; ++i) b.m[size_t(i) * D + i] = 1;
+    // The product is formed on the block bits touched so far (S, ascending):
+    // the block matrix is V (on S) times the identity on the untouched bits,
+    // so early gates act on a small V.
+    std::vector<int> S;               // block-local bits of V, ascending
+    std::vector<cd> V(1, cd(1));      // 1 x 1 identity
     std::vector<cd> G;
     for (int gi : b.members) {
         int sq[SV_MAX_K];
@@ -243,9 +271,37 @@ void block_matrix(const sv_gate *g, Block &b)
         for (int j = 0; j < g[gi].k; ++j) {
             int r = 0;
             while (b.q[r] != sq[j]) ++r;
-            lb[j] = r;
+            // grow S by block bit r if the gate touches it first
+            auto it = std::lower_bound(S.begin(), S.end(), r);
+            if (it == S.end() || *it != r) {
+                const int p = int(it - S.begin());
+                insert_identity_bit(V, int(S.size()), p);
+                S.insert(it, r);
+            }
         }
-        apply_to_columns(b.m, b.k, G, g[gi].k, lb);
+        for (int j = 0; j < g[gi].k; ++j) {
+            int r = 0;
+            while (b.q[r] != sq[j]) ++r;
+            lb[j] = int(std::lower_bound(S.begin(), S.end(), r) - S.begin());
+        }
+        apply_to_columns(V, int(S.size()), G, g[gi].k, lb);
+    }
+    // embed V into the full block: entries agree on the untouched bits
+    const int D = 1 << b.k, m = int(S.size()), d = 1 << m;
+    int smask = 0;
+    for (int r : S) smask |= 1 << r;
+    int dep[1 << SV_MAX_K];  // V index -> block index
+    for (int x = 0; x < d; ++x) {
+        int y = 0;
+        for (int j = 0; j < m; ++j)
+            if ((x >> j) & 1) y |= 1 << S[j];
+        dep[x] = y;
+    }
+    b.m.assign(size_t(D) * D, cd(0));
+    for (int rest = 0; rest < D; ++rest) {
+        if (rest & smask) continue;
+        for (int r = 0; r < d; ++r)
+            for (int c = 0; c < d; ++c) b.m[size_t(rest | dep[r]) * D + (rest | dep[c])] = V[size_t(r) * d + c];
     }
 }
 

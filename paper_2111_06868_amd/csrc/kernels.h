@@ -17,17 +17,19 @@ constexpr int kRedThreads = 256;
 // Register kernel: k <= 3 (k = 4 for complex64), canonical matrix (local bit
 // j <-> sorted_q[j]).  Needs n >= 2 + (number of positions >= 2).
 bool reg_supported(int dtype, int k, const int *sorted_q, int n);
+// psi2 (optional): a second state of the same size and type that receives
+// the same block in the same launch (gridDim.y = 2).
 hipError_t launch_reg(int dtype, int k, const int *sorted_q, const cd *m, void *psi, int n,
-                      hipStream_t st, int grid_cap);
+                      hipStream_t st, int grid_cap, void *psi2 = nullptr);
 // Generic kernel: k = 1..6, canonical matrix already on the device in the
 // state's real type (interleaved re, im).
 hipError_t launch_generic(int dtype, int k, const int *sorted_q, const void *d_m, void *psi, int n,
-                          hipStream_t st);
+                          hipStream_t st, void *psi2 = nullptr);
 // Dense-block MFMA kernels (complex64 state).  k = 4..6, n - k >= 5.
 bool mfma_supported(int k, int n);
 // FP32: d_a = real-form matrix (2^(k+1) x 2^(k+1) floats, see mfma.hip).
 hipError_t launch_mfma_f32(int k, const int *sorted_q, const float *d_a, void *psi, int n,
-                           hipStream_t st, int tc_log, int grid_cap);
+                           hipStream_t st, int tc_log, int grid_cap, void *psi2 = nullptr);
 // Split precision: d_ahi / d_alo = hi and lo parts of the real-form matrix as
 // BF16 (fp16 = false) or FP16 (fp16 = true) bit patterns.
 hipError_t launch_mfma_split(int k, bool fp16, const int *sorted_q, const uint16_t *d_ahi,

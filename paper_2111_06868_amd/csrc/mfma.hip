@@ -54,6 +54,7 @@ constexpr int kMaxTileBits = 6 + 7;
 
 struct MfmaArgs {
     uint64_t n_tiles;
+    float *psi2;                 // second state for gridDim.y = 2 (FP32 kernel: same block on both)
     int kpos[SV_MAX_K];          // block positions, ascending
     int ubit[kMaxTileBits];      // tile-linear bit b -> global position
     int lweight[kMaxTileBits];   // tile-linear bit b -> LDS element offset
@@ -104,8 +105,9 @@ struct F32Cfg {
 
 template <int K, int TCL>
 __global__ void __launch_bounds__((F32Cfg<K, TCL>::THREADS))
-    k_mfma_f32(float *__restrict__ psi, const float *__restrict__ A, const MfmaArgs args)
+    k_mfma_f32(float *__restrict__ psi0, const float *__restrict__ A, const MfmaArgs args)
 {
+    float *__restrict__ psi = blockIdx.y ? args.psi2 : psi0;
     using C = F32Cfg<K, TCL>;
     __shared__ float2 X[C::R * C::P];
     const int tid = threadIdx.x;
@@ -404,12 +406,13 @@ unsigned grid_for(uint64_t n_tiles, int cap)
 }
 
 template <int K, int TCL>
-hipError_t f32_launch(const int *q, const float *d_a, float *psi, int n, hipStream_t st, int cap)
+hipError_t f32_launch(const int *q, const float *d_a, float *psi, float *psi2, int n, hipStream_t st, int cap)
 {
     MfmaArgs a;
     if (fill_args(K, TCL, q, n, a)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_mfma_f32<K, TCL>), dim3(grid_for(a.n_tiles, cap)), dim3(F32Cfg<K, TCL>::THREADS), 0, st,
-                       psi, d_a, a);
+    a.psi2 = psi2;
+    hipLaunchKernelGGL((k_mfma_f32<K, TCL>), dim3(grid_for(a.n_tiles, cap), psi2 ? 2 : 1), dim3(F32Cfg<K, TCL>::THREADS),
+                       0, st, psi, d_a, a);
     return hipGetLastError();
 }
 
@@ -419,6 +422,7 @@ hipError_t split_launch(const int *q, const uint16_t *hi, const uint16_t *lo, fl
 {
     MfmaArgs a;
     if (fill_args(K, TCL, q, n, a)) return hipErrorInvalidValue;
+    a.psi2 = nullptr;
     hipLaunchKernelGGL((k_mfma_split<K, TCL, F16>), dim3(grid_for(a.n_tiles, cap)),
                        dim3(SplitCfg<K, TCL>::THREADS), 0, st, psi, hi, lo, a);
     return hipGetLastError();
@@ -498,13 +502,13 @@ void pack_real_form_split(const cd *m, int k, bool fp16, uint16_t *hi, uint16_t 
 }
 
 hipError_t launch_mfma_f32(int k, const int *q, const float *d_a, void *psi, int n, hipStream_t st, int tcl,
-                           int cap)
+                           int cap, void *psi2)
 {
     if (!mfma_supported(k, n)) return hipErrorInvalidValue;
     if (tcl > n - k) tcl = n - k;
-    float *p = static_cast<float *>(psi);
+    float *p = static_cast<float *>(psi), *p2 = static_cast<float *>(psi2);
 #define SV_F32_CASE(KK, TT) \
-    if (k == KK && tcl == TT) return f32_launch<KK, TT>(q, d_a, p, n, st, cap);
+    if (k == KK && tcl == TT) return f32_launch<KK, TT>(q, d_a, p, p2, n, st, cap);
     SV_F32_CASE(4, 5) SV_F32_CASE(4, 6) SV_F32_CASE(4, 7)
     SV_F32_CASE(5, 5) SV_F32_CASE(5, 6) SV_F32_CASE(5, 7)
     SV_F32_CASE(6, 5) SV_F32_CASE(6, 6)

@@ -112,6 +112,10 @@ void group_tile_passes(const std::vector<Block> &blocks, int n, int precision, s
 // Enqueue the launches on `st` with device operands at `arena`.
 int enqueue(const std::vector<Launch> &launches, int dtype, void *psi, int n, const void *arena,
             hipStream_t st);
+// psi2 (optional): a second state that receives every launch too (one
+// launch covering both where the kernel supports it).
+int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, const void *arena, hipStream_t st,
+            void *psi2 = nullptr);
 
 }  // namespace sv
 

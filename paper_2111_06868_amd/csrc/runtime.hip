@@ -371,9 +371,22 @@ void group_tile_passes(const std::vector<Block> &blocks, int n, int precision, s
 
 int enqueue(const std::vector<Launch> &launches, int dtype, void *psi, int n, const void *arena, hipStream_t st)
 {
+    return enqueue(launches.data(), launches.size(), dtype, psi, n, arena, st);
+}
+
+int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, const void *arena, hipStream_t st,
+            void *psi2)
+{
     const char *A = static_cast<const char *>(arena);
     const Tuning &T = tuning();
-    for (const auto &L : launches) {
+    for (const Launch *it = first; it != first + count; ++it) {
+        const Launch &L = *it;
+        if (psi2 && L.path != PATH_REG && L.path != PATH_GENERIC && L.path != PATH_MFMA32) {
+            // paths without a second-state launch: one launch per state
+            if (int rc = enqueue(it, 1, dtype, psi, n, arena, st)) return rc;
+            if (int rc = enqueue(it, 1, dtype, psi2, n, arena, st)) return rc;
+            continue;
+        }
         if (L.path == PATH_TILE || L.path == PATH_TILE_BF16) {
             // one launch per chunk of blocks whose operands fit the shape's LDS
             const int cap = dev::tile_max_blocks(T.tile_bits, T.tile_waves);
@@ -393,11 +406,11 @@ int enqueue(const std::vector<Launch> &launches, int dtype, void *psi, int n, co
         LaunchTimer timer(stat_class(path_family(L.path), L.k), st);
         hipError_t e = hipSuccess;
         switch (L.path) {
-        case PATH_REG: e = dev::launch_reg(dtype, L.k, L.q, L.m.data(), psi, n, st, T.reg_grid_cap[L.k]); break;
-        case PATH_GENERIC: e = dev::launch_generic(dtype, L.k, L.q, A + L.arena_off, psi, n, st); break;
+        case PATH_REG: e = dev::launch_reg(dtype, L.k, L.q, L.m.data(), psi, n, st, T.reg_grid_cap[L.k], psi2); break;
+        case PATH_GENERIC: e = dev::launch_generic(dtype, L.k, L.q, A + L.arena_off, psi, n, st, psi2); break;
         case PATH_MFMA32:
             e = dev::launch_mfma_f32(L.k, L.q, reinterpret_cast<const float *>(A + L.arena_off), psi, n, st,
-                                     T.mfma_tc_log[L.k], T.mfma_grid_cap[L.k]);
+                                     T.mfma_tc_log[L.k], T.mfma_grid_cap[L.k], psi2);
             break;
         default:
             e = dev::launch_mfma_split(L.k, L.path == PATH_SPLIT_FP16, L.q,
