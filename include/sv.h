@@ -324,6 +324,12 @@ int sv_set_cost_table(int n, int precision, const double *cost_ms);
  * picks one itself; this call overrides it for the whole process (later
  * launches on every state).  SV_ERR_ARG for other pairs. */
 int sv_set_tile_shape(int tile_bits, int waves);
+/* Position limit of the passes that SV_RULE_TILED plans (8..10; default 10,
+ * or the SV_TILE_UNION environment variable at load time).  A larger union
+ * holds more gates per pass but leaves shorter contiguous runs in HBM
+ * (2^(tile_bits - union) amplitudes).  Applies to later sv_fuse /
+ * sv_run_circuit calls in the process.  SV_ERR_ARG outside 8..10. */
+int sv_set_tile_union(int max_positions);
 
 /* ---------------------------------------------------------------- stats */
 /* Per-kernel device timing.  While enabled every kernel launch is bracketed

@@ -25,7 +25,7 @@ from ._native import (C64, C128, PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16, PR
                       SvValueError)
 
 __all__ = ["State", "Plan", "fuse", "gate_matrix", "backward", "Energy", "Batch", "positions",
-           "pauli_sum", "autotune", "set_cost_table", "set_tile_shape", "TILE_SHAPES",
+           "pauli_sum", "autotune", "set_cost_table", "set_tile_shape", "set_tile_union", "TILE_SHAPES",
            "stats_enable", "stats_reset", "stats_query",
            "C64", "C128", "PREC_FP32", "PREC_SPLIT_BF16", "PREC_SPLIT_FP16", "PREC_FP64",
            "RULE_PAPER", "RULE_ENHANCED", "RULE_NONE", "RULE_TILED", "RULE_AUTO", "SvError", "SvValueError"]
@@ -476,6 +476,11 @@ def set_tile_shape(tile_bits: int, waves: int) -> None:
     """Launch shape of the tile passes: 2^tile_bits amplitudes per LDS tile,
     `waves` waves per workgroup (one of TILE_SHAPES), for the whole process."""
     N.check(N.lib().sv_set_tile_shape(int(tile_bits), int(waves)))
+
+
+def set_tile_union(max_positions: int) -> None:
+    """Position limit (8..10) of the passes the tiled rule plans."""
+    N.check(N.lib().sv_set_tile_union(int(max_positions)))
 
 
 def stats_enable(on: bool = True) -> None:

@@ -116,6 +116,7 @@ SIGNATURES = {
     "sv_autotune": (_I, [_P, _I, _D]),
     "sv_set_cost_table": (_I, [_I, _I, _D]),
     "sv_set_tile_shape": (_I, [_I, _I]),
+    "sv_set_tile_union": (_I, [_I]),
     "sv_stats_enable": (_I, [_I]),
     "sv_stats_reset": (_I, []),
     "sv_stats_query": (_I, [_I, _I64P, _D]),

@@ -284,3 +284,12 @@ extern "C" int sv_set_tile_shape(int tile_bits, int waves)
     tuning().tile_waves = waves;
     return SV_OK;
 }
+
+extern "C" int sv_set_tile_union(int max_positions)
+{
+    clear_error();
+    if (max_positions < 8 || max_positions > kTilePassMaxUnion)
+        return fail(SV_ERR_ARG, "tile union %d outside 8..%d", max_positions, kTilePassMaxUnion);
+    set_tile_union_limit(max_positions);
+    return SV_OK;
+}

@@ -266,3 +266,26 @@ def test_enhanced_rule_frontier_counts():
     got = [len(sv.fuse(to_binding(gates), n, k, sv.RULE_ENHANCED)) for k in (4, 5, 6)]
     paper = [len(sv.fuse(to_binding(gates), n, k, sv.RULE_PAPER)) for k in (4, 5, 6)]
     assert all(g < p for g, p in zip(got, paper)), (got, paper)
+
+
+def test_tile_union_setting():
+    """The tiled rule keeps every pass within the configured union limit."""
+    n, gates = wc.config_circuit(2)
+    g = to_binding(gates)
+    counts = {}
+    try:
+        for u in (8, 9, 10):
+            sv.set_tile_union(u)
+            blocks = sv.fuse(g, n, 4, sv.RULE_TILED).blocks(False)
+            unions = {}
+            for b in blocks:
+                if b.tile_pass >= 0:
+                    unions.setdefault(b.tile_pass, set()).update(b.qubits)
+            assert max(len(x) for x in unions.values()) <= u
+            counts[u] = len(unions) + sum(1 for b in blocks if b.tile_pass < 0)
+        for bad in (7, 11, 0):
+            with pytest.raises(ValueError):
+                sv.set_tile_union(bad)
+    finally:
+        sv.set_tile_union(10)
+    assert counts[8] >= counts[9] >= counts[10]

@@ -75,3 +75,29 @@ def test_native_library_is_loaded():
     maps = open("/proc/self/maps").read()
     assert os.path.realpath(_native.LIB_PATH) in maps
     assert L.sv_version() >= 1
+
+
+def test_batch_edge_trajectories():
+    """Boundary sizes of the two batch paths (13: LDS-resident; 14: one tile;
+    22: 256 tiles), trajectories without gates or with one gate."""
+    rng = np.random.default_rng(91)
+    G = wc.Gate
+    trajs = [
+        (13, []),
+        (14, []),
+        (14, [G("X", (0,))]),
+        (15, [G("FSIM", (3, 14), (0.7, 0.3))]),
+        (22, wc.random_gate_list(22, 40, rng, max_k=2)),
+        (14, wc.random_gate_list(14, 60, rng, max_k=2)),
+    ]
+    b = sv.Batch([(n, to_binding(g)) for n, g in trajs], max_k=3)
+    z = b.run(use_graph=True)
+    for i, (n, gates) in enumerate(trajs):
+        want = ref.simulate(n, gates, "0")
+        got = b.read(i)
+        fe = ref.fidelity_error(want, got)
+        assert fe <= 1e-5, (i, n, fe)
+        assert np.max(np.abs(got - want)) <= 1e-5, (i, n)
+        assert abs(z[i] - ref.z0(want)) <= 1e-5, (i, z[i], ref.z0(want))
+    assert abs(z[1] - 1.0) <= 1e-12 and abs(z[2] + 1.0) <= 1e-12
+    print("[parity] batch edge trajectories ok", flush=True)

@@ -351,6 +351,31 @@ def test_tiled_passes_every_shape(shape, precision, n):
         assert ma <= 1e-5
 
 
+@pytest.mark.parametrize("union", [8, 9, 10])
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_tiled_union_limits(union, precision):
+    """Passes planned with 8, 9 and 10 positions (shorter HBM runs, more blocks)."""
+    n = 17
+    rng = np.random.default_rng(1300 + union)
+    gates = wc.random_gate_list(n, 12 * n, rng, max_k=2)
+    prec = sv.PREC_FP32 if precision == "fp32" else sv.PREC_SPLIT_BF16
+    sv.set_tile_union(union)
+    try:
+        plan = sv.fuse(to_binding(gates), n, 4, sv.RULE_TILED)
+        unions = {}
+        for b in plan.blocks(False):
+            if b.tile_pass >= 0:
+                unions.setdefault(b.tile_pass, set()).update(b.qubits)
+        assert unions and max(len(u) for u in unions.values()) <= union
+        want, got, _ = run_both(n, gates, "+", "c64", max_k=4, rule=sv.RULE_TILED, precision=prec)
+    finally:
+        sv.set_tile_union(10)
+    fe, ma = _report("tiled %s union<=%d n=%d (%d passes)" % (precision, union, n, len(unions)), want, got)
+    assert fe <= FID_C64
+    if precision == "fp32":
+        assert ma <= 1e-5
+
+
 def test_c0_tiled():
     n, gates = wc.config_circuit(0)
     want, got, _ = run_both(n, gates, "0", "c64", max_k=4, rule=sv.RULE_TILED)
