@@ -142,6 +142,18 @@ struct TileCopy {
         for (int i = 0; i < kChunks; ++i)
             *reinterpret_cast<vf4 *>(psi + 2 * (base + g_lo + g_hi[i])) = X4[lds_slot + i * kThreads];
     }
+    // Each slot: store the finished tile's value (at base_out) and put the
+    // next tile's value in its place.  The thread owns its slots, so no
+    // barrier is needed between the two.
+    __device__ __forceinline__ void swap(float *psi, uint64_t base_out, vf4 *X4, const vf4 *buf) const
+    {
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) {
+            const vf4 o = X4[lds_slot + i * kThreads];
+            X4[lds_slot + i * kThreads] = buf[i];
+            *reinterpret_cast<vf4 *>(psi + 2 * (base_out + g_lo + g_hi[i])) = o;
+        }
+    }
 };
 
 // Per-block data staged in LDS: the A operand and the swizzled column terms
@@ -313,11 +325,20 @@ __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__re
     TileCopy<TB, WAVES> cp;
     cp.init(args, tid);
 
+    // A finished tile is written to HBM at the top of the next round, before
+    // that round's prefetch is issued: loads and stores may complete out of
+    // order, so any wait for the prefetch also waits for earlier stores, and
+    // these were issued a whole round of block work earlier.
+    if (T >= T_end) return;  // uniform over the workgroup
     vf4 buf[C::CHUNKS];
-    if (T < T_end) cp.load(buf, psi, tile_base(T, args));
-    for (; T < T_end; T += step) {
+    cp.load(buf, psi, tile_base(T, args));
+    uint64_t prev = 0;
+    for (bool first = true; T < T_end; T += step, first = false) {
         const uint64_t base = tile_base(T, args);
-        cp.to_lds(sh.X4, buf);
+        if (first)
+            cp.to_lds(sh.X4, buf);
+        else
+            cp.swap(psi, prev, sh.X4, buf);
         __syncthreads();  // the first one also publishes the staged blocks
         const uint64_t Tn = T + step;
         if (Tn < T_end) cp.load(buf, psi, tile_base(Tn, args));
@@ -325,9 +346,9 @@ __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__re
             apply_block<TB, WAVES, SPLIT>(sh, args, s, w, half, l32);
             __syncthreads();
         }
-        cp.store(psi, base, sh.X4);
-        __syncthreads();
+        prev = base;
     }
+    cp.store(psi, prev, sh.X4);  // the last tile of this workgroup
 }
 
 // One pass over one state: a persistent grid strides over its tiles.
