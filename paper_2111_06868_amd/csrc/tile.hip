@@ -157,8 +157,11 @@ struct TileCopy {
 };
 
 // Per-block data staged in LDS: the A operand and the swizzled column terms
-// (column c = 32 cb + l: cq[cb] ^ cl[l], with cq[cb] = swz(deposit(32 cb))
-// and cl[l] = swz(deposit(l)) over the block's column bits).
+// of lane l32 and column block cb = w NBW + q of wave w: cq[cb] ^ cl[l32].
+// Column index c (deposited into the block's column bits, ascending):
+// FP32 c = 32 cb + l32; split c = (32 w + l32) NBW + q, which puts q on the
+// lowest column bits, so that when tile bit 0 is a column bit the column
+// blocks q and q + 1 of a lane share one 16-byte slot.
 template <int TB, int WAVES>
 struct TileShared {
     using C = TileCfg<TB, WAVES>;
@@ -206,10 +209,11 @@ __device__ __forceinline__ void stage_blocks(TileShared<TB, WAVES> &sh, const ui
         uint32_t m = 0;
         for (int b = 0; b < 4; ++b) m |= 1u << args.tbit[s][b];
         const uint32_t cmask = ((1u << TB) - 1) & ~m;
+        constexpr int NBW = C::NB_PER_WAVE;
         if (r < C::CBLOCKS)
-            sh.cq[s][r] = swz(deposit(uint32_t(r * 32), cmask));
+            sh.cq[s][r] = swz(deposit(SPLIT ? uint32_t((r / NBW) * 32 * NBW + r % NBW) : uint32_t(r * 32), cmask));
         else
-            sh.cl[s][r - C::CBLOCKS] = swz(deposit(uint32_t(r - C::CBLOCKS), cmask));
+            sh.cl[s][r - C::CBLOCKS] = swz(deposit(uint32_t(r - C::CBLOCKS) * (SPLIT ? NBW : 1), cmask));
     }
 }
 
@@ -221,16 +225,43 @@ __device__ __forceinline__ void lds_st(char *Xb, uint32_t byte_off, float re, fl
     *reinterpret_cast<vf2 *>(Xb + byte_off) = v;
 }
 
+// hi = RNE(v), lo = RNE(v - hi) of one (re, im) pair, as packed bf16 pairs
+__device__ __forceinline__ void split_pair(float re, float im, bf16x2 &hi, bf16x2 &lo)
+{
+    vf2 v;
+    v.x = re;
+    v.y = im;
+    hi = __builtin_convertvector(v, bf16x2);
+    lo = __builtin_convertvector(v - __builtin_convertvector(hi, vf2), bf16x2);
+}
+
+__device__ __forceinline__ void lds_st4(char *Xb, uint32_t byte_off, float a, float b, float c, float d)
+{
+    vf4 v;
+    v.x = a;
+    v.y = b;
+    v.z = c;
+    v.w = d;
+    *reinterpret_cast<vf4 *>(Xb + byte_off) = v;
+}
+
 // One block of the pass on the tile in LDS.  D real row = 8 (v / 4) + 4 half
 // + v % 4: acc[4 g + 2 e] and acc[4 g + 2 e + 1] are (re, im) of complex row
 // 4 g + 2 half + e.  Each wave owns its columns, so its reads of the block
 // precede its writes; the caller places the barrier.
+//
+// FP32: lane (half, l32) reads re (half 0) or im (half 1) of complex row j,
+// one 4-byte read per row and column block.  Split: every LDS access moves
+// 16 bytes, two complex values that differ in tile bit 0.  If tile bit 0 is
+// the block's row bit 0, these are rows (t, t + 1) of one column; otherwise
+// tile bit 0 is the lowest column bit, i.e. column blocks (q, q + 1).
 template <int TB, int WAVES, bool SPLIT>
 __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const TileArgs &args, int s, int w, int half,
                                             int l32)
 {
     using C = TileCfg<TB, WAVES>;
     constexpr int NBW = C::NB_PER_WAVE;
+    static_assert(NBW % 2 == 0, "column blocks come in pairs");
     char *Xb = reinterpret_cast<char *>(sh.X4);
     uint32_t rb[4];
 #pragma unroll
@@ -267,40 +298,94 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
                 const float b = *reinterpret_cast<const float *>(Xb + ((row_of(rb, j) << 3) ^ lq[q]));
                 acc[q] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[j], b, acc[q], 0, 0, 0);
             }
-    } else {
-        // step i (K = 16 i .. 16 i + 15): hi fragment ap[i], lo fragment ap[2 + i]
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const vf4 fh = ap[i], fl = ap[2 + i];
-            bf16x8 xah, xal;
-            __builtin_memcpy(&xah, &fh, 16);
-            __builtin_memcpy(&xal, &fl, 16);
+        for (int q = 0; q < NBW; ++q)
 #pragma unroll
-            for (int q = 0; q < NBW; ++q) {
-                // (re, im) pairs split as packed pairs: hi = RNE(v), lo = RNE(v - hi)
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+                for (int e = 0; e < 2; ++e)
+                    lds_st(Xb, (row_of(rb, 4 * g + e) << 3) ^ wq[q], acc[q][4 * g + 2 * e],
+                           acc[q][4 * g + 2 * e + 1]);
+        return;
+    }
+    // split: step i (K = 16 i .. 16 i + 15) uses hi fragment ap[i] and lo
+    // fragment ap[2 + i]; products Ah Xh + Ah Xl + Al Xh
+    bf16x8 xh[2], xl[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const vf4 fh = ap[i], fl = ap[2 + i];
+        __builtin_memcpy(&xh[i], &fh, 16);
+        __builtin_memcpy(&xl[i], &fl, 16);
+    }
+    if (args.tbit[s][0] == 0) {  // uniform: rows (t, t + 1) share a slot
+#pragma unroll
+        for (int q = 0; q < NBW; ++q) {
+            vf4 raw[4];  // rows 8 i + 2 k2 + {0, 1} (plus 4 half) at raw[2 i + k2]
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                raw[k] = *reinterpret_cast<const vf4 *>(Xb + ((row_of(rb, 8 * (k >> 1) + 2 * (k & 1)) << 3) ^ lq[q]));
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
                 bf16x2 ph[4], pl[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const vf2 v = *reinterpret_cast<const vf2 *>(Xb + ((row_of(rb, 8 * i + t) << 3) ^ lq[q]));
-                    ph[t] = __builtin_convertvector(v, bf16x2);
-                    pl[t] = __builtin_convertvector(v - __builtin_convertvector(ph[t], vf2), bf16x2);
+                for (int k2 = 0; k2 < 2; ++k2) {
+                    const vf4 r = raw[2 * i + k2];
+                    split_pair(r.x, r.y, ph[2 * k2], pl[2 * k2]);
+                    split_pair(r.z, r.w, ph[2 * k2 + 1], pl[2 * k2 + 1]);
                 }
                 bf16x8 bh, bl;
                 __builtin_memcpy(&bh, ph, 16);
                 __builtin_memcpy(&bl, pl, 16);
-                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah, bh, acc[q], 0, 0, 0);
-                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xah, bl, acc[q], 0, 0, 0);
-                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xal, bh, acc[q], 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bh, acc[q], 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bl, acc[q], 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], bh, acc[q], 0, 0, 0);
             }
         }
+        // rows 4 g + 2 half + {0, 1} are acc[4 g .. 4 g + 3]
+#pragma unroll
+        for (int q = 0; q < NBW; ++q)
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+                lds_st4(Xb, (row_of(rb, 4 * g) << 3) ^ wq[q], acc[q][4 * g], acc[q][4 * g + 1], acc[q][4 * g + 2],
+                        acc[q][4 * g + 3]);
+    } else {  // column blocks (q, q + 1) share a slot
+#pragma unroll
+        for (int q = 0; q < NBW; q += 2) {
+            vf4 raw[8];  // row 8 i + t (plus 4 half) at raw[4 i + t]: (q, q + 1)
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                raw[k] = *reinterpret_cast<const vf4 *>(Xb + ((row_of(rb, 8 * (k >> 2) + (k & 3)) << 3) ^ lq[q]));
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                bf16x2 ph0[4], pl0[4], ph1[4], pl1[4];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const vf4 r = raw[4 * i + t];
+                    split_pair(r.x, r.y, ph0[t], pl0[t]);
+                    split_pair(r.z, r.w, ph1[t], pl1[t]);
+                }
+                bf16x8 bh0, bl0, bh1, bl1;
+                __builtin_memcpy(&bh0, ph0, 16);
+                __builtin_memcpy(&bl0, pl0, 16);
+                __builtin_memcpy(&bh1, ph1, 16);
+                __builtin_memcpy(&bl1, pl1, 16);
+                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bh0, acc[q], 0, 0, 0);
+                acc[q + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bh1, acc[q + 1], 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bl0, acc[q], 0, 0, 0);
+                acc[q + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bl1, acc[q + 1], 0, 0, 0);
+                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], bh0, acc[q], 0, 0, 0);
+                acc[q + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], bh1, acc[q + 1], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NBW; q += 2)
+#pragma unroll
+            for (int g = 0; g < 4; ++g)
+#pragma unroll
+                for (int e = 0; e < 2; ++e)
+                    lds_st4(Xb, (row_of(rb, 4 * g + e) << 3) ^ wq[q], acc[q][4 * g + 2 * e],
+                            acc[q][4 * g + 2 * e + 1], acc[q + 1][4 * g + 2 * e], acc[q + 1][4 * g + 2 * e + 1]);
     }
-#pragma unroll
-    for (int q = 0; q < NBW; ++q)
-#pragma unroll
-        for (int g = 0; g < 4; ++g)
-#pragma unroll
-            for (int e = 0; e < 2; ++e)
-                lds_st(Xb, (row_of(rb, 4 * g + e) << 3) ^ wq[q], acc[q][4 * g + 2 * e], acc[q][4 * g + 2 * e + 1]);
 }
 
 // The tile loop of one workgroup: tiles T, T + step, .. below T_end of the
