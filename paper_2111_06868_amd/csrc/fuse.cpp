@@ -43,9 +43,11 @@ CostTable default_costs()
     t.valid = true;
     const double c[SV_MAX_K + 1] = {0.0, 1.0, 1.0, 1.0, 1.02, 1.1, 1.6};
     std::memcpy(t.ms, c, sizeof c);
-    // a tile pass is one state pass plus in-LDS work per 4-qubit block
+    // a tile pass is one state pass plus in-LDS work per 4-qubit block; one
+    // block in a tile pass costs a little less than alone (the tile's HBM
+    // copy runs at a higher rate than the dense kernels' strided access)
     t.tile[0] = 0;
-    for (int s = 1; s <= kTilePassMaxBlocks; ++s) t.tile[s] = 1.05 + 0.1 * s;
+    for (int s = 1; s <= kTilePassMaxBlocks; ++s) t.tile[s] = 0.9 + 0.07 * s;
     return t;
 }
 
@@ -450,8 +452,15 @@ std::vector<std::vector<size_t>> tile_groups(const std::vector<Block> &blocks, i
 double tiled_plan_cost(const std::vector<Block> &blocks, int n, const CostTable &cost)
 {
     double c = 0;
-    for (const auto &grp : tile_groups(blocks, n))
-        c += grp.size() == 1 ? cost.ms[blocks[grp[0]].k] : cost.tile[grp.size()];
+    for (const auto &grp : tile_groups(blocks, n)) {
+        if (grp.size() > 1) {
+            c += cost.tile[grp.size()];
+            continue;
+        }
+        // a block alone runs as a one-block tile pass where that is cheaper
+        const int k = blocks[grp[0]].k;
+        c += k <= 4 && n >= 14 ? std::min(cost.ms[k], cost.tile[1]) : cost.ms[k];
+    }
     return c;
 }
 

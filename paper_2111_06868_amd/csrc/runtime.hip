@@ -347,9 +347,13 @@ void tile_pass_blocks(const Block *const *blocks, int count, int n, int (*sub_po
 void group_tile_passes(const std::vector<Block> &blocks, int n, int precision, std::vector<Launch> &out)
 {
     out.clear();
+    const CostTable cost = lookup_costs(n, precision, nullptr);
     for (const auto &grp : tile_groups(blocks, n)) {
-        if (grp.size() == 1) {
-            const Block &b = blocks[grp[0]];
+        // a block alone: its own dense launch, or a tile pass of one block
+        // where that is priced lower
+        const Block &b0 = blocks[grp[0]];
+        if (grp.size() == 1 && !(b0.k <= 4 && dev::tile_supported(n, 4) && cost.tile[1] < cost.ms[b0.k])) {
+            const Block &b = b0;
             Launch L;
             L.k = b.k;
             std::copy(b.q, b.q + SV_MAX_K, L.q);
