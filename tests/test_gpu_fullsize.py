@@ -6,9 +6,11 @@ benchmark times (fused, enhanced rule, k <= 5, FP32 MFMA).
   run (fidelity, norm, first 2^20 amplitudes).
 * 32 qubits: the 632-gate circuit with k = 4..6 blocks in FP32 and in split
   BF16 / FP16 against a complex128 GPU run.
+* 34 qubits: tile passes (split BF16 and FP32) on a 12-qubit circuit spread
+  over the positions, every amplitude of its support against the oracle.
 * 20-qubit ansatz: adjoint gradients against oracle parameter shift and
   finite differences on sampled parameters.
-These need a large GPU (up to 96 GiB) and host memory (up to 24 GiB)."""
+These need a large GPU (up to 128 GiB) and host memory (up to 24 GiB)."""
 import math
 
 import numpy as np
@@ -76,6 +78,41 @@ def test_34q_high_positions_64bit_indexing():
     M = wc.haar_unitary_from_seed(9, 5)
     st.run([("MATRIX", (33, 31, 29, 2, 0), (), -1, M)], max_k=5, rule=sv.RULE_ENHANCED)
     assert abs(st.norm2() - 1) <= 1e-5
+    st.free()
+    del st
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision,tol_fe,tol_abs,tol_norm", [
+    (sv.PREC_SPLIT_BF16, 1e-7, 5e-5, 1e-4),
+    (sv.PREC_FP32, 1e-10, 1e-6, 1e-5),
+])
+def test_34q_tile_passes_vs_oracle(precision, tol_fe, tol_abs, tol_norm):
+    """Tile passes (the benchmark's launch configuration: tiled rule, k <= 4)
+    on a 34-qubit complex64 state (128 GiB).  A 12-qubit random circuit is
+    placed on positions spread from 0 to 33, so the result is a 12-qubit state
+    times |0..0> on the other 22 positions: the oracle's 12-qubit result fixes
+    every amplitude.  All 4096 amplitudes of the support are compared one by
+    one, and the norm shows that nothing leaked outside it."""
+    import torch
+    torch.cuda.empty_cache()
+    n = 34
+    pos = (0, 3, 7, 12, 16, 19, 23, 26, 28, 30, 32, 33)
+    m = len(pos)
+    small = wc.random_gate_list(m, 160, np.random.default_rng(34), max_k=2)
+    gates = [wc.Gate(g.name, tuple(pos[q] for q in g.qubits), g.params) for g in small]
+    plan = sv.fuse(to_binding(gates), n, 4, sv.RULE_TILED).blocks(False)
+    assert sum(1 for b in plan if b.tile_pass >= 0) >= 2 * len(set(b.tile_pass for b in plan if b.tile_pass >= 0))
+    want = ref.simulate(m, small)
+    st = sv.State(n, "c64")
+    st.run(to_binding(gates), max_k=4, rule=sv.RULE_TILED, precision=precision)
+    idx = [sum(((j >> b) & 1) << pos[b] for b in range(m)) for j in range(1 << m)]
+    got = np.array([st.read(i, 1)[0] for i in idx], dtype=np.complex128)
+    fe = ref.fidelity_error(want, got)
+    ma = ref.max_abs(want, got)
+    nd = abs(st.norm2() - 1)
+    print("[parity] 34q tile passes precision=%d: 1-F=%.3e max_abs=%.3e |norm-1|=%.3e" % (precision, fe, ma, nd))
+    assert fe <= tol_fe and ma <= tol_abs and nd <= tol_norm
     st.free()
     del st
     torch.cuda.empty_cache()
