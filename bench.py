@@ -352,7 +352,10 @@ def bench_trajectories(args):
     import paper_2111_06868_amd as sv
     from workloads import circuits as wc
     trajs = wc.trajectory_batch()
-    b = sv.Batch([(t.n, [(g.name, g.qubits, g.params) for g in t.gates]) for t in trajs], max_k=-1)
+    # tile passes of the trajectories with >= 14 qubits: split BF16 unless --precision fp32
+    prec = sv.PREC_FP32 if args.precision == "fp32" else sv.PREC_SPLIT_BF16
+    b = sv.Batch([(t.n, [(g.name, g.qubits, g.params) for g in t.gates]) for t in trajs], max_k=-1,
+                 precision=prec)
     out = {}
 
     def step():
@@ -363,7 +366,8 @@ def bench_trajectories(args):
     print(json.dumps({"metric": "noisy trajectories/s (512 trajectories, 10..22 qubits)",
                       "value": round(len(trajs) / t, 2), "unit": "trajectories/s", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t, 3),
-                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": "f32" if prec == sv.PREC_FP32 else "f32; bf16 hi+lo split tile passes (n >= 14)",
                       "data": "synthetic",
                       "config": {"workload": "512 ladder random circuits, n~U{10..22}, depth~U{8..24}, "
                                              "2q depolarizing p=1e-3 sampled per trajectory",

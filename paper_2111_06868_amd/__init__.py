@@ -405,7 +405,9 @@ class Batch:
     """Many trajectories of different qubit counts run together
     (sv_batch_create / sv_batch_run)."""
 
-    def __init__(self, circuits, max_k: int = -1, stream=None):
+    def __init__(self, circuits, max_k: int = -1, stream=None, precision: int = PREC_FP32):
+        """precision: PREC_FP32 or PREC_SPLIT_BF16 for the tile passes of the
+        trajectories with 14 or more qubits."""
         torch = _torch()
         circuits = list(circuits)
         self.n_qubits = np.array([int(n) for n, _ in circuits], dtype=np.int32)
@@ -422,6 +424,7 @@ class Batch:
         d.n_qubits = self.n_qubits.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
         d.gate_offsets = self.offsets.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
         d.gates = self.gates.ptr
+        d.precision = int(precision)
         self.desc = d
         need = ctypes.c_size_t()
         N.check(N.lib().sv_batch_required_bytes(ctypes.byref(d), ctypes.byref(need)))

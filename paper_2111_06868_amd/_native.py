@@ -64,7 +64,7 @@ class sv_batch_desc(ctypes.Structure):
     _fields_ = [("n_traj", ctypes.c_int32), ("max_k", ctypes.c_int32),
                 ("n_qubits", ctypes.POINTER(ctypes.c_int32)),
                 ("gate_offsets", ctypes.POINTER(ctypes.c_int64)),
-                ("gates", ctypes.POINTER(sv_gate))]
+                ("gates", ctypes.POINTER(sv_gate)), ("precision", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p

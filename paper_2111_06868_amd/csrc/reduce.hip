@@ -71,6 +71,28 @@ __global__ void __launch_bounds__(kRedThreads) k_norm(const T *__restrict__ psi,
     block_reduce_store<1>(a, partials + blockIdx.x);
 }
 
+// complex64 norm: each thread takes 4 consecutive 16-byte pairs of
+// amplitudes per step (4 loads in flight), in a fixed assignment
+__global__ void __launch_bounds__(kRedThreads) k_norm_c64(const float4 *__restrict__ psi, uint64_t N4,
+                                                          double *partials)
+{
+    Acc<1> a{{0.0}};
+    constexpr uint64_t kStep = uint64_t(kRedBlocks) * kRedThreads * 4;
+    for (uint64_t i0 = (uint64_t(blockIdx.x) * kRedThreads + threadIdx.x) * 4; i0 < N4; i0 += kStep) {
+        float4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = i0 + u < N4 ? psi[i0 + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a.v[0] = fma(double(v[u].x), double(v[u].x), a.v[0]);
+            a.v[0] = fma(double(v[u].y), double(v[u].y), a.v[0]);
+            a.v[0] = fma(double(v[u].z), double(v[u].z), a.v[0]);
+            a.v[0] = fma(double(v[u].w), double(v[u].w), a.v[0]);
+        }
+    }
+    block_reduce_store<1>(a, partials + blockIdx.x);
+}
+
 template <typename A, typename B>
 __global__ void __launch_bounds__(kRedThreads) k_inner(const A *__restrict__ a, const B *__restrict__ b, uint64_t N,
                                                       double *partials)
@@ -168,7 +190,10 @@ __global__ void __launch_bounds__(kRedThreads) k_final(const double *__restrict_
 hipError_t launch_norm(int dtype, const void *psi, int n, double *d_partials, double *d_out, hipStream_t st)
 {
     const uint64_t N = uint64_t(1) << n;
-    if (dtype == SV_C64)
+    if (dtype == SV_C64 && n >= 1)
+        hipLaunchKernelGGL(k_norm_c64, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<const float4 *>(psi), N / 2,
+                           d_partials);
+    else if (dtype == SV_C64)
         hipLaunchKernelGGL(k_norm<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<const float *>(psi), N, d_partials);
     else
         hipLaunchKernelGGL(k_norm<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<const double *>(psi), N, d_partials);

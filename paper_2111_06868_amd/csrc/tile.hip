@@ -583,11 +583,15 @@ hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a,
 }
 
 hipError_t launch_tile_batch(const TileUnit *units, int n_units, const TilePass *passes, const uint32_t *pool,
-                             void *buf, hipStream_t st)
+                             void *buf, hipStream_t st, bool split_bf16)
 {
     if (n_units <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_tile_batch<kBatchTileBits, kBatchTileWaves, false>), dim3(unsigned(n_units)),
-                       dim3(64 * kBatchTileWaves), 0, st, units, passes, pool, static_cast<float *>(buf));
+    if (split_bf16)
+        hipLaunchKernelGGL((k_tile_batch<kBatchTileBits, kBatchTileWaves, true>), dim3(unsigned(n_units)),
+                           dim3(64 * kBatchTileWaves), 0, st, units, passes, pool, static_cast<float *>(buf));
+    else
+        hipLaunchKernelGGL((k_tile_batch<kBatchTileBits, kBatchTileWaves, false>), dim3(unsigned(n_units)),
+                           dim3(64 * kBatchTileWaves), 0, st, units, passes, pool, static_cast<float *>(buf));
     return hipGetLastError();
 }
 

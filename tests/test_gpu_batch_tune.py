@@ -31,11 +31,30 @@ def test_batch_small_vs_oracle(max_k, use_graph):
     print("[parity] batch max_k=%s graph=%s ok" % (max_k, use_graph), flush=True)
 
 
-def test_batch_full_size_sampled():
+@pytest.mark.parametrize("max_k", [3, -1])
+def test_batch_split_bf16_vs_oracle(max_k):
+    """Split-BF16 tile passes for the large trajectories (n >= 14): every
+    state against the oracle, at the split's tolerance."""
+    trajs = wc.trajectory_batch(count=10, root_seed=91, p=0.2, n_range=(12, 18), depth_range=(3, 9))
+    assert sum(1 for t in trajs if t.n >= 14) >= 5
+    b = sv.Batch(_batch_inputs(trajs), max_k=max_k, precision=sv.PREC_SPLIT_BF16)
+    z = b.run(use_graph=True)
+    for i, t in enumerate(trajs):
+        want = ref.simulate(t.n, t.gates, "0")
+        got = b.read(i)
+        fe = ref.fidelity_error(want, got)
+        ma = float(np.max(np.abs(got - want)))
+        assert fe <= 1e-6 and ma <= 1e-4, (i, t.n, fe, ma)
+        assert abs(z[i] - ref.z0(want)) <= 1e-4, (i, z[i], ref.z0(want))
+    print("[parity] batch split bf16 max_k=%s ok" % max_k, flush=True)
+
+
+@pytest.mark.parametrize("precision,tol", [(sv.PREC_FP32, 1e-5), (sv.PREC_SPLIT_BF16, 1e-4)])
+def test_batch_full_size_sampled(precision, tol):
     """The 512-trajectory noisy batch (n in 10..22, depth 8..24, p = 1e-3):
     every trajectory with n <= 15 and six larger ones against the oracle."""
     trajs = wc.trajectory_batch()
-    b = sv.Batch(_batch_inputs(trajs), max_k=-1)
+    b = sv.Batch(_batch_inputs(trajs), max_k=-1, precision=precision)
     z = b.run(use_graph=True)
     z2 = b.run(use_graph=True)
     assert np.array_equal(z, z2)
@@ -46,8 +65,9 @@ def test_batch_full_size_sampled():
     for i in picks:
         want = ref.z0(ref.simulate(trajs[i].n, trajs[i].gates, "0"))
         worst = max(worst, abs(z[i] - want))
-    print("[parity] batch 512: %d sampled, max |dZ0| = %.3e, mean Z0 = %.6f" % (len(picks), worst, z.mean()), flush=True)
-    assert worst <= 1e-5
+    print("[parity] batch 512 precision=%d: %d sampled, max |dZ0| = %.3e, mean Z0 = %.6f"
+          % (precision, len(picks), worst, z.mean()), flush=True)
+    assert worst <= tol
     assert np.all(np.abs(z) <= 1 + 1e-6)
 
 
