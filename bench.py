@@ -332,7 +332,7 @@ def bench_gradient(args):
 
     def step():
         psi.set_basis(0)
-        psi.run(ga, max_k=-1, rule=sv.RULE_ENHANCED)
+        psi.run(ga, max_k=-1, rule=sv.RULE_AUTO)
         out["E"] = psi.expectation(H)
         out["g"] = sv.backward(psi, scratch, ga, H, len(thetas))
 

@@ -2,7 +2,10 @@
 // circuits, reductions, adjoint gradients and timing.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <mutex>
+#include <string>
+#include <thread>
 #include <unordered_map>
 
 #include <algorithm>
@@ -755,20 +758,67 @@ int dagger_launches(const sv_gate *g, int hi, int lo, const sv_state *s, std::ve
     std::vector<Block> blocks;
     const int prec = s->dtype == SV_C64 ? SV_PREC_FP32 : SV_PREC_FP64;
     const CostTable cost = lookup_costs(s->n, prec, nullptr);
-    // block size: the cheapest plan under the cost table (complex64 blocks of
-    // 4..6 qubits run on MFMA; complex128 stays at 4)
-    int kbest = std::max(kmax, 4);
-    if (s->dtype == SV_C64 && s->n >= 11) {
+    // The plan of a run (dense blocks of the cheapest k, or tile passes)
+    // depends on its gates' positions and the cost table only; it is
+    // remembered per run structure, so a sweep with new angles only forms
+    // the block matrices.  A colliding entry can only name another valid plan.
+    uint64_t key = 1469598103934665603ull;
+    auto mix = [&key](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
+    mix(uint64_t(s->n));
+    mix(uint64_t(s->dtype));
+    mix(cost_version());
+    mix(uint64_t(tile_union_limit()));
+    mix(uint64_t(cnt));
+    for (int t = 0; t < cnt; ++t) {
+        mix(uint64_t(dg[t].k));
+        for (int j = 0; j < dg[t].k; ++j) mix(uint64_t(dg[t].q[j]));
+    }
+    static std::mutex memo_mu;
+    static std::unordered_map<uint64_t, int> memo;  // k of the dense plan, or 0 for tile passes
+    int choice = -1;
+    {
+        std::lock_guard<std::mutex> lk(memo_mu);
+        auto it = memo.find(key);
+        if (it != memo.end() && (it->second == 0 ? kmax <= 4 : it->second >= kmax)) choice = it->second;
+    }
+    if (choice < 0) {
+        // block size: the cheapest plan under the cost table (complex64
+        // blocks of 4..6 qubits run on MFMA; complex128 stays at 4), or
+        // tile passes of <= 4-qubit blocks (one launch for both states per
+        // pass) where the cost table prices them lower
+        int kbest = std::max(kmax, 4);
         double best = 1e300;
-        for (int k = std::max(kmax, 4); k <= SV_MAX_K; ++k) {
-            if (int rc = fuse_gates(dg.data(), cnt, s->n, k, SV_RULE_ENHANCED, cost, blocks, false)) return rc;
-            const double c = plan_cost(blocks, cost);
-            if (c < best - 1e-12) {
-                best = c;
-                kbest = k;
+        if (s->dtype == SV_C64 && s->n >= 11) {
+            for (int k = std::max(kmax, 4); k <= SV_MAX_K; ++k) {
+                if (int rc = fuse_gates(dg.data(), cnt, s->n, k, SV_RULE_ENHANCED, cost, blocks, false)) return rc;
+                const double c = plan_cost(blocks, cost);
+                if (c < best - 1e-12) {
+                    best = c;
+                    kbest = k;
+                }
             }
         }
+        choice = kbest;
+        if (s->dtype == SV_C64 && kmax <= 4 && dev::tile_supported(s->n, 4)) {
+            if (best > 1e299) {
+                if (int rc = fuse_gates(dg.data(), cnt, s->n, kbest, SV_RULE_ENHANCED, cost, blocks, false)) return rc;
+                best = plan_cost(blocks, cost);
+            }
+            if (int rc = fuse_gates(dg.data(), cnt, s->n, 4, SV_RULE_TILED, cost, blocks, false)) return rc;
+            if (tiled_plan_cost(blocks, s->n, cost) < best - 1e-12) choice = 0;
+        }
+        std::lock_guard<std::mutex> lk(memo_mu);
+        if (memo.size() > 65536) memo.clear();
+        memo[key] = choice;
     }
+    if (choice == 0) {
+        if (int rc = fuse_gates(dg.data(), cnt, s->n, 4, SV_RULE_TILED, cost, blocks)) return rc;
+        std::vector<Launch> tl;
+        group_tile_passes(blocks, s->n, prec, tl);
+        for (auto &L : tl) out.push_back(std::move(L));
+        return SV_OK;
+    }
+    const int kbest = choice;
     if (int rc = fuse_gates(dg.data(), cnt, s->n, kbest, SV_RULE_ENHANCED, cost, blocks)) return rc;
     for (const auto &b : blocks) {
         Launch L;
@@ -802,6 +852,11 @@ extern "C" int sv_backward(sv_state *psi, sv_state *scratch, const sv_gate *g, i
     std::vector<BwdStep> steps;
     std::vector<Launch> launches;
     std::vector<int> slot_param;
+    struct RunJob {
+        int hi, lo;
+        size_t step;
+    };
+    std::vector<RunJob> jobs;  // dagger runs: gates hi..lo, undone at steps[step]
     int i = G - 1;
     while (i >= 0) {
         if (g[i].param >= 0) {
@@ -824,9 +879,7 @@ extern "C" int sv_backward(sv_state *psi, sv_state *scratch, const sv_gate *g, i
                     st.pw[e] = g[t].kind == SV_G_RY ? 1 : 0;
                     slot_param.push_back(g[t].param);
                 }
-                st.l0 = launches.size();
-                if (int rc = dagger_launches(g, i, j + 1, psi, launches)) return rc;
-                st.l1 = launches.size();
+                jobs.push_back({i, j + 1, steps.size()});
                 steps.push_back(st);
                 i = j;
                 continue;
@@ -852,11 +905,36 @@ extern "C" int sv_backward(sv_state *psi, sv_state *scratch, const sv_gate *g, i
         }
         BwdStep st;
         st.kind = BwdStep::UNDO;
-        st.l0 = launches.size();
-        if (int rc = dagger_launches(g, i, j + 1, psi, launches)) return rc;
-        st.l1 = launches.size();
+        jobs.push_back({i, j + 1, steps.size()});
         steps.push_back(st);
         i = j;
+    }
+    // the dagger blocks of the runs are independent host work: spread over
+    // threads, then appended in sweep order
+    {
+        std::vector<std::vector<Launch>> outs(jobs.size());
+        std::vector<int> rcs(jobs.size(), SV_OK);
+        std::vector<std::string> msgs(jobs.size());
+        std::atomic<size_t> next(0);
+        auto worker = [&]() {
+            for (size_t t; (t = next.fetch_add(1)) < jobs.size();) {
+                rcs[t] = dagger_launches(g, jobs[t].hi, jobs[t].lo, psi, outs[t]);
+                if (rcs[t]) msgs[t] = last_error_cstr();
+            }
+        };
+        const unsigned hw = std::max(1u, std::min(8u, std::thread::hardware_concurrency()));
+        const unsigned nt = jobs.size() >= 16 ? std::min<unsigned>(hw, unsigned(jobs.size() / 4)) : 1u;
+        std::vector<std::thread> pool;
+        for (unsigned t = 1; t < nt; ++t) pool.emplace_back(worker);
+        worker();
+        for (auto &th : pool) th.join();
+        for (size_t t = 0; t < jobs.size(); ++t) {
+            if (rcs[t]) return fail(rcs[t], "%s", msgs[t].c_str());
+            BwdStep &st = steps[jobs[t].step];
+            st.l0 = launches.size();
+            for (auto &L : outs[t]) launches.push_back(std::move(L));
+            st.l1 = launches.size();
+        }
     }
     const int slots = int(slot_param.size());
 

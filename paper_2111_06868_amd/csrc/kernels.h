@@ -87,8 +87,10 @@ bool tile_shape_supported(int tile_bits, int waves);
 int tile_wgs_per_cu(int tile_bits, int waves);
 // Blocks one launch of the shape can hold (their operands sit in LDS).
 int tile_max_blocks(int tile_bits, int waves);
+// psi2 (optional): a second state of the same size that receives the same
+// pass in the same launch (gridDim.y = 2).
 hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a, bool split_bf16, void *psi, int n,
-                            hipStream_t st, int grid_cap, int tile_bits, int waves);
+                            hipStream_t st, int grid_cap, int tile_bits, int waves, void *psi2 = nullptr);
 // Host-side packing of the MFMA operands of a canonical k-qubit matrix.
 void pack_real_form_f32(const cd *m, int k, float *out);
 void pack_real_form_split(const cd *m, int k, bool fp16, uint16_t *hi, uint16_t *lo);

@@ -385,7 +385,8 @@ int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, cons
     const Tuning &T = tuning();
     for (const Launch *it = first; it != first + count; ++it) {
         const Launch &L = *it;
-        if (psi2 && L.path != PATH_REG && L.path != PATH_GENERIC && L.path != PATH_MFMA32) {
+        if (psi2 && L.path != PATH_REG && L.path != PATH_GENERIC && L.path != PATH_MFMA32 && L.path != PATH_TILE &&
+            L.path != PATH_TILE_BF16) {
             // paths without a second-state launch: one launch per state
             if (int rc = enqueue(it, 1, dtype, psi, n, arena, st)) return rc;
             if (int rc = enqueue(it, 1, dtype, psi2, n, arena, st)) return rc;
@@ -401,7 +402,7 @@ int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, cons
                 hipError_t e = dev::launch_tile_pass(m, L.sub_pos + c, A + L.arena_off + c * op_bytes,
                                                      L.path == PATH_TILE_BF16, psi, n, st,
                                                      T.tile_grid_cap * dev::tile_wgs_per_cu(T.tile_bits, T.tile_waves),
-                                                     T.tile_bits, T.tile_waves);
+                                                     T.tile_bits, T.tile_waves, psi2);
                 if (e != hipSuccess)
                     return fail(SV_ERR_HIP, "tile pass launch (%d blocks): %s", m, hipGetErrorString(e));
             }

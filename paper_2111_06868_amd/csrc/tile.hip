@@ -436,13 +436,14 @@ __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__re
     cp.store(psi, prev, sh.X4);  // the last tile of this workgroup
 }
 
-// One pass over one state: a persistent grid strides over its tiles.
+// One pass over one state (gridDim.y = 1) or over psi and psi2 alike
+// (gridDim.y = 2): a persistent grid strides over the tiles of its state.
 template <int TB, int WAVES, bool SPLIT>
 __global__ void __launch_bounds__(64 * WAVES) k_tile_pass(float *__restrict__ psi, const uint32_t *__restrict__ A,
-                                                          const TileArgs args)
+                                                          const TileArgs args, float *__restrict__ psi2)
 {
     __shared__ TileShared<TB, WAVES> sh;
-    tile_loop<TB, WAVES, SPLIT>(sh, psi, A, args, blockIdx.x, args.n_tiles, gridDim.x);
+    tile_loop<TB, WAVES, SPLIT>(sh, blockIdx.y ? psi2 : psi, A, args, blockIdx.x, args.n_tiles, gridDim.x);
 }
 
 // Passes of many states in one grid: workgroup i takes tiles [t0, t1) of
@@ -460,15 +461,17 @@ __global__ void __launch_bounds__(64 * WAVES) k_tile_batch(const TileUnit *__res
 }
 
 template <int TB, int WAVES>
-hipError_t tile_launch(const TileArgs &a, const void *d_a, bool split, float *psi, hipStream_t st, int cap)
+hipError_t tile_launch(const TileArgs &a, const void *d_a, bool split, float *psi, float *psi2, hipStream_t st,
+                       int cap)
 {
     uint64_t g = a.n_tiles;
     if (cap > 0 && g > uint64_t(cap)) g = cap;
     const uint32_t *A = static_cast<const uint32_t *>(d_a);
+    const dim3 grid(unsigned(g), psi2 ? 2 : 1);
     if (split)
-        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, true>), dim3(unsigned(g)), dim3(64 * WAVES), 0, st, psi, A, a);
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, true>), grid, dim3(64 * WAVES), 0, st, psi, A, a, psi2);
     else
-        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, false>), dim3(unsigned(g)), dim3(64 * WAVES), 0, st, psi, A, a);
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, false>), grid, dim3(64 * WAVES), 0, st, psi, A, a, psi2);
     return hipGetLastError();
 }
 
@@ -568,18 +571,18 @@ hipError_t make_tile_args(int n_sub, const int (*sub_pos)[4], int n, int tile_bi
 }
 
 hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a, bool split_bf16, void *psi, int n,
-                            hipStream_t st, int grid_cap, int tile_bits, int waves)
+                            hipStream_t st, int grid_cap, int tile_bits, int waves, void *psi2)
 {
     if (!tile_shape_supported(tile_bits, waves)) return hipErrorInvalidValue;
     if (n_sub < 1 || n_sub > tile_max_blocks(tile_bits, waves)) return hipErrorInvalidValue;
     TileArgs a;
     if (hipError_t e = make_tile_args(n_sub, sub_pos, n, tile_bits, &a)) return e;
-    float *p = static_cast<float *>(psi);
+    float *p = static_cast<float *>(psi), *p2 = static_cast<float *>(psi2);
     if (tile_bits == 14)
-        return waves == 16 ? tile_launch<14, 16>(a, d_a, split_bf16, p, st, grid_cap)
-                           : tile_launch<14, 8>(a, d_a, split_bf16, p, st, grid_cap);
-    return waves == 4 ? tile_launch<13, 4>(a, d_a, split_bf16, p, st, grid_cap)
-                      : tile_launch<13, 8>(a, d_a, split_bf16, p, st, grid_cap);
+        return waves == 16 ? tile_launch<14, 16>(a, d_a, split_bf16, p, p2, st, grid_cap)
+                           : tile_launch<14, 8>(a, d_a, split_bf16, p, p2, st, grid_cap);
+    return waves == 4 ? tile_launch<13, 4>(a, d_a, split_bf16, p, p2, st, grid_cap)
+                      : tile_launch<13, 8>(a, d_a, split_bf16, p, p2, st, grid_cap);
 }
 
 hipError_t launch_tile_batch(const TileUnit *units, int n_units, const TilePass *passes, const uint32_t *pool,
