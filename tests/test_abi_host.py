@@ -169,6 +169,39 @@ def test_alloc_rejects_bad_arguments_before_device_work():
     assert h.value is None
 
 
+def test_batch_description_validation():
+    """sv_batch_required_bytes checks the description on the host: sizes
+    (each state 256-byte aligned), precision, max_k, offsets and gates."""
+    L = N.lib()
+    ga = sv.GateArray([("H", (0,)), ("CZ", (0, 1)), ("H", (2,))])
+    nq = np.array([2, 3], dtype=np.int32)
+    offs = np.array([0, 2, 3], dtype=np.int64)
+
+    def desc(**kw):
+        d = N.sv_batch_desc()
+        d.n_traj = 2
+        d.max_k = kw.get("max_k", -1)
+        d.n_qubits = kw.get("nq", nq).ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        d.gate_offsets = kw.get("offs", offs).ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+        d.gates = ga.ptr
+        d.precision = kw.get("precision", 0)
+        return d
+
+    need = ctypes.c_size_t()
+    assert L.sv_batch_required_bytes(ctypes.byref(desc()), ctypes.byref(need)) == N.OK
+    assert need.value == 256 + 256  # 4 and 8 complex64 amplitudes, each padded to 256 bytes
+    assert L.sv_batch_required_bytes(ctypes.byref(desc(precision=sv.PREC_SPLIT_BF16)), ctypes.byref(need)) == N.OK
+    for prec in (sv.PREC_SPLIT_FP16, sv.PREC_FP64, 7):
+        assert L.sv_batch_required_bytes(ctypes.byref(desc(precision=prec)), ctypes.byref(need)) == N.ERR_ARG
+    assert "precision" in L.sv_last_error().decode()
+    assert L.sv_batch_required_bytes(ctypes.byref(desc(max_k=0)), ctypes.byref(need)) == N.ERR_ARG
+    bad_offs = np.array([0, 1, 0], dtype=np.int64)  # trajectory 1 ends before it starts
+    assert L.sv_batch_required_bytes(ctypes.byref(desc(offs=bad_offs)), ctypes.byref(need)) == N.ERR_ARG
+    small = np.array([1, 3], dtype=np.int32)  # CZ on qubit 1 of a 1-qubit trajectory
+    assert L.sv_batch_required_bytes(ctypes.byref(desc(nq=small)), ctypes.byref(need)) == N.ERR_QUBIT
+    assert L.sv_batch_required_bytes(ctypes.byref(desc()), None) == N.ERR_ARG
+
+
 def test_binding_raises_value_error_for_bad_input():
     with pytest.raises(ValueError):
         sv.fuse([("H", (9,))], 4, 2)
