@@ -30,10 +30,10 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 MFMA_FP32_PEAK_TFLOPS = 157.3
 FAMILY_NAMES = {1: "reg", 2: "generic", 3: "mfma_f32", 4: "split_bf16", 5: "split_fp16", 9: "tile",
-                10: "tile_bf16"}
+                10: "tile_bf16", 11: "tile_fp16"}
 KERNEL_SOURCES = {1: "apply.hip", 2: "apply.hip", 3: "mfma.hip", 4: "mfma.hip", 5: "mfma.hip", 9: "tile.hip",
-                  10: "tile.hip"}
-TILE_FAMILIES = (9, 10)
+                  10: "tile.hip", 11: "tile.hip"}
+TILE_FAMILIES = (9, 10, 11)
 
 
 def log(*a):
@@ -202,8 +202,8 @@ def main():
     if dfam in TILE_FAMILIES:
         blocks_per_launch = tile_blocks[dfam] / dcnt
         roofline["blocks_per_launch"] = round(blocks_per_launch, 3)
-        # 8 * 16 flop per amplitude per 4-qubit block; split BF16 runs three products
-        flops = (3 if dfam == 10 else 1) * 8.0 * 16 * (1 << n) * blocks_per_launch
+        # 8 * 16 flop per amplitude per 4-qubit block; split BF16 / FP16 run three products
+        flops = (3 if dfam in (10, 11) else 1) * 8.0 * 16 * (1 << n) * blocks_per_launch
         roofline["mfma_tflops"] = round(flops / (avg_ms * 1e-3) / 1e12, 2)
         if dfam == 9:
             roofline["mfma_frac"] = round(roofline["mfma_tflops"] / MFMA_FP32_PEAK_TFLOPS, 4)

@@ -235,13 +235,17 @@ int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int use_graph);
  * 'evolution')).  Nothing is applied if any gate is invalid.  Asynchronous
  * (synchronises when o->use_graph = 1).  o == NULL means plain per-gate
  * application: {SV_MAX_K, FP32 or FP64 by amplitude type, SV_RULE_NONE, 0}.
- * With SV_RULE_TILED on a complex64 state of >= 14 qubits (FP32 or split
- * precision), up to 4 blocks whose positions span at most 8 qubits are
- * applied together (a later block joins a group only if it commutes past
- * every block it jumps over): each tile of 2^14 amplitudes is staged in LDS
- * once, every block of the group is applied to it with FP32 MFMA (split
- * precisions: hi+lo BF16 MFMA), and the tile is written back, so the group
- * costs one state pass.
+ * With SV_RULE_TILED on a complex64 state of >= 14 qubits, the gates are
+ * grouped into passes whose positions span at most sv_set_tile_union()
+ * positions (default 10), and each pass is fused into blocks of <= 4 qubits
+ * (gates move only where every qubit keeps its own gate order).  Each tile
+ * of 2^14 (or 2^13) amplitudes is staged in LDS once, every block of the
+ * pass is applied to it (SV_PREC_FP32: FP32 MFMA; SV_PREC_SPLIT_BF16 /
+ * SV_PREC_SPLIT_FP16: hi+lo 16-bit MFMA, the FP16 passes holding each tile
+ * scaled by a power of two chosen from its largest magnitude), and the tile
+ * is written back, so a pass costs one read and one write of the state.  A
+ * block left alone runs as a one-block pass where the cost table prices
+ * that lower.
  * SV_RULE_AUTO (with max_k = -1, or max_k as an upper bound) evaluates the
  * enhanced plans for every k and the tiled plans for k <= 4 on block
  * positions only, prices each with the cost table of (n, precision) (from
@@ -342,8 +346,8 @@ int sv_set_tile_union(int max_positions);
  * device milliseconds.  Classes: 100*family + k, families 1 = register
  * apply, 2 = generic apply, 3 = MFMA FP32, 4 = MFMA split BF16, 5 = MFMA split
  * FP16, 6 = reductions, 7 = adjoint, 8 = batch, 9 = FP32 tile passes, 10 =
- * split-BF16 tile passes; k is the block size, or for tile passes the number
- * of blocks in the launch. */
+ * split-BF16 tile passes, 11 = split-FP16 tile passes; k is the block size,
+ * or for tile passes the number of blocks in the launch. */
 int sv_stats_enable(int on);
 int sv_stats_reset(void);
 int sv_stats_query(int cls, int64_t *launches, double *total_ms);

@@ -495,7 +495,7 @@ def stats_reset() -> None:
 
 
 FAMILIES = {"reg": 1, "generic": 2, "mfma_f32": 3, "split_bf16": 4, "split_fp16": 5,
-            "reduce": 6, "adjoint": 7, "batch": 8, "tile": 9, "tile_bf16": 10}
+            "reduce": 6, "adjoint": 7, "batch": 8, "tile": 9, "tile_bf16": 10, "tile_fp16": 11}
 
 
 def stats_query(family: str, k: int):

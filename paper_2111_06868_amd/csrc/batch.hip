@@ -337,7 +337,7 @@ int build_schedule(sv_batch *b, const sv_batch_desc *d, int k)
                     return fail(SV_ERR_ARG, "trajectory %d: tile pass layout", t);
                 pool.resize(pool.size() + size_t(cnt) * dev::kTileOperandWords);
                 for (int i = 0; i < cnt; ++i)
-                    dev::pack_tile_operand(m4.data() + 256 * i, b->split, pool.data() + tp.op_off + dev::kTileOperandWords * i);
+                    dev::pack_tile_operand(m4.data() + 256 * i, b->split ? dev::kTileOperandBF16 : dev::kTileOperandF32, pool.data() + tp.op_off + dev::kTileOperandWords * i);
                 mine.push_back(int(passes.size()));
                 passes.push_back(tp);
             }

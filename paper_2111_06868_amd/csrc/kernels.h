@@ -35,7 +35,7 @@ hipError_t launch_mfma_f32(int k, const int *sorted_q, const float *d_a, void *p
 hipError_t launch_mfma_split(int k, bool fp16, const int *sorted_q, const uint16_t *d_ahi,
                              const uint16_t *d_alo, void *psi, int n, hipStream_t st, int tc_log,
                              int grid_cap);
-// Multi-block tile passes (complex64, FP32 or split-BF16 MFMA): up to
+// Multi-block tile passes (complex64, FP32 or split BF16 / FP16 MFMA): up to
 // tile_max_blocks() 4-qubit blocks whose positions have a union of at most
 // kMaxTileUnion positions, applied in one HBM pass over tiles of
 // 2^tile_bits amplitudes held by workgroups of `waves` waves; shapes
@@ -56,10 +56,12 @@ struct TileArgs {
 };
 // Tile-pass operand of one 4-qubit block (canonical 16 x 16 matrix m), in
 // kTileOperandWords 32-bit words: FP32: Re U then Im U (16 x 16 floats each,
-// row-major); split BF16: the hi then the lo parts of U, one word per entry
-// holding (re, im) as bf16 (re in the low half).
+// row-major); split BF16 / FP16: the hi then the lo parts of U, one word per
+// entry holding (re, im) as 16-bit values (re in the low half).  The
+// precision codes are also the tile passes' arithmetic.
 constexpr int kTileOperandWords = 512;
-void pack_tile_operand(const cd *m, bool split_bf16, uint32_t *out);
+constexpr int kTileOperandF32 = 0, kTileOperandBF16 = 1, kTileOperandF16 = 2;
+void pack_tile_operand(const cd *m, int prec, uint32_t *out);
 // Tile arguments of n_sub blocks (positions ascending per block) on an
 // n-qubit state with 2^tile_bits-amplitude tiles.
 hipError_t make_tile_args(int n_sub, const int (*sub_pos)[4], int n, int tile_bits, TileArgs *out);
@@ -89,7 +91,9 @@ int tile_wgs_per_cu(int tile_bits, int waves);
 int tile_max_blocks(int tile_bits, int waves);
 // psi2 (optional): a second state of the same size that receives the same
 // pass in the same launch (gridDim.y = 2).
-hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a, bool split_bf16, void *psi, int n,
+// prec: kTileOperandF32, kTileOperandBF16 or kTileOperandF16 (FP16 passes
+// hold each tile scaled by a power of two chosen from its largest magnitude).
+hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a, int prec, void *psi, int n,
                             hipStream_t st, int grid_cap, int tile_bits, int waves, void *psi2 = nullptr);
 // Host-side packing of the MFMA operands of a canonical k-qubit matrix.
 void pack_real_form_f32(const cd *m, int k, float *out);

@@ -36,7 +36,7 @@ struct PinBuf {
     ~PinBuf() { release(); }
 };
 
-// Kernel classes for timing (10 * family + k).
+// Kernel families for timing (class = 100 * family + k, see stat_class).
 enum Family {
     FAM_REG = 1,
     FAM_GENERIC = 2,
@@ -48,6 +48,7 @@ enum Family {
     FAM_BATCH = 8,
     FAM_TILE = 9,
     FAM_TILE_BF16 = 10,
+    FAM_TILE_FP16 = 11,
 };
 
 // Statistics class of a launch: 100 * family + k (k = block size, or the
@@ -71,7 +72,10 @@ class LaunchTimer {
 void timing_suspend(bool on);
 
 // Kernel paths for a block.
-enum Path { PATH_REG, PATH_GENERIC, PATH_MFMA32, PATH_SPLIT_BF16, PATH_SPLIT_FP16, PATH_TILE, PATH_TILE_BF16 };
+enum Path { PATH_REG, PATH_GENERIC, PATH_MFMA32, PATH_SPLIT_BF16, PATH_SPLIT_FP16, PATH_TILE, PATH_TILE_BF16, PATH_TILE_FP16 };
+
+// Tile passes: PATH_TILE, PATH_TILE_BF16, PATH_TILE_FP16.
+inline bool is_tile_path(int p) { return p == PATH_TILE || p == PATH_TILE_BF16 || p == PATH_TILE_FP16; }
 
 struct Tuning {
     int reg_grid_cap[SV_MAX_K + 1];   // 0 = one thread per group
@@ -87,13 +91,13 @@ Tuning &tuning();
 Path choose_path(int dtype, int precision, int k, const int *sorted_q, int n);
 int path_family(Path p);
 
-// One block (or, for PATH_TILE, a group of 4-qubit blocks) prepared for launch.
+// One block (or, for a tile path, a group of 4-qubit blocks) prepared for launch.
 struct Launch {
     Path path;
-    int k;                 // PATH_TILE: number of blocks in the group
+    int k;                 // tile paths: number of blocks in the group
     int q[SV_MAX_K];
-    std::vector<cd> m;     // canonical matrix; PATH_TILE: k matrices of 16 x 16
-    int sub_pos[dev::kMaxTileSubBlocks][4] = {};  // PATH_TILE: each block's positions
+    std::vector<cd> m;     // canonical matrix; tile paths: k matrices of 16 x 16
+    int sub_pos[dev::kMaxTileSubBlocks][4] = {};  // tile paths: each block's positions
     size_t arena_off = 0;  // byte offset of device operands (other paths)
     size_t arena_off2 = 0; // second operand (split lo part)
 };
@@ -109,6 +113,10 @@ void tile_pass_blocks(const Block *const *blocks, int count, int n, int (*sub_po
 // Group consecutive blocks into tile passes (see tile.hip); blocks that do not
 // join a group keep their own launch.
 void group_tile_passes(const std::vector<Block> &blocks, int n, int precision, std::vector<Launch> &out);
+// The tile path of a precision (FP32, split BF16, split FP16) and the operand
+// format of a tile path.
+Path tile_path(int precision);
+int tile_operand_prec(int path);
 // Enqueue the launches on `st` with device operands at `arena`.
 int enqueue(const std::vector<Launch> &launches, int dtype, void *psi, int n, const void *arena,
             hipStream_t st);

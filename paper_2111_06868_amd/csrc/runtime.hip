@@ -211,6 +211,7 @@ int path_family(Path p)
     case PATH_SPLIT_BF16: return FAM_SPLIT_BF16;
     case PATH_TILE: return FAM_TILE;
     case PATH_TILE_BF16: return FAM_TILE_BF16;
+    case PATH_TILE_FP16: return FAM_TILE_FP16;
     default: return FAM_SPLIT_FP16;
     }
 }
@@ -235,6 +236,7 @@ size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage)
             break;
         case PATH_TILE:
         case PATH_TILE_BF16:
+        case PATH_TILE_FP16:
             L.arena_off = total;
             total = align256(total + size_t(L.k) * dev::kTileOperandWords * 4);
             break;
@@ -273,8 +275,9 @@ size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage)
             break;
         case PATH_TILE:
         case PATH_TILE_BF16:
+        case PATH_TILE_FP16:
             for (int sb = 0; sb < L.k; ++sb)
-                dev::pack_tile_operand(L.m.data() + 256 * sb, L.path == PATH_TILE_BF16,
+                dev::pack_tile_operand(L.m.data() + 256 * sb, tile_operand_prec(L.path),
                                        reinterpret_cast<uint32_t *>(h + L.arena_off) + dev::kTileOperandWords * sb);
             break;
         default:
@@ -323,6 +326,19 @@ static uint64_t mask_of(const Block &b)
     return m;
 }
 
+Path tile_path(int precision)
+{
+    if (precision == SV_PREC_SPLIT_BF16) return PATH_TILE_BF16;
+    if (precision == SV_PREC_SPLIT_FP16) return PATH_TILE_FP16;
+    return PATH_TILE;
+}
+
+int tile_operand_prec(int path)
+{
+    return path == PATH_TILE_BF16 ? dev::kTileOperandBF16 : path == PATH_TILE_FP16 ? dev::kTileOperandF16
+                                                                                    : dev::kTileOperandF32;
+}
+
 void tile_pass_blocks(const Block *const *blocks, int count, int n, int (*sub_pos)[4], std::vector<cd> &mats)
 {
     uint64_t um = 0;
@@ -363,7 +379,7 @@ void group_tile_passes(const std::vector<Block> &blocks, int n, int precision, s
             continue;
         }
         Launch L;
-        L.path = precision == SV_PREC_SPLIT_BF16 || precision == SV_PREC_SPLIT_FP16 ? PATH_TILE_BF16 : PATH_TILE;
+        L.path = tile_path(precision);
         L.k = int(grp.size());
         std::fill(L.q, L.q + SV_MAX_K, 0);
         std::vector<const Block *> bp;
@@ -385,14 +401,13 @@ int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, cons
     const Tuning &T = tuning();
     for (const Launch *it = first; it != first + count; ++it) {
         const Launch &L = *it;
-        if (psi2 && L.path != PATH_REG && L.path != PATH_GENERIC && L.path != PATH_MFMA32 && L.path != PATH_TILE &&
-            L.path != PATH_TILE_BF16) {
+        if (psi2 && L.path != PATH_REG && L.path != PATH_GENERIC && L.path != PATH_MFMA32 && !is_tile_path(L.path)) {
             // paths without a second-state launch: one launch per state
             if (int rc = enqueue(it, 1, dtype, psi, n, arena, st)) return rc;
             if (int rc = enqueue(it, 1, dtype, psi2, n, arena, st)) return rc;
             continue;
         }
-        if (L.path == PATH_TILE || L.path == PATH_TILE_BF16) {
+        if (is_tile_path(L.path)) {
             // one launch per chunk of blocks whose operands fit the shape's LDS
             const int cap = dev::tile_max_blocks(T.tile_bits, T.tile_waves);
             const size_t op_bytes = 4 * dev::kTileOperandWords;
@@ -400,7 +415,7 @@ int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, cons
                 const int m = std::min(cap, L.k - c);
                 LaunchTimer timer(stat_class(path_family(L.path), m), st);
                 hipError_t e = dev::launch_tile_pass(m, L.sub_pos + c, A + L.arena_off + c * op_bytes,
-                                                     L.path == PATH_TILE_BF16, psi, n, st,
+                                                     tile_operand_prec(L.path), psi, n, st,
                                                      T.tile_grid_cap * dev::tile_wgs_per_cu(T.tile_bits, T.tile_waves),
                                                      T.tile_bits, T.tile_waves, psi2);
                 if (e != hipSuccess)

@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -35,6 +36,12 @@ typedef float vf4 __attribute__((ext_vector_type(4)));
 typedef float vf2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+// Arithmetic of a tile pass: FP32 MFMA, or hi + lo split products in BF16 or
+// FP16 (FP32 accumulation).
+constexpr int kPrecF32 = kTileOperandF32, kPrecBF16 = kTileOperandBF16, kPrecF16 = kTileOperandF16;
 
 constexpr int kOperandWords = 1024;  // LDS words of one block's A fragments: 64 lanes x 16
 
@@ -154,7 +161,58 @@ struct TileCopy {
             *reinterpret_cast<vf4 *>(psi + 2 * (base_out + g_lo + g_hi[i])) = o;
         }
     }
+    // The same with the tile in LDS held scaled: out = LDS * unscale, LDS =
+    // buf * scale (exact powers of two).
+    __device__ __forceinline__ void to_lds_scaled(vf4 *X4, const vf4 *buf, float scale) const
+    {
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) X4[lds_slot + i * kThreads] = buf[i] * scale;
+    }
+    __device__ __forceinline__ void store_scaled(float *psi, uint64_t base, const vf4 *X4, float unscale) const
+    {
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i)
+            *reinterpret_cast<vf4 *>(psi + 2 * (base + g_lo + g_hi[i])) = X4[lds_slot + i * kThreads] * unscale;
+    }
+    __device__ __forceinline__ void swap_scaled(float *psi, uint64_t base_out, vf4 *X4, const vf4 *buf, float scale,
+                                                float unscale) const
+    {
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) {
+            const vf4 o = X4[lds_slot + i * kThreads];
+            X4[lds_slot + i * kThreads] = buf[i] * scale;
+            *reinterpret_cast<vf4 *>(psi + 2 * (base_out + g_lo + g_hi[i])) = o * unscale;
+        }
+    }
+    // largest magnitude of the values in buf
+    __device__ __forceinline__ float max_abs(const vf4 *buf) const
+    {
+        float a = 0.f;
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i)
+            a = fmaxf(a, fmaxf(fmaxf(fabsf(buf[i].x), fabsf(buf[i].y)), fmaxf(fabsf(buf[i].z), fabsf(buf[i].w))));
+        return a;
+    }
 };
+
+// FP16 passes hold the tile in LDS scaled by 2^e, e chosen from the tile's
+// largest magnitude m so that m 2^e lies in [2^7, 2^8).  The blocks act
+// unitarily on the tile, so no value can grow beyond the tile's 2-norm,
+// which is at most sqrt(2^15) m: every value stays below 2^15.5 < 65504 (the
+// FP16 hi parts stay finite) while values many binades below m stay in
+// FP16's normal range.
+__device__ __forceinline__ void tile_scale(float m, float &scale, float &unscale)
+{
+    scale = unscale = 1.f;
+    if (m > 0.f && m <= 3.0e38f) {
+        int e;
+        frexpf(m, &e);  // m in [2^(e-1), 2^e)
+        int s = 8 - e;
+        s = s > 120 ? 120 : (s < -120 ? -120 : s);
+        scale = ldexpf(1.f, s);
+        unscale = ldexpf(1.f, -s);
+    }
+}
 
 // Per-block data staged in LDS: the A operand and the swizzled column terms
 // of lane l32 and column block cb = w NBW + q of wave w: cq[cb] ^ cl[l32].
@@ -169,6 +227,7 @@ struct TileShared {
     uint32_t op[C::MAX_SUB][kOperandWords];
     uint32_t cq[C::MAX_SUB][C::CBLOCKS];
     uint32_t cl[C::MAX_SUB][32];
+    float red[WAVES];  // per-wave partial of the next tile's scale (FP16 passes)
 };
 
 // Stage the launch's blocks: the A fragments of every lane, expanded from the
@@ -182,11 +241,12 @@ struct TileShared {
 //   the bf16 pair A'[r][16 i + 8 half + 2 e + {0, 1}] of step i = p & 1:
 //   (Ur, -Ui) for ri = 0, (Ui, Ur) for ri = 1, at complex column
 //   j = 8 i + 4 half + e.
-template <int TB, int WAVES, bool SPLIT>
+template <int TB, int WAVES, int PREC>
 __device__ __forceinline__ void stage_blocks(TileShared<TB, WAVES> &sh, const uint32_t *A, const TileArgs &args,
                                              int tid)
 {
     using C = TileCfg<TB, WAVES>;
+    constexpr bool SPLIT = PREC != kPrecF32;
     const int nsub = args.n_sub;
     for (int e = tid; e < nsub * kOperandWords; e += C::THREADS) {
         const int s = e / kOperandWords, r = e % kOperandWords;
@@ -225,14 +285,26 @@ __device__ __forceinline__ void lds_st(char *Xb, uint32_t byte_off, float re, fl
     *reinterpret_cast<vf2 *>(Xb + byte_off) = v;
 }
 
-// hi = RNE(v), lo = RNE(v - hi) of one (re, im) pair, as packed bf16 pairs
-__device__ __forceinline__ void split_pair(float re, float im, bf16x2 &hi, bf16x2 &lo)
+// hi = RNE(v), lo = RNE(v - hi) of one (re, im) pair, as packed 16-bit pairs
+// (H2 = bf16x2 or f16x2)
+template <typename H2>
+__device__ __forceinline__ void split_pair(float re, float im, H2 &hi, H2 &lo)
 {
     vf2 v;
     v.x = re;
     v.y = im;
-    hi = __builtin_convertvector(v, bf16x2);
-    lo = __builtin_convertvector(v - __builtin_convertvector(hi, vf2), bf16x2);
+    hi = __builtin_convertvector(v, H2);
+    lo = __builtin_convertvector(v - __builtin_convertvector(hi, vf2), H2);
+}
+
+// One 32 x 32 x 16 product of 16-bit operands with FP32 accumulation.
+__device__ __forceinline__ f32x16 mfma16(bf16x8 a, bf16x8 b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x16 mfma16(f16x8 a, f16x8 b, f32x16 c)
+{
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
 }
 
 __device__ __forceinline__ void lds_st4(char *Xb, uint32_t byte_off, float a, float b, float c, float d)
@@ -255,11 +327,14 @@ __device__ __forceinline__ void lds_st4(char *Xb, uint32_t byte_off, float a, fl
 // 16 bytes, two complex values that differ in tile bit 0.  If tile bit 0 is
 // the block's row bit 0, these are rows (t, t + 1) of one column; otherwise
 // tile bit 0 is the lowest column bit, i.e. column blocks (q, q + 1).
-template <int TB, int WAVES, bool SPLIT>
+template <int TB, int WAVES, int PREC>
 __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const TileArgs &args, int s, int w, int half,
                                             int l32)
 {
     using C = TileCfg<TB, WAVES>;
+    constexpr bool SPLIT = PREC != kPrecF32;
+    using H2 = typename std::conditional<PREC == kPrecF16, f16x2, bf16x2>::type;  // packed 16-bit pair
+    using H8 = typename std::conditional<PREC == kPrecF16, f16x8, bf16x8>::type;  // MFMA operand
     constexpr int NBW = C::NB_PER_WAVE;
     static_assert(NBW % 2 == 0, "column blocks come in pairs");
     char *Xb = reinterpret_cast<char *>(sh.X4);
@@ -310,7 +385,7 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
     }
     // split: step i (K = 16 i .. 16 i + 15) uses hi fragment ap[i] and lo
     // fragment ap[2 + i]; products Ah Xh + Ah Xl + Al Xh
-    bf16x8 xh[2], xl[2];
+    H8 xh[2], xl[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const vf4 fh = ap[i], fl = ap[2 + i];
@@ -326,19 +401,19 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
                 raw[k] = *reinterpret_cast<const vf4 *>(Xb + ((row_of(rb, 8 * (k >> 1) + 2 * (k & 1)) << 3) ^ lq[q]));
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                bf16x2 ph[4], pl[4];
+                H2 ph[4], pl[4];
 #pragma unroll
                 for (int k2 = 0; k2 < 2; ++k2) {
                     const vf4 r = raw[2 * i + k2];
                     split_pair(r.x, r.y, ph[2 * k2], pl[2 * k2]);
                     split_pair(r.z, r.w, ph[2 * k2 + 1], pl[2 * k2 + 1]);
                 }
-                bf16x8 bh, bl;
+                H8 bh, bl;
                 __builtin_memcpy(&bh, ph, 16);
                 __builtin_memcpy(&bl, pl, 16);
-                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bh, acc[q], 0, 0, 0);
-                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bl, acc[q], 0, 0, 0);
-                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], bh, acc[q], 0, 0, 0);
+                acc[q] = mfma16(xh[i], bh, acc[q]);
+                acc[q] = mfma16(xh[i], bl, acc[q]);
+                acc[q] = mfma16(xl[i], bh, acc[q]);
             }
         }
         // rows 4 g + 2 half + {0, 1} are acc[4 g .. 4 g + 3]
@@ -357,24 +432,24 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
                 raw[k] = *reinterpret_cast<const vf4 *>(Xb + ((row_of(rb, 8 * (k >> 2) + (k & 3)) << 3) ^ lq[q]));
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                bf16x2 ph0[4], pl0[4], ph1[4], pl1[4];
+                H2 ph0[4], pl0[4], ph1[4], pl1[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     const vf4 r = raw[4 * i + t];
                     split_pair(r.x, r.y, ph0[t], pl0[t]);
                     split_pair(r.z, r.w, ph1[t], pl1[t]);
                 }
-                bf16x8 bh0, bl0, bh1, bl1;
+                H8 bh0, bl0, bh1, bl1;
                 __builtin_memcpy(&bh0, ph0, 16);
                 __builtin_memcpy(&bl0, pl0, 16);
                 __builtin_memcpy(&bh1, ph1, 16);
                 __builtin_memcpy(&bl1, pl1, 16);
-                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bh0, acc[q], 0, 0, 0);
-                acc[q + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bh1, acc[q + 1], 0, 0, 0);
-                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bl0, acc[q], 0, 0, 0);
-                acc[q + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xh[i], bl1, acc[q + 1], 0, 0, 0);
-                acc[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], bh0, acc[q], 0, 0, 0);
-                acc[q + 1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xl[i], bh1, acc[q + 1], 0, 0, 0);
+                acc[q] = mfma16(xh[i], bh0, acc[q]);
+                acc[q + 1] = mfma16(xh[i], bh1, acc[q + 1]);
+                acc[q] = mfma16(xh[i], bl0, acc[q]);
+                acc[q + 1] = mfma16(xh[i], bl1, acc[q + 1]);
+                acc[q] = mfma16(xl[i], bh0, acc[q]);
+                acc[q + 1] = mfma16(xl[i], bh1, acc[q + 1]);
             }
         }
 #pragma unroll
@@ -389,26 +464,50 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
 }
 
 // The tile loop of one workgroup: tiles T, T + step, .. below T_end of the
-// state at psi.  FP32 (SPLIT = false): A = 32 x 32 FP32 real-form operands,
-// back to back.  Split BF16 (SPLIT = true): A' = Ah + Al (bf16 from the host,
+// state at psi.  FP32 (kPrecF32): A = 32 x 32 FP32 real-form operands, back
+// to back.  Split (kPrecBF16, kPrecF16): A' = Ah + Al (16-bit from the host,
 // hi then lo); each B operand (8 consecutive K values = 4 complex rows of one
-// column) is split while it is read from LDS (v_cvt_pk_bf16_f32), and Ah Xh +
-// Ah Xl + Al Xh run on v_mfma_f32_32x32x16_bf16 with FP32 accumulation (the
-// Al Xl term, ~2^-16 relative, is dropped).
-template <int TB, int WAVES, bool SPLIT>
+// column) is split while it is read from LDS, and Ah Xh + Ah Xl + Al Xh run
+// on 32 x 32 x 16 MFMA with FP32 accumulation (the Al Xl term, ~2^-16
+// relative for BF16 and ~2^-22 for FP16, is dropped).  FP16 passes hold the
+// tile scaled (tile_scale).
+template <int TB, int WAVES, int PREC>
 __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__restrict__ psi,
                                           const uint32_t *__restrict__ A, const TileArgs &args, uint64_t T,
                                           uint64_t T_end, uint64_t step)
 {
     using C = TileCfg<TB, WAVES>;
+    constexpr bool F16 = PREC == kPrecF16;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int half = lane >> 5, l32 = lane & 31;
 
-    stage_blocks<TB, WAVES, SPLIT>(sh, A, args, tid);
+    stage_blocks<TB, WAVES, PREC>(sh, A, args, tid);
     TileCopy<TB, WAVES> cp;
     cp.init(args, tid);
+    // the largest magnitude in buf over the workgroup: a wave maximum into
+    // sh.red[w]; the caller's next barrier publishes it
+    auto wave_max_to_red = [&](const vf4 *buf) {
+        // xor butterflies inside each 32-lane half (ds_swizzle in bit-mask
+        // mode: no lane-index registers), then the two halves via readlane
+        int m = __float_as_int(cp.max_abs(buf));
+        m = __float_as_int(fmaxf(__int_as_float(m), __int_as_float(__builtin_amdgcn_ds_swizzle(m, 0x041F))));
+        m = __float_as_int(fmaxf(__int_as_float(m), __int_as_float(__builtin_amdgcn_ds_swizzle(m, 0x081F))));
+        m = __float_as_int(fmaxf(__int_as_float(m), __int_as_float(__builtin_amdgcn_ds_swizzle(m, 0x101F))));
+        m = __float_as_int(fmaxf(__int_as_float(m), __int_as_float(__builtin_amdgcn_ds_swizzle(m, 0x201F))));
+        m = __float_as_int(fmaxf(__int_as_float(m), __int_as_float(__builtin_amdgcn_ds_swizzle(m, 0x401F))));
+        const float wm = fmaxf(__int_as_float(__builtin_amdgcn_readlane(m, 0)),
+                               __int_as_float(__builtin_amdgcn_readlane(m, 32)));
+        if (lane == 0) sh.red[w] = wm;
+    };
+    auto red_max = [&]() {
+        float m = 0.f;
+#pragma unroll
+        for (int i = 0; i < WAVES; ++i) m = fmaxf(m, sh.red[i]);
+        // uniform over the workgroup: keep it (and the scales) in scalar registers
+        return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, m)));
+    };
 
     // A finished tile is written to HBM at the top of the next round, before
     // that round's prefetch is issued: loads and stores may complete out of
@@ -417,39 +516,65 @@ __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__re
     if (T >= T_end) return;  // uniform over the workgroup
     vf4 buf[C::CHUNKS];
     cp.load(buf, psi, tile_base(T, args));
+    float scale = 1.f, unscale = 1.f, unscale_prev = 1.f;
+    if (F16) {
+        wave_max_to_red(buf);
+        __syncthreads();
+        tile_scale(red_max(), scale, unscale);
+    }
     uint64_t prev = 0;
     for (bool first = true; T < T_end; T += step, first = false) {
         const uint64_t base = tile_base(T, args);
-        if (first)
-            cp.to_lds(sh.X4, buf);
-        else
-            cp.swap(psi, prev, sh.X4, buf);
+        if (F16) {
+            if (first)
+                cp.to_lds_scaled(sh.X4, buf, scale);
+            else
+                cp.swap_scaled(psi, prev, sh.X4, buf, scale, unscale_prev);
+        } else {
+            if (first)
+                cp.to_lds(sh.X4, buf);
+            else
+                cp.swap(psi, prev, sh.X4, buf);
+        }
         __syncthreads();  // the first one also publishes the staged blocks
         const uint64_t Tn = T + step;
-        if (Tn < T_end) cp.load(buf, psi, tile_base(Tn, args));
+        const bool more = Tn < T_end;  // uniform
+        if (more) cp.load(buf, psi, tile_base(Tn, args));
         for (int s = 0; s < args.n_sub; ++s) {
-            apply_block<TB, WAVES, SPLIT>(sh, args, s, w, half, l32);
+            apply_block<TB, WAVES, PREC>(sh, args, s, w, half, l32);
             __syncthreads();
+        }
+        if (F16) {
+            // the next tile's scale (one more barrier per tile)
+            if (more) {
+                wave_max_to_red(buf);
+                __syncthreads();
+            }
+            unscale_prev = unscale;
+            if (more) tile_scale(red_max(), scale, unscale);
         }
         prev = base;
     }
-    cp.store(psi, prev, sh.X4);  // the last tile of this workgroup
+    if (F16)
+        cp.store_scaled(psi, prev, sh.X4, unscale_prev);  // the last tile of this workgroup
+    else
+        cp.store(psi, prev, sh.X4);
 }
 
 // One pass over one state (gridDim.y = 1) or over psi and psi2 alike
 // (gridDim.y = 2): a persistent grid strides over the tiles of its state.
-template <int TB, int WAVES, bool SPLIT>
+template <int TB, int WAVES, int PREC>
 __global__ void __launch_bounds__(64 * WAVES) k_tile_pass(float *__restrict__ psi, const uint32_t *__restrict__ A,
                                                           const TileArgs args, float *__restrict__ psi2)
 {
     __shared__ TileShared<TB, WAVES> sh;
-    tile_loop<TB, WAVES, SPLIT>(sh, blockIdx.y ? psi2 : psi, A, args, blockIdx.x, args.n_tiles, gridDim.x);
+    tile_loop<TB, WAVES, PREC>(sh, blockIdx.y ? psi2 : psi, A, args, blockIdx.x, args.n_tiles, gridDim.x);
 }
 
 // Passes of many states in one grid: workgroup i takes tiles [t0, t1) of
 // the pass units[i] names (states of a batch, each with its own tile layout,
 // blocks and operands).
-template <int TB, int WAVES, bool SPLIT>
+template <int TB, int WAVES, int PREC>
 __global__ void __launch_bounds__(64 * WAVES) k_tile_batch(const TileUnit *__restrict__ units,
                                                            const TilePass *__restrict__ passes,
                                                            const uint32_t *__restrict__ pool, float *__restrict__ buf)
@@ -457,21 +582,23 @@ __global__ void __launch_bounds__(64 * WAVES) k_tile_batch(const TileUnit *__res
     __shared__ TileShared<TB, WAVES> sh;
     const TileUnit u = units[blockIdx.x];
     const TilePass &p = passes[u.pass];
-    tile_loop<TB, WAVES, SPLIT>(sh, buf + 2 * p.state_off, pool + p.op_off, p.args, u.t0, u.t1, 1);
+    tile_loop<TB, WAVES, PREC>(sh, buf + 2 * p.state_off, pool + p.op_off, p.args, u.t0, u.t1, 1);
 }
 
 template <int TB, int WAVES>
-hipError_t tile_launch(const TileArgs &a, const void *d_a, bool split, float *psi, float *psi2, hipStream_t st,
+hipError_t tile_launch(const TileArgs &a, const void *d_a, int prec, float *psi, float *psi2, hipStream_t st,
                        int cap)
 {
     uint64_t g = a.n_tiles;
     if (cap > 0 && g > uint64_t(cap)) g = cap;
     const uint32_t *A = static_cast<const uint32_t *>(d_a);
     const dim3 grid(unsigned(g), psi2 ? 2 : 1);
-    if (split)
-        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, true>), grid, dim3(64 * WAVES), 0, st, psi, A, a, psi2);
+    if (prec == kPrecBF16)
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecBF16>), grid, dim3(64 * WAVES), 0, st, psi, A, a, psi2);
+    else if (prec == kPrecF16)
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF16>), grid, dim3(64 * WAVES), 0, st, psi, A, a, psi2);
     else
-        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, false>), grid, dim3(64 * WAVES), 0, st, psi, A, a, psi2);
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF32>), grid, dim3(64 * WAVES), 0, st, psi, A, a, psi2);
     return hipGetLastError();
 }
 
@@ -498,6 +625,22 @@ int tile_max_blocks(int tile_bits, int waves)
     return waves == 4 ? TileCfg<13, 4>::MAX_SUB : TileCfg<13, 8>::MAX_SUB;
 }
 
+static uint32_t f2h_rne(float x)
+{
+    const _Float16 h = static_cast<_Float16>(x);  // round to nearest even
+    uint16_t u;
+    std::memcpy(&u, &h, 2);
+    return u;
+}
+
+static float h2f(uint32_t u16)
+{
+    const uint16_t u = uint16_t(u16);
+    _Float16 h;
+    std::memcpy(&h, &u, 2);
+    return float(h);
+}
+
 static uint32_t f2bf_rne(float x)
 {
     uint32_t u;
@@ -514,20 +657,30 @@ static float bf2f(uint32_t h)
     return x;
 }
 
-void pack_tile_operand(const cd *m, bool split_bf16, uint32_t *out)
+void pack_tile_operand(const cd *m, int prec, uint32_t *out)
 {
     for (int r = 0; r < 16; ++r)
         for (int c = 0; c < 16; ++c) {
             const double re = m[r * 16 + c].real(), im = m[r * 16 + c].imag();
-            if (!split_bf16) {
+            if (prec == kTileOperandF32) {
                 const float fr = float(re), fi = float(im);
                 std::memcpy(&out[r * 16 + c], &fr, 4);
                 std::memcpy(&out[256 + r * 16 + c], &fi, 4);
                 continue;
             }
             // hi = RNE(x), lo = RNE(x - hi), as (re, im) halves of one word
-            const uint32_t hr = f2bf_rne(float(re)), hi = f2bf_rne(float(im));
-            const uint32_t lr = f2bf_rne(float(re - double(bf2f(hr)))), li = f2bf_rne(float(im - double(bf2f(hi))));
+            uint32_t hr, hi, lr, li;
+            if (prec == kTileOperandF16) {
+                hr = f2h_rne(float(re));
+                hi = f2h_rne(float(im));
+                lr = f2h_rne(float(re - double(h2f(hr))));
+                li = f2h_rne(float(im - double(h2f(hi))));
+            } else {
+                hr = f2bf_rne(float(re));
+                hi = f2bf_rne(float(im));
+                lr = f2bf_rne(float(re - double(bf2f(hr))));
+                li = f2bf_rne(float(im - double(bf2f(hi))));
+            }
             out[r * 16 + c] = hr | (hi << 16);
             out[256 + r * 16 + c] = lr | (li << 16);
         }
@@ -570,19 +723,20 @@ hipError_t make_tile_args(int n_sub, const int (*sub_pos)[4], int n, int tile_bi
     return hipSuccess;
 }
 
-hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a, bool split_bf16, void *psi, int n,
+hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a, int prec, void *psi, int n,
                             hipStream_t st, int grid_cap, int tile_bits, int waves, void *psi2)
 {
+    if (prec != kTileOperandF32 && prec != kTileOperandBF16 && prec != kTileOperandF16) return hipErrorInvalidValue;
     if (!tile_shape_supported(tile_bits, waves)) return hipErrorInvalidValue;
     if (n_sub < 1 || n_sub > tile_max_blocks(tile_bits, waves)) return hipErrorInvalidValue;
     TileArgs a;
     if (hipError_t e = make_tile_args(n_sub, sub_pos, n, tile_bits, &a)) return e;
     float *p = static_cast<float *>(psi), *p2 = static_cast<float *>(psi2);
     if (tile_bits == 14)
-        return waves == 16 ? tile_launch<14, 16>(a, d_a, split_bf16, p, p2, st, grid_cap)
-                           : tile_launch<14, 8>(a, d_a, split_bf16, p, p2, st, grid_cap);
-    return waves == 4 ? tile_launch<13, 4>(a, d_a, split_bf16, p, p2, st, grid_cap)
-                      : tile_launch<13, 8>(a, d_a, split_bf16, p, p2, st, grid_cap);
+        return waves == 16 ? tile_launch<14, 16>(a, d_a, prec, p, p2, st, grid_cap)
+                           : tile_launch<14, 8>(a, d_a, prec, p, p2, st, grid_cap);
+    return waves == 4 ? tile_launch<13, 4>(a, d_a, prec, p, p2, st, grid_cap)
+                      : tile_launch<13, 8>(a, d_a, prec, p, p2, st, grid_cap);
 }
 
 hipError_t launch_tile_batch(const TileUnit *units, int n_units, const TilePass *passes, const uint32_t *pool,
@@ -590,10 +744,10 @@ hipError_t launch_tile_batch(const TileUnit *units, int n_units, const TilePass 
 {
     if (n_units <= 0) return hipSuccess;
     if (split_bf16)
-        hipLaunchKernelGGL((k_tile_batch<kBatchTileBits, kBatchTileWaves, true>), dim3(unsigned(n_units)),
+        hipLaunchKernelGGL((k_tile_batch<kBatchTileBits, kBatchTileWaves, kPrecBF16>), dim3(unsigned(n_units)),
                            dim3(64 * kBatchTileWaves), 0, st, units, passes, pool, static_cast<float *>(buf));
     else
-        hipLaunchKernelGGL((k_tile_batch<kBatchTileBits, kBatchTileWaves, false>), dim3(unsigned(n_units)),
+        hipLaunchKernelGGL((k_tile_batch<kBatchTileBits, kBatchTileWaves, kPrecF32>), dim3(unsigned(n_units)),
                            dim3(64 * kBatchTileWaves), 0, st, units, passes, pool, static_cast<float *>(buf));
     return hipGetLastError();
 }

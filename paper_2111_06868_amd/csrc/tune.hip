@@ -236,7 +236,7 @@ extern "C" int sv_autotune(sv_state *s, int precision, double *cost_ms)
     const bool tiles = !rc && s->dtype == SV_C64 && dev::tile_supported(s->n, 8);
     if (tiles) {
         tuning() = best_tuning;
-        const Path tp = precision == SV_PREC_FP32 ? PATH_TILE : PATH_TILE_BF16;
+        const Path tp = tile_path(precision);
         // tile shape: the fastest pass of 4 blocks
         const int shapes[][2] = {{14, 8}, {14, 16}, {13, 4}, {13, 8}};
         double best_shape = 1e30;

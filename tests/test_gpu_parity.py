@@ -350,15 +350,18 @@ def test_tiled_passes_split_bf16(n):
     assert fe <= FID_C64
 
 
+_TILE_PREC = {"fp32": (sv.PREC_FP32, "tile"), "bf16": (sv.PREC_SPLIT_BF16, "tile_bf16"),
+              "fp16": (sv.PREC_SPLIT_FP16, "tile_fp16")}
+
+
 @pytest.mark.parametrize("shape", [(14, 8), (14, 16), (13, 4), (13, 8)])
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16"])
 @pytest.mark.parametrize("n", [14, 16])
 def test_tiled_passes_every_shape(shape, precision, n):
     """Each tile launch shape (tile bits, waves per workgroup) against the oracle."""
     rng = np.random.default_rng(900 + n + shape[0] + shape[1])
     gates = wc.random_gate_list(n, 10 * n, rng, max_k=2)
-    prec = sv.PREC_FP32 if precision == "fp32" else sv.PREC_SPLIT_BF16
-    fam = "tile" if precision == "fp32" else "tile_bf16"
+    prec, fam = _TILE_PREC[precision]
     sv.set_tile_shape(*shape)
     sv.stats_reset()
     sv.stats_enable(True)
@@ -373,18 +376,18 @@ def test_tiled_passes_every_shape(shape, precision, n):
     fe, ma = _report("tiled %s shape=%s n=%d (%d tile passes)" % (precision, shape, n, tiles), want, got)
     assert tiles > 0
     assert fe <= FID_C64
-    if precision == "fp32":
+    if precision != "bf16":
         assert ma <= 1e-5
 
 
 @pytest.mark.parametrize("union", [8, 9, 10])
-@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16"])
 def test_tiled_union_limits(union, precision):
     """Passes planned with 8, 9 and 10 positions (shorter HBM runs, more blocks)."""
     n = 17
     rng = np.random.default_rng(1300 + union)
     gates = wc.random_gate_list(n, 12 * n, rng, max_k=2)
-    prec = sv.PREC_FP32 if precision == "fp32" else sv.PREC_SPLIT_BF16
+    prec = _TILE_PREC[precision][0]
     sv.set_tile_union(union)
     try:
         plan = sv.fuse(to_binding(gates), n, 4, sv.RULE_TILED)
@@ -398,8 +401,32 @@ def test_tiled_union_limits(union, precision):
         sv.set_tile_union(10)
     fe, ma = _report("tiled %s union<=%d n=%d (%d passes)" % (precision, union, n, len(unions)), want, got)
     assert fe <= FID_C64
-    if precision == "fp32":
+    if precision != "bf16":
         assert ma <= 1e-5
+
+
+@pytest.mark.parametrize("amp_scale", [1e-12, 1.0, 1e6])
+def test_tiled_fp16_scaling(amp_scale):
+    """FP16 tile passes scale each tile from its largest magnitude: states far
+    from unit norm (tiny or huge amplitudes) keep FP16 accuracy and stay
+    finite, and a state of mixed magnitudes (one tile much larger than the
+    rest) keeps the small tiles' relative accuracy."""
+    n = 16
+    rng = np.random.default_rng(1700)
+    gates = wc.random_gate_list(n, 8 * n, rng, max_k=2)
+    x = (rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)) / math.sqrt(2 << n)
+    x[: 1 << 10] *= 1e4  # the low positions' tiles hold much larger values
+    x *= amp_scale
+    want = ref.run_matrices(x.astype(np.complex128), [(ref.matrix_of(g), g.qubits) for g in gates])
+    st = sv.State(n, "c64")
+    st.write(x.astype(np.complex64))
+    st.run(to_binding(gates), max_k=4, rule=sv.RULE_TILED, precision=sv.PREC_SPLIT_FP16)
+    got = st.read()
+    assert np.all(np.isfinite(got))
+    rel = np.max(np.abs(got - want)) / np.max(np.abs(want))
+    fe = ref.fidelity_error(want / np.linalg.norm(want), got / np.linalg.norm(got))
+    print("[parity] tiled fp16 scale=%g: max rel %.3e, 1-F %.3e" % (amp_scale, rel, fe), flush=True)
+    assert rel <= 1e-5 and fe <= 1e-10
 
 
 def test_c0_tiled():
