@@ -6,8 +6,9 @@ benchmark times (fused, enhanced rule, k <= 5, FP32 MFMA).
   run (fidelity, norm, first 2^20 amplitudes).
 * 32 qubits: the 632-gate circuit with k = 4..6 blocks in FP32 and in split
   BF16 / FP16 against a complex128 GPU run.
-* 34 qubits: tile passes (split BF16 and FP32) on a 12-qubit circuit spread
-  over the positions, every amplitude of its support against the oracle.
+* 34 qubits: tile passes (split BF16, split FP16 and FP32) on a 12-qubit
+  circuit spread over the positions, every amplitude of its support against
+  the oracle.
 * 20-qubit ansatz: adjoint gradients against oracle parameter shift and
   finite differences on sampled parameters.
 These need a large GPU (up to 128 GiB) and host memory (up to 24 GiB)."""
@@ -85,6 +86,7 @@ def test_34q_high_positions_64bit_indexing():
 
 @pytest.mark.parametrize("precision,tol_fe,tol_abs,tol_norm", [
     (sv.PREC_SPLIT_BF16, 1e-7, 5e-5, 1e-4),
+    (sv.PREC_SPLIT_FP16, 1e-10, 1e-6, 1e-5),
     (sv.PREC_FP32, 1e-10, 1e-6, 1e-5),
 ])
 def test_34q_tile_passes_vs_oracle(precision, tol_fe, tol_abs, tol_norm):
