@@ -352,8 +352,8 @@ def bench_trajectories(args):
     import paper_2111_06868_amd as sv
     from workloads import circuits as wc
     trajs = wc.trajectory_batch()
-    # tile passes of the trajectories with >= 14 qubits: split BF16 unless --precision fp32
-    prec = sv.PREC_FP32 if args.precision == "fp32" else sv.PREC_SPLIT_BF16
+    # tile passes of the trajectories with >= 14 qubits, by --precision (default split BF16)
+    prec = {"fp32": sv.PREC_FP32, "bf16": sv.PREC_SPLIT_BF16, "fp16": sv.PREC_SPLIT_FP16}[args.precision]
     b = sv.Batch([(t.n, [(g.name, g.qubits, g.params) for g in t.gates]) for t in trajs], max_k=-1,
                  precision=prec)
     out = {}
@@ -367,7 +367,8 @@ def bench_trajectories(args):
                       "value": round(len(trajs) / t, 2), "unit": "trajectories/s", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t, 3),
                       "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-                      "dtype": "f32" if prec == sv.PREC_FP32 else "f32; bf16 hi+lo split tile passes (n >= 14)",
+                      "dtype": {"fp32": "f32", "bf16": "f32; bf16 hi+lo split tile passes (n >= 14)",
+                                "fp16": "f32; f16 hi+lo split tile passes (n >= 14)"}[args.precision],
                       "data": "synthetic",
                       "config": {"workload": "512 ladder random circuits, n~U{10..22}, depth~U{8..24}, "
                                              "2q depolarizing p=1e-3 sampled per trajectory",

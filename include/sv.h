@@ -295,10 +295,10 @@ typedef struct sv_batch_desc {
     const int32_t *n_qubits;
     const int64_t *gate_offsets; /* n_traj + 1 entries */
     const sv_gate *gates;
-    int32_t precision;      /* SV_PREC_FP32 (0) or SV_PREC_SPLIT_BF16: the
-                               arithmetic of the tile passes of trajectories
-                               with 14 or more qubits; smaller ones and all
-                               reductions stay FP32 / FP64 */
+    int32_t precision;      /* SV_PREC_FP32 (0), SV_PREC_SPLIT_BF16 or
+                               SV_PREC_SPLIT_FP16: the arithmetic of the tile
+                               passes of trajectories with 14 or more qubits;
+                               smaller ones and all reductions stay FP32 / FP64 */
 } sv_batch_desc;
 /* Device bytes sv_batch_create needs in dev_buf for this batch. */
 int sv_batch_required_bytes(const sv_batch_desc *d, size_t *out);

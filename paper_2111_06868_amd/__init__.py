@@ -406,8 +406,8 @@ class Batch:
     (sv_batch_create / sv_batch_run)."""
 
     def __init__(self, circuits, max_k: int = -1, stream=None, precision: int = PREC_FP32):
-        """precision: PREC_FP32 or PREC_SPLIT_BF16 for the tile passes of the
-        trajectories with 14 or more qubits."""
+        """precision: PREC_FP32, PREC_SPLIT_BF16 or PREC_SPLIT_FP16 for the
+        tile passes of the trajectories with 14 or more qubits."""
         torch = _torch()
         circuits = list(circuits)
         self.n_qubits = np.array([int(n) for n, _ in circuits], dtype=np.int32)

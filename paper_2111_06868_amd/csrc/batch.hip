@@ -13,7 +13,7 @@
 //     out once.  No HBM traffic per gate.
 //   * LARGE trajectories (n >= 14) are planned with the tiled rule (passes of
 //     several <= 4-qubit blocks, one read and one write of the state each,
-//     FP32 or split-BF16 products by the batch's precision)
+//     FP32 or split BF16 / FP16 products by the batch's precision)
 //     and advance in lock step: launch s runs pass s of every large
 //     trajectory that has one, as tile ranges of a shared grid (one tile
 //     kernel, per-pass layouts and operands read from device tables).  <Z_0>
@@ -226,7 +226,7 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 struct sv_batch {
     int n_traj = 0;
     int max_k = 0;
-    bool split = false;  // split-BF16 tile passes for the large trajectories
+    int tile_prec = dev::kTileOperandF32;  // arithmetic of the large trajectories' tile passes
     hipStream_t stream = nullptr;
     hipStream_t side = nullptr;  // fork stream for graph capture / overlap
     hipEvent_t fork = nullptr, join = nullptr;
@@ -260,8 +260,8 @@ int check_desc(const sv_batch_desc *d)
     if (d->n_traj < 1) return fail(SV_ERR_ARG, "batch needs at least one trajectory");
     if (!d->n_qubits || !d->gate_offsets) return fail(SV_ERR_ARG, "NULL batch arrays");
     if (d->max_k != -1 && (d->max_k < 1 || d->max_k > SV_MAX_K)) return fail(SV_ERR_ARG, "max_k %d", d->max_k);
-    if (d->precision != SV_PREC_FP32 && d->precision != SV_PREC_SPLIT_BF16)
-        return fail(SV_ERR_ARG, "batch precision %d (FP32 or split BF16)", d->precision);
+    if (d->precision != SV_PREC_FP32 && d->precision != SV_PREC_SPLIT_BF16 && d->precision != SV_PREC_SPLIT_FP16)
+        return fail(SV_ERR_ARG, "batch precision %d (FP32, split BF16 or split FP16)", d->precision);
     if (d->gate_offsets[0] != 0) return fail(SV_ERR_ARG, "gate_offsets[0] must be 0");
     for (int t = 0; t < d->n_traj; ++t) {
         const int n = d->n_qubits[t];
@@ -337,7 +337,7 @@ int build_schedule(sv_batch *b, const sv_batch_desc *d, int k)
                     return fail(SV_ERR_ARG, "trajectory %d: tile pass layout", t);
                 pool.resize(pool.size() + size_t(cnt) * dev::kTileOperandWords);
                 for (int i = 0; i < cnt; ++i)
-                    dev::pack_tile_operand(m4.data() + 256 * i, b->split ? dev::kTileOperandBF16 : dev::kTileOperandF32, pool.data() + tp.op_off + dev::kTileOperandWords * i);
+                    dev::pack_tile_operand(m4.data() + 256 * i, b->tile_prec, pool.data() + tp.op_off + dev::kTileOperandWords * i);
                 mine.push_back(int(passes.size()));
                 passes.push_back(tp);
             }
@@ -441,7 +441,7 @@ int enqueue_run(sv_batch *b, hipStream_t main, hipStream_t side)
         const auto *pool = static_cast<const uint32_t *>(b->d_pool.p);
         for (const auto &st : b->steps) {
             LaunchTimer t(stat_class(FAM_BATCH, 3), main);
-            SV_HIP(dev::launch_tile_batch(units + st.first, st.second, passes, pool, b->buf, main, b->split));
+            SV_HIP(dev::launch_tile_batch(units + st.first, st.second, passes, pool, b->buf, main, b->tile_prec));
         }
         LaunchTimer t(stat_class(FAM_BATCH, 4), main);
         double *partial = static_cast<double *>(b->d_partial.p);
@@ -509,7 +509,9 @@ extern "C" int sv_batch_create(const sv_batch_desc *d, void *dev_buf, size_t byt
     if (reinterpret_cast<uintptr_t>(dev_buf) % 256) return fail(SV_ERR_ARG, "device buffer not 256-byte aligned");
     std::unique_ptr<sv_batch> b(new sv_batch);
     b->n_traj = d->n_traj;
-    b->split = d->precision == SV_PREC_SPLIT_BF16;
+    b->tile_prec = d->precision == SV_PREC_SPLIT_BF16   ? dev::kTileOperandBF16
+                   : d->precision == SV_PREC_SPLIT_FP16 ? dev::kTileOperandF16
+                                                        : dev::kTileOperandF32;
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->buf = static_cast<float2 *>(dev_buf);
     b->n_qubits.assign(d->n_qubits, d->n_qubits + d->n_traj);

@@ -66,7 +66,8 @@ void pack_tile_operand(const cd *m, int prec, uint32_t *out);
 // n-qubit state with 2^tile_bits-amplitude tiles.
 hipError_t make_tile_args(int n_sub, const int (*sub_pos)[4], int n, int tile_bits, TileArgs *out);
 // Batched passes (shape (kBatchTileBits, kBatchTileWaves), at most
-// tile_max_blocks() blocks per pass, FP32 or split BF16 operands): pass p of
+// tile_max_blocks() blocks per pass, operands of precision `prec` as
+// launch_tile_pass): pass p of
 // state at complex offset state_off with its operands at pool + op_off
 // (pack_tile_operand layout, kTileOperandWords each); each unit is one
 // workgroup's tile range of one pass.
@@ -83,7 +84,7 @@ struct TileUnit {
     uint64_t t0, t1;     // tiles [t0, t1)
 };
 hipError_t launch_tile_batch(const TileUnit *units, int n_units, const TilePass *passes, const uint32_t *pool,
-                             void *buf, hipStream_t st, bool split_bf16);
+                             void *buf, hipStream_t st, int prec);
 bool tile_supported(int n, int union_bits);
 bool tile_shape_supported(int tile_bits, int waves);
 int tile_wgs_per_cu(int tile_bits, int waves);

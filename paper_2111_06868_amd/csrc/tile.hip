@@ -740,15 +740,20 @@ hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a,
 }
 
 hipError_t launch_tile_batch(const TileUnit *units, int n_units, const TilePass *passes, const uint32_t *pool,
-                             void *buf, hipStream_t st, bool split_bf16)
+                             void *buf, hipStream_t st, int prec)
 {
     if (n_units <= 0) return hipSuccess;
-    if (split_bf16)
-        hipLaunchKernelGGL((k_tile_batch<kBatchTileBits, kBatchTileWaves, kPrecBF16>), dim3(unsigned(n_units)),
-                           dim3(64 * kBatchTileWaves), 0, st, units, passes, pool, static_cast<float *>(buf));
+    const dim3 grid{unsigned(n_units)}, block{unsigned(64 * kBatchTileWaves)};
+    float *b = static_cast<float *>(buf);
+    if (prec == kPrecBF16)
+        hipLaunchKernelGGL((k_tile_batch<kBatchTileBits, kBatchTileWaves, kPrecBF16>), grid, block, 0, st, units, passes,
+                           pool, b);
+    else if (prec == kPrecF16)
+        hipLaunchKernelGGL((k_tile_batch<kBatchTileBits, kBatchTileWaves, kPrecF16>), grid, block, 0, st, units, passes,
+                           pool, b);
     else
-        hipLaunchKernelGGL((k_tile_batch<kBatchTileBits, kBatchTileWaves, kPrecF32>), dim3(unsigned(n_units)),
-                           dim3(64 * kBatchTileWaves), 0, st, units, passes, pool, static_cast<float *>(buf));
+        hipLaunchKernelGGL((k_tile_batch<kBatchTileBits, kBatchTileWaves, kPrecF32>), grid, block, 0, st, units, passes,
+                           pool, b);
     return hipGetLastError();
 }
 

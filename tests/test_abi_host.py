@@ -190,8 +190,9 @@ def test_batch_description_validation():
     need = ctypes.c_size_t()
     assert L.sv_batch_required_bytes(ctypes.byref(desc()), ctypes.byref(need)) == N.OK
     assert need.value == 256 + 256  # 4 and 8 complex64 amplitudes, each padded to 256 bytes
-    assert L.sv_batch_required_bytes(ctypes.byref(desc(precision=sv.PREC_SPLIT_BF16)), ctypes.byref(need)) == N.OK
-    for prec in (sv.PREC_SPLIT_FP16, sv.PREC_FP64, 7):
+    for prec in (sv.PREC_SPLIT_BF16, sv.PREC_SPLIT_FP16):
+        assert L.sv_batch_required_bytes(ctypes.byref(desc(precision=prec)), ctypes.byref(need)) == N.OK
+    for prec in (sv.PREC_FP64, 7):
         assert L.sv_batch_required_bytes(ctypes.byref(desc(precision=prec)), ctypes.byref(need)) == N.ERR_ARG
     assert "precision" in L.sv_last_error().decode()
     assert L.sv_batch_required_bytes(ctypes.byref(desc(max_k=0)), ctypes.byref(need)) == N.ERR_ARG

@@ -32,12 +32,13 @@ def test_batch_small_vs_oracle(max_k, use_graph):
 
 
 @pytest.mark.parametrize("max_k", [3, -1])
-def test_batch_split_bf16_vs_oracle(max_k):
-    """Split-BF16 tile passes for the large trajectories (n >= 14): every
-    state against the oracle, at the split's tolerance."""
+@pytest.mark.parametrize("precision", [sv.PREC_SPLIT_BF16, sv.PREC_SPLIT_FP16])
+def test_batch_split_vs_oracle(max_k, precision):
+    """Split-BF16 / FP16 tile passes for the large trajectories (n >= 14):
+    every state against the oracle, at the split's tolerance."""
     trajs = wc.trajectory_batch(count=10, root_seed=91, p=0.2, n_range=(12, 18), depth_range=(3, 9))
     assert sum(1 for t in trajs if t.n >= 14) >= 5
-    b = sv.Batch(_batch_inputs(trajs), max_k=max_k, precision=sv.PREC_SPLIT_BF16)
+    b = sv.Batch(_batch_inputs(trajs), max_k=max_k, precision=precision)
     z = b.run(use_graph=True)
     for i, t in enumerate(trajs):
         want = ref.simulate(t.n, t.gates, "0")
@@ -46,10 +47,10 @@ def test_batch_split_bf16_vs_oracle(max_k):
         ma = float(np.max(np.abs(got - want)))
         assert fe <= 1e-6 and ma <= 1e-4, (i, t.n, fe, ma)
         assert abs(z[i] - ref.z0(want)) <= 1e-4, (i, z[i], ref.z0(want))
-    print("[parity] batch split bf16 max_k=%s ok" % max_k, flush=True)
+    print("[parity] batch split precision=%d max_k=%s ok" % (precision, max_k), flush=True)
 
 
-@pytest.mark.parametrize("precision,tol", [(sv.PREC_FP32, 1e-5), (sv.PREC_SPLIT_BF16, 1e-4)])
+@pytest.mark.parametrize("precision,tol", [(sv.PREC_FP32, 1e-5), (sv.PREC_SPLIT_BF16, 1e-4), (sv.PREC_SPLIT_FP16, 1e-5)])
 def test_batch_full_size_sampled(precision, tol):
     """The 512-trajectory noisy batch (n in 10..22, depth 8..24, p = 1e-3):
     every trajectory with n <= 15 and six larger ones against the oracle."""
