@@ -104,6 +104,8 @@ def main():
     ap.add_argument("--no-per-gate", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune launch shapes first, fuse with max_k=-1")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--plan", action="store_true",
+                    help="print the fused plan's tile passes (blocks, union, HBM layout) and exit; no GPU needed")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the state-vector path here is built and measured "
@@ -115,6 +117,8 @@ def main():
     import paper_2111_06868_amd as sv
     from workloads import circuits as wc
 
+    if args.plan:
+        return print_plan(args)
     torch.cuda.set_device(0)
     if args.workload == "gradient":
         return bench_gradient(args)
@@ -299,6 +303,46 @@ def main():
     }
     out.update(extra)
     print(json.dumps(out), flush=True)
+
+
+def print_plan(args, tile_bits=14, page_bits=18):
+    """Tile passes of the circuit's plan: for each pass its blocks, the union
+    of their positions and the HBM layout of one tile (the union plus the
+    lowest free positions, tile_bits in all: runs of 2^r contiguous
+    amplitudes, spread over 2^h pages of 2^page_bits amplitudes)."""
+    import paper_2111_06868_amd as sv
+    from workloads import circuits as wc
+
+    n, gates = wc.config_circuit(args.config)
+    ga = sv.GateArray([(g.name, g.qubits, g.params) for g in gates])
+    rule = {"enhanced": sv.RULE_ENHANCED, "paper": sv.RULE_PAPER, "tiled": sv.RULE_TILED,
+            "auto": sv.RULE_AUTO}[args.rule]
+    blocks = sv.fuse(ga, n, args.max_k, rule).blocks(False)
+    groups = []
+    for b in blocks:
+        if b.tile_pass >= 0 and groups and groups[-1][0] == b.tile_pass:
+            groups[-1][1].append(b.qubits)
+        else:
+            groups.append((b.tile_pass, [b.qubits]))
+    print("n=%d gates=%d blocks=%d passes=%d" % (n, len(gates), len(blocks), len(groups)))
+    for i, (tp, qs) in enumerate(groups):
+        union = sorted(set(q for b in qs for q in b))
+        if tp < 0 and len(union) > 4:
+            print("%3d dense k=%d on %s" % (i, len(union), union))
+            continue
+        # a lone block of k <= 4 (tp < 0) may run as a one-block tile pass
+        tile = set(union)
+        for p in range(n):
+            if len(tile) >= tile_bits:
+                break
+            tile.add(p)
+        run = 0
+        while run in tile:
+            run += 1
+        pages = sum(1 for p in tile if p >= page_bits)
+        print("%3d %s s=%d union=%s run=2^%d pages=2^%d blocks=%s"
+              % (i, "tile" if tp >= 0 else "single", len(qs), union, run, pages,
+                 " ".join(",".join(map(str, b)) for b in qs)))
 
 
 def _timed_steps(args, step):

@@ -30,3 +30,30 @@ def test_traffic_summary_is_tied_to_the_kernel_source(tmp_path, monkeypatch):
     (src / "mfma.hip").write_text("// kernel v2\n")
     assert bench.read_traffic(3, 5, 30) is None
     assert bench.read_traffic(3, 4, 30) is None
+
+
+def test_plan_listing_covers_every_pass():
+    """--plan lists the tiled plan of the 30-qubit grid circuit without a GPU:
+    every pass's blocks lie inside its union, unions stay within the tile, and
+    the blocks add up to the plan's block count."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--plan"],
+                       stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    lines = r.stdout.strip().splitlines()
+    head = dict(kv.split("=") for kv in lines[0].split() if "=" in kv)
+    assert head["n"] == "30" and head["gates"] == "845"
+    rows = lines[1:]
+    assert len(rows) == int(head["passes"])
+    total = 0
+    for row in rows:
+        kind = row.split()[1]
+        assert kind in ("tile", "single"), row
+        fields = dict(kv.split("=", 1) for kv in row.split(None, 2)[2].replace(", ", ",").split() if "=" in kv)
+        union = set(int(q) for q in fields["union"].strip("[]").split(","))
+        blocks = [set(int(q) for q in b.split(",")) for b in row.split("blocks=")[1].split()]
+        assert int(fields["s"]) == len(blocks)
+        assert set().union(*blocks) == union
+        assert all(1 <= len(b) <= 4 for b in blocks)
+        assert len(union) <= 10
+        total += len(blocks)
+    assert total == int(head["blocks"])
