@@ -282,6 +282,69 @@ int sv_apply_pauli_sum(sv_state *psi, const sv_pauli_sum *H, sv_state *out);
 int sv_backward(sv_state *psi, sv_state *scratch, const sv_gate *g, int G, const sv_pauli_sum *H,
                 double *grad, int n_params);
 
+/* ---------------------------------------------------------- density matrices */
+/* Density-matrix evolution by the state-vector path (paper, Simulations
+ * section: the density-matrix entry point rewrites a super circuit as a
+ * regular circuit and simulates that).  The density matrix rho of n qubits is a
+ * state of 2n qubits holding rho row-major, as kron(psi, conj(psi)) lays out a
+ * pure state (the paper's State Vector section example): amplitude
+ * r * 2^n + c holds rho[r][c], so the row index sits on positions n..2n-1 and
+ * the column index on positions 0..n-1.  Qubit q of rho is position q + n of
+ * the row index and position q of the column index.  A gate U on qubits Q
+ * becomes U on Q + n and conj(U) on Q; a super operator becomes one dense gate
+ * on the 2k positions (Q + n, Q).
+ *
+ * A super operator on k = 1..3 qubits q[0..k-1] (q[0] the most significant bit
+ * of its local index, as for gates) is either
+ *   - a KrausSuperGate (paper, Gates and Properties section):
+ *       rho -> sum_ij s[i][j] L_i rho R_j^dagger,
+ *     n_left matrices L_i and n_right matrices R_j (2^k x 2^k complex each,
+ *     row-major, re/im interleaved, back to back), s an n_left x n_right
+ *     complex matrix (row-major, interleaved) or NULL for the identity (then
+ *     n_left == n_right: the Kraus channel sum_i K_i rho K_i^dagger when
+ *     left == right); or
+ *   - a MatrixSuperGate: `superop` is the 4^k x 4^k complex matrix acting on
+ *     the row-major vectorisation of the k-qubit rho (local index r 2^k + c),
+ *     with n_left = n_right = 0 and left = right = s = NULL.
+ * It acts after the first `after` gates of the circuit's gate list (0..G;
+ * operators with equal `after` act in array order, and `after` must not
+ * decrease along the array).  Matrices are read during the call and not
+ * retained. */
+typedef struct sv_super_op {
+    int32_t after;
+    int32_t k;
+    int32_t q[3];
+    int32_t n_left;
+    int32_t n_right;
+    int32_t reserved; /* must be 0 */
+    const double *left;
+    const double *right;
+    const double *s;
+    const double *superop;
+} sv_super_op;
+
+/* The 4^k x 4^k matrix of a super operator on the row-major vectorisation of
+ * its k-qubit rho: sum_ij s[i][j] kron(L_i, conj(R_j)), or `superop` itself.
+ * Host only.  out: 2 * 16^k doubles (row-major, interleaved).  SV_ERR_ARG on a
+ * malformed operator. */
+int sv_super_op_matrix(const sv_super_op *op, double *out);
+
+/* Evolve the density matrix held in rho (2n qubits, see above) by the G gates
+ * g (on qubits 0..n-1) with the n_ops super operators inserted among them,
+ * fused and applied exactly as sv_run_circuit applies a circuit of 2n qubits
+ * (same options).  Start from |0..0><0..0| with sv_set_basis(rho, 0).
+ * SV_PREC_SPLIT_FP16 is refused (SV_ERR_ARG): its tile passes rely on blocks
+ * that cannot raise the 2-norm, which super operators may.  Errors:
+ * SV_ERR_ARG (odd rho->n, malformed operator, `after` out of order),
+ * SV_ERR_QUBIT (a qubit >= n or repeated). */
+int sv_dm_run(sv_state *rho, const sv_gate *g, int G, const sv_super_op *ops, int n_ops, const sv_run_opts *o);
+
+/* Tr(rho H) = sum_t coef[t] Re Tr(rho P_t) for a Pauli sum over the n qubits of
+ * rho (masks below bit n), summed in FP64 in a fixed order: Tr(rho P) is the
+ * sum over a of omega(a) rho[a][a ^ x], with P|a> = omega(a)|a ^ x>.
+ * Synchronises.  An identity term (x = z = 0) gives the trace. */
+int sv_dm_expectation(sv_state *rho, const sv_pauli_sum *H, double *out);
+
 /* ---------------------------------------------------------------- batches */
 /* Many independent circuits of different qubit counts (noisy trajectories:
  * the paper's Simulations with noise section samples noise channels on pure
@@ -347,7 +410,9 @@ int sv_set_tile_union(int max_positions);
  * apply, 2 = generic apply, 3 = MFMA FP32, 4 = MFMA split BF16, 5 = MFMA split
  * FP16, 6 = reductions, 7 = adjoint, 8 = batch, 9 = FP32 tile passes, 10 =
  * split-BF16 tile passes, 11 = split-FP16 tile passes; k is the block size,
- * or for tile passes the number of blocks in the launch. */
+ * for tile passes the number of blocks in the launch, and for reductions 1 =
+ * norm, 2 = inner product, 3 = expectation, 4 = Pauli-sum matvec, 5 =
+ * density-matrix trace Tr(rho H). */
 int sv_stats_enable(int on);
 int sv_stats_reset(void);
 int sv_stats_query(int cls, int64_t *launches, double *total_ms);

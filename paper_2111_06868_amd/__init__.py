@@ -257,6 +257,150 @@ class State:
         return out
 
 
+# ------------------------------------------------------------------ density matrices
+class SuperOp:
+    """One super operator (sv_super_op) on qubits q (q[0] the most significant
+    bit of its local index), acting after the first ``after`` gates of a
+    circuit.  Either a KrausSuperGate, rho -> sum_ij s[i, j] L_i rho R_j^dagger
+    (``s`` None = identity: the Kraus channel when left == right), or a
+    MatrixSuperGate: ``superop`` acting on the row-major vectorisation of the
+    k-qubit rho (paper, Gates and Properties section)."""
+
+    def __init__(self, qubits, left=None, right=None, s=None, superop=None, after: int = 0):
+        self.qubits = tuple(int(q) for q in qubits)
+        self.after = int(after)
+        k = len(self.qubits)
+        D = 1 << k
+        as_ops = lambda ms: np.ascontiguousarray(np.array(ms, dtype=np.complex128).reshape(-1, D, D))
+        self.superop = None if superop is None else np.ascontiguousarray(superop, dtype=np.complex128)
+        self.left = None if left is None else as_ops(left)
+        self.right = None if right is None and left is None else as_ops(left if right is None else right)
+        self.s = None if s is None else np.ascontiguousarray(s, dtype=np.complex128)
+
+    def at(self, after: int) -> "SuperOp":
+        """The same operator placed after the first ``after`` gates."""
+        o = SuperOp.__new__(SuperOp)
+        o.__dict__.update(self.__dict__)
+        o.after = int(after)
+        return o
+
+    def fill(self, c: "N.sv_super_op", keep: list):
+        dp = lambda a: (keep.append(a.view(np.float64)) or keep[-1].ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        c.after = self.after
+        c.k = len(self.qubits)
+        if not 1 <= c.k <= 3:
+            raise ValueError("super operator on %d qubits (1..3)" % c.k)
+        for j, q in enumerate(self.qubits):
+            c.q[j] = q
+        c.reserved = 0
+        if self.superop is not None:
+            c.n_left = c.n_right = 0
+            c.superop = dp(self.superop)
+        else:
+            c.n_left, c.n_right = len(self.left), len(self.right)
+            c.left, c.right = dp(self.left), dp(self.right)
+            if self.s is not None:
+                c.s = dp(self.s)
+
+    def matrix(self) -> np.ndarray:
+        """The 4^k x 4^k matrix on the row-major vectorisation (library, host)."""
+        c, keep = N.sv_super_op(), []
+        self.fill(c, keep)
+        D2 = 1 << (2 * len(self.qubits))
+        out = np.zeros(2 * D2 * D2, dtype=np.float64)
+        N.check(N.lib().sv_super_op_matrix(ctypes.byref(c), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out.view(np.complex128).reshape(D2, D2)
+
+
+_PAULI_1Q = {"I": np.eye(2), "X": np.array([[0, 1], [1, 0]]), "Y": np.array([[0, -1j], [1j, 0]]),
+             "Z": np.array([[1, 0], [0, -1]])}
+
+
+def _pauli_string(labels) -> np.ndarray:
+    m = np.ones((1, 1), dtype=np.complex128)
+    for c in labels:  # first label on the most significant local bit
+        m = np.kron(m, _PAULI_1Q[c])
+    return m
+
+
+def depolarizing(qubits, p: float, after: int = 0) -> SuperOp:
+    """Global depolarizing channel rho -> (1 - p) rho + p I/d on the qubits
+    (paper, Noisy gates section), as the Kraus form sum_P (p/d^2) P rho P
+    plus (1 - p) rho."""
+    import itertools
+    k = len(qubits)
+    d = 1 << k
+    ops, w = [], []
+    for labels in itertools.product("IXYZ", repeat=k):
+        ops.append(_pauli_string(labels))
+        w.append(p / (d * d) + (1.0 - p if set(labels) == {"I"} else 0.0))
+    return SuperOp(qubits, left=ops, s=np.diag(w), after=after)
+
+
+def dephasing(qubit: int, p: float, pauli: str = "Z", after: int = 0) -> SuperOp:
+    """rho -> (1 - p) rho + p sigma rho sigma (paper, Noisy gates section)."""
+    return SuperOp((qubit,), left=[np.eye(2), _PAULI_1Q[pauli.upper()]], s=np.diag([1.0 - p, p]), after=after)
+
+
+def amplitude_damping(qubit: int, gamma: float, after: int = 0) -> SuperOp:
+    """Kraus operators |0><0| + sqrt(1 - gamma)|1><1| and sqrt(gamma)|0><1|
+    (paper, Noisy gates section)."""
+    K0 = np.array([[1.0, 0.0], [0.0, np.sqrt(1.0 - gamma)]])
+    K1 = np.array([[0.0, np.sqrt(gamma)], [0.0, 0.0]])
+    return SuperOp((qubit,), left=[K0, K1], after=after)
+
+
+class DensityMatrix:
+    """Density matrix of n qubits held row-major in a State of 2n qubits
+    (rho[r][c] at amplitude r 2^n + c); starts as |0..0><0..0|."""
+
+    def __init__(self, n: int, dtype: str = "c64", stream=None, device=None):
+        self.n = int(n)
+        self.state = State(2 * self.n, dtype, stream, device).set_basis(0)
+
+    @property
+    def dtype(self):
+        return self.state.dtype
+
+    def set_basis(self, index: int):
+        """|index><index|."""
+        self.state.set_basis((int(index) << self.n) | int(index))
+        return self
+
+    def run(self, gates, ops=(), max_k: int = SV_MAX_K, precision: int = None, rule: int = RULE_NONE,
+            use_graph: bool = False):
+        """Evolve by the gates with the super operators among them (sv_dm_run)."""
+        ga = gates if isinstance(gates, GateArray) else GateArray(gates)
+        ops = list(ops)
+        arr = (N.sv_super_op * max(len(ops), 1))()
+        keep = []
+        for j, op in enumerate(ops):
+            op.fill(arr[j], keep)
+        o = N.sv_run_opts()
+        o.max_k = int(max_k)
+        o.precision = (PREC_FP32 if self.dtype == C64 else PREC_FP64) if precision is None else int(precision)
+        o.rule = int(rule)
+        o.use_graph = int(bool(use_graph))
+        N.check(N.lib().sv_dm_run(self.state.h, ga.ptr, ga.n, ctypes.cast(arr, ctypes.POINTER(N.sv_super_op)),
+                                  len(ops), ctypes.byref(o)))
+        return self
+
+    def expectation(self, terms) -> float:
+        """Tr(rho H) in FP64 on the device."""
+        H = terms if isinstance(terms, PauliSum) else PauliSum(terms)
+        out = ctypes.c_double()
+        N.check(N.lib().sv_dm_expectation(self.state.h, H.ptr, ctypes.byref(out)))
+        return out.value
+
+    def trace(self) -> float:
+        return self.expectation([(1.0, ())])
+
+    def read(self) -> np.ndarray:
+        """rho as a 2^n x 2^n array (reads all 4^n entries)."""
+        d = 1 << self.n
+        return self.state.read().reshape(d, d)
+
+
 def fidelity_error(ref: State, psi: State) -> float:
     """1 - |<ref|psi>|^2 / (||ref||^2 ||psi||^2), all in FP64 on the device."""
     ov = ref.inner(psi)

@@ -67,6 +67,13 @@ class sv_batch_desc(ctypes.Structure):
                 ("gates", ctypes.POINTER(sv_gate)), ("precision", ctypes.c_int32)]
 
 
+class sv_super_op(ctypes.Structure):
+    _fields_ = [("after", ctypes.c_int32), ("k", ctypes.c_int32), ("q", ctypes.c_int32 * 3),
+                ("n_left", ctypes.c_int32), ("n_right", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("left", ctypes.POINTER(ctypes.c_double)), ("right", ctypes.POINTER(ctypes.c_double)),
+                ("s", ctypes.POINTER(ctypes.c_double)), ("superop", ctypes.POINTER(ctypes.c_double))]
+
+
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _D = ctypes.POINTER(ctypes.c_double)
@@ -108,6 +115,9 @@ SIGNATURES = {
     "sv_expectation": (_I, [_P, _PS, _D]),
     "sv_apply_pauli_sum": (_I, [_P, _PS, _P]),
     "sv_backward": (_I, [_P, _P, _GP, _I, _PS, _D, _I]),
+    "sv_super_op_matrix": (_I, [ctypes.POINTER(sv_super_op), _D]),
+    "sv_dm_run": (_I, [_P, _GP, _I, ctypes.POINTER(sv_super_op), _I, ctypes.POINTER(sv_run_opts)]),
+    "sv_dm_expectation": (_I, [_P, _PS, _D]),
     "sv_batch_required_bytes": (_I, [ctypes.POINTER(sv_batch_desc), ctypes.POINTER(_SZ)]),
     "sv_batch_create": (_I, [ctypes.POINTER(sv_batch_desc), _P, _SZ, _P, ctypes.POINTER(_P)]),
     "sv_batch_run": (_I, [_P, _I, _D]),

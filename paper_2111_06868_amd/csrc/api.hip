@@ -531,10 +531,11 @@ extern "C" int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int u
 }
 
 // ============================================================== circuits
-extern "C" int sv_run_circuit(sv_state *s, const sv_gate *g, int G, const sv_run_opts *o)
+namespace {
+
+// Fuse and apply a validated state's circuit (sv_run_circuit, sv_dm_run).
+int run_circuit_impl(sv_state *s, const sv_gate *g, int G, const sv_run_opts *o)
 {
-    clear_error();
-    if (int rc = check_state(s)) return rc;
     sv_run_opts d;
     d.max_k = SV_MAX_K;
     d.precision = s->dtype == SV_C64 ? SV_PREC_FP32 : SV_PREC_FP64;
@@ -556,6 +557,33 @@ extern "C" int sv_run_circuit(sv_state *s, const sv_gate *g, int G, const sv_run
     blocks_to_launches(blocks, s, o->precision, rule, L);
     if (int rc = select_device(s)) return rc;
     return run_launches(s, L, o->use_graph != 0);
+}
+
+}  // namespace
+
+extern "C" int sv_run_circuit(sv_state *s, const sv_gate *g, int G, const sv_run_opts *o)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    return run_circuit_impl(s, g, G, o);
+}
+
+// The super circuit is rewritten as a regular circuit of 2n positions
+// (dm_expand) and run like any other circuit.
+extern "C" int sv_dm_run(sv_state *rho, const sv_gate *g, int G, const sv_super_op *ops, int n_ops,
+                         const sv_run_opts *o)
+{
+    clear_error();
+    if (int rc = check_state(rho)) return rc;
+    if (rho->n % 2) return fail(SV_ERR_ARG, "a density matrix needs an even number of state qubits, got %d", rho->n);
+    if (o && o->precision == SV_PREC_SPLIT_FP16)
+        return fail(SV_ERR_ARG, "SV_PREC_SPLIT_FP16 is not available for density matrices (super operators may "
+                                "raise the 2-norm its tile passes rely on)");
+    if (int rc = validate_gates(g, G, rho->n / 2)) return rc;
+    std::vector<sv_gate> full;
+    std::vector<std::vector<double>> store;
+    if (int rc = dm_expand(g, G, rho->n / 2, ops, n_ops, full, store)) return rc;
+    return run_circuit_impl(rho, full.data(), int(full.size()), o);
 }
 
 // ============================================================== reductions
@@ -689,6 +717,32 @@ extern "C" int sv_expectation(sv_state *s, const sv_pauli_sum *H, double *out)
     }
     SV_HIP(hipEventRecord(s->arena_free, s->stream));
     return read_result(s, res, 1, out);
+}
+
+extern "C" int sv_dm_expectation(sv_state *rho, const sv_pauli_sum *H, double *out)
+{
+    clear_error();
+    if (int rc = check_state(rho)) return rc;
+    if (!out) return fail(SV_ERR_ARG, "NULL out");
+    if (rho->n % 2) return fail(SV_ERR_ARG, "a density matrix needs an even number of state qubits, got %d", rho->n);
+    const int n = rho->n / 2;
+    if (int rc = check_pauli(H, n)) return rc;
+    if (H->n_terms == 0) {
+        *out = 0.0;
+        return SV_OK;
+    }
+    if (int rc = select_device(rho)) return rc;
+    SV_HIP(hipEventSynchronize(rho->arena_free));
+    dev::PauliDev P;
+    if (int rc = pauli_tables(rho, H, P)) return rc;
+    double *part = static_cast<double *>(rho->red.p);
+    double *res = part + 2 * dev::kRedBlocks;
+    {
+        LaunchTimer t(stat_class(FAM_REDUCE, 5), rho->stream);
+        SV_HIP(dev::launch_dm_expect(rho->dtype, rho->buf, n, P, part, res, rho->stream));
+    }
+    SV_HIP(hipEventRecord(rho->arena_free, rho->stream));
+    return read_result(rho, res, 1, out);
 }
 
 extern "C" int sv_apply_pauli_sum(sv_state *psi, const sv_pauli_sum *H, sv_state *out)

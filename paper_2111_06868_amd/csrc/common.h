@@ -82,6 +82,13 @@ double tiled_plan_cost(const std::vector<Block> &blocks, int n, const CostTable 
 // Canonical matrix of a block from its member gates.
 void block_matrix(const sv_gate *g, Block &b);
 
+// ---------------------------------------------------------------- density matrices
+// Rewrite gates g (on qubits 0..n-1) with super operators among them as a
+// regular circuit on 2n positions (rho row-major: row index on n..2n-1).  The
+// new MATRIX gates point into `store`.
+int dm_expand(const sv_gate *g, int G, int n, const sv_super_op *ops, int n_ops, std::vector<sv_gate> &out,
+              std::vector<std::vector<double>> &store);
+
 }  // namespace sv
 
 struct sv_plan {

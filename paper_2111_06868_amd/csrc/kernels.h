@@ -130,6 +130,9 @@ hipError_t launch_pauli_expect(int dtype, const void *psi, int n, const PauliDev
                                double *d_out, hipStream_t st);
 hipError_t launch_pauli_apply(int dtype, const void *psi, void *out, int n, const PauliDev &H,
                               hipStream_t st);
+// Tr(rho H) of rho (n qubits) held row-major in a state of 2n qubits.
+hipError_t launch_dm_expect(int dtype, const void *rho, int n, const PauliDev &H, double *d_partials, double *d_out,
+                            hipStream_t st);
 
 // ------------------------------------------------------------------ adjoint
 // One backward step for a k <= 2 gate: if pauli >= 1 (1 = X, 2 = Y, 3 = Z on

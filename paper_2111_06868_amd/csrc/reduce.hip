@@ -1,5 +1,6 @@
 // FP64 reductions over a state: norm, inner product, Pauli-sum expectation,
-// and the Pauli-sum matvec used by the adjoint method.
+// the Pauli-sum matvec used by the adjoint method, and Tr(rho H) of a density
+// matrix held as a state of 2n qubits.
 //
 // Every reduction is a fixed-shape two-stage tree (kRedBlocks x kRedThreads
 // first stage with a fixed grid-stride assignment, LDS tree inside a block,
@@ -149,6 +150,27 @@ __global__ void __launch_bounds__(kRedThreads) k_pauli_expect(const T *__restric
     block_reduce_store<1>(a, partials + blockIdx.x);
 }
 
+// Tr(rho H) for rho held row-major in a state of 2n qubits (rho[r][c] at
+// r 2^n + c).  With P|a> = omega(a)|a ^ x>, Tr(rho P) = sum_a omega(a)
+// rho[a][a ^ x]; omega(a) is the group weight at a (group_weight), and only
+// the real part is summed (H is Hermitian).
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) k_dm_expect(const T *__restrict__ rho, int n, const PauliDev H,
+                                                          double *partials)
+{
+    Acc<1> acc{{0.0}};
+    const uint64_t N = uint64_t(1) << n;
+    for (uint64_t a = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; a < N; a += uint64_t(kRedBlocks) * kRedThreads) {
+        for (int g = 0; g < H.n_groups; ++g) {
+            double rr, ri, wr, wi;
+            ld(rho, (a << n) | (a ^ H.gx[g]), rr, ri);
+            group_weight(H, g, a, wr, wi);
+            acc.v[0] = fma(rr, wr, fma(-ri, wi, acc.v[0]));
+        }
+    }
+    block_reduce_store<1>(acc, partials + blockIdx.x);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_pauli_apply(const T *__restrict__ psi, T *__restrict__ out, uint64_t N,
                                                     const PauliDev H)
@@ -226,6 +248,17 @@ hipError_t launch_pauli_expect(int dtype, const void *psi, int n, const PauliDev
         hipLaunchKernelGGL(k_pauli_expect<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<const float *>(psi), N, H, d_partials);
     else
         hipLaunchKernelGGL(k_pauli_expect<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<const double *>(psi), N, H, d_partials);
+    hipLaunchKernelGGL(k_final<1>, dim3(1), dim3(kRedThreads), 0, st, d_partials, kRedBlocks, d_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_dm_expect(int dtype, const void *rho, int n, const PauliDev &H, double *d_partials, double *d_out,
+                            hipStream_t st)
+{
+    if (dtype == SV_C64)
+        hipLaunchKernelGGL(k_dm_expect<float>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<const float *>(rho), n, H, d_partials);
+    else
+        hipLaunchKernelGGL(k_dm_expect<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<const double *>(rho), n, H, d_partials);
     hipLaunchKernelGGL(k_final<1>, dim3(1), dim3(kRedThreads), 0, st, d_partials, kRedBlocks, d_out);
     return hipGetLastError();
 }

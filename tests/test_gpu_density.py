@@ -1,0 +1,146 @@
+"""GPU parity of density-matrix evolution (sv_dm_run, sv_dm_expectation)
+against the density-matrix oracle on the same seeded inputs, and the exact
+noisy <Z_0> against the mean of sampled Pauli trajectories (paper,
+Simulations with noise section: both treatments of the same channel).
+Complex64 entries must match to 2e-5 (each entry of rho is at most 1 in
+magnitude; the error is FP32 rounding accumulated over the circuit's blocks),
+complex128 to 1e-12."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import paper_2111_06868_amd as sv
+from oracle import density as dm
+from workloads import circuits as wc
+from helpers import to_binding
+
+pytestmark = pytest.mark.gpu
+
+TOL = {sv.PREC_FP32: 2e-5, sv.PREC_SPLIT_BF16: 2e-5, sv.PREC_FP64: 1e-12}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    yield
+    torch.cuda.synchronize()
+
+
+def _noisy_case(rows, cols, depth, seed, p=0.02):
+    """Gates plus matched operator lists: the library's SuperOp objects and
+    the oracle's dicts (same inputs, built independently on each side)."""
+    gates = wc.grid_rqc(rows, cols, depth, seed)
+    n = rows * cols
+    lib_ops, or_ops = [], []
+    fs = [i for i, g in enumerate(gates) if g.name == "FSIM"]
+    for i in fs:
+        q = gates[i].qubits
+        lib_ops.append(sv.depolarizing(q, p, after=i + 1))
+        or_ops.append(dm.depolarizing(q, p, after=i + 1))
+    mid = len(gates) // 2
+    # amplitude damping, a random 2-qubit Kraus channel, a general s form and
+    # a matrix super operator, all in the middle of the circuit
+    lib_ops.append(sv.amplitude_damping(0, 0.1, after=mid))
+    or_ops.append(dm.amplitude_damping(0, 0.1, after=mid))
+    K = wc.random_kraus_from_seed(seed + 1, 2, 3)
+    qk = (n - 1, 0)
+    lib_ops.append(sv.SuperOp(qk, left=K, after=mid))
+    or_ops.append({"qubits": qk, "left": K, "after": mid})
+    L = wc.random_kraus_from_seed(seed + 2, 1, 2)
+    s = np.array([[0.9, 0.05j], [-0.05j, 0.1]])
+    lib_ops.append(sv.SuperOp((1,), left=L, right=L, s=s, after=mid))
+    or_ops.append({"qubits": (1,), "left": L, "right": L, "s": s, "after": mid})
+    S = sv.amplitude_damping(0, 0.3).matrix()
+    lib_ops.append(sv.SuperOp((n - 1,), superop=S, after=mid))
+    or_ops.append({"qubits": (n - 1,), "superop": S, "after": mid})
+    key = lambda o: o.after if hasattr(o, "after") else o["after"]
+    lib_ops.sort(key=key)
+    or_ops.sort(key=key)
+    return n, gates, lib_ops, or_ops
+
+
+def _check(tag, want, got, tol):
+    err = float(np.abs(want - got).max())
+    print("[parity] %-44s max_abs=%.3e" % (tag, err), flush=True)
+    sys.stdout.flush()
+    assert err <= tol, "%s: max_abs %.3e > %.1e" % (tag, err, tol)
+
+
+@pytest.mark.parametrize("rule,max_k", [(sv.RULE_NONE, 6), (sv.RULE_PAPER, 4), (sv.RULE_ENHANCED, 6),
+                                        (sv.RULE_ENHANCED, 3)])
+@pytest.mark.parametrize("dtype,prec", [("c64", sv.PREC_FP32), ("c64", sv.PREC_SPLIT_BF16), ("c128", sv.PREC_FP64)])
+def test_dm_small_vs_oracle(rule, max_k, dtype, prec):
+    n, gates, lib_ops, or_ops = _noisy_case(2, 2, 6, seed=21)
+    want = dm.simulate(n, gates, or_ops)
+    rho = sv.DensityMatrix(n, dtype).run(to_binding(gates), lib_ops, max_k=max_k, precision=prec, rule=rule)
+    _check("dm n=%d %s prec=%d rule=%d k<=%d" % (n, dtype, prec, rule, max_k), want, rho.read(), TOL[prec])
+
+
+@pytest.mark.parametrize("prec", [sv.PREC_FP32, sv.PREC_SPLIT_BF16])
+def test_dm_tile_passes_vs_oracle(prec):
+    # 7 qubits: rho is a 14-qubit state, so the tiled rule runs LDS tile passes
+    n, gates, lib_ops, or_ops = _noisy_case(1, 7, 5, seed=5)
+    want = dm.simulate(n, gates, or_ops)
+    sv.stats_reset()
+    sv.stats_enable(True)
+    rho = sv.DensityMatrix(n, "c64").run(to_binding(gates), lib_ops, max_k=4, precision=prec,
+                                         rule=sv.RULE_TILED)
+    got = rho.read()
+    sv.stats_enable(False)
+    fam = "tile" if prec == sv.PREC_FP32 else "tile_bf16"
+    tiles = sum(sv.stats_query(fam, k)[0] for k in range(1, 17))
+    assert tiles > 0, "no tile pass ran"
+    _check("dm n=%d tiled prec=%d (%d tile launches)" % (n, prec, tiles), want, got, TOL[prec])
+
+
+@pytest.mark.parametrize("dtype,prec", [("c64", sv.PREC_FP32), ("c128", sv.PREC_FP64)])
+def test_dm_expectation_vs_oracle(dtype, prec):
+    n, gates, lib_ops, or_ops = _noisy_case(2, 3, 5, seed=8)
+    want_rho = dm.simulate(n, gates, or_ops)
+    rho = sv.DensityMatrix(n, dtype).run(to_binding(gates), lib_ops, max_k=4, precision=prec,
+                                         rule=sv.RULE_ENHANCED)
+    terms = ([(1.0, ((i, "Z"), (i + 1, "Z"))) for i in range(n - 1)]
+             + [(0.5, ((i, "X"),)) for i in range(n)]
+             + [(0.3, ((0, "Y"), (2, "Y"))), (-0.7, ((1, "X"), (4, "Y"), (5, "Z"))), (0.25, ())])
+    want = dm.expectation(want_rho, terms)
+    got = rho.expectation(terms)
+    tol = 1e-5 if dtype == "c64" else 1e-12
+    print("[parity] dm Tr(rho H) %s: %.12f vs %.12f" % (dtype, got, want), flush=True)
+    assert abs(got - want) <= tol
+    assert abs(rho.trace() - np.trace(want_rho).real) <= tol
+
+
+def test_dm_refuses_fp16_and_odd_states():
+    rho = sv.DensityMatrix(2, "c64")
+    with pytest.raises(sv.SvError):
+        rho.run([("H", (0,))], [], precision=sv.PREC_SPLIT_FP16)
+    odd = sv.DensityMatrix(2, "c64")
+    odd.state = sv.State(5, "c64")
+    with pytest.raises(sv.SvError):
+        odd.run([("H", (0,))])
+    with pytest.raises(sv.SvError):
+        odd.expectation([(1.0, ((0, "Z"),))])
+    with pytest.raises(sv.SvError):  # a gate on qubit 2 of a 2-qubit rho
+        rho.run([("H", (2,))])
+    with pytest.raises(sv.SvError):  # operators out of order
+        rho.run([("H", (0,)), ("H", (1,))], [sv.amplitude_damping(0, 0.1, after=2),
+                                              sv.amplitude_damping(0, 0.1, after=1)])
+
+
+def test_dm_exact_z0_matches_trajectory_mean():
+    # the same depolarizing channel, evolved exactly and sampled on pure
+    # states: the sample mean of <Z_0> must agree within 5 standard errors
+    p = 0.05
+    gates = wc.grid_rqc(2, 4, 10, seed=13)
+    n = 8
+    ops = [sv.depolarizing(g.qubits, p, after=i + 1) for i, g in enumerate(gates) if g.name == "FSIM"]
+    rho = sv.DensityMatrix(n, "c128").run(to_binding(gates), ops, max_k=4, rule=sv.RULE_ENHANCED)
+    exact = rho.expectation([(1.0, ((0, "Z"),))])
+    trajs = wc.pauli_trajectories(gates, p, 2048, seed=77)
+    z = sv.Batch([(n, to_binding(t)) for t in trajs], max_k=4).run()
+    mean, se = float(np.mean(z)), float(np.std(z) / math.sqrt(len(z)))
+    print("[parity] exact <Z0> %.6f, trajectory mean %.6f +- %.6f" % (exact, mean, se), flush=True)
+    assert abs(mean - exact) <= 5 * se + 1e-6

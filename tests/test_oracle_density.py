@@ -1,0 +1,112 @@
+"""Pins of the density-matrix oracle (oracle/density.py) to closed forms,
+to psi psi^dagger of the pinned state-vector oracle, and to the exact mixture
+of sampled Pauli errors (paper, Noisy gates and Simulations with noise
+sections; Gates and Properties section for the super-gate forms)."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from oracle import density as dm
+from oracle import ref
+from workloads import circuits as wc
+from workloads.circuits import Gate
+
+
+def _rand_rho(n, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((1 << n, 1 << n)) + 1j * rng.standard_normal((1 << n, 1 << n))
+    rho = a @ a.conj().T
+    return rho / np.trace(rho)
+
+
+def test_pure_circuit_is_psi_psi_dagger():
+    gates = wc.grid_rqc(2, 2, 6, seed=11)
+    rho = dm.simulate(4, gates)
+    psi = ref.simulate(4, gates, "0")
+    assert np.abs(rho - dm.pure(psi)).max() < 1e-13
+
+
+def test_depolarizing_closed_forms():
+    p = 0.3
+    rho = dm.apply_op(dm.zero(1), dm.depolarizing((0,), p))
+    assert np.abs(rho - np.diag([1 - p / 2, p / 2])).max() < 1e-15
+    r2 = _rand_rho(2, 5)
+    out = dm.apply_op(r2, dm.depolarizing((0, 1), p))
+    assert np.abs(out - ((1 - p) * r2 + p * np.eye(4) / 4)).max() < 1e-15
+    # on one qubit of two: (1 - p) rho + p (I/2 (x) tr_q rho) with q = position 1
+    out = dm.apply_op(r2, dm.depolarizing((1,), p))
+    r = r2.reshape(2, 2, 2, 2)  # [q1, q0, q1', q0']
+    tr1 = np.einsum("aiaj->ij", r)
+    want = (1 - p) * r2 + p * np.kron(np.eye(2) / 2, tr1)
+    assert np.abs(out - want).max() < 1e-15
+
+
+def test_amplitude_damping_closed_form():
+    # RX(-pi/2)|0> = (|0> + i|1>)/sqrt 2; damping gamma
+    g = 0.37
+    rho = dm.simulate(1, [Gate("RX", (0,), (-math.pi / 2,))], [dm.amplitude_damping(0, g, after=1)])
+    want = np.array([[(1 + g) / 2, -1j * math.sqrt(1 - g) / 2],
+                     [1j * math.sqrt(1 - g) / 2, (1 - g) / 2]])
+    assert np.abs(rho - want).max() < 1e-15
+
+
+@pytest.mark.parametrize("theta", [0.0, 0.7, 2.5])
+def test_dephasing_of_rotating_spin(theta):
+    # <X> = (1 - 2p) cos theta and <Y> = (1 - 2p) sin theta after H, RZ(theta), Z-dephasing p
+    p = 0.2
+    rho = dm.simulate(1, [Gate("H", (0,)), Gate("RZ", (0,), (theta,))], [dm.dephasing(0, p, after=2)])
+    assert abs(dm.expectation(rho, [(1.0, ((0, "X"),))]) - (1 - 2 * p) * math.cos(theta)) < 1e-14
+    assert abs(dm.expectation(rho, [(1.0, ((0, "Y"),))]) - (1 - 2 * p) * math.sin(theta)) < 1e-14
+    assert abs(dm.expectation(rho, [(1.0, ())]) - 1.0) < 1e-14
+
+
+def test_channel_equals_exact_mixture_of_sampled_paulis():
+    # the trajectories' noise model: after each fSim, with probability p a
+    # uniform two-qubit Pauli string (identity included)
+    p = 0.05
+    gates = wc.grid_rqc(1, 3, 4, seed=2)
+    fs = [i for i, g in enumerate(gates) if g.name == "FSIM"][:3]
+    gates = gates[:fs[-1] + 1]
+    ops = [dm.depolarizing(gates[i].qubits, p, after=i + 1) for i in fs]
+    rho = dm.simulate(3, gates, ops)
+    want = np.zeros_like(rho)
+    labels = ["".join(t) for t in itertools.product("IXYZ", repeat=2)]
+    for pattern in itertools.product(range(16), repeat=len(fs)):
+        w = 1.0
+        seq = []
+        for i, g in enumerate(gates):
+            seq.append(g)
+            if i in fs:
+                code = pattern[fs.index(i)]
+                w *= (1 - p) * (code == 0) + p / 16
+                a, b = labels[code]
+                if a != "I":
+                    seq.append(Gate(a, (g.qubits[0],)))
+                if b != "I":
+                    seq.append(Gate(b, (g.qubits[1],)))
+        want += w * dm.pure(ref.simulate(3, seq, "0"))
+    assert np.abs(rho - want).max() < 1e-13
+
+
+def test_matrix_super_gate_matches_kraus_form():
+    # row-major vectorisation: vec(A rho B) = kron(A, B^T) vec(rho)
+    rho = _rand_rho(3, 7)
+    K = wc.random_kraus_from_seed(3, 2, 3)
+    R = wc.random_kraus_from_seed(4, 2, 2)
+    s = np.array([[0.3, 0.1j], [0.2, -0.4], [0.05, 0.5]])
+    S = sum(s[i, j] * np.kron(K[i], R[j].conj()) for i in range(3) for j in range(2))
+    for qs in [(0, 2), (2, 1)]:
+        a = dm.apply_kraus_super(rho, K, R, s, qs)
+        b = dm.apply_matrix_super(rho, S, qs)
+        assert np.abs(a - b).max() < 1e-14
+
+
+def test_random_channel_keeps_a_density_matrix():
+    rho = _rand_rho(3, 9)
+    for seed, (qs, m) in enumerate([((1,), 3), ((0, 2), 4), ((2, 0, 1), 2)]):
+        out = dm.apply_op(rho, {"qubits": qs, "left": wc.random_kraus_from_seed(seed, len(qs), m)})
+        assert abs(np.trace(out) - 1) < 1e-13
+        assert np.abs(out - out.conj().T).max() < 1e-14
+        assert np.linalg.eigvalsh(out).min() > -1e-13

@@ -260,3 +260,45 @@ def haar_unitary_from_seed(seed: int, k: int) -> np.ndarray:
     q, r = np.linalg.qr(z)
     ph = np.diag(r) / np.abs(np.diag(r))
     return q * ph[None, :]
+
+
+def random_kraus_from_seed(seed: int, k: int, n_ops: int) -> List[np.ndarray]:
+    """Input generator for Kraus channels: n_ops operators K_i (2^k x 2^k) with
+    sum_i K_i^dagger K_i = I, the blocks of a random isometry (QR of a complex
+    Gaussian (n_ops 2^k) x 2^k matrix).  Both sides receive the same operators."""
+    rng = np.random.default_rng(int(seed))
+    d = 1 << k
+    z = (rng.standard_normal((n_ops * d, d)) + 1j * rng.standard_normal((n_ops * d, d))) / math.sqrt(2)
+    v, _ = np.linalg.qr(z)
+    return [np.ascontiguousarray(v[i * d:(i + 1) * d, :]) for i in range(n_ops)]
+
+
+def noisy_grid_circuit(rows: int, cols: int, depth: int, seed: int, p: float = 1e-3):
+    """Density-matrix workload: the grid random circuit with the two-qubit
+    global depolarizing channel (probability p) after every fSim.  Returns
+    (gates, channels) where a channel is (after, qubits, p): it acts after the
+    first ``after`` gates."""
+    gates = grid_rqc(rows, cols, depth, seed)
+    channels = [(i + 1, g.qubits, p) for i, g in enumerate(gates) if g.name == "FSIM"]
+    return gates, channels
+
+
+def pauli_trajectories(gates: Sequence[Gate], p: float, count: int, seed: int) -> List[List[Gate]]:
+    """``count`` samples of the fixed circuit ``gates`` under the trajectories'
+    noise model: after every fSim, with probability p, a uniform draw from the
+    16 two-qubit Pauli strings (identity included) is inserted."""
+    rng = np.random.default_rng(int(seed))
+    out = []
+    for _ in range(count):
+        seq: List[Gate] = []
+        for g in gates:
+            seq.append(g)
+            if g.name == "FSIM" and float(rng.random()) < p:
+                code = int(rng.integers(16))
+                a, b = PAULI_LABELS[code // 4], PAULI_LABELS[code % 4]
+                if a != "I":
+                    seq.append(Gate(a, (g.qubits[0],)))
+                if b != "I":
+                    seq.append(Gate(b, (g.qubits[1],)))
+        out.append(seq)
+    return out
