@@ -332,7 +332,9 @@ int sv_super_op_matrix(const sv_super_op *op, double *out);
 /* Evolve the density matrix held in rho (2n qubits, see above) by the G gates
  * g (on qubits 0..n-1) with the n_ops super operators inserted among them,
  * fused and applied exactly as sv_run_circuit applies a circuit of 2n qubits
- * (same options).  Start from |0..0><0..0| with sv_set_basis(rho, 0).
+ * (same options; a max_k other than -1 must be at least 2k for the largest
+ * super operator, whose gate spans 2k positions).  Start from |0..0><0..0|
+ * with sv_set_basis(rho, 0).
  * SV_PREC_SPLIT_FP16 is refused (SV_ERR_ARG): its tile passes rely on blocks
  * that cannot raise the 2-norm, which super operators may.  Errors:
  * SV_ERR_ARG (odd rho->n, malformed operator, `after` out of order),

@@ -70,7 +70,7 @@ def _check(tag, want, got, tol):
 
 
 @pytest.mark.parametrize("rule,max_k", [(sv.RULE_NONE, 6), (sv.RULE_PAPER, 4), (sv.RULE_ENHANCED, 6),
-                                        (sv.RULE_ENHANCED, 3)])
+                                        (sv.RULE_ENHANCED, 5)])
 @pytest.mark.parametrize("dtype,prec", [("c64", sv.PREC_FP32), ("c64", sv.PREC_SPLIT_BF16), ("c128", sv.PREC_FP64)])
 def test_dm_small_vs_oracle(rule, max_k, dtype, prec):
     n, gates, lib_ops, or_ops = _noisy_case(2, 2, 6, seed=21)
@@ -125,6 +125,8 @@ def test_dm_refuses_fp16_and_odd_states():
         odd.expectation([(1.0, ((0, "Z"),))])
     with pytest.raises(sv.SvError):  # a gate on qubit 2 of a 2-qubit rho
         rho.run([("H", (2,))])
+    with pytest.raises(sv.SvError):  # a 2-qubit channel is a 4-qubit gate: max_k 3 is too small
+        rho.run([("H", (0,))], [sv.depolarizing((0, 1), 0.1, after=1)], max_k=3, rule=sv.RULE_ENHANCED)
     with pytest.raises(sv.SvError):  # operators out of order
         rho.run([("H", (0,)), ("H", (1,))], [sv.amplitude_damping(0, 0.1, after=2),
                                               sv.amplitude_damping(0, 0.1, after=1)])
