@@ -96,9 +96,10 @@ def main():
     ap.add_argument("--rule", default="tiled", choices=["paper", "enhanced", "tiled", "auto"])
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--config", type=int, default=1, choices=[1, 2])
-    ap.add_argument("--workload", default="circuit", choices=["circuit", "gradient", "trajectories"],
+    ap.add_argument("--workload", default="circuit", choices=["circuit", "gradient", "trajectories", "density"],
                     help="circuit: the grid random circuit (default); gradient: 20-qubit ansatz "
-                         "energy + adjoint gradient; trajectories: 512 noisy trajectories")
+                         "energy + adjoint gradient; trajectories: 512 noisy trajectories; density: "
+                         "exact density matrix of a noisy 15-qubit grid circuit (a 30-qubit state)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference", action="store_true")
     ap.add_argument("--no-per-gate", action="store_true")
@@ -124,6 +125,8 @@ def main():
         return bench_gradient(args)
     if args.workload == "trajectories":
         return bench_trajectories(args)
+    if args.workload == "density":
+        return bench_density(args)
     n, gates = wc.config_circuit(args.config)
     bound = [(g.name, g.qubits, g.params) for g in gates]
     ga = sv.GateArray(bound)
@@ -418,6 +421,78 @@ def bench_trajectories(args):
                                              "2q depolarizing p=1e-3 sampled per trajectory",
                                  "gates": sum(len(t_.gates) for t_ in trajs), "amplitudes": amps},
                       "mean_z0": float(np.mean(out["z"]))}), flush=True)
+
+
+def bench_density(args):
+    """Exact density matrix of the 3x5 grid circuit (depth 20) with the
+    two-qubit depolarizing channel (p = 1e-3) after every fSim: rho of 15
+    qubits is a 30-qubit complex64 state (8 GiB).  One step = reset to
+    |0..0><0..0|, rewrite and fuse the super circuit, apply it (tiled rule),
+    and read Tr(rho Z_0)."""
+    import numpy as np
+    import torch
+    import paper_2111_06868_amd as sv
+    from workloads import circuits as wc
+    if args.precision == "fp16":
+        print("bench.py: density matrices do not run split FP16 tile passes (super operators may raise "
+              "the 2-norm they rely on); use --precision bf16 or fp32", file=sys.stderr)
+        sys.exit(2)
+    n = 15
+    gates, channels = wc.noisy_grid_circuit(3, 5, 20, seed=7, p=1e-3)
+    ga = sv.GateArray([(g.name, g.qubits, g.params) for g in gates])
+    ops = [sv.depolarizing(q, p, after=a) for a, q, p in channels]
+    prec = {"fp32": sv.PREC_FP32, "bf16": sv.PREC_SPLIT_BF16}[args.precision]
+    rho = sv.DensityMatrix(n, "c64")
+    Z0 = sv.pauli_sum([(1.0, ((0, "Z"),))])
+    out = {}
+
+    def step():
+        rho.set_basis(0)
+        rho.run(ga, ops, max_k=4, rule=sv.RULE_TILED, precision=prec)
+        out["z0"] = rho.expectation(Z0)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    sv.stats_reset()
+    sv.stats_enable(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        log("step %d done" % i)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    sv.stats_enable(False)
+    fam = 10 if prec == sv.PREC_SPLIT_BF16 else 9
+    cnt = ms = 0
+    for k in range(1, 17):
+        c, m = sv.stats_query(FAMILY_NAMES[fam], k)
+        cnt, ms = cnt + c, ms + m
+    avg_ms = ms / max(cnt, 1)
+    achieved = 16.0 * (1 << (2 * n)) / (avg_ms * 1e-3) / 1e9
+    # complex128 reference run (not timed): Tr(rho Z_0), trace and the first 2^20 entries
+    ref_rho = sv.DensityMatrix(n, "c128").run(ga, ops, max_k=4, rule=sv.RULE_ENHANCED, precision=sv.PREC_FP64)
+    z0_ref = ref_rho.expectation(Z0)
+    head = 1 << 20
+    max_abs = float(np.abs(rho.state.read(0, head).astype(np.complex128) - ref_rho.state.read(0, head)).max())
+    trace = rho.trace()
+    del ref_rho
+    n_ops = len(gates) + len(channels)
+    print(json.dumps({"metric": "noisy super-circuit operations/s (15-qubit density matrix, exact)",
+                      "value": round(n_ops / t, 2), "unit": "operations/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": round(1e3 * t, 3), "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None,
+                      "dtype": {"fp32": "f32", "bf16": "f32; bf16 hi+lo split tile passes"}[args.precision],
+                      "data": "synthetic",
+                      "config": {"workload": "3x5 grid random circuit, depth 20, 2q depolarizing p=1e-3 after "
+                                             "every fSim; rho as a 30-qubit complex64 state",
+                                 "gates": len(gates), "channels": len(channels)},
+                      "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                                   "kernel": FAMILY_NAMES[fam], "avg_launch_ms": round(avg_ms, 4),
+                                   "launches_per_step": cnt // args.steps},
+                      "z0": out["z0"], "z0_c128": z0_ref, "trace": trace,
+                      "max_abs_first_2^20_vs_c128": max_abs}), flush=True)
 
 
 if __name__ == "__main__":
