@@ -347,6 +347,37 @@ int sv_dm_run(sv_state *rho, const sv_gate *g, int G, const sv_super_op *ops, in
  * Synchronises.  An identity term (x = z = 0) gives the trace. */
 int sv_dm_expectation(sv_state *rho, const sv_pauli_sum *H, double *out);
 
+/* ------------------------------------------ Kraus channels sampled on states */
+/* Pure-state sampling of Kraus channels (paper, Simulations with noise
+ * section: noise is simulated exactly on density matrices or by sampling the
+ * Kraus operators on pure states).  The operator must be a Kraus channel
+ * sum_i K_i rho K_i^dagger in sv_super_op form: n_left = n_right operators
+ * (at most 16), right holding the same matrices as left, s = NULL and
+ * superop = NULL; its qubits index the state directly (`after` is used only
+ * by sv_run_trajectory).  Outcome i has weight p_i = ||K_i psi||^2, which
+ * depends on the state (amplitude damping, for example).
+ *
+ * sv_kraus_probabilities: p_out[i] = ||K_i psi||^2 for i < n_left, summed in
+ * FP64 in one pass over the state.  Synchronises.
+ *
+ * sv_apply_kraus_sampled: with S = sum_i p_i, picks the first operator with a
+ * nonzero weight whose running sum exceeds u * S (u in [0, 1), drawn by the
+ * caller) and replaces psi by K_i psi / sqrt(p_i).  chosen (may be NULL)
+ * receives i, p_chosen (may be NULL) p_i / S.  Synchronises.
+ *
+ * sv_run_trajectory: applies the gates g with the operators ops sampled among
+ * them (operator j after the first ops[j].after gates, `after`
+ * nondecreasing) using uniforms[j]; the gate runs between operators are fused
+ * and applied as by sv_run_circuit with options o.  outcomes (may be NULL)
+ * receives the n_ops chosen indices.
+ *
+ * Errors: SV_ERR_ARG (not a Kraus channel, more than 16 operators, u outside
+ * [0, 1), all weights zero), SV_ERR_QUBIT. */
+int sv_kraus_probabilities(sv_state *s, const sv_super_op *op, double *p_out);
+int sv_apply_kraus_sampled(sv_state *s, const sv_super_op *op, double u, int32_t *chosen, double *p_chosen);
+int sv_run_trajectory(sv_state *s, const sv_gate *g, int G, const sv_super_op *ops, int n_ops,
+                      const double *uniforms, const sv_run_opts *o, int32_t *outcomes);
+
 /* ---------------------------------------------------------------- batches */
 /* Many independent circuits of different qubit counts (noisy trajectories:
  * the paper's Simulations with noise section samples noise channels on pure
@@ -414,7 +445,7 @@ int sv_set_tile_union(int max_positions);
  * split-BF16 tile passes, 11 = split-FP16 tile passes; k is the block size,
  * for tile passes the number of blocks in the launch, and for reductions 1 =
  * norm, 2 = inner product, 3 = expectation, 4 = Pauli-sum matvec, 5 =
- * density-matrix trace Tr(rho H). */
+ * density-matrix trace Tr(rho H), 6 = Kraus outcome weights. */
 int sv_stats_enable(int on);
 int sv_stats_reset(void);
 int sv_stats_query(int cls, int64_t *launches, double *total_ms);

@@ -157,3 +157,44 @@ def amplitude_damping(qubit: int, gamma: float, after: int = 0) -> dict:
     K0 = np.array([[1, 0], [0, np.sqrt(1 - gamma)]], dtype=np.complex128)
     K1 = np.array([[0, np.sqrt(gamma)], [0, 0]], dtype=np.complex128)
     return {"qubits": (qubit,), "left": [K0, K1], "after": after}
+
+
+# -------------------------------------------------------------- sampling on pure states
+# Simulations with noise section: a channel sum_i K_i rho K_i^dagger can be
+# sampled on a pure state.  Outcome i has weight p_i = ||K_i psi||^2; the
+# uniform u picks the first i with a nonzero weight whose running sum exceeds
+# u * sum(p), and psi becomes K_i psi / sqrt(p_i).
+def kraus_probabilities(psi: np.ndarray, kraus, qubits: Sequence[int]):
+    return [ref.norm2(ref.apply(psi.copy(), K, qubits)) for K in kraus]
+
+
+def sample_kraus(psi: np.ndarray, kraus, qubits: Sequence[int], u: float):
+    p = kraus_probabilities(psi, kraus, qubits)
+    total = sum(p)
+    pick, run = -1, 0.0
+    for i, w in enumerate(p):
+        run += w
+        if w > 0:
+            pick = i
+            if u * total < run:
+                break
+    out = ref.apply(psi.copy(), kraus[pick], qubits) / np.sqrt(p[pick])
+    return out, pick
+
+
+def trajectory(n: int, gates, ops, uniforms, initial: str = "0"):
+    """Gates in order with the Kraus channels ops (dicts with "left",
+    "qubits", "after") sampled by uniforms[j]; returns (psi, outcomes)."""
+    psi = ref.product_state(n, initial)
+    ops = list(ops)
+    outcomes = []
+    j = 0
+    for i, g in enumerate(list(gates) + [None]):
+        while j < len(ops) and ops[j]["after"] <= i:
+            psi, pick = sample_kraus(psi, ops[j]["left"], ops[j]["qubits"], uniforms[j])
+            outcomes.append(pick)
+            j += 1
+        if g is None:
+            break
+        ref.apply(psi, ref.matrix_of(g), g.qubits)
+    return psi, outcomes

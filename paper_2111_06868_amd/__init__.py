@@ -251,6 +251,48 @@ class State:
         N.check(N.lib().sv_expectation(self.h, H.ptr, ctypes.byref(out)))
         return out.value
 
+    # -- Kraus channels sampled on the state
+    def kraus_probabilities(self, op: "SuperOp") -> np.ndarray:
+        """||K_i psi||^2 for the Kraus operators of op (FP64 on the device)."""
+        c, keep = N.sv_super_op(), []
+        op.fill(c, keep)
+        out = np.zeros(max(c.n_left, 1), dtype=np.float64)
+        N.check(N.lib().sv_kraus_probabilities(self.h, ctypes.byref(c),
+                                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out[:c.n_left]
+
+    def apply_kraus_sampled(self, op: "SuperOp", u: float):
+        """Apply K_i / sqrt(p_i), i drawn by the uniform u; returns (i, p_i)."""
+        c, keep = N.sv_super_op(), []
+        op.fill(c, keep)
+        i, p = ctypes.c_int32(), ctypes.c_double()
+        N.check(N.lib().sv_apply_kraus_sampled(self.h, ctypes.byref(c), float(u), ctypes.byref(i), ctypes.byref(p)))
+        return i.value, p.value
+
+    def run_trajectory(self, gates, ops, uniforms, max_k: int = SV_MAX_K, precision: int = None,
+                       rule: int = RULE_NONE) -> np.ndarray:
+        """Gates with Kraus channels sampled among them (sv_run_trajectory);
+        returns the chosen operator indices."""
+        ga = gates if isinstance(gates, GateArray) else GateArray(gates)
+        ops = list(ops)
+        arr = (N.sv_super_op * max(len(ops), 1))()
+        keep = []
+        for j, op in enumerate(ops):
+            op.fill(arr[j], keep)
+        u = np.ascontiguousarray(uniforms, dtype=np.float64)
+        if u.size != len(ops):
+            raise ValueError("one uniform per operator")
+        outcomes = np.zeros(max(len(ops), 1), dtype=np.int32)
+        o = N.sv_run_opts()
+        o.max_k = int(max_k)
+        o.precision = (PREC_FP32 if self.dtype == C64 else PREC_FP64) if precision is None else int(precision)
+        o.rule = int(rule)
+        o.use_graph = 0
+        N.check(N.lib().sv_run_trajectory(self.h, ga.ptr, ga.n, ctypes.cast(arr, ctypes.POINTER(N.sv_super_op)),
+                                          len(ops), u.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                          ctypes.byref(o), outcomes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return outcomes[:len(ops)]
+
     def apply_pauli_sum(self, terms, out: "State"):
         H = terms if isinstance(terms, PauliSum) else PauliSum(terms)
         N.check(N.lib().sv_apply_pauli_sum(self.h, H.ptr, out.h))
@@ -274,7 +316,7 @@ class SuperOp:
         as_ops = lambda ms: np.ascontiguousarray(np.array(ms, dtype=np.complex128).reshape(-1, D, D))
         self.superop = None if superop is None else np.ascontiguousarray(superop, dtype=np.complex128)
         self.left = None if left is None else as_ops(left)
-        self.right = None if right is None and left is None else as_ops(left if right is None else right)
+        self.right = self.left if right is None else as_ops(right)
         self.s = None if s is None else np.ascontiguousarray(s, dtype=np.complex128)
 
     def at(self, after: int) -> "SuperOp":

@@ -118,6 +118,10 @@ SIGNATURES = {
     "sv_super_op_matrix": (_I, [ctypes.POINTER(sv_super_op), _D]),
     "sv_dm_run": (_I, [_P, _GP, _I, ctypes.POINTER(sv_super_op), _I, ctypes.POINTER(sv_run_opts)]),
     "sv_dm_expectation": (_I, [_P, _PS, _D]),
+    "sv_kraus_probabilities": (_I, [_P, ctypes.POINTER(sv_super_op), _D]),
+    "sv_apply_kraus_sampled": (_I, [_P, ctypes.POINTER(sv_super_op), ctypes.c_double, _I32P, _D]),
+    "sv_run_trajectory": (_I, [_P, _GP, _I, ctypes.POINTER(sv_super_op), _I, _D,
+                               ctypes.POINTER(sv_run_opts), _I32P]),
     "sv_batch_required_bytes": (_I, [ctypes.POINTER(sv_batch_desc), ctypes.POINTER(_SZ)]),
     "sv_batch_create": (_I, [ctypes.POINTER(sv_batch_desc), _P, _SZ, _P, ctypes.POINTER(_P)]),
     "sv_batch_run": (_I, [_P, _I, _D]),

@@ -393,11 +393,21 @@ extern "C" int sv_gate_matrix(const sv_gate *g, double *out)
     return SV_OK;
 }
 
+namespace {
+int apply_gate_impl(sv_state *s, const sv_gate *g);
+}
+
 extern "C" int sv_apply_gate(sv_state *s, const sv_gate *g)
 {
     clear_error();
     if (int rc = check_state(s)) return rc;
     if (int rc = validate_gates(g, 1, s->n)) return rc;
+    return apply_gate_impl(s, g);
+}
+
+namespace {
+int apply_gate_impl(sv_state *s, const sv_gate *g)
+{
     Launch L;
     L.k = g->k;
     int sq[SV_MAX_K];
@@ -411,6 +421,7 @@ extern "C" int sv_apply_gate(sv_state *s, const sv_gate *g)
     if (int rc = select_device(s)) return rc;
     return run_launches(s, v, false);
 }
+}  // namespace
 
 // ============================================================== fusion
 extern "C" int sv_fuse(const sv_gate *g, int G, int n, int max_k, int rule, sv_plan **out)
@@ -743,6 +754,125 @@ extern "C" int sv_dm_expectation(sv_state *rho, const sv_pauli_sum *H, double *o
     }
     SV_HIP(hipEventRecord(rho->arena_free, rho->stream));
     return read_result(rho, res, 1, out);
+}
+
+namespace {
+
+// p[i] = ||K_i psi||^2 (FP64, one pass over the state).  Synchronises.
+int kraus_weights(sv_state *s, const std::vector<cd> &mats, int n_ops, int k, const int *pos, double *p)
+{
+    if (int rc = select_device(s)) return rc;
+    SV_HIP(s->red.ensure(sizeof(double) * (size_t(dev::kMaxKraus) * dev::kRedBlocks + 64)));
+    SV_HIP(hipEventSynchronize(s->arena_free));
+    const size_t bytes = sizeof(cd) * mats.size();
+    SV_HIP(s->stage.ensure(bytes));
+    SV_HIP(s->arena.ensure(bytes));
+    std::memcpy(s->stage.p, mats.data(), bytes);
+    SV_HIP(hipMemcpyAsync(s->arena.p, s->stage.p, bytes, hipMemcpyHostToDevice, s->stream));
+    dev::KrausDev K;
+    K.n_ops = n_ops;
+    K.k = k;
+    for (int j = 0; j < 3; ++j) K.pos[j] = j < k ? pos[j] : 0;
+    K.m = static_cast<const double *>(s->arena.p);
+    double *part = static_cast<double *>(s->red.p);
+    double *res = part + size_t(dev::kMaxKraus) * dev::kRedBlocks;
+    {
+        LaunchTimer t(stat_class(FAM_REDUCE, 6), s->stream);
+        SV_HIP(dev::launch_kraus_probs(s->dtype, s->buf, s->n, K, part, res, s->stream));
+    }
+    SV_HIP(hipEventRecord(s->arena_free, s->stream));
+    return read_result(s, res, size_t(n_ops), p);
+}
+
+// Draw one Kraus operator with probability p_i / sum p by the uniform u and
+// apply K_i / sqrt(p_i).  The first i whose running sum exceeds u * sum p is
+// taken (zero-weight operators are never taken).
+int sample_kraus(sv_state *s, const sv_super_op &op, double u, int32_t *chosen, double *p_chosen)
+{
+    std::vector<cd> mats;
+    int pos[3];
+    if (int rc = kraus_canonical(op, s->n, mats, pos)) return rc;
+    double p[dev::kMaxKraus];
+    if (int rc = kraus_weights(s, mats, op.n_left, op.k, pos, p)) return rc;
+    double total = 0.0;
+    for (int i = 0; i < op.n_left; ++i) total += p[i];
+    if (!(total > 0.0) || !std::isfinite(total)) return fail(SV_ERR_ARG, "Kraus outcome weights sum to %g", total);
+    int pick = -1;
+    double run = 0.0;
+    for (int i = 0; i < op.n_left; ++i) {
+        run += p[i];
+        if (p[i] > 0.0) pick = i;  // the last nonzero one, should rounding leave u * total above every sum
+        if (p[i] > 0.0 && u * total < run) break;
+    }
+    const size_t D = size_t(1) << op.k;
+    const double scale = 1.0 / std::sqrt(p[pick]);
+    std::vector<double> m(2 * D * D);
+    for (size_t e = 0; e < 2 * D * D; ++e) m[e] = op.left[2 * D * D * pick + e] * scale;
+    sv_gate h{};
+    h.kind = SV_G_MATRIX;
+    h.k = op.k;
+    h.param = -1;
+    for (int a = 0; a < op.k; ++a) h.q[a] = op.q[a];
+    h.m = m.data();
+    if (int rc = apply_gate_impl(s, &h)) return rc;
+    if (chosen) *chosen = pick;
+    if (p_chosen) *p_chosen = p[pick] / total;
+    return SV_OK;
+}
+
+}  // namespace
+
+extern "C" int sv_kraus_probabilities(sv_state *s, const sv_super_op *op, double *p_out)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    if (!op || !p_out) return fail(SV_ERR_ARG, "NULL argument");
+    std::vector<cd> mats;
+    int pos[3];
+    if (int rc = kraus_canonical(*op, s->n, mats, pos)) return rc;
+    return kraus_weights(s, mats, op->n_left, op->k, pos, p_out);
+}
+
+extern "C" int sv_apply_kraus_sampled(sv_state *s, const sv_super_op *op, double u, int32_t *chosen,
+                                      double *p_chosen)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    if (!op) return fail(SV_ERR_ARG, "NULL operator");
+    if (!(u >= 0.0 && u < 1.0)) return fail(SV_ERR_ARG, "uniform %g outside [0, 1)", u);
+    return sample_kraus(s, *op, u, chosen, p_chosen);
+}
+
+extern "C" int sv_run_trajectory(sv_state *s, const sv_gate *g, int G, const sv_super_op *ops, int n_ops,
+                                 const double *uniforms, const sv_run_opts *o, int32_t *outcomes)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    if (int rc = validate_gates(g, G, s->n)) return rc;
+    if (n_ops < 0 || (n_ops && (!ops || !uniforms))) return fail(SV_ERR_ARG, "NULL operator or uniform array");
+    for (int j = 0; j < n_ops; ++j) {
+        std::vector<cd> mats;
+        int pos[3];
+        if (int rc = kraus_canonical(ops[j], s->n, mats, pos)) return rc;
+        if (ops[j].after < 0 || ops[j].after > G || (j && ops[j].after < ops[j - 1].after))
+            return fail(SV_ERR_ARG, "operator %d: after = %d out of order (0..%d, nondecreasing)", j, ops[j].after, G);
+        if (!(uniforms[j] >= 0.0 && uniforms[j] < 1.0))
+            return fail(SV_ERR_ARG, "uniform %d = %g outside [0, 1)", j, uniforms[j]);
+    }
+    int done = 0;
+    for (int j = 0; j <= n_ops; ++j) {
+        const int upto = j < n_ops ? ops[j].after : G;
+        if (upto > done) {
+            if (int rc = run_circuit_impl(s, g + done, upto - done, o)) return rc;
+            done = upto;
+        }
+        if (j < n_ops) {
+            int32_t pick = -1;
+            if (int rc = sample_kraus(s, ops[j], uniforms[j], &pick, nullptr)) return rc;
+            if (outcomes) outcomes[j] = pick;
+        }
+    }
+    return SV_OK;
 }
 
 extern "C" int sv_apply_pauli_sum(sv_state *psi, const sv_pauli_sum *H, sv_state *out)

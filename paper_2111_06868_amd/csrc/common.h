@@ -88,6 +88,10 @@ void block_matrix(const sv_gate *g, Block &b);
 // new MATRIX gates point into `store`.
 int dm_expand(const sv_gate *g, int G, int n, const sv_super_op *ops, int n_ops, std::vector<sv_gate> &out,
               std::vector<std::vector<double>> &store);
+// Kraus channels sampled on pure states (sv_kraus_probabilities and the
+// sampled application): validation and canonical matrices.
+constexpr int kMaxKrausOps = 16;
+int kraus_canonical(const sv_super_op &op, int n, std::vector<cd> &mats, int *sorted_q);
 
 }  // namespace sv
 

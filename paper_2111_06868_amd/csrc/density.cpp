@@ -156,6 +156,34 @@ int dm_expand(const sv_gate *g, int G, int n, const sv_super_op *ops, int n_ops,
     return SV_OK;
 }
 
+// A Kraus channel sum_i K_i rho K_i^dagger for sampling on pure states: the
+// operator must be in Kraus form (no s, no matrix form, right == left) with
+// at most kMaxKrausOps operators on qubits below n.  Fills the canonical
+// matrices (local bit j on the j-th lowest position) and the sorted positions.
+int kraus_canonical(const sv_super_op &op, int n, std::vector<cd> &mats, int *sorted_q)
+{
+    if (int rc = check_super_op(op)) return rc;
+    if (op.superop || op.s) return fail(SV_ERR_ARG, "sampling needs a Kraus channel (no s matrix, no matrix form)");
+    if (op.n_left > kMaxKrausOps) return fail(SV_ERR_ARG, "%d Kraus operators (at most %d)", op.n_left, kMaxKrausOps);
+    const size_t D = size_t(1) << op.k;
+    if (std::memcmp(op.left, op.right, sizeof(double) * 2 * D * D * op.n_left) != 0)
+        return fail(SV_ERR_ARG, "sampling needs right operators equal to the left ones");
+    sv_gate h{};
+    h.kind = SV_G_MATRIX;
+    h.k = op.k;
+    h.param = -1;
+    for (int a = 0; a < op.k; ++a) h.q[a] = op.q[a];
+    if (int rc = check_gate_qubits(h, n)) return rc;
+    mats.clear();
+    for (int i = 0; i < op.n_left; ++i) {
+        h.m = op.left + 2 * D * D * i;
+        std::vector<cd> m;
+        if (int rc = gate_matrix_canonical(h, m, sorted_q)) return rc;
+        mats.insert(mats.end(), m.begin(), m.end());
+    }
+    return SV_OK;
+}
+
 }  // namespace sv
 
 extern "C" int sv_super_op_matrix(const sv_super_op *op, double *out)

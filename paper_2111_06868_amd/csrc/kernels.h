@@ -130,6 +130,20 @@ hipError_t launch_pauli_expect(int dtype, const void *psi, int n, const PauliDev
                                double *d_out, hipStream_t st);
 hipError_t launch_pauli_apply(int dtype, const void *psi, void *out, int n, const PauliDev &H,
                               hipStream_t st);
+// Kraus channel for outcome weights: n_ops operators on k (1..3) ascending
+// positions, 2^k x 2^k complex128 each in the canonical local order (bit j
+// on pos[j]), back to back in device memory.
+constexpr int kMaxKraus = 16;
+struct KrausDev {
+    int n_ops;
+    int k;
+    int pos[3];
+    const double *m;
+};
+// p_i = ||K_i psi||^2 for i < n_ops into d_out[0..kMaxKraus) (FP64; d_partials
+// holds kRedBlocks * kMaxKraus doubles).
+hipError_t launch_kraus_probs(int dtype, const void *psi, int n, const KrausDev &K, double *d_partials,
+                              double *d_out, hipStream_t st);
 // Tr(rho H) of rho (n qubits) held row-major in a state of 2n qubits.
 hipError_t launch_dm_expect(int dtype, const void *rho, int n, const PauliDev &H, double *d_partials, double *d_out,
                             hipStream_t st);

@@ -171,6 +171,59 @@ __global__ void __launch_bounds__(kRedThreads) k_dm_expect(const T *__restrict__
     block_reduce_store<1>(acc, partials + blockIdx.x);
 }
 
+// Outcome weights of a Kraus channel on k sorted positions: p_i = ||K_i psi||^2
+// (paper, Simulations with noise section: channels sampled on pure states).
+// Each thread gathers the 2^k amplitudes of one group (local bit j on the
+// j-th lowest position), forms K_i x for every operator and adds |K_i x|^2,
+// all in FP64.
+template <typename T, int K>
+__global__ void __launch_bounds__(kRedThreads) k_kraus_probs(const T *__restrict__ psi, int n, const KrausDev Kd,
+                                                            double *partials)
+{
+    constexpr int D = 1 << K;
+    Acc<kMaxKraus> acc;
+#pragma unroll
+    for (int i = 0; i < kMaxKraus; ++i) acc.v[i] = 0.0;
+    const uint64_t groups = uint64_t(1) << (n - K);
+    for (uint64_t g = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; g < groups;
+         g += uint64_t(kRedBlocks) * kRedThreads) {
+        uint64_t base = g;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {  // insert a zero bit at each position, lowest first
+            const uint64_t low = base & ((uint64_t(1) << Kd.pos[j]) - 1);
+            base = ((base - low) << 1) | low;
+        }
+        double xr[D], xi[D];
+#pragma unroll
+        for (int m = 0; m < D; ++m) {
+            uint64_t idx = base;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if ((m >> j) & 1) idx |= uint64_t(1) << Kd.pos[j];
+            ld(psi, idx, xr[m], xi[m]);
+        }
+#pragma unroll
+        for (int i = 0; i < kMaxKraus; ++i) {
+            if (i >= Kd.n_ops) break;
+            const double *M = Kd.m + size_t(2) * D * D * i;
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < D; ++r) {
+                double yr = 0.0, yi = 0.0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    const double mr = M[2 * (r * D + c)], mi = M[2 * (r * D + c) + 1];
+                    yr = fma(mr, xr[c], fma(-mi, xi[c], yr));
+                    yi = fma(mr, xi[c], fma(mi, xr[c], yi));
+                }
+                s = fma(yr, yr, fma(yi, yi, s));
+            }
+            acc.v[i] += s;
+        }
+    }
+    block_reduce_store<kMaxKraus>(acc, partials + size_t(blockIdx.x) * kMaxKraus);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_pauli_apply(const T *__restrict__ psi, T *__restrict__ out, uint64_t N,
                                                     const PauliDev H)
@@ -260,6 +313,32 @@ hipError_t launch_dm_expect(int dtype, const void *rho, int n, const PauliDev &H
     else
         hipLaunchKernelGGL(k_dm_expect<double>, dim3(kRedBlocks), dim3(kRedThreads), 0, st, static_cast<const double *>(rho), n, H, d_partials);
     hipLaunchKernelGGL(k_final<1>, dim3(1), dim3(kRedThreads), 0, st, d_partials, kRedBlocks, d_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_kraus_probs(int dtype, const void *psi, int n, const KrausDev &K, double *d_partials,
+                              double *d_out, hipStream_t st)
+{
+    if (K.k < 1 || K.k > 3 || K.k > n || K.n_ops < 1 || K.n_ops > kMaxKraus) return hipErrorInvalidValue;
+    const dim3 g(kRedBlocks), t(kRedThreads);
+    const bool c64 = dtype == SV_C64;
+    const float *pf = static_cast<const float *>(psi);
+    const double *pd = static_cast<const double *>(psi);
+    switch (K.k) {
+    case 1:
+        if (c64) hipLaunchKernelGGL((k_kraus_probs<float, 1>), g, t, 0, st, pf, n, K, d_partials);
+        else hipLaunchKernelGGL((k_kraus_probs<double, 1>), g, t, 0, st, pd, n, K, d_partials);
+        break;
+    case 2:
+        if (c64) hipLaunchKernelGGL((k_kraus_probs<float, 2>), g, t, 0, st, pf, n, K, d_partials);
+        else hipLaunchKernelGGL((k_kraus_probs<double, 2>), g, t, 0, st, pd, n, K, d_partials);
+        break;
+    default:
+        if (c64) hipLaunchKernelGGL((k_kraus_probs<float, 3>), g, t, 0, st, pf, n, K, d_partials);
+        else hipLaunchKernelGGL((k_kraus_probs<double, 3>), g, t, 0, st, pd, n, K, d_partials);
+        break;
+    }
+    hipLaunchKernelGGL(k_final<kMaxKraus>, dim3(1), dim3(kRedThreads), 0, st, d_partials, kRedBlocks, d_out);
     return hipGetLastError();
 }
 

@@ -146,3 +146,79 @@ def test_dm_exact_z0_matches_trajectory_mean():
     mean, se = float(np.mean(z)), float(np.std(z) / math.sqrt(len(z)))
     print("[parity] exact <Z0> %.6f, trajectory mean %.6f +- %.6f" % (exact, mean, se), flush=True)
     assert abs(mean - exact) <= 5 * se + 1e-6
+
+
+# ------------------------------------------------ Kraus channels sampled on states
+def _random_state(n, dtype, seed):
+    rng = np.random.default_rng(seed)
+    psi = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    psi /= np.linalg.norm(psi)
+    return psi, sv.State(n, dtype).write(psi)
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("qs,m", [((0,), 2), ((11,), 4), ((3, 9), 3), ((10, 2, 6), 5), ((1, 0, 11), 16)])
+def test_kraus_probabilities_vs_oracle(dtype, qs, m):
+    n = 12
+    psi, st = _random_state(n, dtype, seed=len(qs) * 10 + m)
+    K = wc.random_kraus_from_seed(100 + m, len(qs), m)
+    got = st.kraus_probabilities(sv.SuperOp(qs, left=K))
+    want = np.array(dm.kraus_probabilities(psi, K, qs))
+    rel = float(np.abs(got - want).max() / want.max())
+    print("[parity] Kraus weights %s q=%s m=%d: rel %.3e" % (dtype, qs, m, rel), flush=True)
+    assert rel <= (1e-6 if dtype == "c64" else 1e-12)
+    assert abs(got.sum() - 1.0) <= (1e-6 if dtype == "c64" else 1e-12)
+
+
+def _jump_case(n, seed, count):
+    gates = wc.grid_rqc(2, n // 2, 6, seed)
+    rng = np.random.default_rng(seed)
+    lib_ops, or_ops = [], []
+    for i, g in enumerate(gates):
+        if g.name == "FSIM" and rng.random() < 0.5:
+            q = int(rng.integers(n))
+            lib_ops.append(sv.amplitude_damping(q, 0.2, after=i + 1))
+            or_ops.append(dm.amplitude_damping(q, 0.2, after=i + 1))
+        if len(lib_ops) >= count:
+            break
+    K = wc.random_kraus_from_seed(seed, 2, 3)
+    last = lib_ops[-1].after
+    lib_ops.append(sv.SuperOp((1, n - 1), left=K, after=last))
+    or_ops.append({"qubits": (1, n - 1), "left": K, "after": last})
+    return gates, lib_ops, or_ops
+
+
+@pytest.mark.parametrize("dtype,prec", [("c64", sv.PREC_FP32), ("c128", sv.PREC_FP64)])
+def test_trajectory_vs_oracle(dtype, prec):
+    n = 10
+    gates, lib_ops, or_ops = _jump_case(n, seed=3, count=8)
+    u = np.random.default_rng(5).random(len(lib_ops))
+    st = sv.State(n, dtype)
+    got = st.run_trajectory(to_binding(gates), lib_ops, u, max_k=4, precision=prec, rule=sv.RULE_ENHANCED)
+    want_psi, want = dm.trajectory(n, gates, or_ops, u)
+    print("[parity] trajectory %s outcomes %s" % (dtype, list(got)), flush=True)
+    assert list(got) == list(want)
+    psi = st.read().astype(np.complex128)
+    err = float(np.abs(psi - want_psi).max())
+    print("[parity] trajectory %s max_abs %.3e" % (dtype, err), flush=True)
+    assert err <= (2e-6 if dtype == "c64" else 1e-12)
+
+
+def test_jump_trajectory_mean_matches_density_matrix():
+    # amplitude damping sampled on pure states against the exact density matrix
+    n = 8
+    gates, lib_ops, _ = _jump_case(n, seed=9, count=10)
+    exact = sv.DensityMatrix(n, "c128").run(to_binding(gates), lib_ops, max_k=4,
+                                            rule=sv.RULE_ENHANCED).expectation([(1.0, ((0, "Z"),))])
+    rng = np.random.default_rng(17)
+    ga = sv.GateArray(to_binding(gates))
+    st = sv.State(n, "c64")
+    Z0 = sv.pauli_sum([(1.0, ((0, "Z"),))])
+    z = []
+    for _ in range(400):
+        st.set_basis(0)
+        st.run_trajectory(ga, lib_ops, rng.random(len(lib_ops)), max_k=4, rule=sv.RULE_ENHANCED)
+        z.append(st.expectation(Z0))
+    mean, se = float(np.mean(z)), float(np.std(z) / math.sqrt(len(z)))
+    print("[parity] exact <Z0> %.6f, jump-trajectory mean %.6f +- %.6f" % (exact, mean, se), flush=True)
+    assert abs(mean - exact) <= 5 * se + 1e-6

@@ -110,3 +110,48 @@ def test_random_channel_keeps_a_density_matrix():
         assert abs(np.trace(out) - 1) < 1e-13
         assert np.abs(out - out.conj().T).max() < 1e-14
         assert np.linalg.eigvalsh(out).min() > -1e-13
+
+
+def test_sampled_amplitude_damping_closed_form():
+    g = 0.3
+    K = dm.amplitude_damping(0, g)["left"]
+    one = np.array([0, 1], dtype=np.complex128)
+    p = dm.kraus_probabilities(one, K, (0,))
+    assert abs(p[0] - (1 - g)) < 1e-15 and abs(p[1] - g) < 1e-15
+    psi, i = dm.sample_kraus(one, K, (0,), 0.5)
+    assert i == 0 and np.abs(psi - one).max() < 1e-15
+    psi, i = dm.sample_kraus(one, K, (0,), 0.8)
+    assert i == 1 and np.abs(psi - np.array([1, 0])).max() < 1e-15
+
+
+def test_branches_of_sampled_channels_sum_to_the_density_matrix():
+    # every outcome sequence, weighted by its probability, reproduces rho
+    n = 3
+    gates = wc.grid_rqc(1, 3, 3, seed=4)
+    ops = [dm.amplitude_damping(0, 0.35, after=3),
+           {"qubits": (2, 1), "left": wc.random_kraus_from_seed(8, 2, 3), "after": 6},
+           dm.dephasing(1, 0.2, "X", after=len(gates))]
+    rho = dm.simulate(n, gates, ops)
+
+    def walk(psi, start, j, weight, acc):
+        stop = ops[j]["after"] if j < len(ops) else len(gates)
+        psi = psi.copy()
+        for g in gates[start:stop]:
+            ref.apply(psi, ref.matrix_of(g), g.qubits)
+        if j == len(ops):
+            acc += weight * dm.pure(psi)
+            return
+        p = dm.kraus_probabilities(psi, ops[j]["left"], ops[j]["qubits"])
+        assert abs(sum(p) - 1) < 1e-13
+        run = 0.0
+        for i, w in enumerate(p):
+            if w > 1e-15:
+                u = (run + w / 2) / sum(p)  # the middle of outcome i's interval
+                nxt, pick = dm.sample_kraus(psi, ops[j]["left"], ops[j]["qubits"], u)
+                assert pick == i
+                walk(nxt, stop, j + 1, weight * w, acc)
+            run += w
+
+    acc = np.zeros_like(rho)
+    walk(ref.product_state(n, "0"), 0, 0, 1.0, acc)
+    assert np.abs(acc - rho).max() < 1e-13
