@@ -96,10 +96,11 @@ def main():
     ap.add_argument("--rule", default="tiled", choices=["paper", "enhanced", "tiled", "auto"])
     ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp16"])
     ap.add_argument("--config", type=int, default=1, choices=[1, 2])
-    ap.add_argument("--workload", default="circuit", choices=["circuit", "gradient", "trajectories", "density"],
+    ap.add_argument("--workload", default="circuit", choices=["circuit", "gradient", "trajectories", "density", "jumps"],
                     help="circuit: the grid random circuit (default); gradient: 20-qubit ansatz "
                          "energy + adjoint gradient; trajectories: 512 noisy trajectories; density: "
-                         "exact density matrix of a noisy 15-qubit grid circuit (a 30-qubit state)")
+                         "exact density matrix of a noisy 15-qubit grid circuit (a 30-qubit state); jumps: "
+                         "amplitude damping sampled on a 26-qubit state")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference", action="store_true")
     ap.add_argument("--no-per-gate", action="store_true")
@@ -127,6 +128,8 @@ def main():
         return bench_trajectories(args)
     if args.workload == "density":
         return bench_density(args)
+    if args.workload == "jumps":
+        return bench_jumps(args)
     n, gates = wc.config_circuit(args.config)
     bound = [(g.name, g.qubits, g.params) for g in gates]
     ga = sv.GateArray(bound)
@@ -493,6 +496,58 @@ def bench_density(args):
                                    "launches_per_step": cnt // args.steps},
                       "z0": out["z0"], "z0_c128": z0_ref, "trace": trace,
                       "max_abs_first_2^20_vs_c128": max_abs}), flush=True)
+
+
+def bench_jumps(args):
+    """Amplitude damping (gamma = 0.01) sampled on a pure 26-qubit state: the
+    2x13 grid circuit of depth 10 with the channel on every qubit after each
+    cycle's fSims.  One step = one trajectory: fused gate runs
+    between channels, and per channel one FP64 pass for the outcome weights,
+    the draw and the application of K_i / sqrt(p_i)."""
+    import numpy as np
+    import paper_2111_06868_amd as sv
+    from workloads import circuits as wc
+    n = 26
+    gates = wc.grid_rqc(2, 13, 10, seed=5)
+    ends = [i + 1 for i, g in enumerate(gates)
+            if g.name == "FSIM" and (i + 1 == len(gates) or gates[i + 1].name != "FSIM")]
+    ops = [sv.amplitude_damping(q, 0.01, after=a) for a in ends for q in range(n)]
+    ga = sv.GateArray([(g.name, g.qubits, g.params) for g in gates])
+    st = sv.State(n, "c64")
+    rng = np.random.default_rng(6)
+    out = {}
+
+    def step():
+        st.set_basis(0)
+        out["jumps"] = int(np.count_nonzero(st.run_trajectory(ga, ops, rng.random(len(ops)), max_k=4,
+                                                              rule=sv.RULE_TILED)))
+
+    for _ in range(args.warmup):
+        step()
+    sv.stats_reset()
+    sv.stats_enable(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        log("step %d done (%d jumps)" % (i, out["jumps"]))
+    t = (time.perf_counter() - t0) / args.steps
+    sv.stats_enable(False)
+    cnt, ms = sv.stats_query("reduce", 6)
+    avg_ms = ms / max(cnt, 1)
+    achieved = 8.0 * (1 << n) / (avg_ms * 1e-3) / 1e9
+    print(json.dumps({"metric": "sampled Kraus channels/s (amplitude damping on a 26-qubit state)",
+                      "value": round(len(ops) / t, 2), "unit": "channels/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": round(1e3 * t, 3), "higher_is_better": True,
+                      "scaling": "weak", "vs_baseline": None, "dtype": "f32 state, f64 weights",
+                      "data": "synthetic",
+                      "config": {"workload": "2x13 grid random circuit, depth 10, amplitude damping gamma=0.01 on "
+                                             "every qubit after each cycle, one trajectory per step",
+                                 "gates": len(gates), "channels": len(ops)},
+                      "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                                   "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                                   "kernel": "k_kraus_probs", "avg_launch_ms": round(avg_ms, 4),
+                                   "launches_per_step": cnt // max(args.steps, 1)},
+                      "jumps_last_step": out["jumps"]}), flush=True)
 
 
 if __name__ == "__main__":

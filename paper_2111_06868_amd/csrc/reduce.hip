@@ -173,52 +173,63 @@ __global__ void __launch_bounds__(kRedThreads) k_dm_expect(const T *__restrict__
 
 // Outcome weights of a Kraus channel on k sorted positions: p_i = ||K_i psi||^2
 // (paper, Simulations with noise section: channels sampled on pure states).
-// Each thread gathers the 2^k amplitudes of one group (local bit j on the
-// j-th lowest position), forms K_i x for every operator and adds |K_i x|^2,
-// all in FP64.
+// Each thread gathers the 2^k amplitudes of U groups (local bit j on the j-th
+// lowest position; all loads issued before any arithmetic, so that U groups
+// are in flight per thread), forms K_i x for every operator and adds
+// |K_i x|^2, all in FP64.  The per-thread order of the groups is fixed, so the
+// result is reproducible.
 template <typename T, int K>
 __global__ void __launch_bounds__(kRedThreads) k_kraus_probs(const T *__restrict__ psi, int n, const KrausDev Kd,
                                                             double *partials)
 {
     constexpr int D = 1 << K;
+    constexpr int U = K == 3 ? 2 : 4;
     Acc<kMaxKraus> acc;
 #pragma unroll
     for (int i = 0; i < kMaxKraus; ++i) acc.v[i] = 0.0;
     const uint64_t groups = uint64_t(1) << (n - K);
-    for (uint64_t g = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; g < groups;
-         g += uint64_t(kRedBlocks) * kRedThreads) {
-        uint64_t base = g;
+    const uint64_t stride = uint64_t(kRedBlocks) * kRedThreads;
+    for (uint64_t g0 = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; g0 < groups; g0 += U * stride) {
+        double xr[U][D], xi[U][D];
 #pragma unroll
-        for (int j = 0; j < K; ++j) {  // insert a zero bit at each position, lowest first
-            const uint64_t low = base & ((uint64_t(1) << Kd.pos[j]) - 1);
-            base = ((base - low) << 1) | low;
-        }
-        double xr[D], xi[D];
+        for (int u = 0; u < U; ++u) {
+            const uint64_t g = g0 + u * stride;
+            uint64_t base = g < groups ? g : 0;
 #pragma unroll
-        for (int m = 0; m < D; ++m) {
-            uint64_t idx = base;
-#pragma unroll
-            for (int j = 0; j < K; ++j)
-                if ((m >> j) & 1) idx |= uint64_t(1) << Kd.pos[j];
-            ld(psi, idx, xr[m], xi[m]);
-        }
-#pragma unroll
-        for (int i = 0; i < kMaxKraus; ++i) {
-            if (i >= Kd.n_ops) break;
-            const double *M = Kd.m + size_t(2) * D * D * i;
-            double s = 0.0;
-#pragma unroll
-            for (int r = 0; r < D; ++r) {
-                double yr = 0.0, yi = 0.0;
-#pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    const double mr = M[2 * (r * D + c)], mi = M[2 * (r * D + c) + 1];
-                    yr = fma(mr, xr[c], fma(-mi, xi[c], yr));
-                    yi = fma(mr, xi[c], fma(mi, xr[c], yi));
-                }
-                s = fma(yr, yr, fma(yi, yi, s));
+            for (int j = 0; j < K; ++j) {  // insert a zero bit at each position, lowest first
+                const uint64_t low = base & ((uint64_t(1) << Kd.pos[j]) - 1);
+                base = ((base - low) << 1) | low;
             }
-            acc.v[i] += s;
+#pragma unroll
+            for (int m = 0; m < D; ++m) {
+                uint64_t idx = base;
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    if ((m >> j) & 1) idx |= uint64_t(1) << Kd.pos[j];
+                ld(psi, idx, xr[u][m], xi[u][m]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (g0 + u * stride >= groups) continue;
+#pragma unroll
+            for (int i = 0; i < kMaxKraus; ++i) {
+                if (i >= Kd.n_ops) continue;  // uniform
+                const double *M = Kd.m + size_t(2) * D * D * i;
+                double s = 0.0;
+#pragma unroll
+                for (int r = 0; r < D; ++r) {
+                    double yr = 0.0, yi = 0.0;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) {
+                        const double mr = M[2 * (r * D + c)], mi = M[2 * (r * D + c) + 1];
+                        yr = fma(mr, xr[u][c], fma(-mi, xi[u][c], yr));
+                        yi = fma(mr, xi[u][c], fma(mi, xr[u][c], yi));
+                    }
+                    s = fma(yr, yr, fma(yi, yi, s));
+                }
+                acc.v[i] += s;
+            }
         }
     }
     block_reduce_store<kMaxKraus>(acc, partials + size_t(blockIdx.x) * kMaxKraus);
