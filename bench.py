@@ -106,6 +106,9 @@ def main():
     ap.add_argument("--no-per-gate", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="tune launch shapes first, fuse with max_k=-1")
     ap.add_argument("--cpu-budget", type=float, default=20.0)
+    ap.add_argument("--lightcone", action="store_true",
+                    help="trajectories: keep only the light cone of qubit 0 (the paper's pop) and run each "
+                         "trajectory on the cone's qubits")
     ap.add_argument("--plan", action="store_true",
                     help="print the fused plan's tile passes (blocks, union, HBM layout) and exit; no GPU needed")
     args = ap.parse_args()
@@ -404,15 +407,17 @@ def bench_trajectories(args):
     trajs = wc.trajectory_batch()
     # tile passes of the trajectories with >= 14 qubits, by --precision (default split BF16)
     prec = {"fp32": sv.PREC_FP32, "bf16": sv.PREC_SPLIT_BF16, "fp16": sv.PREC_SPLIT_FP16}[args.precision]
-    b = sv.Batch([(t.n, [(g.name, g.qubits, g.params) for g in t.gates]) for t in trajs], max_k=-1,
-                 precision=prec)
+    circuits = [(t.n, [(g.name, g.qubits, g.params) for g in t.gates]) for t in trajs]
+    if args.lightcone:
+        circuits = [lightcone_circuit(n_, gs) for n_, gs in circuits]
+    b = sv.Batch(circuits, max_k=-1, precision=prec)
     out = {}
 
     def step():
         out["z"] = b.run(use_graph=True)
 
     t = _timed_steps(args, step)
-    amps = sum(1 << t_.n for t_ in trajs)
+    amps = sum(1 << n_ for n_, _ in circuits)
     print(json.dumps({"metric": "noisy trajectories/s (512 trajectories, 10..22 qubits)",
                       "value": round(len(trajs) / t, 2), "unit": "trajectories/s", "n_gpus": 1,
                       "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t, 3),
@@ -421,9 +426,22 @@ def bench_trajectories(args):
                                 "fp16": "f32; f16 hi+lo split tile passes (n >= 14)"}[args.precision],
                       "data": "synthetic",
                       "config": {"workload": "512 ladder random circuits, n~U{10..22}, depth~U{8..24}, "
-                                             "2q depolarizing p=1e-3 sampled per trajectory",
-                                 "gates": sum(len(t_.gates) for t_ in trajs), "amplitudes": amps},
+                                             "2q depolarizing p=1e-3 sampled per trajectory"
+                                             + ("; light cone of qubit 0 only" if args.lightcone else ""),
+                                 "gates": sum(len(gs) for _, gs in circuits), "amplitudes": amps},
                       "mean_z0": float(np.mean(out["z"]))}), flush=True)
+
+
+def lightcone_circuit(n, gates, pinned=0):
+    """The gates in the light cone of qubit `pinned` (sv.lightcone), moved onto
+    the cone's qubits only (ascending; the pinned qubit 0 stays position 0).
+    Every <O> on the pinned qubit is unchanged: a dropped gate, or a qubit no
+    kept gate touches, cannot reach it."""
+    import paper_2111_06868_amd as sv
+    keep = sv.lightcone(gates, n, (pinned,))
+    used = sorted({pinned} | {q for i in keep for q in gates[i][1]})
+    pos = {q: j for j, q in enumerate(used)}
+    return len(used), [(gates[i][0], tuple(pos[q] for q in gates[i][1])) + tuple(gates[i][2:]) for i in keep]
 
 
 def bench_density(args):

@@ -435,6 +435,28 @@ int sv_set_tile_shape(int tile_bits, int waves);
  * sv_run_circuit calls in the process.  SV_ERR_ARG outside 8..10. */
 int sv_set_tile_union(int max_positions);
 
+/* ------------------------------------------------------- circuit utilities */
+/* Host-only cuts applied before fusion (paper, Circuits section, Circuit
+ * utilities: pop and simplify).  Both write the indices of the gates to keep,
+ * ascending, into keep (room for G entries) and their count into n_keep; the
+ * kept gates are applied in the original order.
+ *
+ * sv_lightcone (pop from the end): walking backwards, a gate touching the
+ * light cone of the `pinned` qubits (bit p = position p) is kept and adds its
+ * qubits to the cone; others are dropped.  Exact for expectations <O> of any
+ * observable O on the pinned qubits (the dropped gates commute with O and
+ * with every later kept gate).  Errors: SV_ERR_ARG, SV_ERR_QUBIT.
+ *
+ * sv_simplify: drops gates equal to the identity and pairs (a, b), b after a
+ * on the same qubits with b a = I, when every kept gate between them commutes
+ * with a: through disjoint qubits, or, if use_matrix_commutation != 0, through
+ * commuting matrices (tested on unions of at most 10 qubits); repeated until
+ * nothing changes.  Entries compare with absolute tolerance 1e-12.  The kept
+ * gates have the same product as the circuit.  Errors: SV_ERR_ARG,
+ * SV_ERR_QUBIT. */
+int sv_lightcone(const sv_gate *g, int G, int n, uint64_t pinned, int32_t *keep, int *n_keep);
+int sv_simplify(const sv_gate *g, int G, int n, int use_matrix_commutation, int32_t *keep, int *n_keep);
+
 /* ---------------------------------------------------------------- stats */
 /* Per-kernel device timing.  While enabled every kernel launch is bracketed
  * by HIP events on its stream; sv_stats_query synchronises the recorded

@@ -25,6 +25,7 @@ from ._native import (C64, C128, PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16, PR
                       SvValueError)
 
 __all__ = ["State", "Plan", "fuse", "gate_matrix", "backward", "Energy", "Batch", "positions",
+           "DensityMatrix", "SuperOp", "depolarizing", "dephasing", "amplitude_damping", "lightcone", "simplify",
            "pauli_sum", "autotune", "set_cost_table", "set_tile_shape", "set_tile_union", "TILE_SHAPES",
            "stats_enable", "stats_reset", "stats_query",
            "C64", "C128", "PREC_FP32", "PREC_SPLIT_BF16", "PREC_SPLIT_FP16", "PREC_FP64",
@@ -105,6 +106,31 @@ def gate_matrix(g) -> np.ndarray:
     out = np.zeros((1 << k) * (1 << k) * 2, dtype=np.float64)
     N.check(N.lib().sv_gate_matrix(ga.ptr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out.view(np.complex128).reshape(1 << k, 1 << k)
+
+
+def lightcone(gates, n: int, pinned) -> List[int]:
+    """Indices of the gates inside the light cone of the pinned qubits, walking
+    from the end (the paper's pop; exact for observables on the pinned qubits)."""
+    ga = gates if isinstance(gates, GateArray) else GateArray(gates)
+    mask = 0
+    for q in pinned:
+        mask |= 1 << int(q)
+    keep = np.zeros(max(ga.n, 1), dtype=np.int32)
+    cnt = ctypes.c_int()
+    N.check(N.lib().sv_lightcone(ga.ptr, ga.n, int(n), mask, keep.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 ctypes.byref(cnt)))
+    return [int(x) for x in keep[:cnt.value]]
+
+
+def simplify(gates, n: int, use_matrix_commutation: bool = True) -> List[int]:
+    """Indices of the gates left after cancelling inverse pairs (the paper's
+    simplify)."""
+    ga = gates if isinstance(gates, GateArray) else GateArray(gates)
+    keep = np.zeros(max(ga.n, 1), dtype=np.int32)
+    cnt = ctypes.c_int()
+    N.check(N.lib().sv_simplify(ga.ptr, ga.n, int(n), int(bool(use_matrix_commutation)),
+                                keep.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(cnt)))
+    return [int(x) for x in keep[:cnt.value]]
 
 
 # ------------------------------------------------------------------ Pauli sums

@@ -131,6 +131,8 @@ SIGNATURES = {
     "sv_set_cost_table": (_I, [_I, _I, _D]),
     "sv_set_tile_shape": (_I, [_I, _I]),
     "sv_set_tile_union": (_I, [_I]),
+    "sv_lightcone": (_I, [_GP, _I, _I, _U64, _I32P, ctypes.POINTER(_I)]),
+    "sv_simplify": (_I, [_GP, _I, _I, _I, _I32P, ctypes.POINTER(_I)]),
     "sv_stats_enable": (_I, [_I]),
     "sv_stats_reset": (_I, []),
     "sv_stats_query": (_I, [_I, _I64P, _D]),

@@ -1,0 +1,109 @@
+"""Host circuit utilities (paper, Circuit utilities: pop and simplify), checked
+against the oracle: light-cone cuts keep every expectation on the pinned
+qubits, simplification keeps the circuit's unitary (brute force), and the
+paper's CPHASE example cancels with its shuffled inverse only when matrix
+commutation is used."""
+import numpy as np
+import pytest
+
+import paper_2111_06868_amd as sv
+from oracle import brute, ref
+from workloads import circuits as wc
+from workloads.circuits import Gate
+from helpers import to_binding
+
+
+def _unitary(n, gates):
+    return brute.circuit_unitary(n, [(ref.matrix_of(g), g.qubits) for g in gates])
+
+
+def _inverse(gates):
+    out = []
+    for g in reversed(gates):
+        m = ref.matrix_of(g).conj().T
+        out.append(("MATRIX", g.qubits, (), -1, m))
+    return out
+
+
+def _to_oracle(bound):
+    """binding tuples -> (matrix, qubits) pairs for the oracle."""
+    ops = []
+    for t in bound:
+        if t[0] == "MATRIX":
+            ops.append((np.asarray(t[4]), tuple(t[1])))
+        else:
+            ops.append((ref.gate_matrix(t[0], t[2] if len(t) > 2 else ()), tuple(t[1])))
+    return ops
+
+
+@pytest.mark.parametrize("pinned", [(0,), (3,), (0, 5), (2, 4)])
+def test_lightcone_keeps_pinned_expectations(pinned):
+    n = 6
+    gates = wc.grid_rqc(2, 3, 3, seed=12)
+    keep = sv.lightcone(to_binding(gates), n, pinned)
+    assert len(keep) < len(gates)  # a shallow circuit has gates outside the cone
+    kept = [gates[i] for i in keep]
+    full = ref.simulate(n, gates, "0")
+    cut = ref.simulate(n, kept, "0")
+    for q in pinned:
+        for p in "XYZ":
+            t = [(1.0, ((q, p),))]
+            assert abs(ref.expectation(full, t) - ref.expectation(cut, t)) < 1e-12
+    if len(pinned) == 2:
+        t = [(1.0, ((pinned[0], "X"), (pinned[1], "Z")))]
+        assert abs(ref.expectation(full, t) - ref.expectation(cut, t)) < 1e-12
+    # every dropped gate lies outside the cone of all later kept gates
+    cone = 0
+    for q in pinned:
+        cone |= 1 << q
+    for i in range(len(gates) - 1, -1, -1):
+        m = sum(1 << q for q in gates[i].qubits)
+        assert (i in keep) == bool(m & cone)
+        if i in keep:
+            cone |= m
+
+
+def test_simplify_paper_cphase_example():
+    # CPHASE(1) on every pair of 5 qubits plus its inverse in shuffled order
+    n = 5
+    circ = [("CPHASE", (a, b), (1.0,)) for a in range(5) for b in range(a + 1, 5)]
+    perm = np.random.default_rng(0).permutation(len(circ))
+    inv = [("CPHASE", circ[i][1], (-1.0,)) for i in reversed(perm)]
+    total = circ + inv
+    assert sv.simplify(total, n, use_matrix_commutation=True) == []
+    assert len(sv.simplify(total, n, use_matrix_commutation=False)) > 0
+
+
+@pytest.mark.parametrize("use_m", [False, True])
+def test_simplify_keeps_the_unitary(use_m):
+    n = 4
+    rng = np.random.default_rng(3)
+    base = wc.grid_rqc(2, 2, 4, seed=6)
+    bound = to_binding(base)
+    # a circuit followed by its inverse cancels completely
+    assert sv.simplify(bound + _inverse(base), n, use_m) == []
+    # inverse pairs separated by gates on other qubits, plus identities
+    mixed = []
+    for g in bound:
+        mixed.append(g)
+        if rng.random() < 0.4:
+            q = int(rng.integers(n))
+            mixed.append(("RZ", (q,), (0.3,)))
+            other = [x for x in range(n) if x != q]
+            mixed.append(("H", (other[0],)))
+            mixed.append(("RZ", (q,), (-0.3,)))
+            mixed.append(("I", (other[1],)))
+    keep = sv.simplify(mixed, n, use_m)
+    assert len(keep) < len(mixed)
+    U_full = brute.circuit_unitary(n, _to_oracle(mixed))
+    U_cut = brute.circuit_unitary(n, _to_oracle([mixed[i] for i in keep]))
+    assert np.abs(U_full - U_cut).max() < 1e-12
+
+
+def test_utilities_refuse_bad_input():
+    with pytest.raises(sv.SvError):
+        sv.lightcone([("H", (3,))], 2, (0,))
+    with pytest.raises(sv.SvError):
+        sv.lightcone([("H", (0,))], 2, (5,))
+    with pytest.raises(sv.SvError):
+        sv.simplify([("CX", (1, 1))], 2)
