@@ -11,6 +11,14 @@ from workloads import circuits as wc
 pytestmark = pytest.mark.gpu
 
 
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    yield
+    torch.cuda.synchronize()
+
+
 def test_lightcone_trajectories_keep_z0():
     trajs = wc.trajectory_batch(count=48, root_seed=11)
     full = [(t.n, [(g.name, g.qubits, g.params) for g in t.gates]) for t in trajs]
