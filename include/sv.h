@@ -435,6 +435,35 @@ int sv_set_tile_shape(int tile_bits, int waves);
  * sv_run_circuit calls in the process.  SV_ERR_ARG outside 8..10. */
 int sv_set_tile_union(int max_positions);
 
+/* ----------------------------------- projections, measurement and control */
+/* Non-unitary and controlled operations (paper, Gates and Properties section:
+ * Projection(state, qubits), Measure(qubits), Control(c_qubits, gate); the
+ * Grover Oracle section builds its oracle as psi - 2 P psi with P the
+ * projection on |0..0>).
+ *
+ * sv_project: psi -> P psi with P = |bits><bits| on the k (1..SV_MAX_K) qubits
+ * q (q[0] the most significant bit of bits); *prob (may be NULL) receives
+ * ||P psi||^2 (FP64); renormalize != 0 then divides by sqrt(prob)
+ * (SV_ERR_ARG if prob is 0).  Synchronises.
+ *
+ * sv_measure: measures the k qubits q one after another, qubit q[j] with the
+ * caller's uniform uniforms[j] in [0, 1) by the rule of
+ * sv_apply_kraus_sampled on {|0><0|, |1><1|} (outcome 0 when u < p_0 / (p_0 +
+ * p_1)); the state collapses and is renormalised.  *bits (q[0] most
+ * significant) and *prob (the probability of the outcome) may be NULL.
+ * Synchronises.
+ *
+ * sv_controlled_gate (host): the gate g controlled by the n_c qubits controls
+ * (acting when all are 1), as a MATRIX gate on (controls..., g's qubits) with
+ * the controls as the most significant local bits, n_c + g->k <= SV_MAX_K.
+ * m_out (2 * 4^(n_c + k) doubles) receives its matrix, which out->m points
+ * to; the caller keeps it alive while the gate is used.
+ *
+ * Errors: SV_ERR_ARG, SV_ERR_QUBIT. */
+int sv_project(sv_state *s, int k, const int32_t *q, uint64_t bits, int renormalize, double *prob);
+int sv_measure(sv_state *s, int k, const int32_t *q, const double *uniforms, uint64_t *bits, double *prob);
+int sv_controlled_gate(const sv_gate *g, int n_c, const int32_t *controls, sv_gate *out, double *m_out);
+
 /* ------------------------------------------------------- circuit utilities */
 /* Host-only cuts applied before fusion (paper, Circuits section, Circuit
  * utilities: pop and simplify).  Both write the indices of the gates to keep,

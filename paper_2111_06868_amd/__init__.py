@@ -26,6 +26,7 @@ from ._native import (C64, C128, PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16, PR
 
 __all__ = ["State", "Plan", "fuse", "gate_matrix", "backward", "Energy", "Batch", "positions",
            "DensityMatrix", "SuperOp", "depolarizing", "dephasing", "amplitude_damping", "lightcone", "simplify",
+           "controlled",
            "pauli_sum", "autotune", "set_cost_table", "set_tile_shape", "set_tile_union", "TILE_SHAPES",
            "stats_enable", "stats_reset", "stats_query",
            "C64", "C128", "PREC_FP32", "PREC_SPLIT_BF16", "PREC_SPLIT_FP16", "PREC_FP64",
@@ -106,6 +107,19 @@ def gate_matrix(g) -> np.ndarray:
     out = np.zeros((1 << k) * (1 << k) * 2, dtype=np.float64)
     N.check(N.lib().sv_gate_matrix(ga.ptr, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out.view(np.complex128).reshape(1 << k, 1 << k)
+
+
+def controlled(gate, controls):
+    """The gate controlled by the control qubits (acting when all are 1), as a
+    MATRIX gate tuple on (controls..., gate qubits) (sv_controlled_gate)."""
+    ga = GateArray([gate])
+    c = np.ascontiguousarray([int(x) for x in controls], dtype=np.int32)
+    k = c.size + ga.arr[0].k
+    m = np.zeros(2 * (1 << k) * (1 << k), dtype=np.float64)
+    out = N.sv_gate()
+    N.check(N.lib().sv_controlled_gate(ga.ptr, c.size, c.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                       ctypes.byref(out), m.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return ("MATRIX", tuple(int(out.q[j]) for j in range(k)), (), -1, m.view(np.complex128).reshape(1 << k, 1 << k))
 
 
 def lightcone(gates, n: int, pinned) -> List[int]:
@@ -276,6 +290,31 @@ class State:
         out = ctypes.c_double()
         N.check(N.lib().sv_expectation(self.h, H.ptr, ctypes.byref(out)))
         return out.value
+
+    # -- projections and measurement
+    def project(self, qubits, bits: str, renormalize: bool = True) -> float:
+        """psi -> |bits><bits| psi on the qubits (bits[0] on qubits[0]);
+        returns ||P psi||^2 (sv_project)."""
+        q = np.ascontiguousarray([int(x) for x in qubits], dtype=np.int32)
+        if len(bits) != q.size or set(bits) - {"0", "1"}:
+            raise ValueError("bits must be a 0/1 string with one character per qubit")
+        p = ctypes.c_double()
+        N.check(N.lib().sv_project(self.h, q.size, q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(bits, 2),
+                                   int(bool(renormalize)), ctypes.byref(p)))
+        return p.value
+
+    def measure(self, qubits, uniforms):
+        """Measure the qubits one after another with the given uniforms;
+        returns (bit string, probability of the outcome) (sv_measure)."""
+        q = np.ascontiguousarray([int(x) for x in qubits], dtype=np.int32)
+        u = np.ascontiguousarray(uniforms, dtype=np.float64)
+        if u.size != q.size:
+            raise ValueError("one uniform per measured qubit")
+        bits, p = ctypes.c_uint64(), ctypes.c_double()
+        N.check(N.lib().sv_measure(self.h, q.size, q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   u.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(bits),
+                                   ctypes.byref(p)))
+        return format(bits.value, "0%db" % q.size), p.value
 
     # -- Kraus channels sampled on the state
     def kraus_probabilities(self, op: "SuperOp") -> np.ndarray:

@@ -131,6 +131,9 @@ SIGNATURES = {
     "sv_set_cost_table": (_I, [_I, _I, _D]),
     "sv_set_tile_shape": (_I, [_I, _I]),
     "sv_set_tile_union": (_I, [_I]),
+    "sv_project": (_I, [_P, _I, _I32P, _U64, _I, _D]),
+    "sv_measure": (_I, [_P, _I, _I32P, _D, ctypes.POINTER(_U64), _D]),
+    "sv_controlled_gate": (_I, [_GP, _I, _I32P, _GP, _D]),
     "sv_lightcone": (_I, [_GP, _I, _I, _U64, _I32P, ctypes.POINTER(_I)]),
     "sv_simplify": (_I, [_GP, _I, _I, _I, _I32P, ctypes.POINTER(_I)]),
     "sv_stats_enable": (_I, [_I]),

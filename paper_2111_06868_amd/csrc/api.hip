@@ -875,6 +875,111 @@ extern "C" int sv_run_trajectory(sv_state *s, const sv_gate *g, int G, const sv_
     return SV_OK;
 }
 
+// ============================================================== projections, measurement, control
+extern "C" int sv_project(sv_state *s, int k, const int32_t *q, uint64_t bits, int renormalize, double *prob)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    if (k < 1 || k > SV_MAX_K || !q) return fail(SV_ERR_ARG, "projection on %d qubits (1..%d)", k, SV_MAX_K);
+    if (bits >> k) return fail(SV_ERR_ARG, "bits 0x%llx exceed %d qubits", (unsigned long long)bits, k);
+    sv_gate h{};
+    h.kind = SV_G_MATRIX;
+    h.k = k;
+    h.param = -1;
+    for (int j = 0; j < k; ++j) h.q[j] = q[j];
+    if (int rc = check_gate_qubits(h, s->n)) return rc;
+    // |bits><bits| on q (q[0] the most significant bit of bits)
+    const size_t D = size_t(1) << k;
+    std::vector<double> m(2 * D * D, 0.0);
+    m[2 * (bits * D + bits)] = 1.0;
+    h.m = m.data();
+    if (int rc = select_device(s)) return rc;
+    if (int rc = apply_gate_impl(s, &h)) return rc;
+    double p = 0.0;
+    if (int rc = sv_norm(s, &p)) return rc;
+    if (renormalize) {
+        if (!(p > 0.0)) return fail(SV_ERR_ARG, "the projection has probability 0; cannot renormalise");
+        const double c = 1.0 / std::sqrt(p);
+        const double sc[8] = {c, 0, 0, 0, 0, 0, c, 0};  // c I on q[0]
+        sv_gate t{};
+        t.kind = SV_G_MATRIX;
+        t.k = 1;
+        t.q[0] = q[0];
+        t.param = -1;
+        t.m = sc;
+        if (int rc = apply_gate_impl(s, &t)) return rc;
+    }
+    if (prob) *prob = p;
+    return SV_OK;
+}
+
+extern "C" int sv_measure(sv_state *s, int k, const int32_t *q, const double *uniforms, uint64_t *bits,
+                          double *prob)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    if (k < 1 || k > s->n || !q || !uniforms) return fail(SV_ERR_ARG, "measurement of %d qubits", k);
+    for (int j = 0; j < k; ++j) {
+        if (q[j] < 0 || q[j] >= s->n) return fail(SV_ERR_QUBIT, "qubit %d outside 0..%d", q[j], s->n - 1);
+        for (int i = 0; i < j; ++i)
+            if (q[i] == q[j]) return fail(SV_ERR_QUBIT, "qubit %d repeated", q[j]);
+        if (!(uniforms[j] >= 0.0 && uniforms[j] < 1.0))
+            return fail(SV_ERR_ARG, "uniform %d = %g outside [0, 1)", j, uniforms[j]);
+    }
+    // qubit by qubit: the Kraus set {|0><0|, |1><1|} sampled with uniforms[j]
+    static const double proj[16] = {1, 0, 0, 0, 0, 0, 0, 0,   // |0><0|
+                                    0, 0, 0, 0, 0, 0, 1, 0};  // |1><1|
+    uint64_t out = 0;
+    double ptot = 1.0;
+    for (int j = 0; j < k; ++j) {
+        sv_super_op op{};
+        op.after = 0;
+        op.k = 1;
+        op.q[0] = q[j];
+        op.n_left = op.n_right = 2;
+        op.left = op.right = proj;
+        int32_t b = 0;
+        double pb = 0.0;
+        if (int rc = sample_kraus(s, op, uniforms[j], &b, &pb)) return rc;
+        out = (out << 1) | uint64_t(b);
+        ptot *= pb;
+    }
+    if (bits) *bits = out;
+    if (prob) *prob = ptot;
+    return SV_OK;
+}
+
+extern "C" int sv_controlled_gate(const sv_gate *g, int n_c, const int32_t *controls, sv_gate *out, double *m_out)
+{
+    clear_error();
+    if (!g || !out || !m_out || (n_c > 0 && !controls)) return fail(SV_ERR_ARG, "NULL argument");
+    if (int rc = check_gate_shape(*g)) return rc;
+    if (n_c < 1 || n_c + g->k > SV_MAX_K)
+        return fail(SV_ERR_ARG, "%d controls on a %d-qubit gate (at most %d qubits in all)", n_c, g->k, SV_MAX_K);
+    sv_gate h{};
+    h.kind = SV_G_MATRIX;
+    h.k = n_c + g->k;
+    h.param = -1;
+    for (int j = 0; j < n_c; ++j) h.q[j] = controls[j];
+    for (int j = 0; j < g->k; ++j) h.q[n_c + j] = g->q[j];
+    if (int rc = check_gate_qubits(h, 64)) return rc;
+    std::vector<cd> U;
+    if (int rc = gate_matrix_abi(*g, U)) return rc;
+    // identity, except the block where every control (the most significant
+    // local bits) is 1, which holds U
+    const size_t D = size_t(1) << h.k, d = size_t(1) << g->k, off = D - d;
+    std::fill(m_out, m_out + 2 * D * D, 0.0);
+    for (size_t i = 0; i < off; ++i) m_out[2 * (i * D + i)] = 1.0;
+    for (size_t r = 0; r < d; ++r)
+        for (size_t c = 0; c < d; ++c) {
+            m_out[2 * ((off + r) * D + off + c)] = U[r * d + c].real();
+            m_out[2 * ((off + r) * D + off + c) + 1] = U[r * d + c].imag();
+        }
+    h.m = m_out;
+    *out = h;
+    return SV_OK;
+}
+
 extern "C" int sv_apply_pauli_sum(sv_state *psi, const sv_pauli_sum *H, sv_state *out)
 {
     clear_error();
