@@ -59,7 +59,10 @@ extern "C" {
 /* arithmetic used to apply fused blocks (sv_run_opts.precision) */
 #define SV_PREC_FP32 0       /* complex64 state; FP32 matvec / FP32 MFMA           */
 #define SV_PREC_SPLIT_BF16 1 /* complex64 state; k>=4 blocks as hi+lo BF16 MFMA    */
-#define SV_PREC_SPLIT_FP16 2 /* complex64 state; k>=4 blocks as hi+lo FP16 MFMA    */
+#define SV_PREC_SPLIT_FP16 2 /* complex64 state; k>=4 blocks as hi+lo FP16 MFMA;   */
+                             /* MATRIX gates must be unitary (to 1e-6), else       */
+                             /* SV_ERR_ARG: tile passes rely on norm-preserving    */
+                             /* blocks                                             */
 #define SV_PREC_FP64 3       /* complex128 state; FP64 arithmetic throughout       */
 
 /* fusion rules (sv_fuse) */

@@ -535,6 +535,11 @@ extern "C" int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int u
     for (const auto &b : p->blocks)
         for (int j = 0; j < b.k; ++j)
             if (b.q[j] >= s->n) return fail(SV_ERR_QUBIT, "plan position %d outside a %d-qubit state", b.q[j], s->n);
+    if (precision == SV_PREC_SPLIT_FP16)
+        for (size_t i = 0; i < p->blocks.size(); ++i) {
+            std::string what = "plan block " + std::to_string(i);
+            if (int rc = check_unitary(p->blocks[i].m, p->blocks[i].k, what.c_str())) return rc;
+        }
     std::vector<Launch> L;
     blocks_to_launches(p->blocks, s, precision, p->rule, L);
     if (int rc = select_device(s)) return rc;
@@ -555,6 +560,8 @@ int run_circuit_impl(sv_state *s, const sv_gate *g, int G, const sv_run_opts *o)
     if (!o) o = &d;
     if (int rc = check_precision(s, o->precision)) return rc;
     if (int rc = validate_gates(g, G, s->n)) return rc;
+    if (o->precision == SV_PREC_SPLIT_FP16)
+        if (int rc = check_fp16_gates(g, G)) return rc;
     int max_k = o->max_k, rule = o->rule;
     if (rule < SV_RULE_PAPER || rule > SV_RULE_AUTO) return fail(SV_ERR_ARG, "unknown fusion rule %d", rule);
     if (max_k != -1 && (max_k < 1 || max_k > SV_MAX_K))

@@ -271,6 +271,7 @@ int check_desc(const sv_batch_desc *d)
         for (int64_t g = d->gate_offsets[t]; g < d->gate_offsets[t + 1]; ++g) {
             int rc = check_gate_shape(d->gates[g]);
             if (!rc) rc = check_gate_qubits(d->gates[g], n);
+            if (!rc && d->precision == SV_PREC_SPLIT_FP16) rc = check_fp16_gates(d->gates + g, 1);
             if (rc) return rc;
         }
     }

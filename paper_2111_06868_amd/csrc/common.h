@@ -29,6 +29,10 @@ int gate_matrix_abi(const sv_gate &g, std::vector<cd> &out);
 // Gate matrix and positions in CANONICAL order: positions sorted ascending,
 // local bit j <-> j-th lowest position.
 int gate_matrix_canonical(const sv_gate &g, std::vector<cd> &m, int *sorted_q);
+// Split FP16 needs norm-preserving blocks: U^dagger U = I to 1e-6 per entry
+// (check_unitary), for every MATRIX gate of a list (check_fp16_gates).
+int check_unitary(const std::vector<cd> &U, int k, const char *what);
+int check_fp16_gates(const sv_gate *g, int G);
 // Convert between the ABI order of a block whose positions q[0..k-1] are
 // already ascending (q[0] most significant) and the canonical order (q[0]
 // least significant): a bit reversal of the local index, an involution.

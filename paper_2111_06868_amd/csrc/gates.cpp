@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstring>
 
+#include <string>
+
 #include "common.h"
 
 namespace sv {
@@ -179,6 +181,35 @@ void reverse_local_bits(const std::vector<cd> &in, int k, std::vector<cd> &out)
     out.assign(size_t(D) * D, cd(0));
     for (int a = 0; a < D; ++a)
         for (int b = 0; b < D; ++b) out[size_t(rev(a)) * D + rev(b)] = in[size_t(a) * D + b];
+}
+
+// Split-FP16 tile passes hold each tile scaled so that its largest value is
+// below 2^8 and rely on blocks that cannot raise the tile's 2-norm; a unitary
+// (checked to 1e-6 per entry of U^dagger U) cannot.
+int check_unitary(const std::vector<cd> &U, int k, const char *what)
+{
+    const size_t d = size_t(1) << k;
+    for (size_t i = 0; i < d; ++i)
+        for (size_t j = 0; j < d; ++j) {
+            cd acc = 0;
+            for (size_t r = 0; r < d; ++r) acc += std::conj(U[r * d + i]) * U[r * d + j];
+            if (std::abs(acc - cd(i == j ? 1.0 : 0.0)) > 1e-6)
+                return fail(SV_ERR_ARG, "%s is not unitary (|U^dagger U - I| > 1e-6); split FP16 needs unitary gates",
+                            what);
+        }
+    return SV_OK;
+}
+
+int check_fp16_gates(const sv_gate *g, int G)
+{
+    for (int i = 0; i < G; ++i) {
+        if (g[i].kind != SV_G_MATRIX) continue;  // the named gates are unitary
+        std::vector<cd> U;
+        if (int rc = gate_matrix_abi(g[i], U)) return rc;
+        std::string what = "matrix gate " + std::to_string(i);
+        if (int rc = check_unitary(U, g[i].k, what.c_str())) return rc;
+    }
+    return SV_OK;
 }
 
 }  // namespace sv

@@ -98,3 +98,18 @@ def test_grover_oracle_as_a_diagonal_gate_matches_the_paper():
     # the same with sv_project: the projection on 00 has probability 1/4
     st2 = sv.State(3, "c128").set_product("+")
     assert abs(st2.project((1, 0), "00", renormalize=False) - 0.25) < 1e-15
+
+
+def test_split_fp16_refuses_non_unitary_matrices():
+    A = np.array([[1.0, 0.5], [0.0, 1.0]])  # not unitary: it can raise the norm
+    U = wc.haar_unitary_from_seed(9, 1)
+    st = sv.State(14, "c64")
+    with pytest.raises(sv.SvError):
+        st.run([("MATRIX", (3,), (), -1, A)], max_k=4, precision=sv.PREC_SPLIT_FP16, rule=sv.RULE_TILED)
+    st.run([("MATRIX", (3,), (), -1, U)], max_k=4, precision=sv.PREC_SPLIT_FP16, rule=sv.RULE_TILED)
+    plan = sv.fuse([("MATRIX", (3,), (), -1, A), ("H", (4,))], 14, 4, sv.RULE_TILED)
+    with pytest.raises(sv.SvError):
+        st.apply_plan(plan, precision=sv.PREC_SPLIT_FP16)
+    st.apply_plan(plan, precision=sv.PREC_SPLIT_BF16)  # split BF16 keeps FP32's range
+    with pytest.raises(sv.SvError):
+        sv.Batch([(14, [("MATRIX", (0,), (), -1, A)])], max_k=4, precision=sv.PREC_SPLIT_FP16)
