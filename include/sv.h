@@ -447,7 +447,8 @@ int sv_set_tile_union(int max_positions);
  * sv_project: psi -> P psi with P = |bits><bits| on the k (1..SV_MAX_K) qubits
  * q (q[0] the most significant bit of bits); *prob (may be NULL) receives
  * ||P psi||^2 (FP64); renormalize != 0 then divides by sqrt(prob)
- * (SV_ERR_ARG if prob is 0).  Synchronises.
+ * (SV_ERR_ARG if prob is 0, the state then being left at P psi = 0).
+ * Synchronises.
  *
  * sv_measure: measures the k qubits q one after another, qubit q[j] with the
  * caller's uniform uniforms[j] in [0, 1) by the rule of

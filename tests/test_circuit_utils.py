@@ -107,3 +107,12 @@ def test_utilities_refuse_bad_input():
         sv.lightcone([("H", (0,))], 2, (5,))
     with pytest.raises(sv.SvError):
         sv.simplify([("CX", (1, 1))], 2)
+
+
+def test_utilities_edge_cases():
+    gates = to_binding(wc.grid_rqc(2, 2, 3, seed=1))
+    assert sv.lightcone([], 3, (0,)) == []
+    assert sv.simplify([], 3) == []
+    assert sv.lightcone(gates, 4, (0, 1, 2, 3)) == list(range(len(gates)))
+    assert sv.lightcone(gates, 4, ()) == []
+    assert sv.simplify([("I", (0,)), ("X", (1,)), ("X", (1,))], 2) == []

@@ -224,3 +224,28 @@ def test_jump_trajectory_mean_matches_density_matrix():
     mean, se = float(np.mean(z)), float(np.std(z) / math.sqrt(len(z)))
     print("[parity] exact <Z0> %.6f, jump-trajectory mean %.6f +- %.6f" % (exact, mean, se), flush=True)
     assert abs(mean - exact) <= 5 * se + 1e-6
+
+
+def test_density_and_sampling_edge_cases():
+    # one-qubit rho: operators only (no gates), one before the first gate
+    rho = sv.DensityMatrix(1, "c128").run([], [sv.amplitude_damping(0, 0.5, after=0)])
+    assert np.abs(rho.read() - np.diag([1.0, 0.0])).max() < 1e-15
+    rho = sv.DensityMatrix(1, "c128")
+    rho.run([("X", (0,))], [sv.dephasing(0, 0.3, after=0), sv.amplitude_damping(0, 0.25, after=1)])
+    assert np.abs(rho.read() - np.diag([0.25, 0.75])).max() < 1e-15
+    assert abs(rho.trace() - 1.0) < 1e-15
+    # |index><index|
+    assert abs(sv.DensityMatrix(3, "c128").set_basis(5).expectation([(1.0, ((0, "Z"),))]) + 1.0) < 1e-15
+    # a trajectory without operators is the plain run
+    gates = to_binding(wc.grid_rqc(2, 3, 4, seed=2))
+    a = sv.State(6, "c128").run(gates, max_k=4, rule=sv.RULE_ENHANCED).read()
+    st = sv.State(6, "c128")
+    assert len(st.run_trajectory(gates, [], [], max_k=4, rule=sv.RULE_ENHANCED)) == 0
+    assert np.abs(st.read() - a).max() < 1e-15
+    # measuring every qubit of a basis state is deterministic, whatever the draws
+    st = sv.State(5, "c64").set_basis(0b10110)
+    bits, p = st.measure([4, 3, 2, 1, 0], [0.99, 0.01, 0.5, 0.99, 0.01])
+    assert bits == "10110" and abs(p - 1.0) < 1e-12
+    # a projection with probability 0 cannot be renormalised
+    with pytest.raises(sv.SvError):
+        sv.State(2, "c64").project((0,), "1", renormalize=True)
