@@ -9,4 +9,7 @@ Modules:
             metrics, Pauli expectations, parameter-shift / finite-difference
             gradients, the paper's greedy fusion rule, trajectories.
   brute  -- the full 2^n x 2^n unitary built from Kronecker products (n <= 8).
+  density -- density matrices: gates, Kraus / matrix super operators, the
+            noise channels, Tr(rho H), and channels sampled on pure states.
+  ops    -- projections, measurements and controlled gates.
 """

@@ -1,7 +1,7 @@
 """Oracle: plain complex128 density-matrix evolution -- TEST INFRASTRUCTURE ONLY.
 
-Only tests, the smoke check and the benchmark's CPU-baseline leg use this
-module; the product path never does.  It shares no code with the HIP library.
+Only tests use this module; the product path never does.  It shares no code
+with the HIP library.
 
 What it computes (paper, Gates and Properties section: KrausSuperGate
 rho -> sum_ij s_ij L_i rho R_j^dagger and MatrixSuperGate, a matrix acting on
