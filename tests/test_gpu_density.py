@@ -249,3 +249,40 @@ def test_density_and_sampling_edge_cases():
     # a projection with probability 0 cannot be renormalised
     with pytest.raises(sv.SvError):
         sv.State(2, "c64").project((0,), "1", renormalize=True)
+
+
+def test_dm_many_tiles_vs_oracle():
+    # 9 qubits: rho is an 18-qubit state, 16 tiles of 2^14 per tile pass
+    n, gates, lib_ops, or_ops = _noisy_case(3, 3, 4, seed=31)
+    want = dm.simulate(n, gates, or_ops)
+    sv.stats_reset()
+    sv.stats_enable(True)
+    rho = sv.DensityMatrix(n, "c64").run(to_binding(gates), lib_ops, max_k=4, precision=sv.PREC_SPLIT_BF16,
+                                         rule=sv.RULE_TILED)
+    got = rho.read()
+    sv.stats_enable(False)
+    tiles = sum(sv.stats_query("tile_bf16", k)[0] for k in range(1, 17))
+    assert tiles > 0
+    _check("dm n=%d tiled bf16, 16 tiles (%d launches)" % (n, tiles), want, got, TOL[sv.PREC_SPLIT_BF16])
+
+
+@pytest.mark.parametrize("prec", [sv.PREC_FP32, sv.PREC_SPLIT_BF16])
+def test_trajectory_with_tile_passes_vs_oracle(prec):
+    # 16 qubits: the gate runs between channels go through tile passes
+    n = 16
+    gates, lib_ops, or_ops = _jump_case(n, seed=21, count=6)
+    u = np.random.default_rng(8).random(len(lib_ops))
+    u[1::2] = 0.95 + 0.04 * u[1::2]
+    st = sv.State(n, "c64")
+    sv.stats_reset()
+    sv.stats_enable(True)
+    got = st.run_trajectory(to_binding(gates), lib_ops, u, max_k=4, precision=prec, rule=sv.RULE_TILED)
+    psi = st.read().astype(np.complex128)
+    sv.stats_enable(False)
+    fam = "tile" if prec == sv.PREC_FP32 else "tile_bf16"
+    assert sum(sv.stats_query(fam, k)[0] for k in range(1, 17)) > 0, "no tile pass ran"
+    want_psi, want = dm.trajectory(n, gates, or_ops, u)
+    assert [int(x) for x in got] == list(want) and any(x > 0 for x in want)
+    fe = 1 - abs(np.vdot(want_psi, psi)) ** 2 / (np.vdot(psi, psi).real * np.vdot(want_psi, want_psi).real)
+    print("[parity] tiled trajectory n=%d prec=%d outcomes %s 1-F %.3e" % (n, prec, list(want), fe), flush=True)
+    assert fe <= 1e-5
