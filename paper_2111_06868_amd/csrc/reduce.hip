@@ -235,6 +235,81 @@ __global__ void __launch_bounds__(kRedThreads) k_kraus_probs(const T *__restrict
     block_reduce_store<kMaxKraus>(acc, partials + size_t(blockIdx.x) * kMaxKraus);
 }
 
+// The same for complex64 states with 16-byte loads: when the channel's lowest
+// position is 0 (LOW0), amplitudes m and m + 1 of a group are adjacent; else
+// the groups 2h and 2h + 1 differ only in position 0, so amplitude m of both is
+// one float4.  Each thread takes U units (groups, or pairs of groups) per step.
+template <int K, bool LOW0>
+__global__ void __launch_bounds__(kRedThreads) k_kraus_probs_c64(const float4 *__restrict__ psi, int n,
+                                                                const KrausDev Kd, double *partials)
+{
+    constexpr int D = 1 << K;
+    constexpr int G = LOW0 ? 1 : 2;                // groups per unit
+    constexpr int L = LOW0 ? D / 2 : D;            // float4 loads per unit
+    constexpr int U = K == 3 ? (LOW0 ? 2 : 1) : 4;
+    Acc<kMaxKraus> acc;
+#pragma unroll
+    for (int i = 0; i < kMaxKraus; ++i) acc.v[i] = 0.0;
+    const uint64_t units = uint64_t(1) << (n - K - (LOW0 ? 0 : 1));
+    const uint64_t stride = uint64_t(kRedBlocks) * kRedThreads;
+    for (uint64_t h0 = uint64_t(blockIdx.x) * kRedThreads + threadIdx.x; h0 < units; h0 += U * stride) {
+        float4 v[U][L];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint64_t h = h0 + u * stride;
+            uint64_t base = h < units ? (LOW0 ? h : h << 1) : 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const uint64_t low = base & ((uint64_t(1) << Kd.pos[j]) - 1);
+                base = ((base - low) << 1) | low;
+            }
+#pragma unroll
+            for (int l = 0; l < L; ++l) {
+                const int m = LOW0 ? 2 * l : l;
+                uint64_t idx = base;
+#pragma unroll
+                for (int j = 0; j < K; ++j)
+                    if ((m >> j) & 1) idx |= uint64_t(1) << Kd.pos[j];
+                v[u][l] = psi[idx >> 1];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (h0 + u * stride >= units) continue;
+#pragma unroll
+            for (int gsel = 0; gsel < G; ++gsel) {
+                double xr[D], xi[D];
+#pragma unroll
+                for (int m = 0; m < D; ++m) {
+                    const float4 w = LOW0 ? v[u][m >> 1] : v[u][m];
+                    const bool hi = LOW0 ? (m & 1) : gsel;
+                    xr[m] = hi ? w.z : w.x;
+                    xi[m] = hi ? w.w : w.y;
+                }
+#pragma unroll
+                for (int i = 0; i < kMaxKraus; ++i) {
+                    if (i >= Kd.n_ops) continue;  // uniform
+                    const double *M = Kd.m + size_t(2) * D * D * i;
+                    double s = 0.0;
+#pragma unroll
+                    for (int r = 0; r < D; ++r) {
+                        double yr = 0.0, yi = 0.0;
+#pragma unroll
+                        for (int c = 0; c < D; ++c) {
+                            const double mr = M[2 * (r * D + c)], mi = M[2 * (r * D + c) + 1];
+                            yr = fma(mr, xr[c], fma(-mi, xi[c], yr));
+                            yi = fma(mr, xi[c], fma(mi, xr[c], yi));
+                        }
+                        s = fma(yr, yr, fma(yi, yi, s));
+                    }
+                    acc.v[i] += s;
+                }
+            }
+        }
+    }
+    block_reduce_store<kMaxKraus>(acc, partials + size_t(blockIdx.x) * kMaxKraus);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_pauli_apply(const T *__restrict__ psi, T *__restrict__ out, uint64_t N,
                                                     const PauliDev H)
@@ -335,6 +410,27 @@ hipError_t launch_kraus_probs(int dtype, const void *psi, int n, const KrausDev 
     const bool c64 = dtype == SV_C64;
     const float *pf = static_cast<const float *>(psi);
     const double *pd = static_cast<const double *>(psi);
+    // complex64 with 16-byte loads (needs a pair of groups when position 0 is free)
+    if (c64 && (K.pos[0] == 0 || n - K.k >= 1)) {
+        const float4 *p4 = static_cast<const float4 *>(psi);
+        const bool low0 = K.pos[0] == 0;
+        switch (K.k) {
+        case 1:
+            if (low0) hipLaunchKernelGGL((k_kraus_probs_c64<1, true>), g, t, 0, st, p4, n, K, d_partials);
+            else hipLaunchKernelGGL((k_kraus_probs_c64<1, false>), g, t, 0, st, p4, n, K, d_partials);
+            break;
+        case 2:
+            if (low0) hipLaunchKernelGGL((k_kraus_probs_c64<2, true>), g, t, 0, st, p4, n, K, d_partials);
+            else hipLaunchKernelGGL((k_kraus_probs_c64<2, false>), g, t, 0, st, p4, n, K, d_partials);
+            break;
+        default:
+            if (low0) hipLaunchKernelGGL((k_kraus_probs_c64<3, true>), g, t, 0, st, p4, n, K, d_partials);
+            else hipLaunchKernelGGL((k_kraus_probs_c64<3, false>), g, t, 0, st, p4, n, K, d_partials);
+            break;
+        }
+        hipLaunchKernelGGL(k_final<kMaxKraus>, dim3(1), dim3(kRedThreads), 0, st, d_partials, kRedBlocks, d_out);
+        return hipGetLastError();
+    }
     switch (K.k) {
     case 1:
         if (c64) hipLaunchKernelGGL((k_kraus_probs<float, 1>), g, t, 0, st, pf, n, K, d_partials);

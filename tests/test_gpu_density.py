@@ -157,7 +157,8 @@ def _random_state(n, dtype, seed):
 
 
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
-@pytest.mark.parametrize("qs,m", [((0,), 2), ((11,), 4), ((3, 9), 3), ((10, 2, 6), 5), ((1, 0, 11), 16)])
+@pytest.mark.parametrize("qs,m", [((0,), 2), ((11,), 4), ((3, 9), 3), ((5, 0), 4), ((10, 2, 6), 5),
+                                  ((1, 0, 11), 16)])
 def test_kraus_probabilities_vs_oracle(dtype, qs, m):
     n = 12
     psi, st = _random_state(n, dtype, seed=len(qs) * 10 + m)
