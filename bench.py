@@ -184,7 +184,7 @@ def main():
     t_total = time.perf_counter() - t0
     ms_step = 1e3 * t_total / args.steps
     # kernel durations: K more steps with a HIP event pair around every launch
-    # on the library's stream (the events themselves cost about 3 % of a step)
+    # on the library's stream, kept out of the throughput run
     sv.stats_reset()
     sv.stats_enable(True)
     torch.cuda.synchronize()
