@@ -155,3 +155,25 @@ def test_branches_of_sampled_channels_sum_to_the_density_matrix():
     acc = np.zeros_like(rho)
     walk(ref.product_state(n, "0"), 0, 0, 1.0, acc)
     assert np.abs(acc - rho).max() < 1e-13
+
+
+def test_trajectory_follows_the_drawn_branch():
+    # dm.trajectory with given draws equals the branch built step by step from
+    # kraus_probabilities and sample_kraus at the same places in the circuit
+    n = 3
+    gates = wc.grid_rqc(1, 3, 3, seed=4)
+    ops = [dm.amplitude_damping(0, 0.35, after=3),
+           {"qubits": (2, 1), "left": wc.random_kraus_from_seed(8, 2, 3), "after": 6},
+           dm.dephasing(1, 0.2, "X", after=len(gates))]
+    u = [0.9, 0.5, 0.1]
+    psi, outcomes = dm.trajectory(n, gates, ops, u)
+    want = ref.product_state(n, "0")
+    start = 0
+    for j, op in enumerate(ops):
+        for g in gates[start:op["after"]]:
+            ref.apply(want, ref.matrix_of(g), g.qubits)
+        start = op["after"]
+        want, pick = dm.sample_kraus(want, op["left"], op["qubits"], u[j])
+        assert pick == outcomes[j]
+    assert np.abs(psi - want).max() < 1e-14
+    assert outcomes[0] == 1  # u = 0.9 jumps: the |1> weight after the first gates exceeds 0.1
