@@ -231,12 +231,22 @@ def norm2(psi: np.ndarray) -> float:
 
 
 def fidelity_error(ref: np.ndarray, psi: np.ndarray) -> float:
-    """1 - |<ref|psi>|^2 / (||ref||^2 ||psi||^2)."""
+    """1 - |<ref|psi>|^2 / (||ref||^2 ||psi||^2): blind to a global phase and
+    to the norms of both states."""
     ov = inner(ref, psi.astype(np.complex128))
     return 1.0 - abs(ov) ** 2 / (norm2(ref) * norm2(psi.astype(np.complex128)))
 
 
+def fidelity_error_raw(ref: np.ndarray, psi: np.ndarray) -> float:
+    """|1 - |<ref|psi>|^2 / ||ref||^2| with psi NOT renormalised: the reference
+    (an exact evolution of a unit state) is taken as the unit vector, so a norm
+    error of psi shows up here while fidelity_error hides it."""
+    ov = inner(ref, psi.astype(np.complex128))
+    return abs(1.0 - abs(ov) ** 2 / norm2(ref))
+
+
 def max_abs(ref: np.ndarray, psi: np.ndarray) -> float:
+    """max_i |ref_i - psi_i| (complex modulus, no phase alignment)."""
     return float(np.max(np.abs(ref - psi.astype(np.complex128))))
 
 

@@ -307,7 +307,53 @@ def check_trajectories():
     assert abs(ref.z0(ref.basis_state(5, 1)) + 1) < 1e-15
 
 
+
+def check_metrics():
+    """The parity metrics against values fixed by mathematics.
+    * RY(t)|0> = cos(t/2)|0> + sin(t/2)|1>, so against |0> the fidelity is
+      cos^2(t/2) and 1-F = sin^2(t/2); on n qubits, |+>^n against |0..0> has
+      fidelity 2^-n.
+    * 1-F is blind to a global phase and to the scale of either state; the raw
+      error |1 - |<ref|psi>|^2| of a scaled unit state c psi is |1 - c^2|.
+    * Orthogonal states have 1-F = 1.
+    * max-abs is the largest complex modulus of the difference."""
+    zero = ref.basis_state(1, 0)
+    for t in (0.0, 0.3, 1.1, math.pi / 2, 2.5, math.pi):
+        psi = zero.copy()
+        ref.apply(psi, ref.gate_matrix("RY", (t,)), (0,))
+        want = math.sin(t / 2) ** 2
+        assert abs(ref.fidelity_error(zero, psi) - want) < 1e-15, (t, ref.fidelity_error(zero, psi), want)
+        assert abs(ref.fidelity_error(psi, zero) - want) < 1e-15
+        assert abs(ref.fidelity_error_raw(zero, psi) - want) < 1e-15
+        # a scaled copy: the normalised error is unchanged, the raw one is not
+        assert abs(ref.fidelity_error(zero, 3.0 * psi) - want) < 1e-14
+        assert abs(ref.fidelity_error(0.25 * zero, psi) - want) < 1e-14
+    for n in range(1, 7):
+        plus = ref.product_state(n, "+")
+        z = ref.basis_state(n, 0)
+        assert abs(ref.fidelity_error(z, plus) - (1 - 2.0 ** -n)) < 1e-15, n
+    rng = np.random.default_rng(13)
+    v = rng.normal(size=64) + 1j * rng.normal(size=64)
+    v /= np.linalg.norm(v)
+    for c, phi in ((1.0, 0.7), (0.5, -2.0), (1.0 + 1e-4, 3.0)):
+        w = c * np.exp(1j * phi) * v
+        assert abs(ref.fidelity_error(v, w)) < 1e-14, (c, phi)
+        assert abs(ref.fidelity_error_raw(v, w) - abs(1 - c * c)) < 1e-13, (c, phi)
+    # orthogonal states
+    a = ref.product_state(3, "+")
+    b = ref.product_state(3, "+-+")
+    assert abs(ref.fidelity_error(a, b) - 1.0) < 1e-15
+    assert abs(ref.fidelity_error_raw(a, b) - 1.0) < 1e-15
+    # max-abs on hand-built vectors: moduli of complex differences
+    r = np.array([1.0, 0.0, 0.5j, -0.25], dtype=complex)
+    p = np.array([1.0, 3e-3 + 4e-3j, 0.5j, -0.25 + 1e-3], dtype=complex)
+    assert abs(ref.max_abs(r, p) - 5e-3) < 1e-17
+    assert abs(ref.max_abs(r, p.astype(np.complex64)) - 5e-3) < 1e-9
+    assert ref.max_abs(r, r) == 0.0
+    assert abs(ref.max_abs(r, -r) - 2.0) < 1e-16
+
 ALL_CHECKS = [
+    check_metrics,
     check_grover_worked_example,
     check_compress_worked_example,
     check_apply_vs_brute,

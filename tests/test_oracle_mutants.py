@@ -148,6 +148,34 @@ def mut_param_shift_wrong_shift(mp):
     mp.setattr(ref, "param_shift_grad", ps)
 
 
+
+def mut_fidelity_unsquared_overlap(mp):
+    """|<ref|psi>| used where its square belongs (halves every small 1-F)."""
+    def fe(r, psi):
+        ov = ref.inner(r, psi.astype(np.complex128))
+        return 1.0 - abs(ov) / math.sqrt(ref.norm2(r) * ref.norm2(psi.astype(np.complex128)))
+    mp.setattr(ref, "fidelity_error", fe)
+
+
+def mut_fidelity_unnormalised(mp):
+    """The norms of the two states left out of 1-F."""
+    def fe(r, psi):
+        return 1.0 - abs(ref.inner(r, psi.astype(np.complex128))) ** 2
+    mp.setattr(ref, "fidelity_error", fe)
+
+
+def mut_fidelity_raw_renormalised(mp):
+    """The raw error divided by ||psi||^2 as well (hides norm drift)."""
+    def fe(r, psi):
+        ov = ref.inner(r, psi.astype(np.complex128))
+        return abs(1.0 - abs(ov) ** 2 / (ref.norm2(r) * ref.norm2(psi.astype(np.complex128))))
+    mp.setattr(ref, "fidelity_error_raw", fe)
+
+
+def mut_max_abs_real_part(mp):
+    """Only real parts compared."""
+    mp.setattr(ref, "max_abs", lambda r, psi: float(np.max(np.abs((r - psi.astype(np.complex128)).real))))
+
 MUTANTS = [
     mut_local_bit_order, mut_transposed_matrix, mut_position_mirror,
     mut_conjugated_gates, mut_fsim_sign, mut_rotation_full_angle,
@@ -155,6 +183,8 @@ MUTANTS = [
     mut_expectation_dropped_term, mut_expectation_imag,
     mut_fusion_append_current, mut_fusion_first_intersecting,
     mut_param_shift_wrong_shift,
+    mut_fidelity_unsquared_overlap, mut_fidelity_unnormalised,
+    mut_fidelity_raw_renormalised, mut_max_abs_real_part,
 ]
 
 
