@@ -152,11 +152,26 @@ def dephasing(qubit: int, p: float, pauli: str = "Z", after: int = 0) -> dict:
     return {"qubits": (qubit,), "left": [np.sqrt(1 - p) * PAULI["I"], np.sqrt(p) * PAULI[pauli]], "after": after}
 
 
-def amplitude_damping(qubit: int, gamma: float, after: int = 0) -> dict:
-    """Kraus operators |0><0| + sqrt(1 - gamma)|1><1| and sqrt(gamma)|0><1|."""
-    K0 = np.array([[1, 0], [0, np.sqrt(1 - gamma)]], dtype=np.complex128)
+def amplitude_damping(qubit: int, gamma: float, excitation: float = 0.0, after: int = 0) -> dict:
+    """Kraus operators sqrt(1 - excitation)|0><0| + sqrt(1 - gamma)|1><1| and
+    sqrt(gamma)|0><1|, plus sqrt(excitation)|1><0| for a nonzero excitation
+    rate (the generalized channel: |1> -> |0> with probability gamma, |0> ->
+    |1> with probability excitation).  excitation = 0 is the paper's pair."""
+    K0 = np.array([[np.sqrt(1 - excitation), 0], [0, np.sqrt(1 - gamma)]], dtype=np.complex128)
     K1 = np.array([[0, np.sqrt(gamma)], [0, 0]], dtype=np.complex128)
-    return {"qubits": (qubit,), "left": [K0, K1], "after": after}
+    ops = [K0, K1]
+    if excitation > 0:
+        ops.append(np.array([[0, 0], [np.sqrt(excitation), 0]], dtype=np.complex128))
+    return {"qubits": (qubit,), "left": ops, "after": after}
+
+
+def pauli_channel(qubits, s, after: int = 0) -> dict:
+    """GlobalPauliChannel rho -> sum_ij s_ij sigma_i rho sigma_j over the 4^k
+    Pauli strings; string i has base-4 digits (first digit on qubits[0]) 0..3
+    = I, X, Y, Z.  A KrausSuperGate with left = right = the strings."""
+    k = len(qubits)
+    strings = [pauli_string("".join(t)) for t in itertools.product("IXYZ", repeat=k)]
+    return {"qubits": tuple(qubits), "left": strings, "s": np.asarray(s, dtype=np.complex128), "after": after}
 
 
 # -------------------------------------------------------------- sampling on pure states

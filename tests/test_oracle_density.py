@@ -177,3 +177,59 @@ def test_trajectory_follows_the_drawn_branch():
         assert pick == outcomes[j]
     assert np.abs(psi - want).max() < 1e-14
     assert outcomes[0] == 1  # u = 0.9 jumps: the |1> weight after the first gates exceeds 0.1
+
+
+def test_generalized_amplitude_damping_closed_forms():
+    # populations: |0> -> diag(1 - b, b), |1> -> diag(g, 1 - g); coherences
+    # shrink by sqrt((1 - b)(1 - g)); repeated application relaxes to the
+    # population b / (b + g) of |1>
+    g, b = 0.3, 0.12
+    op = dm.amplitude_damping(0, g, b)
+    assert np.abs(dm.apply_op(dm.zero(1), op) - np.diag([1 - b, b])).max() < 1e-15
+    assert np.abs(dm.apply_op(np.diag([0, 1]).astype(complex), op) - np.diag([g, 1 - g])).max() < 1e-15
+    plus = np.full((2, 2), 0.5, dtype=complex)
+    out = dm.apply_op(plus, op)
+    assert abs(out[0, 1] - 0.5 * math.sqrt((1 - b) * (1 - g))) < 1e-15
+    assert abs(out[1, 0] - 0.5 * math.sqrt((1 - b) * (1 - g))) < 1e-15
+    rho = plus
+    for _ in range(300):
+        rho = dm.apply_op(rho, op)
+    assert abs(rho[1, 1].real - b / (b + g)) < 1e-13 and abs(rho[0, 1]) < 1e-13
+    # excitation 0: the paper's two operators
+    assert len(dm.amplitude_damping(0, g)["left"]) == 2
+
+
+def test_pauli_channel_closed_forms():
+    import scipy.linalg as sl
+    # rank one, s = v v^dagger with v = cos a e_I - i sin a e_P: rho -> K rho K^dagger,
+    # K = exp(-i a P) (P a Pauli string, P^2 = I)
+    a = 0.37
+    for qubits, label in (((0,), "Z"), ((1, 0), "XY"), ((0, 2, 1), "ZIX")):
+        k = len(qubits)
+        idx = sum("IXYZ".index(c) * 4 ** (k - 1 - j) for j, c in enumerate(label))
+        v = np.zeros(4 ** k, dtype=complex)
+        v[0], v[idx] = math.cos(a), -1j * math.sin(a)
+        rho = _rand_rho(3, 21)
+        out = dm.apply_op(rho, dm.pauli_channel(qubits, np.outer(v, v.conj())))
+        P = dm.pauli_string(label)
+        K = sl.expm(-1j * a * P)
+        want = dm.apply_kraus_super(rho, [K], [K], None, qubits)
+        assert np.abs(out - want).max() < 1e-14
+    # rank one on a single qubit against the rotation of the gate table:
+    # exp(-i a Z) = RZ(2a)
+    rho = _rand_rho(1, 22)
+    v = np.array([math.cos(a), 0, 0, -1j * math.sin(a)])
+    out = dm.apply_op(rho, dm.pauli_channel((0,), np.outer(v, v.conj())))
+    assert np.abs(out - dm.apply_gate(rho, ref.gate_matrix("RZ", (2 * a,)), (0,))).max() < 1e-15
+    # diagonal s: Z dephasing, off-diagonals times (1 - 2p)
+    p = 0.15
+    out = dm.apply_op(rho, dm.pauli_channel((0,), np.diag([1 - p, 0, 0, p])))
+    assert np.abs(out - np.array([[rho[0, 0], (1 - 2 * p) * rho[0, 1]],
+                                  [(1 - 2 * p) * rho[1, 0], rho[1, 1]]])).max() < 1e-15
+    # the depolarizing weights as a diagonal s give the depolarizing channel
+    d2 = 16
+    w = np.full(d2, 0.2 / d2)
+    w[0] += 0.8
+    r2 = _rand_rho(2, 23)
+    assert np.abs(dm.apply_op(r2, dm.pauli_channel((0, 1), np.diag(w)))
+                  - ((1 - 0.2) * r2 + 0.2 * np.eye(4) / 4)).max() < 1e-15

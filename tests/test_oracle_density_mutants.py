@@ -15,6 +15,7 @@ _apply_kraus = dm.apply_kraus_super
 _apply_matrix = dm.apply_matrix_super
 _depol = dm.depolarizing
 _damp = dm.amplitude_damping
+_pauli_ch = dm.pauli_channel
 _sample = dm.sample_kraus
 _project = ops.project
 _measure = ops.measure
@@ -31,6 +32,8 @@ PINS = [
     D.test_sampled_amplitude_damping_closed_form,
     D.test_branches_of_sampled_channels_sum_to_the_density_matrix,
     D.test_trajectory_follows_the_drawn_branch,
+    D.test_generalized_amplitude_damping_closed_forms,
+    D.test_pauli_channel_closed_forms,
     O.test_grover_oracle_by_projection_matches_the_paper,
     O.test_controlled_gates_are_the_textbook_ones,
     O.test_measure_ghz_collapses,
@@ -85,11 +88,41 @@ def mut_depolarizing_weight(mp):
 
 
 def mut_damping_transposed(mp):
-    def f(qubit, gamma, after=0):
-        op = _damp(qubit, gamma, after)
-        op["left"] = [op["left"][0], op["left"][1].T.copy()]
+    def f(qubit, gamma, excitation=0.0, after=0):
+        op = _damp(qubit, gamma, excitation, after)
+        op["left"] = [op["left"][0], op["left"][1].T.copy()] + op["left"][2:]
         return op
     mp.setattr(dm, "amplitude_damping", f)
+
+
+def mut_excitation_keeps_k0(mp):
+    """The excitation operator added without shrinking |0><0| in K0."""
+    def f(qubit, gamma, excitation=0.0, after=0):
+        op = _damp(qubit, gamma, excitation, after)
+        op["left"][0] = np.diag([1.0, np.sqrt(1 - gamma)]).astype(complex)
+        return op
+    mp.setattr(dm, "amplitude_damping", f)
+
+
+def mut_excitation_swapped_rates(mp):
+    """The excitation rate on the decay operator and the decay rate on the excitation one."""
+    def f(qubit, gamma, excitation=0.0, after=0):
+        op = _damp(qubit, gamma, excitation, after)
+        if excitation > 0:
+            op["left"][1], op["left"][2] = (np.sqrt(excitation / gamma) * op["left"][1],
+                                            np.sqrt(gamma / excitation) * op["left"][2])
+        return op
+    mp.setattr(dm, "amplitude_damping", f)
+
+
+def mut_pauli_channel_transposed_s(mp):
+    """s_ji in place of s_ij."""
+    mp.setattr(dm, "pauli_channel", lambda qubits, s, after=0: _pauli_ch(qubits, np.asarray(s).T, after))
+
+
+def mut_pauli_channel_reversed_digits(mp):
+    """The first base-4 digit on the last qubit."""
+    mp.setattr(dm, "pauli_channel", lambda qubits, s, after=0: _pauli_ch(tuple(qubits)[::-1], s, after))
 
 
 def mut_sample_last_outcome(mp):
@@ -134,7 +167,9 @@ def mut_controlled_top_block(mp):
 
 
 MUTANTS = [mut_right_transpose, mut_kraus_ignores_s, mut_kraus_right_not_adjoint, mut_matrix_super_column_major,
-           mut_depolarizing_weight, mut_damping_transposed, mut_sample_last_outcome, mut_sample_unnormalised,
+           mut_depolarizing_weight, mut_damping_transposed, mut_excitation_keeps_k0, mut_excitation_swapped_rates,
+           mut_pauli_channel_transposed_s, mut_pauli_channel_reversed_digits, mut_sample_last_outcome,
+           mut_sample_unnormalised,
            mut_project_bits_reversed, mut_measure_rule_inverted, mut_controlled_top_block]
 
 
