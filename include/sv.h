@@ -264,6 +264,21 @@ int sv_inner(sv_state *a, sv_state *b, double *re, double *im);
 /* <psi|H|psi> for a Pauli sum H, FP64 accumulation.  Synchronises.
  * SV_ERR_ARG if a mask has bits at or above n or too many terms. */
 int sv_expectation(sv_state *s, const sv_pauli_sum *H, double *out);
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the value of
+ * sv_expectation for the n-qubit state of amplitude type dtype (SV_C64 or
+ * SV_C128) held in dev_psi (device memory of the current device, 2^n
+ * amplitudes, 256-byte aligned, owned by the caller), computed on hip_stream
+ * (NULL = default stream) by the same kernels.  The call allocates nothing:
+ * the term tables and reduction partials live in a fixed 192 KiB array that
+ * each GPU holds until the process ends; every call on a GPU reuses it, so
+ * calls that overlap on one GPU (from several host threads or streams) race
+ * and the library serialises them.  Synchronises.  Errors: SV_ERR_ARG (NULL,
+ * bad n, dtype or alignment, malformed sum), SV_ERR_QUBIT (a mask at or above
+ * bit n), SV_ERR_SIZE (tables larger than the array; cannot happen within
+ * SV_MAX_PAULI_TERMS terms), SV_ERR_HIP. */
+int sv_expectation_noalloc(const void *dev_psi, int n, int dtype, void *hip_stream, const sv_pauli_sum *H,
+                           double *out);
 /* psi <- H psi for a Pauli sum H (into `out`, a second state of the same n
  * and type; psi is unchanged).  Asynchronous. */
 int sv_apply_pauli_sum(sv_state *psi, const sv_pauli_sum *H, sv_state *out);

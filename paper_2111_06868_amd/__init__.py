@@ -25,7 +25,7 @@ from ._native import (C64, C128, PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16, PR
                       SvValueError)
 
 __all__ = ["State", "Plan", "fuse", "gate_matrix", "backward", "Energy", "Batch", "positions",
-           "DensityMatrix", "SuperOp", "depolarizing", "dephasing", "amplitude_damping", "lightcone", "simplify",
+           "DensityMatrix", "SuperOp", "depolarizing", "dephasing", "amplitude_damping", "lightcone", "simplify", "expectation_noalloc",
            "controlled",
            "pauli_sum", "autotune", "set_cost_table", "set_tile_shape", "set_tile_union", "TILE_SHAPES",
            "stats_enable", "stats_reset", "stats_query",
@@ -182,6 +182,23 @@ class PauliSum:
 
 def pauli_sum(terms) -> PauliSum:
     return PauliSum(terms)
+
+
+def expectation_noalloc(tensor, n: int, terms, stream=None) -> float:
+    """<psi|H|psi> of the n-qubit state held in a device tensor (complex64 as
+    float32 pairs, complex128 as float64 pairs) without any device allocation
+    (sv_expectation_noalloc): term tables and partials live in the library's
+    fixed per-device array."""
+    torch = _torch()
+    dt = {torch.float32: C64, torch.float64: C128}.get(tensor.dtype)
+    if dt is None or tensor.numel() < (2 << int(n)) or not tensor.is_contiguous():
+        raise ValueError("expected a contiguous float32/float64 tensor of at least 2^(n+1) elements")
+    H = terms if isinstance(terms, PauliSum) else PauliSum(terms)
+    st = stream if stream is not None else torch.cuda.current_stream(tensor.device)
+    out = ctypes.c_double()
+    N.check(N.lib().sv_expectation_noalloc(ctypes.c_void_p(tensor.data_ptr()), int(n), dt,
+                                           ctypes.c_void_p(st.cuda_stream), H.ptr, ctypes.byref(out)))
+    return out.value
 
 
 # ------------------------------------------------------------------ states

@@ -113,6 +113,7 @@ SIGNATURES = {
     "sv_norm": (_I, [_P, _D]),
     "sv_inner": (_I, [_P, _P, _D, _D]),
     "sv_expectation": (_I, [_P, _PS, _D]),
+    "sv_expectation_noalloc": (_I, [_P, _I, _I, _P, _PS, _D]),
     "sv_apply_pauli_sum": (_I, [_P, _PS, _P]),
     "sv_backward": (_I, [_P, _P, _GP, _I, _PS, _D, _I]),
     "sv_super_op_matrix": (_I, [ctypes.POINTER(sv_super_op), _D]),

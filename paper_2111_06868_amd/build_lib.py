@@ -15,7 +15,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["gates.cpp", "fuse.cpp", "density.cpp", "circuit_utils.cpp", "runtime.hip", "api.hip", "apply.hip", "mfma.hip",
-           "reduce.hip", "backward.hip", "batch.hip", "tune.hip", "tile.hip"]
+           "reduce.hip", "backward.hip", "batch.hip", "tune.hip", "tile.hip", "noalloc.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-I", os.path.join(ROOT, "include")]

@@ -616,6 +616,24 @@ int read_result(sv_state *s, const double *d_src, size_t count, double *out)
     return SV_OK;
 }
 
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Group terms by x mask, stage the tables and upload them into the arena.
+// The caller synchronised arena_free and records it after its launches.
+int pauli_tables(sv_state *s, const sv_pauli_sum *H, dev::PauliDev &P)
+{
+    const size_t total = pauli_table_bytes(H);
+    SV_HIP(s->stage.ensure(total));
+    SV_HIP(s->arena.ensure(total));
+    pauli_table_fill(H, static_cast<char *>(s->stage.p), static_cast<const char *>(s->arena.p), P);
+    SV_HIP(hipMemcpyAsync(s->arena.p, s->stage.p, total, hipMemcpyHostToDevice, s->stream));
+    return SV_OK;
+}
+
+}  // namespace
+
+namespace sv {
+
 int check_pauli(const sv_pauli_sum *H, int n)
 {
     if (!H) return fail(SV_ERR_ARG, "NULL Pauli sum");
@@ -631,11 +649,35 @@ int check_pauli(const sv_pauli_sum *H, int n)
     return SV_OK;
 }
 
-size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+namespace {
 
-// Group terms by x mask, stage the tables and upload them into the arena.
-// The caller synchronised arena_free and records it after its launches.
-int pauli_tables(sv_state *s, const sv_pauli_sum *H, dev::PauliDev &P)
+// Byte offsets of the device tables of a Pauli sum with ng x-mask groups and
+// nt terms: group masks, group offsets, term z masks, coefficients, i-powers.
+struct PauliLayout {
+    size_t gx, goff, tz, tc, tp, total;
+    PauliLayout(int ng, int nt)
+    {
+        gx = 0;
+        goff = al256(gx + 8 * std::max(ng, 1));
+        tz = al256(goff + 4 * (ng + 1));
+        tc = al256(tz + 8 * std::max(nt, 1));
+        tp = al256(tc + 8 * std::max(nt, 1));
+        total = al256(tp + 4 * std::max(nt, 1));
+    }
+};
+
+int count_x_groups(const sv_pauli_sum *H)
+{
+    std::vector<uint64_t> x(H->xmask, H->xmask + H->n_terms);
+    std::sort(x.begin(), x.end());
+    return int(std::unique(x.begin(), x.end()) - x.begin());
+}
+
+}  // namespace
+
+size_t pauli_table_bytes(const sv_pauli_sum *H) { return PauliLayout(count_x_groups(H), H->n_terms).total; }
+
+void pauli_table_fill(const sv_pauli_sum *H, char *h, const char *d, dev::PauliDev &P)
 {
     const int nt = H->n_terms;
     std::vector<int> order(nt);
@@ -651,32 +693,24 @@ int pauli_tables(sv_state *s, const sv_pauli_sum *H, dev::PauliDev &P)
     }
     goff.push_back(nt);
     const int ng = int(gx.size());
-    const size_t o_gx = 0, o_goff = al256(o_gx + 8 * std::max(ng, 1)), o_tz = al256(o_goff + 4 * (ng + 1)),
-                 o_tc = al256(o_tz + 8 * std::max(nt, 1)), o_tp = al256(o_tc + 8 * std::max(nt, 1)),
-                 total = al256(o_tp + 4 * std::max(nt, 1));
-    SV_HIP(s->stage.ensure(total));
-    SV_HIP(s->arena.ensure(total));
-    char *h = static_cast<char *>(s->stage.p);
-    std::memcpy(h + o_gx, gx.data(), 8 * ng);
-    std::memcpy(h + o_goff, goff.data(), 4 * (ng + 1));
+    const PauliLayout L(ng, nt);
+    std::memcpy(h + L.gx, gx.data(), 8 * ng);
+    std::memcpy(h + L.goff, goff.data(), 4 * (ng + 1));
     for (int i = 0; i < nt; ++i) {
         const int t = order[i];
-        reinterpret_cast<uint64_t *>(h + o_tz)[i] = H->zmask[t];
-        reinterpret_cast<double *>(h + o_tc)[i] = H->coef[t];
-        reinterpret_cast<int32_t *>(h + o_tp)[i] = __builtin_popcountll(H->xmask[t] & H->zmask[t]) & 3;
+        reinterpret_cast<uint64_t *>(h + L.tz)[i] = H->zmask[t];
+        reinterpret_cast<double *>(h + L.tc)[i] = H->coef[t];
+        reinterpret_cast<int32_t *>(h + L.tp)[i] = __builtin_popcountll(H->xmask[t] & H->zmask[t]) & 3;
     }
-    SV_HIP(hipMemcpyAsync(s->arena.p, s->stage.p, total, hipMemcpyHostToDevice, s->stream));
-    char *d = static_cast<char *>(s->arena.p);
     P.n_groups = ng;
-    P.gx = reinterpret_cast<const uint64_t *>(d + o_gx);
-    P.goff = reinterpret_cast<const int32_t *>(d + o_goff);
-    P.tz = reinterpret_cast<const uint64_t *>(d + o_tz);
-    P.tc = reinterpret_cast<const double *>(d + o_tc);
-    P.tpow = reinterpret_cast<const int32_t *>(d + o_tp);
-    return SV_OK;
+    P.gx = reinterpret_cast<const uint64_t *>(d + L.gx);
+    P.goff = reinterpret_cast<const int32_t *>(d + L.goff);
+    P.tz = reinterpret_cast<const uint64_t *>(d + L.tz);
+    P.tc = reinterpret_cast<const double *>(d + L.tc);
+    P.tpow = reinterpret_cast<const int32_t *>(d + L.tp);
 }
 
-}  // namespace
+}  // namespace sv
 
 extern "C" int sv_norm(sv_state *s, double *out)
 {

@@ -125,6 +125,14 @@ int enqueue(const std::vector<Launch> &launches, int dtype, void *psi, int n, co
 int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, const void *arena, hipStream_t st,
             void *psi2 = nullptr);
 
+// Pauli sums: validation (terms, masks below bit n, finite coefficients),
+// and the device tables (terms grouped by x mask) laid out in host memory h
+// for a copy to device address d: their byte size, and the fill, which also
+// points P at d.
+int check_pauli(const sv_pauli_sum *H, int n);
+size_t pauli_table_bytes(const sv_pauli_sum *H);
+void pauli_table_fill(const sv_pauli_sum *H, char *h, const char *d, dev::PauliDev &P);
+
 }  // namespace sv
 
 struct sv_state {
