@@ -65,6 +65,17 @@ def read_traffic(fam: int, k: int, n: int):
         return None
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (as lscpu prints it), from /proc/cpuinfo."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.lower().startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n, gates, budget_s=20.0):
     """The oracle (complex128, gate at a time, OpenMP over amplitude groups)
     on the full-size state for the circuit's first gates."""
@@ -85,6 +96,115 @@ def cpu_baseline(n, gates, budget_s=20.0):
     del psi
     return {"value": done / dt, "unit": "gates/s", "cores": threads, "kind": "oracle",
             "sample": "first %d of %d gates on the full %d-qubit complex128 state" % (done, len(ops), n)}
+
+
+def cpu_baseline_one_thread(config, budget_s):
+    """cpu_baseline in a child process limited to one OpenMP thread."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    code = ("import json, sys; sys.path.insert(0, %r); import bench; from workloads import circuits as wc; "
+            "n, g = wc.config_circuit(%d); print(json.dumps(bench.cpu_baseline(n, g, %r)))" % (ROOT, config, budget_s))
+    r = subprocess.run([sys.executable, "-c", code], env=env, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                       text=True, timeout=budget_s + 300)
+    if r.returncode != 0:
+        log("one-thread oracle failed: %s" % r.stderr[-500:])
+        return None
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def small_circuit_lines(steps=20):
+    """The 14-qubit grid circuit (225 gates, a 128 KiB state that a compute
+    unit's LDS could hold): microseconds per gate on the GPU, fused (tiled
+    rule, k <= 4, split BF16, as the headline) and per gate, and for the CPU
+    oracle (all threads)."""
+    import numpy as np
+    import torch
+    import paper_2111_06868_amd as sv
+    from oracle import ref
+    from workloads import circuits as wc
+    n, gates = wc.config_circuit(0)
+    ga = sv.GateArray([(g.name, g.qubits, g.params) for g in gates])
+    st = sv.State(n, "c64")
+    out = {}
+    for name, kw in (("fused", dict(max_k=4, rule=sv.RULE_TILED, precision=sv.PREC_SPLIT_BF16)),
+                     ("per_gate", dict(rule=sv.RULE_NONE))):
+        st.set_basis(0).run(ga, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            st.set_basis(0).run(ga, **kw)
+        torch.cuda.synchronize()
+        out["gpu_%s_us_per_gate" % name] = round(1e6 * (time.perf_counter() - t0) / steps / len(gates), 3)
+    want = ref.simulate(n, gates, "0")
+    out["gpu_fused_fidelity_err"] = ref.fidelity_error(want, st.set_basis(0).run(
+        ga, max_k=4, rule=sv.RULE_TILED, precision=sv.PREC_SPLIT_BF16).read())
+    t0 = time.perf_counter()
+    reps = 0
+    while reps < 3 or time.perf_counter() - t0 < 1.0:
+        ref.simulate(n, gates, "0")
+        reps += 1
+    out["cpu_oracle_us_per_gate"] = round(1e6 * (time.perf_counter() - t0) / reps / len(gates), 3)
+    out["workload"] = "grid random circuit 2x7 depth 12 seed 0, 14 qubits, 225 gates"
+    return out
+
+
+def plan_tiles(blocks, n, tile_bits=14, page_bits=18):
+    """The launches of a plan's tile passes and lone blocks: for each, the
+    blocks' qubits, the union of their positions and the HBM layout of one
+    tile (the union plus the lowest free positions, tile_bits in all: runs of
+    2^run contiguous amplitudes, spread over 2^pages pages of 2^page_bits
+    amplitudes)."""
+    groups = []
+    for b in blocks:
+        if b.tile_pass >= 0 and groups and groups[-1][0] == b.tile_pass:
+            groups[-1][1].append(b.qubits)
+        else:
+            groups.append((b.tile_pass, [b.qubits]))
+    out = []
+    for tp, qs in groups:
+        union = sorted(set(q for b in qs for q in b))
+        tile = set(union)
+        for p in range(n):
+            if len(tile) >= tile_bits:
+                break
+            tile.add(p)
+        run = 0
+        while run in tile:
+            run += 1
+        out.append({"tile_pass": tp, "blocks": qs, "union": union, "tile": sorted(tile), "run": run,
+                    "pages": sum(1 for p in tile if p >= page_bits)})
+    return out
+
+
+def copy_ceiling(st, tiles, max_blocks, reps=3):
+    """Streaming read + write passes (sv_stream_probe) over the state at the
+    layouts of the plan's tile-pass launches, and at whole 128 KiB runs and
+    the 128-byte runs of the top ten positions: the achievable time of a pass
+    with each layout."""
+    n = st.n
+    cache = {}
+
+    def probe(tile):
+        key = tuple(tile)
+        if key not in cache:
+            cache[key] = st.stream_probe(key, reps=reps)
+        return cache[key]
+
+    contiguous = probe(range(14))
+    top = probe(list(range(4)) + list(range(n - 10, n)))
+    launches = []
+    for t in tiles:
+        if t["tile_pass"] >= 0 or len(t["union"]) <= 4:
+            count = -(-len(t["blocks"]) // max_blocks)
+            launches += [probe(t["tile"])] * count
+    pass_bytes = 16.0 * (1 << n)
+    out = {"contiguous_ms": round(contiguous, 4), "contiguous_GBps": round(pass_bytes / contiguous / 1e6, 1),
+           "top10_128B_runs_ms": round(top, 4), "top10_128B_runs_GBps": round(pass_bytes / top / 1e6, 1)}
+    if launches:
+        mean = sum(launches) / len(launches)
+        out.update({"plan_layouts_ms_per_launch": round(mean, 4),
+                    "plan_layouts_GBps": round(pass_bytes / mean / 1e6, 1), "plan_launches": len(launches)})
+    return out
 
 
 def main():
@@ -225,18 +345,31 @@ def main():
     if dfam in TILE_FAMILIES:
         blocks_per_launch = tile_blocks[dfam] / dcnt
         roofline["blocks_per_launch"] = round(blocks_per_launch, 3)
-        # 8 * 16 flop per amplitude per 4-qubit block; split BF16 / FP16 run three products
-        flops = (3 if dfam in (10, 11) else 1) * 8.0 * 16 * (1 << n) * blocks_per_launch
+        # 8 * 16 flop per amplitude per 4-qubit block; split BF16 runs four products, FP16 three
+        flops = {10: 4, 11: 3}.get(dfam, 1) * 8.0 * 16 * (1 << n) * blocks_per_launch
         roofline["mfma_tflops"] = round(flops / (avg_ms * 1e-3) / 1e12, 2)
         if dfam == 9:
             roofline["mfma_frac"] = round(roofline["mfma_tflops"] / MFMA_FP32_PEAK_TFLOPS, 4)
     if dfam in (3, 4, 5):
-        flops = 8.0 * (1 << dk) * (1 << n) * (3 if dfam in (4, 5) else 1)
+        flops = 8.0 * (1 << dk) * (1 << n) * {4: 4, 5: 3}.get(dfam, 1)
         roofline["mfma_tflops"] = round(flops / (avg_ms * 1e-3) / 1e12, 2)
         if dfam == 3:
             roofline["mfma_frac"] = round(roofline["mfma_tflops"] / MFMA_FP32_PEAK_TFLOPS, 4)
     log("timed %.1f ms/step; dominant %s avg %.3f ms -> %.0f GB/s" % (ms_step, roofline["kernel"], avg_ms, achieved))
     fused_state = st
+
+    # the achievable copy at the same layouts (the state is left unchanged)
+    _, _, max_blocks = sv.get_tile_shape()
+    ceiling = copy_ceiling(st, plan_tiles(blocks, n) if rule == sv.RULE_TILED else [], max_blocks)
+    roofline["copy_ceiling"] = ceiling
+    if dfam in TILE_FAMILIES and "plan_layouts_GBps" in ceiling:
+        roofline["frac_of_copy_ceiling"] = round(achieved / ceiling["plan_layouts_GBps"], 4)
+    log("copy ceiling: %s" % ceiling)
+    # host planning (fusion and block matrices), which each step repeats before its launches
+    t1 = time.perf_counter()
+    for _ in range(5):
+        sv.fuse(ga, n, args.max_k, rule)
+    host_plan_ms = 1e3 * (time.perf_counter() - t1) / 5
 
     extra = {}
     pg = None
@@ -264,6 +397,8 @@ def main():
         first = 1 << 20
         a = refst.read(0, first)
         extra["fidelity_err_fused"] = fe_fused
+        # unnormalised: 1 - |<ref|psi>|^2 with ||ref|| = 1, which norm drift does not cancel
+        extra["fidelity_err_raw_fused"] = 1.0 - abs(refst.inner(fused_state)) ** 2
         extra["max_abs_first_2^20_fused"] = float(np.max(np.abs(fused_state.read(0, first) - a)))
         fe_pg = None
         if pg is not None:
@@ -294,6 +429,12 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cpu = cpu_baseline(n, gates, args.cpu_budget)
+        cpu["cpu_model"] = cpu_model()
+        one = cpu_baseline_one_thread(args.config, args.cpu_budget / 2)
+        if one is not None:
+            cpu["one_thread"] = {"value": one["value"], "unit": one["unit"], "sample": one["sample"]}
+        log("14-qubit circuit lines ...")
+        extra["small_circuit"] = small_circuit_lines()
 
     out = {
         "metric": "gates/s + effective HBM GB/s at 30q; fused vs per-gate at <=1e-5 fidelity err",
@@ -307,7 +448,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16 hi+lo split, f32 accumulate",
+        "dtype": {"fp32": "f32", "bf16": "bf16 split (3-part matrix, hi+lo state), f32 accumulate",
                   "fp16": "f16 hi+lo split, f32 accumulate"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "grid random circuit %s, %d qubits, %d gates, complex64, fused k<=%d (%s rule, %s)"
@@ -318,6 +459,7 @@ def main():
         "state_passes": state_passes,
         "effective_GBps": round(state_passes * pass_bytes / (ms_step * 1e-3) / 1e9, 1),
         "kernel_ms_per_step": round(kernel_ms_total, 3),
+        "host_fusion_ms_per_step": round(host_plan_ms, 3),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -338,31 +480,16 @@ def print_plan(args, tile_bits=14, page_bits=18):
     rule = {"enhanced": sv.RULE_ENHANCED, "paper": sv.RULE_PAPER, "tiled": sv.RULE_TILED,
             "auto": sv.RULE_AUTO}[args.rule]
     blocks = sv.fuse(ga, n, args.max_k, rule).blocks(False)
-    groups = []
-    for b in blocks:
-        if b.tile_pass >= 0 and groups and groups[-1][0] == b.tile_pass:
-            groups[-1][1].append(b.qubits)
-        else:
-            groups.append((b.tile_pass, [b.qubits]))
-    print("n=%d gates=%d blocks=%d passes=%d" % (n, len(gates), len(blocks), len(groups)))
-    for i, (tp, qs) in enumerate(groups):
-        union = sorted(set(q for b in qs for q in b))
-        if tp < 0 and len(union) > 4:
-            print("%3d dense k=%d on %s" % (i, len(union), union))
+    tiles = plan_tiles(blocks, n, tile_bits, page_bits)
+    print("n=%d gates=%d blocks=%d passes=%d" % (n, len(gates), len(blocks), len(tiles)))
+    for i, t in enumerate(tiles):
+        if t["tile_pass"] < 0 and len(t["union"]) > 4:
+            print("%3d dense k=%d on %s" % (i, len(t["union"]), t["union"]))
             continue
-        # a lone block of k <= 4 (tp < 0) may run as a one-block tile pass
-        tile = set(union)
-        for p in range(n):
-            if len(tile) >= tile_bits:
-                break
-            tile.add(p)
-        run = 0
-        while run in tile:
-            run += 1
-        pages = sum(1 for p in tile if p >= page_bits)
+        # a lone block of k <= 4 (tile_pass < 0) may run as a one-block tile pass
         print("%3d %s s=%d union=%s run=2^%d pages=2^%d blocks=%s"
-              % (i, "tile" if tp >= 0 else "single", len(qs), union, run, pages,
-                 " ".join(",".join(map(str, b)) for b in qs)))
+              % (i, "tile" if t["tile_pass"] >= 0 else "single", len(t["blocks"]), t["union"], t["run"],
+                 t["pages"], " ".join(",".join(map(str, b)) for b in t["blocks"])))
 
 
 def _timed_steps(args, step):
@@ -445,14 +572,12 @@ def bench_trajectories(args):
 
 def lightcone_circuit(n, gates, pinned=0):
     """The gates in the light cone of qubit `pinned` (sv.lightcone), moved onto
-    the cone's qubits only (ascending; the pinned qubit 0 stays position 0).
-    Every <O> on the pinned qubit is unchanged: a dropped gate, or a qubit no
-    kept gate touches, cannot reach it."""
+    the qubits they touch (sv.compact_qubits; the pinned qubit 0 stays
+    position 0)."""
     import paper_2111_06868_amd as sv
     keep = sv.lightcone(gates, n, (pinned,))
-    used = sorted({pinned} | {q for i in keep for q in gates[i][1]})
-    pos = {q: j for j, q in enumerate(used)}
-    return len(used), [(gates[i][0], tuple(pos[q] for q in gates[i][1])) + tuple(gates[i][2:]) for i in keep]
+    n_used, moved, _ = sv.compact_qubits([gates[i] for i in keep], n, (pinned,))
+    return n_used, moved
 
 
 def bench_density(args):

@@ -136,7 +136,7 @@ typedef struct sv_run_opts {
                           value with the lowest cost in the autotuned table   */
     int32_t precision; /* SV_PREC_*; must match the state's amplitude type    */
     int32_t rule;      /* SV_RULE_*                                           */
-    int32_t use_graph; /* 1: capture the launches in a hipGraph, replay it    */
+    int32_t use_graph; /* 1: run the launches as one hipGraph, kept per state */
 } sv_run_opts;
 
 typedef struct sv_state sv_state;
@@ -226,17 +226,20 @@ int sv_plan_rule(const sv_plan *p, int *out);
  * pass number >= 0 are applied together in one read and one write of the
  * state; -1 means the block is applied on its own. */
 int sv_plan_block_pass(const sv_plan *p, int b, int32_t *pass);
-/* Apply a plan's blocks in order with the given SV_PREC_* arithmetic; with
- * use_graph = 1 the launches are captured into a hipGraph that is replayed
- * once (and the call synchronises).  SV_ERR_QUBIT if the plan's positions do
- * not fit the state. */
+/* Apply a plan's blocks in order with the given SV_PREC_* arithmetic.  With
+ * use_graph = 1 the launches are captured into a hipGraph and launched as one;
+ * the state keeps the instantiated graph, and a later call whose launches have
+ * the same structure (block positions, kernels, launch shapes; the matrices
+ * may differ, as when angles change) updates it in place
+ * (hipGraphExecUpdate) instead of instantiating a new one.  Asynchronous in
+ * both modes.  SV_ERR_QUBIT if the plan's positions do not fit the state. */
 int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int use_graph);
 
 /* ---------------------------------------------------------------- circuits */
 /* Validate the G gates, fuse them (sv_fuse with o->max_k, o->rule) and apply
  * the blocks in order (paper, Simulations section: simulate(..., optimize=
  * 'evolution')).  Nothing is applied if any gate is invalid.  Asynchronous
- * (synchronises when o->use_graph = 1).  o == NULL means plain per-gate
+ * (use_graph as for sv_apply_plan).  o == NULL means plain per-gate
  * application: {SV_MAX_K, FP32 or FP64 by amplitude type, SV_RULE_NONE, 0}.
  * With SV_RULE_TILED on a complex64 state of >= 14 qubits, the gates are
  * grouped into passes whose positions span at most sv_set_tile_union()
@@ -368,15 +371,20 @@ int sv_dm_expectation(sv_state *rho, const sv_pauli_sum *H, double *out);
 /* ------------------------------------------ Kraus channels sampled on states */
 /* Pure-state sampling of Kraus channels (paper, Simulations with noise
  * section: noise is simulated exactly on density matrices or by sampling the
- * Kraus operators on pure states).  The operator must be a Kraus channel
- * sum_i K_i rho K_i^dagger in sv_super_op form: n_left = n_right operators
- * (at most 16), right holding the same matrices as left, s = NULL and
- * superop = NULL; its qubits index the state directly (`after` is used only
- * by sv_run_trajectory).  Outcome i has weight p_i = ||K_i psi||^2, which
- * depends on the state (amplitude damping, for example).
+ * Kraus operators on pure states).  The operator must be a KrausSuperGate
+ * whose right operators equal its left ones (n_left = n_right, at most 64,
+ * superop = NULL), either in Kraus form (s = NULL): the channel sum_i K_i rho
+ * K_i^dagger, or with a Hermitian positive semidefinite s (a GlobalPauliChannel
+ * with a general s, for example), which is first turned into its Kraus form
+ * as sv_kraus_form does.  Its qubits index the state directly (`after` is
+ * used only by sv_run_trajectory).  Outcome i has weight p_i = ||K_i psi||^2,
+ * which depends on the state (amplitude damping, for example).
  *
- * sv_kraus_probabilities: p_out[i] = ||K_i psi||^2 for i < n_left, summed in
- * FP64 in one pass over the state.  Synchronises.
+ * sv_kraus_probabilities: p_out[i] = ||K_i psi||^2 for the operators K_i of
+ * the Kraus form (n_left of them when s = NULL, the rank of s otherwise, in
+ * the order sv_kraus_form gives; the other of the n_left entries are set to
+ * 0), summed in FP64 in one pass over the state per 16 operators.
+ * Synchronises.
  *
  * sv_apply_kraus_sampled: with S = sum_i p_i, picks the first operator with a
  * nonzero weight whose running sum exceeds u * S (u in [0, 1), drawn by the
@@ -395,6 +403,56 @@ int sv_kraus_probabilities(sv_state *s, const sv_super_op *op, double *p_out);
 int sv_apply_kraus_sampled(sv_state *s, const sv_super_op *op, double u, int32_t *chosen, double *p_chosen);
 int sv_run_trajectory(sv_state *s, const sv_gate *g, int G, const sv_super_op *ops, int n_ops,
                       const double *uniforms, const sv_run_opts *o, int32_t *outcomes);
+
+/* ------------------------------------------------------------ noise channels */
+/* The channels of the paper's Noisy gates section as KrausSuperGates.  Each
+ * call fills `out` (with the given `after`) and writes the operators
+ * (2^k x 2^k complex matrices, row-major, (re, im) interleaved, back to back)
+ * into the caller's `mats`, which out->left and out->right point to; the
+ * caller keeps `mats` (and `s`) alive while `out` is used.  Except for
+ * sv_channel_pauli the result is in Kraus form (s = NULL), so it serves
+ * sv_dm_run and the sampled entry points alike.  The paper's Local versions
+ * (noise applied independently to each qubit) are one single-qubit channel
+ * per qubit, in any order (they act on different qubits and commute).
+ *
+ * sv_channel_depolarizing: rho -> (1 - p) rho + p I/d on the k = 1..3 qubits
+ * q (d = 2^k, p in [0, 1]), as the identity with weight 1 - p + p/d^2 and the
+ * other d^2 - 1 Pauli strings with weight p/d^2, K = sqrt(weight) P.  mats:
+ * 4^k matrices (2 * 16^k doubles).
+ *
+ * sv_channel_dephasing: rho -> (1 - p) rho + p sigma rho sigma on one qubit,
+ * sigma = X, Y or Z (pauli = 1, 2 or 3), p in [0, 1].  mats: 2 matrices (16
+ * doubles).
+ *
+ * sv_channel_amplitude_damping: K0 = sqrt(1 - beta)|0><0| + sqrt(1 - gamma)
+ * |1><1|, K1 = sqrt(gamma)|0><1| and, for an excitation rate beta > 0, K2 =
+ * sqrt(beta)|1><0| (gamma, beta in [0, 1]).  beta = 0 gives the paper's two
+ * operators; beta > 0 the generalized channel with |1> -> |0> at rate gamma and
+ * |0> -> |1> at rate beta.  mats: room for 3 matrices (24 doubles);
+ * out->n_left is 2 or 3.
+ *
+ * sv_channel_pauli: the GlobalPauliChannel rho -> sum_ij s_ij sigma_i rho
+ * sigma_j on the k = 1..3 qubits q: left = right = the 4^k Pauli strings,
+ * string i = sum_j i_j 4^(k-1-j) with i_j in {0, 1, 2, 3} = {I, X, Y, Z}
+ * acting on q[j], and out->s = s, the caller's 4^k x 4^k complex matrix
+ * (row-major, interleaved).  mats: 4^k matrices.
+ *
+ * sv_kraus_form: the Kraus form sum_m K_m rho K_m^dagger of a KrausSuperGate
+ * sum_ij s_ij L_i rho L_j^dagger whose right operators equal its left ones
+ * and whose s is NULL (the operators are copied) or Hermitian positive
+ * semidefinite (to 1e-12 relative): with s = V diag(lambda) V^dagger (FP64
+ * Jacobi eigendecomposition), K_m = sqrt(lambda_m) sum_i V_im L_i for every
+ * lambda_m above 1e-14 times the largest.  mats: room for n_left matrices;
+ * out (may alias in) receives the Kraus form and its operator count.
+ *
+ * Errors: SV_ERR_ARG (NULL, parameters out of range, k outside 1..3, s not
+ * Hermitian or not positive semidefinite, right != left), SV_ERR_QUBIT
+ * (negative or repeated qubit). */
+int sv_channel_depolarizing(int k, const int32_t *q, double p, int after, double *mats, sv_super_op *out);
+int sv_channel_dephasing(int qubit, int pauli, double p, int after, double *mats, sv_super_op *out);
+int sv_channel_amplitude_damping(int qubit, double gamma, double beta, int after, double *mats, sv_super_op *out);
+int sv_channel_pauli(int k, const int32_t *q, const double *s, int after, double *mats, sv_super_op *out);
+int sv_kraus_form(const sv_super_op *in, double *mats, sv_super_op *out);
 
 /* ---------------------------------------------------------------- batches */
 /* Many independent circuits of different qubit counts (noisy trajectories:
@@ -435,17 +493,32 @@ int sv_batch_free(sv_batch *b);
  * (milliseconds per block application, cost_ms[k], cost_ms[0] unused) for
  * this (n, precision).  Synchronises. */
 int sv_autotune(sv_state *scratch, int precision, double *cost_ms);
-/* Install a cost table for (n, precision) without timing (e.g. from a cache). */
+/* Install a cost table for (n, precision) without timing. */
 int sv_set_cost_table(int n, int precision, const double *cost_ms);
+/* Tuning cache.  When the environment variable SV_TUNE_CACHE names a file,
+ * every successful sv_autotune records there, under the key (GPU architecture,
+ * e.g. gfx950; n; precision), the cost table of every block size k (and of
+ * tile passes of 1..16 blocks) and the launch shapes it chose, replacing the
+ * older record of that key; the first sv_alloc of the process installs the
+ * records of the current device's architecture.  sv_tune_cache_load installs
+ * them from `path` (NULL: SV_TUNE_CACHE) on demand; the launch shapes come
+ * from the file's last matching record.  *loaded (may be NULL) receives the
+ * number of records installed.  Errors: SV_ERR_ARG (no path, unreadable
+ * file), SV_ERR_HIP. */
+int sv_tune_cache_load(const char *path, int *loaded);
 /* Select the launch shape of the multi-block tile passes (SV_RULE_TILED):
  * tiles of 2^tile_bits amplitudes held in LDS by workgroups of `waves`
  * 64-lane waves.  Supported: (14, 8) and (14, 16), one 128 KiB tile per
  * compute unit; (13, 4), two 64 KiB workgroups per compute unit; (13, 8).
- * A launch holds at most 7 blocks ((14, *)), 3 ((13, 4)) or 16 ((13, 8));
- * longer passes are split into several launches.  sv_autotune
+ * A launch holds at most 5 blocks ((14, *)), 2 ((13, 4)) or 15 ((13, 8));
+ * the tiled rule plans passes of at most that many blocks (the gates of a
+ * further block go to the next pass).  sv_autotune
  * picks one itself; this call overrides it for the whole process (later
  * launches on every state).  SV_ERR_ARG for other pairs. */
 int sv_set_tile_shape(int tile_bits, int waves);
+/* The current launch shape of the tile passes and the number of blocks one
+ * launch of it holds (pointers may be NULL). */
+int sv_get_tile_shape(int *tile_bits, int *waves, int *max_blocks);
 /* Position limit of the passes that SV_RULE_TILED plans (8..10; default 10,
  * or the SV_TILE_UNION environment variable at load time).  A larger union
  * holds more gates per pass but leaves shorter contiguous runs in HBM
@@ -485,15 +558,32 @@ int sv_controlled_gate(const sv_gate *g, int n_c, const int32_t *controls, sv_ga
 
 /* ------------------------------------------------------- circuit utilities */
 /* Host-only cuts applied before fusion (paper, Circuits section, Circuit
- * utilities: pop and simplify).  Both write the indices of the gates to keep,
- * ascending, into keep (room for G entries) and their count into n_keep; the
- * kept gates are applied in the original order.
+ * utilities: pop, which removes gates outside the light cone of pinned qubits
+ * from either side of the circuit, and simplify).  Both write the indices of
+ * the gates to keep, ascending, into keep (room for G entries) and their count
+ * into n_keep; the kept gates are applied in the original order.
  *
- * sv_lightcone (pop from the end): walking backwards, a gate touching the
- * light cone of the `pinned` qubits (bit p = position p) is kept and adds its
- * qubits to the cone; others are dropped.  Exact for expectations <O> of any
- * observable O on the pinned qubits (the dropped gates commute with O and
- * with every later kept gate).  Errors: SV_ERR_ARG, SV_ERR_QUBIT.
+ * sv_lightcone (pop): direction SV_POP_RIGHT walks backwards from the end: a
+ * gate touching the light cone of the `pinned` qubits (bit p = position p) is
+ * kept and adds its qubits to the cone; others are dropped.  Exact for
+ * expectations <O> of any observable O on the pinned qubits, from any initial
+ * state (the dropped gates commute with O and with every later kept gate).
+ * SV_POP_LEFT is the same walk forwards from the start (the right walk of the
+ * inverted circuit): the circuit equals K D, K the kept gates and D the
+ * dropped ones, which act only on unpinned qubits and commute with every
+ * earlier kept gate; so the kept gates give the same output state whenever D
+ * leaves the input unchanged (inputs rho_pinned (x) sigma with sigma
+ * maximally mixed, or invariant under D).  Errors: SV_ERR_ARG (bad direction),
+ * SV_ERR_QUBIT.
+ *
+ * sv_compact_qubits: renames the qubits that the G gates touch, plus the
+ * pinned ones, to positions 0 .. n_used - 1 in ascending order of their old
+ * positions: out[i] is g[i] on the new positions (matrix pointers shared),
+ * pos_map[p] (n entries) the new position of old position p or -1.  Run on
+ * the kept gates of a light cone, it moves a circuit onto the cone's qubits.
+ * From a product initial state, every expectation on the kept qubits is
+ * unchanged: an untouched qubit keeps its own product factor.  Errors:
+ * SV_ERR_ARG, SV_ERR_QUBIT.
  *
  * sv_simplify: drops gates equal to the identity and pairs (a, b), b after a
  * on the same qubits with b a = I, when every kept gate between them commutes
@@ -502,8 +592,24 @@ int sv_controlled_gate(const sv_gate *g, int n_c, const int32_t *controls, sv_ga
  * nothing changes.  Entries compare with absolute tolerance 1e-12.  The kept
  * gates have the same product as the circuit.  Errors: SV_ERR_ARG,
  * SV_ERR_QUBIT. */
-int sv_lightcone(const sv_gate *g, int G, int n, uint64_t pinned, int32_t *keep, int *n_keep);
+#define SV_POP_RIGHT 0
+#define SV_POP_LEFT 1
+int sv_lightcone(const sv_gate *g, int G, int n, uint64_t pinned, int direction, int32_t *keep, int *n_keep);
+int sv_compact_qubits(const sv_gate *g, int G, int n, uint64_t pinned, sv_gate *out, int32_t *pos_map, int *n_used);
 int sv_simplify(const sv_gate *g, int G, int n, int use_matrix_commutation, int32_t *keep, int *n_keep);
+
+/* ---------------------------------------------------------- measurement */
+/* The achievable rate of one state pass: `reps` streaming read + write passes
+ * over the complex64 state (n >= 14; every value is written back where it was
+ * read, so the state is unchanged) in tiles of 2^14 amplitudes spanned by
+ * the 14 positions set in tile_positions (position 0 among them), the HBM
+ * layout of a tile pass with those tile positions, with no LDS staging and no
+ * block work.  Positions 0..13 give whole 128 KiB runs; 0..3 with the top ten
+ * positions the 128-byte runs of a pass over the highest positions.  One
+ * workgroup per compute unit, as the tile passes.  *ms_per_pass receives the
+ * mean device milliseconds per pass (HIP events on the state's stream).
+ * Synchronises.  Errors: SV_ERR_ARG, SV_ERR_QUBIT, SV_ERR_HIP. */
+int sv_stream_probe(sv_state *s, uint64_t tile_positions, int reps, double *ms_per_pass);
 
 /* ---------------------------------------------------------------- stats */
 /* Per-kernel device timing.  While enabled every kernel launch is bracketed
@@ -517,6 +623,9 @@ int sv_simplify(const sv_gate *g, int G, int n, int use_matrix_commutation, int3
  * norm, 2 = inner product, 3 = expectation, 4 = Pauli-sum matvec, 5 =
  * density-matrix trace Tr(rho H), 6 = Kraus outcome weights. */
 int sv_stats_enable(int on);
+/* Graph runs of a state (use_graph = 1 calls): their count and how many of
+ * them reused the state's instantiated graph (updated in place). */
+int sv_graph_stats(const sv_state *s, int64_t *runs, int64_t *reused);
 int sv_stats_reset(void);
 int sv_stats_query(int cls, int64_t *launches, double *total_ms);
 

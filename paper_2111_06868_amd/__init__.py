@@ -25,9 +25,10 @@ from ._native import (C64, C128, PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16, PR
                       SvValueError)
 
 __all__ = ["State", "Plan", "fuse", "gate_matrix", "backward", "Energy", "Batch", "positions",
-           "DensityMatrix", "SuperOp", "depolarizing", "dephasing", "amplitude_damping", "lightcone", "simplify", "expectation_noalloc",
+           "DensityMatrix", "SuperOp", "depolarizing", "dephasing", "amplitude_damping", "pauli_channel",
+           "local_channels", "kraus_form", "lightcone", "compact_qubits", "simplify", "expectation_noalloc",
            "controlled",
-           "pauli_sum", "autotune", "set_cost_table", "set_tile_shape", "set_tile_union", "TILE_SHAPES",
+           "pauli_sum", "autotune", "set_cost_table", "tune_cache_load", "set_tile_shape", "get_tile_shape", "set_tile_union", "TILE_SHAPES",
            "stats_enable", "stats_reset", "stats_query",
            "C64", "C128", "PREC_FP32", "PREC_SPLIT_BF16", "PREC_SPLIT_FP16", "PREC_FP64",
            "RULE_PAPER", "RULE_ENHANCED", "RULE_NONE", "RULE_TILED", "RULE_AUTO", "SvError", "SvValueError"]
@@ -122,18 +123,46 @@ def controlled(gate, controls):
     return ("MATRIX", tuple(int(out.q[j]) for j in range(k)), (), -1, m.view(np.complex128).reshape(1 << k, 1 << k))
 
 
-def lightcone(gates, n: int, pinned) -> List[int]:
-    """Indices of the gates inside the light cone of the pinned qubits, walking
-    from the end (the paper's pop; exact for observables on the pinned qubits)."""
-    ga = gates if isinstance(gates, GateArray) else GateArray(gates)
+def _mask(qubits) -> int:
     mask = 0
-    for q in pinned:
+    for q in qubits:
         mask |= 1 << int(q)
+    return mask
+
+
+def lightcone(gates, n: int, pinned, direction: str = "right") -> List[int]:
+    """Indices of the gates inside the light cone of the pinned qubits (the
+    paper's pop, sv_lightcone): direction "right" walks from the end (exact for
+    observables on the pinned qubits), "left" from the start."""
+    ga = gates if isinstance(gates, GateArray) else GateArray(gates)
+    d = {"right": N.POP_RIGHT, "left": N.POP_LEFT}.get(direction)
+    if d is None:
+        raise ValueError("direction must be 'right' or 'left'")
     keep = np.zeros(max(ga.n, 1), dtype=np.int32)
     cnt = ctypes.c_int()
-    N.check(N.lib().sv_lightcone(ga.ptr, ga.n, int(n), mask, keep.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
-                                 ctypes.byref(cnt)))
+    N.check(N.lib().sv_lightcone(ga.ptr, ga.n, int(n), _mask(pinned), d,
+                                 keep.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(cnt)))
     return [int(x) for x in keep[:cnt.value]]
+
+
+def compact_qubits(gates, n: int, pinned=()):
+    """(n_used, gates, pos_map): the gates moved onto the qubits they touch
+    plus the pinned ones, renumbered 0.. in ascending order
+    (sv_compact_qubits); pos_map[p] is old position p's new one or -1."""
+    gates = list(gates)
+    ga = GateArray(gates)
+    out = (N.sv_gate * max(ga.n, 1))()
+    pos = np.zeros(int(n), dtype=np.int32)
+    used = ctypes.c_int()
+    N.check(N.lib().sv_compact_qubits(ga.ptr, ga.n, int(n), _mask(pinned), ctypes.cast(out, ctypes.POINTER(N.sv_gate)),
+                                      pos.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(used)))
+    moved = []
+    for i, g in enumerate(gates):
+        t = tuple(g) if isinstance(g, tuple) else (g.name, tuple(g.qubits), tuple(getattr(g, "params", ())),
+                                                   getattr(g, "param_index", -1)) + (
+            (g.matrix,) if getattr(g, "matrix", None) is not None else ())
+        moved.append((t[0], tuple(int(out[i].q[j]) for j in range(out[i].k))) + t[2:])
+    return used.value, moved, [int(x) for x in pos]
 
 
 def simplify(gates, n: int, use_matrix_commutation: bool = True) -> List[int]:
@@ -290,6 +319,19 @@ class State:
         N.check(N.lib().sv_apply_plan(self.h, plan.h, prec, int(bool(use_graph))))
         return self
 
+    def graph_stats(self):
+        """(graph runs, runs that reused the state's instantiated graph)."""
+        runs, reused = ctypes.c_int64(), ctypes.c_int64()
+        N.check(N.lib().sv_graph_stats(self.h, ctypes.byref(runs), ctypes.byref(reused)))
+        return runs.value, reused.value
+
+    def stream_probe(self, tile_positions, reps: int = 10) -> float:
+        """Mean ms of a streaming read + write pass over this complex64 state
+        in tiles spanned by the 14 tile positions (sv_stream_probe)."""
+        ms = ctypes.c_double()
+        N.check(N.lib().sv_stream_probe(self.h, _mask(tile_positions), int(reps), ctypes.byref(ms)))
+        return ms.value
+
     # -- reductions (FP64)
     def norm2(self) -> float:
         out = ctypes.c_double()
@@ -436,42 +478,97 @@ class SuperOp:
         return out.view(np.complex128).reshape(D2, D2)
 
 
-_PAULI_1Q = {"I": np.eye(2), "X": np.array([[0, 1], [1, 0]]), "Y": np.array([[0, -1j], [1j, 0]]),
-             "Z": np.array([[1, 0], [0, -1]])}
-
-
-def _pauli_string(labels) -> np.ndarray:
-    m = np.ones((1, 1), dtype=np.complex128)
-    for c in labels:  # first label on the most significant local bit
-        m = np.kron(m, _PAULI_1Q[c])
-    return m
+def _super_from_c(c: "N.sv_super_op", mats: np.ndarray, s=None) -> SuperOp:
+    """A SuperOp holding the operators a library constructor wrote."""
+    k = c.k
+    D = 1 << k
+    ops = mats.view(np.complex128)[: c.n_left * D * D].reshape(c.n_left, D, D).copy()
+    return SuperOp(tuple(int(c.q[j]) for j in range(k)), left=ops, s=s, after=int(c.after))
 
 
 def depolarizing(qubits, p: float, after: int = 0) -> SuperOp:
     """Global depolarizing channel rho -> (1 - p) rho + p I/d on the qubits
-    (paper, Noisy gates section), as the Kraus form sum_P (p/d^2) P rho P
-    plus (1 - p) rho."""
-    import itertools
-    k = len(qubits)
-    d = 1 << k
-    ops, w = [], []
-    for labels in itertools.product("IXYZ", repeat=k):
-        ops.append(_pauli_string(labels))
-        w.append(p / (d * d) + (1.0 - p if set(labels) == {"I"} else 0.0))
-    return SuperOp(qubits, left=ops, s=np.diag(w), after=after)
+    (paper, Noisy gates section; sv_channel_depolarizing)."""
+    q = np.ascontiguousarray([int(x) for x in qubits], dtype=np.int32)
+    if not 1 <= q.size <= 3:
+        raise ValueError("depolarizing channel on %d qubits (1..3)" % q.size)
+    mats = np.zeros(2 * 16 ** q.size, dtype=np.float64)
+    c = N.sv_super_op()
+    N.check(N.lib().sv_channel_depolarizing(q.size, q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), float(p),
+                                            int(after), mats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            ctypes.byref(c)))
+    return _super_from_c(c, mats)
+
+
+_PAULI_INDEX = {"X": 1, "Y": 2, "Z": 3}
 
 
 def dephasing(qubit: int, p: float, pauli: str = "Z", after: int = 0) -> SuperOp:
-    """rho -> (1 - p) rho + p sigma rho sigma (paper, Noisy gates section)."""
-    return SuperOp((qubit,), left=[np.eye(2), _PAULI_1Q[pauli.upper()]], s=np.diag([1.0 - p, p]), after=after)
+    """rho -> (1 - p) rho + p sigma rho sigma (paper, Noisy gates section;
+    sv_channel_dephasing)."""
+    if pauli.upper() not in _PAULI_INDEX:
+        raise ValueError("dephasing Pauli must be X, Y or Z")
+    mats = np.zeros(16, dtype=np.float64)
+    c = N.sv_super_op()
+    N.check(N.lib().sv_channel_dephasing(int(qubit), _PAULI_INDEX[pauli.upper()], float(p), int(after),
+                                         mats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(c)))
+    return _super_from_c(c, mats)
 
 
-def amplitude_damping(qubit: int, gamma: float, after: int = 0) -> SuperOp:
-    """Kraus operators |0><0| + sqrt(1 - gamma)|1><1| and sqrt(gamma)|0><1|
-    (paper, Noisy gates section)."""
-    K0 = np.array([[1.0, 0.0], [0.0, np.sqrt(1.0 - gamma)]])
-    K1 = np.array([[0.0, np.sqrt(gamma)], [0.0, 0.0]])
-    return SuperOp((qubit,), left=[K0, K1], after=after)
+def amplitude_damping(qubit: int, gamma: float, excitation: float = 0.0, after: int = 0) -> SuperOp:
+    """Kraus operators sqrt(1 - excitation)|0><0| + sqrt(1 - gamma)|1><1|,
+    sqrt(gamma)|0><1| and, for a nonzero excitation rate, sqrt(excitation)
+    |1><0| (paper, Noisy gates section; sv_channel_amplitude_damping)."""
+    mats = np.zeros(24, dtype=np.float64)
+    c = N.sv_super_op()
+    N.check(N.lib().sv_channel_amplitude_damping(int(qubit), float(gamma), float(excitation), int(after),
+                                                 mats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                                 ctypes.byref(c)))
+    return _super_from_c(c, mats)
+
+
+def pauli_channel(qubits, s, after: int = 0) -> SuperOp:
+    """GlobalPauliChannel rho -> sum_ij s_ij sigma_i rho sigma_j (paper, Noisy
+    gates section; sv_channel_pauli): s is 4^k x 4^k, string i = sum_j i_j
+    4^(k-1-j) with i_j in 0..3 = I, X, Y, Z on qubits[j]."""
+    q = np.ascontiguousarray([int(x) for x in qubits], dtype=np.int32)
+    if not 1 <= q.size <= 3:
+        raise ValueError("Pauli channel on %d qubits (1..3)" % q.size)
+    S = np.ascontiguousarray(s, dtype=np.complex128)
+    if S.shape != (4 ** q.size, 4 ** q.size):
+        raise ValueError("s must be %dx%d" % (4 ** q.size, 4 ** q.size))
+    mats = np.zeros(2 * 16 ** q.size, dtype=np.float64)
+    c = N.sv_super_op()
+    N.check(N.lib().sv_channel_pauli(q.size, q.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     S.view(np.float64).ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     int(after), mats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                     ctypes.byref(c)))
+    return _super_from_c(c, mats, s=S)
+
+
+def local_channels(make, qubits, *params, after: int = 0) -> List[SuperOp]:
+    """The paper's Local version of a one-qubit channel: make(qubit, *params)
+    on each qubit, each parameter either one value for every qubit or one
+    value per qubit."""
+    qubits = list(qubits)
+    cols = []
+    for v in params:
+        seq = list(v) if isinstance(v, (list, tuple, np.ndarray)) and np.ndim(v) == 1 and len(v) == len(qubits) \
+            and not isinstance(v, str) else [v] * len(qubits)
+        cols.append(seq)
+    return [make(q, *[c[i] for c in cols], after=after) for i, q in enumerate(qubits)]
+
+
+def kraus_form(op: SuperOp) -> SuperOp:
+    """The Kraus form of a KrausSuperGate with right == left and Hermitian
+    PSD s (sv_kraus_form)."""
+    c, keep = N.sv_super_op(), []
+    op.fill(c, keep)
+    mats = np.zeros(2 * max(c.n_left, 1) * (1 << (2 * c.k)), dtype=np.float64)
+    out = N.sv_super_op()
+    N.check(N.lib().sv_kraus_form(ctypes.byref(c), mats.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  ctypes.byref(out)))
+    return _super_from_c(out, mats)
 
 
 class DensityMatrix:
@@ -739,6 +836,14 @@ def set_cost_table(n: int, precision: int, cost) -> None:
     N.check(N.lib().sv_set_cost_table(int(n), int(precision), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
 
+def tune_cache_load(path: str = None) -> int:
+    """Install the cost tables and launch shapes saved in a tuning cache
+    (sv_tune_cache_load; path None = $SV_TUNE_CACHE); returns the count."""
+    n = ctypes.c_int()
+    N.check(N.lib().sv_tune_cache_load(None if path is None else path.encode(), ctypes.byref(n)))
+    return n.value
+
+
 TILE_SHAPES = ((14, 8), (14, 16), (13, 4), (13, 8))
 MAX_TILE_LAUNCH_BLOCKS = 16  # blocks one tile-pass launch can hold (stats classes k = 1..16)
 
@@ -747,6 +852,13 @@ def set_tile_shape(tile_bits: int, waves: int) -> None:
     """Launch shape of the tile passes: 2^tile_bits amplitudes per LDS tile,
     `waves` waves per workgroup (one of TILE_SHAPES), for the whole process."""
     N.check(N.lib().sv_set_tile_shape(int(tile_bits), int(waves)))
+
+
+def get_tile_shape():
+    """(tile_bits, waves, blocks per launch) of the tile passes (sv_get_tile_shape)."""
+    b, w, m = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    N.check(N.lib().sv_get_tile_shape(ctypes.byref(b), ctypes.byref(w), ctypes.byref(m)))
+    return b.value, w.value, m.value
 
 
 def set_tile_union(max_positions: int) -> None:

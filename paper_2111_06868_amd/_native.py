@@ -34,6 +34,9 @@ RULE_NONE = 2
 RULE_TILED = 3
 RULE_AUTO = 4
 
+POP_RIGHT = 0
+POP_LEFT = 1
+
 GATE_KINDS = {
     "MATRIX": 0, "I": 1, "X": 2, "Y": 3, "Z": 4, "H": 5, "SQRT_X": 6, "SQRT_Y": 7,
     "SQRT_W": 8, "RX": 9, "RY": 10, "RZ": 11, "CZ": 12, "CX": 13, "CPHASE": 14,
@@ -123,6 +126,12 @@ SIGNATURES = {
     "sv_apply_kraus_sampled": (_I, [_P, ctypes.POINTER(sv_super_op), ctypes.c_double, _I32P, _D]),
     "sv_run_trajectory": (_I, [_P, _GP, _I, ctypes.POINTER(sv_super_op), _I, _D,
                                ctypes.POINTER(sv_run_opts), _I32P]),
+    "sv_channel_depolarizing": (_I, [_I, _I32P, ctypes.c_double, _I, _D, ctypes.POINTER(sv_super_op)]),
+    "sv_channel_dephasing": (_I, [_I, _I, ctypes.c_double, _I, _D, ctypes.POINTER(sv_super_op)]),
+    "sv_channel_amplitude_damping": (_I, [_I, ctypes.c_double, ctypes.c_double, _I, _D,
+                                          ctypes.POINTER(sv_super_op)]),
+    "sv_channel_pauli": (_I, [_I, _I32P, _D, _I, _D, ctypes.POINTER(sv_super_op)]),
+    "sv_kraus_form": (_I, [ctypes.POINTER(sv_super_op), _D, ctypes.POINTER(sv_super_op)]),
     "sv_batch_required_bytes": (_I, [ctypes.POINTER(sv_batch_desc), ctypes.POINTER(_SZ)]),
     "sv_batch_create": (_I, [ctypes.POINTER(sv_batch_desc), _P, _SZ, _P, ctypes.POINTER(_P)]),
     "sv_batch_run": (_I, [_P, _I, _D]),
@@ -130,14 +139,19 @@ SIGNATURES = {
     "sv_batch_free": (_I, [_P]),
     "sv_autotune": (_I, [_P, _I, _D]),
     "sv_set_cost_table": (_I, [_I, _I, _D]),
+    "sv_tune_cache_load": (_I, [ctypes.c_char_p, ctypes.POINTER(_I)]),
     "sv_set_tile_shape": (_I, [_I, _I]),
     "sv_set_tile_union": (_I, [_I]),
+    "sv_get_tile_shape": (_I, [ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
     "sv_project": (_I, [_P, _I, _I32P, _U64, _I, _D]),
     "sv_measure": (_I, [_P, _I, _I32P, _D, ctypes.POINTER(_U64), _D]),
     "sv_controlled_gate": (_I, [_GP, _I, _I32P, _GP, _D]),
-    "sv_lightcone": (_I, [_GP, _I, _I, _U64, _I32P, ctypes.POINTER(_I)]),
+    "sv_lightcone": (_I, [_GP, _I, _I, _U64, _I, _I32P, ctypes.POINTER(_I)]),
+    "sv_compact_qubits": (_I, [_GP, _I, _I, _U64, _GP, _I32P, ctypes.POINTER(_I)]),
     "sv_simplify": (_I, [_GP, _I, _I, _I, _I32P, ctypes.POINTER(_I)]),
+    "sv_stream_probe": (_I, [_P, _U64, _I, _D]),
     "sv_stats_enable": (_I, [_I]),
+    "sv_graph_stats": (_I, [_P, _I64P, _I64P]),
     "sv_stats_reset": (_I, []),
     "sv_stats_query": (_I, [_I, _I64P, _D]),
 }

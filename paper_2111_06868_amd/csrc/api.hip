@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <fstream>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -93,9 +94,12 @@ int run_launches(sv_state *s, std::vector<Launch> &launches, bool use_graph)
         SV_HIP(hipEventRecord(s->arena_free, s->stream));
         return rc;
     }
+    // Capture the launches, then reuse the state's instantiated graph when the
+    // new one has the same topology (hipGraphExecUpdate takes the new kernel
+    // arguments: matrices, operand addresses), else instantiate anew.  The
+    // previous launch of that graph has finished: arena_free was synchronised.
     if (!s->capture_stream) SV_HIP(hipStreamCreateWithFlags(&s->capture_stream, hipStreamNonBlocking));
     hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
     SV_HIP(hipStreamBeginCapture(s->capture_stream, hipStreamCaptureModeThreadLocal));
     timing_suspend(true);
     int rc = enqueue(launches, s->dtype, s->buf, s->n, s->arena.p, s->capture_stream);
@@ -106,13 +110,28 @@ int run_launches(sv_state *s, std::vector<Launch> &launches, bool use_graph)
         return rc;
     }
     if (e != hipSuccess) return fail(SV_ERR_HIP, "graph capture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e == hipSuccess) e = hipGraphLaunch(exec, s->stream);
-    if (e == hipSuccess) e = hipEventRecord(s->arena_free, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-    if (exec) (void)hipGraphExecDestroy(exec);
+    bool updated = false;
+    if (s->graph_exec) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res = hipGraphExecUpdateError;
+        updated = hipGraphExecUpdate(s->graph_exec, graph, &bad, &res) == hipSuccess && res == hipGraphExecUpdateSuccess;
+        if (!updated) {
+            (void)hipGetLastError();  // a refused update is not an error of this call
+            (void)hipGraphExecDestroy(s->graph_exec);
+            s->graph_exec = nullptr;
+        }
+    }
+    if (!updated) e = hipGraphInstantiate(&s->graph_exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return fail(SV_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
+    if (e == hipSuccess) e = hipGraphLaunch(s->graph_exec, s->stream);
+    if (e == hipSuccess) e = hipEventRecord(s->arena_free, s->stream);
+    if (e != hipSuccess) {
+        if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+        s->graph_exec = nullptr;
+        return fail(SV_ERR_HIP, "graph launch: %s", hipGetErrorString(e));
+    }
+    ++s->graph_launches;
+    if (updated) ++s->graph_updates;
     return SV_OK;
 }
 
@@ -268,6 +287,13 @@ extern "C" int sv_alloc(int n, int dtype, void *dev_buf, size_t bytes, void *hip
         sv_free(s);
         return rc;
     }
+    // the first state of the process installs a saved tuning cache, if any
+    static std::once_flag cache_once;
+    std::call_once(cache_once, [&] {
+        const char *path = std::getenv("SV_TUNE_CACHE");
+        if (path && *path && std::ifstream(path).good()) (void)load_tuning(path, s->device, nullptr);
+        clear_error();
+    });
     *out = s;
     return SV_OK;
 }
@@ -278,6 +304,7 @@ extern "C" int sv_free(sv_state *s)
     (void)hipSetDevice(s->device);
     (void)hipStreamSynchronize(s->stream);
     if (s->owns && s->buf) (void)hipFree(s->buf);
+    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
     if (s->capture_stream) (void)hipStreamDestroy(s->capture_stream);
     if (s->arena_free) (void)hipEventDestroy(s->arena_free);
     delete s;
@@ -799,30 +826,33 @@ extern "C" int sv_dm_expectation(sv_state *rho, const sv_pauli_sum *H, double *o
 
 namespace {
 
-// p[i] = ||K_i psi||^2 (FP64, one pass over the state).  Synchronises.
-int kraus_weights(sv_state *s, const std::vector<cd> &mats, int n_ops, int k, const int *pos, double *p)
+// p[i] = ||K_i psi||^2 (FP64; one pass over the state per kMaxKraus
+// operators).  Synchronises.
+int kraus_weights(sv_state *s, const KrausSet &ks, double *p)
 {
     if (int rc = select_device(s)) return rc;
-    SV_HIP(s->red.ensure(sizeof(double) * (size_t(dev::kMaxKraus) * dev::kRedBlocks + 64)));
+    constexpr int kChunks = (kMaxKrausOps + dev::kMaxKraus - 1) / dev::kMaxKraus;
+    SV_HIP(s->red.ensure(sizeof(double) * (size_t(dev::kMaxKraus) * dev::kRedBlocks + dev::kMaxKraus * kChunks)));
     SV_HIP(hipEventSynchronize(s->arena_free));
-    const size_t bytes = sizeof(cd) * mats.size();
+    const size_t bytes = sizeof(cd) * ks.canon.size();
     SV_HIP(s->stage.ensure(bytes));
     SV_HIP(s->arena.ensure(bytes));
-    std::memcpy(s->stage.p, mats.data(), bytes);
+    std::memcpy(s->stage.p, ks.canon.data(), bytes);
     SV_HIP(hipMemcpyAsync(s->arena.p, s->stage.p, bytes, hipMemcpyHostToDevice, s->stream));
-    dev::KrausDev K;
-    K.n_ops = n_ops;
-    K.k = k;
-    for (int j = 0; j < 3; ++j) K.pos[j] = j < k ? pos[j] : 0;
-    K.m = static_cast<const double *>(s->arena.p);
     double *part = static_cast<double *>(s->red.p);
     double *res = part + size_t(dev::kMaxKraus) * dev::kRedBlocks;
-    {
+    const size_t D2 = size_t(1) << (2 * ks.k);
+    for (int c0 = 0; c0 < ks.n_ops; c0 += dev::kMaxKraus) {
+        dev::KrausDev K;
+        K.n_ops = std::min(dev::kMaxKraus, ks.n_ops - c0);
+        K.k = ks.k;
+        for (int j = 0; j < 3; ++j) K.pos[j] = j < ks.k ? ks.sorted_q[j] : 0;
+        K.m = static_cast<const double *>(s->arena.p) + 2 * D2 * c0;
         LaunchTimer t(stat_class(FAM_REDUCE, 6), s->stream);
-        SV_HIP(dev::launch_kraus_probs(s->dtype, s->buf, s->n, K, part, res, s->stream));
+        SV_HIP(dev::launch_kraus_probs(s->dtype, s->buf, s->n, K, part, res + c0, s->stream));
     }
     SV_HIP(hipEventRecord(s->arena_free, s->stream));
-    return read_result(s, res, size_t(n_ops), p);
+    return read_result(s, res, size_t(ks.n_ops), p);
 }
 
 // Draw one Kraus operator with probability p_i / sum p by the uniform u and
@@ -830,30 +860,29 @@ int kraus_weights(sv_state *s, const std::vector<cd> &mats, int n_ops, int k, co
 // taken (zero-weight operators are never taken).
 int sample_kraus(sv_state *s, const sv_super_op &op, double u, int32_t *chosen, double *p_chosen)
 {
-    std::vector<cd> mats;
-    int pos[3];
-    if (int rc = kraus_canonical(op, s->n, mats, pos)) return rc;
-    double p[dev::kMaxKraus];
-    if (int rc = kraus_weights(s, mats, op.n_left, op.k, pos, p)) return rc;
+    KrausSet ks;
+    if (int rc = kraus_canonical(op, s->n, ks)) return rc;
+    double p[kMaxKrausOps];
+    if (int rc = kraus_weights(s, ks, p)) return rc;
     double total = 0.0;
-    for (int i = 0; i < op.n_left; ++i) total += p[i];
+    for (int i = 0; i < ks.n_ops; ++i) total += p[i];
     if (!(total > 0.0) || !std::isfinite(total)) return fail(SV_ERR_ARG, "Kraus outcome weights sum to %g", total);
     int pick = -1;
     double run = 0.0;
-    for (int i = 0; i < op.n_left; ++i) {
+    for (int i = 0; i < ks.n_ops; ++i) {
         run += p[i];
         if (p[i] > 0.0) pick = i;  // the last nonzero one, should rounding leave u * total above every sum
         if (p[i] > 0.0 && u * total < run) break;
     }
-    const size_t D = size_t(1) << op.k;
+    const size_t D = size_t(1) << ks.k;
     const double scale = 1.0 / std::sqrt(p[pick]);
     std::vector<double> m(2 * D * D);
-    for (size_t e = 0; e < 2 * D * D; ++e) m[e] = op.left[2 * D * D * pick + e] * scale;
+    for (size_t e = 0; e < 2 * D * D; ++e) m[e] = ks.abi[2 * D * D * pick + e] * scale;
     sv_gate h{};
     h.kind = SV_G_MATRIX;
-    h.k = op.k;
+    h.k = ks.k;
     h.param = -1;
-    for (int a = 0; a < op.k; ++a) h.q[a] = op.q[a];
+    for (int a = 0; a < ks.k; ++a) h.q[a] = ks.q[a];
     h.m = m.data();
     if (int rc = apply_gate_impl(s, &h)) return rc;
     if (chosen) *chosen = pick;
@@ -868,10 +897,11 @@ extern "C" int sv_kraus_probabilities(sv_state *s, const sv_super_op *op, double
     clear_error();
     if (int rc = check_state(s)) return rc;
     if (!op || !p_out) return fail(SV_ERR_ARG, "NULL argument");
-    std::vector<cd> mats;
-    int pos[3];
-    if (int rc = kraus_canonical(*op, s->n, mats, pos)) return rc;
-    return kraus_weights(s, mats, op->n_left, op->k, pos, p_out);
+    KrausSet ks;
+    if (int rc = kraus_canonical(*op, s->n, ks)) return rc;
+    if (int rc = kraus_weights(s, ks, p_out)) return rc;
+    for (int i = ks.n_ops; i < op->n_left; ++i) p_out[i] = 0.0;
+    return SV_OK;
 }
 
 extern "C" int sv_apply_kraus_sampled(sv_state *s, const sv_super_op *op, double u, int32_t *chosen,
@@ -892,9 +922,8 @@ extern "C" int sv_run_trajectory(sv_state *s, const sv_gate *g, int G, const sv_
     if (int rc = validate_gates(g, G, s->n)) return rc;
     if (n_ops < 0 || (n_ops && (!ops || !uniforms))) return fail(SV_ERR_ARG, "NULL operator or uniform array");
     for (int j = 0; j < n_ops; ++j) {
-        std::vector<cd> mats;
-        int pos[3];
-        if (int rc = kraus_canonical(ops[j], s->n, mats, pos)) return rc;
+        KrausSet ks;
+        if (int rc = kraus_canonical(ops[j], s->n, ks)) return rc;
         if (ops[j].after < 0 || ops[j].after > G || (j && ops[j].after < ops[j - 1].after))
             return fail(SV_ERR_ARG, "operator %d: after = %d out of order (0..%d, nondecreasing)", j, ops[j].after, G);
         if (!(uniforms[j] >= 0.0 && uniforms[j] < 1.0))
@@ -1336,4 +1365,13 @@ extern "C" int sv_stats_query(int cls, int64_t *launches, double *total_ms)
     clear_error();
     if (!launches || !total_ms) return fail(SV_ERR_ARG, "NULL argument");
     return stats_query(cls, launches, total_ms);
+}
+
+extern "C" int sv_graph_stats(const sv_state *s, int64_t *runs, int64_t *reused)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    if (runs) *runs = s->graph_launches;
+    if (reused) *reused = s->graph_updates;
+    return SV_OK;
 }

@@ -114,16 +114,25 @@ bool is_identity(const GateInfo &ig, int k)
 
 }  // namespace sv
 
-// Light cone (pop): walking from the end of the circuit, the cone starts as the
-// pinned qubits; a gate that touches the cone is kept and adds its qubits, any
-// other gate is dropped.  A dropped gate acts only on qubits outside the cone
-// of every later kept gate, so it commutes with all of them and with any
-// observable on the pinned qubits, and cancels in <psi| U^dagger O U |psi>.
-extern "C" int sv_lightcone(const sv_gate *g, int G, int n, uint64_t pinned, int32_t *keep, int *n_keep)
+// Light cone (pop).  SV_POP_RIGHT walks from the end of the circuit: the cone
+// starts as the pinned qubits; a gate that touches the cone is kept and adds
+// its qubits, any other gate is dropped.  A dropped gate acts only on qubits
+// outside the cone of every later kept gate, so it commutes with all of them
+// and with any observable on the pinned qubits, and cancels in
+// <psi| U^dagger O U |psi>.  SV_POP_LEFT is the same walk from the start: a
+// dropped gate is disjoint from every earlier kept gate and from the pinned
+// qubits, so U = K D with K the kept gates and D the dropped ones, acting on
+// the other qubits only; the pinned qubits' influence (U (rho_pinned (x)
+// sigma) U^dagger for any sigma that D leaves unchanged, e.g. I/2^m) needs K
+// only.  It is the right walk of the inverted circuit.
+extern "C" int sv_lightcone(const sv_gate *g, int G, int n, uint64_t pinned, int direction, int32_t *keep,
+                            int *n_keep)
 {
     sv::clear_error();
     if (!keep || !n_keep) return sv::fail(SV_ERR_ARG, "NULL output");
     if (n < 1 || n > 64) return sv::fail(SV_ERR_ARG, "n = %d outside 1..64", n);
+    if (direction != SV_POP_RIGHT && direction != SV_POP_LEFT)
+        return sv::fail(SV_ERR_ARG, "direction %d (SV_POP_RIGHT or SV_POP_LEFT)", direction);
     if (n < 64 && (pinned >> n)) return sv::fail(SV_ERR_QUBIT, "pinned qubits beyond qubit %d", n - 1);
     if (G < 0 || (G && !g)) return sv::fail(SV_ERR_ARG, "bad gate array");
     for (int i = 0; i < G; ++i) {
@@ -133,16 +142,47 @@ extern "C" int sv_lightcone(const sv_gate *g, int G, int n, uint64_t pinned, int
     }
     uint64_t cone = pinned;
     std::vector<int32_t> kept;
-    for (int i = G - 1; i >= 0; --i) {
+    const bool right = direction == SV_POP_RIGHT;
+    for (int t = 0; t < G; ++t) {
+        const int i = right ? G - 1 - t : t;
         const uint64_t m = sv::qubit_mask(g[i]);
         if (m & cone) {
             cone |= m;
             kept.push_back(i);
         }
     }
-    std::reverse(kept.begin(), kept.end());
+    if (right) std::reverse(kept.begin(), kept.end());
     std::copy(kept.begin(), kept.end(), keep);
     *n_keep = int(kept.size());
+    return SV_OK;
+}
+
+// Compaction: the qubits that the gates touch, plus the pinned ones, renamed
+// to positions 0, 1, .. in ascending order of their old positions.  A qubit
+// that no gate touches keeps its initial product factor, which drops out of
+// every reduced state of the others.
+extern "C" int sv_compact_qubits(const sv_gate *g, int G, int n, uint64_t pinned, sv_gate *out, int32_t *pos_map,
+                                 int *n_used)
+{
+    sv::clear_error();
+    if (!pos_map || !n_used || (G && !out)) return sv::fail(SV_ERR_ARG, "NULL output");
+    if (n < 1 || n > 64) return sv::fail(SV_ERR_ARG, "n = %d outside 1..64", n);
+    if (n < 64 && (pinned >> n)) return sv::fail(SV_ERR_QUBIT, "pinned qubits beyond qubit %d", n - 1);
+    if (G < 0 || (G && !g)) return sv::fail(SV_ERR_ARG, "bad gate array");
+    uint64_t used = pinned;
+    for (int i = 0; i < G; ++i) {
+        int rc = sv::check_gate_shape(g[i]);
+        if (!rc) rc = sv::check_gate_qubits(g[i], n);
+        if (rc) return rc;
+        used |= sv::qubit_mask(g[i]);
+    }
+    int next = 0;
+    for (int p = 0; p < n; ++p) pos_map[p] = ((used >> p) & 1) ? next++ : -1;
+    for (int i = 0; i < G; ++i) {
+        out[i] = g[i];
+        for (int j = 0; j < g[i].k; ++j) out[i].q[j] = pos_map[g[i].q[j]];
+    }
+    *n_used = next;
     return SV_OK;
 }
 

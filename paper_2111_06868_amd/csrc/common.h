@@ -58,6 +58,10 @@ struct CostTable {
     double tile[kTilePassMaxBlocks + 1] = {0};  // one tile pass holding s blocks of 4 qubits
 };
 
+// Blocks one tile-pass launch of the current launch shape holds; the tiled
+// rule plans passes of at most this many blocks.
+int tile_pass_capacity();
+
 // Union limit of the tile passes that SV_RULE_TILED plans (8 ..
 // kTilePassMaxUnion; default 10, or the SV_TILE_UNION environment variable).
 int tile_union_limit();
@@ -93,9 +97,21 @@ void block_matrix(const sv_gate *g, Block &b);
 int dm_expand(const sv_gate *g, int G, int n, const sv_super_op *ops, int n_ops, std::vector<sv_gate> &out,
               std::vector<std::vector<double>> &store);
 // Kraus channels sampled on pure states (sv_kraus_probabilities and the
-// sampled application): validation and canonical matrices.
-constexpr int kMaxKrausOps = 16;
-int kraus_canonical(const sv_super_op &op, int n, std::vector<cd> &mats, int *sorted_q);
+// sampled application): validation, Kraus form and canonical matrices.
+constexpr int kMaxKrausOps = 64;
+struct KrausSet {
+    int k = 0, n_ops = 0;
+    int q[3] = {0, 0, 0};         // qubits, q[0] the most significant local bit
+    int sorted_q[3] = {0, 0, 0};  // ascending
+    std::vector<double> abi;      // n_ops matrices, ABI order, interleaved
+    std::vector<cd> canon;        // n_ops matrices, canonical order
+};
+int kraus_canonical(const sv_super_op &op, int n, KrausSet &out);
+// Kraus form of a KrausSuperGate (right == left; s NULL or Hermitian PSD):
+// n_ops matrices in ABI order (see sv_kraus_form).
+int kraus_form(const sv_super_op &op, std::vector<double> &abi, int *n_ops);
+// A = V diag(w) V^dagger for a Hermitian n x n matrix (cyclic Jacobi).
+void hermitian_eigen(std::vector<cd> A, int n, std::vector<double> &w, std::vector<cd> &V);
 
 }  // namespace sv
 

@@ -156,30 +156,33 @@ int dm_expand(const sv_gate *g, int G, int n, const sv_super_op *ops, int n_ops,
     return SV_OK;
 }
 
-// A Kraus channel sum_i K_i rho K_i^dagger for sampling on pure states: the
-// operator must be in Kraus form (no s, no matrix form, right == left) with
-// at most kMaxKrausOps operators on qubits below n.  Fills the canonical
-// matrices (local bit j on the j-th lowest position) and the sorted positions.
-int kraus_canonical(const sv_super_op &op, int n, std::vector<cd> &mats, int *sorted_q)
+// A Kraus channel sum_i K_i rho K_i^dagger for sampling on pure states: a
+// KrausSuperGate on qubits below n in Kraus form (s = NULL) or with a
+// Hermitian positive semidefinite s (turned into Kraus form, kraus_form),
+// right == left, at most kMaxKrausOps operators.  Fills the ABI-order and the
+// canonical matrices (local bit j on the j-th lowest position), their count
+// and the sorted positions.
+int kraus_canonical(const sv_super_op &op, int n, KrausSet &out)
 {
     if (int rc = check_super_op(op)) return rc;
-    if (op.superop || op.s) return fail(SV_ERR_ARG, "sampling needs a Kraus channel (no s matrix, no matrix form)");
-    if (op.n_left > kMaxKrausOps) return fail(SV_ERR_ARG, "%d Kraus operators (at most %d)", op.n_left, kMaxKrausOps);
+    if (op.superop) return fail(SV_ERR_ARG, "sampling needs a Kraus channel, not a matrix super operator");
+    if (int rc = kraus_form(op, out.abi, &out.n_ops)) return rc;
+    if (out.n_ops > kMaxKrausOps) return fail(SV_ERR_ARG, "%d Kraus operators (at most %d)", out.n_ops, kMaxKrausOps);
     const size_t D = size_t(1) << op.k;
-    if (std::memcmp(op.left, op.right, sizeof(double) * 2 * D * D * op.n_left) != 0)
-        return fail(SV_ERR_ARG, "sampling needs right operators equal to the left ones");
     sv_gate h{};
     h.kind = SV_G_MATRIX;
     h.k = op.k;
     h.param = -1;
     for (int a = 0; a < op.k; ++a) h.q[a] = op.q[a];
     if (int rc = check_gate_qubits(h, n)) return rc;
-    mats.clear();
-    for (int i = 0; i < op.n_left; ++i) {
-        h.m = op.left + 2 * D * D * i;
+    out.k = op.k;
+    for (int a = 0; a < 3; ++a) out.q[a] = a < op.k ? op.q[a] : 0;
+    out.canon.clear();
+    for (int i = 0; i < out.n_ops; ++i) {
+        h.m = out.abi.data() + 2 * D * D * i;
         std::vector<cd> m;
-        if (int rc = gate_matrix_canonical(h, m, sorted_q)) return rc;
-        mats.insert(mats.end(), m.begin(), m.end());
+        if (int rc = gate_matrix_canonical(h, m, out.sorted_q)) return rc;
+        out.canon.insert(out.canon.end(), m.begin(), m.end());
     }
     return SV_OK;
 }

@@ -339,20 +339,35 @@ int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTa
         for (int gi = 0; gi < G; ++gi)
             if (g[gi].k > max_k)
                 return fail(SV_ERR_ARG, "gate %d acts on %d qubits, more than max_k=%d", gi, g[gi].k, max_k);
-        std::vector<int> all(G);
-        for (int i = 0; i < G; ++i) all[i] = i;
+        // Passes one at a time: the first union group of the gates left, cut
+        // into blocks; a pass keeps at most `cap` blocks (what one tile launch
+        // holds), and the gates of any further blocks return to the pool, so
+        // that the next pass can take them with its own gates.  They follow
+        // the kept blocks on every qubit they share, and the pool stays in
+        // circuit order.
+        const size_t cap = size_t(std::max(1, tile_pass_capacity()));
+        std::vector<int> pool(G);
+        for (int i = 0; i < G; ++i) pool[i] = i;
+        std::vector<char> taken(G, 0);
         int pass = 0;
-        for (const auto &pg : frontier_groups(g, all, tile_union_limit())) {
-            const auto sub = frontier_groups(g, pg, max_k);
-            for (size_t c = 0; c < sub.size(); c += kTilePassMaxBlocks) {
-                const size_t e = std::min(sub.size(), c + kTilePassMaxBlocks);
-                const size_t first = blocks.size();
-                blocks_of_groups(g, std::vector<std::vector<int>>(sub.begin() + c, sub.begin() + e), blocks);
-                if (e - c >= 2) {
-                    for (size_t b = first; b < blocks.size(); ++b) blocks[b].pass = pass;
-                    ++pass;
-                }
+        while (!pool.empty()) {
+            const auto groups = frontier_groups(g, pool, tile_union_limit());
+            if (groups.empty()) break;
+            const auto sub = frontier_groups(g, groups.front(), max_k);
+            const size_t e = std::min(sub.size(), cap);
+            const size_t first = blocks.size();
+            blocks_of_groups(g, std::vector<std::vector<int>>(sub.begin(), sub.begin() + e), blocks);
+            if (e >= 2) {
+                for (size_t b = first; b < blocks.size(); ++b) blocks[b].pass = pass;
+                ++pass;
             }
+            for (size_t b = first; b < blocks.size(); ++b)
+                for (int gi : blocks[b].members) taken[gi] = 1;
+            std::vector<int> rest;
+            rest.reserve(pool.size());
+            for (int gi : pool)
+                if (!taken[gi]) rest.push_back(gi);
+            pool.swap(rest);
         }
         return with_matrices ? block_matrices(g, blocks) : SV_OK;
     }

@@ -30,11 +30,11 @@ bool mfma_supported(int k, int n);
 // FP32: d_a = real-form matrix (2^(k+1) x 2^(k+1) floats, see mfma.hip).
 hipError_t launch_mfma_f32(int k, const int *sorted_q, const float *d_a, void *psi, int n,
                            hipStream_t st, int tc_log, int grid_cap, void *psi2 = nullptr);
-// Split precision: d_ahi / d_alo = hi and lo parts of the real-form matrix as
-// BF16 (fp16 = false) or FP16 (fp16 = true) bit patterns.
-hipError_t launch_mfma_split(int k, bool fp16, const int *sorted_q, const uint16_t *d_ahi,
-                             const uint16_t *d_alo, void *psi, int n, hipStream_t st, int tc_log,
-                             int grid_cap);
+// Split precision: d_parts[0..2] = the parts of the real-form matrix
+// (pack_real_form_split) as BF16 (fp16 = false: three parts) or FP16 (fp16 =
+// true: two parts, d_parts[2] unused) bit patterns.
+hipError_t launch_mfma_split(int k, bool fp16, const int *sorted_q, const uint16_t *const *d_parts, void *psi,
+                             int n, hipStream_t st, int tc_log, int grid_cap);
 // Multi-block tile passes (complex64, FP32 or split BF16 / FP16 MFMA): up to
 // tile_max_blocks() 4-qubit blocks whose positions have a union of at most
 // kMaxTileUnion positions, applied in one HBM pass over tiles of
@@ -56,10 +56,11 @@ struct TileArgs {
 };
 // Tile-pass operand of one 4-qubit block (canonical 16 x 16 matrix m), in
 // kTileOperandWords 32-bit words: FP32: Re U then Im U (16 x 16 floats each,
-// row-major); split BF16 / FP16: the hi then the lo parts of U, one word per
-// entry holding (re, im) as 16-bit values (re in the low half).  The
+// row-major); split BF16: three parts of U (part p = RNE(U - parts before
+// it)), split FP16: two parts, 256 words each, one word per entry holding
+// (re, im) as 16-bit values (re in the low half); unused words are 0.  The
 // precision codes are also the tile passes' arithmetic.
-constexpr int kTileOperandWords = 512;
+constexpr int kTileOperandWords = 768;
 constexpr int kTileOperandF32 = 0, kTileOperandBF16 = 1, kTileOperandF16 = 2;
 void pack_tile_operand(const cd *m, int prec, uint32_t *out);
 // Tile arguments of n_sub blocks (positions ascending per block) on an
@@ -98,7 +99,9 @@ hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a,
                             hipStream_t st, int grid_cap, int tile_bits, int waves, void *psi2 = nullptr);
 // Host-side packing of the MFMA operands of a canonical k-qubit matrix.
 void pack_real_form_f32(const cd *m, int k, float *out);
-void pack_real_form_split(const cd *m, int k, bool fp16, uint16_t *hi, uint16_t *lo);
+// Split parts: part p = RNE(A' - parts before it), three for BF16, two for
+// FP16 (parts[2] then all zero), real_form_elems(k) each.
+void pack_real_form_split(const cd *m, int k, bool fp16, uint16_t *const *parts);
 size_t real_form_elems(int k);
 
 // ------------------------------------------------------------------ state init / copy

@@ -28,12 +28,16 @@
 //   * the grid is persistent over tiles; the next tile's HBM loads are
 //     issued before the current tile's MFMA work (register double buffer).
 //
-// Split precision (BF16 or FP16 hi + lo, FP32 accumulation): A' = Ah + Al,
-// X = Xh + Xl, and A'X ~ Ah Xh + Ah Xl + Al Xh (the dropped Al Xl term is
-// ~2^-16 relative for BF16, ~2^-22 for FP16).  X is split once, while staging
-// into LDS, in the v_mfma_f32_32x32x16 operand layout (8 consecutive K values
-// per lane).  FP16 tiles are scaled by a power of two chosen from the tile's
-// largest component (exact), so small amplitudes stay in FP16's normal range.
+// Split precision (16-bit parts, FP32 accumulation): the host writes A' as
+// three BF16 parts A' = A_0 + A_1 + A_2 (part p = RNE(A' - parts before it),
+// about FP32's 24 significand bits in all) or two FP16 parts; X = Xh + Xl,
+// and A'X ~ sum_p A_p Xh + A_0 Xl.  The dropped products (A_1 Xl and below:
+// ~2^-16 relative for BF16, ~2^-22 for FP16) vary with X, so they do not
+// add up coherently over blocks; the matrix itself is represented to about
+// 2^-24, which keeps the norm.  X is split once, while staging into LDS, in
+// the v_mfma_f32_32x32x16 operand layout (8 consecutive K values per lane).
+// FP16 tiles are scaled by a power of two chosen from the tile's largest
+// component (exact), so small amplitudes stay in FP16's normal range.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -235,9 +239,11 @@ struct SplitCfg {
 
 template <int K, int TCL, bool F16>
 __global__ void __launch_bounds__((SplitCfg<K, TCL>::THREADS))
-    k_mfma_split(float *__restrict__ psi, const uint16_t *__restrict__ Ah, const uint16_t *__restrict__ Al,
-                 const MfmaArgs args)
+    k_mfma_split(float *__restrict__ psi, const uint16_t *__restrict__ A0, const uint16_t *__restrict__ A1,
+                 const uint16_t *__restrict__ A2, const MfmaArgs args)
 {
+    constexpr int NP = F16 ? 2 : 3;  // parts of A'
+    const uint16_t *const parts[3] = {A0, A1, A2};
     using C = SplitCfg<K, TCL>;
     // B operand planes: [R/4 groups][TC columns][8 halves] for hi and lo
     __shared__ uint4 Bh[(C::R / 4) * C::TC];
@@ -250,14 +256,15 @@ __global__ void __launch_bounds__((SplitCfg<K, TCL>::THREADS))
     const int mslab = w / C::NB, nb = w % C::NB;
     const int half = lane >> 5, l32 = lane & 31;
 
-    // A' slab: for step i, lane holds A'[mslab*32 + l32][16 i + 8 half + e], e < 8
-    uint4 ah[C::NI], al[C::NI];
+    // A' slab: for step i, lane holds part p of A'[mslab*32 + l32][16 i + 8 half + e], e < 8
+    uint4 ap[NP][C::NI];
 #pragma unroll
-    for (int i = 0; i < C::NI; ++i) {
-        const size_t off = size_t(mslab * 32 + l32) * (2 * C::R) + 16 * i + 8 * half;
-        ah[i] = *reinterpret_cast<const uint4 *>(Ah + off);
-        al[i] = *reinterpret_cast<const uint4 *>(Al + off);
-    }
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int i = 0; i < C::NI; ++i) {
+            const size_t off = size_t(mslab * 32 + l32) * (2 * C::R) + 16 * i + 8 * half;
+            ap[p][i] = *reinterpret_cast<const uint4 *>(parts[p] + off);
+        }
 
     uint64_t g_lo;
     uint32_t l_lo;
@@ -335,23 +342,25 @@ __global__ void __launch_bounds__((SplitCfg<K, TCL>::THREADS))
             const uint4 bh = Bh[(2 * i + half) * C::TC + col];
             const uint4 bl = Bl[(2 * i + half) * C::TC + col];
             if (F16) {
-                f16x8 xa_h, xa_l, xb_h, xb_l;
-                __builtin_memcpy(&xa_h, &ah[i], 16);
-                __builtin_memcpy(&xa_l, &al[i], 16);
+                f16x8 xa[NP], xb_h, xb_l;
+#pragma unroll
+                for (int p = 0; p < NP; ++p) __builtin_memcpy(&xa[p], &ap[p][i], 16);
                 __builtin_memcpy(&xb_h, &bh, 16);
                 __builtin_memcpy(&xb_l, &bl, 16);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa_h, xb_h, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa_h, xb_l, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa_l, xb_h, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa[0], xb_h, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa[0], xb_l, acc, 0, 0, 0);
+#pragma unroll
+                for (int p = 1; p < NP; ++p) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa[p], xb_h, acc, 0, 0, 0);
             } else {
-                bf16x8 xa_h, xa_l, xb_h, xb_l;
-                __builtin_memcpy(&xa_h, &ah[i], 16);
-                __builtin_memcpy(&xa_l, &al[i], 16);
+                bf16x8 xa[NP], xb_h, xb_l;
+#pragma unroll
+                for (int p = 0; p < NP; ++p) __builtin_memcpy(&xa[p], &ap[p][i], 16);
                 __builtin_memcpy(&xb_h, &bh, 16);
                 __builtin_memcpy(&xb_l, &bl, 16);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa_h, xb_h, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa_h, xb_l, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa_l, xb_h, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[0], xb_h, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[0], xb_l, acc, 0, 0, 0);
+#pragma unroll
+                for (int p = 1; p < NP; ++p) acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(xa[p], xb_h, acc, 0, 0, 0);
             }
         }
 #pragma unroll
@@ -417,14 +426,13 @@ hipError_t f32_launch(const int *q, const float *d_a, float *psi, float *psi2, i
 }
 
 template <int K, int TCL, bool F16>
-hipError_t split_launch(const int *q, const uint16_t *hi, const uint16_t *lo, float *psi, int n, hipStream_t st,
-                        int cap)
+hipError_t split_launch(const int *q, const uint16_t *const *parts, float *psi, int n, hipStream_t st, int cap)
 {
     MfmaArgs a;
     if (fill_args(K, TCL, q, n, a)) return hipErrorInvalidValue;
     a.psi2 = nullptr;
     hipLaunchKernelGGL((k_mfma_split<K, TCL, F16>), dim3(grid_for(a.n_tiles, cap)),
-                       dim3(SplitCfg<K, TCL>::THREADS), 0, st, psi, hi, lo, a);
+                       dim3(SplitCfg<K, TCL>::THREADS), 0, st, psi, parts[0], parts[1], parts[2], a);
     return hipGetLastError();
 }
 
@@ -479,9 +487,10 @@ void pack_real_form_f32(const cd *m, int k, float *out)
         }
 }
 
-void pack_real_form_split(const cd *m, int k, bool fp16, uint16_t *hi, uint16_t *lo)
+void pack_real_form_split(const cd *m, int k, bool fp16, uint16_t *const *parts)
 {
     const int R = 1 << k, R2 = 2 * R;
+    const int np = fp16 ? 2 : 3;
     for (int i = 0; i < R; ++i)
         for (int j = 0; j < R; ++j) {
             const double ur = m[size_t(i) * R + j].real(), ui = m[size_t(i) * R + j].imag();
@@ -489,13 +498,19 @@ void pack_real_form_split(const cd *m, int k, bool fp16, uint16_t *hi, uint16_t 
             for (int s = 0; s < 2; ++s)
                 for (int t = 0; t < 2; ++t) {
                     const size_t o = size_t(2 * i + s) * R2 + 2 * j + t;
-                    const double x = v[s][t];
-                    if (fp16) {
-                        hi[o] = host_f2h(float(x));
-                        lo[o] = host_f2h(float(x - double(host_h2f(hi[o]))));
-                    } else {
-                        hi[o] = host_f2bf(float(x));
-                        lo[o] = host_f2bf(float(x - double(host_bf2f(hi[o]))));
+                    double x = v[s][t];  // part p = RNE(x - parts before it)
+                    for (int p = 0; p < 3; ++p) {
+                        if (p >= np) {
+                            parts[p][o] = 0;
+                            continue;
+                        }
+                        if (fp16) {
+                            parts[p][o] = host_f2h(float(x));
+                            x -= double(host_h2f(parts[p][o]));
+                        } else {
+                            parts[p][o] = host_f2bf(float(x));
+                            x -= double(host_bf2f(parts[p][o]));
+                        }
                     }
                 }
         }
@@ -516,16 +531,16 @@ hipError_t launch_mfma_f32(int k, const int *q, const float *d_a, void *psi, int
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_mfma_split(int k, bool fp16, const int *q, const uint16_t *d_ahi, const uint16_t *d_alo, void *psi,
-                             int n, hipStream_t st, int tcl, int cap)
+hipError_t launch_mfma_split(int k, bool fp16, const int *q, const uint16_t *const *d_parts, void *psi, int n,
+                             hipStream_t st, int tcl, int cap)
 {
     if (!mfma_supported(k, n)) return hipErrorInvalidValue;
     if (tcl > n - k) tcl = n - k;
     float *p = static_cast<float *>(psi);
 #define SV_SPLIT_CASE(KK, TT)                                                                       \
     if (k == KK && tcl == TT)                                                                       \
-        return fp16 ? split_launch<KK, TT, true>(q, d_ahi, d_alo, p, n, st, cap)                    \
-                    : split_launch<KK, TT, false>(q, d_ahi, d_alo, p, n, st, cap);
+        return fp16 ? split_launch<KK, TT, true>(q, d_parts, p, n, st, cap)                         \
+                    : split_launch<KK, TT, false>(q, d_parts, p, n, st, cap);
     SV_SPLIT_CASE(4, 5) SV_SPLIT_CASE(4, 6) SV_SPLIT_CASE(4, 7)
     SV_SPLIT_CASE(5, 5) SV_SPLIT_CASE(5, 6)
     SV_SPLIT_CASE(6, 5) SV_SPLIT_CASE(6, 6)

@@ -99,7 +99,8 @@ struct Launch {
     std::vector<cd> m;     // canonical matrix; tile paths: k matrices of 16 x 16
     int sub_pos[dev::kMaxTileSubBlocks][4] = {};  // tile paths: each block's positions
     size_t arena_off = 0;  // byte offset of device operands (other paths)
-    size_t arena_off2 = 0; // second operand (split lo part)
+    size_t arena_off2 = 0; // second and third operands (split parts 1 and 2)
+    size_t arena_off3 = 0;
 };
 
 // Pack the device operands of `launches` into `stage` (host) and return the
@@ -125,6 +126,10 @@ int enqueue(const std::vector<Launch> &launches, int dtype, void *psi, int n, co
 int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, const void *arena, hipStream_t st,
             void *psi2 = nullptr);
 
+// Install the autotuned cost tables and launch shapes saved in the tuning
+// cache file `path` for the architecture of `device` (see sv_autotune).
+int load_tuning(const char *path, int device, int *loaded);
+
 // Pauli sums: validation (terms, masks below bit n, finite coefficients),
 // and the device tables (terms grouped by x mask) laid out in host memory h
 // for a copy to device address d: their byte size, and the fill, which also
@@ -149,5 +154,7 @@ struct sv_state {
     sv::DevBuf arena;      // device operands (matrices, Pauli tables)
     sv::PinBuf stage;      // pinned staging of the operands
     hipEvent_t arena_free = nullptr;  // recorded after the last launch reading the arena
+    hipGraphExec_t graph_exec = nullptr;  // last instantiated launch graph (use_graph runs)
+    int64_t graph_launches = 0, graph_updates = 0;  // graph runs, and those that reused graph_exec
     sv::DevBuf grad;       // adjoint partials
 };

@@ -190,6 +190,12 @@ Tuning &tuning()
     return t;
 }
 
+int tile_pass_capacity()
+{
+    const Tuning &t = tuning();
+    return dev::tile_max_blocks(t.tile_bits, t.tile_waves);
+}
+
 Path choose_path(int dtype, int precision, int k, const int *q, int n)
 {
     if (dtype == SV_C128) return dev::reg_supported(dtype, k, q, n) ? PATH_REG : PATH_GENERIC;
@@ -245,6 +251,8 @@ size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage)
             total = align256(total + dev::real_form_elems(L.k) * 2);
             L.arena_off2 = total;
             total = align256(total + dev::real_form_elems(L.k) * 2);
+            L.arena_off3 = total;
+            total = align256(total + dev::real_form_elems(L.k) * 2);
             break;
         }
     }
@@ -280,11 +288,13 @@ size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage)
                 dev::pack_tile_operand(L.m.data() + 256 * sb, tile_operand_prec(L.path),
                                        reinterpret_cast<uint32_t *>(h + L.arena_off) + dev::kTileOperandWords * sb);
             break;
-        default:
-            dev::pack_real_form_split(L.m.data(), L.k, L.path == PATH_SPLIT_FP16,
-                                      reinterpret_cast<uint16_t *>(h + L.arena_off),
-                                      reinterpret_cast<uint16_t *>(h + L.arena_off2));
+        default: {
+            uint16_t *const parts[3] = {reinterpret_cast<uint16_t *>(h + L.arena_off),
+                                        reinterpret_cast<uint16_t *>(h + L.arena_off2),
+                                        reinterpret_cast<uint16_t *>(h + L.arena_off3)};
+            dev::pack_real_form_split(L.m.data(), L.k, L.path == PATH_SPLIT_FP16, parts);
             break;
+        }
         }
     }
     return total;
@@ -432,12 +442,14 @@ int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, cons
             e = dev::launch_mfma_f32(L.k, L.q, reinterpret_cast<const float *>(A + L.arena_off), psi, n, st,
                                      T.mfma_tc_log[L.k], T.mfma_grid_cap[L.k], psi2);
             break;
-        default:
-            e = dev::launch_mfma_split(L.k, L.path == PATH_SPLIT_FP16, L.q,
-                                       reinterpret_cast<const uint16_t *>(A + L.arena_off),
-                                       reinterpret_cast<const uint16_t *>(A + L.arena_off2), psi, n, st,
+        default: {
+            const uint16_t *const parts[3] = {reinterpret_cast<const uint16_t *>(A + L.arena_off),
+                                              reinterpret_cast<const uint16_t *>(A + L.arena_off2),
+                                              reinterpret_cast<const uint16_t *>(A + L.arena_off3)};
+            e = dev::launch_mfma_split(L.k, L.path == PATH_SPLIT_FP16, L.q, parts, psi, n, st,
                                        T.split_tc_log[L.k], T.mfma_grid_cap[L.k]);
             break;
+        }
         }
         if (e != hipSuccess) return fail(SV_ERR_HIP, "kernel launch (path %d, k=%d): %s", int(L.path), L.k, hipGetErrorString(e));
     }

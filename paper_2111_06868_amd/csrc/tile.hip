@@ -13,8 +13,9 @@
 // complex GEMM Y = U_s X with X viewed as 16 rows (the block's tile bits) x
 // 2^(TB-4) columns (the other tile bits): one MFMA chain per 32-column block,
 // the real form A' = [[Ur,-Ui],[Ui,Ur]] interleaved by (re, im) as the A
-// operand.  The A operands of all blocks of the pass, and their column
-// address tables, are staged into LDS once per workgroup next to the tile.
+// operand.  The operands of all blocks of the pass, expanded into each
+// lane's A' fragments, and their column address tables are staged into LDS
+// once per workgroup next to the tile.
 // B operands and results are addressed in LDS as row(j) XOR column(c) (bit
 // deposits, then an XOR swizzle against bank conflicts).  Each wave owns
 // whole columns, so blocks update the tile in place with one barrier between
@@ -43,7 +44,11 @@ typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 // FP16 (FP32 accumulation).
 constexpr int kPrecF32 = kTileOperandF32, kPrecBF16 = kTileOperandBF16, kPrecF16 = kTileOperandF16;
 
-constexpr int kOperandWords = 1024;  // LDS words of one block's A fragments: 64 lanes x 16
+// LDS words of one block's operand: the A' fragments of the 64 lanes, 24
+// words per lane (FP32: 16; split: 8 per part), expanded at staging so that
+// the block loop reads them as they are.
+constexpr int kLaneWords = 24;
+constexpr int kOperandWords = 64 * kLaneWords;
 
 // Tile of 2^TB amplitudes held by a workgroup of WAVES waves: 2^TB / 16
 // columns per 4-qubit block, in blocks of 32 split evenly over the waves.
@@ -230,17 +235,16 @@ struct TileShared {
     float red[WAVES];  // per-wave partial of the next tile's scale (FP16 passes)
 };
 
-// Stage the launch's blocks: the A fragments of every lane, expanded from the
-// compact operands (pack_tile_operand) into 16 consecutive words per lane,
-// and the column tables.  Lane (half, l32) takes row r = l32 of the real
-// form A' = [[Ur,-Ui],[Ui,Ur]] interleaved by (re, im): complex row
-// ci = r / 2, part ri = r % 2.
-//   FP32: word j = A'[r][2 j + half], i.e. Ur[ci][j] (ri == half), -Ui[ci][j]
-//   (ri = 0, half = 1) or Ui[ci][j] (ri = 1, half = 0).
-//   split: words 4 p + e (p = 0, 1 hi steps, 2, 3 lo steps; e = 0..3) hold
-//   the bf16 pair A'[r][16 i + 8 half + 2 e + {0, 1}] of step i = p & 1:
-//   (Ur, -Ui) for ri = 0, (Ui, Ur) for ri = 1, at complex column
-//   j = 8 i + 4 half + e.
+// Stage the launch's blocks: each lane's A' fragments, expanded from the
+// compact operands (pack_tile_operand) into kLaneWords consecutive words per
+// lane, and the column tables.  Lane (half, l32) takes row r = l32 of A' =
+// [[Ur,-Ui],[Ui,Ur]] interleaved by (re, im): complex row ci = r / 2, part
+// ri = r % 2.
+//   FP32: word j < 16 = A'[r][2 j + half], i.e. Ur[ci][j] (ri == half),
+//   -Ui[ci][j] (ri = 0, half = 1) or Ui[ci][j] (ri = 1, half = 0).
+//   split: word 8 p + 4 i + e (part p = 0..2, step i = 0, 1, e = 0..3) holds
+//   the 16-bit pair A'[r][16 i + 8 half + 2 e + {0, 1}] of part p: (Ur, -Ui)
+//   for ri = 0, (Ui, Ur) for ri = 1, at complex column j = 8 i + 4 half + e.
 template <int TB, int WAVES, int PREC>
 __device__ __forceinline__ void stage_blocks(TileShared<TB, WAVES> &sh, const uint32_t *A, const TileArgs &args,
                                              int tid)
@@ -250,12 +254,12 @@ __device__ __forceinline__ void stage_blocks(TileShared<TB, WAVES> &sh, const ui
     const int nsub = args.n_sub;
     for (int e = tid; e < nsub * kOperandWords; e += C::THREADS) {
         const int s = e / kOperandWords, r = e % kOperandWords;
-        const int lane = r / 16, wd = r % 16;
+        const int lane = r / kLaneWords, wd = r % kLaneWords;
         const int half = lane >> 5, l32 = lane & 31, ci = l32 >> 1, ri = l32 & 1;
-        const uint32_t *cop = A + s * kTileOperandWords;
+        const uint32_t *cop = A + size_t(s) * kTileOperandWords;
         uint32_t v;
         if (!SPLIT) {
-            v = cop[(ri == half ? 0 : 256) + ci * 16 + wd];
+            v = wd < 16 ? cop[(ri == half ? 0 : 256) + ci * 16 + wd] : 0u;
             if (ri == 0 && half == 1) v ^= 0x80000000u;
         } else {
             const int part = wd >> 3, i = (wd >> 2) & 1, e4 = wd & 3;
@@ -355,7 +359,8 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
     for (int q = 0; q < NBW; ++q)
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[q][v] = 0.f;
-    const vf4 *ap = reinterpret_cast<const vf4 *>(&sh.op[s][(half * 32 + l32) * 16]);  // staged fragments
+    const uint32_t *op = sh.op[s];
+    const vf4 *ap = reinterpret_cast<const vf4 *>(op + (half * 32 + l32) * kLaneWords);  // staged fragments
     if (!SPLIT) {
         float a[16];
 #pragma unroll
@@ -383,37 +388,41 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
                            acc[q][4 * g + 2 * e + 1]);
         return;
     }
-    // split: step i (K = 16 i .. 16 i + 15) uses hi fragment ap[i] and lo
-    // fragment ap[2 + i]; products Ah Xh + Ah Xl + Al Xh
-    H8 xh[2], xl[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const vf4 fh = ap[i], fl = ap[2 + i];
-        __builtin_memcpy(&xh[i], &fh, 16);
-        __builtin_memcpy(&xl[i], &fl, 16);
-    }
+    // split: step i (K = 16 i .. 16 i + 15) with the operand's parts A_p
+    // (BF16: three, FP16: two) and the tile values split as X_h + X_l:
+    // sum_p A_p X_h + A_0 X_l
+    constexpr int NP = PREC == kPrecBF16 ? 3 : 2;
+    auto fragment = [&](int p, int i) {
+        H8 h;
+        const vf4 f = ap[2 * p + i];
+        __builtin_memcpy(&h, &f, 16);
+        return h;
+    };
     if (args.tbit[s][0] == 0) {  // uniform: rows (t, t + 1) share a slot
 #pragma unroll
-        for (int q = 0; q < NBW; ++q) {
-            vf4 raw[4];  // rows 8 i + 2 k2 + {0, 1} (plus 4 half) at raw[2 i + k2]
+        for (int i = 0; i < 2; ++i) {
+            H8 xa[NP];
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                raw[k] = *reinterpret_cast<const vf4 *>(Xb + ((row_of(rb, 8 * (k >> 1) + 2 * (k & 1)) << 3) ^ lq[q]));
+            for (int p = 0; p < NP; ++p) xa[p] = fragment(p, i);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int q = 0; q < NBW; ++q) {
+                vf4 raw[2];  // rows 8 i + 2 k2 + {0, 1} (plus 4 half)
+#pragma unroll
+                for (int k2 = 0; k2 < 2; ++k2)
+                    raw[k2] = *reinterpret_cast<const vf4 *>(Xb + ((row_of(rb, 8 * i + 2 * k2) << 3) ^ lq[q]));
                 H2 ph[4], pl[4];
 #pragma unroll
                 for (int k2 = 0; k2 < 2; ++k2) {
-                    const vf4 r = raw[2 * i + k2];
-                    split_pair(r.x, r.y, ph[2 * k2], pl[2 * k2]);
-                    split_pair(r.z, r.w, ph[2 * k2 + 1], pl[2 * k2 + 1]);
+                    split_pair(raw[k2].x, raw[k2].y, ph[2 * k2], pl[2 * k2]);
+                    split_pair(raw[k2].z, raw[k2].w, ph[2 * k2 + 1], pl[2 * k2 + 1]);
                 }
                 H8 bh, bl;
                 __builtin_memcpy(&bh, ph, 16);
                 __builtin_memcpy(&bl, pl, 16);
-                acc[q] = mfma16(xh[i], bh, acc[q]);
-                acc[q] = mfma16(xh[i], bl, acc[q]);
-                acc[q] = mfma16(xl[i], bh, acc[q]);
+                acc[q] = mfma16(xa[0], bh, acc[q]);
+                acc[q] = mfma16(xa[0], bl, acc[q]);
+#pragma unroll
+                for (int p = 1; p < NP; ++p) acc[q] = mfma16(xa[p], bh, acc[q]);
             }
         }
         // rows 4 g + 2 half + {0, 1} are acc[4 g .. 4 g + 3]
@@ -425,31 +434,36 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
                         acc[q][4 * g + 3]);
     } else {  // column blocks (q, q + 1) share a slot
 #pragma unroll
-        for (int q = 0; q < NBW; q += 2) {
-            vf4 raw[8];  // row 8 i + t (plus 4 half) at raw[4 i + t]: (q, q + 1)
+        for (int i = 0; i < 2; ++i) {
+            H8 xa[NP];
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
-                raw[k] = *reinterpret_cast<const vf4 *>(Xb + ((row_of(rb, 8 * (k >> 2) + (k & 3)) << 3) ^ lq[q]));
+            for (int p = 0; p < NP; ++p) xa[p] = fragment(p, i);
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int q = 0; q < NBW; q += 2) {
+                vf4 raw[4];  // row 8 i + t (plus 4 half): column blocks (q, q + 1)
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+                    raw[t] = *reinterpret_cast<const vf4 *>(Xb + ((row_of(rb, 8 * i + t) << 3) ^ lq[q]));
                 H2 ph0[4], pl0[4], ph1[4], pl1[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const vf4 r = raw[4 * i + t];
-                    split_pair(r.x, r.y, ph0[t], pl0[t]);
-                    split_pair(r.z, r.w, ph1[t], pl1[t]);
+                    split_pair(raw[t].x, raw[t].y, ph0[t], pl0[t]);
+                    split_pair(raw[t].z, raw[t].w, ph1[t], pl1[t]);
                 }
                 H8 bh0, bl0, bh1, bl1;
                 __builtin_memcpy(&bh0, ph0, 16);
                 __builtin_memcpy(&bl0, pl0, 16);
                 __builtin_memcpy(&bh1, ph1, 16);
                 __builtin_memcpy(&bl1, pl1, 16);
-                acc[q] = mfma16(xh[i], bh0, acc[q]);
-                acc[q + 1] = mfma16(xh[i], bh1, acc[q + 1]);
-                acc[q] = mfma16(xh[i], bl0, acc[q]);
-                acc[q + 1] = mfma16(xh[i], bl1, acc[q + 1]);
-                acc[q] = mfma16(xl[i], bh0, acc[q]);
-                acc[q + 1] = mfma16(xl[i], bh1, acc[q + 1]);
+                acc[q] = mfma16(xa[0], bh0, acc[q]);
+                acc[q + 1] = mfma16(xa[0], bh1, acc[q + 1]);
+                acc[q] = mfma16(xa[0], bl0, acc[q]);
+                acc[q + 1] = mfma16(xa[0], bl1, acc[q + 1]);
+#pragma unroll
+                for (int p = 1; p < NP; ++p) {
+                    acc[q] = mfma16(xa[p], bh0, acc[q]);
+                    acc[q + 1] = mfma16(xa[p], bh1, acc[q + 1]);
+                }
             }
         }
 #pragma unroll
@@ -464,13 +478,15 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
 }
 
 // The tile loop of one workgroup: tiles T, T + step, .. below T_end of the
-// state at psi.  FP32 (kPrecF32): A = 32 x 32 FP32 real-form operands, back
-// to back.  Split (kPrecBF16, kPrecF16): A' = Ah + Al (16-bit from the host,
-// hi then lo); each B operand (8 consecutive K values = 4 complex rows of one
-// column) is split while it is read from LDS, and Ah Xh + Ah Xl + Al Xh run
-// on 32 x 32 x 16 MFMA with FP32 accumulation (the Al Xl term, ~2^-16
-// relative for BF16 and ~2^-22 for FP16, is dropped).  FP16 passes hold the
-// tile scaled (tile_scale).
+// state at psi.  A = the blocks' compact operands (pack_tile_operand), back to
+// back.  FP32 (kPrecF32): FP32 MFMA.  Split (kPrecBF16, kPrecF16): the host
+// splits U into 16-bit parts, U = A_0 + A_1 + A_2 for BF16 (8 more
+// significand bits each, about FP32's 24 in all) and A_0 + A_1 for FP16;
+// each B operand (8 consecutive K values = 4 complex rows of one column) is
+// split as X_h + X_l while it is read from LDS, and sum_p A_p X_h + A_0 X_l
+// run on 32 x 32 x 16 MFMA with FP32 accumulation (the dropped products are
+// about 2^-16 (BF16) and 2^-22 (FP16) relative and uncorrelated with X).
+// FP16 passes hold the tile scaled (tile_scale).
 template <int TB, int WAVES, int PREC>
 __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__restrict__ psi,
                                           const uint32_t *__restrict__ A, const TileArgs &args, uint64_t T,
@@ -665,6 +681,7 @@ static float bf2f(uint32_t h)
 
 void pack_tile_operand(const cd *m, int prec, uint32_t *out)
 {
+    std::memset(out, 0, sizeof(uint32_t) * kTileOperandWords);
     for (int r = 0; r < 16; ++r)
         for (int c = 0; c < 16; ++c) {
             const double re = m[r * 16 + c].real(), im = m[r * 16 + c].imag();
@@ -674,21 +691,25 @@ void pack_tile_operand(const cd *m, int prec, uint32_t *out)
                 std::memcpy(&out[256 + r * 16 + c], &fi, 4);
                 continue;
             }
-            // hi = RNE(x), lo = RNE(x - hi), as (re, im) halves of one word
-            uint32_t hr, hi, lr, li;
-            if (prec == kTileOperandF16) {
-                hr = f2h_rne(float(re));
-                hi = f2h_rne(float(im));
-                lr = f2h_rne(float(re - double(h2f(hr))));
-                li = f2h_rne(float(im - double(h2f(hi))));
-            } else {
-                hr = f2bf_rne(float(re));
-                hi = f2bf_rne(float(im));
-                lr = f2bf_rne(float(re - double(bf2f(hr))));
-                li = f2bf_rne(float(im - double(bf2f(hi))));
+            // part p = RNE(x - parts 0..p-1), as (re, im) halves of one word:
+            // three BF16 parts, two FP16 parts
+            const int parts = prec == kTileOperandF16 ? 2 : 3;
+            double xr = re, xi = im;
+            for (int p = 0; p < parts; ++p) {
+                uint32_t hr, hi;
+                if (prec == kTileOperandF16) {
+                    hr = f2h_rne(float(xr));
+                    hi = f2h_rne(float(xi));
+                    xr -= double(h2f(hr));
+                    xi -= double(h2f(hi));
+                } else {
+                    hr = f2bf_rne(float(xr));
+                    hi = f2bf_rne(float(xi));
+                    xr -= double(bf2f(hr));
+                    xi -= double(bf2f(hi));
+                }
+                out[256 * p + r * 16 + c] = hr | (hi << 16);
             }
-            out[r * 16 + c] = hr | (hi << 16);
-            out[256 + r * 16 + c] = lr | (li << 16);
         }
 }
 

@@ -17,7 +17,16 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+#include <string>
 #include <vector>
+
+#include <unistd.h>
 
 #include "runtime.h"
 
@@ -158,7 +167,143 @@ int time_tile(sv_state *s, Path path, int nsub, int reps, double *ms_out)
     return SV_OK;
 }
 
+// ------------------------------------------------------------ tuning cache
+// One text line per (architecture, n, precision):
+//   sv-tune-1 <arch> <n> <precision> <ms[1..6]> <tile[1..16]> <launch shapes>
+// with the launch shapes as reg_grid_cap[0..6] mfma_tc_log[0..6]
+// mfma_grid_cap[0..6] split_tc_log[0..6] k4_reg tile_grid_cap tile_bits
+// tile_waves.  Saving replaces the line of the same key.
+constexpr const char *kTuneTag = "sv-tune-1";
+std::mutex g_cache_mu;
+
+int device_arch(int device, std::string &arch)
+{
+    hipDeviceProp_t prop;
+    SV_HIP(hipGetDeviceProperties(&prop, device));
+    arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');  // drop feature flags (gfx950:sramecc+:xnack-)
+    if (colon != std::string::npos) arch.resize(colon);
+    return SV_OK;
+}
+
+std::string tuning_line(const std::string &arch, int n, int precision, const CostTable &c, const Tuning &t)
+{
+    std::ostringstream o;
+    o.precision(17);
+    o << kTuneTag << ' ' << arch << ' ' << n << ' ' << precision;
+    for (int k = 1; k <= SV_MAX_K; ++k) o << ' ' << c.ms[k];
+    for (int b = 1; b <= kTilePassMaxBlocks; ++b) o << ' ' << c.tile[b];
+    for (int k = 0; k <= SV_MAX_K; ++k) o << ' ' << t.reg_grid_cap[k];
+    for (int k = 0; k <= SV_MAX_K; ++k) o << ' ' << t.mfma_tc_log[k];
+    for (int k = 0; k <= SV_MAX_K; ++k) o << ' ' << t.mfma_grid_cap[k];
+    for (int k = 0; k <= SV_MAX_K; ++k) o << ' ' << t.split_tc_log[k];
+    o << ' ' << int(t.k4_reg) << ' ' << t.tile_grid_cap << ' ' << t.tile_bits << ' ' << t.tile_waves;
+    return o.str();
+}
+
+// Parse one line: false for other tags, architectures or malformed lines.
+bool parse_tuning_line(const std::string &line, const std::string &arch, int &n, int &precision, double *ms,
+                       double *tile, Tuning &t)
+{
+    std::istringstream in(line);
+    std::string tag, a;
+    if (!(in >> tag >> a >> n >> precision) || tag != kTuneTag || a != arch) return false;
+    if (n < 1 || n > SV_MAX_QUBITS_C64 || precision < SV_PREC_FP32 || precision > SV_PREC_FP64) return false;
+    ms[0] = tile[0] = 0;
+    for (int k = 1; k <= SV_MAX_K; ++k)
+        if (!(in >> ms[k]) || !(ms[k] > 0) || !std::isfinite(ms[k])) return false;
+    for (int b = 1; b <= kTilePassMaxBlocks; ++b)
+        if (!(in >> tile[b]) || !(tile[b] >= 0) || !std::isfinite(tile[b])) return false;
+    int k4 = 0;
+    for (int k = 0; k <= SV_MAX_K; ++k) in >> t.reg_grid_cap[k];
+    for (int k = 0; k <= SV_MAX_K; ++k) in >> t.mfma_tc_log[k];
+    for (int k = 0; k <= SV_MAX_K; ++k) in >> t.mfma_grid_cap[k];
+    for (int k = 0; k <= SV_MAX_K; ++k) in >> t.split_tc_log[k];
+    if (!(in >> k4 >> t.tile_grid_cap >> t.tile_bits >> t.tile_waves)) return false;
+    t.k4_reg = k4 != 0;
+    for (int k = 0; k <= SV_MAX_K; ++k)
+        if (t.reg_grid_cap[k] < 0 || t.mfma_grid_cap[k] < 0 || t.mfma_tc_log[k] < 5 || t.mfma_tc_log[k] > 7 ||
+            t.split_tc_log[k] < 5 || t.split_tc_log[k] > 7)
+            return false;
+    return t.tile_grid_cap >= 1 && dev::tile_shape_supported(t.tile_bits, t.tile_waves);
+}
+
+int save_tuning(const char *path, int device, int n, int precision)
+{
+    std::string arch;
+    if (int rc = device_arch(device, arch)) return rc;
+    bool found = false;
+    const CostTable c = lookup_costs(n, precision, &found);
+    if (!found) return fail(SV_ERR_ARG, "no cost table for n = %d, precision %d", n, precision);
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    std::vector<std::string> keep;
+    {
+        std::ifstream in(path);
+        std::string line;
+        while (std::getline(in, line)) {
+            std::istringstream f(line);
+            std::string tag, a;
+            int ln = -1, lp = -1;
+            f >> tag >> a >> ln >> lp;
+            if (tag == kTuneTag && a == arch && ln == n && lp == precision) continue;  // replaced below
+            if (!line.empty()) keep.push_back(line);
+        }
+    }
+    keep.push_back(tuning_line(arch, n, precision, c, tuning()));
+    const std::string tmp = std::string(path) + ".tmp" + std::to_string(::getpid());
+    {
+        std::ofstream out(tmp);
+        for (const auto &l : keep) out << l << '\n';
+        if (!out) return fail(SV_ERR_ARG, "cannot write the tuning cache %s", tmp.c_str());
+    }
+    if (std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return fail(SV_ERR_ARG, "cannot replace the tuning cache %s", path);
+    }
+    return SV_OK;
+}
+
 }  // namespace
+
+namespace sv {
+
+// Install the cost tables of `path` recorded for the device's architecture;
+// the launch shapes come from the last such line.  Returns the count.
+int load_tuning(const char *path, int device, int *loaded)
+{
+    std::string arch;
+    if (int rc = device_arch(device, arch)) return rc;
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    std::ifstream in(path);
+    if (!in) return fail(SV_ERR_ARG, "cannot read the tuning cache %s", path);
+    std::string line;
+    int count = 0;
+    Tuning last = tuning();
+    while (std::getline(in, line)) {
+        int n = 0, precision = 0;
+        double ms[SV_MAX_K + 1], tile[kTilePassMaxBlocks + 1];
+        Tuning t = tuning();
+        if (!parse_tuning_line(line, arch, n, precision, ms, tile, t)) continue;
+        store_costs(n, precision, ms, tile);
+        last = t;
+        ++count;
+    }
+    if (count) tuning() = last;
+    if (loaded) *loaded = count;
+    return SV_OK;
+}
+
+}  // namespace sv
+
+extern "C" int sv_tune_cache_load(const char *path, int *loaded)
+{
+    clear_error();
+    if (!path) path = std::getenv("SV_TUNE_CACHE");
+    if (!path || !*path) return fail(SV_ERR_ARG, "no path given and SV_TUNE_CACHE is not set");
+    int device = 0;
+    SV_HIP(hipGetDevice(&device));
+    return sv::load_tuning(path, device, loaded);
+}
 
 extern "C" int sv_autotune(sv_state *s, int precision, double *cost_ms)
 {
@@ -259,6 +404,8 @@ extern "C" int sv_autotune(sv_state *s, int precision, double *cost_ms)
     if (rc) return rc;
     tuning() = best_tuning;
     store_costs(s->n, precision, cost_ms, tiles ? tile_ms : nullptr);
+    if (const char *path = std::getenv("SV_TUNE_CACHE"))
+        if (*path) return save_tuning(path, s->device, s->n, precision);
     return SV_OK;
 }
 
@@ -282,6 +429,16 @@ extern "C" int sv_set_tile_shape(int tile_bits, int waves)
                     tile_bits, waves);
     tuning().tile_bits = tile_bits;
     tuning().tile_waves = waves;
+    return SV_OK;
+}
+
+extern "C" int sv_get_tile_shape(int *tile_bits, int *waves, int *max_blocks)
+{
+    clear_error();
+    const Tuning &t = tuning();
+    if (tile_bits) *tile_bits = t.tile_bits;
+    if (waves) *waves = t.tile_waves;
+    if (max_blocks) *max_blocks = dev::tile_max_blocks(t.tile_bits, t.tile_waves);
     return SV_OK;
 }
 

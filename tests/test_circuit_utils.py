@@ -1,6 +1,7 @@
-"""Host circuit utilities (paper, Circuit utilities: pop and simplify), checked
-against the oracle: light-cone cuts keep every expectation on the pinned
-qubits, simplification keeps the circuit's unitary (brute force), and the
+"""Host circuit utilities (paper, Circuit utilities: pop from either side and
+simplify), checked against the oracle: right light-cone cuts keep every
+expectation on the pinned qubits, left cuts keep the output for the pinned
+qubits' input with the others maximally mixed, compaction keeps expectations, simplification keeps the circuit's unitary (brute force), and the
 paper's CPHASE example cancels with its shuffled inverse only when matrix
 commutation is used."""
 import numpy as np
@@ -63,6 +64,70 @@ def test_lightcone_keeps_pinned_expectations(pinned):
             cone |= m
 
 
+@pytest.mark.parametrize("pinned", [(0,), (4,), (1, 5)])
+def test_left_pop_keeps_the_pinned_qubits_influence(pinned):
+    # walking from the start: the circuit equals K D with D acting on unpinned
+    # qubits only, so with the other qubits maximally mixed the output density
+    # matrix is the kept gates' alone (density-matrix oracle, any rho_pinned)
+    from oracle import density as dm
+    n = 6
+    gates = wc.grid_rqc(2, 3, 3, seed=14)
+    keep = sv.lightcone(to_binding(gates), n, pinned, direction="left")
+    assert 0 < len(keep) < len(gates)
+    kept = [gates[i] for i in keep]
+    rng = np.random.default_rng(5)
+    k = len(pinned)
+    a = rng.standard_normal((1 << k, 1 << k)) + 1j * rng.standard_normal((1 << k, 1 << k))
+    rp = a @ a.conj().T
+    rp /= np.trace(rp)
+    # rho_pinned on the pinned positions, I/2^(n-k) on the others
+    rho = np.zeros((1 << n, 1 << n), dtype=complex)
+    for r in range(1 << n):
+        for c in range(1 << n):
+            rest_r = [(r >> q) & 1 for q in range(n) if q not in pinned]
+            rest_c = [(c >> q) & 1 for q in range(n) if q not in pinned]
+            if rest_r != rest_c:
+                continue
+            ir = sum(((r >> q) & 1) << (k - 1 - j) for j, q in enumerate(pinned))
+            ic = sum(((c >> q) & 1) << (k - 1 - j) for j, q in enumerate(pinned))
+            rho[r, c] = rp[ir, ic] / (1 << (n - k))
+    full = dm.simulate(n, gates, rho=rho)
+    cut = dm.simulate(n, kept, rho=rho)
+    assert np.abs(full - cut).max() < 1e-13
+    # the kept set is the forward cone; the dropped gates never touch a pinned qubit
+    cone = sum(1 << q for q in pinned)
+    for i, g in enumerate(gates):
+        m = sum(1 << q for q in g.qubits)
+        assert (i in keep) == bool(m & cone)
+        if i in keep:
+            cone |= m
+        else:
+            assert not any(q in pinned for q in g.qubits)
+    # it is the right pop of the inverted circuit
+    inv = _inverse(gates)
+    assert sorted(len(gates) - 1 - i for i in sv.lightcone(inv, n, pinned)) == keep
+
+
+def test_compact_qubits_moves_the_cone_and_keeps_expectations():
+    n = 8
+    gates = wc.grid_rqc(2, 4, 2, seed=9)
+    bound = to_binding(gates)
+    keep = sv.lightcone(bound, n, (3,))
+    kept = [bound[i] for i in keep]
+    n_used, moved, pos = sv.compact_qubits(kept, n, (3,))
+    used = sorted({3} | {q for g in kept for q in g[1]})
+    assert n_used == len(used) < n
+    assert [pos[p] for p in used] == list(range(n_used))
+    assert all(pos[p] == -1 for p in range(n) if p not in used)
+    for g, h in zip(kept, moved):
+        assert h[0] == g[0] and h[1] == tuple(pos[q] for q in g[1]) and h[2:] == g[2:]
+    full = ref.simulate(n, gates, "0")
+    small = ref.run_matrices(ref.product_state(n_used, "0"), _to_oracle(moved))
+    for p in "XYZ":
+        assert abs(ref.expectation(full, [(1.0, ((3, p),))])
+                   - ref.expectation(small, [(1.0, ((pos[3], p),))])) < 1e-12
+
+
 def test_simplify_paper_cphase_example():
     # CPHASE(1) on every pair of 5 qubits plus its inverse in shuffled order
     n = 5
@@ -107,6 +172,10 @@ def test_utilities_refuse_bad_input():
         sv.lightcone([("H", (0,))], 2, (5,))
     with pytest.raises(sv.SvError):
         sv.simplify([("CX", (1, 1))], 2)
+    with pytest.raises(ValueError):
+        sv.lightcone([("H", (0,))], 2, (0,), direction="up")
+    with pytest.raises(sv.SvError):
+        sv.compact_qubits([("H", (2,))], 2, (0,))
 
 
 def test_utilities_edge_cases():
@@ -115,4 +184,7 @@ def test_utilities_edge_cases():
     assert sv.simplify([], 3) == []
     assert sv.lightcone(gates, 4, (0, 1, 2, 3)) == list(range(len(gates)))
     assert sv.lightcone(gates, 4, ()) == []
+    assert sv.lightcone(gates, 4, (0, 1, 2, 3), direction="left") == list(range(len(gates)))
+    assert sv.lightcone([], 3, (0,), direction="left") == []
+    assert sv.compact_qubits([], 3, (1,))[:2] == (1, [])
     assert sv.simplify([("I", (0,)), ("X", (1,)), ("X", (1,))], 2) == []

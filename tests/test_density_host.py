@@ -52,9 +52,64 @@ def test_channel_helpers_vs_oracle():
     pairs = [(sv.depolarizing((0, 2), 0.2), dm.depolarizing((0, 2), 0.2)),
              (sv.depolarizing((1,), 0.7), dm.depolarizing((1,), 0.7)),
              (sv.dephasing(2, 0.3, "X"), dm.dephasing(2, 0.3, "X")),
-             (sv.amplitude_damping(1, 0.45), dm.amplitude_damping(1, 0.45))]
+             (sv.amplitude_damping(1, 0.45), dm.amplitude_damping(1, 0.45)),
+             (sv.amplitude_damping(0, 0.3, 0.12), dm.amplitude_damping(0, 0.3, 0.12)),
+             (sv.depolarizing((2, 1, 0), 0.35), dm.depolarizing((2, 1, 0), 0.35))]
     for lib_op, or_op in pairs:
         assert np.abs(_lib_apply(rho, lib_op) - dm.apply_op(rho, or_op)).max() < 1e-14
+        # the constructors' own operators, applied by the oracle
+        assert np.abs(dm.apply_op(rho, {"qubits": lib_op.qubits, "left": list(lib_op.left)})
+                      - dm.apply_op(rho, or_op)).max() < 1e-14
+
+
+def _psd(dim, rank, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((dim, rank)) + 1j * rng.standard_normal((dim, rank))
+    s = a @ a.conj().T
+    return s / np.trace(s).real
+
+
+@pytest.mark.parametrize("qs,rank", [((0,), 4), ((2,), 1), ((1, 0), 16), ((0, 2), 5), ((2, 0, 1), 7)])
+def test_pauli_channel_and_its_kraus_form_vs_oracle(qs, rank):
+    rho = _rand_rho(3, 4)
+    s = _psd(4 ** len(qs), rank, 30 + rank)
+    want = dm.apply_op(rho, dm.pauli_channel(qs, s))
+    op = sv.pauli_channel(qs, s)
+    assert np.abs(_lib_apply(rho, op) - want).max() < 1e-14
+    kf = sv.kraus_form(op)
+    assert len(kf.left) == rank and kf.s is None
+    assert np.abs(dm.apply_op(rho, {"qubits": qs, "left": list(kf.left)}) - want).max() < 1e-13
+    assert np.abs(_lib_apply(rho, kf) - want).max() < 1e-13
+
+
+def test_local_channels_are_one_channel_per_qubit():
+    rho = _rand_rho(3, 5)
+    ops = sv.local_channels(sv.amplitude_damping, (0, 2, 1), [0.1, 0.2, 0.3], 0.05)
+    assert [o.qubits for o in ops] == [(0,), (2,), (1,)]
+    want = rho
+    for q, g in zip((0, 2, 1), (0.1, 0.2, 0.3)):
+        want = dm.apply_op(want, dm.amplitude_damping(q, g, 0.05))
+    got = rho
+    for o in ops:
+        got = _lib_apply(got, o)
+    assert np.abs(got - want).max() < 1e-14
+
+
+def test_channel_constructors_refuse_bad_input():
+    with pytest.raises(ValueError):
+        sv.depolarizing((0,), 1.5)
+    with pytest.raises(ValueError):
+        sv.depolarizing((0, 0), 0.1)
+    with pytest.raises(ValueError):
+        sv.amplitude_damping(0, 0.2, -0.1)
+    with pytest.raises(ValueError):
+        sv.dephasing(0, 0.2, "W")
+    not_herm = np.zeros((4, 4), dtype=complex)
+    not_herm[0, 1] = 1.0
+    with pytest.raises(ValueError):
+        sv.kraus_form(sv.pauli_channel((0,), not_herm))
+    with pytest.raises(ValueError):
+        sv.kraus_form(sv.pauli_channel((0,), np.diag([1.0, -0.5, 0, 0])))
 
 
 def test_malformed_super_ops_are_refused():

@@ -13,6 +13,7 @@ import pytest
 
 import paper_2111_06868_amd as sv
 from oracle import density as dm
+from oracle import ref
 from workloads import circuits as wc
 from helpers import to_binding
 
@@ -287,3 +288,94 @@ def test_trajectory_with_tile_passes_vs_oracle(prec):
     fe = 1 - abs(np.vdot(want_psi, psi)) ** 2 / (np.vdot(psi, psi).real * np.vdot(want_psi, want_psi).real)
     print("[parity] tiled trajectory n=%d prec=%d outcomes %s 1-F %.3e" % (n, prec, list(want), fe), flush=True)
     assert fe <= 1e-5
+
+
+def test_kraus_probabilities_beyond_16_operators():
+    # 40 operators on 3 qubits: three launches of the weights kernel
+    for dtype, tol in (("c64", 1e-6), ("c128", 1e-12)):
+        n = 12
+        psi, st = _random_state(n, dtype, seed=41)
+        K = wc.random_kraus_from_seed(140, 3, 40)
+        got = st.kraus_probabilities(sv.SuperOp((4, 0, 9), left=K))
+        want = np.array(dm.kraus_probabilities(psi, K, (4, 0, 9)))
+        rel = float(np.abs(got - want).max() / want.max())
+        print("[parity] Kraus weights %s, 40 operators: rel %.3e" % (dtype, rel), flush=True)
+        assert got.size == 40 and rel <= tol
+
+
+def _psd(dim, rank, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((dim, rank)) + 1j * rng.standard_normal((dim, rank))
+    s = a @ a.conj().T
+    return s / np.trace(s).real
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_sampled_general_pauli_channel_branches_vs_density_oracle(dtype):
+    """A GlobalPauliChannel with a general (rank-3, off-diagonal) s and a
+    generalized amplitude damping, sampled on pure states on the GPU: every
+    outcome branch, drawn with the middle of its interval and weighted by its
+    probability, sums to the density-matrix oracle's rho."""
+    n = 5
+    gates = wc.grid_rqc(1, 5, 4, seed=21)
+    # a trace-preserving s of rank 3: s_ij = sum_m c_mi conj(c_mj), c_m the Pauli
+    # coefficients of three random Kraus operators (sum_m K_m^dagger K_m = I)
+    P = [dm.pauli_string(a + b) for a in "IXYZ" for b in "IXYZ"]
+    C = np.array([[np.trace(Pi.conj().T @ K) / 4 for Pi in P] for K in wc.random_kraus_from_seed(22, 2, 3)])
+    s = C.T @ C.conj()
+    mid = len(gates) // 2
+    lib_ops = [sv.pauli_channel((3, 1), s, after=mid), sv.amplitude_damping(2, 0.3, 0.1, after=len(gates))]
+    or_ops = [dm.pauli_channel((3, 1), s, after=mid), dm.amplitude_damping(2, 0.3, 0.1, after=len(gates))]
+    want = dm.simulate(n, gates, or_ops)
+    bound = to_binding(gates)
+    acc = np.zeros_like(want)
+    count = [0]
+
+    def walk(psi, start, j, weight):
+        stop = lib_ops[j].after if j < len(lib_ops) else len(gates)
+        st = sv.State(n, dtype).write(psi)
+        st.run(bound[start:stop], max_k=4, rule=sv.RULE_ENHANCED)
+        if j == len(lib_ops):
+            v = st.read().astype(np.complex128)
+            acc[:] += weight * np.outer(v, v.conj())
+            count[0] += 1
+            return
+        p = st.kraus_probabilities(lib_ops[j])
+        total, run = p.sum(), 0.0
+        before = st.read()
+        for i, w in enumerate(p):
+            if w > 1e-12:
+                br = sv.State(n, dtype).write(before)
+                pick, _ = br.apply_kraus_sampled(lib_ops[j], (run + w / 2) / total)
+                assert pick == i
+                walk(br.read(), stop, j + 1, weight * w / total)
+            run += w
+
+    walk(ref.product_state(n, "0"), 0, 0, 1.0)
+    err = float(np.abs(acc - want).max())
+    print("[parity] sampled Pauli channel (general s) branches %s: %d branches, max |d rho| %.3e"
+          % (dtype, count[0], err), flush=True)
+    assert count[0] == 3 * 3
+    assert err <= (2e-6 if dtype == "c64" else 1e-12)
+
+
+@pytest.mark.parametrize("dtype,prec", [("c64", sv.PREC_FP32), ("c128", sv.PREC_FP64)])
+def test_dm_library_channels_vs_oracle(dtype, prec):
+    """Density matrices with the library-built channels of the Noisy gates
+    section: a general Pauli channel, its Kraus form, the generalized
+    amplitude damping, a three-qubit depolarizing channel and local dephasing."""
+    n = 4
+    gates = wc.grid_rqc(2, 2, 5, seed=31)
+    s = _psd(16, 5, 32)
+    a, b = 4, len(gates) - 3
+    lib_ops = [sv.pauli_channel((0, 3), s, after=a), sv.kraus_form(sv.pauli_channel((2, 1), s, after=a + 1)),
+               sv.amplitude_damping(1, 0.2, 0.05, after=b), sv.depolarizing((3, 0, 2), 0.15, after=b)]
+    lib_ops += sv.local_channels(sv.dephasing, (0, 1, 2), [0.1, 0.2, 0.3], "X", after=len(gates))
+    or_ops = [dm.pauli_channel((0, 3), s, after=a), dm.pauli_channel((2, 1), s, after=a + 1),
+              dm.amplitude_damping(1, 0.2, 0.05, after=b), dm.depolarizing((3, 0, 2), 0.15, after=b)]
+    or_ops += [dm.dephasing(q, p, "X", after=len(gates)) for q, p in ((0, 0.1), (1, 0.2), (2, 0.3))]
+    want = dm.simulate(n, gates, or_ops)
+    rho = sv.DensityMatrix(n, dtype).run(to_binding(gates), lib_ops, max_k=6, rule=sv.RULE_ENHANCED, precision=prec)
+    err = float(np.abs(rho.read() - want).max())
+    print("[parity] density matrix with library channels %s: max %.3e" % (dtype, err), flush=True)
+    assert err <= (1e-6 if dtype == "c64" else 1e-12)

@@ -1,18 +1,21 @@
-"""GPU parity at the full workload sizes, in the launch configuration the
-benchmark times (fused, enhanced rule, k <= 5, FP32 MFMA).
+"""GPU parity at the full workload sizes.
 
-* 30 qubits: a prefix of the 845-gate circuit against the CPU oracle on the
-  whole 2^30-amplitude state, then the whole circuit against a complex128 GPU
-  run (fidelity, norm, first 2^20 amplitudes).
+* 30 qubits, in the launch configuration the benchmark times (tiled rule,
+  k <= 4, split-BF16 tile passes) and in the enhanced FP32 configuration
+  (k <= 5): a 100-gate prefix of the 845-gate circuit against the CPU oracle on
+  the whole 2^30-amplitude state, then the whole circuit against a complex128
+  GPU run (fidelity, raw fidelity, norm, first 2^20 amplitudes).
 * 32 qubits: the 632-gate circuit with k = 4..6 blocks in FP32 and in split
   BF16 / FP16 against a complex128 GPU run.
 * 34 qubits: tile passes (split BF16, split FP16 and FP32) on a 12-qubit
   circuit spread over the positions, every amplitude of its support against
   the oracle.
-* 20-qubit ansatz: adjoint gradients against oracle parameter shift and
-  finite differences on sampled parameters.
+* 20-qubit ansatz: the energy and all 480 adjoint gradients against the
+  oracle's parameter-shift and finite-difference values (stored by
+  tests/golden/make_full_size_golden.py), plus a direct oracle check on a few.
 These need a large GPU (up to 128 GiB) and host memory (up to 24 GiB)."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -23,38 +26,72 @@ from workloads import circuits as wc
 from helpers import to_binding
 
 pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+# the benchmark's configuration and the enhanced FP32 one:
+# (rule, max_k, precision, bound on 1-F, on max-abs, on |norm - 1|)
+CONFIGS = {
+    "tiled_bf16_k4": (sv.RULE_TILED, 4, sv.PREC_SPLIT_BF16, 1e-5, 1e-6, 1e-6),
+    "enhanced_fp32_k5": (sv.RULE_ENHANCED, 5, sv.PREC_FP32, 1e-5, 1e-6, 1e-6),
+}
 
 
 def _fe_dev(a, b):
     return sv.fidelity_error(a, b)
 
 
-def test_30q_prefix_vs_oracle_full_state():
+@pytest.fixture(scope="module")
+def prefix30():
     n, gates = wc.config_circuit(1)
     prefix = gates[:100]
-    st = sv.State(n, "c64").run(to_binding(prefix), max_k=5, rule=sv.RULE_ENHANCED)
-    got = st.read()
-    del st
     want = ref.simulate(n, prefix, "0")
+    yield n, prefix, want
+
+
+@pytest.mark.parametrize("cfg", sorted(CONFIGS))
+def test_30q_prefix_vs_oracle_full_state(prefix30, cfg):
+    rule, k, prec, tol_fe, tol_abs, tol_norm = CONFIGS[cfg]
+    n, prefix, want = prefix30
+    st = sv.State(n, "c64").run(to_binding(prefix), max_k=k, rule=rule, precision=prec)
+    got = st.read()
+    nd = abs(st.norm2() - 1)
+    st.free()
+    del st
     fe = ref.fidelity_error(want, got)
-    ma = float(np.max(np.abs(want - got)))
-    print("[parity] 30q prefix(100 gates) fused k<=5 vs oracle: 1-F=%.3e max_abs=%.3e" % (fe, ma), flush=True)
-    assert fe <= 1e-5 and ma <= 1e-6
+    fr = ref.fidelity_error_raw(want, got)
+    ma = ref.max_abs(want, got)
+    print("[parity] 30q prefix(100 gates) %s vs oracle (all 2^30): 1-F=%.3e raw 1-F=%.3e max_abs=%.3e "
+          "|norm-1|=%.2e" % (cfg, fe, fr, ma, nd), flush=True)
+    assert fe <= tol_fe and fr <= tol_fe and ma <= tol_abs and nd <= tol_norm
 
 
-def test_30q_full_circuit_vs_c128():
+@pytest.fixture(scope="module")
+def ref30():
     n, gates = wc.config_circuit(1)
     g = sv.GateArray(to_binding(gates))
     refst = sv.State(n, "c128").run(g)
-    fused = sv.State(n, "c64").run(g, max_k=5, rule=sv.RULE_ENHANCED)
+    assert abs(refst.norm2() - 1) <= 1e-12
+    yield n, g, refst
+    refst.free()
+
+
+@pytest.mark.parametrize("cfg", sorted(CONFIGS))
+def test_30q_full_circuit_vs_c128(ref30, cfg):
+    rule, k, prec, tol_fe, tol_abs, tol_norm = CONFIGS[cfg]
+    n, g, refst = ref30
+    fused = sv.State(n, "c64").run(g, max_k=k, rule=rule, precision=prec)
     fe = _fe_dev(refst, fused)
+    ov = refst.inner(fused)
+    fr = 1.0 - abs(ov) ** 2  # raw: no renormalisation (the reference has norm 1 to 1e-12)
+    nd = abs(fused.norm2() - 1)
     a = refst.read(0, 1 << 20)
     b = fused.read(0, 1 << 20)
     ma = float(np.max(np.abs(a - b)))
-    print("[parity] 30q full fused k<=5 vs GPU c128: 1-F=%.3e max_abs(first 2^20)=%.3e norm-1=%.2e"
-          % (fe, ma, fused.norm2() - 1), flush=True)
-    assert fe <= 1e-5
-    assert abs(refst.norm2() - 1) <= 1e-12
+    fused.free()
+    print("[parity] 30q full %s vs GPU c128: 1-F=%.3e raw 1-F=%.3e max_abs(first 2^20)=%.3e |norm-1|=%.2e"
+          % (cfg, fe, fr, ma, nd), flush=True)
+    assert fe <= tol_fe and abs(fr) <= tol_fe
+    assert ma <= tol_abs and nd <= tol_norm
     # Porter-Thomas sanity (not a pin): 2^n sum |psi|^4 ~ 2 for a deep random circuit
     p = np.abs(a) ** 2
     assert 1.0 < (1 << 20) * np.sum(p ** 2) / np.sum(p) ** 2 < 3.0
@@ -139,27 +176,39 @@ def test_32q_blocks_vs_c128(ref32, precision):
     print("[parity] 32q fused k<=6 precision=%d vs GPU c128: 1-F=%.3e max_abs(first 2^20)=%.3e"
           % (precision, fe, ma), flush=True)
     assert fe <= 1e-5
+    assert ma <= 1e-6
 
 
-def test_20q_ansatz_adjoint_sampled():
+def _ansatz_golden():
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "ansatz20_gradients.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    e = float(rows[0][1])
+    ps = np.array([float(r[1]) for r in rows[1:]])
+    fd = np.array([float(r[2]) for r in rows[1:]])
+    assert [int(r[0]) for r in rows[1:]] == list(range(480))
+    return e, ps, fd
+
+
+def test_20q_ansatz_adjoint_all_gradients():
     n = 20
     gates, thetas = wc.ansatz_circuit(n, 12, seed=3)
     H = wc.ansatz_observable(n)
+    e_ref, ps, fd = _ansatz_golden()
     psi = sv.State(n, "c64").run(to_binding(gates), max_k=4, rule=sv.RULE_ENHANCED)
     e = psi.expectation(H)
-    e_ref = ref.energy(n, gates, thetas, H)
     scratch = sv.State(n, "c64")
     g = sv.backward(psi, scratch, to_binding(gates), H, len(thetas))
-    idx = list(range(0, 480, 40)) + [479, 21, 200]
-    ps = ref.param_shift_grad(n, gates, thetas, H, indices=idx)
-    fd = ref.fd_grad(n, gates, thetas, H, h=1e-3, indices=idx)
-    rel_ps = np.linalg.norm(g[idx] - ps) / np.linalg.norm(ps)
-    rel_fd = np.linalg.norm(g[idx] - fd) / np.linalg.norm(fd)
-    print("[parity] 20q ansatz E=%.8f (oracle %.8f); grad rel vs PS %.3e, vs FD(h=1e-3) %.3e"
-          % (e, e_ref, rel_ps, rel_fd), flush=True)
-    assert abs(e - e_ref) <= 1e-4
-    assert rel_ps <= 1e-4 and rel_fd <= 1e-4
+    rel_ps = np.linalg.norm(g - ps) / np.linalg.norm(ps)
+    rel_fd = np.linalg.norm(g - fd) / np.linalg.norm(fd)
     scale = 1e-2 * np.max(np.abs(ps))
-    assert np.all(np.abs(g[idx] - ps) <= 1e-4 * np.maximum(np.abs(ps), scale))
+    worst = float(np.max(np.abs(g - ps) / np.maximum(np.abs(ps), scale)))
+    print("[parity] 20q ansatz E=%.8f (oracle %.8f); all 480 gradients: rel vs PS %.3e, vs FD(h=1e-3) %.3e, "
+          "worst component %.3e" % (e, e_ref, rel_ps, rel_fd, worst), flush=True)
+    assert abs(e - e_ref) <= 1e-5
+    assert rel_ps <= 1e-4 and rel_fd <= 1e-4
+    assert worst <= 1e-4
+    # the stored values against the oracle itself on a few angles
+    idx = [0, 21, 239, 479]
+    assert np.abs(ref.param_shift_grad(n, gates, thetas, H, indices=idx) - ps[idx]).max() <= 1e-12
     # the adjoint pass consumed psi back to |0..0>
     assert abs(abs(psi.read(0, 1)[0]) - 1) <= 1e-4

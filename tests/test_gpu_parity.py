@@ -237,6 +237,35 @@ def test_graph_replay_matches_eager():
         sv.State(n, "c64").run(g[:10])  # eager work between replays
 
 
+@pytest.mark.parametrize("rule,prec", [(sv.RULE_ENHANCED, sv.PREC_FP32), (sv.RULE_TILED, sv.PREC_SPLIT_BF16)])
+def test_graph_kept_per_state_updates_with_new_angles(rule, prec):
+    """One state runs the ansatz with use_graph again and again: new angles
+    keep the launch structure, so the state's graph is updated in place, and
+    each run matches the eager run and the oracle; a different circuit
+    instantiates a new graph.  Eager work and synchronisation come between
+    the graph runs."""
+    n = 16
+    gates, thetas = wc.ansatz_circuit(n, 3, seed=8)
+    st = sv.State(n, "c64")
+    rng = np.random.default_rng(9)
+    for rep in range(4):
+        th = thetas if rep == 0 else rng.uniform(0, 2 * np.pi, len(thetas))
+        cur = wc.with_thetas(gates, th)
+        g = to_binding(cur)
+        st.set_basis(0).run(g, max_k=4, rule=rule, precision=prec, use_graph=True)
+        got = st.read()
+        eager = sv.State(n, "c64").run(g, max_k=4, rule=rule, precision=prec).read()
+        assert np.array_equal(got, eager), rep
+        assert ref.fidelity_error(ref.simulate(n, cur, "0"), got) <= FID_C64
+        sv.State(n, "c64").run(g[:10]).synchronize()  # eager work between graph runs
+    runs, reused = st.graph_stats()
+    assert runs == 4 and reused == 3
+    other = to_binding(wc.grid_rqc(4, 4, 4, seed=3))
+    got = st.set_basis(0).run(other, max_k=4, rule=rule, precision=prec, use_graph=True).read()
+    assert np.array_equal(got, sv.State(n, "c64").run(other, max_k=4, rule=rule, precision=prec).read())
+    assert st.graph_stats() == (5, 3)
+
+
 def test_stats_count_launches():
     n, gates = wc.config_circuit(0)
     sv.stats_reset()
@@ -515,3 +544,24 @@ def test_invalid_calls_leave_the_state_untouched():
     with pytest.raises(ValueError):
         st.expectation([(1.0, ((7, "Z"),))])
     assert np.array_equal(st.read(), before)
+
+
+def test_stream_probe_keeps_the_state():
+    """The streaming read + write probe (the achievable rate of a pass) moves
+    every amplitude back where it was: the state is bitwise unchanged, for
+    contiguous tiles, the top-position layout and a scattered one."""
+    n = 18
+    rng = np.random.default_rng(12)
+    psi = (rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)).astype(np.complex64)
+    st = sv.State(n, "c64").write(psi)
+    layouts = [range(14), list(range(4)) + list(range(8, 18)), [0, 1, 3, 4, 6, 7, 9, 10, 12, 13, 14, 15, 16, 17]]
+    for pos in layouts:
+        ms = st.stream_probe(pos, reps=3)
+        assert ms > 0
+        assert np.array_equal(st.read(), psi), pos
+    with pytest.raises(sv.SvValueError):
+        st.stream_probe(range(1, 15))  # position 0 missing
+    with pytest.raises(sv.SvValueError):
+        st.stream_probe(range(13))  # 13 positions
+    with pytest.raises(sv.SvValueError):
+        sv.State(13, "c64").stream_probe(range(13))
