@@ -119,60 +119,89 @@ uint64_t gate_mask(const sv_gate &g)
 // adds the fewest positions (the earliest on ties) while it stays within
 // max_union positions.  Members are listed in the order they are applied.
 // Every gate must act on at most max_union qubits.
-std::vector<std::vector<int>> frontier_groups(const sv_gate *g, const std::vector<int> &idx, int max_union)
-{
-    const int G = int(idx.size());
-    std::vector<uint64_t> mask(G);
-    std::vector<std::vector<int>> queue(64);
-    uint64_t used = 0;
-    for (int t = 0; t < G; ++t) {
-        mask[t] = gate_mask(g[idx[t]]);
-        used |= mask[t];
+class Frontier {
+  public:
+    Frontier(const sv_gate *g, const std::vector<int> &idx) : idx_(idx), mask_(idx.size()), queue_(64), head_(64, 0)
+    {
+        const int G = int(idx.size());
+        for (int t = 0; t < G; ++t) {
+            mask_[t] = gate_mask(g[idx[t]]);
+            used_ |= mask_[t];
+        }
+        for (uint64_t m = used_; m; m &= m - 1) queue_[__builtin_ctzll(m)].reserve(G);
+        for (int t = 0; t < G; ++t)
+            for (uint64_t m = mask_[t]; m; m &= m - 1) queue_[__builtin_ctzll(m)].push_back(t);
+        for (int t = 0; t < G; ++t) slot_[idx[t]] = t;
+        left_ = G;
     }
-    for (uint64_t m = used; m; m &= m - 1) queue[__builtin_ctzll(m)].reserve(G);
-    for (int t = 0; t < G; ++t)
-        for (uint64_t m = mask[t]; m; m &= m - 1) queue[__builtin_ctzll(m)].push_back(t);
-    std::vector<size_t> head(64, 0);
-    auto at_head = [&](int p) { return head[p] < queue[p].size() ? queue[p][head[p]] : -1; };
-    auto ready = [&](int t) {
-        for (uint64_t m = mask[t]; m; m &= m - 1)
-            if (at_head(__builtin_ctzll(m)) != t) return false;
-        return true;
-    };
-    std::vector<std::vector<int>> out;
-    int left = G;
-    while (left > 0) {
+    // The next group (gate indices of the caller's list), or false when none is left.
+    bool next(int max_union, std::vector<int> &grp)
+    {
+        grp.clear();
+        if (left_ <= 0) return false;
         uint64_t U = 0;
-        std::vector<int> grp;
         for (;;) {
             for (bool again = true; again;) {
                 again = false;
                 for (uint64_t m = U; m; m &= m - 1) {
                     const int p = __builtin_ctzll(m);
-                    for (int t; (t = at_head(p)) >= 0 && !(mask[t] & ~U) && ready(t);) {
-                        grp.push_back(idx[t]);
-                        --left;
-                        for (uint64_t mm = mask[t]; mm; mm &= mm - 1) ++head[__builtin_ctzll(mm)];
+                    for (int t; (t = at_head(p)) >= 0 && !(mask_[t] & ~U) && ready(t);) {
+                        grp.push_back(idx_[t]);
+                        --left_;
+                        for (uint64_t mm = mask_[t]; mm; mm &= mm - 1) ++head_[__builtin_ctzll(mm)];
                         again = true;
                     }
                 }
             }
             int best = -1, best_add = 65;
-            for (uint64_t pm = used; pm; pm &= pm - 1) {
+            for (uint64_t pm = used_; pm; pm &= pm - 1) {
                 const int t = at_head(__builtin_ctzll(pm));
-                if (t < 0 || !ready(t) || popc(U | mask[t]) > max_union) continue;
-                const int add = popc(mask[t] & ~U);
+                if (t < 0 || !ready(t) || popc(U | mask_[t]) > max_union) continue;
+                const int add = popc(mask_[t] & ~U);
                 if (add < best_add || (add == best_add && t < best)) {
                     best_add = add;
                     best = t;
                 }
             }
             if (best < 0) break;
-            U |= mask[best];
+            U |= mask_[best];
         }
-        if (grp.empty()) break;  // only reachable with a gate wider than max_union
-        out.push_back(std::move(grp));
+        return !grp.empty();  // empty only with a gate wider than max_union
     }
+    // Undo the taking of `gates`, which must be, on each of their qubits, the
+    // last ones taken there.
+    void give_back(const std::vector<int> &gates)
+    {
+        for (int gi : gates) {
+            const int t = slot_.at(gi);
+            for (uint64_t m = mask_[t]; m; m &= m - 1) --head_[__builtin_ctzll(m)];
+            ++left_;
+        }
+    }
+
+  private:
+    int at_head(int p) const { return head_[p] < queue_[p].size() ? queue_[p][head_[p]] : -1; }
+    bool ready(int t) const
+    {
+        for (uint64_t m = mask_[t]; m; m &= m - 1)
+            if (at_head(__builtin_ctzll(m)) != t) return false;
+        return true;
+    }
+    const std::vector<int> &idx_;
+    std::vector<uint64_t> mask_;
+    std::vector<std::vector<int>> queue_;
+    std::vector<size_t> head_;
+    std::map<int, int> slot_;  // caller's gate index -> position in idx
+    uint64_t used_ = 0;
+    int left_ = 0;
+};
+
+std::vector<std::vector<int>> frontier_groups(const sv_gate *g, const std::vector<int> &idx, int max_union)
+{
+    Frontier f(g, idx);
+    std::vector<std::vector<int>> out;
+    std::vector<int> grp;
+    while (f.next(max_union, grp)) out.push_back(grp);
     return out;
 }
 
@@ -187,6 +216,69 @@ void blocks_of_groups(const sv_gate *g, const std::vector<std::vector<int>> &gro
             if ((m >> p) & 1) B.q[B.k++] = p;
         B.members = grp;
         blocks.push_back(std::move(B));
+    }
+}
+
+uint64_t block_mask(const Block &b)
+{
+    uint64_t m = 0;
+    for (int j = 0; j < b.k; ++j) m |= uint64_t(1) << b.q[j];
+    return m;
+}
+
+// Every block of a tile pass costs a full sweep of the tile in LDS, however
+// few qubits it has.  A block is dissolved into a neighbour when the nearest
+// earlier block (or, failing that, the nearest later one) that shares a qubit
+// with it can take its qubits: the union stays within max_k qubits and the
+// neighbour's pass within max_union positions.  No block in between touches
+// its qubits, so its gates commute with everything they move past; they join
+// the neighbour's members after (earlier neighbour) or before (later
+// neighbour) its own.  Repeated until no block can go.
+void merge_small_blocks(const sv_gate *g, int max_k, int max_union, std::vector<Block> &blocks)
+{
+    (void)g;
+    auto pass_union = [&](int pass) {
+        uint64_t u = 0;
+        for (const auto &b : blocks)
+            if (b.pass == pass) u |= block_mask(b);
+        return u;
+    };
+    auto fits = [&](const Block &into, uint64_t add) {
+        const uint64_t m = block_mask(into) | add;
+        if (popc(m) > max_k) return false;
+        return into.pass < 0 || popc(pass_union(into.pass) | add) <= max_union;
+    };
+    auto set_mask = [](Block &b, uint64_t m) {
+        b.k = 0;
+        for (int p = 0; p < 64; ++p)
+            if ((m >> p) & 1) b.q[b.k++] = p;
+    };
+    for (bool changed = true; changed;) {
+        changed = false;
+        for (size_t i = 0; i < blocks.size() && !changed; ++i) {
+            const uint64_t m = block_mask(blocks[i]);
+            int before = -1, after = -1;
+            for (int j = int(i) - 1; j >= 0; --j)
+                if (block_mask(blocks[j]) & m) { before = j; break; }
+            for (size_t j = i + 1; j < blocks.size(); ++j)
+                if (block_mask(blocks[j]) & m) { after = int(j); break; }
+            int into = -1;
+            if (before >= 0 && fits(blocks[before], m)) into = before;
+            else if (after >= 0 && fits(blocks[after], m)) into = after;
+            if (into < 0) continue;
+            Block &t = blocks[into];
+            const uint64_t tm = block_mask(t) | m;
+            if (into < int(i)) {
+                t.members.insert(t.members.end(), blocks[i].members.begin(), blocks[i].members.end());
+            } else {
+                std::vector<int> mem = blocks[i].members;
+                mem.insert(mem.end(), t.members.begin(), t.members.end());
+                t.members.swap(mem);
+            }
+            set_mask(t, tm);
+            blocks.erase(blocks.begin() + i);
+            changed = true;
+        }
     }
 }
 
@@ -339,21 +431,20 @@ int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTa
         for (int gi = 0; gi < G; ++gi)
             if (g[gi].k > max_k)
                 return fail(SV_ERR_ARG, "gate %d acts on %d qubits, more than max_k=%d", gi, g[gi].k, max_k);
-        // Passes one at a time: the first union group of the gates left, cut
-        // into blocks; a pass keeps at most `cap` blocks (what one tile launch
-        // holds), and the gates of any further blocks return to the pool, so
-        // that the next pass can take them with its own gates.  They follow
-        // the kept blocks on every qubit they share, and the pool stays in
-        // circuit order.
+        // Passes one at a time: the next union group, cut into blocks; a pass
+        // keeps at most `cap` blocks (what one tile launch holds), and the
+        // gates of any further blocks go back to the frontier, so that the
+        // next pass can take them with its own gates.  They follow the kept
+        // blocks on every qubit they share, so on each of their qubits they
+        // are the last gates taken.
         const size_t cap = size_t(std::max(1, tile_pass_capacity()));
-        std::vector<int> pool(G);
-        for (int i = 0; i < G; ++i) pool[i] = i;
-        std::vector<char> taken(G, 0);
+        std::vector<int> all(G);
+        for (int i = 0; i < G; ++i) all[i] = i;
+        Frontier passes(g, all);
+        std::vector<int> pg;
         int pass = 0;
-        while (!pool.empty()) {
-            const auto groups = frontier_groups(g, pool, tile_union_limit());
-            if (groups.empty()) break;
-            const auto sub = frontier_groups(g, groups.front(), max_k);
+        while (passes.next(tile_union_limit(), pg)) {
+            const auto sub = frontier_groups(g, pg, max_k);
             const size_t e = std::min(sub.size(), cap);
             const size_t first = blocks.size();
             blocks_of_groups(g, std::vector<std::vector<int>>(sub.begin(), sub.begin() + e), blocks);
@@ -361,14 +452,11 @@ int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTa
                 for (size_t b = first; b < blocks.size(); ++b) blocks[b].pass = pass;
                 ++pass;
             }
-            for (size_t b = first; b < blocks.size(); ++b)
-                for (int gi : blocks[b].members) taken[gi] = 1;
-            std::vector<int> rest;
-            rest.reserve(pool.size());
-            for (int gi : pool)
-                if (!taken[gi]) rest.push_back(gi);
-            pool.swap(rest);
+            std::vector<int> back;
+            for (size_t c = e; c < sub.size(); ++c) back.insert(back.end(), sub[c].begin(), sub[c].end());
+            passes.give_back(back);
         }
+        merge_small_blocks(g, max_k, tile_union_limit(), blocks);
         return with_matrices ? block_matrices(g, blocks) : SV_OK;
     }
     std::vector<WBlock> wb;

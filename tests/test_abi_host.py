@@ -275,6 +275,21 @@ def test_tiled_plan_structure(cfg):
             passes.setdefault(b.tile_pass, set()).update(b.qubits)
         prev = b.tile_pass
     assert passes and all(len(u) <= 10 for u in passes.values())
+    # at most one launch's capacity of blocks per pass
+    cap = sv.get_tile_shape()[2]
+    per_pass = {}
+    for b in blocks:
+        if b.tile_pass >= 0:
+            per_pass[b.tile_pass] = per_pass.get(b.tile_pass, 0) + 1
+    assert max(per_pass.values()) <= cap
+    # no block of fewer than 4 qubits could have joined the nearest earlier
+    # block sharing a qubit with it
+    for i, b in enumerate(blocks):
+        m = set(b.qubits)
+        prev_b = next((blocks[j] for j in range(i - 1, -1, -1) if set(blocks[j].qubits) & m), None)
+        if prev_b is not None and len(m | set(prev_b.qubits)) <= 4:
+            u = passes.get(prev_b.tile_pass, set(prev_b.qubits))
+            assert prev_b.tile_pass >= 0 and len(u | m) > 10
     n_launch = len(passes) + sum(1 for b in blocks if b.tile_pass < 0)
     # far fewer state passes than blocks (30 q: 26 passes for 845 gates)
     assert n_launch <= len(blocks) // 3
