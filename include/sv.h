@@ -519,6 +519,21 @@ int sv_set_tile_shape(int tile_bits, int waves);
 /* The current launch shape of the tile passes and the number of blocks one
  * launch of it holds (pointers may be NULL). */
 int sv_get_tile_shape(int *tile_bits, int *waves, int *max_blocks);
+/* Layout of one tile pass of n_sub 4-qubit blocks (sub_pos: 4 ascending
+ * positions per block, n_sub rows) on an n-qubit complex64 state, as the
+ * tile passes lay it out for launch shape (tile_bits, waves) and tile
+ * arithmetic `precision` (SV_PREC_FP32, _SPLIT_BF16 or _SPLIT_FP16).  Host
+ * only: no device work.  tile_pos[b] (tile_bits entries) receives the state
+ * position of tile bit b: the blocks' union, then the lowest positions
+ * outside it, ascending.  lds_image[b] receives where tile bit b lands in
+ * the tile's LDS copy: tile index i sits at LDS index XOR of lds_image[b]
+ * over the set bits b of i, a permutation of 0 .. 2^tile_bits - 1 that keeps
+ * bit 0; it is chosen per pass so that the 16-byte LDS accesses of the
+ * blocks hit distinct banks.  *conflicts (may be NULL) receives the extra
+ * LDS cycles left by that choice (0 when it is free of bank conflicts; 0
+ * for FP32).  Errors: SV_ERR_ARG. */
+int sv_tile_placement(int n_sub, const int32_t *sub_pos, int n, int tile_bits, int waves, int precision,
+                      int32_t *tile_pos, uint32_t *lds_image, int32_t *conflicts);
 /* Position limit of the passes that SV_RULE_TILED plans (8..10; default 10,
  * or the SV_TILE_UNION environment variable at load time).  A larger union
  * holds more gates per pass but leaves shorter contiguous runs in HBM

@@ -861,6 +861,21 @@ def get_tile_shape():
     return b.value, w.value, m.value
 
 
+def tile_placement(blocks, n: int, tile_bits: int = 14, waves: int = 16, precision: int = PREC_SPLIT_BF16):
+    """Layout of one tile pass of 4-qubit blocks (sv_tile_placement): the
+    state position of each tile bit, the LDS image of each tile bit, and the
+    extra LDS cycles the model counts for that placement."""
+    pos = np.ascontiguousarray([sorted(int(q) for q in b) for b in blocks], dtype=np.int32).reshape(-1)
+    tp = np.zeros(tile_bits, dtype=np.int32)
+    img = np.zeros(tile_bits, dtype=np.uint32)
+    c = ctypes.c_int32()
+    N.check(N.lib().sv_tile_placement(len(blocks), pos.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(n),
+                                      int(tile_bits), int(waves), int(precision),
+                                      tp.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                      img.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), ctypes.byref(c)))
+    return tp, img, c.value
+
+
 def set_tile_union(max_positions: int) -> None:
     """Position limit (8..10) of the passes the tiled rule plans."""
     N.check(N.lib().sv_set_tile_union(int(max_positions)))

@@ -143,6 +143,7 @@ SIGNATURES = {
     "sv_set_tile_shape": (_I, [_I, _I]),
     "sv_set_tile_union": (_I, [_I]),
     "sv_get_tile_shape": (_I, [ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+    "sv_tile_placement": (_I, [_I, _I32P, _I, _I, _I, _I, _I32P, ctypes.POINTER(ctypes.c_uint32), _I32P]),
     "sv_project": (_I, [_P, _I, _I32P, _U64, _I, _D]),
     "sv_measure": (_I, [_P, _I, _I32P, _D, ctypes.POINTER(_U64), _D]),
     "sv_controlled_gate": (_I, [_GP, _I, _I32P, _GP, _D]),

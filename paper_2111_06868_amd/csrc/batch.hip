@@ -334,7 +334,8 @@ int build_schedule(sv_batch *b, const sv_batch_desc *d, int k)
                 std::memset(&tp, 0, sizeof tp);
                 tp.state_off = b->state_off[t];
                 tp.op_off = pool.size();
-                if (dev::make_tile_args(cnt, sub_pos, n, dev::kBatchTileBits, &tp.args) != hipSuccess)
+                if (dev::make_tile_args(cnt, sub_pos, n, dev::kBatchTileBits, dev::kBatchTileWaves, b->tile_prec,
+                                       &tp.args) != hipSuccess)
                     return fail(SV_ERR_ARG, "trajectory %d: tile pass layout", t);
                 pool.resize(pool.size() + size_t(cnt) * dev::kTileOperandWords);
                 for (int i = 0; i < cnt; ++i)

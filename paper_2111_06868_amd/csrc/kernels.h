@@ -53,6 +53,7 @@ struct TileArgs {
     int n_ext;
     int n_sub;                         // blocks in this launch
     int tbit[kMaxTileSubBlocks][4];    // per block: its tile bits, ascending
+    uint32_t swz[kMaxTileBits];        // LDS index of each tile bit (XOR-linear placement)
 };
 // Tile-pass operand of one 4-qubit block (canonical 16 x 16 matrix m), in
 // kTileOperandWords 32-bit words: FP32: Re U then Im U (16 x 16 floats each,
@@ -64,8 +65,13 @@ constexpr int kTileOperandWords = 768;
 constexpr int kTileOperandF32 = 0, kTileOperandBF16 = 1, kTileOperandF16 = 2;
 void pack_tile_operand(const cd *m, int prec, uint32_t *out);
 // Tile arguments of n_sub blocks (positions ascending per block) on an
-// n-qubit state with 2^tile_bits-amplitude tiles.
-hipError_t make_tile_args(int n_sub, const int (*sub_pos)[4], int n, int tile_bits, TileArgs *out);
+// n-qubit state with 2^tile_bits-amplitude tiles, for a launch of `waves`
+// waves in arithmetic `prec` (the LDS placement is chosen for them).
+hipError_t make_tile_args(int n_sub, const int (*sub_pos)[4], int n, int tile_bits, int waves, int prec,
+                          TileArgs *out);
+// Extra LDS cycles (bank conflicts) that the placement of `a` leaves in the
+// block loop of a split pass, by the bank model of make_tile_args; 0 for FP32.
+int tile_placement_conflicts(const TileArgs &a, int tile_bits, int waves, int prec);
 // Batched passes (shape (kBatchTileBits, kBatchTileWaves), at most
 // tile_max_blocks() blocks per pass, operands of precision `prec` as
 // launch_tile_pass): pass p of

@@ -24,6 +24,7 @@
 
 #include <cstring>
 #include <type_traits>
+#include <utility>
 
 #include "kernels.h"
 
@@ -43,6 +44,9 @@ typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 // Arithmetic of a tile pass: FP32 MFMA, or hi + lo split products in BF16 or
 // FP16 (FP32 accumulation).
 constexpr int kPrecF32 = kTileOperandF32, kPrecBF16 = kTileOperandBF16, kPrecF16 = kTileOperandF16;
+// Split BF16: parts of the tile values (2 or 3) and whether A_1 X_1 is formed
+constexpr int kBF16StateParts = 2;
+constexpr bool kBF16Cross = false;
 
 // LDS words of one block's operand: the A' fragments of the 64 lanes, 24
 // words per lane (FP32: 16; split: 8 per part), expanded at staging so that
@@ -84,12 +88,18 @@ __device__ __forceinline__ uint32_t deposit(uint32_t v, uint32_t mask)
     return r;
 }
 
-// LDS placement of tile index i: tile bits 5..8 are XORed into bits 1..4.
-// Bit 0 is kept, so the pair (2t, 2t + 1) stays one aligned 16-byte slot for
-// the HBM copies, and the map is linear over XOR: swz(a ^ b) = swz(a) ^
-// swz(b).  A block whose rows sit on the lowest tile bits would otherwise
-// read its 32 columns at a 128-byte stride, all in the same few banks.
-__device__ __forceinline__ uint32_t swz(uint32_t i) { return i ^ ((i >> 4) & 0x1Eu); }
+// LDS placement of tile index i: S(i), linear over XOR, with image a.swz[b]
+// of tile bit b (chosen per pass on the host, choose_swizzle).  S keeps bit 0,
+// so the pair (2t, 2t + 1) stays one aligned 16-byte slot for the HBM copies,
+// and permutes the tile's indices.
+__device__ __forceinline__ uint32_t swz(uint32_t i, const TileArgs &a)
+{
+    uint32_t r = 0;
+#pragma unroll
+    for (int b = 0; b < kMaxTileBits; ++b)
+        if ((i >> b) & 1) r ^= a.swz[b];
+    return r;
+}
 
 __device__ __forceinline__ uint64_t tile_base(uint64_t T, const TileArgs &a)
 {
@@ -128,15 +138,18 @@ struct TileCopy {
     static constexpr int kThreads = TileCfg<TB, WAVES>::THREADS;
     uint64_t g_lo;               // global offset of tile index 2 * tid
     uint64_t g_hi[kChunks];      // uniform: offset of tile index 2 * i * THREADS
-    uint32_t lds_slot;           // swizzled float4 slot of tile index 2 * tid
+    uint32_t lds_slot;           // float4 slot of tile index 2 * tid: S(2 tid) / 2
+    uint32_t lds_hi[kChunks];    // uniform: S(2 i THREADS) / 2, XORed onto lds_slot
 
     __device__ __forceinline__ void init(const TileArgs &args, int tid)
     {
         g_lo = global_off<TB>(uint32_t(2 * tid), args);
 #pragma unroll
-        for (int i = 0; i < kChunks; ++i) g_hi[i] = global_off<TB>(uint32_t(2 * i * kThreads), args);
-        // swz(2 f) / 2 = f ^ ((f >> 4) & 15); the chunk term only touches bits >= 8
-        lds_slot = uint32_t(tid) ^ ((uint32_t(tid) >> 4) & 15u);
+        for (int i = 0; i < kChunks; ++i) {
+            g_hi[i] = global_off<TB>(uint32_t(2 * i * kThreads), args);
+            lds_hi[i] = swz(uint32_t(2 * i * kThreads), args) >> 1;
+        }
+        lds_slot = swz(uint32_t(2 * tid), args) >> 1;
     }
     __device__ __forceinline__ void load(vf4 *buf, const float *psi, uint64_t base) const
     {
@@ -146,13 +159,13 @@ struct TileCopy {
     __device__ __forceinline__ void to_lds(vf4 *X4, const vf4 *buf) const
     {
 #pragma unroll
-        for (int i = 0; i < kChunks; ++i) X4[lds_slot + i * kThreads] = buf[i];
+        for (int i = 0; i < kChunks; ++i) X4[lds_slot ^ lds_hi[i]] = buf[i];
     }
     __device__ __forceinline__ void store(float *psi, uint64_t base, const vf4 *X4) const
     {
 #pragma unroll
         for (int i = 0; i < kChunks; ++i)
-            *reinterpret_cast<vf4 *>(psi + 2 * (base + g_lo + g_hi[i])) = X4[lds_slot + i * kThreads];
+            *reinterpret_cast<vf4 *>(psi + 2 * (base + g_lo + g_hi[i])) = X4[lds_slot ^ lds_hi[i]];
     }
     // Each slot: store the finished tile's value (at base_out) and put the
     // next tile's value in its place.  The thread owns its slots, so no
@@ -161,8 +174,8 @@ struct TileCopy {
     {
 #pragma unroll
         for (int i = 0; i < kChunks; ++i) {
-            const vf4 o = X4[lds_slot + i * kThreads];
-            X4[lds_slot + i * kThreads] = buf[i];
+            const vf4 o = X4[lds_slot ^ lds_hi[i]];
+            X4[lds_slot ^ lds_hi[i]] = buf[i];
             *reinterpret_cast<vf4 *>(psi + 2 * (base_out + g_lo + g_hi[i])) = o;
         }
     }
@@ -171,21 +184,21 @@ struct TileCopy {
     __device__ __forceinline__ void to_lds_scaled(vf4 *X4, const vf4 *buf, float scale) const
     {
 #pragma unroll
-        for (int i = 0; i < kChunks; ++i) X4[lds_slot + i * kThreads] = buf[i] * scale;
+        for (int i = 0; i < kChunks; ++i) X4[lds_slot ^ lds_hi[i]] = buf[i] * scale;
     }
     __device__ __forceinline__ void store_scaled(float *psi, uint64_t base, const vf4 *X4, float unscale) const
     {
 #pragma unroll
         for (int i = 0; i < kChunks; ++i)
-            *reinterpret_cast<vf4 *>(psi + 2 * (base + g_lo + g_hi[i])) = X4[lds_slot + i * kThreads] * unscale;
+            *reinterpret_cast<vf4 *>(psi + 2 * (base + g_lo + g_hi[i])) = X4[lds_slot ^ lds_hi[i]] * unscale;
     }
     __device__ __forceinline__ void swap_scaled(float *psi, uint64_t base_out, vf4 *X4, const vf4 *buf, float scale,
                                                 float unscale) const
     {
 #pragma unroll
         for (int i = 0; i < kChunks; ++i) {
-            const vf4 o = X4[lds_slot + i * kThreads];
-            X4[lds_slot + i * kThreads] = buf[i] * scale;
+            const vf4 o = X4[lds_slot ^ lds_hi[i]];
+            X4[lds_slot ^ lds_hi[i]] = buf[i] * scale;
             *reinterpret_cast<vf4 *>(psi + 2 * (base_out + g_lo + g_hi[i])) = o * unscale;
         }
     }
@@ -275,9 +288,10 @@ __device__ __forceinline__ void stage_blocks(TileShared<TB, WAVES> &sh, const ui
         const uint32_t cmask = ((1u << TB) - 1) & ~m;
         constexpr int NBW = C::NB_PER_WAVE;
         if (r < C::CBLOCKS)
-            sh.cq[s][r] = swz(deposit(SPLIT ? uint32_t((r / NBW) * 32 * NBW + r % NBW) : uint32_t(r * 32), cmask));
+            sh.cq[s][r] = swz(deposit(SPLIT ? uint32_t((r / NBW) * 32 * NBW + r % NBW) : uint32_t(r * 32), cmask),
+                              args);
         else
-            sh.cl[s][r - C::CBLOCKS] = swz(deposit(uint32_t(r - C::CBLOCKS) * (SPLIT ? NBW : 1), cmask));
+            sh.cl[s][r - C::CBLOCKS] = swz(deposit(uint32_t(r - C::CBLOCKS) * (SPLIT ? NBW : 1), cmask), args);
     }
 }
 
@@ -289,16 +303,20 @@ __device__ __forceinline__ void lds_st(char *Xb, uint32_t byte_off, float re, fl
     *reinterpret_cast<vf2 *>(Xb + byte_off) = v;
 }
 
-// hi = RNE(v), lo = RNE(v - hi) of one (re, im) pair, as packed 16-bit pairs
-// (H2 = bf16x2 or f16x2)
-template <typename H2>
-__device__ __forceinline__ void split_pair(float re, float im, H2 &hi, H2 &lo)
+// hi = RNE(v), lo = RNE(v - hi) and, with three parts, lo2 = RNE(v - hi - lo)
+// of one (re, im) pair, as packed 16-bit pairs (H2 = bf16x2 or f16x2).  The
+// differences are exact in FP32.
+template <int NS, typename H2>
+__device__ __forceinline__ void split_pair(float re, float im, H2 *parts)
 {
     vf2 v;
     v.x = re;
     v.y = im;
-    hi = __builtin_convertvector(v, H2);
-    lo = __builtin_convertvector(v - __builtin_convertvector(hi, vf2), H2);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) {
+        parts[j] = __builtin_convertvector(v, H2);
+        if (j + 1 < NS) v -= __builtin_convertvector(parts[j], vf2);
+    }
 }
 
 // One 32 x 32 x 16 product of 16-bit operands with FP32 accumulation.
@@ -344,7 +362,7 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
     char *Xb = reinterpret_cast<char *>(sh.X4);
     uint32_t rb[4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) rb[b] = swz(1u << args.tbit[s][b]);
+    for (int b = 0; b < 4; ++b) rb[b] = args.swz[args.tbit[s][b]];
     const uint32_t cl = sh.cl[s][l32];
     uint32_t lq[NBW], wq[NBW];  // lane byte terms of this lane's column in block q
 #pragma unroll
@@ -389,14 +407,28 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
         return;
     }
     // split: step i (K = 16 i .. 16 i + 15) with the operand's parts A_p
-    // (BF16: three, FP16: two) and the tile values split as X_h + X_l:
-    // sum_p A_p X_h + A_0 X_l
+    // (BF16: three, FP16: two) and the tile values split into NS parts X_s:
+    // every A_p X_0, every A_0 X_s, and A_1 X_1 when CROSS, the smaller terms
+    // accumulated first.
     constexpr int NP = PREC == kPrecBF16 ? 3 : 2;
+    constexpr int NS = PREC == kPrecBF16 ? kBF16StateParts : 2;
+    constexpr bool CROSS = PREC == kPrecBF16 && kBF16Cross;
     auto fragment = [&](int p, int i) {
         H8 h;
         const vf4 f = ap[2 * p + i];
         __builtin_memcpy(&h, &f, 16);
         return h;
+    };
+    auto products = [&](f32x16 c, const H8 *xa, const H8 *b) {
+#pragma unroll
+        for (int d = NP + NS - 2; d >= 0; --d)  // A_p X_s is about 2^(-8 (p + s)) of A X
+#pragma unroll
+            for (int sp = 0; sp < NS; ++sp) {
+                const int p = d - sp;
+                if (p >= 0 && p < NP && (sp == 0 || p == 0 || (CROSS && p == 1 && sp == 1)))
+                    c = mfma16(xa[p], b[sp], c);
+            }
+        return c;
     };
     if (args.tbit[s][0] == 0) {  // uniform: rows (t, t + 1) share a slot
 #pragma unroll
@@ -410,19 +442,19 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
 #pragma unroll
                 for (int k2 = 0; k2 < 2; ++k2)
                     raw[k2] = *reinterpret_cast<const vf4 *>(Xb + ((row_of(rb, 8 * i + 2 * k2) << 3) ^ lq[q]));
-                H2 ph[4], pl[4];
+                H2 pp[4][NS];
 #pragma unroll
                 for (int k2 = 0; k2 < 2; ++k2) {
-                    split_pair(raw[k2].x, raw[k2].y, ph[2 * k2], pl[2 * k2]);
-                    split_pair(raw[k2].z, raw[k2].w, ph[2 * k2 + 1], pl[2 * k2 + 1]);
+                    split_pair<NS>(raw[k2].x, raw[k2].y, pp[2 * k2]);
+                    split_pair<NS>(raw[k2].z, raw[k2].w, pp[2 * k2 + 1]);
                 }
-                H8 bh, bl;
-                __builtin_memcpy(&bh, ph, 16);
-                __builtin_memcpy(&bl, pl, 16);
-                acc[q] = mfma16(xa[0], bh, acc[q]);
-                acc[q] = mfma16(xa[0], bl, acc[q]);
+                H8 b[NS];
 #pragma unroll
-                for (int p = 1; p < NP; ++p) acc[q] = mfma16(xa[p], bh, acc[q]);
+                for (int sp = 0; sp < NS; ++sp) {
+                    H2 t[4] = {pp[0][sp], pp[1][sp], pp[2][sp], pp[3][sp]};
+                    __builtin_memcpy(&b[sp], t, 16);
+                }
+                acc[q] = products(acc[q], xa, b);
             }
         }
         // rows 4 g + 2 half + {0, 1} are acc[4 g .. 4 g + 3]
@@ -444,26 +476,22 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
                     raw[t] = *reinterpret_cast<const vf4 *>(Xb + ((row_of(rb, 8 * i + t) << 3) ^ lq[q]));
-                H2 ph0[4], pl0[4], ph1[4], pl1[4];
+                H2 p0[4][NS], p1[4][NS];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    split_pair(raw[t].x, raw[t].y, ph0[t], pl0[t]);
-                    split_pair(raw[t].z, raw[t].w, ph1[t], pl1[t]);
+                    split_pair<NS>(raw[t].x, raw[t].y, p0[t]);
+                    split_pair<NS>(raw[t].z, raw[t].w, p1[t]);
                 }
-                H8 bh0, bl0, bh1, bl1;
-                __builtin_memcpy(&bh0, ph0, 16);
-                __builtin_memcpy(&bl0, pl0, 16);
-                __builtin_memcpy(&bh1, ph1, 16);
-                __builtin_memcpy(&bl1, pl1, 16);
-                acc[q] = mfma16(xa[0], bh0, acc[q]);
-                acc[q + 1] = mfma16(xa[0], bh1, acc[q + 1]);
-                acc[q] = mfma16(xa[0], bl0, acc[q]);
-                acc[q + 1] = mfma16(xa[0], bl1, acc[q + 1]);
+                H8 b0[NS], b1[NS];
 #pragma unroll
-                for (int p = 1; p < NP; ++p) {
-                    acc[q] = mfma16(xa[p], bh0, acc[q]);
-                    acc[q + 1] = mfma16(xa[p], bh1, acc[q + 1]);
+                for (int sp = 0; sp < NS; ++sp) {
+                    H2 t0[4] = {p0[0][sp], p0[1][sp], p0[2][sp], p0[3][sp]};
+                    H2 t1[4] = {p1[0][sp], p1[1][sp], p1[2][sp], p1[3][sp]};
+                    __builtin_memcpy(&b0[sp], t0, 16);
+                    __builtin_memcpy(&b1[sp], t1, 16);
                 }
+                acc[q] = products(acc[q], xa, b0);
+                acc[q + 1] = products(acc[q + 1], xa, b1);
             }
         }
 #pragma unroll
@@ -713,7 +741,90 @@ void pack_tile_operand(const cd *m, int prec, uint32_t *out)
         }
 }
 
-hipError_t make_tile_args(int n_sub, const int (*sub_pos)[4], int n, int tile_bits, TileArgs *out)
+namespace {
+
+int gf2_rank(uint32_t *v, int k)
+{
+    int r = 0;
+    for (int bit = 0; bit < 32 && r < k; ++bit) {
+        int piv = -1;
+        for (int i = r; i < k; ++i)
+            if ((v[i] >> bit) & 1) {
+                piv = i;
+                break;
+            }
+        if (piv < 0) continue;
+        std::swap(v[r], v[piv]);
+        for (int i = 0; i < k; ++i)
+            if (i != r && ((v[i] >> bit) & 1)) v[i] ^= v[r];
+        ++r;
+    }
+    return r;
+}
+
+// Extra LDS cycles of the block loop's 16-byte accesses under the placement
+// `img` (image of each tile bit).  Such an access is served a group of lanes
+// at a time: 8 lanes over 32 four-byte banks or 16 lanes over 64.  The lanes
+// of a group hold columns whose indices differ in 3 (4) consecutive bits
+// starting at bit `lane_shift`, the rows being the same; the group is free of
+// conflicts when the LDS images of those column bits are independent on LDS
+// index bits 1..3 (1..4), and otherwise takes 2^(deficit) cycles.
+int placement_conflicts(const uint32_t *img, const TileArgs &a, int tile_bits, int lane_shift)
+{
+    int c = 0;
+    for (int s = 0; s < a.n_sub; ++s) {
+        uint32_t m = 0;
+        for (int b = 0; b < 4; ++b) m |= 1u << a.tbit[s][b];
+        int cpos[kMaxTileBits], nc = 0;
+        for (int b = 0; b < tile_bits; ++b)
+            if (!((m >> b) & 1)) cpos[nc++] = b;
+        uint32_t v3[3], v4[4];
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t x = img[cpos[lane_shift + j]] >> 1;
+            if (j < 3) v3[j] = x & 7u;
+            v4[j] = x & 15u;
+        }
+        c += (1 << (3 - gf2_rank(v3, 3))) - 1 + (1 << (4 - gf2_rank(v4, 4))) - 1;
+    }
+    return c;
+}
+
+// The pass's LDS placement S.  Candidates keep tile bits 0..3 in place and
+// add to the image of bit b >= 4 some of LDS bits 1..3 and, for b >= 5, bit 4:
+// S is then unit lower triangular over GF(2), a permutation of the tile's
+// indices that keeps bit 0.  The first candidate XORs bits 5..8 into bits
+// 1..4; while some block still has conflicts, seeded random candidates
+// (at most 512, the same sequence for every pass) are tried and the best kept.
+void choose_swizzle(TileArgs &a, int tile_bits, int lane_shift)
+{
+    uint32_t best[kMaxTileBits], cand[kMaxTileBits];
+    for (int b = 0; b < tile_bits; ++b) best[b] = (1u << b) ^ (((1u << b) >> 4) & 0x1Eu);
+    // FP32 passes (lane_shift < 0: 4-byte accesses, MFMA-bound) keep the first
+    int bc = lane_shift < 0 ? 0 : placement_conflicts(best, a, tile_bits, lane_shift);
+    uint64_t x = 0x9E3779B97F4A7C15ull;
+    for (int t = 0; t < 512 && bc > 0; ++t) {
+        for (int b = 0; b < tile_bits; ++b) {
+            cand[b] = 1u << b;
+            if (b < 4) continue;
+            x ^= x << 13;
+            x ^= x >> 7;
+            x ^= x << 17;
+            cand[b] |= uint32_t(x & 7u) << 1;
+            if (b >= 5) cand[b] |= uint32_t((x >> 3) & 1u) << 4;
+        }
+        const int c = placement_conflicts(cand, a, tile_bits, lane_shift);
+        if (c < bc) {
+            bc = c;
+            std::memcpy(best, cand, sizeof(uint32_t) * size_t(tile_bits));
+        }
+    }
+    for (int b = 0; b < kMaxTileBits; ++b) a.swz[b] = b < tile_bits ? best[b] : 0u;
+}
+
+}  // namespace
+
+hipError_t make_tile_args(int n_sub, const int (*sub_pos)[4], int n, int tile_bits, int waves, int prec,
+                          TileArgs *out)
 {
     const int kTileBits = tile_bits;
     if ((tile_bits != 13 && tile_bits != 14) || n_sub < 1 || n_sub > kMaxTileSubBlocks || n < kTileBits)
@@ -747,7 +858,18 @@ hipError_t make_tile_args(int n_sub, const int (*sub_pos)[4], int n, int tile_bi
             a.tbit[s][i] = t;
         }
     a.n_tiles = uint64_t(1) << (n - kTileBits);
+    // lanes of a wave take columns l32 NBW + q (split) or l32 (FP32), so a
+    // lane group's columns differ from column bit log2(NBW) (split) or 0 up
+    if (waves <= 0 || (1 << (tile_bits - 9)) % waves) return hipErrorInvalidValue;
+    const int nbw = (1 << (tile_bits - 9)) / waves;
+    choose_swizzle(a, tile_bits, prec == kTileOperandF32 ? -1 : __builtin_ctz(unsigned(nbw)));
     return hipSuccess;
+}
+
+int tile_placement_conflicts(const TileArgs &a, int tile_bits, int waves, int prec)
+{
+    if (prec == kTileOperandF32 || waves <= 0) return 0;
+    return placement_conflicts(a.swz, a, tile_bits, __builtin_ctz(unsigned((1 << (tile_bits - 9)) / waves)));
 }
 
 hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a, int prec, void *psi, int n,
@@ -757,7 +879,7 @@ hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a,
     if (!tile_shape_supported(tile_bits, waves)) return hipErrorInvalidValue;
     if (n_sub < 1 || n_sub > tile_max_blocks(tile_bits, waves)) return hipErrorInvalidValue;
     TileArgs a;
-    if (hipError_t e = make_tile_args(n_sub, sub_pos, n, tile_bits, &a)) return e;
+    if (hipError_t e = make_tile_args(n_sub, sub_pos, n, tile_bits, waves, prec, &a)) return e;
     float *p = static_cast<float *>(psi), *p2 = static_cast<float *>(psi2);
     if (tile_bits == 14)
         return waves == 16 ? tile_launch<14, 16>(a, d_a, prec, p, p2, st, grid_cap)

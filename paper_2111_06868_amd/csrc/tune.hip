@@ -442,6 +442,32 @@ extern "C" int sv_get_tile_shape(int *tile_bits, int *waves, int *max_blocks)
     return SV_OK;
 }
 
+extern "C" int sv_tile_placement(int n_sub, const int32_t *sub_pos, int n, int tile_bits, int waves, int precision,
+                                 int32_t *tile_pos, uint32_t *lds_image, int32_t *conflicts)
+{
+    clear_error();
+    if (!sub_pos || !tile_pos || !lds_image) return fail(SV_ERR_ARG, "NULL argument");
+    if (!dev::tile_shape_supported(tile_bits, waves))
+        return fail(SV_ERR_ARG, "tile shape (%d bits, %d waves) is not supported", tile_bits, waves);
+    if (precision < SV_PREC_FP32 || precision > SV_PREC_SPLIT_FP16)
+        return fail(SV_ERR_ARG, "precision %d has no tile passes", precision);
+    if (n_sub < 1 || n_sub > dev::kMaxTileSubBlocks) return fail(SV_ERR_ARG, "n_sub = %d", n_sub);
+    if (n < tile_bits || n > SV_MAX_QUBITS_C64) return fail(SV_ERR_ARG, "n = %d", n);
+    int pos[dev::kMaxTileSubBlocks][4];
+    for (int s = 0; s < n_sub; ++s)
+        for (int i = 0; i < 4; ++i) pos[s][i] = sub_pos[4 * s + i];
+    dev::TileArgs a;
+    if (dev::make_tile_args(n_sub, pos, n, tile_bits, waves, precision, &a) != hipSuccess)
+        return fail(SV_ERR_ARG, "blocks need 4 ascending positions below n, with a union of at most %d",
+                    dev::kMaxTileUnion);
+    for (int b = 0; b < tile_bits; ++b) {
+        tile_pos[b] = a.ubit[b];
+        lds_image[b] = a.swz[b];
+    }
+    if (conflicts) *conflicts = dev::tile_placement_conflicts(a, tile_bits, waves, precision);
+    return SV_OK;
+}
+
 extern "C" int sv_set_tile_union(int max_positions)
 {
     clear_error();
