@@ -30,10 +30,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBPS = 8000.0
 MFMA_FP32_PEAK_TFLOPS = 157.3
 FAMILY_NAMES = {1: "reg", 2: "generic", 3: "mfma_f32", 4: "split_bf16", 5: "split_fp16", 9: "tile",
-                10: "tile_bf16", 11: "tile_fp16"}
+                10: "tile_bf16", 11: "tile_fp16", 12: "tile_bf16x3"}
 KERNEL_SOURCES = {1: "apply.hip", 2: "apply.hip", 3: "mfma.hip", 4: "mfma.hip", 5: "mfma.hip", 9: "tile.hip",
-                  10: "tile.hip", 11: "tile.hip"}
-TILE_FAMILIES = (9, 10, 11)
+                  10: "tile.hip", 11: "tile.hip", 12: "tile.hip"}
+TILE_FAMILIES = (9, 10, 11, 12)
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 4}  # SV_PREC_* codes
 
 
 def log(*a):
@@ -214,7 +215,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--max-k", type=int, default=4)
     ap.add_argument("--rule", default="tiled", choices=["paper", "enhanced", "tiled", "auto"])
-    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp16", "bf16x3"])
     ap.add_argument("--config", type=int, default=1, choices=[1, 2])
     ap.add_argument("--workload", default="circuit", choices=["circuit", "gradient", "trajectories", "density", "jumps"],
                     help="circuit: the grid random circuit (default); gradient: 20-qubit ansatz "
@@ -258,7 +259,7 @@ def main():
     ga = sv.GateArray(bound)
     rule = {"enhanced": sv.RULE_ENHANCED, "paper": sv.RULE_PAPER, "tiled": sv.RULE_TILED,
             "auto": sv.RULE_AUTO}[args.rule]
-    prec = {"fp32": sv.PREC_FP32, "bf16": sv.PREC_SPLIT_BF16, "fp16": sv.PREC_SPLIT_FP16}[args.precision]
+    prec = PRECISIONS[args.precision]
     G = len(gates)
     pass_bytes = 16.0 * (1 << n)
 
@@ -345,8 +346,9 @@ def main():
     if dfam in TILE_FAMILIES:
         blocks_per_launch = tile_blocks[dfam] / dcnt
         roofline["blocks_per_launch"] = round(blocks_per_launch, 3)
-        # 8 * 16 flop per amplitude per 4-qubit block; split BF16 runs four products, FP16 three
-        flops = {10: 4, 11: 3}.get(dfam, 1) * 8.0 * 16 * (1 << n) * blocks_per_launch
+        # 8 * 16 flop per amplitude per 4-qubit block; split BF16 runs four products, FP16 three,
+        # BF16X3 six
+        flops = {10: 4, 11: 3, 12: 6}.get(dfam, 1) * 8.0 * 16 * (1 << n) * blocks_per_launch
         roofline["mfma_tflops"] = round(flops / (avg_ms * 1e-3) / 1e12, 2)
         if dfam == 9:
             roofline["mfma_frac"] = round(roofline["mfma_tflops"] / MFMA_FP32_PEAK_TFLOPS, 4)
@@ -449,7 +451,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "bf16": "bf16 split (3-part matrix, hi+lo state), f32 accumulate",
-                  "fp16": "f16 hi+lo split, f32 accumulate"}[args.precision],
+                  "fp16": "f16 hi+lo split, f32 accumulate",
+                  "bf16x3": "bf16 split (3-part matrix, 3-part state), f32 accumulate"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "grid random circuit %s, %d qubits, %d gates, complex64, fused k<=%d (%s rule, %s)"
                    % ({1: "5x6 depth 20 seed 1", 2: "4x8 depth 14 seed 2"}[args.config], n, G, args.max_k,
@@ -544,7 +547,7 @@ def bench_trajectories(args):
     from workloads import circuits as wc
     trajs = wc.trajectory_batch()
     # tile passes of the trajectories with >= 14 qubits, by --precision (default split BF16)
-    prec = {"fp32": sv.PREC_FP32, "bf16": sv.PREC_SPLIT_BF16, "fp16": sv.PREC_SPLIT_FP16}[args.precision]
+    prec = PRECISIONS[args.precision]
     circuits = [(t.n, [(g.name, g.qubits, g.params) for g in t.gates]) for t in trajs]
     if args.lightcone:
         circuits = [lightcone_circuit(n_, gs) for n_, gs in circuits]
@@ -561,7 +564,8 @@ def bench_trajectories(args):
                       "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t, 3),
                       "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
                       "dtype": {"fp32": "f32", "bf16": "f32; bf16 hi+lo split tile passes (n >= 14)",
-                                "fp16": "f32; f16 hi+lo split tile passes (n >= 14)"}[args.precision],
+                                "fp16": "f32; f16 hi+lo split tile passes (n >= 14)",
+                                "bf16x3": "f32; bf16 three-part split tile passes (n >= 14)"}[args.precision],
                       "data": "synthetic",
                       "config": {"workload": "512 ladder random circuits, n~U{10..22}, depth~U{8..24}, "
                                              "2q depolarizing p=1e-3 sampled per trajectory"
@@ -598,7 +602,7 @@ def bench_density(args):
     gates, channels = wc.noisy_grid_circuit(3, 5, 20, seed=7, p=1e-3)
     ga = sv.GateArray([(g.name, g.qubits, g.params) for g in gates])
     ops = [sv.depolarizing(q, p, after=a) for a, q, p in channels]
-    prec = {"fp32": sv.PREC_FP32, "bf16": sv.PREC_SPLIT_BF16}[args.precision]
+    prec = PRECISIONS[args.precision]
     rho = sv.DensityMatrix(n, "c64")
     Z0 = sv.pauli_sum([(1.0, ((0, "Z"),))])
     out = {}
@@ -620,7 +624,7 @@ def bench_density(args):
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / args.steps
     sv.stats_enable(False)
-    fam = 10 if prec == sv.PREC_SPLIT_BF16 else 9
+    fam = {sv.PREC_SPLIT_BF16: 10, sv.PREC_SPLIT_BF16X3: 12}.get(prec, 9)
     cnt = ms = 0
     for k in range(1, 17):
         c, m = sv.stats_query(FAMILY_NAMES[fam], k)
@@ -639,7 +643,8 @@ def bench_density(args):
                       "value": round(n_ops / t, 2), "unit": "operations/s", "n_gpus": 1, "steps": args.steps,
                       "warmup": args.warmup, "ms_per_step": round(1e3 * t, 3), "higher_is_better": True,
                       "scaling": "weak", "vs_baseline": None,
-                      "dtype": {"fp32": "f32", "bf16": "f32; bf16 hi+lo split tile passes"}[args.precision],
+                      "dtype": {"fp32": "f32", "bf16": "f32; bf16 hi+lo split tile passes",
+                                "bf16x3": "f32; bf16 three-part split tile passes"}[args.precision],
                       "data": "synthetic",
                       "config": {"workload": "3x5 grid random circuit, depth 20, 2q depolarizing p=1e-3 after "
                                              "every fSim; rho as a 30-qubit complex64 state",

@@ -64,6 +64,10 @@ extern "C" {
                              /* SV_ERR_ARG: tile passes rely on norm-preserving    */
                              /* blocks                                             */
 #define SV_PREC_FP64 3       /* complex128 state; FP64 arithmetic throughout       */
+#define SV_PREC_SPLIT_BF16X3 4 /* complex64 state; tile passes as BF16 MFMA with   */
+                               /* the tile values in three parts as well (six    */
+                               /* products, about FP32's accuracy); other blocks */
+                               /* as SV_PREC_FP32                                */
 
 /* fusion rules (sv_fuse) */
 #define SV_RULE_PAPER 0    /* the paper's compress() rule, reproduced exactly    */
@@ -248,7 +252,8 @@ int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int use_graph);
  * of 2^14 (or 2^13) amplitudes is staged in LDS once, every block of the
  * pass is applied to it (SV_PREC_FP32: FP32 MFMA; SV_PREC_SPLIT_BF16 /
  * SV_PREC_SPLIT_FP16: hi+lo 16-bit MFMA, the FP16 passes holding each tile
- * scaled by a power of two chosen from its largest magnitude), and the tile
+ * scaled by a power of two chosen from its largest magnitude;
+ * SV_PREC_SPLIT_BF16X3: BF16 MFMA on three parts of each value), and the tile
  * is written back, so a pass costs one read and one write of the state.  A
  * block left alone runs as a one-block pass where the cost table prices
  * that lower.
@@ -467,8 +472,9 @@ typedef struct sv_batch_desc {
     const int32_t *n_qubits;
     const int64_t *gate_offsets; /* n_traj + 1 entries */
     const sv_gate *gates;
-    int32_t precision;      /* SV_PREC_FP32 (0), SV_PREC_SPLIT_BF16 or
-                               SV_PREC_SPLIT_FP16: the arithmetic of the tile
+    int32_t precision;      /* SV_PREC_FP32 (0), SV_PREC_SPLIT_BF16,
+                               SV_PREC_SPLIT_FP16 or SV_PREC_SPLIT_BF16X3:
+                               the arithmetic of the tile
                                passes of trajectories with 14 or more qubits;
                                smaller ones and all reductions stay FP32 / FP64 */
 } sv_batch_desc;
@@ -522,7 +528,8 @@ int sv_get_tile_shape(int *tile_bits, int *waves, int *max_blocks);
 /* Layout of one tile pass of n_sub 4-qubit blocks (sub_pos: 4 ascending
  * positions per block, n_sub rows) on an n-qubit complex64 state, as the
  * tile passes lay it out for launch shape (tile_bits, waves) and tile
- * arithmetic `precision` (SV_PREC_FP32, _SPLIT_BF16 or _SPLIT_FP16).  Host
+ * arithmetic `precision` (SV_PREC_FP32, _SPLIT_BF16, _SPLIT_FP16 or
+ * _SPLIT_BF16X3).  Host
  * only: no device work.  tile_pos[b] (tile_bits entries) receives the state
  * position of tile bit b: the blocks' union, then the lowest positions
  * outside it, ascending.  lds_image[b] receives where tile bit b lands in

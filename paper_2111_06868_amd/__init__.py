@@ -21,6 +21,7 @@ import numpy as np
 
 from . import _native as N
 from ._native import (C64, C128, PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16, PREC_FP64,  # noqa: F401
+                      PREC_SPLIT_BF16X3,
                       RULE_PAPER, RULE_ENHANCED, RULE_NONE, RULE_TILED, RULE_AUTO, SV_MAX_K, GATE_KINDS, SvError,
                       SvValueError)
 
@@ -30,7 +31,7 @@ __all__ = ["State", "Plan", "fuse", "gate_matrix", "backward", "Energy", "Batch"
            "controlled",
            "pauli_sum", "autotune", "set_cost_table", "tune_cache_load", "set_tile_shape", "get_tile_shape", "set_tile_union", "TILE_SHAPES",
            "stats_enable", "stats_reset", "stats_query",
-           "C64", "C128", "PREC_FP32", "PREC_SPLIT_BF16", "PREC_SPLIT_FP16", "PREC_FP64",
+           "C64", "C128", "PREC_FP32", "PREC_SPLIT_BF16", "PREC_SPLIT_FP16", "PREC_FP64", "PREC_SPLIT_BF16X3",
            "RULE_PAPER", "RULE_ENHANCED", "RULE_NONE", "RULE_TILED", "RULE_AUTO", "SvError", "SvValueError"]
 
 
@@ -771,7 +772,7 @@ class Batch:
     (sv_batch_create / sv_batch_run)."""
 
     def __init__(self, circuits, max_k: int = -1, stream=None, precision: int = PREC_FP32):
-        """precision: PREC_FP32, PREC_SPLIT_BF16 or PREC_SPLIT_FP16 for the
+        """precision: PREC_FP32, PREC_SPLIT_BF16, PREC_SPLIT_FP16 or PREC_SPLIT_BF16X3 for the
         tile passes of the trajectories with 14 or more qubits."""
         torch = _torch()
         circuits = list(circuits)
@@ -890,7 +891,7 @@ def stats_reset() -> None:
 
 
 FAMILIES = {"reg": 1, "generic": 2, "mfma_f32": 3, "split_bf16": 4, "split_fp16": 5,
-            "reduce": 6, "adjoint": 7, "batch": 8, "tile": 9, "tile_bf16": 10, "tile_fp16": 11}
+            "reduce": 6, "adjoint": 7, "batch": 8, "tile": 9, "tile_bf16": 10, "tile_fp16": 11, "tile_bf16x3": 12}
 
 
 def stats_query(family: str, k: int):

@@ -27,6 +27,7 @@ PREC_FP32 = 0
 PREC_SPLIT_BF16 = 1
 PREC_SPLIT_FP16 = 2
 PREC_FP64 = 3
+PREC_SPLIT_BF16X3 = 4
 
 RULE_PAPER = 0
 RULE_ENHANCED = 1

@@ -57,7 +57,7 @@ int stream_after(hipStream_t to, hipStream_t from)
 
 int check_precision(const sv_state *s, int precision)
 {
-    if (precision < SV_PREC_FP32 || precision > SV_PREC_FP64) return fail(SV_ERR_ARG, "unknown precision %d", precision);
+    if (precision < SV_PREC_FP32 || precision > SV_PREC_SPLIT_BF16X3) return fail(SV_ERR_ARG, "unknown precision %d", precision);
     if ((s->dtype == SV_C128) != (precision == SV_PREC_FP64))
         return fail(SV_ERR_ARG, "precision %d does not match the state's amplitude type", precision);
     return SV_OK;

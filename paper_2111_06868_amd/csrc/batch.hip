@@ -260,8 +260,9 @@ int check_desc(const sv_batch_desc *d)
     if (d->n_traj < 1) return fail(SV_ERR_ARG, "batch needs at least one trajectory");
     if (!d->n_qubits || !d->gate_offsets) return fail(SV_ERR_ARG, "NULL batch arrays");
     if (d->max_k != -1 && (d->max_k < 1 || d->max_k > SV_MAX_K)) return fail(SV_ERR_ARG, "max_k %d", d->max_k);
-    if (d->precision != SV_PREC_FP32 && d->precision != SV_PREC_SPLIT_BF16 && d->precision != SV_PREC_SPLIT_FP16)
-        return fail(SV_ERR_ARG, "batch precision %d (FP32, split BF16 or split FP16)", d->precision);
+    if (d->precision != SV_PREC_FP32 && d->precision != SV_PREC_SPLIT_BF16 && d->precision != SV_PREC_SPLIT_FP16 &&
+        d->precision != SV_PREC_SPLIT_BF16X3)
+        return fail(SV_ERR_ARG, "batch precision %d (FP32, split BF16, split FP16 or split BF16X3)", d->precision);
     if (d->gate_offsets[0] != 0) return fail(SV_ERR_ARG, "gate_offsets[0] must be 0");
     for (int t = 0; t < d->n_traj; ++t) {
         const int n = d->n_qubits[t];
@@ -511,9 +512,7 @@ extern "C" int sv_batch_create(const sv_batch_desc *d, void *dev_buf, size_t byt
     if (reinterpret_cast<uintptr_t>(dev_buf) % 256) return fail(SV_ERR_ARG, "device buffer not 256-byte aligned");
     std::unique_ptr<sv_batch> b(new sv_batch);
     b->n_traj = d->n_traj;
-    b->tile_prec = d->precision == SV_PREC_SPLIT_BF16   ? dev::kTileOperandBF16
-                   : d->precision == SV_PREC_SPLIT_FP16 ? dev::kTileOperandF16
-                                                        : dev::kTileOperandF32;
+    b->tile_prec = tile_operand_prec(tile_path(d->precision));
     b->stream = static_cast<hipStream_t>(hip_stream);
     b->buf = static_cast<float2 *>(dev_buf);
     b->n_qubits.assign(d->n_qubits, d->n_qubits + d->n_traj);

@@ -57,12 +57,13 @@ struct TileArgs {
 };
 // Tile-pass operand of one 4-qubit block (canonical 16 x 16 matrix m), in
 // kTileOperandWords 32-bit words: FP32: Re U then Im U (16 x 16 floats each,
-// row-major); split BF16: three parts of U (part p = RNE(U - parts before
-// it)), split FP16: two parts, 256 words each, one word per entry holding
-// (re, im) as 16-bit values (re in the low half); unused words are 0.  The
-// precision codes are also the tile passes' arithmetic.
+// row-major); split BF16 (both BF16 codes): three parts of U (part p =
+// RNE(U - parts before it)), split FP16: two parts, 256 words each, one word
+// per entry holding (re, im) as 16-bit values (re in the low half); unused
+// words are 0.  The precision codes are also the tile passes' arithmetic:
+// kTileOperandBF16X3 splits the tile values into three parts instead of two.
 constexpr int kTileOperandWords = 768;
-constexpr int kTileOperandF32 = 0, kTileOperandBF16 = 1, kTileOperandF16 = 2;
+constexpr int kTileOperandF32 = 0, kTileOperandBF16 = 1, kTileOperandF16 = 2, kTileOperandBF16X3 = 3;
 void pack_tile_operand(const cd *m, int prec, uint32_t *out);
 // Tile arguments of n_sub blocks (positions ascending per block) on an
 // n-qubit state with 2^tile_bits-amplitude tiles, for a launch of `waves`

@@ -49,6 +49,7 @@ enum Family {
     FAM_TILE = 9,
     FAM_TILE_BF16 = 10,
     FAM_TILE_FP16 = 11,
+    FAM_TILE_BF16X3 = 12,
 };
 
 // Statistics class of a launch: 100 * family + k (k = block size, or the
@@ -72,10 +73,23 @@ class LaunchTimer {
 void timing_suspend(bool on);
 
 // Kernel paths for a block.
-enum Path { PATH_REG, PATH_GENERIC, PATH_MFMA32, PATH_SPLIT_BF16, PATH_SPLIT_FP16, PATH_TILE, PATH_TILE_BF16, PATH_TILE_FP16 };
+enum Path {
+    PATH_REG,
+    PATH_GENERIC,
+    PATH_MFMA32,
+    PATH_SPLIT_BF16,
+    PATH_SPLIT_FP16,
+    PATH_TILE,
+    PATH_TILE_BF16,
+    PATH_TILE_FP16,
+    PATH_TILE_BF16X3
+};
 
-// Tile passes: PATH_TILE, PATH_TILE_BF16, PATH_TILE_FP16.
-inline bool is_tile_path(int p) { return p == PATH_TILE || p == PATH_TILE_BF16 || p == PATH_TILE_FP16; }
+// Tile passes: PATH_TILE, PATH_TILE_BF16, PATH_TILE_FP16, PATH_TILE_BF16X3.
+inline bool is_tile_path(int p)
+{
+    return p == PATH_TILE || p == PATH_TILE_BF16 || p == PATH_TILE_FP16 || p == PATH_TILE_BF16X3;
+}
 
 struct Tuning {
     int reg_grid_cap[SV_MAX_K + 1];   // 0 = one thread per group

@@ -218,6 +218,7 @@ int path_family(Path p)
     case PATH_TILE: return FAM_TILE;
     case PATH_TILE_BF16: return FAM_TILE_BF16;
     case PATH_TILE_FP16: return FAM_TILE_FP16;
+    case PATH_TILE_BF16X3: return FAM_TILE_BF16X3;
     default: return FAM_SPLIT_FP16;
     }
 }
@@ -243,6 +244,7 @@ size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage)
         case PATH_TILE:
         case PATH_TILE_BF16:
         case PATH_TILE_FP16:
+        case PATH_TILE_BF16X3:
             L.arena_off = total;
             total = align256(total + size_t(L.k) * dev::kTileOperandWords * 4);
             break;
@@ -284,6 +286,7 @@ size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage)
         case PATH_TILE:
         case PATH_TILE_BF16:
         case PATH_TILE_FP16:
+        case PATH_TILE_BF16X3:
             for (int sb = 0; sb < L.k; ++sb)
                 dev::pack_tile_operand(L.m.data() + 256 * sb, tile_operand_prec(L.path),
                                        reinterpret_cast<uint32_t *>(h + L.arena_off) + dev::kTileOperandWords * sb);
@@ -340,13 +343,16 @@ Path tile_path(int precision)
 {
     if (precision == SV_PREC_SPLIT_BF16) return PATH_TILE_BF16;
     if (precision == SV_PREC_SPLIT_FP16) return PATH_TILE_FP16;
+    if (precision == SV_PREC_SPLIT_BF16X3) return PATH_TILE_BF16X3;
     return PATH_TILE;
 }
 
 int tile_operand_prec(int path)
 {
-    return path == PATH_TILE_BF16 ? dev::kTileOperandBF16 : path == PATH_TILE_FP16 ? dev::kTileOperandF16
-                                                                                    : dev::kTileOperandF32;
+    return path == PATH_TILE_BF16     ? dev::kTileOperandBF16
+           : path == PATH_TILE_FP16   ? dev::kTileOperandF16
+           : path == PATH_TILE_BF16X3 ? dev::kTileOperandBF16X3
+                                      : dev::kTileOperandF32;
 }
 
 void tile_pass_blocks(const Block *const *blocks, int count, int n, int (*sub_pos)[4], std::vector<cd> &mats)

@@ -43,10 +43,8 @@ typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
 // Arithmetic of a tile pass: FP32 MFMA, or hi + lo split products in BF16 or
 // FP16 (FP32 accumulation).
-constexpr int kPrecF32 = kTileOperandF32, kPrecBF16 = kTileOperandBF16, kPrecF16 = kTileOperandF16;
-// Split BF16: parts of the tile values (2 or 3) and whether A_1 X_1 is formed
-constexpr int kBF16StateParts = 2;
-constexpr bool kBF16Cross = false;
+constexpr int kPrecF32 = kTileOperandF32, kPrecBF16 = kTileOperandBF16, kPrecF16 = kTileOperandF16,
+              kPrecBF16X3 = kTileOperandBF16X3;
 
 // LDS words of one block's operand: the A' fragments of the 64 lanes, 24
 // words per lane (FP32: 16; split: 8 per part), expanded at staging so that
@@ -410,9 +408,9 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
     // (BF16: three, FP16: two) and the tile values split into NS parts X_s:
     // every A_p X_0, every A_0 X_s, and A_1 X_1 when CROSS, the smaller terms
     // accumulated first.
-    constexpr int NP = PREC == kPrecBF16 ? 3 : 2;
-    constexpr int NS = PREC == kPrecBF16 ? kBF16StateParts : 2;
-    constexpr bool CROSS = PREC == kPrecBF16 && kBF16Cross;
+    constexpr int NP = PREC == kPrecF16 ? 2 : 3;
+    constexpr int NS = PREC == kPrecBF16X3 ? 3 : 2;
+    constexpr bool CROSS = PREC == kPrecBF16X3;
     auto fragment = [&](int p, int i) {
         H8 h;
         const vf4 f = ap[2 * p + i];
@@ -507,14 +505,17 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
 
 // The tile loop of one workgroup: tiles T, T + step, .. below T_end of the
 // state at psi.  A = the blocks' compact operands (pack_tile_operand), back to
-// back.  FP32 (kPrecF32): FP32 MFMA.  Split (kPrecBF16, kPrecF16): the host
-// splits U into 16-bit parts, U = A_0 + A_1 + A_2 for BF16 (8 more
-// significand bits each, about FP32's 24 in all) and A_0 + A_1 for FP16;
-// each B operand (8 consecutive K values = 4 complex rows of one column) is
-// split as X_h + X_l while it is read from LDS, and sum_p A_p X_h + A_0 X_l
-// run on 32 x 32 x 16 MFMA with FP32 accumulation (the dropped products are
-// about 2^-16 (BF16) and 2^-22 (FP16) relative and uncorrelated with X).
-// FP16 passes hold the tile scaled (tile_scale).
+// back.  FP32 (kPrecF32): FP32 MFMA.  Split (kPrecBF16, kPrecBF16X3,
+// kPrecF16): the host splits U into 16-bit parts, U = A_0 + A_1 + A_2 for
+// BF16 (8 more significand bits each, about FP32's 24 in all) and A_0 + A_1
+// for FP16; each B operand (8 consecutive K values = 4 complex rows of one
+// column) is split while it is read from LDS, into X_0 + X_1 (kPrecBF16,
+// kPrecF16) or X_0 + X_1 + X_2 (kPrecBF16X3), and the products
+// sum_p A_p X_0 + sum_s A_0 X_s (plus A_1 X_1 for kPrecBF16X3) run on
+// 32 x 32 x 16 MFMA with FP32 accumulation.  The dropped terms are about
+// 2^-17 (BF16: the state's third part, A_1 X_1), 2^-22 (FP16) and 2^-25
+// (BF16X3) relative to the result.  FP16 passes hold the tile scaled
+// (tile_scale).
 template <int TB, int WAVES, int PREC>
 __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__restrict__ psi,
                                           const uint32_t *__restrict__ A, const TileArgs &args, uint64_t T,
@@ -645,6 +646,8 @@ hipError_t tile_launch(const TileArgs &a, const void *d_a, int prec, float *psi,
     const dim3 grid(unsigned(g), psi2 ? 2 : 1);
     if (prec == kPrecBF16)
         hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecBF16>), grid, dim3(64 * WAVES), 0, st, psi, A, a, psi2);
+    else if (prec == kPrecBF16X3)
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecBF16X3>), grid, dim3(64 * WAVES), 0, st, psi, A, a, psi2);
     else if (prec == kPrecF16)
         hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF16>), grid, dim3(64 * WAVES), 0, st, psi, A, a, psi2);
     else
@@ -875,7 +878,8 @@ int tile_placement_conflicts(const TileArgs &a, int tile_bits, int waves, int pr
 hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a, int prec, void *psi, int n,
                             hipStream_t st, int grid_cap, int tile_bits, int waves, void *psi2)
 {
-    if (prec != kTileOperandF32 && prec != kTileOperandBF16 && prec != kTileOperandF16) return hipErrorInvalidValue;
+    if (prec != kTileOperandF32 && prec != kTileOperandBF16 && prec != kTileOperandF16 && prec != kTileOperandBF16X3)
+        return hipErrorInvalidValue;
     if (!tile_shape_supported(tile_bits, waves)) return hipErrorInvalidValue;
     if (n_sub < 1 || n_sub > tile_max_blocks(tile_bits, waves)) return hipErrorInvalidValue;
     TileArgs a;
@@ -894,7 +898,10 @@ hipError_t launch_tile_batch(const TileUnit *units, int n_units, const TilePass 
     if (n_units <= 0) return hipSuccess;
     const dim3 grid{unsigned(n_units)}, block{unsigned(64 * kBatchTileWaves)};
     float *b = static_cast<float *>(buf);
-    if (prec == kPrecBF16)
+    if (prec == kPrecBF16X3)
+        hipLaunchKernelGGL((k_tile_batch<kBatchTileBits, kBatchTileWaves, kPrecBF16X3>), grid, block, 0, st, units,
+                           passes, pool, b);
+    else if (prec == kPrecBF16)
         hipLaunchKernelGGL((k_tile_batch<kBatchTileBits, kBatchTileWaves, kPrecBF16>), grid, block, 0, st, units, passes,
                            pool, b);
     else if (prec == kPrecF16)

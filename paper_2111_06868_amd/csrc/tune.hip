@@ -208,7 +208,7 @@ bool parse_tuning_line(const std::string &line, const std::string &arch, int &n,
     std::istringstream in(line);
     std::string tag, a;
     if (!(in >> tag >> a >> n >> precision) || tag != kTuneTag || a != arch) return false;
-    if (n < 1 || n > SV_MAX_QUBITS_C64 || precision < SV_PREC_FP32 || precision > SV_PREC_FP64) return false;
+    if (n < 1 || n > SV_MAX_QUBITS_C64 || precision < SV_PREC_FP32 || precision > SV_PREC_SPLIT_BF16X3) return false;
     ms[0] = tile[0] = 0;
     for (int k = 1; k <= SV_MAX_K; ++k)
         if (!(in >> ms[k]) || !(ms[k] > 0) || !std::isfinite(ms[k])) return false;
@@ -309,7 +309,7 @@ extern "C" int sv_autotune(sv_state *s, int precision, double *cost_ms)
 {
     clear_error();
     if (!s || !cost_ms) return fail(SV_ERR_ARG, "NULL argument");
-    if (precision < SV_PREC_FP32 || precision > SV_PREC_FP64) return fail(SV_ERR_ARG, "precision %d", precision);
+    if (precision < SV_PREC_FP32 || precision > SV_PREC_SPLIT_BF16X3) return fail(SV_ERR_ARG, "precision %d", precision);
     if ((s->dtype == SV_C128) != (precision == SV_PREC_FP64))
         return fail(SV_ERR_ARG, "precision %d does not match the state's amplitude type", precision);
     SV_HIP(hipSetDevice(s->device));
@@ -413,7 +413,7 @@ extern "C" int sv_set_cost_table(int n, int precision, const double *cost_ms)
 {
     clear_error();
     if (n < 1 || n > SV_MAX_QUBITS_C64) return fail(SV_ERR_ARG, "n = %d", n);
-    if (precision < SV_PREC_FP32 || precision > SV_PREC_FP64) return fail(SV_ERR_ARG, "precision %d", precision);
+    if (precision < SV_PREC_FP32 || precision > SV_PREC_SPLIT_BF16X3) return fail(SV_ERR_ARG, "precision %d", precision);
     if (!cost_ms) return fail(SV_ERR_ARG, "NULL cost table");
     for (int k = 1; k <= SV_MAX_K; ++k)
         if (!(cost_ms[k] > 0) || !std::isfinite(cost_ms[k])) return fail(SV_ERR_ARG, "cost_ms[%d] must be positive", k);
@@ -449,7 +449,7 @@ extern "C" int sv_tile_placement(int n_sub, const int32_t *sub_pos, int n, int t
     if (!sub_pos || !tile_pos || !lds_image) return fail(SV_ERR_ARG, "NULL argument");
     if (!dev::tile_shape_supported(tile_bits, waves))
         return fail(SV_ERR_ARG, "tile shape (%d bits, %d waves) is not supported", tile_bits, waves);
-    if (precision < SV_PREC_FP32 || precision > SV_PREC_SPLIT_FP16)
+    if (precision < SV_PREC_FP32 || precision > SV_PREC_SPLIT_BF16X3 || precision == SV_PREC_FP64)
         return fail(SV_ERR_ARG, "precision %d has no tile passes", precision);
     if (n_sub < 1 || n_sub > dev::kMaxTileSubBlocks) return fail(SV_ERR_ARG, "n_sub = %d", n_sub);
     if (n < tile_bits || n > SV_MAX_QUBITS_C64) return fail(SV_ERR_ARG, "n = %d", n);
@@ -457,14 +457,15 @@ extern "C" int sv_tile_placement(int n_sub, const int32_t *sub_pos, int n, int t
     for (int s = 0; s < n_sub; ++s)
         for (int i = 0; i < 4; ++i) pos[s][i] = sub_pos[4 * s + i];
     dev::TileArgs a;
-    if (dev::make_tile_args(n_sub, pos, n, tile_bits, waves, precision, &a) != hipSuccess)
+    const int tprec = tile_operand_prec(tile_path(precision));
+    if (dev::make_tile_args(n_sub, pos, n, tile_bits, waves, tprec, &a) != hipSuccess)
         return fail(SV_ERR_ARG, "blocks need 4 ascending positions below n, with a union of at most %d",
                     dev::kMaxTileUnion);
     for (int b = 0; b < tile_bits; ++b) {
         tile_pos[b] = a.ubit[b];
         lds_image[b] = a.swz[b];
     }
-    if (conflicts) *conflicts = dev::tile_placement_conflicts(a, tile_bits, waves, precision);
+    if (conflicts) *conflicts = dev::tile_placement_conflicts(a, tile_bits, waves, tprec);
     return SV_OK;
 }
 

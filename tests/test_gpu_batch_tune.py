@@ -58,7 +58,7 @@ def _golden_z0():
     return float(rows[0][1]), [int(r[1]) for r in rows[1:]], np.array([float(r[2]) for r in rows[1:]])
 
 
-@pytest.mark.parametrize("precision", [sv.PREC_FP32, sv.PREC_SPLIT_BF16, sv.PREC_SPLIT_FP16])
+@pytest.mark.parametrize("precision", [sv.PREC_FP32, sv.PREC_SPLIT_BF16, sv.PREC_SPLIT_FP16, sv.PREC_SPLIT_BF16X3])
 def test_batch_full_size_vs_oracle(precision):
     """The 512-trajectory noisy batch (n in 10..22, depth 8..24, p = 1e-3):
     <Z_0> of every trajectory against the oracle's (stored by
@@ -82,7 +82,7 @@ def test_batch_full_size_vs_oracle(precision):
         assert abs(ref.trajectory_z0(trajs[i]) - z_ref[i]) <= 1e-12
 
 
-@pytest.mark.parametrize("precision", [sv.PREC_FP32, sv.PREC_SPLIT_BF16, sv.PREC_FP64])
+@pytest.mark.parametrize("precision", [sv.PREC_FP32, sv.PREC_SPLIT_BF16, sv.PREC_FP64, sv.PREC_SPLIT_BF16X3])
 def test_autotune_then_fuse_auto(precision):
     n = 16
     dtype = "c128" if precision == sv.PREC_FP64 else "c64"

@@ -19,7 +19,8 @@ from helpers import to_binding
 
 pytestmark = pytest.mark.gpu
 
-TOL = {sv.PREC_FP32: 2e-5, sv.PREC_SPLIT_BF16: 2e-5, sv.PREC_FP64: 1e-12}
+TOL = {sv.PREC_FP32: 2e-5, sv.PREC_SPLIT_BF16: 2e-5, sv.PREC_SPLIT_BF16X3: 2e-5, sv.PREC_FP64: 1e-12}
+TILE_FAMILY = {sv.PREC_FP32: "tile", sv.PREC_SPLIT_BF16: "tile_bf16", sv.PREC_SPLIT_BF16X3: "tile_bf16x3"}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -80,7 +81,7 @@ def test_dm_small_vs_oracle(rule, max_k, dtype, prec):
     _check("dm n=%d %s prec=%d rule=%d k<=%d" % (n, dtype, prec, rule, max_k), want, rho.read(), TOL[prec])
 
 
-@pytest.mark.parametrize("prec", [sv.PREC_FP32, sv.PREC_SPLIT_BF16])
+@pytest.mark.parametrize("prec", [sv.PREC_FP32, sv.PREC_SPLIT_BF16, sv.PREC_SPLIT_BF16X3])
 def test_dm_tile_passes_vs_oracle(prec):
     # 7 qubits: rho is a 14-qubit state, so the tiled rule runs LDS tile passes
     n, gates, lib_ops, or_ops = _noisy_case(1, 7, 5, seed=5)
@@ -91,8 +92,7 @@ def test_dm_tile_passes_vs_oracle(prec):
                                          rule=sv.RULE_TILED)
     got = rho.read()
     sv.stats_enable(False)
-    fam = "tile" if prec == sv.PREC_FP32 else "tile_bf16"
-    tiles = sum(sv.stats_query(fam, k)[0] for k in range(1, 17))
+    tiles = sum(sv.stats_query(TILE_FAMILY[prec], k)[0] for k in range(1, 17))
     assert tiles > 0, "no tile pass ran"
     _check("dm n=%d tiled prec=%d (%d tile launches)" % (n, prec, tiles), want, got, TOL[prec])
 
@@ -253,22 +253,28 @@ def test_density_and_sampling_edge_cases():
         sv.State(2, "c64").project((0,), "1", renormalize=True)
 
 
-def test_dm_many_tiles_vs_oracle():
+@pytest.mark.parametrize("prec", [sv.PREC_SPLIT_BF16, sv.PREC_SPLIT_BF16X3])
+def test_dm_many_tiles_vs_oracle(prec):
     # 9 qubits: rho is an 18-qubit state, 16 tiles of 2^14 per tile pass
     n, gates, lib_ops, or_ops = _noisy_case(3, 3, 4, seed=31)
     want = dm.simulate(n, gates, or_ops)
     sv.stats_reset()
     sv.stats_enable(True)
-    rho = sv.DensityMatrix(n, "c64").run(to_binding(gates), lib_ops, max_k=4, precision=sv.PREC_SPLIT_BF16,
+    rho = sv.DensityMatrix(n, "c64").run(to_binding(gates), lib_ops, max_k=4, precision=prec,
                                          rule=sv.RULE_TILED)
     got = rho.read()
+    tr = rho.trace()
     sv.stats_enable(False)
-    tiles = sum(sv.stats_query("tile_bf16", k)[0] for k in range(1, 17))
+    tiles = sum(sv.stats_query(TILE_FAMILY[prec], k)[0] for k in range(1, 17))
     assert tiles > 0
-    _check("dm n=%d tiled bf16, 16 tiles (%d launches)" % (n, tiles), want, got, TOL[sv.PREC_SPLIT_BF16])
+    _check("dm n=%d tiled prec=%d, 16 tiles (%d launches), trace error %.2e" % (n, prec, tiles,
+                                                                             tr - np.trace(want).real),
+           want, got, TOL[prec])
+    if prec == sv.PREC_SPLIT_BF16X3:  # FP32's accuracy (the case holds non-trace-preserving operators)
+        assert abs(tr - np.trace(want).real) <= 1e-6 and float(np.abs(got - want).max()) <= 1e-7
 
 
-@pytest.mark.parametrize("prec", [sv.PREC_FP32, sv.PREC_SPLIT_BF16])
+@pytest.mark.parametrize("prec", [sv.PREC_FP32, sv.PREC_SPLIT_BF16, sv.PREC_SPLIT_BF16X3])
 def test_trajectory_with_tile_passes_vs_oracle(prec):
     # 16 qubits: the gate runs between channels go through tile passes
     n = 16
@@ -281,8 +287,7 @@ def test_trajectory_with_tile_passes_vs_oracle(prec):
     got = st.run_trajectory(to_binding(gates), lib_ops, u, max_k=4, precision=prec, rule=sv.RULE_TILED)
     psi = st.read().astype(np.complex128)
     sv.stats_enable(False)
-    fam = "tile" if prec == sv.PREC_FP32 else "tile_bf16"
-    assert sum(sv.stats_query(fam, k)[0] for k in range(1, 17)) > 0, "no tile pass ran"
+    assert sum(sv.stats_query(TILE_FAMILY[prec], k)[0] for k in range(1, 17)) > 0, "no tile pass ran"
     want_psi, want = dm.trajectory(n, gates, or_ops, u)
     assert [int(x) for x in got] == list(want) and any(x > 0 for x in want)
     fe = 1 - abs(np.vdot(want_psi, psi)) ** 2 / (np.vdot(psi, psi).real * np.vdot(want_psi, want_psi).real)

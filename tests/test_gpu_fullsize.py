@@ -1,8 +1,8 @@
 """GPU parity at the full workload sizes.
 
 * 30 qubits, in the launch configuration the benchmark times (tiled rule,
-  k <= 4, split-BF16 tile passes) and in the enhanced FP32 configuration
-  (k <= 5): a 100-gate prefix of the 845-gate circuit against the CPU oracle on
+  k <= 4, split-BF16 tile passes), with three-part split-BF16 tile passes,
+  and in the enhanced FP32 configuration (k <= 5): a 100-gate prefix of the 845-gate circuit against the CPU oracle on
   the whole 2^30-amplitude state, then the whole circuit against a complex128
   GPU run (fidelity, raw fidelity, norm, first 2^20 amplitudes).
 * 32 qubits: the 632-gate circuit with k = 4..6 blocks in FP32 and in split
@@ -33,6 +33,7 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 CONFIGS = {
     "tiled_bf16_k4": (sv.RULE_TILED, 4, sv.PREC_SPLIT_BF16, 1e-5, 1e-6, 1e-6),
     "enhanced_fp32_k5": (sv.RULE_ENHANCED, 5, sv.PREC_FP32, 1e-5, 1e-6, 1e-6),
+    "tiled_bf16x3_k4": (sv.RULE_TILED, 4, sv.PREC_SPLIT_BF16X3, 1e-10, 1e-8, 1e-6),
 }
 
 
@@ -62,7 +63,8 @@ def test_30q_prefix_vs_oracle_full_state(prefix30, cfg):
     ma = ref.max_abs(want, got)
     print("[parity] 30q prefix(100 gates) %s vs oracle (all 2^30): 1-F=%.3e raw 1-F=%.3e max_abs=%.3e "
           "|norm-1|=%.2e" % (cfg, fe, fr, ma, nd), flush=True)
-    assert fe <= tol_fe and fr <= tol_fe and ma <= tol_abs and nd <= tol_norm
+    # raw 1-F also carries the norm drift
+    assert fe <= tol_fe and fr <= tol_fe + 2 * tol_norm and ma <= tol_abs and nd <= tol_norm
 
 
 @pytest.fixture(scope="module")
@@ -90,7 +92,7 @@ def test_30q_full_circuit_vs_c128(ref30, cfg):
     fused.free()
     print("[parity] 30q full %s vs GPU c128: 1-F=%.3e raw 1-F=%.3e max_abs(first 2^20)=%.3e |norm-1|=%.2e"
           % (cfg, fe, fr, ma, nd), flush=True)
-    assert fe <= tol_fe and abs(fr) <= tol_fe
+    assert fe <= tol_fe and abs(fr) <= tol_fe + 2 * tol_norm
     assert ma <= tol_abs and nd <= tol_norm
     # Porter-Thomas sanity (not a pin): 2^n sum |psi|^4 ~ 2 for a deep random circuit
     p = np.abs(a) ** 2
@@ -123,6 +125,7 @@ def test_34q_high_positions_64bit_indexing():
 
 @pytest.mark.parametrize("precision,tol_fe,tol_abs,tol_norm", [
     (sv.PREC_SPLIT_BF16, 1e-7, 5e-5, 1e-4),
+    (sv.PREC_SPLIT_BF16X3, 1e-10, 1e-6, 1e-5),
     (sv.PREC_SPLIT_FP16, 1e-10, 1e-6, 1e-5),
     (sv.PREC_FP32, 1e-10, 1e-6, 1e-5),
 ])

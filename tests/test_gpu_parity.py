@@ -380,11 +380,11 @@ def test_tiled_passes_split_bf16(n):
 
 
 _TILE_PREC = {"fp32": (sv.PREC_FP32, "tile"), "bf16": (sv.PREC_SPLIT_BF16, "tile_bf16"),
-              "fp16": (sv.PREC_SPLIT_FP16, "tile_fp16")}
+              "fp16": (sv.PREC_SPLIT_FP16, "tile_fp16"), "bf16x3": (sv.PREC_SPLIT_BF16X3, "tile_bf16x3")}
 
 
 @pytest.mark.parametrize("shape", [(14, 8), (14, 16), (13, 4), (13, 8)])
-@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16", "bf16x3"])
 @pytest.mark.parametrize("n", [14, 16])
 def test_tiled_passes_every_shape(shape, precision, n):
     """Each tile launch shape (tile bits, waves per workgroup) against the oracle."""
@@ -407,10 +407,12 @@ def test_tiled_passes_every_shape(shape, precision, n):
     assert fe <= FID_C64
     if precision != "bf16":
         assert ma <= 1e-5
+    if precision == "bf16x3":  # FP32's accuracy
+        assert fe <= 1e-10 and ma <= 1e-6
 
 
 @pytest.mark.parametrize("union", [8, 9, 10])
-@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16", "bf16x3"])
 def test_tiled_union_limits(union, precision):
     """Passes planned with 8, 9 and 10 positions (shorter HBM runs, more blocks)."""
     n = 17

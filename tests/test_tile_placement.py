@@ -168,6 +168,13 @@ def test_other_shapes_free_of_bank_conflicts(tb, waves, cap):
             assert max(_lds_cycles(img, tbit, tb, waves)) == 1.0
 
 
+def test_three_part_split_uses_the_split_placement():
+    for n, blocks in _passes(1)[:6]:
+        a = sv.tile_placement(blocks, n, 14, 16, sv.PREC_SPLIT_BF16)
+        b = sv.tile_placement(blocks, n, 14, 16, sv.PREC_SPLIT_BF16X3)
+        assert np.array_equal(a[1], b[1]) and a[2] == b[2] == 0
+
+
 def test_fp32_keeps_the_fixed_placement_and_refusals():
     tp, img, c = sv.tile_placement([[0, 1, 2, 3]], 16, 14, 16, sv.PREC_FP32)
     assert c == 0 and [int(v) for v in img] == [(1 << b) ^ (((1 << b) >> 4) & 0x1E) for b in range(14)]
