@@ -177,29 +177,6 @@ struct TileCopy {
             *reinterpret_cast<vf4 *>(psi + 2 * (base_out + g_lo + g_hi[i])) = o;
         }
     }
-    // The same with the tile in LDS held scaled: out = LDS * unscale, LDS =
-    // buf * scale (exact powers of two).
-    __device__ __forceinline__ void to_lds_scaled(vf4 *X4, const vf4 *buf, float scale) const
-    {
-#pragma unroll
-        for (int i = 0; i < kChunks; ++i) X4[lds_slot ^ lds_hi[i]] = buf[i] * scale;
-    }
-    __device__ __forceinline__ void store_scaled(float *psi, uint64_t base, const vf4 *X4, float unscale) const
-    {
-#pragma unroll
-        for (int i = 0; i < kChunks; ++i)
-            *reinterpret_cast<vf4 *>(psi + 2 * (base + g_lo + g_hi[i])) = X4[lds_slot ^ lds_hi[i]] * unscale;
-    }
-    __device__ __forceinline__ void swap_scaled(float *psi, uint64_t base_out, vf4 *X4, const vf4 *buf, float scale,
-                                                float unscale) const
-    {
-#pragma unroll
-        for (int i = 0; i < kChunks; ++i) {
-            const vf4 o = X4[lds_slot ^ lds_hi[i]];
-            X4[lds_slot ^ lds_hi[i]] = buf[i] * scale;
-            *reinterpret_cast<vf4 *>(psi + 2 * (base_out + g_lo + g_hi[i])) = o * unscale;
-        }
-    }
     // largest magnitude of the values in buf
     __device__ __forceinline__ float max_abs(const vf4 *buf) const
     {
@@ -211,12 +188,13 @@ struct TileCopy {
     }
 };
 
-// FP16 passes hold the tile in LDS scaled by 2^e, e chosen from the tile's
-// largest magnitude m so that m 2^e lies in [2^7, 2^8).  The blocks act
-// unitarily on the tile, so no value can grow beyond the tile's 2-norm,
-// which is at most sqrt(2^15) m: every value stays below 2^15.5 < 65504 (the
-// FP16 hi parts stay finite) while values many binades below m stay in
-// FP16's normal range.
+// FP16 passes scale the tile's values by 2^e where they are split, e chosen
+// from the tile's largest magnitude m (at copy-in) so that m 2^e lies in
+// [2^7, 2^8), and scale the products back by 2^-e (exact powers of two).  The
+// blocks act unitarily on the tile, so no value can grow beyond the tile's
+// 2-norm, which is at most sqrt(2^15) m: every scaled value stays below
+// 2^15.5 < 65504 (the FP16 parts stay finite) while values many binades below
+// m stay in FP16's normal range.
 __device__ __forceinline__ void tile_scale(float m, float &scale, float &unscale)
 {
     scale = unscale = 1.f;
@@ -349,7 +327,7 @@ __device__ __forceinline__ void lds_st4(char *Xb, uint32_t byte_off, float a, fl
 // tile bit 0 is the lowest column bit, i.e. column blocks (q, q + 1).
 template <int TB, int WAVES, int PREC>
 __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const TileArgs &args, int s, int w, int half,
-                                            int l32)
+                                            int l32, float scale, float unscale)
 {
     using C = TileCfg<TB, WAVES>;
     constexpr bool SPLIT = PREC != kPrecF32;
@@ -408,9 +386,18 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
     // (BF16: three, FP16: two) and the tile values split into NS parts X_s:
     // every A_p X_0, every A_0 X_s, and A_1 X_1 when CROSS, the smaller terms
     // accumulated first.
-    constexpr int NP = PREC == kPrecF16 ? 2 : 3;
+    // FP16: the values are scaled by `scale` before the split, A_1 is held
+    // multiplied by 2^11 and meets X_0 2^-11 (so that neither falls below
+    // FP16's normal range), and the sums are scaled back by `unscale`.
+    constexpr bool F16 = PREC == kPrecF16;
+    constexpr int NP = F16 ? 2 : 3;
     constexpr int NS = PREC == kPrecBF16X3 ? 3 : 2;
     constexpr bool CROSS = PREC == kPrecBF16X3;
+    auto scaled = [&](vf4 v) { return F16 ? v * scale : v; };
+    auto out = [&](float v) { return F16 ? v * unscale : v; };
+    // X_0 2^-11 of a pair's X_0 (FP16 only; exact unless it falls below
+    // FP16's normal range, where its product with A_1 is below 2^-35 of m)
+    auto low_pair = [&](H2 x0) { return __builtin_convertvector(__builtin_convertvector(x0, vf2) * 0x1p-11f, H2); };
     auto fragment = [&](int p, int i) {
         H8 h;
         const vf4 f = ap[2 * p + i];
@@ -439,7 +426,7 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
                 vf4 raw[2];  // rows 8 i + 2 k2 + {0, 1} (plus 4 half)
 #pragma unroll
                 for (int k2 = 0; k2 < 2; ++k2)
-                    raw[k2] = *reinterpret_cast<const vf4 *>(Xb + ((row_of(rb, 8 * i + 2 * k2) << 3) ^ lq[q]));
+                    raw[k2] = scaled(*reinterpret_cast<const vf4 *>(Xb + ((row_of(rb, 8 * i + 2 * k2) << 3) ^ lq[q])));
                 H2 pp[4][NS];
 #pragma unroll
                 for (int k2 = 0; k2 < 2; ++k2) {
@@ -452,7 +439,16 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
                     H2 t[4] = {pp[0][sp], pp[1][sp], pp[2][sp], pp[3][sp]};
                     __builtin_memcpy(&b[sp], t, 16);
                 }
-                acc[q] = products(acc[q], xa, b);
+                if constexpr (F16) {
+                    H2 t[4] = {low_pair(pp[0][0]), low_pair(pp[1][0]), low_pair(pp[2][0]), low_pair(pp[3][0])};
+                    H8 bs;
+                    __builtin_memcpy(&bs, t, 16);
+                    acc[q] = mfma16(xa[0], b[1], acc[q]);
+                    acc[q] = mfma16(xa[1], bs, acc[q]);
+                    acc[q] = mfma16(xa[0], b[0], acc[q]);
+                } else {
+                    acc[q] = products(acc[q], xa, b);
+                }
             }
         }
         // rows 4 g + 2 half + {0, 1} are acc[4 g .. 4 g + 3]
@@ -460,8 +456,8 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
         for (int q = 0; q < NBW; ++q)
 #pragma unroll
             for (int g = 0; g < 4; ++g)
-                lds_st4(Xb, (row_of(rb, 4 * g) << 3) ^ wq[q], acc[q][4 * g], acc[q][4 * g + 1], acc[q][4 * g + 2],
-                        acc[q][4 * g + 3]);
+                lds_st4(Xb, (row_of(rb, 4 * g) << 3) ^ wq[q], out(acc[q][4 * g]), out(acc[q][4 * g + 1]),
+                        out(acc[q][4 * g + 2]), out(acc[q][4 * g + 3]));
     } else {  // column blocks (q, q + 1) share a slot
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
@@ -473,7 +469,7 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
                 vf4 raw[4];  // row 8 i + t (plus 4 half): column blocks (q, q + 1)
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
-                    raw[t] = *reinterpret_cast<const vf4 *>(Xb + ((row_of(rb, 8 * i + t) << 3) ^ lq[q]));
+                    raw[t] = scaled(*reinterpret_cast<const vf4 *>(Xb + ((row_of(rb, 8 * i + t) << 3) ^ lq[q])));
                 H2 p0[4][NS], p1[4][NS];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
@@ -488,8 +484,26 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
                     __builtin_memcpy(&b0[sp], t0, 16);
                     __builtin_memcpy(&b1[sp], t1, 16);
                 }
-                acc[q] = products(acc[q], xa, b0);
-                acc[q + 1] = products(acc[q + 1], xa, b1);
+                if constexpr (F16) {
+                    H2 t0[4], t1[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        t0[t] = low_pair(p0[t][0]);
+                        t1[t] = low_pair(p1[t][0]);
+                    }
+                    H8 bs0, bs1;
+                    __builtin_memcpy(&bs0, t0, 16);
+                    __builtin_memcpy(&bs1, t1, 16);
+                    acc[q] = mfma16(xa[0], b0[1], acc[q]);
+                    acc[q + 1] = mfma16(xa[0], b1[1], acc[q + 1]);
+                    acc[q] = mfma16(xa[1], bs0, acc[q]);
+                    acc[q + 1] = mfma16(xa[1], bs1, acc[q + 1]);
+                    acc[q] = mfma16(xa[0], b0[0], acc[q]);
+                    acc[q + 1] = mfma16(xa[0], b1[0], acc[q + 1]);
+                } else {
+                    acc[q] = products(acc[q], xa, b0);
+                    acc[q + 1] = products(acc[q + 1], xa, b1);
+                }
             }
         }
 #pragma unroll
@@ -498,8 +512,9 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
             for (int g = 0; g < 4; ++g)
 #pragma unroll
                 for (int e = 0; e < 2; ++e)
-                    lds_st4(Xb, (row_of(rb, 4 * g + e) << 3) ^ wq[q], acc[q][4 * g + 2 * e],
-                            acc[q][4 * g + 2 * e + 1], acc[q + 1][4 * g + 2 * e], acc[q + 1][4 * g + 2 * e + 1]);
+                    lds_st4(Xb, (row_of(rb, 4 * g + e) << 3) ^ wq[q], out(acc[q][4 * g + 2 * e]),
+                            out(acc[q][4 * g + 2 * e + 1]), out(acc[q + 1][4 * g + 2 * e]),
+                            out(acc[q + 1][4 * g + 2 * e + 1]));
     }
 }
 
@@ -561,27 +576,22 @@ __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__re
     if (T >= T_end) return;  // uniform over the workgroup
     vf4 buf[C::CHUNKS];
     cp.load(buf, psi, tile_base(T, args));
-    float scale = 1.f, unscale = 1.f, unscale_prev = 1.f;
-    if (F16) {
-        wave_max_to_red(buf);
-        __syncthreads();
-        tile_scale(red_max(), scale, unscale);
-    }
     uint64_t prev = 0;
     for (bool first = true; T < T_end; T += step, first = false) {
         const uint64_t base = tile_base(T, args);
+        if (first)
+            cp.to_lds(sh.X4, buf);
+        else
+            cp.swap(psi, prev, sh.X4, buf);
+        if (F16) wave_max_to_red(buf);  // this tile's largest magnitude, published by the barrier
+        __syncthreads();                // the first one also publishes the staged blocks
+        float scale = 1.f, unscale = 1.f;
         if (F16) {
-            if (first)
-                cp.to_lds_scaled(sh.X4, buf, scale);
-            else
-                cp.swap_scaled(psi, prev, sh.X4, buf, scale, unscale_prev);
-        } else {
-            if (first)
-                cp.to_lds(sh.X4, buf);
-            else
-                cp.swap(psi, prev, sh.X4, buf);
+            tile_scale(red_max(), scale, unscale);
+            // uniform: held in scalar registers through the block loop
+            scale = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, scale)));
+            unscale = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, unscale)));
         }
-        __syncthreads();  // the first one also publishes the staged blocks
         const uint64_t Tn = T + step;
         const bool more = Tn < T_end;  // uniform
         if (more) {
@@ -592,24 +602,12 @@ __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__re
             __builtin_amdgcn_s_setprio(0);
         }
         for (int s = 0; s < args.n_sub; ++s) {
-            apply_block<TB, WAVES, PREC>(sh, args, s, w, half, l32);
+            apply_block<TB, WAVES, PREC>(sh, args, s, w, half, l32, scale, unscale);
             __syncthreads();
-        }
-        if (F16) {
-            // the next tile's scale (one more barrier per tile)
-            if (more) {
-                wave_max_to_red(buf);
-                __syncthreads();
-            }
-            unscale_prev = unscale;
-            if (more) tile_scale(red_max(), scale, unscale);
         }
         prev = base;
     }
-    if (F16)
-        cp.store_scaled(psi, prev, sh.X4, unscale_prev);  // the last tile of this workgroup
-    else
-        cp.store(psi, prev, sh.X4);
+    cp.store(psi, prev, sh.X4);  // the last tile of this workgroup
 }
 
 // One pass over one state (gridDim.y = 1) or over psi and psi2 alike
@@ -723,16 +721,19 @@ void pack_tile_operand(const cd *m, int prec, uint32_t *out)
                 continue;
             }
             // part p = RNE(x - parts 0..p-1), as (re, im) halves of one word:
-            // three BF16 parts, two FP16 parts
+            // three BF16 parts, two FP16 parts (the second held times 2^11,
+            // which keeps it in FP16's normal range; the kernel pairs it with
+            // X_0 2^-11)
             const int parts = prec == kTileOperandF16 ? 2 : 3;
             double xr = re, xi = im;
             for (int p = 0; p < parts; ++p) {
                 uint32_t hr, hi;
                 if (prec == kTileOperandF16) {
-                    hr = f2h_rne(float(xr));
-                    hi = f2h_rne(float(xi));
-                    xr -= double(h2f(hr));
-                    xi -= double(h2f(hi));
+                    const double f = p ? 2048.0 : 1.0;
+                    hr = f2h_rne(float(xr * f));
+                    hi = f2h_rne(float(xi * f));
+                    xr -= double(h2f(hr)) / f;
+                    xi -= double(h2f(hi)) / f;
                 } else {
                     hr = f2bf_rne(float(xr));
                     hi = f2bf_rne(float(xi));
