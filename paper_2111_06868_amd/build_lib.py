@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libsv.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["gates.cpp", "fuse.cpp", "density.cpp", "circuit_utils.cpp", "channels.cpp", "runtime.hip", "api.hip", "apply.hip", "mfma.hip",
+SOURCES = ["gates.cpp", "fuse.cpp", "density.cpp", "circuit_utils.cpp", "channels.cpp", "placement.cpp", "runtime.hip", "api.hip", "apply.hip", "mfma.hip",
            "reduce.hip", "backward.hip", "batch.hip", "tune.hip", "tile.hip", "noalloc.hip", "stream.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -70,8 +70,12 @@ void pack_tile_operand(const cd *m, int prec, uint32_t *out);
 // waves in arithmetic `prec` (the LDS placement is chosen for them).
 hipError_t make_tile_args(int n_sub, const int (*sub_pos)[4], int n, int tile_bits, int waves, int prec,
                           TileArgs *out);
+// The pass's LDS placement (a.swz) for its blocks (a.tbit, a.n_sub), launch
+// shape and arithmetic (placement.cpp; make_tile_args calls it).
+void choose_tile_placement(TileArgs &a, int tile_bits, int waves, int prec);
 // Extra LDS cycles (bank conflicts) that the placement of `a` leaves in the
-// block loop of a split pass, by the bank model of make_tile_args; 0 for FP32.
+// block loop of a split pass, by the bank model of choose_tile_placement; 0
+// for FP32.
 int tile_placement_conflicts(const TileArgs &a, int tile_bits, int waves, int prec);
 // Batched passes (shape (kBatchTileBits, kBatchTileWaves), at most
 // tile_max_blocks() blocks per pass, operands of precision `prec` as
