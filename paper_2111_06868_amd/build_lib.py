@@ -13,6 +13,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libsv.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
+ROCM_INCLUDE = os.path.join(os.path.dirname(os.path.dirname(os.path.realpath(HIPCC))), "include")
 
 SOURCES = ["gates.cpp", "fuse.cpp", "density.cpp", "circuit_utils.cpp", "channels.cpp", "placement.cpp", "runtime.hip", "api.hip", "apply.hip", "mfma.hip",
            "reduce.hip", "backward.hip", "batch.hip", "tune.hip", "tile.hip", "noalloc.hip", "stream.hip"]
@@ -29,7 +30,8 @@ def _compile(src: str) -> str:
     if src.endswith(".hip"):
         cmd = [HIPCC, "-x", "hip"] + COMMON + DEVICE + ["-c", path, "-o", obj]
     else:
-        cmd = [HIPCC, "-x", "c++"] + COMMON + ["-D__HIP_PLATFORM_AMD__", "-c", path, "-o", obj]
+        cmd = [HIPCC, "-x", "c++"] + COMMON + ["-D__HIP_PLATFORM_AMD__", "-isystem", ROCM_INCLUDE, "-c", path,
+                                               "-o", obj]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(ln for ln in r.stdout.splitlines()
                     if "packed-fp32-ops' is not a recognized feature" not in ln)

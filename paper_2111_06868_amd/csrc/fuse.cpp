@@ -237,37 +237,47 @@ uint64_t block_mask(const Block &b)
 void merge_small_blocks(const sv_gate *g, int max_k, int max_union, std::vector<Block> &blocks)
 {
     (void)g;
-    auto pass_union = [&](int pass) {
+    std::vector<uint64_t> mask(blocks.size());
+    int n_pass = 0;
+    for (size_t i = 0; i < blocks.size(); ++i) {
+        mask[i] = block_mask(blocks[i]);
+        n_pass = std::max(n_pass, blocks[i].pass + 1);
+    }
+    std::vector<uint64_t> pass_union(size_t(n_pass), 0);  // positions of each pass's blocks
+    auto recompute = [&](int pass) {
+        if (pass < 0) return;
         uint64_t u = 0;
-        for (const auto &b : blocks)
-            if (b.pass == pass) u |= block_mask(b);
-        return u;
+        for (size_t j = 0; j < blocks.size(); ++j)
+            if (blocks[j].pass == pass) u |= mask[j];
+        pass_union[size_t(pass)] = u;
     };
-    auto fits = [&](const Block &into, uint64_t add) {
-        const uint64_t m = block_mask(into) | add;
-        if (popc(m) > max_k) return false;
-        return into.pass < 0 || popc(pass_union(into.pass) | add) <= max_union;
-    };
-    auto set_mask = [](Block &b, uint64_t m) {
-        b.k = 0;
-        for (int p = 0; p < 64; ++p)
-            if ((m >> p) & 1) b.q[b.k++] = p;
+    for (int p = 0; p < n_pass; ++p) recompute(p);
+    auto fits = [&](size_t into, uint64_t add) {
+        if (popc(mask[into] | add) > max_k) return false;
+        const int pass = blocks[into].pass;
+        return pass < 0 || popc(pass_union[size_t(pass)] | add) <= max_union;
     };
     for (bool changed = true; changed;) {
         changed = false;
         for (size_t i = 0; i < blocks.size() && !changed; ++i) {
-            const uint64_t m = block_mask(blocks[i]);
+            const uint64_t m = mask[i];
             int before = -1, after = -1;
             for (int j = int(i) - 1; j >= 0; --j)
-                if (block_mask(blocks[j]) & m) { before = j; break; }
+                if (mask[size_t(j)] & m) {
+                    before = j;
+                    break;
+                }
             for (size_t j = i + 1; j < blocks.size(); ++j)
-                if (block_mask(blocks[j]) & m) { after = int(j); break; }
+                if (mask[j] & m) {
+                    after = int(j);
+                    break;
+                }
             int into = -1;
-            if (before >= 0 && fits(blocks[before], m)) into = before;
-            else if (after >= 0 && fits(blocks[after], m)) into = after;
+            if (before >= 0 && fits(size_t(before), m)) into = before;
+            else if (after >= 0 && fits(size_t(after), m)) into = after;
             if (into < 0) continue;
-            Block &t = blocks[into];
-            const uint64_t tm = block_mask(t) | m;
+            Block &t = blocks[size_t(into)];
+            const uint64_t tm = mask[size_t(into)] | m;
             if (into < int(i)) {
                 t.members.insert(t.members.end(), blocks[i].members.begin(), blocks[i].members.end());
             } else {
@@ -275,8 +285,14 @@ void merge_small_blocks(const sv_gate *g, int max_k, int max_union, std::vector<
                 mem.insert(mem.end(), t.members.begin(), t.members.end());
                 t.members.swap(mem);
             }
-            set_mask(t, tm);
-            blocks.erase(blocks.begin() + i);
+            t.k = 0;
+            for (uint64_t r = tm; r; r &= r - 1) t.q[t.k++] = __builtin_ctzll(r);
+            mask[size_t(into)] = tm;
+            const int gone = blocks[i].pass;
+            blocks.erase(blocks.begin() + long(i));
+            mask.erase(mask.begin() + long(i));
+            recompute(gone);
+            recompute(t.pass);
             changed = true;
         }
     }
