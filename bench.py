@@ -5,7 +5,10 @@ sqrt(X)/sqrt(Y)/sqrt(W), 245 fSim(pi/2, pi/6)), complex64 state of 2^30
 amplitudes (8 GiB), seed 1.  One step = reset to |0..0>, fuse the gates
 (greedy fusion, blocks of at most max_k qubits) and apply every block, then
 the FP64 norm: the whole path from gate list to reduced result.  Inputs are
-resident on the device before the timed region.
+resident on the device before the timed region.  Default arithmetic: tiled
+passes of 4-qubit blocks as split FP16 MFMA products (FP32's per-amplitude
+error; `--precision` selects split BF16, BF16 with a three-part state, or
+FP32).
 
 Reported next to the fused throughput: the plain per-gate complex64 run, the
 fidelity error and amplitude max-abs error of both against a complex128 GPU
@@ -35,6 +38,8 @@ KERNEL_SOURCES = {1: "apply.hip", 2: "apply.hip", 3: "mfma.hip", 4: "mfma.hip", 
                   10: "tile.hip", 11: "tile.hip", 12: "tile.hip"}
 TILE_FAMILIES = (9, 10, 11, 12)
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 4}  # SV_PREC_* codes
+DEFAULT_PRECISION = {"circuit": "fp16", "gradient": "fp32", "trajectories": "bf16", "density": "bf16x3",
+                     "jumps": "fp32"}
 
 
 def log(*a):
@@ -113,11 +118,11 @@ def cpu_baseline_one_thread(config, budget_s):
     return json.loads(r.stdout.strip().splitlines()[-1])
 
 
-def small_circuit_lines(steps=20):
+def small_circuit_lines(prec, steps=20):
     """The 14-qubit grid circuit (225 gates, a 128 KiB state that a compute
     unit's LDS could hold): microseconds per gate on the GPU, fused (tiled
-    rule, k <= 4, split BF16, as the headline) and per gate, and for the CPU
-    oracle (all threads)."""
+    rule, k <= 4, in the headline's arithmetic `prec`) and per gate, and for
+    the CPU oracle (all threads)."""
     import numpy as np
     import torch
     import paper_2111_06868_amd as sv
@@ -127,7 +132,7 @@ def small_circuit_lines(steps=20):
     ga = sv.GateArray([(g.name, g.qubits, g.params) for g in gates])
     st = sv.State(n, "c64")
     out = {}
-    for name, kw in (("fused", dict(max_k=4, rule=sv.RULE_TILED, precision=sv.PREC_SPLIT_BF16)),
+    for name, kw in (("fused", dict(max_k=4, rule=sv.RULE_TILED, precision=prec)),
                      ("per_gate", dict(rule=sv.RULE_NONE))):
         st.set_basis(0).run(ga, **kw)
         torch.cuda.synchronize()
@@ -138,7 +143,7 @@ def small_circuit_lines(steps=20):
         out["gpu_%s_us_per_gate" % name] = round(1e6 * (time.perf_counter() - t0) / steps / len(gates), 3)
     want = ref.simulate(n, gates, "0")
     out["gpu_fused_fidelity_err"] = ref.fidelity_error(want, st.set_basis(0).run(
-        ga, max_k=4, rule=sv.RULE_TILED, precision=sv.PREC_SPLIT_BF16).read())
+        ga, max_k=4, rule=sv.RULE_TILED, precision=prec).read())
     t0 = time.perf_counter()
     reps = 0
     while reps < 3 or time.perf_counter() - t0 < 1.0:
@@ -215,7 +220,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--max-k", type=int, default=4)
     ap.add_argument("--rule", default="tiled", choices=["paper", "enhanced", "tiled", "auto"])
-    ap.add_argument("--precision", default="bf16", choices=["fp32", "bf16", "fp16", "bf16x3"])
+    ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "fp16", "bf16x3"],
+                    help="tile-pass arithmetic; default: fp16 for the circuits (FP32's per-amplitude "
+                         "error, unitary gates), bf16x3 for the density matrix (trace-preserving to "
+                         "about 1e-6), bf16 for the trajectory batch")
     ap.add_argument("--config", type=int, default=1, choices=[1, 2])
     ap.add_argument("--workload", default="circuit", choices=["circuit", "gradient", "trajectories", "density", "jumps"],
                     help="circuit: the grid random circuit (default); gradient: 20-qubit ansatz "
@@ -233,6 +241,8 @@ def main():
     ap.add_argument("--plan", action="store_true",
                     help="print the fused plan's tile passes (blocks, union, HBM layout) and exit; no GPU needed")
     args = ap.parse_args()
+    if args.precision is None:
+        args.precision = DEFAULT_PRECISION[args.workload]
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the state-vector path here is built and measured "
               "on a single MI355X (--gpus %d is not supported)" % args.gpus, file=sys.stderr)
@@ -436,7 +446,7 @@ def main():
         if one is not None:
             cpu["one_thread"] = {"value": one["value"], "unit": one["unit"], "sample": one["sample"]}
         log("14-qubit circuit lines ...")
-        extra["small_circuit"] = small_circuit_lines()
+        extra["small_circuit"] = small_circuit_lines(prec)
 
     out = {
         "metric": "gates/s + effective HBM GB/s at 30q; fused vs per-gate at <=1e-5 fidelity err",
@@ -451,7 +461,7 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "bf16": "bf16 split (3-part matrix, hi+lo state), f32 accumulate",
-                  "fp16": "f16 hi+lo split, f32 accumulate",
+                  "fp16": "f16 split (2-part matrix, hi+lo state, per-tile scale), f32 accumulate",
                   "bf16x3": "bf16 split (3-part matrix, 3-part state), f32 accumulate"}[args.precision],
         "data": "synthetic",
         "config": {"workload": "grid random circuit %s, %d qubits, %d gates, complex64, fused k<=%d (%s rule, %s)"
