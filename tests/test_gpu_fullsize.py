@@ -1,8 +1,8 @@
 """GPU parity at the full workload sizes.
 
 * 30 qubits, in the launch configuration the benchmark times (tiled rule,
-  k <= 4, split-BF16 tile passes), with three-part split-BF16 tile passes,
-  and in the enhanced FP32 configuration (k <= 5): a 100-gate prefix of the 845-gate circuit against the CPU oracle on
+  k <= 4, split-FP16 tile passes), with split-BF16 and three-part split-BF16
+  tile passes, and in the enhanced FP32 configuration (k <= 5): a 100-gate prefix of the 845-gate circuit against the CPU oracle on
   the whole 2^30-amplitude state, then the whole circuit against a complex128
   GPU run (fidelity, raw fidelity, norm, first 2^20 amplitudes).
 * 32 qubits: the 632-gate circuit with k = 4..6 blocks in FP32 and in split
@@ -28,9 +28,11 @@ from helpers import to_binding
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
-# the benchmark's configuration and the enhanced FP32 one:
+# the benchmark's configuration (tiled, split FP16), the other tile
+# arithmetics and the enhanced FP32 one:
 # (rule, max_k, precision, bound on 1-F, on max-abs, on |norm - 1|)
 CONFIGS = {
+    "tiled_fp16_k4": (sv.RULE_TILED, 4, sv.PREC_SPLIT_FP16, 1e-10, 1e-8, 1e-6),
     "tiled_bf16_k4": (sv.RULE_TILED, 4, sv.PREC_SPLIT_BF16, 1e-5, 1e-6, 1e-6),
     "enhanced_fp32_k5": (sv.RULE_ENHANCED, 5, sv.PREC_FP32, 1e-5, 1e-6, 1e-6),
     "tiled_bf16x3_k4": (sv.RULE_TILED, 4, sv.PREC_SPLIT_BF16X3, 1e-10, 1e-8, 1e-6),
