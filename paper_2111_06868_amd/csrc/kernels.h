@@ -102,12 +102,26 @@ bool tile_shape_supported(int tile_bits, int waves);
 int tile_wgs_per_cu(int tile_bits, int waves);
 // Blocks one launch of the shape can hold (their operands sit in LDS).
 int tile_max_blocks(int tile_bits, int waves);
+// The FP16 tile passes of one run and the state's norm, which their unitary
+// blocks keep: the first pass (out) writes each workgroup's sum of squares of
+// the values it reads, one double per workgroup of its grid; later passes
+// (in, n_in = that grid) scale the whole pass by a power of two from the norm
+// instead of scaling each tile from its largest magnitude.
+struct TileNorm {
+    const double *in = nullptr;
+    int n_in = 0;
+    double *out = nullptr;
+};
 // psi2 (optional): a second state of the same size that receives the same
 // pass in the same launch (gridDim.y = 2).
-// prec: kTileOperandF32, kTileOperandBF16 or kTileOperandF16 (FP16 passes
-// hold each tile scaled by a power of two chosen from its largest magnitude).
+// prec: kTileOperandF32, kTileOperandBF16, kTileOperandBF16X3 or
+// kTileOperandF16 (FP16 passes scale each tile by a power of two chosen from
+// its largest magnitude, or, with norm.in, the whole pass from the norm).
+// norm: FP16 and one state only.  *grid_out (may be NULL) receives the
+// number of workgroups launched.
 hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a, int prec, void *psi, int n,
-                            hipStream_t st, int grid_cap, int tile_bits, int waves, void *psi2 = nullptr);
+                            hipStream_t st, int grid_cap, int tile_bits, int waves, void *psi2 = nullptr,
+                            const TileNorm &norm = TileNorm{}, int *grid_out = nullptr);
 // Host-side packing of the MFMA operands of a canonical k-qubit matrix.
 void pack_real_form_f32(const cd *m, int k, float *out);
 // Split parts: part p = RNE(A' - parts before it), three for BF16, two for

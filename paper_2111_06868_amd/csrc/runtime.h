@@ -115,7 +115,11 @@ struct Launch {
     size_t arena_off = 0;  // byte offset of device operands (other paths)
     size_t arena_off2 = 0; // second and third operands (split parts 1 and 2)
     size_t arena_off3 = 0;
+    size_t norm_off = 0;   // split-FP16 tile paths: byte offset of the run's norm partials
 };
+// Doubles the norm partials of a run's split-FP16 tile passes may take (one
+// per workgroup of the first such pass).
+constexpr int kTileNormSlots = 4096;
 
 // Pack the device operands of `launches` into `stage` (host) and return the
 // total byte count; offsets are written into the launches.

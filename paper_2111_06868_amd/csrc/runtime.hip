@@ -258,6 +258,14 @@ size_t pack_operands(std::vector<Launch> &launches, int dtype, PinBuf &stage)
             break;
         }
     }
+    // one region for the norm partials of the run's split-FP16 tile passes
+    bool fp16_tiles = false;
+    for (const auto &L : launches) fp16_tiles = fp16_tiles || L.path == PATH_TILE_FP16;
+    if (fp16_tiles) {
+        for (auto &L : launches)
+            if (L.path == PATH_TILE_FP16) L.norm_off = total;
+        total = align256(total + sizeof(double) * kTileNormSlots);
+    }
     if (total == 0) return 0;
     if (stage.ensure(total) != hipSuccess) return size_t(-1);
     char *h = static_cast<char *>(stage.p);
@@ -415,6 +423,9 @@ int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, cons
 {
     const char *A = static_cast<const char *>(arena);
     const Tuning &T = tuning();
+    // split-FP16 tile passes of one state: the first writes the norm partials,
+    // the later ones take their scale from them (unitary blocks keep the norm)
+    int norm_grid = 0;
     for (const Launch *it = first; it != first + count; ++it) {
         const Launch &L = *it;
         if (psi2 && L.path != PATH_REG && L.path != PATH_GENERIC && L.path != PATH_MFMA32 && !is_tile_path(L.path)) {
@@ -427,15 +438,30 @@ int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, cons
             // one launch per chunk of blocks whose operands fit the shape's LDS
             const int cap = dev::tile_max_blocks(T.tile_bits, T.tile_waves);
             const size_t op_bytes = 4 * dev::kTileOperandWords;
+            const int grid_cap = T.tile_grid_cap * dev::tile_wgs_per_cu(T.tile_bits, T.tile_waves);
+            const uint64_t n_tiles = uint64_t(1) << (n - T.tile_bits);
+            const uint64_t grid = grid_cap > 0 && n_tiles > uint64_t(grid_cap) ? uint64_t(grid_cap) : n_tiles;
+            const bool use_norm = L.path == PATH_TILE_FP16 && !psi2 && grid <= uint64_t(kTileNormSlots);
             for (int c = 0; c < L.k; c += cap) {
                 const int m = std::min(cap, L.k - c);
+                dev::TileNorm norm;
+                int launched = 0;
+                if (use_norm) {
+                    double *part = reinterpret_cast<double *>(const_cast<char *>(A) + L.norm_off);
+                    if (norm_grid > 0) {
+                        norm.in = part;
+                        norm.n_in = norm_grid;
+                    } else {
+                        norm.out = part;
+                    }
+                }
                 LaunchTimer timer(stat_class(path_family(L.path), m), st);
                 hipError_t e = dev::launch_tile_pass(m, L.sub_pos + c, A + L.arena_off + c * op_bytes,
-                                                     tile_operand_prec(L.path), psi, n, st,
-                                                     T.tile_grid_cap * dev::tile_wgs_per_cu(T.tile_bits, T.tile_waves),
-                                                     T.tile_bits, T.tile_waves, psi2);
+                                                     tile_operand_prec(L.path), psi, n, st, grid_cap, T.tile_bits,
+                                                     T.tile_waves, psi2, norm, &launched);
                 if (e != hipSuccess)
                     return fail(SV_ERR_HIP, "tile pass launch (%d blocks): %s", m, hipGetErrorString(e));
+                if (norm.out) norm_grid = launched;
             }
             continue;
         }

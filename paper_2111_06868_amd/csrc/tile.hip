@@ -153,6 +153,38 @@ struct TileCopy {
 #pragma unroll
         for (int i = 0; i < kChunks; ++i) buf[i] = *reinterpret_cast<const vf4 *>(psi + 2 * (base + g_lo + g_hi[i]));
     }
+    // The same with a scale for the values in LDS (exact powers of two): LDS =
+    // buf * scale, out = LDS * unscale.
+    __device__ __forceinline__ void to_lds_scaled(vf4 *X4, const vf4 *buf, float scale) const
+    {
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) X4[lds_slot ^ lds_hi[i]] = buf[i] * scale;
+    }
+    __device__ __forceinline__ void store_scaled(float *psi, uint64_t base, const vf4 *X4, float unscale) const
+    {
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i)
+            *reinterpret_cast<vf4 *>(psi + 2 * (base + g_lo + g_hi[i])) = X4[lds_slot ^ lds_hi[i]] * unscale;
+    }
+    __device__ __forceinline__ void swap_scaled(float *psi, uint64_t base_out, vf4 *X4, const vf4 *buf, float scale,
+                                                float unscale) const
+    {
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) {
+            const vf4 o = X4[lds_slot ^ lds_hi[i]];
+            X4[lds_slot ^ lds_hi[i]] = buf[i] * scale;
+            *reinterpret_cast<vf4 *>(psi + 2 * (base_out + g_lo + g_hi[i])) = o * unscale;
+        }
+    }
+    // sum of the squares of the values in buf
+    __device__ __forceinline__ float sum_sq(const vf4 *buf) const
+    {
+        float a = 0.f;
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i)
+            a += buf[i].x * buf[i].x + buf[i].y * buf[i].y + buf[i].z * buf[i].z + buf[i].w * buf[i].w;
+        return a;
+    }
     __device__ __forceinline__ void to_lds(vf4 *X4, const vf4 *buf) const
     {
 #pragma unroll
@@ -207,6 +239,23 @@ __device__ __forceinline__ void tile_scale(float m, float &scale, float &unscale
     }
 }
 
+// A scale for a whole pass of FP16 products from the state's 2-norm r (the
+// blocks keep it): 2^e with r 2^e in [2^14, 2^15), so that no value, being at
+// most r in magnitude, exceeds 2^15 once scaled.  Scale 1 if r is 0 or not
+// finite.
+__device__ __forceinline__ void norm_scale(double r, float &scale, float &unscale)
+{
+    scale = unscale = 1.f;
+    if (r > 0.0 && r <= 1e300) {
+        int e;
+        frexp(r, &e);  // r in [2^(e-1), 2^e)
+        int s = 15 - e;
+        s = s > 120 ? 120 : (s < -120 ? -120 : s);
+        scale = ldexpf(1.f, s);
+        unscale = ldexpf(1.f, -s);
+    }
+}
+
 // Per-block data staged in LDS: the A operand and the swizzled column terms
 // of lane l32 and column block cb = w NBW + q of wave w: cq[cb] ^ cl[l32].
 // Column index c (deposited into the block's column bits, ascending):
@@ -221,6 +270,7 @@ struct TileShared {
     uint32_t cq[C::MAX_SUB][C::CBLOCKS];
     uint32_t cl[C::MAX_SUB][32];
     float red[WAVES];  // per-wave partial of the next tile's scale (FP16 passes)
+    float nrm[WAVES];  // per-wave sum of squares read so far (FP16 passes that report the norm)
 };
 
 // Stage the launch's blocks: each lane's A' fragments, expanded from the
@@ -324,7 +374,7 @@ __device__ __forceinline__ void lds_st4(char *Xb, uint32_t byte_off, float a, fl
 // 16 bytes, two complex values that differ in tile bit 0.  If tile bit 0 is
 // the block's row bit 0, these are rows (t, t + 1) of one column; otherwise
 // tile bit 0 is the lowest column bit, i.e. column blocks (q, q + 1).
-template <int TB, int WAVES, int PREC>
+template <int TB, int WAVES, int PREC, int SCALE>
 __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const TileArgs &args, int s, int w, int half,
                                             int l32, float scale, float unscale)
 {
@@ -385,18 +435,26 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
     // (BF16: three, FP16: two) and the tile values split into NS parts X_s:
     // every A_p X_0, every A_0 X_s, and A_1 X_1 when CROSS, the smaller terms
     // accumulated first.
-    // FP16: the values are scaled by `scale` before the split, A_1 is held
-    // multiplied by 2^11 and meets X_0 2^-11 (so that neither falls below
-    // FP16's normal range), and the sums are scaled back by `unscale`.
+    // FP16: the values are scaled by `scale` before the split (SCALE 0: one
+    // scale per tile; SCALE 1: the tile is held scaled in LDS with one scale
+    // per pass), A_1 is held multiplied by 2^11 and meets X_0 2^-11 (so that
+    // neither falls below FP16's normal range), and the sums are scaled back
+    // by `unscale` (SCALE 0).
     constexpr bool F16 = PREC == kPrecF16;
+    constexpr bool SCALE_HERE = F16 && SCALE == 0;
     constexpr int NP = F16 ? 2 : 3;
     constexpr int NS = PREC == kPrecBF16X3 ? 3 : 2;
     constexpr bool CROSS = PREC == kPrecBF16X3;
-    auto scaled = [&](vf4 v) { return F16 ? v * scale : v; };
-    auto out = [&](float v) { return F16 ? v * unscale : v; };
+    auto scaled = [&](vf4 v) { return SCALE_HERE ? v * scale : v; };
+    auto out = [&](float v) { return SCALE_HERE ? v * unscale : v; };
     // X_0 2^-11 of a pair's X_0 (FP16 only; exact unless it falls below
     // FP16's normal range, where its product with A_1 is below 2^-35 of m)
-    auto low_pair = [&](H2 x0) { return __builtin_convertvector(__builtin_convertvector(x0, vf2) * 0x1p-11f, H2); };
+    auto low_pair = [&](H2 x0) {
+        vf2 c;
+        c.x = 0x1p-11f;
+        c.y = 0x1p-11f;
+        return x0 * __builtin_convertvector(c, H2);  // a packed 16-bit multiply
+    };
     auto fragment = [&](int p, int i) {
         H8 h;
         const vf4 f = ap[2 * p + i];
@@ -530,10 +588,10 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
 // 2^-17 (BF16: the state's third part, A_1 X_1), 2^-22 (FP16) and 2^-25
 // (BF16X3) relative to the result.  FP16 passes hold the tile scaled
 // (tile_scale).
-template <int TB, int WAVES, int PREC>
+template <int TB, int WAVES, int PREC, int SCALE>
 __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__restrict__ psi,
                                           const uint32_t *__restrict__ A, const TileArgs &args, uint64_t T,
-                                          uint64_t T_end, uint64_t step)
+                                          uint64_t T_end, uint64_t step, const TileNorm &norm)
 {
     using C = TileCfg<TB, WAVES>;
     constexpr bool F16 = PREC == kPrecF16;
@@ -572,20 +630,58 @@ __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__re
     // that round's prefetch is issued: loads and stores may complete out of
     // order, so any wait for the prefetch also waits for earlier stores, and
     // these were issued a whole round of block work earlier.
-    if (T >= T_end) return;  // uniform over the workgroup
+    // FP16 with SCALE 1: one scale for the pass from the state's norm, the
+    // sum of the workgroups' sums of squares that an earlier pass of the run
+    // wrote (fixed order; uniform, in scalar registers)
+    float pscale = 1.f, punscale = 1.f;
+    if (F16 && SCALE == 1) {
+        double r2 = 0.0;
+        for (int i = 0; i < norm.n_in; ++i) r2 += norm.in[i];
+        norm_scale(sqrt(r2), pscale, punscale);
+        pscale = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, pscale)));
+        punscale = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, punscale)));
+    }
+    // SCALE 2: per-tile scales as SCALE 0, and the workgroup's sum of squares to norm.out
+    constexpr bool want_norm = F16 && SCALE == 2;
+    if (T >= T_end) {  // uniform over the workgroup
+        if (want_norm && tid == 0) norm.out[blockIdx.x] = 0.0;
+        return;
+    }
+    // the wave's sum of squares of what it reads (want_norm), kept in LDS
+    auto wave_sum = [&](float v) {
+        v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x041F));
+        v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x081F));
+        v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x101F));
+        v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x201F));
+        v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0)) +
+               __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    };
+    if (want_norm && lane == 0) sh.nrm[w] = 0.f;
     vf4 buf[C::CHUNKS];
     cp.load(buf, psi, tile_base(T, args));
     uint64_t prev = 0;
     for (bool first = true; T < T_end; T += step, first = false) {
         const uint64_t base = tile_base(T, args);
-        if (first)
-            cp.to_lds(sh.X4, buf);
-        else
-            cp.swap(psi, prev, sh.X4, buf);
-        if (F16) wave_max_to_red(buf);  // this tile's largest magnitude, published by the barrier
-        __syncthreads();                // the first one also publishes the staged blocks
+        if (F16 && SCALE == 1) {
+            if (first)
+                cp.to_lds_scaled(sh.X4, buf, pscale);
+            else
+                cp.swap_scaled(psi, prev, sh.X4, buf, pscale, punscale);
+        } else {
+            if (first)
+                cp.to_lds(sh.X4, buf);
+            else
+                cp.swap(psi, prev, sh.X4, buf);
+        }
+        if (want_norm) {
+            const float v = wave_sum(cp.sum_sq(buf));
+            if (lane == 0) sh.nrm[w] += v;  // only this wave's lane 0 touches sh.nrm[w]
+        }
+        if (F16 && SCALE != 1) wave_max_to_red(buf);  // this tile's largest magnitude, published by the barrier
+        __syncthreads();  // the first one also publishes the staged blocks
         float scale = 1.f, unscale = 1.f;
-        if (F16) {
+        if (F16 && SCALE != 1) {
             tile_scale(red_max(), scale, unscale);
             // uniform: held in scalar registers through the block loop
             scale = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, scale)));
@@ -601,22 +697,38 @@ __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__re
             __builtin_amdgcn_s_setprio(0);
         }
         for (int s = 0; s < args.n_sub; ++s) {
-            apply_block<TB, WAVES, PREC>(sh, args, s, w, half, l32, scale, unscale);
+            apply_block<TB, WAVES, PREC, SCALE == 1 ? 1 : 0>(sh, args, s, w, half, l32, scale, unscale);
             __syncthreads();
         }
         prev = base;
     }
-    cp.store(psi, prev, sh.X4);  // the last tile of this workgroup
+    // the last tile of this workgroup
+    if (F16 && SCALE == 1)
+        cp.store_scaled(psi, prev, sh.X4, punscale);
+    else
+        cp.store(psi, prev, sh.X4);
+    if (want_norm) {
+        // the workgroup's sum of squares: the wave sums in wave order, in FP64
+        // (the norm only has to be right to a factor of two)
+        __syncthreads();
+        if (tid == 0) {
+            double t = 0.0;
+            for (int i = 0; i < WAVES; ++i) t += double(sh.nrm[i]);
+            norm.out[blockIdx.x] = t;
+        }
+    }
 }
 
 // One pass over one state (gridDim.y = 1) or over psi and psi2 alike
 // (gridDim.y = 2): a persistent grid strides over the tiles of its state.
-template <int TB, int WAVES, int PREC>
+template <int TB, int WAVES, int PREC, int SCALE>
 __global__ void __launch_bounds__(64 * WAVES) k_tile_pass(float *__restrict__ psi, const uint32_t *__restrict__ A,
-                                                          const TileArgs args, float *__restrict__ psi2)
+                                                          const TileArgs args, float *__restrict__ psi2,
+                                                          const TileNorm norm)
 {
     __shared__ TileShared<TB, WAVES> sh;
-    tile_loop<TB, WAVES, PREC>(sh, blockIdx.y ? psi2 : psi, A, args, blockIdx.x, args.n_tiles, gridDim.x);
+    tile_loop<TB, WAVES, PREC, SCALE>(sh, blockIdx.y ? psi2 : psi, A, args, blockIdx.x, args.n_tiles, gridDim.x,
+                                      norm);
 }
 
 // Passes of many states in one grid: workgroup i takes tiles [t0, t1) of
@@ -630,25 +742,31 @@ __global__ void __launch_bounds__(64 * WAVES) k_tile_batch(const TileUnit *__res
     __shared__ TileShared<TB, WAVES> sh;
     const TileUnit u = units[blockIdx.x];
     const TilePass &p = passes[u.pass];
-    tile_loop<TB, WAVES, PREC>(sh, buf + 2 * p.state_off, pool + p.op_off, p.args, u.t0, u.t1, 1);
+    tile_loop<TB, WAVES, PREC, 0>(sh, buf + 2 * p.state_off, pool + p.op_off, p.args, u.t0, u.t1, 1, TileNorm{});
 }
 
 template <int TB, int WAVES>
 hipError_t tile_launch(const TileArgs &a, const void *d_a, int prec, float *psi, float *psi2, hipStream_t st,
-                       int cap)
+                       int cap, const TileNorm &norm, int *grid_out)
 {
     uint64_t g = a.n_tiles;
     if (cap > 0 && g > uint64_t(cap)) g = cap;
+    if (grid_out) *grid_out = int(g);
     const uint32_t *A = static_cast<const uint32_t *>(d_a);
     const dim3 grid(unsigned(g), psi2 ? 2 : 1);
+    const dim3 block(64 * WAVES);
     if (prec == kPrecBF16)
-        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecBF16>), grid, dim3(64 * WAVES), 0, st, psi, A, a, psi2);
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecBF16, 0>), grid, block, 0, st, psi, A, a, psi2, TileNorm{});
     else if (prec == kPrecBF16X3)
-        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecBF16X3>), grid, dim3(64 * WAVES), 0, st, psi, A, a, psi2);
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecBF16X3, 0>), grid, block, 0, st, psi, A, a, psi2, TileNorm{});
+    else if (prec == kPrecF16 && norm.in)
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF16, 1>), grid, block, 0, st, psi, A, a, psi2, norm);
+    else if (prec == kPrecF16 && norm.out)
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF16, 2>), grid, block, 0, st, psi, A, a, psi2, norm);
     else if (prec == kPrecF16)
-        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF16>), grid, dim3(64 * WAVES), 0, st, psi, A, a, psi2);
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF16, 0>), grid, block, 0, st, psi, A, a, psi2, TileNorm{});
     else
-        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF32>), grid, dim3(64 * WAVES), 0, st, psi, A, a, psi2);
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF32, 0>), grid, block, 0, st, psi, A, a, psi2, TileNorm{});
     return hipGetLastError();
 }
 
@@ -787,8 +905,11 @@ hipError_t make_tile_args(int n_sub, const int (*sub_pos)[4], int n, int tile_bi
 }
 
 hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a, int prec, void *psi, int n,
-                            hipStream_t st, int grid_cap, int tile_bits, int waves, void *psi2)
+                            hipStream_t st, int grid_cap, int tile_bits, int waves, void *psi2, const TileNorm &norm,
+                            int *grid_out)
 {
+    if ((norm.in || norm.out) && (prec != kTileOperandF16 || psi2 || (norm.in && norm.n_in < 1)))
+        return hipErrorInvalidValue;
     if (prec != kTileOperandF32 && prec != kTileOperandBF16 && prec != kTileOperandF16 && prec != kTileOperandBF16X3)
         return hipErrorInvalidValue;
     if (!tile_shape_supported(tile_bits, waves)) return hipErrorInvalidValue;
@@ -797,10 +918,10 @@ hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a,
     if (hipError_t e = make_tile_args(n_sub, sub_pos, n, tile_bits, waves, prec, &a)) return e;
     float *p = static_cast<float *>(psi), *p2 = static_cast<float *>(psi2);
     if (tile_bits == 14)
-        return waves == 16 ? tile_launch<14, 16>(a, d_a, prec, p, p2, st, grid_cap)
-                           : tile_launch<14, 8>(a, d_a, prec, p, p2, st, grid_cap);
-    return waves == 4 ? tile_launch<13, 4>(a, d_a, prec, p, p2, st, grid_cap)
-                      : tile_launch<13, 8>(a, d_a, prec, p, p2, st, grid_cap);
+        return waves == 16 ? tile_launch<14, 16>(a, d_a, prec, p, p2, st, grid_cap, norm, grid_out)
+                           : tile_launch<14, 8>(a, d_a, prec, p, p2, st, grid_cap, norm, grid_out);
+    return waves == 4 ? tile_launch<13, 4>(a, d_a, prec, p, p2, st, grid_cap, norm, grid_out)
+                      : tile_launch<13, 8>(a, d_a, prec, p, p2, st, grid_cap, norm, grid_out);
 }
 
 hipError_t launch_tile_batch(const TileUnit *units, int n_units, const TilePass *passes, const uint32_t *pool,
