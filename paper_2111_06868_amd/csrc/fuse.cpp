@@ -131,7 +131,6 @@ class Frontier {
         for (uint64_t m = used_; m; m &= m - 1) queue_[__builtin_ctzll(m)].reserve(G);
         for (int t = 0; t < G; ++t)
             for (uint64_t m = mask_[t]; m; m &= m - 1) queue_[__builtin_ctzll(m)].push_back(t);
-        for (int t = 0; t < G; ++t) slot_[idx[t]] = t;
         left_ = G;
     }
     // The next group (gate indices of the caller's list), or false when none is left.
@@ -172,8 +171,14 @@ class Frontier {
     // last ones taken there.
     void give_back(const std::vector<int> &gates)
     {
+        if (slot_.empty() && !gates.empty()) {  // formed on first use
+            int top = 0;
+            for (int gi : idx_) top = std::max(top, gi);
+            slot_.assign(size_t(top) + 1, -1);
+            for (size_t t = 0; t < idx_.size(); ++t) slot_[size_t(idx_[t])] = int(t);
+        }
         for (int gi : gates) {
-            const int t = slot_.at(gi);
+            const int t = slot_.at(size_t(gi));
             for (uint64_t m = mask_[t]; m; m &= m - 1) --head_[__builtin_ctzll(m)];
             ++left_;
         }
@@ -191,7 +196,7 @@ class Frontier {
     std::vector<uint64_t> mask_;
     std::vector<std::vector<int>> queue_;
     std::vector<size_t> head_;
-    std::map<int, int> slot_;  // caller's gate index -> position in idx
+    std::vector<int> slot_;  // caller's gate index -> position in idx (formed by give_back)
     uint64_t used_ = 0;
     int left_ = 0;
 };
