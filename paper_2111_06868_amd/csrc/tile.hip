@@ -283,28 +283,33 @@ struct TileShared {
 //   split: word 8 p + 4 i + e (part p = 0..2, step i = 0, 1, e = 0..3) holds
 //   the 16-bit pair A'[r][16 i + 8 half + 2 e + {0, 1}] of part p: (Ur, -Ui)
 //   for ri = 0, (Ui, Ur) for ri = 1, at complex column j = 8 i + 4 half + e.
+// Words an arithmetic does not read (FP32 and FP16: 16..23) are not written.
 template <int TB, int WAVES, int PREC>
 __device__ __forceinline__ void stage_blocks(TileShared<TB, WAVES> &sh, const uint32_t *A, const TileArgs &args,
                                              int tid)
 {
     using C = TileCfg<TB, WAVES>;
     constexpr bool SPLIT = PREC != kPrecF32;
+    // words of a lane's fragments that the block loop reads: FP32 16, split
+    // 8 per part (FP16: two parts, BF16: three)
+    constexpr int USED = !SPLIT ? 16 : (PREC == kPrecF16 ? 16 : 24);
+    static_assert(USED <= kLaneWords, "fragment words");
     const int nsub = args.n_sub;
-    for (int e = tid; e < nsub * kOperandWords; e += C::THREADS) {
-        const int s = e / kOperandWords, r = e % kOperandWords;
-        const int lane = r / kLaneWords, wd = r % kLaneWords;
+    for (int e = tid; e < nsub * 64 * USED; e += C::THREADS) {
+        const int s = e / (64 * USED), r = e % (64 * USED);
+        const int lane = r / USED, wd = r % USED;
         const int half = lane >> 5, l32 = lane & 31, ci = l32 >> 1, ri = l32 & 1;
         const uint32_t *cop = A + size_t(s) * kTileOperandWords;
         uint32_t v;
         if (!SPLIT) {
-            v = wd < 16 ? cop[(ri == half ? 0 : 256) + ci * 16 + wd] : 0u;
+            v = cop[(ri == half ? 0 : 256) + ci * 16 + wd];
             if (ri == 0 && half == 1) v ^= 0x80000000u;
         } else {
             const int part = wd >> 3, i = (wd >> 2) & 1, e4 = wd & 3;
             const uint32_t w = cop[part * 256 + ci * 16 + 8 * i + 4 * half + e4];
             v = ri ? ((w >> 16) | (w << 16)) : (w ^ 0x80000000u);
         }
-        sh.op[s][r] = v;
+        sh.op[s][lane * kLaneWords + wd] = v;
     }
     for (int e = tid; e < nsub * (C::CBLOCKS + 32); e += C::THREADS) {
         const int s = e / (C::CBLOCKS + 32), r = e % (C::CBLOCKS + 32);
