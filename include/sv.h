@@ -251,9 +251,11 @@ int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int use_graph);
  * (gates move only where every qubit keeps its own gate order).  Each tile
  * of 2^14 (or 2^13) amplitudes is staged in LDS once, every block of the
  * pass is applied to it (SV_PREC_FP32: FP32 MFMA; SV_PREC_SPLIT_BF16 /
- * SV_PREC_SPLIT_FP16: hi+lo 16-bit MFMA, the FP16 passes holding each tile
- * scaled by a power of two chosen from its largest magnitude;
- * SV_PREC_SPLIT_BF16X3: BF16 MFMA on three parts of each value), and the tile
+ * SV_PREC_SPLIT_FP16: hi+lo 16-bit MFMA, the FP16 values scaled by a power of
+ * two, chosen per tile from its largest magnitude in the call's first FP16
+ * pass and per pass from the state's norm, which that pass measures, in the
+ * later ones; SV_PREC_SPLIT_BF16X3: BF16 MFMA on three parts of each value),
+ * and the tile
  * is written back, so a pass costs one read and one write of the state.  A
  * block left alone runs as a one-block pass where the cost table prices
  * that lower.
