@@ -347,10 +347,13 @@ __global__ void __launch_bounds__((SplitCfg<K, TCL>::THREADS))
                 for (int p = 0; p < NP; ++p) __builtin_memcpy(&xa[p], &ap[p][i], 16);
                 __builtin_memcpy(&xb_h, &bh, 16);
                 __builtin_memcpy(&xb_l, &bl, 16);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa[0], xb_h, acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa[0], xb_l, acc, 0, 0, 0);
+                // A_1 is held times 2^11 (FP16's normal range): it meets X_h 2^-11
+                f16x8 k11;
 #pragma unroll
-                for (int p = 1; p < NP; ++p) acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa[p], xb_h, acc, 0, 0, 0);
+                for (int e = 0; e < 8; ++e) k11[e] = _Float16(0x1p-11f);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa[0], xb_l, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa[1], xb_h * k11, acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_32x32x16_f16(xa[0], xb_h, acc, 0, 0, 0);
             } else {
                 bf16x8 xa[NP], xb_h, xb_l;
 #pragma unroll
@@ -504,9 +507,10 @@ void pack_real_form_split(const cd *m, int k, bool fp16, uint16_t *const *parts)
                             parts[p][o] = 0;
                             continue;
                         }
-                        if (fp16) {
-                            parts[p][o] = host_f2h(float(x));
-                            x -= double(host_h2f(parts[p][o]));
+                        if (fp16) {  // the second part held times 2^11
+                            const double f = p ? 2048.0 : 1.0;
+                            parts[p][o] = host_f2h(float(x * f));
+                            x -= double(host_h2f(parts[p][o])) / f;
                         } else {
                             parts[p][o] = host_f2bf(float(x));
                             x -= double(host_bf2f(parts[p][o]));
