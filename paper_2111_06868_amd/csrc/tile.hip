@@ -591,8 +591,10 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
 // sum_p A_p X_0 + sum_s A_0 X_s (plus A_1 X_1 for kPrecBF16X3) run on
 // 32 x 32 x 16 MFMA with FP32 accumulation.  The dropped terms are about
 // 2^-17 (BF16: the state's third part, A_1 X_1), 2^-22 (FP16) and 2^-25
-// (BF16X3) relative to the result.  FP16 passes hold the tile scaled
-// (tile_scale).
+// (BF16X3) relative to the result.  FP16 passes scale the values per tile
+// (tile_scale; SCALE 0, and SCALE 2, which also reports the workgroup's sum
+// of squares to norm.out) or per pass from the state's norm (norm_scale;
+// SCALE 1, from the sums an earlier pass of the run reported).
 template <int TB, int WAVES, int PREC, int SCALE>
 __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__restrict__ psi,
                                           const uint32_t *__restrict__ A, const TileArgs &args, uint64_t T,
@@ -631,10 +633,6 @@ __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__re
         return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, m)));
     };
 
-    // A finished tile is written to HBM at the top of the next round, before
-    // that round's prefetch is issued: loads and stores may complete out of
-    // order, so any wait for the prefetch also waits for earlier stores, and
-    // these were issued a whole round of block work earlier.
     // FP16 with SCALE 1: one scale for the pass from the state's norm, the
     // sum of the workgroups' sums of squares that an earlier pass of the run
     // wrote (fixed order; uniform, in scalar registers)
@@ -663,6 +661,10 @@ __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__re
                __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
     };
     if (want_norm && lane == 0) sh.nrm[w] = 0.f;
+    // A finished tile is written to HBM at the top of the next round, before
+    // that round's prefetch is issued: loads and stores may complete out of
+    // order, so any wait for the prefetch also waits for earlier stores, and
+    // these were issued a whole round of block work earlier.
     vf4 buf[C::CHUNKS];
     cp.load(buf, psi, tile_base(T, args));
     uint64_t prev = 0;
