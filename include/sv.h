@@ -246,8 +246,13 @@ int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int use_graph);
  * (use_graph as for sv_apply_plan).  o == NULL means plain per-gate
  * application: {SV_MAX_K, FP32 or FP64 by amplitude type, SV_RULE_NONE, 0}.
  * With SV_RULE_TILED on a complex64 state of >= 14 qubits, the gates are
- * grouped into passes whose positions span at most sv_set_tile_union()
- * positions (default 10), and each pass is fused into blocks of <= 4 qubits
+ * grouped into passes whose positions U leave contiguous HBM runs no shorter
+ * than those of a union of sv_set_tile_union() positions (default 10): the
+ * tile of a pass is U plus the lowest positions outside it, 14 (or 13) in
+ * all, and its runs, 2^r amplitudes with r its lowest positions 0, 1, .. in
+ * a row, must hold at least 2^(tile bits - limit); so every union of <= 10
+ * positions qualifies, and up to 14 when U holds the lowest positions.  Each
+ * pass is fused into blocks of <= 4 qubits
  * (gates move only where every qubit keeps its own gate order).  Each tile
  * of 2^14 (or 2^13) amplitudes is staged in LDS once, every block of the
  * pass is applied to it (SV_PREC_FP32: FP32 MFMA; SV_PREC_SPLIT_BF16 /
@@ -543,11 +548,13 @@ int sv_get_tile_shape(int *tile_bits, int *waves, int *max_blocks);
  * for FP32).  Errors: SV_ERR_ARG. */
 int sv_tile_placement(int n_sub, const int32_t *sub_pos, int n, int tile_bits, int waves, int precision,
                       int32_t *tile_pos, uint32_t *lds_image, int32_t *conflicts);
-/* Position limit of the passes that SV_RULE_TILED plans (8..10; default 10,
- * or the SV_TILE_UNION environment variable at load time).  A larger union
- * holds more gates per pass but leaves shorter contiguous runs in HBM
- * (2^(tile_bits - union) amplitudes).  Applies to later sv_fuse /
- * sv_run_circuit calls in the process.  SV_ERR_ARG outside 8..10. */
+/* Union limit of the passes that SV_RULE_TILED plans (8..10; default 10,
+ * or the SV_TILE_UNION environment variable at load time): every pass's tile
+ * is made of contiguous HBM runs of at least 2^(tile_bits - limit)
+ * amplitudes, the runs a union of `limit` positions leaves.  A larger limit
+ * holds more gates per pass but allows shorter runs.  Applies to later
+ * sv_fuse / sv_run_circuit calls in the process.  SV_ERR_ARG outside
+ * 8..10. */
 int sv_set_tile_union(int max_positions);
 
 /* ----------------------------------- projections, measurement and control */

@@ -186,6 +186,7 @@ int choose_plan(const sv_gate *g, int G, int n, int dtype, int precision, int ru
     mix(uint64_t(max_k + 8));
     mix(cost_version());
     mix(uint64_t(tile_union_limit()));
+    mix(uint64_t(tile_pass_bits()) | uint64_t(tile_pass_capacity()) << 8);
     mix(uint64_t(G));
     for (int i = 0; i < G; ++i) {
         mix(uint64_t(g[i].kind) | uint64_t(g[i].k) << 8);
@@ -1127,6 +1128,7 @@ int dagger_launches(const sv_gate *g, int hi, int lo, const sv_state *s, std::ve
     mix(uint64_t(s->dtype));
     mix(cost_version());
     mix(uint64_t(tile_union_limit()));
+    mix(uint64_t(tile_pass_bits()) | uint64_t(tile_pass_capacity()) << 8);
     mix(uint64_t(cnt));
     for (int t = 0; t < cnt; ++t) {
         mix(uint64_t(dg[t].k));

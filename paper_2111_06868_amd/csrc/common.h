@@ -40,7 +40,7 @@ void reverse_local_bits(const std::vector<cd> &in, int k, std::vector<cd> &out);
 
 // ---------------------------------------------------------------- fusion
 // Tile passes (SV_RULE_TILED): at most kTilePassMaxBlocks blocks of <= 4
-// qubits whose positions span at most kTilePassMaxUnion positions.
+// qubits; kTilePassMaxUnion bounds the union limit (tile_union_limit).
 constexpr int kTilePassMaxBlocks = 16;
 constexpr int kTilePassMaxUnion = 10;
 
@@ -62,10 +62,24 @@ struct CostTable {
 // rule plans passes of at most this many blocks.
 int tile_pass_capacity();
 
+// Tile bits of the current launch shape (13 or 14).
+int tile_pass_bits();
+
 // Union limit of the tile passes that SV_RULE_TILED plans (8 ..
 // kTilePassMaxUnion; default 10, or the SV_TILE_UNION environment variable).
 int tile_union_limit();
 void set_tile_union_limit(int u);
+// The tile of a pass whose blocks cover the positions U is U plus the lowest
+// positions outside it, tile_bits in all; its amplitudes lie in runs of
+// 2^tile_run_bits(U, tile_bits) consecutive ones (its positions 0, 1, .. in a
+// row).
+int tile_run_bits(uint64_t U, int tile_bits);
+// The tiled rule lets a pass cover U when U fits a tile whose runs are at
+// least as long as those of any union of `limit` positions, 2^(tile_bits -
+// limit) amplitudes: every union of at most `limit` positions, and larger
+// ones that hold enough of the lowest positions.  States of fewer than
+// tile_bits qubits keep to `limit` positions.
+bool tile_union_fits(uint64_t U, int n, int tile_bits, int limit);
 
 // Cost table used when no autotuned table exists (relative units).
 CostTable default_costs();

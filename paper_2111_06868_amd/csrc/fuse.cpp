@@ -20,9 +20,9 @@
 //     keeps each qubit's gate sequence, and a block grows by the ready gate
 //     that adds the fewest new positions.
 // The tiled rule applies frontier grouping twice: passes whose positions
-// span at most tile_union_limit() positions, then blocks of at most 4 qubits
-// inside each pass, which a tile kernel applies in one read and one write of
-// the state.
+// form a tile of runs no shorter than those of a tile_union_limit()-position
+// union (tile_union_fits), then blocks of at most 4 qubits inside each pass,
+// which a tile kernel applies in one read and one write of the state.
 #include <algorithm>
 #include <atomic>
 #include <cstdlib>
@@ -59,6 +59,24 @@ static int g_tile_union = [] {
 
 int tile_union_limit() { return g_tile_union; }
 void set_tile_union_limit(int u) { g_tile_union = std::min(std::max(u, 8), kTilePassMaxUnion); }
+
+int tile_run_bits(uint64_t U, int tile_bits)
+{
+    uint64_t t = U;
+    for (int p = 0; p < 64 && __builtin_popcountll(t) < tile_bits; ++p) t |= uint64_t(1) << p;
+    int r = 0;
+    while (r < 64 && ((t >> r) & 1)) ++r;
+    return r;
+}
+
+bool tile_union_fits(uint64_t U, int n, int tile_bits, int limit)
+{
+    // a union of u <= limit positions leaves tile_bits - u fillers, and the
+    // lowest positions 0 .. tile_bits - u - 1 are then all in the tile
+    const int u = __builtin_popcountll(U);
+    if (u <= limit) return true;
+    return n >= tile_bits && u <= tile_bits && tile_run_bits(U, tile_bits) >= tile_bits - limit;
+}
 
 static std::mutex g_cost_mu;
 static std::map<std::pair<int, int>, CostTable> g_costs;
@@ -117,8 +135,8 @@ uint64_t gate_mask(const sv_gate &g)
 // every ready gate (first unapplied gate on each of its qubits) whose
 // positions it already covers, and otherwise widens by the ready gate that
 // adds the fewest positions (the earliest on ties) while it stays within
-// max_union positions.  Members are listed in the order they are applied.
-// Every gate must act on at most max_union qubits.
+// what `fits` accepts (a predicate on position sets).  Members are listed in
+// the order they are applied.  `fits` must accept every gate's own positions.
 class Frontier {
   public:
     Frontier(const sv_gate *g, const std::vector<int> &idx) : idx_(idx), mask_(idx.size()), queue_(64), head_(64, 0)
@@ -134,7 +152,8 @@ class Frontier {
         left_ = G;
     }
     // The next group (gate indices of the caller's list), or false when none is left.
-    bool next(int max_union, std::vector<int> &grp)
+    template <class Fits>
+    bool next(Fits fits, std::vector<int> &grp)
     {
         grp.clear();
         if (left_ <= 0) return false;
@@ -155,7 +174,7 @@ class Frontier {
             int best = -1, best_add = 65;
             for (uint64_t pm = used_; pm; pm &= pm - 1) {
                 const int t = at_head(__builtin_ctzll(pm));
-                if (t < 0 || !ready(t) || popc(U | mask_[t]) > max_union) continue;
+                if (t < 0 || !ready(t) || !fits(U | mask_[t])) continue;
                 const int add = popc(mask_[t] & ~U);
                 if (add < best_add || (add == best_add && t < best)) {
                     best_add = add;
@@ -165,7 +184,7 @@ class Frontier {
             if (best < 0) break;
             U |= mask_[best];
         }
-        return !grp.empty();  // empty only with a gate wider than max_union
+        return !grp.empty();  // empty only with a gate that `fits` refuses
     }
     // Undo the taking of `gates`, which must be, on each of their qubits, the
     // last ones taken there.
@@ -206,7 +225,7 @@ std::vector<std::vector<int>> frontier_groups(const sv_gate *g, const std::vecto
     Frontier f(g, idx);
     std::vector<std::vector<int>> out;
     std::vector<int> grp;
-    while (f.next(max_union, grp)) out.push_back(grp);
+    while (f.next([max_union](uint64_t u) { return popc(u) <= max_union; }, grp)) out.push_back(grp);
     return out;
 }
 
@@ -235,11 +254,12 @@ uint64_t block_mask(const Block &b)
 // few qubits it has.  A block is dissolved into a neighbour when the nearest
 // earlier block (or, failing that, the nearest later one) that shares a qubit
 // with it can take its qubits: the union stays within max_k qubits and the
-// neighbour's pass within max_union positions.  No block in between touches
+// neighbour's pass a union that `pass_fits` accepts.  No block in between touches
 // its qubits, so its gates commute with everything they move past; they join
 // the neighbour's members after (earlier neighbour) or before (later
 // neighbour) its own.  Repeated until no block can go.
-void merge_small_blocks(const sv_gate *g, int max_k, int max_union, std::vector<Block> &blocks)
+template <class Fits>
+void merge_small_blocks(const sv_gate *g, int max_k, Fits pass_fits, std::vector<Block> &blocks)
 {
     (void)g;
     std::vector<uint64_t> mask(blocks.size());
@@ -260,7 +280,7 @@ void merge_small_blocks(const sv_gate *g, int max_k, int max_union, std::vector<
     auto fits = [&](size_t into, uint64_t add) {
         if (popc(mask[into] | add) > max_k) return false;
         const int pass = blocks[into].pass;
-        return pass < 0 || popc(pass_union[size_t(pass)] | add) <= max_union;
+        return pass < 0 || pass_fits(pass_union[size_t(pass)] | add);
     };
     for (bool changed = true; changed;) {
         changed = false;
@@ -442,7 +462,6 @@ static int block_matrices(const sv_gate *g, std::vector<Block> &blocks)
 int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTable &cost,
                std::vector<Block> &blocks, bool with_matrices)
 {
-    (void)n;
     if (max_k < 1 || max_k > SV_MAX_K) return fail(SV_ERR_ARG, "max_k %d outside 1..%d", max_k, SV_MAX_K);
     if (rule != SV_RULE_PAPER && rule != SV_RULE_ENHANCED && rule != SV_RULE_NONE && rule != SV_RULE_TILED)
         return fail(SV_ERR_ARG, "unknown fusion rule %d", rule);
@@ -464,7 +483,9 @@ int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTa
         Frontier passes(g, all);
         std::vector<int> pg;
         int pass = 0;
-        while (passes.next(tile_union_limit(), pg)) {
+        const int tile_bits = tile_pass_bits(), limit = tile_union_limit();
+        auto pass_fits = [n, tile_bits, limit](uint64_t u) { return tile_union_fits(u, n, tile_bits, limit); };
+        while (passes.next(pass_fits, pg)) {
             const auto sub = frontier_groups(g, pg, max_k);
             const size_t e = std::min(sub.size(), cap);
             const size_t first = blocks.size();
@@ -477,7 +498,7 @@ int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTa
             for (size_t c = e; c < sub.size(); ++c) back.insert(back.end(), sub[c].begin(), sub[c].end());
             passes.give_back(back);
         }
-        merge_small_blocks(g, max_k, tile_union_limit(), blocks);
+        merge_small_blocks(g, max_k, pass_fits, blocks);
         return with_matrices ? block_matrices(g, blocks) : SV_OK;
     }
     std::vector<WBlock> wb;

@@ -37,14 +37,14 @@ hipError_t launch_mfma_split(int k, bool fp16, const int *sorted_q, const uint16
                              int n, hipStream_t st, int tc_log, int grid_cap);
 // Multi-block tile passes (complex64, FP32 or split BF16 / FP16 MFMA): up to
 // tile_max_blocks() 4-qubit blocks whose positions have a union of at most
-// kMaxTileUnion positions, applied in one HBM pass over tiles of
+// tile_bits positions, applied in one HBM pass over tiles of
 // 2^tile_bits amplitudes held by workgroups of `waves` waves; shapes
 // (14, 8), (14, 16), (13, 4), (13, 8).  sub_pos rows ascending.  d_a = the
 // blocks' operands (pack_tile_operand), back to back.  Needs n >= tile_bits.
 constexpr int kMaxTileSubBlocks = kTilePassMaxBlocks;
-constexpr int kMaxTileUnion = kTilePassMaxUnion;
 constexpr int kMinTileQubits = 14;
 constexpr int kMaxTileBits = 14;
+constexpr int kMaxTileUnion = kMaxTileBits;
 // Layout and blocks of one tile pass over one state.
 struct TileArgs {
     uint64_t n_tiles;

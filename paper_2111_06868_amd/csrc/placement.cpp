@@ -65,7 +65,7 @@ int placement_conflicts(const uint32_t *img, const TileArgs &a, int tile_bits, i
 // S is then unit lower triangular over GF(2), a permutation of the tile's
 // indices that keeps bit 0.  The first candidate XORs bits 5..8 into bits
 // 1..4; while some block still has conflicts, seeded random candidates
-// (at most 512, the same sequence for every pass) are tried and the best kept.
+// (at most 2048, the same sequence for every pass) are tried and the best kept.
 void search_swizzle(TileArgs &a, int tile_bits, int lane_shift)
 {
     uint32_t best[kMaxTileBits], cand[kMaxTileBits];
@@ -73,7 +73,7 @@ void search_swizzle(TileArgs &a, int tile_bits, int lane_shift)
     // FP32 passes (lane_shift < 0: 4-byte accesses, MFMA-bound) keep the first
     int bc = lane_shift < 0 ? 0 : placement_conflicts(best, a, tile_bits, lane_shift);
     uint64_t x = 0x9E3779B97F4A7C15ull;
-    for (int t = 0; t < 512 && bc > 0; ++t) {
+    for (int t = 0; t < 2048 && bc > 0; ++t) {
         for (int b = 0; b < tile_bits; ++b) {
             cand[b] = 1u << b;
             if (b < 4) continue;

@@ -190,6 +190,8 @@ Tuning &tuning()
     return t;
 }
 
+int tile_pass_bits() { return tuning().tile_bits; }
+
 int tile_pass_capacity()
 {
     const Tuning &t = tuning();

@@ -1,11 +1,11 @@
 // Multi-block tile passes: a sequence of fused blocks of <= 4 qubits applied
 // to a state in ONE read and ONE write of HBM.
 //
-// The blocks of a pass act on a union U of at most kMaxTileUnion positions.
-// A tile is the 2^TB amplitudes (TB = 13 or 14: 64 or 128 KiB of complex64 in
-// LDS) spanned by U plus the lowest TB - |U| positions outside U (tile bit b
-// <-> position u_b, ascending), so it is made of contiguous runs of at least
-// 2^(TB - |U|) amplitudes.  For every value of the remaining n - TB bits there
+// The blocks of a pass act on a union U of at most TB positions.  A tile is
+// the 2^TB amplitudes (TB = 13 or 14: 64 or 128 KiB of complex64 in LDS)
+// spanned by U plus the lowest TB - |U| positions outside U (tile bit b <->
+// position u_b, ascending), so it is made of contiguous runs of at least
+// 2^(TB - |U|) amplitudes, longer when U holds low positions.  For every value of the remaining n - TB bits there
 // is one tile; tiles are copied in and out with 16-byte accesses along those
 // runs (tile bit 0 is always position 0).
 //
@@ -886,7 +886,7 @@ hipError_t make_tile_args(int n_sub, const int (*sub_pos)[4], int n, int tile_bi
             umask |= uint64_t(1) << sub_pos[s][i];
         }
     const int nu = __builtin_popcountll(umask);
-    if (nu > kMaxTileUnion) return hipErrorInvalidValue;
+    if (nu > kTileBits) return hipErrorInvalidValue;
     // tile positions: the union plus the lowest positions outside it
     uint64_t tmask = umask;
     for (int p = 0; p < n && __builtin_popcountll(tmask) < kTileBits; ++p) tmask |= uint64_t(1) << p;

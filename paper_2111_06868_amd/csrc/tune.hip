@@ -460,7 +460,7 @@ extern "C" int sv_tile_placement(int n_sub, const int32_t *sub_pos, int n, int t
     const int tprec = tile_operand_prec(tile_path(precision));
     if (dev::make_tile_args(n_sub, pos, n, tile_bits, waves, tprec, &a) != hipSuccess)
         return fail(SV_ERR_ARG, "blocks need 4 ascending positions below n, with a union of at most %d",
-                    dev::kMaxTileUnion);
+                    tile_bits);
     for (int b = 0; b < tile_bits; ++b) {
         tile_pos[b] = a.ubit[b];
         lds_image[b] = a.swz[b];

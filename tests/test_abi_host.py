@@ -255,11 +255,43 @@ def _valid_order(gates, order):
     return True
 
 
+def _tile_runs(union, tile_bits=14):
+    """log2 of the run length of the tile of a union: the union plus its
+    lowest missing positions, tile_bits in all, then count 0, 1, .. in a row."""
+    tile = set(union)
+    p = 0
+    while len(tile) < tile_bits:
+        tile.add(p)
+        p += 1
+    r = 0
+    while r in tile:
+        r += 1
+    return r
+
+
+def _pass_fits(union, limit=10, tile_bits=14):
+    # the default union limit 10: a tile of 128-byte runs (2^4 amplitudes) or longer
+    return len(union) <= tile_bits and _tile_runs(union, tile_bits) >= tile_bits - limit
+
+
+def test_tile_runs_of_small_unions():
+    """Every union of at most 10 positions gives runs of at least 2^4 amplitudes,
+    so the tile-fit rule only widens the old 10-position limit."""
+    rng = np.random.default_rng(5)
+    for _ in range(2000):
+        u = set(rng.choice(30, size=int(rng.integers(1, 11)), replace=False).tolist())
+        assert _pass_fits(u)
+    assert _tile_runs(range(14)) == 14 and _tile_runs(range(16, 30)) == 0
+    assert _pass_fits(set(range(4)) | set(range(20, 30))) and not _pass_fits(set(range(3)) | set(range(19, 30)))
+
+
 @pytest.mark.parametrize("cfg", [1, 2])
 def test_tiled_plan_structure(cfg):
-    """SV_RULE_TILED: passes of <= 10 positions (the default union limit)
-    made of blocks of <= 4 qubits, consecutive, with every gate once and each
-    qubit's gates in order."""
+    """SV_RULE_TILED: passes whose tiles are made of runs of at least 2^4
+    amplitudes (the default union limit 10: every union of <= 10 positions,
+    and larger ones holding enough low positions), made of blocks of <= 4
+    qubits, consecutive, with every gate once and each qubit's gates in
+    order."""
     n, gates = wc.config_circuit(cfg)
     plan = sv.fuse(to_binding(gates), n, 4, sv.RULE_TILED)
     blocks = plan.blocks(False)
@@ -274,7 +306,8 @@ def test_tiled_plan_structure(cfg):
             assert b.tile_pass not in passes or prev == b.tile_pass  # consecutive
             passes.setdefault(b.tile_pass, set()).update(b.qubits)
         prev = b.tile_pass
-    assert passes and all(len(u) <= 10 for u in passes.values())
+    assert passes and all(_pass_fits(u) for u in passes.values())
+    assert any(len(u) > 10 for u in passes.values())  # the grid circuits use the wider unions
     # at most one launch's capacity of blocks per pass
     cap = sv.get_tile_shape()[2]
     per_pass = {}
@@ -289,9 +322,9 @@ def test_tiled_plan_structure(cfg):
         prev_b = next((blocks[j] for j in range(i - 1, -1, -1) if set(blocks[j].qubits) & m), None)
         if prev_b is not None and len(m | set(prev_b.qubits)) <= 4:
             u = passes.get(prev_b.tile_pass, set(prev_b.qubits))
-            assert prev_b.tile_pass >= 0 and len(u | m) > 10
+            assert prev_b.tile_pass >= 0 and not _pass_fits(u | m)
     n_launch = len(passes) + sum(1 for b in blocks if b.tile_pass < 0)
-    # far fewer state passes than blocks (30 q: 26 passes for 845 gates)
+    # far fewer state passes than blocks (30 q: 22 passes for 845 gates)
     assert n_launch <= len(blocks) // 3
 
 
@@ -318,7 +351,8 @@ def test_enhanced_rule_frontier_counts():
 
 
 def test_tile_union_setting():
-    """The tiled rule keeps every pass within the configured union limit."""
+    """The tiled rule keeps every pass's tile to runs of at least
+    2^(14 - limit) amplitudes for the configured union limit."""
     n, gates = wc.config_circuit(2)
     g = to_binding(gates)
     counts = {}
@@ -330,7 +364,7 @@ def test_tile_union_setting():
             for b in blocks:
                 if b.tile_pass >= 0:
                     unions.setdefault(b.tile_pass, set()).update(b.qubits)
-            assert max(len(x) for x in unions.values()) <= u
+            assert all(_pass_fits(x, limit=u) for x in unions.values())
             counts[u] = len(unions) + sum(1 for b in blocks if b.tile_pass < 0)
         for bad in (7, 11, 0):
             with pytest.raises(ValueError):

@@ -54,6 +54,15 @@ def test_plan_listing_covers_every_pass():
         assert int(fields["s"]) == len(blocks)
         assert set().union(*blocks) == union
         assert all(1 <= len(b) <= 4 for b in blocks)
-        assert len(union) <= 10
+        # the tile (the union plus its lowest missing positions, 14 in all)
+        # is made of runs of at least 2^4 amplitudes
+        tile, p = set(union), 0
+        while len(tile) < 14:
+            tile.add(p)
+            p += 1
+        run = 0
+        while run in tile:
+            run += 1
+        assert len(union) <= 14 and (len(union) <= 10 or run >= 4), row
         total += len(blocks)
     assert total == int(head["blocks"])

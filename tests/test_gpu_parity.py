@@ -411,10 +411,78 @@ def test_tiled_passes_every_shape(shape, precision, n):
         assert fe <= 1e-10 and ma <= 1e-6
 
 
+def _tile_runs(union, tile_bits):
+    """log2 of the HBM run length of a pass's tile: the union plus its lowest
+    missing positions, tile_bits in all, then count positions 0, 1, .. in a row."""
+    tile, p = set(union), 0
+    while len(tile) < tile_bits:
+        tile.add(p)
+        p += 1
+    r = 0
+    while r in tile:
+        r += 1
+    return r
+
+
+def _wide_circuit(n, seed):
+    """Gates that the tiled rule packs into passes of more than 10 positions:
+    pairs on positions 0..13 (a pass whose union is a whole 14-bit tile), then
+    gates on 0..3 and the top ten positions (unions of 11..13 that keep
+    128-byte runs), then random gates everywhere."""
+    rng = np.random.default_rng(seed)
+    two_pi = 2 * math.pi
+    gates = [Gate("H", (q,), ()) for q in range(14)]
+    gates += [Gate("FSIM", (2 * i, 2 * i + 1), (float(rng.uniform(0, two_pi)), float(rng.uniform(0, two_pi))))
+              for i in range(7)]
+    gates += [Gate(g.name, tuple(q if q < 4 else q + n - 14 for q in g.qubits), g.params)
+              for g in wc.random_gate_list(14, 60, rng, max_k=2)]
+    return gates + wc.random_gate_list(n, 6 * n, rng, max_k=2)
+
+
+@pytest.mark.parametrize("shape", [(14, 16), (14, 8), (13, 8)])
+@pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16", "bf16x3"])
+@pytest.mark.parametrize("n", [16, 19])
+def test_tiled_wide_unions(shape, precision, n):
+    """Passes of 11..14 positions (a tile with no filler positions, and
+    unions that hold positions 0..3 beside high ones) against the oracle."""
+    tb = shape[0]
+    gates = _wide_circuit(n, 40 + n)
+    prec, fam = _TILE_PREC[precision]
+    sv.set_tile_shape(*shape)
+    sv.stats_reset()
+    sv.stats_enable(True)
+    try:
+        plan = sv.fuse(to_binding(gates), n, 4, sv.RULE_TILED)
+        unions = {}
+        for b in plan.blocks(False):
+            if b.tile_pass >= 0:
+                unions.setdefault(b.tile_pass, set()).update(b.qubits)
+        sizes = sorted(len(u) for u in unions.values())
+        assert all(len(u) <= tb and _tile_runs(u, tb) >= tb - 10 for u in unions.values()), unions
+        assert sizes[-1] >= 13
+        if tb == 14 and n == 16:
+            assert sizes[-1] == 14
+        want, got, st = run_both(n, gates, "+", "c64", max_k=4, rule=sv.RULE_TILED, precision=prec)
+        st.synchronize()
+        tiles = sum(sv.stats_query(fam, s)[0] for s in range(1, sv.MAX_TILE_LAUNCH_BLOCKS + 1))
+    finally:
+        sv.stats_enable(False)
+        sv.stats_reset()
+        sv.set_tile_shape(14, 16)
+    fe, ma = _report("tiled %s shape=%s n=%d unions %s" % (precision, shape, n, sizes), want, got)
+    assert tiles >= len(unions)
+    assert fe <= FID_C64
+    if precision != "bf16":
+        assert ma <= 1e-5
+    if precision == "bf16x3":
+        assert fe <= 1e-10 and ma <= 1e-6
+
+
 @pytest.mark.parametrize("union", [8, 9, 10])
 @pytest.mark.parametrize("precision", ["fp32", "bf16", "fp16", "bf16x3"])
 def test_tiled_union_limits(union, precision):
-    """Passes planned with 8, 9 and 10 positions (shorter HBM runs, more blocks)."""
+    """Passes planned with union limits 8, 9 and 10 (HBM runs of at least
+    2^(14 - limit) amplitudes: shorter runs, more blocks per pass)."""
     n = 17
     rng = np.random.default_rng(1300 + union)
     gates = wc.random_gate_list(n, 12 * n, rng, max_k=2)
@@ -426,7 +494,7 @@ def test_tiled_union_limits(union, precision):
         for b in plan.blocks(False):
             if b.tile_pass >= 0:
                 unions.setdefault(b.tile_pass, set()).update(b.qubits)
-        assert unions and max(len(u) for u in unions.values()) <= union
+        assert unions and all(_tile_runs(u, 14) >= 14 - union for u in unions.values())
         want, got, _ = run_both(n, gates, "+", "c64", max_k=4, rule=sv.RULE_TILED, precision=prec)
     finally:
         sv.set_tile_union(10)

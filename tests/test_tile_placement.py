@@ -127,7 +127,7 @@ def test_placement_is_a_permutation_keeping_pairs():
             assert np.array_equal(np.sort(full), np.arange(1 << tb))
 
 
-@pytest.mark.parametrize("cfg,most", [(1, 0), (2, 1)])
+@pytest.mark.parametrize("cfg,most", [(1, 0), (2, 0)])
 def test_benchmark_passes_bank_conflicts(cfg, most):
     """The library's count of extra LDS cycles equals what the address model
     finds (per block: cycles over ideal - 1, summed over both bank models),
@@ -161,6 +161,9 @@ def test_default_placement_had_conflicts_and_model_agrees():
 def test_other_shapes_free_of_bank_conflicts(tb, waves, cap):
     for n, blocks in _passes(1)[:8]:
         blocks = blocks[:cap]
+        u = set(q for b in blocks for q in b)
+        if len(u) > tb or (len(u) == tb and 0 not in u):
+            continue  # no tb-bit tile holds it with position 0 as tile bit 0
         tp, img, conflicts = sv.tile_placement(blocks, n, tb, waves)
         assert conflicts == 0
         for b in blocks:
