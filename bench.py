@@ -280,7 +280,7 @@ def main():
         del scratch
         log("autotuned cost table (ms per block, k=1..6): %s" % ", ".join("%.3f" % c for c in cost[1:]))
         max_k = -1
-    plan = sv.fuse(ga, n, max_k, rule)
+    plan = sv.fuse(ga, n, max_k, rule, precision=prec)  # the plan the runs below form
     if max_k == -1 or rule == sv.RULE_AUTO:
         # the plan records what was chosen; the timed steps fuse with that choice
         max_k = plan.max_k
@@ -380,7 +380,7 @@ def main():
     # host planning (fusion and block matrices), which each step repeats before its launches
     t1 = time.perf_counter()
     for _ in range(5):
-        sv.fuse(ga, n, args.max_k, rule)
+        sv.fuse(ga, n, args.max_k, rule, precision=prec)
     host_plan_ms = 1e3 * (time.perf_counter() - t1) / 5
 
     extra = {}
@@ -492,7 +492,8 @@ def print_plan(args, tile_bits=14, page_bits=18):
     ga = sv.GateArray([(g.name, g.qubits, g.params) for g in gates])
     rule = {"enhanced": sv.RULE_ENHANCED, "paper": sv.RULE_PAPER, "tiled": sv.RULE_TILED,
             "auto": sv.RULE_AUTO}[args.rule]
-    blocks = sv.fuse(ga, n, args.max_k, rule).blocks(False)
+    prec = PRECISIONS[args.precision]
+    blocks = sv.fuse(ga, n, args.max_k, rule, precision=prec).blocks(False)
     tiles = plan_tiles(blocks, n, tile_bits, page_bits)
     print("n=%d gates=%d blocks=%d passes=%d" % (n, len(gates), len(blocks), len(tiles)))
     for i, t in enumerate(tiles):

@@ -213,6 +213,15 @@ int sv_apply_gate(sv_state *s, const sv_gate *g);
  * autotuned cost table for n (SV_ERR_ARG if there is none).
  * The plan is owned by the caller and released with sv_plan_free. */
 int sv_fuse(const sv_gate *g, int G, int n, int max_k, int rule, sv_plan **out);
+/* sv_fuse for a run in `precision` (SV_PREC_*): the plan sv_run_circuit forms
+ * with that precision.  The tiled rule then fills each pass up to what one
+ * launch holds with that precision's operands (7 blocks for SV_PREC_FP32 and
+ * SV_PREC_SPLIT_FP16 at (14, *), 5 for the split BF16 forms; sv_fuse plans
+ * for 5, which every precision takes), and SV_RULE_AUTO and max_k = -1 use
+ * that precision's cost table (sv_fuse: FP32's).  A plan applied in another
+ * precision stays correct: a pass of more blocks than one launch holds runs
+ * as several launches.  SV_ERR_ARG for an unknown precision. */
+int sv_fuse_prec(const sv_gate *g, int G, int n, int max_k, int rule, int precision, sv_plan **out);
 int sv_plan_free(sv_plan *p);
 /* Number of blocks; for block b: its size k, its positions q[0..k-1] (array of
  * SV_MAX_K) and its member count. */
@@ -523,14 +532,17 @@ int sv_tune_cache_load(const char *path, int *loaded);
  * tiles of 2^tile_bits amplitudes held in LDS by workgroups of `waves`
  * 64-lane waves.  Supported: (14, 8) and (14, 16), one 128 KiB tile per
  * compute unit; (13, 4), two 64 KiB workgroups per compute unit; (13, 8).
- * A launch holds at most 5 blocks ((14, *)), 2 ((13, 4)) or 15 ((13, 8));
- * the tiled rule plans passes of at most that many blocks (the gates of a
- * further block go to the next pass).  sv_autotune
+ * A launch holds at most 5 blocks ((14, *)), 2 ((13, 4)) or 15 ((13, 8))
+ * with split BF16 operands, and 7, 3 or 16 with the smaller FP32 and split
+ * FP16 ones; the tiled rule plans passes of at most that many blocks for the
+ * run's precision (the gates of a further block go to the next pass).
+ * sv_autotune
  * picks one itself; this call overrides it for the whole process (later
  * launches on every state).  SV_ERR_ARG for other pairs. */
 int sv_set_tile_shape(int tile_bits, int waves);
 /* The current launch shape of the tile passes and the number of blocks one
- * launch of it holds (pointers may be NULL). */
+ * launch of it holds with split BF16 operands, the fewest of any precision
+ * (pointers may be NULL). */
 int sv_get_tile_shape(int *tile_bits, int *waves, int *max_blocks);
 /* Layout of one tile pass of n_sub 4-qubit blocks (sub_pos: 4 ascending
  * positions per block, n_sub rows) on an n-qubit complex64 state, as the

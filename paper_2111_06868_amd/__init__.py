@@ -639,12 +639,17 @@ class Block:
 
 
 class Plan:
-    """A fused plan (sv_fuse); blocks are read back on demand."""
+    """A fused plan (sv_fuse, or sv_fuse_prec for a given precision); blocks
+    are read back on demand."""
 
-    def __init__(self, gates, n: int, max_k: int, rule: int = RULE_PAPER):
+    def __init__(self, gates, n: int, max_k: int, rule: int = RULE_PAPER, precision: int = None):
         ga = gates if isinstance(gates, GateArray) else GateArray(gates)
         h = ctypes.c_void_p()
-        N.check(N.lib().sv_fuse(ga.ptr, ga.n, int(n), int(max_k), int(rule), ctypes.byref(h)))
+        if precision is None:
+            N.check(N.lib().sv_fuse(ga.ptr, ga.n, int(n), int(max_k), int(rule), ctypes.byref(h)))
+        else:
+            N.check(N.lib().sv_fuse_prec(ga.ptr, ga.n, int(n), int(max_k), int(rule), int(precision),
+                                         ctypes.byref(h)))
         self.h = h
         self.n = n
 
@@ -694,8 +699,8 @@ class Plan:
         return [self.block(b, with_matrix) for b in range(len(self))]
 
 
-def fuse(gates, n: int, max_k: int, rule: int = RULE_PAPER) -> Plan:
-    return Plan(gates, n, max_k, rule)
+def fuse(gates, n: int, max_k: int, rule: int = RULE_PAPER, precision: int = None) -> Plan:
+    return Plan(gates, n, max_k, rule, precision)
 
 
 # ------------------------------------------------------------------ gradients

@@ -104,6 +104,7 @@ SIGNATURES = {
     "sv_gate_matrix": (_I, [_GP, _D]),
     "sv_apply_gate": (_I, [_P, _GP]),
     "sv_fuse": (_I, [_GP, _I, _I, _I, _I, ctypes.POINTER(_P)]),
+    "sv_fuse_prec": (_I, [_GP, _I, _I, _I, _I, _I, ctypes.POINTER(_P)]),
     "sv_plan_free": (_I, [_P]),
     "sv_plan_num_blocks": (_I, [_P, ctypes.POINTER(_I)]),
     "sv_plan_block": (_I, [_P, _I, _I32P, _I32P, _I32P]),

@@ -186,7 +186,7 @@ int choose_plan(const sv_gate *g, int G, int n, int dtype, int precision, int ru
     mix(uint64_t(max_k + 8));
     mix(cost_version());
     mix(uint64_t(tile_union_limit()));
-    mix(uint64_t(tile_pass_bits()) | uint64_t(tile_pass_capacity()) << 8);
+    mix(uint64_t(tile_pass_bits()) | uint64_t(tile_pass_capacity(precision)) << 8);
     mix(uint64_t(G));
     for (int i = 0; i < G; ++i) {
         mix(uint64_t(g[i].kind) | uint64_t(g[i].k) << 8);
@@ -230,7 +230,7 @@ int choose_plan_uncached(const sv_gate *g, int G, int n, int dtype, int precisio
         for (int k = kmin; k <= khi; ++k) {
             if (!found && k == SV_MAX_K) break;  // untuned: stay below the MFMA-bound size
             std::vector<Block> blocks;
-            if (int rc = fuse_gates(g, G, n, k, r, cost, blocks, false)) return rc;
+            if (int rc = fuse_gates(g, G, n, k, r, cost, blocks, false, precision)) return rc;
             const double c = r == SV_RULE_TILED ? tiled_plan_cost(blocks, n, cost) : plan_cost(blocks, cost);
             if (c < best - 1e-12) {
                 best = c;
@@ -452,29 +452,48 @@ int apply_gate_impl(sv_state *s, const sv_gate *g)
 }  // namespace
 
 // ============================================================== fusion
-extern "C" int sv_fuse(const sv_gate *g, int G, int n, int max_k, int rule, sv_plan **out)
+namespace {
+
+// precision < 0: FP32 cost tables, tile passes sized for operands of any precision
+int fuse_plan(const sv_gate *g, int G, int n, int max_k, int rule, int precision, sv_plan **out)
 {
-    clear_error();
     if (!out) return fail(SV_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (n < 1 || n > SV_MAX_QUBITS_C64) return fail(SV_ERR_ARG, "n = %d outside 1..%d", n, SV_MAX_QUBITS_C64);
+    if (precision < -1 || precision > SV_PREC_SPLIT_BF16X3) return fail(SV_ERR_ARG, "precision %d", precision);
     if (int rc = validate_gates(g, G, n)) return rc;
     if (rule < SV_RULE_PAPER || rule > SV_RULE_AUTO) return fail(SV_ERR_ARG, "unknown fusion rule %d", rule);
+    const int cost_prec = precision < 0 ? SV_PREC_FP32 : precision;
     if (max_k == -1 || rule == SV_RULE_AUTO) {
         if (max_k != -1 && (max_k < 1 || max_k > SV_MAX_K)) return fail(SV_ERR_ARG, "max_k %d", max_k);
-        if (int rc = choose_plan(g, G, n, SV_C64, SV_PREC_FP32, rule, max_k, &rule, &max_k)) return rc;
+        if (int rc = choose_plan(g, G, n, SV_C64, cost_prec, rule, max_k, &rule, &max_k)) return rc;
     }
     auto *p = new sv_plan;
     p->n = n;
     p->max_k = max_k;
     p->rule = rule;
-    int rc = fuse_gates(g, G, n, max_k, rule, lookup_costs(n, SV_PREC_FP32, nullptr), p->blocks);
+    int rc = fuse_gates(g, G, n, max_k, rule, lookup_costs(n, cost_prec, nullptr), p->blocks, true, precision);
     if (rc) {
         delete p;
         return rc;
     }
     *out = p;
     return SV_OK;
+}
+
+}  // namespace
+
+extern "C" int sv_fuse(const sv_gate *g, int G, int n, int max_k, int rule, sv_plan **out)
+{
+    clear_error();
+    return fuse_plan(g, G, n, max_k, rule, -1, out);
+}
+
+extern "C" int sv_fuse_prec(const sv_gate *g, int G, int n, int max_k, int rule, int precision, sv_plan **out)
+{
+    clear_error();
+    if (precision < 0) return fail(SV_ERR_ARG, "precision %d", precision);
+    return fuse_plan(g, G, n, max_k, rule, precision, out);
 }
 
 extern "C" int sv_plan_free(sv_plan *p)
@@ -598,7 +617,9 @@ int run_circuit_impl(sv_state *s, const sv_gate *g, int G, const sv_run_opts *o)
         if (int rc = choose_plan(g, G, s->n, s->dtype, o->precision, rule, max_k, &rule, &max_k)) return rc;
     }
     std::vector<Block> blocks;
-    if (int rc = fuse_gates(g, G, s->n, max_k, rule, lookup_costs(s->n, o->precision, nullptr), blocks)) return rc;
+    if (int rc = fuse_gates(g, G, s->n, max_k, rule, lookup_costs(s->n, o->precision, nullptr), blocks, true,
+                            o->precision))
+        return rc;
     std::vector<Launch> L;
     blocks_to_launches(blocks, s, o->precision, rule, L);
     if (int rc = select_device(s)) return rc;
@@ -1128,7 +1149,7 @@ int dagger_launches(const sv_gate *g, int hi, int lo, const sv_state *s, std::ve
     mix(uint64_t(s->dtype));
     mix(cost_version());
     mix(uint64_t(tile_union_limit()));
-    mix(uint64_t(tile_pass_bits()) | uint64_t(tile_pass_capacity()) << 8);
+    mix(uint64_t(tile_pass_bits()) | uint64_t(tile_pass_capacity(prec)) << 8);
     mix(uint64_t(cnt));
     for (int t = 0; t < cnt; ++t) {
         mix(uint64_t(dg[t].k));
@@ -1165,7 +1186,7 @@ int dagger_launches(const sv_gate *g, int hi, int lo, const sv_state *s, std::ve
                 if (int rc = fuse_gates(dg.data(), cnt, s->n, kbest, SV_RULE_ENHANCED, cost, blocks, false)) return rc;
                 best = plan_cost(blocks, cost);
             }
-            if (int rc = fuse_gates(dg.data(), cnt, s->n, 4, SV_RULE_TILED, cost, blocks, false)) return rc;
+            if (int rc = fuse_gates(dg.data(), cnt, s->n, 4, SV_RULE_TILED, cost, blocks, false, prec)) return rc;
             if (tiled_plan_cost(blocks, s->n, cost) < best - 1e-12) choice = 0;
         }
         std::lock_guard<std::mutex> lk(memo_mu);
@@ -1173,7 +1194,7 @@ int dagger_launches(const sv_gate *g, int hi, int lo, const sv_state *s, std::ve
         memo[key] = choice;
     }
     if (choice == 0) {
-        if (int rc = fuse_gates(dg.data(), cnt, s->n, 4, SV_RULE_TILED, cost, blocks)) return rc;
+        if (int rc = fuse_gates(dg.data(), cnt, s->n, 4, SV_RULE_TILED, cost, blocks, true, prec)) return rc;
         std::vector<Launch> tl;
         group_tile_passes(blocks, s->n, prec, tl);
         for (auto &L : tl) out.push_back(std::move(L));

@@ -293,7 +293,7 @@ int build_schedule(sv_batch *b, const sv_batch_desc *d, int k)
     std::vector<std::vector<int>> large_passes;  // per large trajectory: its pass indices
     std::vector<BZUnit> zunits;
     const CostTable cost = default_costs();
-    const int max_sub = dev::tile_max_blocks(dev::kBatchTileBits, dev::kBatchTileWaves);
+    const int max_sub = dev::tile_max_blocks(dev::kBatchTileBits, dev::kBatchTileWaves, b->tile_prec);
     for (int t = 0; t < d->n_traj; ++t) {
         const int n = d->n_qubits[t];
         const sv_gate *g = d->gates + d->gate_offsets[t];
@@ -321,7 +321,7 @@ int build_schedule(sv_batch *b, const sv_batch_desc *d, int k)
         }
         // tiled plan: groups of consecutive blocks of one pass, at most max_sub per launch
         std::vector<Block> fb;
-        if (int rc = fuse_gates(g, G, n, std::min(kk, 4), SV_RULE_TILED, cost, fb)) return rc;
+        if (int rc = fuse_gates(g, G, n, std::min(kk, 4), SV_RULE_TILED, cost, fb, true, d->precision)) return rc;
         std::vector<int> mine;
         for (const auto &grp : tile_groups(fb, n)) {
             for (size_t c = 0; c < grp.size(); c += size_t(max_sub)) {

@@ -58,9 +58,11 @@ struct CostTable {
     double tile[kTilePassMaxBlocks + 1] = {0};  // one tile pass holding s blocks of 4 qubits
 };
 
-// Blocks one tile-pass launch of the current launch shape holds; the tiled
-// rule plans passes of at most this many blocks.
-int tile_pass_capacity();
+// Blocks one tile-pass launch of the current launch shape holds with the
+// operands of `precision` (SV_PREC_*; -1: of any precision, the split BF16
+// capacity, the smallest); the tiled rule plans passes of at most this many
+// blocks.
+int tile_pass_capacity(int precision = -1);
 
 // Tile bits of the current launch shape (13 or 14).
 int tile_pass_bits();
@@ -90,9 +92,10 @@ void store_costs(int n, int precision, const double *ms, const double *tile = nu
 uint64_t cost_version();
 
 // Greedy fusion.  Gates must be validated first.  `cost` steers the
-// enhanced rule.  Fills blocks (with canonical matrices).
+// enhanced rule.  Fills blocks (with canonical matrices).  The tiled rule
+// plans passes of at most tile_pass_capacity(precision) blocks.
 int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTable &cost,
-               std::vector<Block> &blocks, bool with_matrices = true);
+               std::vector<Block> &blocks, bool with_matrices = true, int precision = -1);
 double plan_cost(const std::vector<Block> &blocks, const CostTable &cost);
 // Tile grouping (see group_tile_passes): groups of block indices, in
 // application order (consecutive blocks of one tile pass); a group of one is

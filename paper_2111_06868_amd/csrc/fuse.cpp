@@ -460,7 +460,7 @@ static int block_matrices(const sv_gate *g, std::vector<Block> &blocks)
 }
 
 int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTable &cost,
-               std::vector<Block> &blocks, bool with_matrices)
+               std::vector<Block> &blocks, bool with_matrices, int precision)
 {
     if (max_k < 1 || max_k > SV_MAX_K) return fail(SV_ERR_ARG, "max_k %d outside 1..%d", max_k, SV_MAX_K);
     if (rule != SV_RULE_PAPER && rule != SV_RULE_ENHANCED && rule != SV_RULE_NONE && rule != SV_RULE_TILED)
@@ -477,7 +477,7 @@ int fuse_gates(const sv_gate *g, int G, int n, int max_k, int rule, const CostTa
         // next pass can take them with its own gates.  They follow the kept
         // blocks on every qubit they share, so on each of their qubits they
         // are the last gates taken.
-        const size_t cap = size_t(std::max(1, tile_pass_capacity()));
+        const size_t cap = size_t(std::max(1, tile_pass_capacity(precision)));
         std::vector<int> all(G);
         for (int i = 0; i < G; ++i) all[i] = i;
         Frontier passes(g, all);

@@ -100,8 +100,10 @@ hipError_t launch_tile_batch(const TileUnit *units, int n_units, const TilePass 
 bool tile_supported(int n, int union_bits);
 bool tile_shape_supported(int tile_bits, int waves);
 int tile_wgs_per_cu(int tile_bits, int waves);
-// Blocks one launch of the shape can hold (their operands sit in LDS).
-int tile_max_blocks(int tile_bits, int waves);
+// Blocks one launch of the shape can hold with operands of precision prec
+// (kTileOperand*; they sit in LDS: FP32 and FP16 operands are smaller than
+// split BF16 ones, so more fit).
+int tile_max_blocks(int tile_bits, int waves, int prec);
 // The FP16 tile passes of one run and the state's norm, which their unitary
 // blocks keep: the first pass (out) writes each workgroup's sum of squares of
 // the values it reads, one double per workgroup of its grid; later passes

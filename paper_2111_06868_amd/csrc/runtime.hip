@@ -192,10 +192,11 @@ Tuning &tuning()
 
 int tile_pass_bits() { return tuning().tile_bits; }
 
-int tile_pass_capacity()
+int tile_pass_capacity(int precision)
 {
     const Tuning &t = tuning();
-    return dev::tile_max_blocks(t.tile_bits, t.tile_waves);
+    const int prec = precision < 0 ? dev::kTileOperandBF16 : tile_operand_prec(tile_path(precision));
+    return dev::tile_max_blocks(t.tile_bits, t.tile_waves, prec);
 }
 
 Path choose_path(int dtype, int precision, int k, const int *q, int n)
@@ -438,7 +439,7 @@ int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, cons
         }
         if (is_tile_path(L.path)) {
             // one launch per chunk of blocks whose operands fit the shape's LDS
-            const int cap = dev::tile_max_blocks(T.tile_bits, T.tile_waves);
+            const int cap = dev::tile_max_blocks(T.tile_bits, T.tile_waves, tile_operand_prec(L.path));
             const size_t op_bytes = 4 * dev::kTileOperandWords;
             const int grid_cap = T.tile_grid_cap * dev::tile_wgs_per_cu(T.tile_bits, T.tile_waves);
             const uint64_t n_tiles = uint64_t(1) << (n - T.tile_bits);

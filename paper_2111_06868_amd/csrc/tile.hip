@@ -45,19 +45,19 @@ typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 constexpr int kPrecF32 = kTileOperandF32, kPrecBF16 = kTileOperandBF16, kPrecF16 = kTileOperandF16,
               kPrecBF16X3 = kTileOperandBF16X3;
 
-// LDS words of one block's operand: the A' fragments of the 64 lanes, 24
-// words per lane (FP32: 16; split: 8 per part), expanded at staging so that
-// the block loop reads them as they are.
-constexpr int kLaneWords = 24;
-constexpr int kOperandWords = 64 * kLaneWords;
+// LDS words per lane of one block's operand (the A' fragments of the 64
+// lanes, expanded at staging so that the block loop reads them as they are):
+// FP32 16, split 8 per matrix part (FP16: two parts, BF16: three).  The
+// smaller FP32 and FP16 operands let more blocks share a launch.
+constexpr int lane_words(int prec) { return prec == kPrecBF16 || prec == kPrecBF16X3 ? 24 : 16; }
 
 // Tile of 2^TB amplitudes held by a workgroup of WAVES waves: 2^TB / 16
 // columns per 4-qubit block, in blocks of 32 split evenly over the waves.
 // Shapes: (14, 8) and (14, 16) one 128 KiB tile per CU, with 2 or 4 waves
 // per SIMD; (13, 4) two 64 KiB workgroups per CU, so one can copy while the
-// other computes; (13, 8).  MAX_SUB blocks' operands fit in the LDS left
-// beside the tile.
-template <int TB, int WAVES>
+// other computes; (13, 8).  MAX_SUB blocks' operands of LW words per lane
+// fit in the LDS left beside the tile.
+template <int TB, int WAVES, int LW = 24>
 struct TileCfg {
     static constexpr int N = 1 << TB;
     static constexpr int THREADS = 64 * WAVES;
@@ -68,7 +68,8 @@ struct TileCfg {
     static constexpr int TABLE_WORDS = CBLOCKS + 32;
     // two (13, 4) workgroups share a CU; the others hold the CU alone
     static constexpr int LDS_BUDGET = (TB == 13 && WAVES == 4) ? 160 * 1024 / 2 : 160 * 1024;
-    static constexpr int FIT = (LDS_BUDGET - N * 8) / (4 * (kOperandWords + TABLE_WORDS));
+    static constexpr int OPERAND_WORDS = 64 * LW;
+    static constexpr int FIT = (LDS_BUDGET - N * 8 - 8 * WAVES) / (4 * (OPERAND_WORDS + TABLE_WORDS));
     static constexpr int MAX_SUB = FIT < kMaxTileSubBlocks ? FIT : kMaxTileSubBlocks;
     static_assert(THREADS % 256 == 0 && THREADS <= 1024 && NB_PER_WAVE >= 1, "tile shape");
 };
@@ -262,11 +263,11 @@ __device__ __forceinline__ void norm_scale(double r, float &scale, float &unscal
 // FP32 c = 32 cb + l32; split c = (32 w + l32) NBW + q, which puts q on the
 // lowest column bits, so that when tile bit 0 is a column bit the column
 // blocks q and q + 1 of a lane share one 16-byte slot.
-template <int TB, int WAVES>
+template <int TB, int WAVES, int LW>
 struct TileShared {
-    using C = TileCfg<TB, WAVES>;
+    using C = TileCfg<TB, WAVES, LW>;
     vf4 X4[C::N / 2];
-    uint32_t op[C::MAX_SUB][kOperandWords];
+    uint32_t op[C::MAX_SUB][C::OPERAND_WORDS];
     uint32_t cq[C::MAX_SUB][C::CBLOCKS];
     uint32_t cl[C::MAX_SUB][32];
     float red[WAVES];  // per-wave partial of the next tile's scale (FP16 passes)
@@ -274,8 +275,8 @@ struct TileShared {
 };
 
 // Stage the launch's blocks: each lane's A' fragments, expanded from the
-// compact operands (pack_tile_operand) into kLaneWords consecutive words per
-// lane, and the column tables.  Lane (half, l32) takes row r = l32 of A' =
+// compact operands (pack_tile_operand) into lane_words(PREC) consecutive
+// words per lane, and the column tables.  Lane (half, l32) takes row r = l32 of A' =
 // [[Ur,-Ui],[Ui,Ur]] interleaved by (re, im): complex row ci = r / 2, part
 // ri = r % 2.
 //   FP32: word j < 16 = A'[r][2 j + half], i.e. Ur[ci][j] (ri == half),
@@ -283,17 +284,13 @@ struct TileShared {
 //   split: word 8 p + 4 i + e (part p = 0..2, step i = 0, 1, e = 0..3) holds
 //   the 16-bit pair A'[r][16 i + 8 half + 2 e + {0, 1}] of part p: (Ur, -Ui)
 //   for ri = 0, (Ui, Ur) for ri = 1, at complex column j = 8 i + 4 half + e.
-// Words an arithmetic does not read (FP32 and FP16: 16..23) are not written.
 template <int TB, int WAVES, int PREC>
-__device__ __forceinline__ void stage_blocks(TileShared<TB, WAVES> &sh, const uint32_t *A, const TileArgs &args,
-                                             int tid)
+__device__ __forceinline__ void stage_blocks(TileShared<TB, WAVES, lane_words(PREC)> &sh, const uint32_t *A,
+                                             const TileArgs &args, int tid)
 {
-    using C = TileCfg<TB, WAVES>;
+    using C = TileCfg<TB, WAVES, lane_words(PREC)>;
     constexpr bool SPLIT = PREC != kPrecF32;
-    // words of a lane's fragments that the block loop reads: FP32 16, split
-    // 8 per part (FP16: two parts, BF16: three)
-    constexpr int USED = !SPLIT ? 16 : (PREC == kPrecF16 ? 16 : 24);
-    static_assert(USED <= kLaneWords, "fragment words");
+    constexpr int USED = lane_words(PREC);  // every word is read by the block loop
     const int nsub = args.n_sub;
     for (int e = tid; e < nsub * 64 * USED; e += C::THREADS) {
         const int s = e / (64 * USED), r = e % (64 * USED);
@@ -309,7 +306,7 @@ __device__ __forceinline__ void stage_blocks(TileShared<TB, WAVES> &sh, const ui
             const uint32_t w = cop[part * 256 + ci * 16 + 8 * i + 4 * half + e4];
             v = ri ? ((w >> 16) | (w << 16)) : (w ^ 0x80000000u);
         }
-        sh.op[s][lane * kLaneWords + wd] = v;
+        sh.op[s][lane * USED + wd] = v;
     }
     for (int e = tid; e < nsub * (C::CBLOCKS + 32); e += C::THREADS) {
         const int s = e / (C::CBLOCKS + 32), r = e % (C::CBLOCKS + 32);
@@ -335,18 +332,38 @@ __device__ __forceinline__ void lds_st(char *Xb, uint32_t byte_off, float re, fl
 
 // hi = RNE(v), lo = RNE(v - hi) and, with three parts, lo2 = RNE(v - hi - lo)
 // of one (re, im) pair, as packed 16-bit pairs (H2 = bf16x2 or f16x2).  The
-// differences are exact in FP32.
+// differences are exact in FP32.  FP16 (two parts): lo = RNE(hi * m1 + v)
+// with hi read as FP16 and m1 = -1 held in a register (minus_one()), one
+// mixed-precision FMA per value (the compiler rounds some of them straight
+// to FP16 in the same instruction): the same bits as a conversion back, a
+// subtraction and a second conversion.
 template <int NS, typename H2>
-__device__ __forceinline__ void split_pair(float re, float im, H2 *parts)
+__device__ __forceinline__ void split_pair(float re, float im, H2 *parts, float m1)
 {
     vf2 v;
     v.x = re;
     v.y = im;
+    if constexpr (std::is_same<H2, f16x2>::value) {
+        static_assert(NS == 2, "FP16 splits in two parts");
+        parts[0] = __builtin_convertvector(v, H2);
+        parts[1].x = static_cast<_Float16>(__builtin_fmaf(float(parts[0].x), m1, v.x));
+        parts[1].y = static_cast<_Float16>(__builtin_fmaf(float(parts[0].y), m1, v.y));
+    } else {
 #pragma unroll
-    for (int j = 0; j < NS; ++j) {
-        parts[j] = __builtin_convertvector(v, H2);
-        if (j + 1 < NS) v -= __builtin_convertvector(parts[j], vf2);
+        for (int j = 0; j < NS; ++j) {
+            parts[j] = __builtin_convertvector(v, H2);
+            if (j + 1 < NS) v -= __builtin_convertvector(parts[j], vf2);
+        }
     }
+}
+
+// -1.0f in a scalar register, opaque to the compiler: with the literal it
+// folds v + hi * (-1) back into a conversion and a subtraction.
+__device__ __forceinline__ float minus_one()
+{
+    int bits;
+    asm volatile("s_mov_b32 %0, 0xbf800000" : "=s"(bits));
+    return __builtin_bit_cast(float, bits);
 }
 
 // One 32 x 32 x 16 product of 16-bit operands with FP32 accumulation.
@@ -380,10 +397,10 @@ __device__ __forceinline__ void lds_st4(char *Xb, uint32_t byte_off, float a, fl
 // the block's row bit 0, these are rows (t, t + 1) of one column; otherwise
 // tile bit 0 is the lowest column bit, i.e. column blocks (q, q + 1).
 template <int TB, int WAVES, int PREC, int SCALE>
-__device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const TileArgs &args, int s, int w, int half,
-                                            int l32, float scale, float unscale)
+__device__ __forceinline__ void apply_block(TileShared<TB, WAVES, lane_words(PREC)> &sh, const TileArgs &args, int s,
+                                            int w, int half, int l32, float scale, float unscale)
 {
-    using C = TileCfg<TB, WAVES>;
+    using C = TileCfg<TB, WAVES, lane_words(PREC)>;
     constexpr bool SPLIT = PREC != kPrecF32;
     using H2 = typename std::conditional<PREC == kPrecF16, f16x2, bf16x2>::type;  // packed 16-bit pair
     using H8 = typename std::conditional<PREC == kPrecF16, f16x8, bf16x8>::type;  // MFMA operand
@@ -408,7 +425,7 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
 #pragma unroll
         for (int v = 0; v < 16; ++v) acc[q][v] = 0.f;
     const uint32_t *op = sh.op[s];
-    const vf4 *ap = reinterpret_cast<const vf4 *>(op + (half * 32 + l32) * kLaneWords);  // staged fragments
+    const vf4 *ap = reinterpret_cast<const vf4 *>(op + (half * 32 + l32) * lane_words(PREC));  // staged fragments
     if (!SPLIT) {
         float a[16];
 #pragma unroll
@@ -460,6 +477,7 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
         c.y = 0x1p-11f;
         return x0 * __builtin_convertvector(c, H2);  // a packed 16-bit multiply
     };
+    const float m1 = F16 ? minus_one() : -1.f;
     auto fragment = [&](int p, int i) {
         H8 h;
         const vf4 f = ap[2 * p + i];
@@ -492,8 +510,8 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
                 H2 pp[4][NS];
 #pragma unroll
                 for (int k2 = 0; k2 < 2; ++k2) {
-                    split_pair<NS>(raw[k2].x, raw[k2].y, pp[2 * k2]);
-                    split_pair<NS>(raw[k2].z, raw[k2].w, pp[2 * k2 + 1]);
+                    split_pair<NS>(raw[k2].x, raw[k2].y, pp[2 * k2], m1);
+                    split_pair<NS>(raw[k2].z, raw[k2].w, pp[2 * k2 + 1], m1);
                 }
                 H8 b[NS];
 #pragma unroll
@@ -535,8 +553,8 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
                 H2 p0[4][NS], p1[4][NS];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    split_pair<NS>(raw[t].x, raw[t].y, p0[t]);
-                    split_pair<NS>(raw[t].z, raw[t].w, p1[t]);
+                    split_pair<NS>(raw[t].x, raw[t].y, p0[t], m1);
+                    split_pair<NS>(raw[t].z, raw[t].w, p1[t], m1);
                 }
                 H8 b0[NS], b1[NS];
 #pragma unroll
@@ -596,7 +614,7 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES> &sh, const Til
 // of squares to norm.out) or per pass from the state's norm (norm_scale;
 // SCALE 1, from the sums an earlier pass of the run reported).
 template <int TB, int WAVES, int PREC, int SCALE>
-__device__ __forceinline__ void tile_loop(TileShared<TB, WAVES> &sh, float *__restrict__ psi,
+__device__ __forceinline__ void tile_loop(TileShared<TB, WAVES, lane_words(PREC)> &sh, float *__restrict__ psi,
                                           const uint32_t *__restrict__ A, const TileArgs &args, uint64_t T,
                                           uint64_t T_end, uint64_t step, const TileNorm &norm)
 {
@@ -733,7 +751,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_tile_pass(float *__restrict__ ps
                                                           const TileArgs args, float *__restrict__ psi2,
                                                           const TileNorm norm)
 {
-    __shared__ TileShared<TB, WAVES> sh;
+    __shared__ TileShared<TB, WAVES, lane_words(PREC)> sh;
     tile_loop<TB, WAVES, PREC, SCALE>(sh, blockIdx.y ? psi2 : psi, A, args, blockIdx.x, args.n_tiles, gridDim.x,
                                       norm);
 }
@@ -746,7 +764,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_tile_batch(const TileUnit *__res
                                                            const TilePass *__restrict__ passes,
                                                            const uint32_t *__restrict__ pool, float *__restrict__ buf)
 {
-    __shared__ TileShared<TB, WAVES> sh;
+    __shared__ TileShared<TB, WAVES, lane_words(PREC)> sh;
     const TileUnit u = units[blockIdx.x];
     const TilePass &p = passes[u.pass];
     tile_loop<TB, WAVES, PREC, 0>(sh, buf + 2 * p.state_off, pool + p.op_off, p.args, u.t0, u.t1, 1, TileNorm{});
@@ -793,11 +811,17 @@ int tile_wgs_per_cu(int tile_bits, int waves)
     return tile_bits == 13 && waves == 4 ? 2 : 1;
 }
 
-int tile_max_blocks(int tile_bits, int waves)
+template <int LW>
+static int max_blocks_of(int tile_bits, int waves)
+{
+    if (tile_bits == 14) return waves == 16 ? TileCfg<14, 16, LW>::MAX_SUB : TileCfg<14, 8, LW>::MAX_SUB;
+    return waves == 4 ? TileCfg<13, 4, LW>::MAX_SUB : TileCfg<13, 8, LW>::MAX_SUB;
+}
+
+int tile_max_blocks(int tile_bits, int waves, int prec)
 {
     if (!tile_shape_supported(tile_bits, waves)) return 0;
-    if (tile_bits == 14) return waves == 16 ? TileCfg<14, 16>::MAX_SUB : TileCfg<14, 8>::MAX_SUB;
-    return waves == 4 ? TileCfg<13, 4>::MAX_SUB : TileCfg<13, 8>::MAX_SUB;
+    return lane_words(prec) == 24 ? max_blocks_of<24>(tile_bits, waves) : max_blocks_of<16>(tile_bits, waves);
 }
 
 static uint32_t f2h_rne(float x)
@@ -920,7 +944,7 @@ hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a,
     if (prec != kTileOperandF32 && prec != kTileOperandBF16 && prec != kTileOperandF16 && prec != kTileOperandBF16X3)
         return hipErrorInvalidValue;
     if (!tile_shape_supported(tile_bits, waves)) return hipErrorInvalidValue;
-    if (n_sub < 1 || n_sub > tile_max_blocks(tile_bits, waves)) return hipErrorInvalidValue;
+    if (n_sub < 1 || n_sub > tile_max_blocks(tile_bits, waves, prec)) return hipErrorInvalidValue;
     TileArgs a;
     if (hipError_t e = make_tile_args(n_sub, sub_pos, n, tile_bits, waves, prec, &a)) return e;
     float *p = static_cast<float *>(psi), *p2 = static_cast<float *>(psi2);

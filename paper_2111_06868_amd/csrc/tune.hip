@@ -438,7 +438,7 @@ extern "C" int sv_get_tile_shape(int *tile_bits, int *waves, int *max_blocks)
     const Tuning &t = tuning();
     if (tile_bits) *tile_bits = t.tile_bits;
     if (waves) *waves = t.tile_waves;
-    if (max_blocks) *max_blocks = dev::tile_max_blocks(t.tile_bits, t.tile_waves);
+    if (max_blocks) *max_blocks = dev::tile_max_blocks(t.tile_bits, t.tile_waves, dev::kTileOperandBF16);
     return SV_OK;
 }
 

@@ -350,6 +350,30 @@ def test_enhanced_rule_frontier_counts():
     assert all(g < p for g, p in zip(got, paper)), (got, paper)
 
 
+def test_plans_per_precision():
+    """sv_fuse_prec: the tiled rule fills passes up to one launch of the
+    precision's operands (split BF16: 5 blocks; FP32 and split FP16, whose
+    operands are smaller: 7), with every gate once in circuit order."""
+    n, gates = wc.config_circuit(1)
+    g = to_binding(gates)
+    counts = {}
+    for prec, cap in ((sv.PREC_SPLIT_BF16, 5), (sv.PREC_SPLIT_BF16X3, 5), (sv.PREC_FP32, 7),
+                      (sv.PREC_SPLIT_FP16, 7), (None, 5)):
+        blocks = sv.fuse(g, n, 4, sv.RULE_TILED, precision=prec).blocks(False)
+        order = [i for b in blocks for i in b.members]
+        assert sorted(order) == list(range(len(gates))) and _valid_order(gates, order)
+        per_pass, unions = {}, {}
+        for b in blocks:
+            if b.tile_pass >= 0:
+                per_pass[b.tile_pass] = per_pass.get(b.tile_pass, 0) + 1
+                unions.setdefault(b.tile_pass, set()).update(b.qubits)
+        assert max(per_pass.values()) <= cap and all(_pass_fits(u) for u in unions.values())
+        counts[prec] = (len(per_pass), max(per_pass.values()))
+    assert counts[sv.PREC_SPLIT_FP16][1] > 5 and counts[sv.PREC_SPLIT_FP16][0] < counts[None][0]
+    with pytest.raises(ValueError):
+        sv.fuse(g, n, 4, sv.RULE_TILED, precision=9)
+
+
 def test_tile_union_setting():
     """The tiled rule keeps every pass's tile to runs of at least
     2^(14 - limit) amplitudes for the configured union limit."""

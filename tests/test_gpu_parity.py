@@ -241,9 +241,11 @@ def test_graph_replay_matches_eager():
 def test_graph_kept_per_state_updates_with_new_angles(rule, prec):
     """One state runs the ansatz with use_graph again and again: new angles
     keep the launch structure, so the state's graph is updated in place, and
-    each run matches the eager run and the oracle; a different circuit
-    instantiates a new graph.  Eager work and synchronisation come between
-    the graph runs."""
+    each run matches the eager run and the oracle; a different circuit then
+    runs through the same state (the runtime's graph update either takes the
+    new launches or is refused and a new graph is instantiated) and matches
+    its eager run.  Eager work and synchronisation come between the graph
+    runs."""
     n = 16
     gates, thetas = wc.ansatz_circuit(n, 3, seed=8)
     st = sv.State(n, "c64")
@@ -263,7 +265,8 @@ def test_graph_kept_per_state_updates_with_new_angles(rule, prec):
     other = to_binding(wc.grid_rqc(4, 4, 4, seed=3))
     got = st.set_basis(0).run(other, max_k=4, rule=rule, precision=prec, use_graph=True).read()
     assert np.array_equal(got, sv.State(n, "c64").run(other, max_k=4, rule=rule, precision=prec).read())
-    assert st.graph_stats() == (5, 3)
+    runs, reused = st.graph_stats()
+    assert runs == 5 and reused in (3, 4)
 
 
 def test_stats_count_launches():
@@ -452,7 +455,7 @@ def test_tiled_wide_unions(shape, precision, n):
     sv.stats_reset()
     sv.stats_enable(True)
     try:
-        plan = sv.fuse(to_binding(gates), n, 4, sv.RULE_TILED)
+        plan = sv.fuse(to_binding(gates), n, 4, sv.RULE_TILED, precision=prec)  # the run's plan
         unions = {}
         for b in plan.blocks(False):
             if b.tile_pass >= 0:
@@ -465,12 +468,15 @@ def test_tiled_wide_unions(shape, precision, n):
         want, got, st = run_both(n, gates, "+", "c64", max_k=4, rule=sv.RULE_TILED, precision=prec)
         st.synchronize()
         tiles = sum(sv.stats_query(fam, s)[0] for s in range(1, sv.MAX_TILE_LAUNCH_BLOCKS + 1))
+        full = sv.stats_query(fam, 7)[0]  # launches of 7 blocks (FP32 and split FP16 operands)
     finally:
         sv.stats_enable(False)
         sv.stats_reset()
         sv.set_tile_shape(14, 16)
     fe, ma = _report("tiled %s shape=%s n=%d unions %s" % (precision, shape, n, sizes), want, got)
     assert tiles >= len(unions)
+    if tb == 14 and precision in ("fp32", "fp16"):
+        assert full > 0
     assert fe <= FID_C64
     if precision != "bf16":
         assert ma <= 1e-5
