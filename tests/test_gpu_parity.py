@@ -465,18 +465,23 @@ def test_tiled_wide_unions(shape, precision, n):
         assert sizes[-1] >= 13
         if tb == 14 and n == 16:
             assert sizes[-1] == 14
+        per_pass = {}
+        for b in plan.blocks(False):
+            if b.tile_pass >= 0:
+                per_pass[b.tile_pass] = per_pass.get(b.tile_pass, 0) + 1
         want, got, st = run_both(n, gates, "+", "c64", max_k=4, rule=sv.RULE_TILED, precision=prec)
         st.synchronize()
-        tiles = sum(sv.stats_query(fam, s)[0] for s in range(1, sv.MAX_TILE_LAUNCH_BLOCKS + 1))
-        full = sv.stats_query(fam, 7)[0]  # launches of 7 blocks (FP32 and split FP16 operands)
+        launches = {s: sv.stats_query(fam, s)[0] for s in range(1, sv.MAX_TILE_LAUNCH_BLOCKS + 1)}
     finally:
         sv.stats_enable(False)
         sv.stats_reset()
         sv.set_tile_shape(14, 16)
     fe, ma = _report("tiled %s shape=%s n=%d unions %s" % (precision, shape, n, sizes), want, got)
-    assert tiles >= len(unions)
-    if tb == 14 and precision in ("fp32", "fp16"):
-        assert full > 0
+    # one launch per planned pass, of the planned block count
+    for s in range(2, sv.MAX_TILE_LAUNCH_BLOCKS + 1):
+        assert launches[s] == sum(1 for c in per_pass.values() if c == s), (s, launches, per_pass)
+    if tb == 14 and precision in ("fp32", "fp16"):  # their smaller operands: more than 5 blocks a launch
+        assert max(per_pass.values()) > 5
     assert fe <= FID_C64
     if precision != "bf16":
         assert ma <= 1e-5
