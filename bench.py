@@ -38,7 +38,7 @@ KERNEL_SOURCES = {1: "apply.hip", 2: "apply.hip", 3: "mfma.hip", 4: "mfma.hip", 
                   10: "tile.hip", 11: "tile.hip", 12: "tile.hip"}
 TILE_FAMILIES = (9, 10, 11, 12)
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16x3": 4}  # SV_PREC_* codes
-DEFAULT_PRECISION = {"circuit": "fp16", "gradient": "fp32", "trajectories": "bf16", "density": "bf16x3",
+DEFAULT_PRECISION = {"circuit": "fp16", "gradient": "fp32", "trajectories": "fp16", "density": "bf16x3",
                      "jumps": "fp32"}
 
 
@@ -222,8 +222,8 @@ def main():
     ap.add_argument("--rule", default="tiled", choices=["paper", "enhanced", "tiled", "auto"])
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "fp16", "bf16x3"],
                     help="tile-pass arithmetic; default: fp16 for the circuits (FP32's per-amplitude "
-                         "error, unitary gates), bf16x3 for the density matrix (trace-preserving to "
-                         "about 1e-6), bf16 for the trajectory batch")
+                         "error, unitary gates) and the trajectory batch (per-tile scales), bf16x3 for "
+                         "the density matrix (trace-preserving to about 1e-6)")
     ap.add_argument("--config", type=int, default=1, choices=[1, 2])
     ap.add_argument("--workload", default="circuit", choices=["circuit", "gradient", "trajectories", "density", "jumps"],
                     help="circuit: the grid random circuit (default); gradient: 20-qubit ansatz "
@@ -557,7 +557,7 @@ def bench_trajectories(args):
     import paper_2111_06868_amd as sv
     from workloads import circuits as wc
     trajs = wc.trajectory_batch()
-    # tile passes of the trajectories with >= 14 qubits, by --precision (default split BF16)
+    # tile passes of the trajectories with >= 14 qubits, by --precision (default split FP16)
     prec = PRECISIONS[args.precision]
     circuits = [(t.n, [(g.name, g.qubits, g.params) for g in t.gates]) for t in trajs]
     if args.lightcone:

@@ -51,6 +51,19 @@ constexpr int kPrecF32 = kTileOperandF32, kPrecBF16 = kTileOperandBF16, kPrecF16
 // smaller FP32 and FP16 operands let more blocks share a launch.
 constexpr int lane_words(int prec) { return prec == kPrecBF16 || prec == kPrecBF16X3 ? 24 : 16; }
 
+// 16-byte chunk c of lane L's fragments sits at chunk c ^ frag_swz<LW>(L) of
+// its LW words.  With 64-byte lanes (LW = 16) the lanes of one 16-byte LDS
+// access (8 over 32 banks, or 16 over 64) would otherwise meet four to a
+// bank group; the XOR with lane bits (1 ^ 3, 2) puts them on distinct banks.
+// The 96-byte lanes of split BF16 (two to a group) stay in order: the same
+// XOR there (lane bits 2 ^ 3) costs those kernels register spills.
+template <int LW>
+__device__ __forceinline__ uint32_t frag_swz(uint32_t lane)
+{
+    if constexpr (LW == 16) return (((lane >> 1) ^ (lane >> 3)) & 1u) | ((lane >> 1) & 2u);
+    return 0u;
+}
+
 // Tile of 2^TB amplitudes held by a workgroup of WAVES waves: 2^TB / 16
 // columns per 4-qubit block, in blocks of 32 split evenly over the waves.
 // Shapes: (14, 8) and (14, 16) one 128 KiB tile per CU, with 2 or 4 waves
@@ -306,7 +319,8 @@ __device__ __forceinline__ void stage_blocks(TileShared<TB, WAVES, lane_words(PR
             const uint32_t w = cop[part * 256 + ci * 16 + 8 * i + 4 * half + e4];
             v = ri ? ((w >> 16) | (w << 16)) : (w ^ 0x80000000u);
         }
-        sh.op[s][lane * USED + wd] = v;
+        const int at = int(((uint32_t(wd) >> 2) ^ frag_swz<USED>(uint32_t(lane))) << 2) | (wd & 3);
+        sh.op[s][lane * USED + at] = v;
     }
     for (int e = tid; e < nsub * (C::CBLOCKS + 32); e += C::THREADS) {
         const int s = e / (C::CBLOCKS + 32), r = e % (C::CBLOCKS + 32);
@@ -426,11 +440,12 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES, lane_words(PRE
         for (int v = 0; v < 16; ++v) acc[q][v] = 0.f;
     const uint32_t *op = sh.op[s];
     const vf4 *ap = reinterpret_cast<const vf4 *>(op + (half * 32 + l32) * lane_words(PREC));  // staged fragments
+    const uint32_t fsw = frag_swz<lane_words(PREC)>(uint32_t(half * 32 + l32));  // their chunk order
     if (!SPLIT) {
         float a[16];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const vf4 v = ap[i];
+            const vf4 v = ap[uint32_t(i) ^ fsw];
             a[4 * i] = v.x;
             a[4 * i + 1] = v.y;
             a[4 * i + 2] = v.z;
@@ -480,7 +495,7 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES, lane_words(PRE
     const float m1 = F16 ? minus_one() : -1.f;
     auto fragment = [&](int p, int i) {
         H8 h;
-        const vf4 f = ap[2 * p + i];
+        const vf4 f = ap[uint32_t(2 * p + i) ^ fsw];
         __builtin_memcpy(&h, &f, 16);
         return h;
     };
