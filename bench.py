@@ -370,9 +370,11 @@ def main():
     log("timed %.1f ms/step; dominant %s avg %.3f ms -> %.0f GB/s" % (ms_step, roofline["kernel"], avg_ms, achieved))
     fused_state = st
 
-    # the achievable copy at the same layouts (the state is left unchanged)
-    _, _, max_blocks = sv.get_tile_shape()
-    ceiling = copy_ceiling(st, plan_tiles(blocks, n) if rule == sv.RULE_TILED else [], max_blocks)
+    # the achievable copy at the same layouts (the state is left unchanged);
+    # the plan was formed for this precision, so each of its passes is one launch
+    tiles = plan_tiles(blocks, n) if rule == sv.RULE_TILED else []
+    max_blocks = max([len(t["blocks"]) for t in tiles] + [1])
+    ceiling = copy_ceiling(st, tiles, max_blocks)
     roofline["copy_ceiling"] = ceiling
     if dfam in TILE_FAMILIES and "plan_layouts_GBps" in ceiling:
         roofline["frac_of_copy_ceiling"] = round(achieved / ceiling["plan_layouts_GBps"], 4)
