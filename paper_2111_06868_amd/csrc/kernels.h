@@ -108,11 +108,16 @@ int tile_max_blocks(int tile_bits, int waves, int prec);
 // blocks keep: the first pass (out) writes each workgroup's sum of squares of
 // the values it reads, one double per workgroup of its grid; later passes
 // (in, n_in = that grid) scale the whole pass by a power of two from the norm
-// instead of scaling each tile from its largest magnitude.
+// instead of scaling each tile from its largest magnitude.  Between such
+// passes the state may stay in HBM times that scale: in_scaled = it is read
+// that way (no scaling at copy-in), out_scaled = it is left that way (no
+// unscaling at copy-out).  Every pass of the run has the same scale, and
+// launches in between act on the scaled state linearly.
 struct TileNorm {
     const double *in = nullptr;
     int n_in = 0;
     double *out = nullptr;
+    int in_scaled = 0, out_scaled = 0;
 };
 // psi2 (optional): a second state of the same size that receives the same
 // pass in the same launch (gridDim.y = 2).

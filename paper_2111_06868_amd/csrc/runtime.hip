@@ -427,8 +427,24 @@ int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, cons
     const char *A = static_cast<const char *>(arena);
     const Tuning &T = tuning();
     // split-FP16 tile passes of one state: the first writes the norm partials,
-    // the later ones take their scale from them (unitary blocks keep the norm)
-    int norm_grid = 0;
+    // the later ones take their scale from them (unitary blocks keep the norm,
+    // so it is one scale for all of them), and from the second of them to the
+    // last the state stays in HBM times that scale: the second scales it at
+    // copy-in, the last unscales it at copy-out, the ones between copy it as
+    // it is.  Launches in between act on it linearly; the state is plain again
+    // when this call's launches end.
+    const uint64_t norm_tiles = uint64_t(1) << (n - T.tile_bits);
+    const int norm_grid_cap = T.tile_grid_cap * dev::tile_wgs_per_cu(T.tile_bits, T.tile_waves);
+    const uint64_t norm_grid_size =
+        norm_grid_cap > 0 && norm_tiles > uint64_t(norm_grid_cap) ? uint64_t(norm_grid_cap) : norm_tiles;
+    int norm_launches = 0;  // split-FP16 tile launches of this call that take part
+    if (!psi2 && norm_grid_size <= uint64_t(kTileNormSlots))
+        for (const Launch *it = first; it != first + count; ++it)
+            if (it->path == PATH_TILE_FP16) {
+                const int cap = dev::tile_max_blocks(T.tile_bits, T.tile_waves, dev::kTileOperandF16);
+                norm_launches += (it->k + cap - 1) / cap;
+            }
+    int norm_grid = 0, norm_done = 0;
     for (const Launch *it = first; it != first + count; ++it) {
         const Launch &L = *it;
         if (psi2 && L.path != PATH_REG && L.path != PATH_GENERIC && L.path != PATH_MFMA32 && !is_tile_path(L.path)) {
@@ -454,6 +470,8 @@ int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, cons
                     if (norm_grid > 0) {
                         norm.in = part;
                         norm.n_in = norm_grid;
+                        norm.in_scaled = norm_done >= 2;
+                        norm.out_scaled = norm_done + 1 < norm_launches;
                     } else {
                         norm.out = part;
                     }
@@ -465,6 +483,7 @@ int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, cons
                 if (e != hipSuccess)
                     return fail(SV_ERR_HIP, "tile pass launch (%d blocks): %s", m, hipGetErrorString(e));
                 if (norm.out) norm_grid = launched;
+                if (use_norm) ++norm_done;
             }
             continue;
         }

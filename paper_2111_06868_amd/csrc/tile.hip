@@ -668,15 +668,22 @@ __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES, lane_words(PREC)
 
     // FP16 with SCALE 1: one scale for the pass from the state's norm, the
     // sum of the workgroups' sums of squares that an earlier pass of the run
-    // wrote (fixed order; uniform, in scalar registers)
+    // wrote (fixed order; uniform, in scalar registers).  The copy-in
+    // multiplies by it unless the state is already held scaled in HBM, and
+    // the copy-out divides by it unless the state is to stay scaled.  SCALE 3:
+    // the state is held scaled in HBM before and after the pass, so the pass
+    // copies it as it is.
     float pscale = 1.f, punscale = 1.f;
     if (F16 && SCALE == 1) {
         double r2 = 0.0;
         for (int i = 0; i < norm.n_in; ++i) r2 += norm.in[i];
         norm_scale(sqrt(r2), pscale, punscale);
+        if (norm.in_scaled) pscale = 1.f;
+        if (norm.out_scaled) punscale = 1.f;
         pscale = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, pscale)));
         punscale = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, punscale)));
     }
+    constexpr bool PER_TILE = F16 && (SCALE == 0 || SCALE == 2);  // scales from each tile's maximum
     // SCALE 2: per-tile scales as SCALE 0, and the workgroup's sum of squares to norm.out
     constexpr bool want_norm = F16 && SCALE == 2;
     if (T >= T_end) {  // uniform over the workgroup
@@ -718,10 +725,10 @@ __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES, lane_words(PREC)
             const float v = wave_sum(cp.sum_sq(buf));
             if (lane == 0) sh.nrm[w] += v;  // only this wave's lane 0 touches sh.nrm[w]
         }
-        if (F16 && SCALE != 1) wave_max_to_red(buf);  // this tile's largest magnitude, published by the barrier
+        if (PER_TILE) wave_max_to_red(buf);  // this tile's largest magnitude, published by the barrier
         __syncthreads();  // the first one also publishes the staged blocks
         float scale = 1.f, unscale = 1.f;
-        if (F16 && SCALE != 1) {
+        if (PER_TILE) {
             tile_scale(red_max(), scale, unscale);
             // uniform: held in scalar registers through the block loop
             scale = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, scale)));
@@ -737,7 +744,7 @@ __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES, lane_words(PREC)
             __builtin_amdgcn_s_setprio(0);
         }
         for (int s = 0; s < args.n_sub; ++s) {
-            apply_block<TB, WAVES, PREC, SCALE == 1 ? 1 : 0>(sh, args, s, w, half, l32, scale, unscale);
+            apply_block<TB, WAVES, PREC, F16 && !PER_TILE ? 1 : 0>(sh, args, s, w, half, l32, scale, unscale);
             __syncthreads();
         }
         prev = base;
@@ -799,6 +806,8 @@ hipError_t tile_launch(const TileArgs &a, const void *d_a, int prec, float *psi,
         hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecBF16, 0>), grid, block, 0, st, psi, A, a, psi2, TileNorm{});
     else if (prec == kPrecBF16X3)
         hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecBF16X3, 0>), grid, block, 0, st, psi, A, a, psi2, TileNorm{});
+    else if (prec == kPrecF16 && norm.in && norm.in_scaled && norm.out_scaled)
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF16, 3>), grid, block, 0, st, psi, A, a, psi2, norm);
     else if (prec == kPrecF16 && norm.in)
         hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF16, 1>), grid, block, 0, st, psi, A, a, psi2, norm);
     else if (prec == kPrecF16 && norm.out)
@@ -956,6 +965,7 @@ hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a,
 {
     if ((norm.in || norm.out) && (prec != kTileOperandF16 || psi2 || (norm.in && norm.n_in < 1)))
         return hipErrorInvalidValue;
+    if ((norm.in_scaled || norm.out_scaled) && !norm.in) return hipErrorInvalidValue;
     if (prec != kTileOperandF32 && prec != kTileOperandBF16 && prec != kTileOperandF16 && prec != kTileOperandBF16X3)
         return hipErrorInvalidValue;
     if (!tile_shape_supported(tile_bits, waves)) return hipErrorInvalidValue;
