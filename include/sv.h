@@ -268,9 +268,11 @@ int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int use_graph);
  * SV_PREC_SPLIT_FP16: hi+lo 16-bit MFMA, the FP16 values scaled by a power of
  * two, chosen per tile from its largest magnitude in the call's first FP16
  * pass and per pass from the state's norm, which that pass measures, in the
- * later ones; SV_PREC_SPLIT_BF16X3: BF16 MFMA on three parts of each value),
- * and the tile
- * is written back, so a pass costs one read and one write of the state.  A
+ * later ones, between which the state stays in HBM times that one scale
+ * until the call's last FP16 pass; SV_PREC_SPLIT_BF16X3: BF16 MFMA on three
+ * parts of each value), and the tile is written back, so a pass costs one
+ * read and one write of the state.  The state is plain again when the
+ * call's launches end (asynchronously, like the call).  A
  * block left alone runs as a one-block pass where the cost table prices
  * that lower.
  * SV_RULE_AUTO (with max_k = -1, or max_k as an upper bound) evaluates the

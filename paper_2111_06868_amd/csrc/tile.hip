@@ -627,7 +627,8 @@ __device__ __forceinline__ void apply_block(TileShared<TB, WAVES, lane_words(PRE
 // (BF16X3) relative to the result.  FP16 passes scale the values per tile
 // (tile_scale; SCALE 0, and SCALE 2, which also reports the workgroup's sum
 // of squares to norm.out) or per pass from the state's norm (norm_scale;
-// SCALE 1, from the sums an earlier pass of the run reported).
+// SCALE 1, from the sums an earlier pass of the run reported; SCALE 3, the
+// same scale with the state already held scaled in HBM, copied as it is).
 template <int TB, int WAVES, int PREC, int SCALE>
 __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES, lane_words(PREC)> &sh, float *__restrict__ psi,
                                           const uint32_t *__restrict__ A, const TileArgs &args, uint64_t T,
