@@ -237,7 +237,8 @@ def test_graph_replay_matches_eager():
         sv.State(n, "c64").run(g[:10])  # eager work between replays
 
 
-@pytest.mark.parametrize("rule,prec", [(sv.RULE_ENHANCED, sv.PREC_FP32), (sv.RULE_TILED, sv.PREC_SPLIT_BF16)])
+@pytest.mark.parametrize("rule,prec", [(sv.RULE_ENHANCED, sv.PREC_FP32), (sv.RULE_TILED, sv.PREC_SPLIT_BF16),
+                                       (sv.RULE_TILED, sv.PREC_SPLIT_FP16)])
 def test_graph_kept_per_state_updates_with_new_angles(rule, prec):
     """One state runs the ansatz with use_graph again and again: new angles
     keep the launch structure, so the state's graph is updated in place, and
