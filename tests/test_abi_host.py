@@ -370,8 +370,24 @@ def test_plans_per_precision():
         assert max(per_pass.values()) <= cap and all(_pass_fits(u) for u in unions.values())
         counts[prec] = (len(per_pass), max(per_pass.values()))
     assert counts[sv.PREC_SPLIT_FP16][1] > 5 and counts[sv.PREC_SPLIT_FP16][0] < counts[None][0]
-    with pytest.raises(ValueError):
-        sv.fuse(g, n, 4, sv.RULE_TILED, precision=9)
+    for bad in (9, -1):
+        with pytest.raises(ValueError):
+            sv.fuse(g, n, 4, sv.RULE_TILED, precision=bad)
+
+
+def test_small_states_keep_the_union_limit():
+    """Below 14 qubits no tile holds a pass, and the tiled rule keeps to unions
+    of at most the limit (10); at 14 qubits and above wider unions appear."""
+    rng = np.random.default_rng(77)
+    for n, wide in ((12, False), (13, False), (16, True)):
+        gates = wc.random_gate_list(n, 30 * n, rng, max_k=2)
+        blocks = sv.fuse(to_binding(gates), n, 4, sv.RULE_TILED, precision=sv.PREC_SPLIT_FP16).blocks(False)
+        unions = {}
+        for b in blocks:
+            if b.tile_pass >= 0:
+                unions.setdefault(b.tile_pass, set()).update(b.qubits)
+        assert unions and all(_pass_fits(u) for u in unions.values())
+        assert (max(len(u) for u in unions.values()) > 10) == wide, (n, sorted(len(u) for u in unions.values()))
 
 
 def test_tile_union_setting():
