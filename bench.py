@@ -298,8 +298,9 @@ def main():
     stream = st.stream
 
     def step():
-        st.set_basis(0)
-        st.run(ga, max_k=args.max_k, rule=rule, precision=prec)
+        # |0..0> and the circuit in one call: the first tile pass produces the
+        # basis state itself instead of reading a filled state
+        st.run(ga, max_k=args.max_k, rule=rule, precision=prec, basis=0)
         return st.norm2()
 
     for _ in range(args.warmup):

@@ -280,6 +280,15 @@ int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int use_graph);
  * positions only, prices each with the cost table of (n, precision) (from
  * sv_autotune, or relative defaults), and fuses the cheapest. */
 int sv_run_circuit(sv_state *s, const sv_gate *g, int G, const sv_run_opts *o);
+/* sv_set_basis(s, basis) followed by sv_run_circuit(s, g, G, o) (paper,
+ * Simulations section: simulate with a computational-basis initial state),
+ * as one call: when the plan starts with an FP32 or split-FP16 tile pass,
+ * that pass produces the basis state itself and reads nothing from HBM (the
+ * state's earlier contents are not read; no fill runs); otherwise the state
+ * is filled first.
+ * The result is the same as the two calls'.  Nothing is changed if any gate
+ * is invalid.  Asynchronous.  SV_ERR_ARG for basis >= 2^n. */
+int sv_run_circuit_basis(sv_state *s, uint64_t basis, const sv_gate *g, int G, const sv_run_opts *o);
 
 /* ---------------------------------------------------------------- reductions */
 /* ||psi||^2 in FP64 (fixed-order two-stage reduction).  Synchronises. */

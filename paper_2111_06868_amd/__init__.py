@@ -304,15 +304,19 @@ class State:
         return self
 
     def run(self, gates, max_k: int = SV_MAX_K, precision: int = None, rule: int = RULE_NONE,
-            use_graph: bool = False):
-        """Fuse (rule, max_k) and apply the gates (sv_run_circuit)."""
+            use_graph: bool = False, basis: int = None):
+        """Fuse (rule, max_k) and apply the gates (sv_run_circuit); with
+        `basis`, start from the basis state |basis> (sv_run_circuit_basis)."""
         ga = gates if isinstance(gates, GateArray) else GateArray(gates)
         o = N.sv_run_opts()
         o.max_k = int(max_k)
         o.precision = (PREC_FP32 if self.dtype == C64 else PREC_FP64) if precision is None else int(precision)
         o.rule = int(rule)
         o.use_graph = int(bool(use_graph))
-        N.check(N.lib().sv_run_circuit(self.h, ga.ptr, ga.n, ctypes.byref(o)))
+        if basis is None:
+            N.check(N.lib().sv_run_circuit(self.h, ga.ptr, ga.n, ctypes.byref(o)))
+        else:
+            N.check(N.lib().sv_run_circuit_basis(self.h, int(basis), ga.ptr, ga.n, ctypes.byref(o)))
         return self
 
     def apply_plan(self, plan: "Plan", precision: int = None, use_graph: bool = False):

@@ -115,6 +115,7 @@ SIGNATURES = {
     "sv_plan_rule": (_I, [_P, ctypes.POINTER(_I)]),
     "sv_apply_plan": (_I, [_P, _P, _I, _I]),
     "sv_run_circuit": (_I, [_P, _GP, _I, ctypes.POINTER(sv_run_opts)]),
+    "sv_run_circuit_basis": (_I, [_P, ctypes.c_uint64, _GP, _I, ctypes.POINTER(sv_run_opts)]),
     "sv_norm": (_I, [_P, _D]),
     "sv_inner": (_I, [_P, _P, _D, _D]),
     "sv_expectation": (_I, [_P, _PS, _D]),

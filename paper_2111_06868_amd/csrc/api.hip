@@ -597,7 +597,9 @@ extern "C" int sv_apply_plan(sv_state *s, const sv_plan *p, int precision, int u
 namespace {
 
 // Fuse and apply a validated state's circuit (sv_run_circuit, sv_dm_run).
-int run_circuit_impl(sv_state *s, const sv_gate *g, int G, const sv_run_opts *o)
+// basis >= 0: the state first becomes |basis> (sv_run_circuit_basis): the
+// first launch produces it itself when it is a tile pass, else it is filled.
+int run_circuit_impl(sv_state *s, const sv_gate *g, int G, const sv_run_opts *o, int64_t basis = -1)
 {
     sv_run_opts d;
     d.max_k = SV_MAX_K;
@@ -623,6 +625,14 @@ int run_circuit_impl(sv_state *s, const sv_gate *g, int G, const sv_run_opts *o)
     std::vector<Launch> L;
     blocks_to_launches(blocks, s, o->precision, rule, L);
     if (int rc = select_device(s)) return rc;
+    if (basis >= 0) {
+        // FP32 and split-FP16 tile passes start from the basis state
+        // themselves; other first launches get it filled in
+        if (!L.empty() && (L[0].path == PATH_TILE || L[0].path == PATH_TILE_FP16))
+            L[0].basis = basis;
+        else
+            SV_HIP(dev::launch_fill_basis(s->dtype, s->buf, s->n, uint64_t(basis), s->stream));
+    }
     return run_launches(s, L, o->use_graph != 0);
 }
 
@@ -633,6 +643,14 @@ extern "C" int sv_run_circuit(sv_state *s, const sv_gate *g, int G, const sv_run
     clear_error();
     if (int rc = check_state(s)) return rc;
     return run_circuit_impl(s, g, G, o);
+}
+
+extern "C" int sv_run_circuit_basis(sv_state *s, uint64_t basis, const sv_gate *g, int G, const sv_run_opts *o)
+{
+    clear_error();
+    if (int rc = check_state(s)) return rc;
+    if (basis >> s->n) return fail(SV_ERR_ARG, "basis index %llu >= 2^%d", (unsigned long long)basis, s->n);
+    return run_circuit_impl(s, g, G, o, int64_t(basis));
 }
 
 // The super circuit is rewritten as a regular circuit of 2n positions

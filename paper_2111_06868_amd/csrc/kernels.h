@@ -118,6 +118,10 @@ struct TileNorm {
     int n_in = 0;
     double *out = nullptr;
     int in_scaled = 0, out_scaled = 0;
+    // >= 0 (FP32 and split FP16, one state): the pass reads nothing from
+    // HBM; its input is the computational basis state |basis> (amplitude 1
+    // there, 0 elsewhere), and it writes the whole state as any pass does.
+    int64_t basis = -1;
 };
 // psi2 (optional): a second state of the same size that receives the same
 // pass in the same launch (gridDim.y = 2).

@@ -116,6 +116,7 @@ struct Launch {
     size_t arena_off2 = 0; // second and third operands (split parts 1 and 2)
     size_t arena_off3 = 0;
     size_t norm_off = 0;   // split-FP16 tile paths: byte offset of the run's norm partials
+    int64_t basis = -1;    // tile paths, >= 0: the launch's first chunk starts the state from |basis>
 };
 // Doubles the norm partials of a run's split-FP16 tile passes may take (one
 // per workgroup of the first such pass).

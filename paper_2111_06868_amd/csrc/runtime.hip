@@ -476,6 +476,7 @@ int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, cons
                         norm.out = part;
                     }
                 }
+                if (c == 0 && L.basis >= 0) norm.basis = L.basis;  // reads nothing: the state starts here
                 LaunchTimer timer(stat_class(path_family(L.path), m), st);
                 hipError_t e = dev::launch_tile_pass(m, L.sub_pos + c, A + L.arena_off + c * op_bytes,
                                                      tile_operand_prec(L.path), psi, n, st, grid_cap, T.tile_bits,

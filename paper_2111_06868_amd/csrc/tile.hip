@@ -167,6 +167,23 @@ struct TileCopy {
 #pragma unroll
         for (int i = 0; i < kChunks; ++i) buf[i] = *reinterpret_cast<const vf4 *>(psi + 2 * (base + g_lo + g_hi[i]));
     }
+    // The same tile of a basis state, read from nowhere: zeros, and 1 at tile
+    // index t when the basis state lies in this tile (`here`).  Thread tid's
+    // chunk i holds tile indices 2 (tid + i THREADS) and the next one.
+    __device__ __forceinline__ void basis(vf4 *buf, bool here, uint32_t t, int tid) const
+    {
+        const uint32_t pair = t >> 1;
+#pragma unroll
+        for (int i = 0; i < kChunks; ++i) {
+            buf[i] = vf4{0.f, 0.f, 0.f, 0.f};
+            if (here && pair == uint32_t(tid) + uint32_t(i) * kThreads) {
+                if (t & 1u)
+                    buf[i].z = 1.f;
+                else
+                    buf[i].x = 1.f;
+            }
+        }
+    }
     // The same with a scale for the values in LDS (exact powers of two): LDS =
     // buf * scale, out = LDS * unscale.
     __device__ __forceinline__ void to_lds_scaled(vf4 *X4, const vf4 *buf, float scale) const
@@ -706,8 +723,31 @@ __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES, lane_words(PREC)
     // that round's prefetch is issued: loads and stores may complete out of
     // order, so any wait for the prefetch also waits for earlier stores, and
     // these were issued a whole round of block work earlier.
+    // a pass that starts the state from a basis state reads nothing: the
+    // basis state lies in the tile whose outside positions match its bits,
+    // at the tile index its tile-position bits form (FP32 and split FP16; in
+    // the split BF16 kernels the extra registers made them spill)
+    constexpr bool CAN_SYNTH = PREC == kPrecF32 || PREC == kPrecF16;
+    const bool synth = CAN_SYNTH && norm.basis >= 0;  // uniform
+    uint64_t b_out = 0;
+    uint32_t b_t = 0;
+    if (synth) {
+        const uint64_t b = uint64_t(norm.basis);
+        uint64_t in_mask = 0;
+        for (int j = 0; j < TB; ++j) {
+            b_t |= uint32_t((b >> args.ubit[j]) & 1u) << j;
+            in_mask |= uint64_t(1) << args.ubit[j];
+        }
+        b_out = b & ~in_mask;
+    }
+    auto fetch = [&](vf4 *into, uint64_t base) {
+        if (synth)
+            cp.basis(into, base == b_out, b_t, tid);
+        else
+            cp.load(into, psi, base);
+    };
     vf4 buf[C::CHUNKS];
-    cp.load(buf, psi, tile_base(T, args));
+    fetch(buf, tile_base(T, args));
     uint64_t prev = 0;
     for (bool first = true; T < T_end; T += step, first = false) {
         const uint64_t base = tile_base(T, args);
@@ -741,7 +781,7 @@ __device__ __forceinline__ void tile_loop(TileShared<TB, WAVES, lane_words(PREC)
             // the next tile's loads go out at raised wave priority, ahead of
             // the other waves' block work on the SIMD (2-3 % per pass)
             __builtin_amdgcn_s_setprio(3);
-            cp.load(buf, psi, tile_base(Tn, args));
+            fetch(buf, tile_base(Tn, args));
             __builtin_amdgcn_s_setprio(0);
         }
         for (int s = 0; s < args.n_sub; ++s) {
@@ -803,10 +843,12 @@ hipError_t tile_launch(const TileArgs &a, const void *d_a, int prec, float *psi,
     const uint32_t *A = static_cast<const uint32_t *>(d_a);
     const dim3 grid(unsigned(g), psi2 ? 2 : 1);
     const dim3 block(64 * WAVES);
+    TileNorm plain;  // the variants without the norm take only the basis start
+    plain.basis = norm.basis;
     if (prec == kPrecBF16)
-        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecBF16, 0>), grid, block, 0, st, psi, A, a, psi2, TileNorm{});
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecBF16, 0>), grid, block, 0, st, psi, A, a, psi2, plain);
     else if (prec == kPrecBF16X3)
-        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecBF16X3, 0>), grid, block, 0, st, psi, A, a, psi2, TileNorm{});
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecBF16X3, 0>), grid, block, 0, st, psi, A, a, psi2, plain);
     else if (prec == kPrecF16 && norm.in && norm.in_scaled && norm.out_scaled)
         hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF16, 3>), grid, block, 0, st, psi, A, a, psi2, norm);
     else if (prec == kPrecF16 && norm.in)
@@ -814,9 +856,9 @@ hipError_t tile_launch(const TileArgs &a, const void *d_a, int prec, float *psi,
     else if (prec == kPrecF16 && norm.out)
         hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF16, 2>), grid, block, 0, st, psi, A, a, psi2, norm);
     else if (prec == kPrecF16)
-        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF16, 0>), grid, block, 0, st, psi, A, a, psi2, TileNorm{});
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF16, 0>), grid, block, 0, st, psi, A, a, psi2, plain);
     else
-        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF32, 0>), grid, block, 0, st, psi, A, a, psi2, TileNorm{});
+        hipLaunchKernelGGL((k_tile_pass<TB, WAVES, kPrecF32, 0>), grid, block, 0, st, psi, A, a, psi2, plain);
     return hipGetLastError();
 }
 
@@ -967,6 +1009,9 @@ hipError_t launch_tile_pass(int n_sub, const int (*sub_pos)[4], const void *d_a,
     if ((norm.in || norm.out) && (prec != kTileOperandF16 || psi2 || (norm.in && norm.n_in < 1)))
         return hipErrorInvalidValue;
     if ((norm.in_scaled || norm.out_scaled) && !norm.in) return hipErrorInvalidValue;
+    if (norm.basis >= 0 && (psi2 || n >= 63 || (uint64_t(norm.basis) >> n) != 0 || norm.in_scaled ||
+                            (prec != kTileOperandF32 && prec != kTileOperandF16)))
+        return hipErrorInvalidValue;
     if (prec != kTileOperandF32 && prec != kTileOperandBF16 && prec != kTileOperandF16 && prec != kTileOperandBF16X3)
         return hipErrorInvalidValue;
     if (!tile_shape_supported(tile_bits, waves)) return hipErrorInvalidValue;

@@ -647,3 +647,53 @@ def test_stream_probe_keeps_the_state():
         st.stream_probe(range(13))  # 13 positions
     with pytest.raises(sv.SvValueError):
         sv.State(13, "c64").stream_probe(range(13))
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16", "bf16x3"])
+@pytest.mark.parametrize("shape", [(14, 16), (13, 8)])
+def test_run_from_basis_state(precision, shape):
+    """sv_run_circuit_basis: the same state as sv_set_basis followed by
+    sv_run_circuit, bit for bit, whatever the state held before (FP32 and
+    split-FP16 tile passes produce the basis state in their first pass; the
+    other precisions and plans that start with another launch fill it)."""
+    prec = _TILE_PREC[precision][0]
+    sv.set_tile_shape(*shape)
+    try:
+        for n in (14, 16, 19):
+            rng = np.random.default_rng(4000 + n + shape[1])
+            glist = wc.random_gate_list(n, 10 * n, rng, max_k=2)
+            gates = to_binding(glist)
+            for b in (0, int(rng.integers(1 << n)), (1 << n) - 1):
+                want = sv.State(n, "c64").set_basis(b).run(gates, max_k=4, rule=sv.RULE_TILED, precision=prec).read()
+                st = sv.State(n, "c64").set_product("+")  # overwritten, never read
+                got = st.run(gates, max_k=4, rule=sv.RULE_TILED, precision=prec, basis=b).read()
+                assert np.array_equal(got, want), (n, b)
+                if b == 0 and n == 16:
+                    ref_state = ref.simulate(n, glist, "0")
+                    _report("run from |0> %s shape=%s n=%d" % (precision, shape, n), ref_state, got)
+                    assert ref.fidelity_error(ref_state, got) <= FID_C64
+    finally:
+        sv.set_tile_shape(14, 16)
+
+
+def test_run_from_basis_state_other_rules_and_refusals():
+    """Plans without tile passes fill the basis state first; an index beyond
+    the state and an invalid gate are refused with the state untouched."""
+    n = 15
+    rng = np.random.default_rng(4100)
+    gates = to_binding(wc.random_gate_list(n, 60, rng, max_k=3))
+    for rule, k in ((sv.RULE_ENHANCED, 5), (sv.RULE_NONE, 6)):
+        want = sv.State(n, "c64").set_basis(5).run(gates, max_k=k, rule=rule).read()
+        got = sv.State(n, "c64").set_product("-").run(gates, max_k=k, rule=rule, basis=5).read()
+        assert np.array_equal(got, want)
+    want = sv.State(n, "c128").set_basis(3).run(gates).read()
+    got = sv.State(n, "c128").set_product("+").run(gates, basis=3).read()
+    assert np.array_equal(got, want)
+    st = sv.State(n, "c64").set_product("+")
+    before = st.read()
+    with pytest.raises(ValueError):
+        st.run(gates, max_k=4, rule=sv.RULE_TILED, basis=1 << n)
+    bad = to_binding([wc.Gate("H", (n,), ())])
+    with pytest.raises(ValueError):
+        st.run(bad, max_k=4, rule=sv.RULE_TILED, basis=0)
+    assert np.array_equal(st.read(), before)
