@@ -697,3 +697,28 @@ def test_run_from_basis_state_other_rules_and_refusals():
     with pytest.raises(ValueError):
         st.run(bad, max_k=4, rule=sv.RULE_TILED, basis=0)
     assert np.array_equal(st.read(), before)
+
+
+def test_run_from_basis_state_in_a_graph():
+    """The basis start captured in a graph: replays with new angles and
+    with and without the basis start match the eager runs bit for bit."""
+    n = 16
+    gates, thetas = wc.ansatz_circuit(n, 3, seed=12)
+    st = sv.State(n, "c64")
+    rng = np.random.default_rng(13)
+    for rep in range(4):
+        g = to_binding(wc.with_thetas(gates, rng.uniform(0, 2 * np.pi, len(thetas))))
+        basis = None if rep == 2 else int(rng.integers(1 << n))
+        if basis is None:
+            st.set_basis(7)
+            want = sv.State(n, "c64").set_basis(7).run(g, max_k=4, rule=sv.RULE_TILED,
+                                                          precision=sv.PREC_SPLIT_FP16).read()
+        else:
+            want = sv.State(n, "c64").set_basis(basis).run(g, max_k=4, rule=sv.RULE_TILED,
+                                                              precision=sv.PREC_SPLIT_FP16).read()
+        got = st.run(g, max_k=4, rule=sv.RULE_TILED, precision=sv.PREC_SPLIT_FP16, use_graph=True,
+                     basis=basis).read()
+        assert np.array_equal(got, want), rep
+        sv.State(n, "c64").run(g[:10]).synchronize()  # eager work between graph runs
+    runs, _ = st.graph_stats()
+    assert runs == 4
