@@ -433,7 +433,7 @@ int enqueue(const Launch *first, size_t count, int dtype, void *psi, int n, cons
     // copy-in, the last unscales it at copy-out, the ones between copy it as
     // it is.  Launches in between act on it linearly; the state is plain again
     // when this call's launches end.
-    const uint64_t norm_tiles = uint64_t(1) << (n - T.tile_bits);
+    const uint64_t norm_tiles = n >= T.tile_bits ? uint64_t(1) << (n - T.tile_bits) : 0;  // no tile passes below
     const int norm_grid_cap = T.tile_grid_cap * dev::tile_wgs_per_cu(T.tile_bits, T.tile_waves);
     const uint64_t norm_grid_size =
         norm_grid_cap > 0 && norm_tiles > uint64_t(norm_grid_cap) ? uint64_t(norm_grid_cap) : norm_tiles;
