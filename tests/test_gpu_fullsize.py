@@ -217,3 +217,21 @@ def test_20q_ansatz_adjoint_all_gradients():
     assert np.abs(ref.param_shift_grad(n, gates, thetas, H, indices=idx) - ps[idx]).max() <= 1e-12
     # the adjoint pass consumed psi back to |0..0>
     assert abs(abs(psi.read(0, 1)[0]) - 1) <= 1e-4
+
+
+@pytest.mark.parametrize("precision", [sv.PREC_SPLIT_FP16, sv.PREC_SPLIT_BF16X3])
+def test_32q_tiled_vs_c128(ref32, precision):
+    """The 32-qubit grid circuit in the 32-qubit bench configuration: tiled
+    rule, k <= 4, started from |0..0> in the first tile pass (split FP16) or
+    filled (split BF16X3), against the complex128 run: fidelity, amplitudes
+    and norm (split FP16 keeps the complex64 norm for unitary blocks)."""
+    n, g, refst = ref32
+    st = sv.State(n, "c64").set_product("+")
+    st.run(g, max_k=4, rule=sv.RULE_TILED, precision=precision, basis=0)
+    fe = _fe_dev(refst, st)
+    ma = float(np.max(np.abs(refst.read(0, 1 << 20) - st.read(0, 1 << 20))))
+    nd = abs(st.norm2() - 1)
+    print("[parity] 32q tiled k<=4 precision=%d vs GPU c128: 1-F=%.3e max_abs(first 2^20)=%.3e |norm-1|=%.2e"
+          % (precision, fe, ma, nd), flush=True)
+    assert fe <= 1e-10 and ma <= 1e-8 and nd <= 1e-6
+    st.free()
