@@ -217,7 +217,8 @@ int sv_fuse(const sv_gate *g, int G, int n, int max_k, int rule, sv_plan **out);
  * with that precision.  The tiled rule then fills each pass up to what one
  * launch holds with that precision's operands (7 blocks for SV_PREC_FP32 and
  * SV_PREC_SPLIT_FP16 at (14, *), 5 for the split BF16 forms; sv_fuse plans
- * for 5, which every precision takes), and SV_RULE_AUTO and max_k = -1 use
+ * for the split BF16 capacity, which every precision takes), and
+ * SV_RULE_AUTO and max_k = -1 use
  * that precision's cost table (sv_fuse: FP32's).  A plan applied in another
  * precision stays correct: a pass of more blocks than one launch holds runs
  * as several launches.  SV_ERR_ARG for an unknown precision. */
