@@ -542,22 +542,27 @@ def bench_gradient(args):
     H = sv.pauli_sum(wc.ansatz_observable(n))
     ga = sv.GateArray([(g.name, g.qubits, g.params, g.param_index) for g in gates])
     psi, scratch = sv.State(n, "c64"), sv.State(n, "c64")
+    prec = PRECISIONS[args.precision]
     # launch shapes and block costs for 20-qubit states (sizes the fusion of
     # the forward circuit and of the adjoint's dagger blocks)
-    sv.autotune(scratch, sv.PREC_FP32)
+    sv.autotune(scratch, prec)
     out = {}
 
     def step():
         psi.set_basis(0)
-        psi.run(ga, max_k=-1, rule=sv.RULE_AUTO)
+        psi.run(ga, max_k=-1, rule=sv.RULE_AUTO, precision=prec)
         out["E"] = psi.expectation(H)
-        out["g"] = sv.backward(psi, scratch, ga, H, len(thetas))
+        out["g"] = sv.backward(psi, scratch, ga, H, len(thetas), precision=prec)
 
     t = _timed_steps(args, step)
     print(json.dumps({"metric": "energy + adjoint gradient evaluations/s (20-qubit ansatz, 480 parameters)",
                       "value": round(1.0 / t, 3), "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
                       "warmup": args.warmup, "ms_per_step": round(1e3 * t, 3), "higher_is_better": True,
-                      "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+                      "scaling": "weak", "vs_baseline": None,
+                      "dtype": {"fp32": "f32", "bf16": "f32 state; bf16 hi+lo split products",
+                                "fp16": "f32 state; f16 hi+lo split products",
+                                "bf16x3": "f32 state; bf16 three-part split products"}[args.precision],
+                      "data": "synthetic",
                       "config": {"workload": "20-qubit ansatz, 12 layers RY/RZ + CZ ladder, 708 gates, 480 angles"},
                       "energy": out["E"], "grad_norm": float(np.linalg.norm(out["g"]))}), flush=True)
 

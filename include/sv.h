@@ -335,6 +335,14 @@ int sv_apply_pauli_sum(sv_state *psi, const sv_pauli_sum *H, sv_state *out);
  * non-rotation). */
 int sv_backward(sv_state *psi, sv_state *scratch, const sv_gate *g, int G, const sv_pauli_sum *H,
                 double *grad, int n_params);
+/* sv_backward with the undoing of the gate runs in `precision` (SV_PREC_*,
+ * as for sv_run_circuit: split FP16 needs unitary MATRIX gates and scales
+ * each tile of either state by a power of two from its own largest
+ * magnitude).  sv_backward is this call with FP32 (complex64) or FP64
+ * (complex128).  Errors as sv_backward, and SV_ERR_ARG for a precision the
+ * state's amplitude type does not take. */
+int sv_backward_prec(sv_state *psi, sv_state *scratch, const sv_gate *g, int G, const sv_pauli_sum *H,
+                     double *grad, int n_params, int precision);
 
 /* ---------------------------------------------------------- density matrices */
 /* Density-matrix evolution by the state-vector path (paper, Simulations

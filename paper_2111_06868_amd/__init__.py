@@ -708,14 +708,17 @@ def fuse(gates, n: int, max_k: int, rule: int = RULE_PAPER, precision: int = Non
 
 
 # ------------------------------------------------------------------ gradients
-def backward(psi: State, scratch: State, gates, terms, n_params: int) -> np.ndarray:
-    """Adjoint dE/dtheta (sv_backward); psi holds the forward output and is
-    consumed."""
+def backward(psi: State, scratch: State, gates, terms, n_params: int, precision: int = None) -> np.ndarray:
+    """Adjoint dE/dtheta (sv_backward, or sv_backward_prec with a
+    precision); psi holds the forward output and is consumed."""
     ga = gates if isinstance(gates, GateArray) else GateArray(gates)
     H = terms if isinstance(terms, PauliSum) else PauliSum(terms)
     grad = np.zeros(max(int(n_params), 1), dtype=np.float64)
-    N.check(N.lib().sv_backward(psi.h, scratch.h, ga.ptr, ga.n, H.ptr,
-                                grad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), int(n_params)))
+    gp = grad.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    if precision is None:
+        N.check(N.lib().sv_backward(psi.h, scratch.h, ga.ptr, ga.n, H.ptr, gp, int(n_params)))
+    else:
+        N.check(N.lib().sv_backward_prec(psi.h, scratch.h, ga.ptr, ga.n, H.ptr, gp, int(n_params), int(precision)))
     return grad[:n_params]
 
 

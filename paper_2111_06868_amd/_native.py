@@ -122,6 +122,7 @@ SIGNATURES = {
     "sv_expectation_noalloc": (_I, [_P, _I, _I, _P, _PS, _D]),
     "sv_apply_pauli_sum": (_I, [_P, _PS, _P]),
     "sv_backward": (_I, [_P, _P, _GP, _I, _PS, _D, _I]),
+    "sv_backward_prec": (_I, [_P, _P, _GP, _I, _PS, _D, _I, _I]),
     "sv_super_op_matrix": (_I, [ctypes.POINTER(sv_super_op), _D]),
     "sv_dm_run": (_I, [_P, _GP, _I, ctypes.POINTER(sv_super_op), _I, ctypes.POINTER(sv_run_opts)]),
     "sv_dm_expectation": (_I, [_P, _PS, _D]),

@@ -1129,7 +1129,7 @@ struct BwdStep {
 
 // Fuse the daggers of gates hi, hi-1, .., lo (in that order) into blocks and
 // append their launches.
-int dagger_launches(const sv_gate *g, int hi, int lo, const sv_state *s, std::vector<Launch> &out)
+int dagger_launches(const sv_gate *g, int hi, int lo, const sv_state *s, int prec, std::vector<Launch> &out)
 {
     const int cnt = hi - lo + 1;
     std::vector<sv_gate> dg(cnt);
@@ -1155,7 +1155,6 @@ int dagger_launches(const sv_gate *g, int hi, int lo, const sv_state *s, std::ve
         kmax = std::max(kmax, src.k);
     }
     std::vector<Block> blocks;
-    const int prec = s->dtype == SV_C64 ? SV_PREC_FP32 : SV_PREC_FP64;
     const CostTable cost = lookup_costs(s->n, prec, nullptr);
     // The plan of a run (dense blocks of the cheapest k, or tile passes)
     // depends on its gates' positions and the cost table only; it is
@@ -1165,6 +1164,7 @@ int dagger_launches(const sv_gate *g, int hi, int lo, const sv_state *s, std::ve
     auto mix = [&key](uint64_t v) { key = (key ^ v) * 1099511628211ull; };
     mix(uint64_t(s->n));
     mix(uint64_t(s->dtype));
+    mix(uint64_t(prec));
     mix(cost_version());
     mix(uint64_t(tile_union_limit()));
     mix(uint64_t(tile_pass_bits()) | uint64_t(tile_pass_capacity(prec)) << 8);
@@ -1233,15 +1233,42 @@ int dagger_launches(const sv_gate *g, int hi, int lo, const sv_state *s, std::ve
 
 }  // namespace
 
+namespace {
+
+int backward_impl(sv_state *psi, sv_state *scratch, const sv_gate *g, int G, const sv_pauli_sum *H, double *grad,
+                  int n_params, int prec);
+
+}  // namespace
+
 extern "C" int sv_backward(sv_state *psi, sv_state *scratch, const sv_gate *g, int G, const sv_pauli_sum *H,
                            double *grad, int n_params)
 {
     clear_error();
+    if (!psi) return fail(SV_ERR_ARG, "NULL state handle");
+    return backward_impl(psi, scratch, g, G, H, grad, n_params, psi->dtype == SV_C64 ? SV_PREC_FP32 : SV_PREC_FP64);
+}
+
+extern "C" int sv_backward_prec(sv_state *psi, sv_state *scratch, const sv_gate *g, int G, const sv_pauli_sum *H,
+                                double *grad, int n_params, int precision)
+{
+    clear_error();
+    if (!psi) return fail(SV_ERR_ARG, "NULL state handle");
+    if (int rc = check_precision(psi, precision)) return rc;
+    return backward_impl(psi, scratch, g, G, H, grad, n_params, precision);
+}
+
+namespace {
+
+int backward_impl(sv_state *psi, sv_state *scratch, const sv_gate *g, int G, const sv_pauli_sum *H, double *grad,
+                  int n_params, int prec)
+{
     if (!psi || !scratch) return fail(SV_ERR_ARG, "NULL state handle");
     if (psi == scratch) return fail(SV_ERR_ARG, "scratch must be a different state");
     if (psi->n != scratch->n || psi->dtype != scratch->dtype) return fail(SV_ERR_ARG, "states differ in n or type");
     if (n_params < 0 || (n_params > 0 && !grad)) return fail(SV_ERR_ARG, "bad gradient buffer");
     if (int rc = validate_gates(g, G, psi->n)) return rc;
+    if (prec == SV_PREC_SPLIT_FP16)
+        if (int rc = check_fp16_gates(g, G)) return rc;
     if (int rc = check_pauli(H, psi->n)) return rc;
     for (int i = 0; i < G; ++i)
         if (g[i].param >= n_params) return fail(SV_ERR_ARG, "gate %d: param %d >= n_params %d", i, g[i].param, n_params);
@@ -1318,7 +1345,7 @@ extern "C" int sv_backward(sv_state *psi, sv_state *scratch, const sv_gate *g, i
         std::atomic<size_t> next(0);
         auto worker = [&]() {
             for (size_t t; (t = next.fetch_add(1)) < jobs.size();) {
-                rcs[t] = dagger_launches(g, jobs[t].hi, jobs[t].lo, psi, outs[t]);
+                rcs[t] = dagger_launches(g, jobs[t].hi, jobs[t].lo, psi, prec, outs[t]);
                 if (rcs[t]) msgs[t] = last_error_cstr();
             }
         };
@@ -1389,6 +1416,8 @@ extern "C" int sv_backward(sv_state *psi, sv_state *scratch, const sv_gate *g, i
     if (int rc = stream_after(scratch->stream, psi->stream)) return rc;
     return SV_OK;
 }
+
+}  // namespace
 
 // ============================================================== stats
 extern "C" int sv_stats_enable(int on)

@@ -219,6 +219,32 @@ def test_20q_ansatz_adjoint_all_gradients():
     assert abs(abs(psi.read(0, 1)[0]) - 1) <= 1e-4
 
 
+@pytest.mark.parametrize("rule", [sv.RULE_TILED, sv.RULE_ENHANCED])
+def test_20q_ansatz_adjoint_split_fp16(rule):
+    """The 20-qubit ansatz with the forward run and the adjoint sweep's undone
+    gate runs in split FP16 (per-tile scales on both states): E and all 480
+    gradients against the stored oracle values, as in FP32."""
+    n = 20
+    gates, thetas = wc.ansatz_circuit(n, 12, seed=3)
+    H = wc.ansatz_observable(n)
+    e_ref, ps, fd = _ansatz_golden()
+    prec = sv.PREC_SPLIT_FP16
+    psi = sv.State(n, "c64").run(to_binding(gates), max_k=4, rule=rule, precision=prec)
+    e = psi.expectation(H)
+    scratch = sv.State(n, "c64")
+    g = sv.backward(psi, scratch, to_binding(gates), H, len(thetas), precision=prec)
+    rel_ps = np.linalg.norm(g - ps) / np.linalg.norm(ps)
+    scale = 1e-2 * np.max(np.abs(ps))
+    worst = float(np.max(np.abs(g - ps) / np.maximum(np.abs(ps), scale)))
+    print("[parity] 20q ansatz split FP16 rule=%d E=%.8f (oracle %.8f); rel vs PS %.3e, worst component %.3e"
+          % (rule, e, e_ref, rel_ps, worst), flush=True)
+    assert abs(e - e_ref) <= 1e-5
+    assert rel_ps <= 1e-4 and worst <= 1e-4
+    assert abs(abs(psi.read(0, 1)[0]) - 1) <= 1e-4
+    with pytest.raises(ValueError):
+        sv.backward(sv.State(n, "c128"), sv.State(n, "c128"), to_binding(gates), H, len(thetas), precision=prec)
+
+
 @pytest.mark.parametrize("precision", [sv.PREC_SPLIT_FP16, sv.PREC_SPLIT_BF16X3])
 def test_32q_tiled_vs_c128(ref32, precision):
     """The 32-qubit grid circuit in the 32-qubit bench configuration: tiled
