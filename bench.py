@@ -223,7 +223,8 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp32", "bf16", "fp16", "bf16x3"],
                     help="tile-pass arithmetic; default: fp16 for the circuits (FP32's per-amplitude "
                          "error, unitary gates) and the trajectory batch (per-tile scales), bf16x3 for "
-                         "the density matrix (trace-preserving to about 1e-6)")
+                         "the density matrix (trace-preserving to about 1e-6), fp32 for the gradient "
+                         "and the sampled jumps")
     ap.add_argument("--config", type=int, default=1, choices=[1, 2])
     ap.add_argument("--workload", default="circuit", choices=["circuit", "gradient", "trajectories", "density", "jumps"],
                     help="circuit: the grid random circuit (default); gradient: 20-qubit ansatz "
